@@ -1,0 +1,562 @@
+/*
+ * FP64 CPU oracle for the Min-Path-Tracing per-path minimisation.
+ * TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU-baseline timing); the
+ * product path never uses it.  See mpt_oracle.h for what is computed and
+ * which reading of the paper each piece takes.
+ *
+ * Deliberately plain: the residual is a dense vector, the Jacobian a dense
+ * rows x 3n matrix, the normal equations a dense 3n x 3n matrix solved by
+ * textbook Cholesky.  No blocking, no band structure, no fusion.
+ */
+#include "mpt_oracle.h"
+#include <math.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXN 5
+#define MAXU (3 * MAXN)
+#define MAXR (4 * MAXN)
+
+enum { TP = 0, TL = 1, TQ = 2, TC = 3 };
+
+/* ------------------------------------------------------------ small algebra */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+/* C = A B for 3x3 */
+static void mm3(double A[3][3], double B[3][3], double C[3][3])
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0;
+            for (int k = 0; k < 3; k++) s += A[i][k] * B[k][j];
+            C[i][j] = s;
+        }
+}
+/* P(u) = (I - u^ u^T)/|u| : derivative of u/|u| with respect to u */
+static void unit_jac(const double *uh, double len, double P[3][3])
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) P[i][j] = ((i == j ? 1.0 : 0.0) - uh[i] * uh[j]) / len;
+}
+
+/* ------------------------------------------------------------ primitives */
+static int prim_type(const orc_scene *s, int id, const double **rec)
+{
+    if (id < 0) return -1;
+    if (id < s->n_pl) { *rec = s->pl + 13 * (size_t)id; return TP; }
+    id -= s->n_pl;
+    if (id < s->n_ln) { *rec = s->ln + 8 * (size_t)id; return TL; }
+    id -= s->n_ln;
+    if (id < s->n_q) { *rec = s->q + 17 * (size_t)id; return TQ; }
+    id -= s->n_q;
+    if (id < s->n_c) { *rec = s->c + 7 * (size_t)id; return TC; }
+    return -1;
+}
+
+static void quad_A(const double *q, double A[3][3])
+{
+    A[0][0] = q[3]; A[0][1] = q[4]; A[0][2] = q[5];
+    A[1][0] = q[4]; A[1][1] = q[6]; A[1][2] = q[7];
+    A[2][0] = q[5]; A[2][1] = q[7]; A[2][2] = q[8];
+}
+
+/* Implicit value and gradient of a surface (Eq. 11 row, Eq. 2 gradient). */
+static void surface_eval(int t, const double *r, const double *X, double *f, double g[3], double H[3][3])
+{
+    if (t == TP) {
+        *f = dot3(r, X) - r[3];
+        for (int i = 0; i < 3; i++) g[i] = r[i];
+        memset(H, 0, 9 * sizeof(double));
+    } else {
+        double A[3][3], w[3];
+        quad_A(r, A);
+        sub3(X, r, w);
+        double Aw[3];
+        for (int i = 0; i < 3; i++) Aw[i] = A[i][0] * w[0] + A[i][1] * w[1] + A[i][2] * w[2];
+        *f = dot3(w, Aw) + dot3(r + 9, w) + r[12];
+        for (int i = 0; i < 3; i++) g[i] = 2.0 * Aw[i] + r[9 + i];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) H[i][j] = 2.0 * A[i][j];
+    }
+}
+
+/* Orthonormal pair across a unit direction e (any such pair gives the same
+ * normal equations, only the rows rotate). */
+static void across(const double *e, double u1[3], double u2[3])
+{
+    double a[3] = {0, 0, 0};
+    double ax = fabs(e[0]), ay = fabs(e[1]), az = fabs(e[2]);
+    if (ax <= ay && ax <= az) a[0] = 1; else if (ay <= az) a[1] = 1; else a[2] = 1;
+    cross3(e, a, u1);
+    double l = norm3(u1);
+    for (int i = 0; i < 3; i++) u1[i] /= l;
+    cross3(e, u1, u2);
+}
+
+/* Edge direction e^ at X and its derivative (Eq. 4; circle: tangent field). */
+static int edge_dir(int t, const double *r, const double *X, double e[3], double E[3][3])
+{
+    if (t == TL) {
+        for (int i = 0; i < 3; i++) e[i] = r[3 + i];
+        memset(E, 0, 9 * sizeof(double));
+        return 0;
+    }
+    double d[3], w[3];
+    sub3(X, r, d);
+    cross3(r + 3, d, w);
+    double lw = norm3(w);
+    if (!(lw > 0)) return -1;
+    for (int i = 0; i < 3; i++) e[i] = w[i] / lw;
+    const double *nc = r + 3;
+    double K[3][3] = {{0, -nc[2], nc[1]}, {nc[2], 0, -nc[0]}, {-nc[1], nc[0], 0}};
+    double P[3][3];
+    unit_jac(e, lw, P);
+    mm3(P, K, E);
+    return 0;
+}
+
+/* Two rows that vanish exactly on the edge curve, with their gradients. */
+static void edge_rows(int t, const double *r, const double *X, double f[2], double df[2][3])
+{
+    double d[3];
+    if (t == TL) {
+        double u1[3], u2[3];
+        across(r + 3, u1, u2);
+        sub3(X, r, d);
+        f[0] = dot3(d, u1);
+        f[1] = dot3(d, u2);
+        for (int i = 0; i < 3; i++) { df[0][i] = u1[i]; df[1][i] = u2[i]; }
+    } else {
+        sub3(X, r, d);
+        double R = r[6];
+        f[0] = dot3(d, r + 3);
+        f[1] = (dot3(d, d) - R * R) / (2.0 * R);
+        for (int i = 0; i < 3; i++) { df[0][i] = r[3 + i]; df[1][i] = d[i] / R; }
+    }
+}
+
+/* ------------------------------------------------------------ residual */
+/*
+ * Rows of interaction k, in metres:
+ *   reflection  S_k (r^ - (i^ - 2<i^,n^>n^))      3 rows  (Eq. 8 rescaled)
+ *               f_k(X_k)                          1 row   (Eq. 11)
+ *   diffraction S_k <i^ - r^, e^>                 1 row   (Eq. 9 rescaled)
+ *               two rows vanishing on the edge    2 rows  (Eq. 11 for edges)
+ * with i = X_k - X_{k-1}, r = X_{k+1} - X_k and S_k = (|i| + |r|)/2.  Eq. (8)
+ * equals |i| times the unit form; the mean length keeps the rows in metres
+ * without the spurious zeros |i| = 0 would create, and it grows away from
+ * the scene so that the cost has no descent towards infinity.
+ */
+int orc_residual(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                 const double *X, double *R, double *J)
+{
+    int nu = 3 * n, row = 0;
+    if (J) memset(J, 0, sizeof(double) * (size_t)MAXR * nu);
+    for (int k = 0; k < n; k++) {
+        const double *rec;
+        int t = prim_type(s, ids[k], &rec);
+        const double *Xp = (k == 0) ? s->tx : X + 3 * (k - 1);
+        const double *Xk = X + 3 * k;
+        const double *Xn = (k == n - 1) ? rx : X + 3 * (k + 1);
+        double a[3], b[3];
+        sub3(Xk, Xp, a);
+        sub3(Xn, Xk, b);
+        double la = norm3(a), lb = norm3(b);
+        if (!(la > 0) || !(lb > 0)) return -1;
+        double ih[3], rh[3];
+        for (int i = 0; i < 3; i++) { ih[i] = a[i] / la; rh[i] = b[i] / lb; }
+        double Pa[3][3], Pb[3][3];
+        unit_jac(ih, la, Pa);
+        unit_jac(rh, lb, Pb);
+        /* unit-form law rows u and their derivatives with respect to
+         * X_{k-1}, X_k, X_{k+1}: Up, Uk, Un (nl rows each) */
+        double u[3], Up[3][3], Uk[3][3], Un[3][3];
+        int nl;
+        double obj[2], dobj[2][3];
+        int no;
+        if (t == TP || t == TQ) {
+            double f, g[3], H[3][3];
+            surface_eval(t, rec, Xk, &f, g, H);
+            double lg = norm3(g);
+            if (!(lg > 0)) return -1;
+            double nh[3];
+            for (int i = 0; i < 3; i++) nh[i] = g[i] / lg;
+            double sdot = dot3(ih, nh);
+            for (int i = 0; i < 3; i++) u[i] = rh[i] - ih[i] + 2.0 * sdot * nh[i];
+            double Q[3][3], QPa[3][3], Nm[3][3], Pn[3][3], T[3][3], TN[3][3];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    Q[i][j] = (i == j ? 1.0 : 0.0) - 2.0 * nh[i] * nh[j];
+                    Pn[i][j] = (i == j ? 1.0 : 0.0) - nh[i] * nh[j];
+                }
+            mm3(Q, Pa, QPa);
+            mm3(Pn, H, Nm); /* d n^ / dX = (I - n n^T) H / |g| */
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) Nm[i][j] /= lg;
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) T[i][j] = 2.0 * (nh[i] * ih[j] + (i == j ? sdot : 0.0));
+            mm3(T, Nm, TN);
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    Up[i][j] = QPa[i][j];
+                    Un[i][j] = Pb[i][j];
+                    Uk[i][j] = -Pb[i][j] - QPa[i][j] + TN[i][j];
+                }
+            nl = 3;
+            obj[0] = f;
+            for (int j = 0; j < 3; j++) dobj[0][j] = g[j];
+            no = 1;
+        } else if (t == TL || t == TC) {
+            double e[3], E[3][3];
+            if (edge_dir(t, rec, Xk, e, E)) return -1;
+            double dv[3];
+            for (int i = 0; i < 3; i++) dv[i] = ih[i] - rh[i];
+            u[0] = dot3(dv, e);
+            for (int j = 0; j < 3; j++) {
+                double ePa = 0, ePb = 0, dE = 0;
+                for (int i = 0; i < 3; i++) {
+                    ePa += e[i] * Pa[i][j];
+                    ePb += e[i] * Pb[i][j];
+                    dE += dv[i] * E[i][j];
+                }
+                Up[0][j] = -ePa;
+                Un[0][j] = -ePb;
+                Uk[0][j] = ePa + ePb + dE;
+            }
+            nl = 1;
+            edge_rows(t, rec, Xk, obj, dobj);
+            no = 2;
+        } else {
+            return -1;
+        }
+        /* scale the law rows by S = (|i| + |r|)/2 (product rule for J) */
+        double S = 0.5 * (la + lb);
+        double dSp[3], dSk[3], dSn[3];
+        for (int j = 0; j < 3; j++) {
+            dSp[j] = -0.5 * ih[j];
+            dSk[j] = 0.5 * (ih[j] - rh[j]);
+            dSn[j] = 0.5 * rh[j];
+        }
+#define JAC(rw, blk, col) J[(size_t)(rw) * nu + 3 * (blk) + (col)]
+        for (int i = 0; i < nl; i++) {
+            R[row + i] = S * u[i];
+            if (J)
+                for (int j = 0; j < 3; j++) {
+                    if (k > 0) JAC(row + i, k - 1, j) += S * Up[i][j] + u[i] * dSp[j];
+                    if (k < n - 1) JAC(row + i, k + 1, j) += S * Un[i][j] + u[i] * dSn[j];
+                    JAC(row + i, k, j) += S * Uk[i][j] + u[i] * dSk[j];
+                }
+        }
+        for (int i = 0; i < no; i++) {
+            R[row + nl + i] = obj[i];
+            if (J)
+                for (int j = 0; j < 3; j++) JAC(row + nl + i, k, j) += dobj[i][j];
+        }
+#undef JAC
+        row += nl + no;
+    }
+    return row;
+}
+
+/* ------------------------------------------------------------ start points */
+static void project(int t, const double *r, const double *P, double *X)
+{
+    if (t == TP) {
+        double f = dot3(r, P) - r[3];
+        for (int i = 0; i < 3; i++) X[i] = P[i] - f * r[i];
+    } else if (t == TL) {
+        double d[3];
+        sub3(P, r, d);
+        double sp = dot3(d, r + 3);
+        for (int i = 0; i < 3; i++) X[i] = r[i] + sp * r[3 + i];
+    } else if (t == TQ) {
+        /* one Newton projection step onto f = 0 */
+        double f, g[3], H[3][3];
+        surface_eval(t, r, P, &f, g, H);
+        double gg = dot3(g, g);
+        for (int i = 0; i < 3; i++) X[i] = (gg > 0) ? P[i] - f * g[i] / gg : P[i];
+    } else {
+        /* nearest point of the circle: drop onto its plane, push to radius R */
+        double d[3], w[3];
+        sub3(P, r, d);
+        double h = dot3(d, r + 3);
+        for (int i = 0; i < 3; i++) w[i] = d[i] - h * r[3 + i];
+        double lw = norm3(w);
+        if (!(lw > 0)) {
+            double u2[3];
+            across(r + 3, w, u2);
+            lw = 1.0;
+        }
+        for (int i = 0; i < 3; i++) X[i] = r[i] + r[6] * w[i] / lw;
+    }
+}
+
+void orc_init_line(const orc_scene *s, const double rx[3], int n, const int32_t *ids, double *X)
+{
+    for (int k = 0; k < n; k++) {
+        const double *rec;
+        int t = prim_type(s, ids[k], &rec);
+        double a = (double)(k + 1) / (double)(n + 1), P[3];
+        for (int i = 0; i < 3; i++) P[i] = s->tx[i] + a * (rx[i] - s->tx[i]);
+        project(t, rec, P, X + 3 * k);
+    }
+}
+
+/* ------------------------------------------------------------ LM */
+/* In-place Cholesky of the dense SPD matrix M (lower triangle); 0 on success. */
+static int cholesky(double *M, int m)
+{
+    for (int j = 0; j < m; j++) {
+        double d = M[j * m + j];
+        for (int k = 0; k < j; k++) d -= M[j * m + k] * M[j * m + k];
+        if (!(d > 0)) return -1;
+        d = sqrt(d);
+        M[j * m + j] = d;
+        for (int i = j + 1; i < m; i++) {
+            double v = M[i * m + j];
+            for (int k = 0; k < j; k++) v -= M[i * m + k] * M[j * m + k];
+            M[i * m + j] = v / d;
+        }
+    }
+    return 0;
+}
+
+static void chol_solve(const double *L, int m, const double *b, double *x)
+{
+    double y[MAXU];
+    for (int i = 0; i < m; i++) {
+        double v = b[i];
+        for (int k = 0; k < i; k++) v -= L[i * m + k] * y[k];
+        y[i] = v / L[i * m + i];
+    }
+    for (int i = m - 1; i >= 0; i--) {
+        double v = y[i];
+        for (int k = i + 1; k < m; k++) v -= L[k * m + i] * x[k];
+        x[i] = v / L[i * m + i];
+    }
+}
+
+static double inf_norm(const double *v, int m)
+{
+    double r = 0;
+    for (int i = 0; i < m; i++) r = fmax(r, fabs(v[i]));
+    return r;
+}
+
+static int outside_guard(const orc_scene *s, const double *X, int n)
+{
+    for (int k = 0; k < n; k++)
+        for (int i = 0; i < 3; i++) {
+            double c = 0.5 * (s->lo[i] + s->hi[i]);
+            double h = 10.0 * 0.5 * (s->hi[i] - s->lo[i]) + 1.0;
+            if (!(fabs(X[3 * k + i] - c) <= h)) return 1;
+        }
+    return 0;
+}
+
+static int ids_ok(const orc_scene *s, int n, const int32_t *ids)
+{
+    int tot = s->n_pl + s->n_ln + s->n_q + s->n_c;
+    if (n < 1 || n > MAXN) return 0;
+    for (int k = 0; k < n; k++)
+        if (ids[k] < 0 || ids[k] >= tot) return 0;
+    return 1;
+}
+
+/* normal equations A = J^T J, g = J^T R (dense) */
+static void normal_eq(const double *J, const double *R, int m, int nu, double *A, double *g)
+{
+    for (int i = 0; i < nu; i++) {
+        double gi = 0;
+        for (int r = 0; r < m; r++) gi += J[r * nu + i] * R[r];
+        g[i] = gi;
+        for (int j = 0; j < nu; j++) {
+            double a = 0;
+            for (int r = 0; r < m; r++) a += J[r * nu + i] * J[r * nu + j];
+            A[i * nu + j] = a;
+        }
+    }
+}
+
+int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                  const double *x0, const orc_lm_opts *o, double *X, double *cost, int32_t *iters)
+{
+    int nu = 3 * n;
+    *iters = 0;
+    *cost = INFINITY;
+    if (!ids_ok(s, n, ids)) return ORC_BAD_INPUT;
+    for (int i = 0; i < 3; i++)
+        if (!isfinite(rx[i])) return ORC_BAD_INPUT;
+    if (x0) {
+        for (int i = 0; i < nu; i++) {
+            X[i] = x0[i];
+            if (!isfinite(X[i])) return ORC_BAD_INPUT;
+        }
+    } else {
+        orc_init_line(s, rx, n, ids, X);
+    }
+    double R[MAXR], J[MAXR * MAXU], A[MAXU * MAXU], g[MAXU], M[MAXU * MAXU], dx[MAXU], mg[MAXU];
+    double Xt[MAXU], Rt[MAXR];
+    double lam = 0, C = INFINITY, C_ref = INFINITY, rinf = INFINITY;
+    int status = ORC_MAXITER, small = 0;
+    if (outside_guard(s, X, n)) return ORC_DIVERGED;
+    for (int it = 1; it <= o->max_iter; it++) {
+        *iters = it;
+        /* linearise at the current points */
+        int m = orc_residual(s, rx, n, ids, X, R, J);
+        if (m < 0) { status = ORC_DEGENERATE; break; }
+        C = 0;
+        for (int r = 0; r < m; r++) C += R[r] * R[r];
+        rinf = inf_norm(R, m);
+        normal_eq(J, R, m, nu, A, g);
+        double dmax = 0;
+        for (int i = 0; i < nu; i++) dmax = fmax(dmax, A[i * nu + i]);
+        if (it == 1) { lam = o->lambda0 * dmax; C_ref = C; }
+        if (rinf <= o->tol_res) { small = 1; break; }
+        /* plateau: too small a decrease of the cost over a window ends the
+         * descent; the point is then classified by its residual */
+        if (o->plateau_win > 0 && it > 1 && (it - 1) % o->plateau_win == 0) {
+            if (C > o->plateau_frac * C_ref) { small = 1; break; }
+            C_ref = C;
+        }
+        /* (J^T J + lambda diag(J^T J)) dx = -J^T R, diag floored at 1e-12 max */
+        for (int i = 0; i < nu * nu; i++) M[i] = A[i];
+        for (int i = 0; i < nu; i++) M[i * nu + i] += lam * fmax(A[i * nu + i], 1e-12 * dmax);
+        if (cholesky(M, nu)) {
+            lam *= 10.0;
+            if (lam > 1e12 * dmax) { status = ORC_STALLED; break; }
+            continue;
+        }
+        for (int i = 0; i < nu; i++) mg[i] = -g[i];
+        chol_solve(M, nu, mg, dx);
+        for (int i = 0; i < nu; i++) Xt[i] = X[i] + dx[i];
+        int is_small = inf_norm(dx, nu) <= o->tol_step * (1.0 + inf_norm(X, nu));
+        /* a trial point outside the guard box counts as a cost increase */
+        int mt = outside_guard(s, Xt, n) ? -1 : orc_residual(s, rx, n, ids, Xt, Rt, NULL);
+        double Ct = INFINITY;
+        if (mt == m) {
+            Ct = 0;
+            for (int r = 0; r < m; r++) Ct += Rt[r] * Rt[r];
+        }
+        if (Ct < C) {
+            for (int i = 0; i < nu; i++) X[i] = Xt[i];
+            C = Ct;
+            rinf = inf_norm(Rt, m);
+            lam = fmax(lam / 10.0, 1e-15 * dmax);
+            if (is_small) { small = 1; break; }
+        } else {
+            if (is_small) { small = 1; break; }
+            lam *= 10.0;
+            if (lam > 1e12 * dmax) { status = ORC_STALLED; break; }
+        }
+    }
+    *cost = C;
+    if (small) status = (rinf <= o->tau_root) ? ORC_CONVERGED : ORC_LOCALMIN;
+    return status;
+}
+
+/* ------------------------------------------------------------ acceptance */
+static int in_extent(int t, const double *r, const double *X)
+{
+    double d[3];
+    if (t == TP) {
+        sub3(X, r + 4, d);
+        double a = dot3(d, r + 7), b = dot3(d, r + 10);
+        return a >= 0.0 && a <= dot3(r + 7, r + 7) && b >= 0.0 && b <= dot3(r + 10, r + 10);
+    }
+    if (t == TL) {
+        sub3(X, r, d);
+        double sp = dot3(d, r + 3);
+        return sp >= r[6] && sp <= r[7];
+    }
+    if (t == TQ) {
+        sub3(X, r, d);
+        double h = dot3(d, r + 13), w[3];
+        for (int i = 0; i < 3; i++) w[i] = d[i] - h * r[13 + i];
+        return dot3(w, w) <= r[16] * r[16];
+    }
+    return 1; /* a circle is its own finite extent */
+}
+
+int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                   const double *X, int status, double tau_res, double min_seg)
+{
+    if (status != ORC_CONVERGED || !ids_ok(s, n, ids)) return 0;
+    double R[MAXR];
+    int m = orc_residual(s, rx, n, ids, X, R, NULL);
+    if (m < 0 || !(inf_norm(R, m) <= tau_res)) return 0;
+    for (int k = 0; k <= n; k++) {
+        const double *P = (k == 0) ? s->tx : X + 3 * (k - 1);
+        const double *Q = (k == n) ? rx : X + 3 * k;
+        double d[3];
+        sub3(Q, P, d);
+        if (!(norm3(d) >= min_seg)) return 0;
+    }
+    for (int k = 0; k < n; k++) {
+        const double *rec;
+        int t = prim_type(s, ids[k], &rec);
+        if (!in_extent(t, rec, X + 3 * k)) return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------ batches */
+void orc_solve_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                     const int32_t *order, const int32_t *prim, const double *x0,
+                     const orc_lm_opts *o, double *x, double *cost, int32_t *iters,
+                     uint8_t *status, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < nb; i++) {
+        int n = order[i];
+        int32_t ids[MAXN];
+        double X[MAXU], X0[MAXU];
+        for (int k = 0; k < MAXN; k++) ids[k] = prim[k * nb + i];
+        if (x0)
+            for (int j = 0; j < MAXU; j++) X0[j] = x0[j * nb + i];
+        for (int j = 0; j < MAXU; j++) X[j] = 0.0;
+        double c;
+        int32_t it;
+        int st = (n >= 1 && n <= MAXN)
+                     ? orc_solve_one(s, rx + 3 * (size_t)rx_index[i], n, ids, x0 ? X0 : NULL, o, X, &c, &it)
+                     : ORC_BAD_INPUT;
+        if (!(n >= 1 && n <= MAXN)) { c = INFINITY; it = 0; }
+        for (int j = 0; j < MAXU; j++) x[j * nb + i] = (j < 3 * n) ? X[j] : 0.0;
+        cost[i] = c;
+        iters[i] = it;
+        status[i] = (uint8_t)st;
+    }
+}
+
+void orc_accept_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                      const int32_t *order, const int32_t *prim, const double *x,
+                      const uint8_t *status, double tau_res, double min_seg, uint8_t *accept,
+                      int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < nb; i++) {
+        int n = order[i];
+        int32_t ids[MAXN];
+        double X[MAXU];
+        for (int k = 0; k < MAXN; k++) ids[k] = prim[k * nb + i];
+        for (int j = 0; j < MAXU; j++) X[j] = x[j * nb + i];
+        accept[i] = (n >= 1 && n <= MAXN)
+                        ? (uint8_t)orc_accept_one(s, rx + 3 * (size_t)rx_index[i], n, ids, X, status[i], tau_res, min_seg)
+                        : 0;
+    }
+}

@@ -1,0 +1,103 @@
+/*
+ * FP64 CPU oracle for the Min-Path-Tracing per-path minimisation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, obviously correct
+ * reference used by the tests, by smoke() and by the CPU-baseline leg of the
+ * benchmark.  The product path never links, loads or calls it.  It shares no
+ * code with the HIP library.
+ *
+ * What it computes (paper Sec. III-B, Eqs. (8)-(12)): for one candidate path
+ * (TX = X_0, RX = X_{n+1}, interaction list L_1..L_n), the points
+ * X_1..X_n that minimise C = |I(X)|^2 + |F(X)|^2, where I stacks the
+ * reflection (Eq. 8) and diffraction (Eq. 9) residuals and F the implicit
+ * object equations (Eq. 11).  A path exists iff the minimum is 0 (Eq. 12),
+ * and it is kept iff the cost is below a threshold and every point lies on
+ * the finite object (Alg. 1, the acceptance test).
+ *
+ * Readings of the paper taken here (each also listed in the design notes):
+ *  - the reflection rows are S_k (r^ - (i^ - 2<i^,n^>n^)) and the
+ *    diffraction row S_k <i^ - r^, e^>, with S_k the mean length of the two
+ *    segments at X_k: Eq. (8) is |i| times the unit form and Eq. (9) the
+ *    unit form itself, so this is the "rescaling" Sec. III-B allows, chosen
+ *    to keep every row in metres, to avoid the spurious zeros of |i| = 0 and
+ *    to make the cost grow away from the scene;
+ *  - a surface adds one row f(X) (plane n.X - d; quadric scaled so that
+ *    |grad f| = 1 at its vertex); an edge adds two rows (a straight edge:
+ *    the two coordinates across the line; a circle: distance to its plane
+ *    and (|X-c|^2 - R^2)/(2R));
+ *  - the minimiser is Levenberg-Marquardt with Marquardt's diagonal scaling
+ *    (the paper only says "gradient descent");
+ *  - initial points: each object's projection of the point k/(n+1) of the
+ *    way along the TX -> RX segment, or caller-given points.
+ *
+ * Parity status: every function here is pinned by the CPU tests (closed
+ * forms of the image method and of the Keller point, the paper's Fig. 5
+ * example, Fermat-length invariants, finite-difference Jacobians, shooting
+ * constructions and brute force).  No function is parity-unpinned.
+ */
+#ifndef MPT_ORACLE_H
+#define MPT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_CONVERGED = 0, ORC_MAXITER = 1, ORC_STALLED = 2, ORC_DIVERGED = 3,
+       ORC_DEGENERATE = 4, ORC_BAD_INPUT = 5, ORC_LOCALMIN = 6 };
+
+typedef struct {
+    double tx[3];
+    double lo[3], hi[3];           /* scene box; the guard box is 10x it plus 1 m:
+                                      trial points outside it are rejected, a start
+                                      point outside it is DIVERGED */
+    int32_t n_pl, n_ln, n_q, n_c;  /* counts; global ids are type-major */
+    const double *pl;              /* [n_pl][13] n, d, o, eu, ev            */
+    const double *ln;              /* [n_ln][8]  p, e, s0, s1               */
+    const double *q;               /* [n_q][17]  p, A(6), b, c, ax, r_ap     */
+    const double *c;               /* [n_c][7]   c, n, R                    */
+} orc_scene;
+
+typedef struct {
+    int32_t max_iter;      /* 200 */
+    double  tol_step;      /* converged when |dx|_inf <= tol_step*(1+|x|_inf) */
+    double  tol_res;       /* converged when |R|_inf <= tol_res */
+    double  tau_root;      /* a converged point is a root iff |R|_inf <= tau_root */
+    double  lambda0;       /* initial damping relative to max diag(J^T J) */
+    int32_t plateau_win;   /* every plateau_win iterations the cost must have */
+    double  plateau_frac;  /* dropped below plateau_frac x its value before   */
+} orc_lm_opts;
+
+/* Residual rows (and, if J != NULL, the dense Jacobian, row-major
+ * [rows][3n]) at the points X (x1,y1,z1,x2,...).  Returns the row count,
+ * or -1 when a direction is undefined (zero-length segment, zero gradient,
+ * point on a circle's axis). */
+int orc_residual(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                 const double *X, double *R, double *J);
+
+/* Straight-line initial points (3n values). */
+void orc_init_line(const orc_scene *s, const double rx[3], int n, const int32_t *ids, double *X);
+
+/* One solve; x0 may be NULL (straight-line start).  Returns the status. */
+int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                  const double *x0, const orc_lm_opts *o, double *X, double *cost, int32_t *iters);
+
+/* Finite-object acceptance of a solved path (1 accepted / 0 rejected). */
+int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                   const double *X, int status, double tau_res, double min_seg);
+
+/* Batched forms, component-major [15][nb] point arrays; OpenMP over solves.
+ * x0 may be NULL. */
+void orc_solve_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                     const int32_t *order, const int32_t *prim, const double *x0,
+                     const orc_lm_opts *o, double *x, double *cost, int32_t *iters,
+                     uint8_t *status, int nthreads);
+void orc_accept_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                      const int32_t *order, const int32_t *prim, const double *x,
+                      const uint8_t *status, double tau_res, double min_seg, uint8_t *accept,
+                      int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

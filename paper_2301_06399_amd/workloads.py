@@ -1,0 +1,423 @@
+"""Seeded synthetic workloads for the batched path solve.
+
+This module only *draws* inputs: scenes of implicit primitives, receiver
+positions, interaction sequences and (optionally) random initial guesses.
+It holds none of the method's arithmetic (no residuals, projections,
+solves or acceptance tests), so both the HIP path and the CPU oracle can
+consume its output without sharing any of the method's code.
+
+Scene model (paper Sec. II): every object is an implicit primitive.  The
+records below are the flat FP64 layouts the C interfaces take; the global
+primitive id is type-major: planes, then straight edges, then quadrics,
+then circular edges.
+
+  plane    (13): n(3) unit normal, d with n.x = d, o(3) rectangle corner,
+                 eu(3), ev(3) rectangle side vectors (full length)
+  line     (8) : p(3) point, e(3) unit direction, s0, s1 (parameter range)
+  quadric  (17): p(3) anchor, A(6) = xx,xy,xz,yy,yz,zz of the symmetric
+                 matrix, b(3), c, ax(3) patch axis, r_ap aperture radius;
+                 f(x) = (x-p)^T A (x-p) + b^T (x-p) + c
+  circle   (7) : c(3) centre, n(3) unit normal of its plane, R radius
+
+All seeds derive from S = 230106399 as S + 1000*cfg + stream with the
+streams scene=1, rx=2, seq=3, init=4, train=5, heldout=6.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+SEED_BASE = 230106399
+STREAM = {"scene": 1, "rx": 2, "seq": 3, "init": 4, "train": 5, "heldout": 6}
+
+PLANE_W, LINE_W, QUAD_W, CIRC_W = 13, 8, 17, 7
+T_PLANE, T_LINE, T_QUAD, T_CIRC = 0, 1, 2, 3
+MAX_ORDER = 5
+
+
+def seed(cfg: int, stream: str) -> int:
+    return SEED_BASE + 1000 * cfg + STREAM[stream]
+
+
+@dataclass
+class Scene:
+    tx: np.ndarray
+    planes: np.ndarray = field(default_factory=lambda: np.zeros((0, PLANE_W)))
+    lines: np.ndarray = field(default_factory=lambda: np.zeros((0, LINE_W)))
+    quadrics: np.ndarray = field(default_factory=lambda: np.zeros((0, QUAD_W)))
+    circles: np.ndarray = field(default_factory=lambda: np.zeros((0, CIRC_W)))
+    aabb_lo: np.ndarray = field(default_factory=lambda: np.zeros(3))
+    aabb_hi: np.ndarray = field(default_factory=lambda: np.zeros(3))
+
+    def __post_init__(self):
+        self.tx = np.ascontiguousarray(self.tx, dtype=np.float64)
+        for k in ("planes", "lines", "quadrics", "circles"):
+            setattr(self, k, np.ascontiguousarray(getattr(self, k), dtype=np.float64))
+        self.aabb_lo = np.ascontiguousarray(self.aabb_lo, dtype=np.float64)
+        self.aabb_hi = np.ascontiguousarray(self.aabb_hi, dtype=np.float64)
+
+    @property
+    def counts(self):
+        return (len(self.planes), len(self.lines), len(self.quadrics), len(self.circles))
+
+    @property
+    def n_prims(self):
+        return sum(self.counts)
+
+    def type_of(self, gid: np.ndarray) -> np.ndarray:
+        """Primitive type of global ids (type-major numbering)."""
+        c = np.cumsum(self.counts)
+        return np.searchsorted(c, gid, side="right").astype(np.int32)
+
+
+@dataclass
+class Batch:
+    """A batch of solves: one (RX, interaction list) each.
+
+    rx        [n_rx, 3] FP64 receiver positions
+    rx_index  [n] int32 index into rx
+    order     [n] int32 number of interactions n_t in 1..5
+    prim      [5, n] int32 global primitive ids, -1 beyond the order
+    x0        optional [15, n] FP64 initial points (component-major)
+    """
+    rx: np.ndarray
+    rx_index: np.ndarray
+    order: np.ndarray
+    prim: np.ndarray
+    x0: np.ndarray | None = None
+
+    def __post_init__(self):
+        self.rx = np.ascontiguousarray(self.rx, dtype=np.float64)
+        self.rx_index = np.ascontiguousarray(self.rx_index, dtype=np.int32)
+        self.order = np.ascontiguousarray(self.order, dtype=np.int32)
+        self.prim = np.ascontiguousarray(self.prim, dtype=np.int32)
+        if self.x0 is not None:
+            self.x0 = np.ascontiguousarray(self.x0, dtype=np.float64)
+
+    @property
+    def n(self):
+        return len(self.order)
+
+    def subset(self, idx):
+        idx = np.asarray(idx)
+        return Batch(self.rx, self.rx_index[idx], self.order[idx], self.prim[:, idx],
+                     None if self.x0 is None else self.x0[:, idx])
+
+
+# ---------------------------------------------------------------- records
+def plane_rect(n, d, o, eu, ev):
+    return np.concatenate([np.asarray(n, float), [float(d)], np.asarray(o, float),
+                           np.asarray(eu, float), np.asarray(ev, float)])
+
+
+def line_seg(p, e, s0, s1):
+    return np.concatenate([np.asarray(p, float), np.asarray(e, float), [float(s0), float(s1)]])
+
+
+def paraboloid(vertex, axis, focal):
+    """Paraboloid of revolution with its vertex, unit axis and focal length F.
+
+    In its own frame z' = (x'^2 + y'^2)/(4F); written as f = 0 with f scaled by
+    1/(4F) so that |grad f| = 1 at the vertex.  The patch is r' <= 2F.
+    """
+    ax = np.asarray(axis, float)
+    A = (np.eye(3) - np.outer(ax, ax)) / (4.0 * focal)
+    return np.concatenate([np.asarray(vertex, float),
+                           [A[0, 0], A[0, 1], A[0, 2], A[1, 1], A[1, 2], A[2, 2]],
+                           -ax, [0.0], ax, [2.0 * focal]])
+
+
+def circle(c, n, R):
+    return np.concatenate([np.asarray(c, float), np.asarray(n, float), [float(R)]])
+
+
+def _unit(v):
+    v = np.asarray(v, float)
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+# ---------------------------------------------------------------- helpers
+def _no_repeat_sequences(rng, n, order, pool_of_slot):
+    """Draw prim ids [5, n]: slot k is drawn from pool_of_slot(k) (array of
+    candidate ids per solve, or a 1-D pool), no element equal to the previous."""
+    prim = np.full((MAX_ORDER, n), -1, dtype=np.int32)
+    for k in range(MAX_ORDER):
+        act = order > k
+        pool = pool_of_slot(k)
+        if isinstance(pool, np.ndarray) and pool.ndim == 1:
+            draw = pool[rng.integers(0, len(pool), n)]
+        else:
+            draw = pool(n)
+        prim[k, act] = draw[act]
+        if k > 0:
+            while True:
+                bad = act & (prim[k] == prim[k - 1])
+                if not bad.any():
+                    break
+                nb = int(bad.sum())
+                if isinstance(pool, np.ndarray) and pool.ndim == 1:
+                    prim[k, bad] = pool[rng.integers(0, len(pool), nb)]
+                else:
+                    prim[k, bad] = pool(n)[bad]
+    return prim
+
+
+def _near_infinite_object(scene: Scene, pts: np.ndarray, gids: np.ndarray, margin: float):
+    """True where a point lies within `margin` of the infinite plane or line of
+    the given primitive (input hygiene only: keeps grazing inputs out)."""
+    out = np.zeros(len(gids), dtype=bool)
+    t = scene.type_of(np.maximum(gids, 0))
+    npl, nln = len(scene.planes), len(scene.lines)
+    m = (gids >= 0) & (t == T_PLANE)
+    if m.any():
+        P = scene.planes[gids[m]]
+        out[m] = np.abs(np.einsum("ij,ij->i", P[:, 0:3], pts[m]) - P[:, 3]) < margin
+    m = (gids >= 0) & (t == T_LINE)
+    if m.any():
+        L = scene.lines[gids[m] - npl]
+        w = pts[m] - L[:, 0:3]
+        perp = w - np.einsum("ij,ij->i", w, L[:, 3:6])[:, None] * L[:, 3:6]
+        out[m] = np.linalg.norm(perp, axis=1) < margin
+    return out
+
+
+# ---------------------------------------------------------------- config 1
+def room_scene() -> Scene:
+    """10 x 10 x 3 m room: 6 walls and 2 wall-junction edges, TX at (2,3,1.5)."""
+    L, W, H = 10.0, 10.0, 3.0
+    planes = np.stack([
+        plane_rect([1, 0, 0], 0.0, [0, 0, 0], [0, W, 0], [0, 0, H]),
+        plane_rect([1, 0, 0], L, [L, 0, 0], [0, W, 0], [0, 0, H]),
+        plane_rect([0, 1, 0], 0.0, [0, 0, 0], [L, 0, 0], [0, 0, H]),
+        plane_rect([0, 1, 0], W, [0, W, 0], [L, 0, 0], [0, 0, H]),
+        plane_rect([0, 0, 1], 0.0, [0, 0, 0], [L, 0, 0], [0, W, 0]),
+        plane_rect([0, 0, 1], H, [0, 0, H], [L, 0, 0], [0, W, 0]),
+    ])
+    lines = np.stack([
+        line_seg([0, 0, 0], [0, 0, 1], 0.0, H),      # vertical corner x=0,y=0
+        line_seg([0, W, H], [1, 0, 0], 0.0, L),      # y=10 wall / ceiling junction
+    ])
+    return Scene(tx=np.array([2.0, 3.0, 1.5]), planes=planes, lines=lines,
+                 aabb_lo=np.zeros(3), aabb_hi=np.array([L, W, H]))
+
+
+def config1(n_rx: int = 256) -> tuple[Scene, Batch]:
+    """Room, all sequences of length 1-2 over the 8 objects with no immediate
+    repeat: 8 + 8*7 = 64 per receiver."""
+    sc = room_scene()
+    rng = np.random.default_rng(seed(1, "rx"))
+    rx = np.column_stack([rng.uniform(0.1, 9.9, n_rx), rng.uniform(0.1, 9.9, n_rx),
+                          np.full(n_rx, 1.5)])
+    seqs = [(a,) for a in range(8)] + [(a, b) for a in range(8) for b in range(8) if a != b]
+    per = len(seqs)
+    n = n_rx * per
+    order = np.empty(n, np.int32)
+    prim = np.full((MAX_ORDER, n), -1, np.int32)
+    for j, s in enumerate(seqs):
+        order[j::per] = len(s)
+        for k, g in enumerate(s):
+            prim[k, j::per] = g
+    rx_index = np.repeat(np.arange(n_rx, dtype=np.int32), per)
+    return sc, Batch(rx, rx_index, order, prim)
+
+
+# ---------------------------------------------------------------- config 2
+def street_canyon_scene(cfg: int = 2, n_boxes: int = 50, tx_height: float = 30.0):
+    """Ground [0,200]^2 plus non-overlapping axis-aligned boxes (2 m clearance):
+    per box 4 walls + roof (rectangles) and 4 vertical + 4 roof edges."""
+    rng = np.random.default_rng(seed(cfg, "scene"))
+    size = 200.0
+    boxes = []
+    while len(boxes) < n_boxes:
+        w, d = rng.uniform(10, 30, 2)
+        h = rng.uniform(10, 40)
+        cx = rng.uniform(w / 2, size - w / 2)
+        cy = rng.uniform(d / 2, size - d / 2)
+        if abs(h - tx_height) < 1e-2:
+            continue
+        if all(abs(cx - b[0]) >= (w + b[2]) / 2 + 2 or abs(cy - b[1]) >= (d + b[3]) / 2 + 2
+               for b in boxes):
+            boxes.append((cx, cy, w, d, h))
+    planes = [plane_rect([0, 0, 1], 0.0, [0, 0, 0], [size, 0, 0], [0, size, 0])]
+    lines = []
+    for cx, cy, w, d, h in boxes:
+        x0, x1, y0, y1 = cx - w / 2, cx + w / 2, cy - d / 2, cy + d / 2
+        planes += [
+            plane_rect([1, 0, 0], x0, [x0, y0, 0], [0, d, 0], [0, 0, h]),
+            plane_rect([1, 0, 0], x1, [x1, y0, 0], [0, d, 0], [0, 0, h]),
+            plane_rect([0, 1, 0], y0, [x0, y0, 0], [w, 0, 0], [0, 0, h]),
+            plane_rect([0, 1, 0], y1, [x0, y1, 0], [w, 0, 0], [0, 0, h]),
+            plane_rect([0, 0, 1], h, [x0, y0, h], [w, 0, 0], [0, d, 0]),
+        ]
+        for (x, y) in ((x0, y0), (x1, y0), (x1, y1), (x0, y1)):
+            lines.append(line_seg([x, y, 0], [0, 0, 1], 0.0, h))
+        lines += [line_seg([x0, y0, h], [1, 0, 0], 0.0, w), line_seg([x0, y1, h], [1, 0, 0], 0.0, w),
+                  line_seg([x0, y0, h], [0, 1, 0], 0.0, d), line_seg([x1, y0, h], [0, 1, 0], 0.0, d)]
+    boxes = np.array(boxes)
+
+    def free_xy(r, n, margin=1.0):
+        out = np.empty((0, 2))
+        while len(out) < n:
+            p = r.uniform(0, size, (4 * n + 16, 2))
+            inside = np.zeros(len(p), bool)
+            for cx, cy, w, d, h in boxes:
+                inside |= (np.abs(p[:, 0] - cx) < w / 2 + margin) & (np.abs(p[:, 1] - cy) < d / 2 + margin)
+            out = np.vstack([out, p[~inside]])
+        return out[:n]
+
+    txy = free_xy(rng, 1)[0]
+    sc = Scene(tx=np.array([txy[0], txy[1], tx_height]), planes=np.array(planes),
+               lines=np.array(lines), aabb_lo=np.zeros(3),
+               aabb_hi=np.array([size, size, max(40.0, boxes[:, 4].max())]))
+    sc._boxes = boxes
+    sc._free_xy = free_xy
+    return sc
+
+
+def _resample_near(sc, rx, batch_rx_index, prim, order, rng, pools, margin=1e-3):
+    """Redraw sequence elements whose infinite object passes within `margin` of
+    TX or of the receiver of that solve."""
+    for k in range(MAX_ORDER):
+        for _ in range(100):
+            act = order > k
+            g = prim[k]
+            bad = act & (_near_infinite_object(sc, np.broadcast_to(sc.tx, (len(g), 3)), g, margin)
+                         | _near_infinite_object(sc, rx[batch_rx_index], g, margin))
+            if not bad.any():
+                break
+            nb = int(bad.sum())
+            pool = pools(k)
+            new = pool[rng.integers(0, len(pool), nb)] if isinstance(pool, np.ndarray) else pool(nb)
+            prim[k, bad] = new
+            # keep the no-repeat rule
+            for kk in (k, k + 1):
+                if 0 < kk < MAX_ORDER:
+                    rep = (order > kk) & (prim[kk] == prim[kk - 1])
+                    while rep.any():
+                        pool2 = pools(kk)
+                        nr = int(rep.sum())
+                        prim[kk, rep] = (pool2[rng.integers(0, len(pool2), nr)]
+                                         if isinstance(pool2, np.ndarray) else pool2(nr))
+                        rep = (order > kk) & (prim[kk] == prim[kk - 1])
+    return prim
+
+
+def config2(n_rx: int = 4096, per_rx: int = 64) -> tuple[Scene, Batch]:
+    sc = street_canyon_scene(2)
+    rng = np.random.default_rng(seed(2, "rx"))
+    xy = sc._free_xy(rng, n_rx)
+    rx = np.column_stack([xy, np.full(n_rx, 1.5)])
+    rs = np.random.default_rng(seed(2, "seq"))
+    n = n_rx * per_rx
+    order = rs.integers(1, 4, n).astype(np.int32)
+    pool = np.arange(sc.n_prims, dtype=np.int32)
+    prim = _no_repeat_sequences(rs, n, order, lambda k: pool)
+    rx_index = np.repeat(np.arange(n_rx, dtype=np.int32), per_rx)
+    prim = _resample_near(sc, rx, rx_index, prim, order, rs, lambda k: pool)
+    return sc, Batch(rx, rx_index, order, prim)
+
+
+# ---------------------------------------------------------------- config 3
+def curved_scene(cfg: int = 3, n_quad: int = 200, n_circ: int = 100, rng=None) -> Scene:
+    rng = rng or np.random.default_rng(seed(cfg, "scene"))
+    lo, hi = np.zeros(3), np.array([200.0, 200.0, 40.0])
+    quads = []
+    for _ in range(n_quad):
+        F = rng.uniform(1, 5)
+        v = rng.uniform(lo, hi)
+        ax = _unit(rng.normal(size=3))
+        quads.append(paraboloid(v, ax, F))
+    circs = []
+    for _ in range(n_circ):
+        R = rng.uniform(0.5, 3)
+        c = rng.uniform(lo, hi)
+        nn = _unit(rng.normal(size=3))
+        circs.append(circle(c, nn, R))
+    return Scene(tx=np.array([100.0, 100.0, 20.0]), quadrics=np.array(quads).reshape(-1, QUAD_W),
+                 circles=np.array(circs).reshape(-1, CIRC_W), aabb_lo=lo, aabb_hi=hi)
+
+
+def config3(n_rx: int = 16384, per_rx: int = 64) -> tuple[Scene, Batch]:
+    sc = curved_scene(3)
+    rng = np.random.default_rng(seed(3, "rx"))
+    rx = rng.uniform(sc.aabb_lo, sc.aabb_hi, (n_rx, 3))
+    rs = np.random.default_rng(seed(3, "seq"))
+    n = n_rx * per_rx
+    order = rs.integers(1, 6, n).astype(np.int32)
+    pool = np.arange(sc.n_prims, dtype=np.int32)
+    prim = _no_repeat_sequences(rs, n, order, lambda k: pool)
+    return sc, Batch(rx, np.repeat(np.arange(n_rx, dtype=np.int32), per_rx), order, prim)
+
+
+# ---------------------------------------------------------------- config 5
+def stress_scene() -> Scene:
+    sc = street_canyon_scene(5)
+    q = curved_scene(5, n_quad=30, n_circ=0, rng=np.random.default_rng(seed(5, "scene") + 77))
+    out = Scene(tx=sc.tx, planes=sc.planes, lines=sc.lines, quadrics=q.quadrics,
+                aabb_lo=sc.aabb_lo, aabb_hi=sc.aabb_hi)
+    out._boxes, out._free_xy = sc._boxes, sc._free_xy
+    return out
+
+
+def config5(n_rx: int = 16384, per_rx: int = 1024) -> tuple[Scene, Batch]:
+    """Orders 3-5 with at least two diffractions; diffractions on the box edges,
+    reflections on the facets and the paraboloids."""
+    sc = stress_scene()
+    rng = np.random.default_rng(seed(5, "rx"))
+    xy = sc._free_xy(rng, n_rx)
+    rx = np.column_stack([xy, np.full(n_rx, 1.5)])
+    rs = np.random.default_rng(seed(5, "seq"))
+    n = n_rx * per_rx
+    order = rs.integers(3, 6, n).astype(np.int32)
+    nd = (rs.random(n) * (order - 1)).astype(np.int32) + 2       # U{2..order}
+    npl, nln, nq, _ = sc.counts
+    edges = np.arange(npl, npl + nln, dtype=np.int32)
+    refl = np.concatenate([np.arange(npl, dtype=np.int32),
+                           np.arange(npl + nln, npl + nln + nq, dtype=np.int32)])
+    # choose which slots diffract: random permutation keys, the nd smallest
+    keys = rs.random((MAX_ORDER, n))
+    keys[np.arange(MAX_ORDER)[:, None] >= order[None, :]] = 2.0
+    rank = np.argsort(np.argsort(keys, axis=0), axis=0)
+    is_d = rank < nd[None, :]
+    dpool, rpool = edges, refl
+
+    def slot_pool(k):
+        def draw(m):
+            a = dpool[rs.integers(0, len(dpool), n)]
+            b = rpool[rs.integers(0, len(rpool), n)]
+            return np.where(is_d[k], a, b)
+        return draw
+    prim = _no_repeat_sequences(rs, n, order, slot_pool)
+    return sc, Batch(rx, np.repeat(np.arange(n_rx, dtype=np.int32), per_rx), order, prim)
+
+
+# ---------------------------------------------------------------- paper example
+def fig5_scene() -> tuple[Scene, Batch]:
+    """The two-mirror example of the image-method figure, lifted to 3-D at z=0:
+    mirror 1 on y = x for (0,0)-(3.5,3.5), mirror 2 on x = 5 for y in [0.5,4];
+    BS (2,-1), UE (2,4)."""
+    s2 = np.sqrt(0.5)
+    planes = np.stack([
+        plane_rect([s2, -s2, 0], 0.0, [0, 0, -1], [3.5, 3.5, 0], [0, 0, 2]),
+        plane_rect([1, 0, 0], 5.0, [5, 0.5, -1], [0, 3.5, 0], [0, 0, 2]),
+    ])
+    sc = Scene(tx=np.array([2.0, -1.0, 0.0]), planes=planes,
+               aabb_lo=np.array([-1.0, -1.0, -1.0]), aabb_hi=np.array([11.0, 4.0, 1.0]))
+    b = Batch(np.array([[2.0, 4.0, 0.0]]), np.array([0]), np.array([2]),
+              np.array([[0], [1], [-1], [-1], [-1]]))
+    return sc, b
+
+
+def random_init(scene: Scene, batch: Batch, cfg: int, restart: int = 0) -> np.ndarray:
+    """Random initial points inside the scene box (the paper's random guess),
+    drawn here and passed to both sides as an input."""
+    rng = np.random.default_rng([seed(cfg, "init"), restart])
+    x0 = np.zeros((3 * MAX_ORDER, batch.n))
+    lo, hi = scene.aabb_lo, scene.aabb_hi
+    for k in range(MAX_ORDER):
+        for c in range(3):
+            x0[3 * k + c] = rng.uniform(lo[c], hi[c], batch.n)
+    return x0
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
