@@ -1,0 +1,227 @@
+/*
+ * mpt.h - C ABI of the MI355X (gfx950) batched Min-Path-Tracing solver.
+ *
+ * The library solves, for every candidate path of a batch, the small
+ * nonlinear minimisation of Sec. III-B of the paper (Eqs. (8)-(12)): the
+ * unknowns are the interaction points X_1..X_n (n <= 5) on the listed objects
+ * (planes and quadric surfaces reflect, straight and circular edges
+ * diffract); the cost stacks the reflection law (Eq. 8), the Keller-cone
+ * diffraction law (Eq. 9) and the implicit object equations (Eq. 11).  A path
+ * exists iff the minimum is zero (Eq. 12); it is kept iff the cost is below
+ * a threshold and every point lies on the finite object (Alg. 1, the
+ * acceptance test after find_minimum_path).
+ *
+ * Conventions
+ *  - Every function returns an mpt_status; no C++ exception crosses the ABI.
+ *    On failure mpt_last_error() describes the problem.
+ *  - A bad *path* is not a call error: it gets a per-solve status code.
+ *  - Units are metres in a right-handed world frame.  The signs of normals
+ *    and edge directions are irrelevant (Eq. 1 is even in n, Eq. 3 flips
+ *    both sides).
+ *  - Scene memory belongs to the context.  Batch and output buffers are
+ *    device pointers owned by the caller and never freed by the library.
+ *  - Work is enqueued on the context's HIP stream and is asynchronous unless
+ *    a function says it synchronises.  One context per host thread.
+ */
+#ifndef MPT_H
+#define MPT_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpt_ctx mpt_ctx;
+
+typedef enum {
+    MPT_OK = 0,
+    MPT_E_INVALID_ARG = 1,   /* null pointer, bad size, non-finite scene value */
+    MPT_E_NOMEM = 2,         /* device allocation failed or over the ctx cap    */
+    MPT_E_DEVICE = 3,        /* a HIP call failed                               */
+    MPT_E_NO_SCENE = 4,      /* solve/accept before mpt_scene_upload            */
+    MPT_E_UNSUPPORTED = 5,   /* option value not implemented                    */
+    MPT_E_NO_MODEL = 6       /* learned start requested without a network       */
+} mpt_status;
+
+/* Per-solve status codes (uint8).  Bit 7 (MPT_PATH_FALLBACK) marks a solve
+ * that was re-solved by the plain FP64 solver after the FP32 stage. */
+enum {
+    MPT_PATH_CONVERGED = 0,  /* stationary with |R|_inf <= tau_root: a root     */
+    MPT_PATH_MAXITER = 1,    /* iteration cap reached                           */
+    MPT_PATH_STALLED = 2,    /* damping grew past 1e12 x max diag(J^T J)        */
+    MPT_PATH_DIVERGED = 3,   /* start point outside the guard box               */
+    MPT_PATH_DEGENERATE = 4, /* zero-length segment, zero gradient, circle axis */
+    MPT_PATH_BAD_INPUT = 5,  /* order outside 1..5, bad id, non-finite input    */
+    MPT_PATH_LOCALMIN = 6,   /* stationary but |R|_inf > tau_root: no path      */
+    MPT_PATH_FALLBACK = 0x80
+};
+
+enum { MPT_PLANE = 0, MPT_LINE = 1, MPT_QUADRIC = 2, MPT_CIRCLE = 3 };
+enum { MPT_MAX_ORDER = 5 };
+
+/* Record widths (doubles) of the host scene arrays. */
+enum { MPT_PLANE_W = 13, MPT_LINE_W = 8, MPT_QUADRIC_W = 17, MPT_CIRCLE_W = 7 };
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (for example the caller's current stream), or NULL for a
+ * context-owned stream.  *out receives the context. */
+mpt_status mpt_create(int device, void *hip_stream, mpt_ctx **out);
+/* Release every device buffer of the context (synchronises its stream). */
+mpt_status mpt_destroy(mpt_ctx *ctx);
+/* Text of the last error on this context; valid until the next call. */
+const char *mpt_last_error(const mpt_ctx *ctx);
+/* Replace the stream work is enqueued on (NULL: the context's own). */
+mpt_status mpt_set_stream(mpt_ctx *ctx, void *hip_stream);
+/* Block until all work enqueued by the context has finished. */
+mpt_status mpt_synchronize(mpt_ctx *ctx);
+
+/*
+ * Scene: the object database D of Alg. 1 (Sec. II: one implicit equation per
+ * object, infinite first, the finite extent kept for validation) and the
+ * transmitter (the paper's BS).  Host FP64 arrays, row-major records:
+ *   planes   [n_planes][13]   n(3) unit normal, d (n.x = d), o(3) corner,
+ *                             eu(3), ev(3) rectangle sides (full length)
+ *   lines    [n_lines][8]     p(3), e(3) unit direction, s0, s1 (extent)
+ *   quadrics [n_quadrics][17] p(3) anchor, A(6) = xx,xy,xz,yy,yz,zz,
+ *                             b(3), c with f = (x-p)^T A (x-p) + b^T(x-p) + c,
+ *                             ax(3) patch axis, r_ap patch radius about ax
+ *   circles  [n_circles][7]   c(3) centre, n(3) unit plane normal, R
+ * Global primitive ids are type-major: planes, lines, quadrics, circles.
+ * aabb_lo/hi bound the scene; the guard box is that box scaled 10x about
+ * its centre plus 1 m.  The arrays are copied (and packed by a device
+ * kernel into the solver's FP64 and TX-local FP32 records); the caller keeps
+ * ownership.  Errors: MPT_E_INVALID_ARG for non-finite values, non-unit
+ * directions (|1-|v|| > 1e-9) or a non-positive radius.  Synchronises. */
+typedef struct {
+    double tx[3];
+    double aabb_lo[3], aabb_hi[3];
+    int32_t n_planes, n_lines, n_quadrics, n_circles;
+    const double *planes, *lines, *quadrics, *circles;
+} mpt_scene_desc;
+mpt_status mpt_scene_upload(mpt_ctx *ctx, const mpt_scene_desc *scene);
+
+/*
+ * A batch of candidate paths: the interaction lists L of Sec. II (one per
+ * solve) with their receiver (the paper's UE).  All pointers are DEVICE
+ * pointers owned by the caller:
+ *   rx        [n_rx][3] FP64 receiver positions
+ *   rx_index  [n] int32 receiver of each solve
+ *   order     [n] int32 number of interactions n_t, 1..5
+ *   prim      [5][n] int32 global primitive ids (component-major; entries
+ *             beyond the order are ignored)
+ *   x0        [15][n] FP64 start points for MPT_INIT_USER, else NULL
+ */
+typedef struct {
+    int64_t n;
+    int32_t n_rx;
+    const double *rx;
+    const int32_t *rx_index;
+    const int32_t *order;
+    const int32_t *prim;
+    const double *x0;
+} mpt_batch_desc;
+
+enum { MPT_FP64_PLAIN = 0, MPT_FP32_POLISH64 = 1 };
+enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2 };
+enum { MPT_FALLBACK_NONE = 0, MPT_FALLBACK_GPU_FP64 = 1 };
+enum { MPT_SCHED_GRID = 0, MPT_SCHED_PERSISTENT = 1 };
+
+/* Solver options; mpt_default_opts fills the defaults noted here. */
+typedef struct {
+    int32_t precision;     /* MPT_FP32_POLISH64                                 */
+    int32_t init;          /* MPT_INIT_LINE: the projection onto each object of
+                              the point k/(n+1) of the way from TX to RX        */
+    int32_t max_iter;      /* 200  FP64 Levenberg-Marquardt cap                 */
+    int32_t max_iter32;    /* 100  FP32 stage cap                               */
+    int32_t polish_steps;  /* 5    FP64 Gauss-Newton polish steps at most       */
+    int32_t fallback;      /* MPT_FALLBACK_GPU_FP64                             */
+    int32_t plateau_win;   /* 10   window of the plateau test (0: off)          */
+    int32_t sched;         /* MPT_SCHED_PERSISTENT                              */
+    int32_t block;         /* 0: autotuned threads per block                    */
+    int32_t grid;          /* 0: autotuned blocks (persistent schedule)         */
+    double plateau_frac;   /* 0.999 the cost must fall below frac x its value
+                              one window earlier, else the descent ends         */
+    double tol_step;       /* 1e-12 stop when |dx|_inf <= tol_step (1+|x|_inf)  */
+    double tol_res;        /* 1e-13 stop when |R|_inf <= tol_res (metres)       */
+    double tau_root;       /* 1e-9  a stationary point is a root iff |R|_inf <= */
+    double lambda0;        /* 1e-3  initial damping / max diag(J^T J)           */
+    double tol_step32;     /* 1e-6  FP32 stage step tolerance (relative)        */
+    double tol_res32;      /* 1e-5  FP32 stage residual tolerance (metres)      */
+    double polish_gate;    /* 1e-2  FP32 end points with |R|_inf above this are
+                              final (no path); below it they are polished       */
+} mpt_solve_opts;
+void mpt_default_opts(mpt_solve_opts *opts);
+
+/* Outputs, DEVICE pointers owned by the caller:
+ *   x      [15][n] FP64 points (component-major, zero beyond 3*order)
+ *   cost   [n] FP64 final cost C = |R|^2 (Eq. 12 with the rescaled rows)
+ *   iters  [n] int32 iterations run (FP32 + polish + fallback)
+ *   status [n] uint8 MPT_PATH_* code, bit 7 = fallback used               */
+typedef struct {
+    double *x;
+    double *cost;
+    int32_t *iters;
+    uint8_t *status;
+} mpt_solve_out;
+
+/*
+ * find_minimum_path of Alg. 1 for every solve of the batch (Sec. III-B,
+ * Eq. 12): Levenberg-Marquardt on the rescaled residual, in FP64
+ * (MPT_FP64_PLAIN) or in FP32 in a frame centred on TX followed by an FP64
+ * Gauss-Newton polish (MPT_FP32_POLISH64), with the plain FP64 solver as
+ * fallback for solves the FP32 stage leaves ambiguous.  Solves are binned by
+ * order and run by one persistent launch.  Asynchronous.
+ * Errors: MPT_E_NO_SCENE, MPT_E_INVALID_ARG (null pointer, n < 0, n_rx < 1),
+ * MPT_E_NO_MODEL (learned start without a network), MPT_E_NOMEM.
+ */
+mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_opts *opts,
+                           const mpt_solve_out *out);
+
+/*
+ * The acceptance test of Alg. 1 ("C < threshold and X is valid") in FP64 on
+ * solve outputs: accept[i] = 1 iff status is CONVERGED (bit 7 ignored),
+ * |R(x)|_inf <= tau_res, every segment is at least min_seg long and every
+ * point lies in its finite extent (closed sets: rectangle, edge segment,
+ * paraboloid patch radius; a circle is its own extent).  Writes accept [n]
+ * uint8, the accepted ids in increasing order into accepted_idx [n] int32 and
+ * their count into d_count (device int32).  If h_count is not NULL the call
+ * synchronises and stores the count there.  All array pointers are device
+ * pointers owned by the caller.
+ */
+mpt_status mpt_accept(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_out *in,
+                      double tau_res, double min_seg, uint8_t *accept, int32_t *accepted_idx,
+                      int32_t *d_count, int64_t *h_count);
+
+/*
+ * Learned warm start (replaces the random guess of Alg. 1 by a network's
+ * prediction).  Network: 96 features -> 256 -> 256 -> 256 -> 15 with GELU,
+ * BF16 weights and activations, FP32 accumulation on the matrix cores; FP32
+ * master weights and Adam state live in the context.  Features are built on
+ * the device in a frame centred on TX and scaled by 1/|RX-TX|; the outputs
+ * are the points in that frame.
+ */
+/* Initialise the network with seeded random weights. */
+mpt_status mpt_mlp_init(mpt_ctx *ctx, uint64_t seed);
+/* One Adam step of the masked mean-squared error between the predicted and
+ * the target points of the given solves (targets: x [15][n] FP64 device, the
+ * solver's converged points; mask: rows beyond each order and solves whose
+ * `use` flag (uint8 [n], may be NULL = all) is zero are ignored).  *d_loss
+ * (device FP32, may be NULL) receives the loss before the step. */
+mpt_status mpt_mlp_train_step(mpt_ctx *ctx, const mpt_batch_desc *batch, const double *target_x,
+                              const uint8_t *use, float lr, float *d_loss);
+/* Predicted points [15][n] FP64 world frame (device, caller-owned). */
+mpt_status mpt_mlp_predict(mpt_ctx *ctx, const mpt_batch_desc *batch, double *x_out);
+/* Serialise / restore the network (FP32 master weights and Adam state).
+ * mpt_mlp_save with blob = NULL stores the needed size in *bytes. */
+mpt_status mpt_mlp_save(mpt_ctx *ctx, void *blob, size_t *bytes);
+mpt_status mpt_mlp_load(mpt_ctx *ctx, const void *blob, size_t bytes);
+
+/* Per-stage timings of the last mpt_solve_batch in milliseconds (HIP
+ * events; synchronises): [0] bin, [1] learned start, [2] solve, [3] fallback. */
+mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,388 @@
+// Device-side math of the batched Min-Path-Tracing solve (gfx950).
+//
+// One lane owns one candidate path.  Everything a Levenberg-Marquardt
+// iteration needs lives in that lane's registers: the points X_1..X_N, the
+// block-banded normal equations and their Cholesky factor.  The order N is a
+// template parameter so every loop unrolls and every index is a constant.
+//
+// Paper, Sec. III-B: the residual of interaction k depends on X_{k-1}, X_k,
+// X_{k+1} only, so J is block-tridiagonal and J^T J block-pentadiagonal with
+// 3x3 blocks (the tridiagonal structure the conclusion suggests exploiting).
+// Only the 93 (N = 5) in-band entries of J^T J are ever touched.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpt {
+
+constexpr int kRec = 18;        // doubles / floats per packed primitive record
+constexpr int kMaxN = 5;
+
+enum : int { TP = 0, TL = 1, TQ = 2, TC = 3 };
+enum : int { ST_CONV = 0, ST_MAXIT = 1, ST_STALL = 2, ST_DIVERGED = 3, ST_DEGEN = 4,
+             ST_BAD = 5, ST_LOCALMIN = 6, ST_RUNNING = 255 };
+
+// Packed record layout (kRec wide), written by the scene pack kernel:
+//  plane   : n[0..2] d[3] o[4..6] eu[7..9] ev[10..12]
+//  line    : p[0..2] e[3..5] s0[6] s1[7] u1[8..10] u2[11..13]
+//  quadric : p[0..2] A[3..8] (xx xy xz yy yz zz) b[9..11] c[12] ax[13..15] rap[16]
+//  circle  : c[0..2] n[3..5] R[6]
+
+template <typename T>
+struct SceneT {
+    const T *rec;      // [n_prims][kRec]
+    int n_pl, n_pl_ln, n_pl_ln_q, n_all;
+    T tx[3];           // transmitter in this frame (0 in the TX-local frame)
+    T glo[3], ghi[3];  // guard box
+};
+
+__device__ __forceinline__ int prim_type(int id, int a, int b, int c)
+{
+    return (id < a) ? TP : (id < b) ? TL : (id < c) ? TQ : TC;
+}
+
+template <typename T> __device__ __forceinline__ T dsqrt(T x);
+template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <typename T> __device__ __forceinline__ T drcp(T x) { return T(1) / x; }
+
+template <typename T>
+__device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// -------------------------------------------------------------------------
+// Rows of one interaction (5 slots: 0..2 law rows, 3..4 object rows; unused
+// slots are exactly zero with zero derivatives).  Law rows are the unit-form
+// laws scaled by S = (|i| + |r|)/2 (metres):
+//   reflection  S (r^ - i^ + 2 <i^,n^> n^)                (Eqs. 1, 2, 8)
+//   diffraction S <i^ - r^, e^>                           (Eqs. 3, 4, 9)
+// object rows: f(X) for a surface; for a straight edge the two coordinates
+// across the line; for a circle the distance to its plane and
+// (|X-c|^2 - R^2)/(2R)                                     (Eq. 11)
+// Derivative blocks: Jp = d/dX_{k-1} (law rows), Jk = d/dX_k (all rows),
+// Jn = d/dX_{k+1} (law rows).
+// Returns false when a direction is undefined (degenerate).
+// -------------------------------------------------------------------------
+template <typename T, bool WITH_J>
+__device__ __forceinline__ bool interaction_rows(int t, const T *__restrict__ r, const T *Xp, const T *Xk,
+                                                 const T *Xn, T u[5], T Jp[3][3], T Jk[5][3], T Jn[3][3])
+{
+    // No early exits: an undefined direction sets valid = false and the
+    // arithmetic continues on a harmless substitute value.
+    bool valid = true;
+    T a[3], b[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) { a[i] = Xk[i] - Xp[i]; b[i] = Xn[i] - Xk[i]; }
+    T la2 = dot3(a, a), lb2 = dot3(b, b);
+    valid = valid && (la2 > T(0)) && (lb2 > T(0));
+    la2 = (la2 > T(0)) ? la2 : T(1);
+    lb2 = (lb2 > T(0)) ? lb2 : T(1);
+    const T la = dsqrt(la2), lb = dsqrt(lb2);
+    const T ia = drcp(la), ib = drcp(lb);
+    T ih[3], rh[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) { ih[i] = a[i] * ia; rh[i] = b[i] * ib; }
+    const T S = T(0.5) * (la + lb);
+    const bool surf = (t == TP) || (t == TQ);
+    const bool quad = (t == TQ);
+
+    if (surf) {
+        // plane: g = n, f = n.X - d.  quadric: w = X - p, g = 2 A w + b,
+        // f = w^T A w + b^T w + c.  A = [[a0 a1 a2][a1 a3 a4][a2 a4 a5]]
+        const T a0 = quad ? r[3] : T(0), a1 = quad ? r[4] : T(0), a2 = quad ? r[5] : T(0);
+        const T a3 = quad ? r[6] : T(0), a4 = quad ? r[7] : T(0), a5 = quad ? r[8] : T(0);
+        T g[3], f;
+        {
+            const T w0 = Xk[0] - r[0], w1 = Xk[1] - r[1], w2 = Xk[2] - r[2];
+            const T Aw0 = a0 * w0 + a1 * w1 + a2 * w2;
+            const T Aw1 = a1 * w0 + a3 * w1 + a4 * w2;
+            const T Aw2 = a2 * w0 + a4 * w1 + a5 * w2;
+            if (quad) {
+                f = w0 * Aw0 + w1 * Aw1 + w2 * Aw2 + r[9] * w0 + r[10] * w1 + r[11] * w2 + r[12];
+                g[0] = T(2) * Aw0 + r[9];
+                g[1] = T(2) * Aw1 + r[10];
+                g[2] = T(2) * Aw2 + r[11];
+            } else {
+                f = r[0] * Xk[0] + r[1] * Xk[1] + r[2] * Xk[2] - r[3];
+                g[0] = r[0];
+                g[1] = r[1];
+                g[2] = r[2];
+            }
+        }
+        T lg2 = dot3(g, g);
+        valid = valid && (lg2 > T(0));
+        lg2 = (lg2 > T(0)) ? lg2 : T(1);
+        const T ig = drcp(dsqrt(lg2));
+        const T nh[3] = {g[0] * ig, g[1] * ig, g[2] * ig};
+        const T s = dot3(ih, nh);
+        T ul[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) ul[i] = rh[i] - ih[i] + T(2) * s * nh[i];
+#pragma unroll
+        for (int i = 0; i < 3; i++) u[i] = S * ul[i];
+        u[3] = f;
+        u[4] = T(0);
+        if (WITH_J) {
+            // (Q Pa)_ij = Pa_ij - nh_i m_j with m = 2 (nh - s ih)/|a|
+            T m[3];
+#pragma unroll
+            for (int j = 0; j < 3; j++) m[j] = T(2) * (nh[j] - s * ih[j]) * ia;
+            // curvature: Nm = (I - nh nh^T) B, B = 2A/|g|; TN = 2 (nh ih^T + s I) Nm
+            //   = 2 nh q^T + 2 s (B - nh v^T), v = B nh, q = B ih - s v
+            const T c2 = T(2) * ig;
+            const T b0 = c2 * a0, b1 = c2 * a1, b2 = c2 * a2, b3 = c2 * a3, b4 = c2 * a4, b5 = c2 * a5;
+            const T v[3] = {b0 * nh[0] + b1 * nh[1] + b2 * nh[2], b1 * nh[0] + b3 * nh[1] + b4 * nh[2],
+                            b2 * nh[0] + b4 * nh[1] + b5 * nh[2]};
+            const T q[3] = {b0 * ih[0] + b1 * ih[1] + b2 * ih[2] - s * v[0],
+                            b1 * ih[0] + b3 * ih[1] + b4 * ih[2] - s * v[1],
+                            b2 * ih[0] + b4 * ih[1] + b5 * ih[2] - s * v[2]};
+            const T Bm[3][3] = {{b0, b1, b2}, {b1, b3, b4}, {b2, b4, b5}};
+            const T s2 = T(2) * s;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    const T tn = T(2) * nh[i] * q[j] + s2 * (Bm[i][j] - nh[i] * v[j]);
+                    const T pa = ((i == j) ? ia : T(0)) - ih[i] * ih[j] * ia;
+                    const T pb = ((i == j) ? ib : T(0)) - rh[i] * rh[j] * ib;
+                    const T qpa = pa - nh[i] * m[j];
+                    // product rule with dS: dS/dX_{k-1} = -ih/2, dS/dX_k = (ih - rh)/2, dS/dX_{k+1} = rh/2
+                    Jp[i][j] = S * qpa - T(0.5) * ul[i] * ih[j];
+                    Jn[i][j] = S * pb + T(0.5) * ul[i] * rh[j];
+                    Jk[i][j] = S * (tn - pb - qpa) + T(0.5) * ul[i] * (ih[j] - rh[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 3; j++) { Jk[3][j] = g[j]; Jk[4][j] = T(0); }
+        }
+    } else {
+        const bool circ = (t == TC);
+        const T d[3] = {Xk[0] - r[0], Xk[1] - r[1], Xk[2] - r[2]};
+        const T dv[3] = {ih[0] - rh[0], ih[1] - rh[1], ih[2] - rh[2]};
+        // line: e fixed, rows across the line.  circle: e = n x d / |n x d|,
+        // rows <d,n> and (|d|^2 - R^2)/(2R)
+        const T n0 = r[3], n1 = r[4], n2 = r[5];
+        const T w[3] = {n1 * d[2] - n2 * d[1], n2 * d[0] - n0 * d[2], n0 * d[1] - n1 * d[0]};
+        T lw2 = dot3(w, w);
+        valid = valid && (!circ || (lw2 > T(0)));
+        lw2 = (lw2 > T(0)) ? lw2 : T(1);
+        const T iw = drcp(dsqrt(lw2));
+        T e[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) e[i] = circ ? w[i] * iw : r[3 + i];
+        const T R = circ ? r[6] : T(1), iR = drcp(R);
+        T go0[3], go1[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            go0[j] = circ ? r[3 + j] : r[8 + j];
+            go1[j] = circ ? d[j] * iR : r[11 + j];
+        }
+        const T o0 = dot3(d, go0);
+        const T o1 = circ ? (dot3(d, d) - R * R) * (T(0.5) * iR) : dot3(d, go1);
+        const T u0 = dot3(dv, e);
+        u[0] = S * u0;
+        u[1] = T(0);
+        u[2] = T(0);
+        u[3] = o0;
+        u[4] = o1;
+        if (WITH_J) {
+            // circle: dv^T de/dX = (dv x n - <dv,e> (e x n)) / |w|; line: 0
+            const T dxn[3] = {dv[1] * n2 - dv[2] * n1, dv[2] * n0 - dv[0] * n2, dv[0] * n1 - dv[1] * n0};
+            const T exn[3] = {e[1] * n2 - e[2] * n1, e[2] * n0 - e[0] * n2, e[0] * n1 - e[1] * n0};
+            const T ei = dot3(e, ih), er = dot3(e, rh);
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const T dvE = circ ? (dxn[j] - u0 * exn[j]) * iw : T(0);
+                const T ePa = (e[j] - ei * ih[j]) * ia;
+                const T ePb = (e[j] - er * rh[j]) * ib;
+                Jp[0][j] = -S * ePa - T(0.5) * u0 * ih[j];
+                Jn[0][j] = -S * ePb + T(0.5) * u0 * rh[j];
+                Jk[0][j] = S * (ePa + ePb + dvE) + T(0.5) * u0 * (ih[j] - rh[j]);
+#pragma unroll
+                for (int i = 1; i < 3; i++) { Jp[i][j] = T(0); Jn[i][j] = T(0); Jk[i][j] = T(0); }
+                Jk[3][j] = go0[j];
+                Jk[4][j] = go1[j];
+            }
+        }
+    }
+    return valid;
+}
+
+// ------------------------------------------------------------------ band
+template <int N>
+struct Band {
+    static constexpr int M = 3 * N;
+    static constexpr int SIZE = M * (M + 1) / 2;
+    __host__ __device__ static constexpr bool in(int i, int j) { return i >= j && (i / 3 - j / 3) <= 2; }
+    __host__ __device__ static constexpr int at(int i, int j) { return i * (i + 1) / 2 + j; }
+};
+
+// Per-solve inputs as seen by the solver (in the solver's frame).
+template <typename T, int N>
+struct PathIn {
+    T rx[3];
+    int id[N];
+    int ty[N];
+};
+
+// Points of interaction k for the residual evaluated at X + dx (dx may be
+// null): X_0 = TX, X_{N+1} = RX.
+template <typename T, int N>
+__device__ __forceinline__ void point_at(int k, const T *X, const T *dx, const T *tx, const T *rx, T out[3])
+{
+    if (k < 0) { out[0] = tx[0]; out[1] = tx[1]; out[2] = tx[2]; return; }
+    if (k >= N) { out[0] = rx[0]; out[1] = rx[1]; out[2] = rx[2]; return; }
+#pragma unroll
+    for (int i = 0; i < 3; i++) out[i] = X[3 * k + i] + (dx ? dx[3 * k + i] : T(0));
+}
+
+// Residual cost and inf-norm at X (+dx).  Returns false if degenerate.
+template <typename T, int N>
+__device__ __forceinline__ bool eval_cost(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X, const T *dx,
+                                          T &C, T &rinf)
+{
+    C = T(0);
+    rinf = T(0);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        T Xp[3], Xk[3], Xn[3], u[5];
+        point_at<T, N>(k - 1, X, dx, sc.tx, p.rx, Xp);
+        point_at<T, N>(k, X, dx, sc.tx, p.rx, Xk);
+        point_at<T, N>(k + 1, X, dx, sc.tx, p.rx, Xn);
+        const bool okk = interaction_rows<T, false>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xk, Xn, u,
+                                                    nullptr, nullptr, nullptr);
+        ok = ok && okk;
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            C += u[i] * u[i];
+            rinf = fmax(rinf, fabs(u[i]));
+        }
+    }
+    return ok;
+}
+
+// Residual, J^T J (in-band, packed lower) and g = J^T R at X.
+template <typename T, int N>
+__device__ __forceinline__ bool assemble(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X,
+                                         T *A, T *g, T &C, T &rinf)
+{
+    constexpr int M = 3 * N;
+#pragma unroll
+    for (int i = 0; i < M; i++)
+#pragma unroll
+        for (int j = 0; j <= i; j++)
+            if (Band<N>::in(i, j)) A[Band<N>::at(i, j)] = T(0);
+#pragma unroll
+    for (int i = 0; i < M; i++) g[i] = T(0);
+    C = T(0);
+    rinf = T(0);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        T Xp[3], Xk[3], Xn[3], u[5], Jp[3][3], Jk[5][3], Jn[3][3];
+        point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
+        point_at<T, N>(k, X, nullptr, sc.tx, p.rx, Xk);
+        point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
+        const bool okk = interaction_rows<T, true>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xk, Xn, u, Jp, Jk, Jn);
+        ok = ok && okk;
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            C += u[i] * u[i];
+            rinf = fmax(rinf, fabs(u[i]));
+        }
+        // law rows couple blocks k-1, k, k+1
+#pragma unroll
+        for (int row = 0; row < 3; row++) {
+            T jr[9];
+#pragma unroll
+            for (int c = 0; c < 3; c++) { jr[c] = Jp[row][c]; jr[3 + c] = Jk[row][c]; jr[6 + c] = Jn[row][c]; }
+#pragma unroll
+            for (int bi = 0; bi < 3; bi++) {
+                const int Bi = k - 1 + bi;
+                if (Bi < 0 || Bi >= N) continue;
+#pragma unroll
+                for (int ci = 0; ci < 3; ci++) {
+                    const int gi = 3 * Bi + ci;
+                    g[gi] += jr[3 * bi + ci] * u[row];
+#pragma unroll
+                    for (int bj = 0; bj < 3; bj++) {
+                        const int Bj = k - 1 + bj;
+                        if (Bj < 0 || Bj >= N) continue;
+#pragma unroll
+                        for (int cj = 0; cj < 3; cj++) {
+                            const int gj = 3 * Bj + cj;
+                            if (gj > gi) continue;
+                            A[Band<N>::at(gi, gj)] += jr[3 * bi + ci] * jr[3 * bj + cj];
+                        }
+                    }
+                }
+            }
+        }
+        // object rows touch block k only
+#pragma unroll
+        for (int row = 3; row < 5; row++) {
+#pragma unroll
+            for (int ci = 0; ci < 3; ci++) {
+                const int gi = 3 * k + ci;
+                g[gi] += Jk[row][ci] * u[row];
+#pragma unroll
+                for (int cj = 0; cj <= ci; cj++) A[Band<N>::at(gi, 3 * k + cj)] += Jk[row][ci] * Jk[row][cj];
+            }
+        }
+    }
+    return ok;
+}
+
+// In-place banded Cholesky of the packed lower band; false if not SPD.
+template <typename T, int N>
+__device__ __forceinline__ bool chol_band(T *A)
+{
+    constexpr int M = 3 * N;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < M; j++) {
+        T d = A[Band<N>::at(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; k++)
+            if (Band<N>::in(j, k)) d -= A[Band<N>::at(j, k)] * A[Band<N>::at(j, k)];
+        ok = ok && (d > T(0));
+        d = dsqrt(d > T(0) ? d : T(1));
+        A[Band<N>::at(j, j)] = d;
+        const T inv = drcp(d);
+#pragma unroll
+        for (int i = j + 1; i < M; i++) {
+            if (!Band<N>::in(i, j)) continue;
+            T v = A[Band<N>::at(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; k++)
+                if (Band<N>::in(i, k) && Band<N>::in(j, k)) v -= A[Band<N>::at(i, k)] * A[Band<N>::at(j, k)];
+            A[Band<N>::at(i, j)] = v * inv;
+        }
+    }
+    return ok;
+}
+
+// Solve L L^T x = b in place (b -> x).
+template <typename T, int N>
+__device__ __forceinline__ void chol_solve_band(const T *L, T *b)
+{
+    constexpr int M = 3 * N;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        T v = b[i];
+#pragma unroll
+        for (int k = 0; k < i; k++)
+            if (Band<N>::in(i, k)) v -= L[Band<N>::at(i, k)] * b[k];
+        b[i] = v / L[Band<N>::at(i, i)];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; i--) {
+        T v = b[i];
+#pragma unroll
+        for (int k = i + 1; k < M; k++)
+            if (Band<N>::in(k, i)) v -= L[Band<N>::at(k, i)] * b[k];
+        b[i] = v / L[Band<N>::at(i, i)];
+    }
+}
+
+}  // namespace mpt

@@ -1,0 +1,76 @@
+// Internal interfaces shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "mpt_device.hpp"
+
+namespace mpt {
+
+enum : int { MODE_PLAIN64 = 0, MODE_FP32 = 1, MODE_FALLBACK64 = 2 };
+enum : int { INIT_LINE = 0, INIT_USER = 1, INIT_LEARNED = 2 };
+
+// Scene as the kernels see it (device pointers).
+struct SceneDev {
+    const double *rec64;  // [n_all][kRec] world frame
+    const float *rec32;   // [n_all][kRec] TX-local frame
+    int n_pl, n_pl_ln, n_pl_ln_q, n_all;
+    double tx[3];
+    double glo[3], ghi[3];
+};
+
+struct BatchDev {
+    int64_t n;
+    int n_rx;
+    const double *rx;
+    const int *rx_index;
+    const int *order;
+    const int *prim;
+    const double *x0;
+};
+
+struct OutDev {
+    double *x;
+    double *cost;
+    int *iters;
+    uint8_t *status;
+};
+
+struct OutDevC {
+    const double *x;
+    const double *cost;
+    const int *iters;
+    const uint8_t *status;
+};
+
+struct OptsDev {
+    int init, max_iter, max_iter32, polish_steps, fallback, plateau_win;
+    double plateau_frac, tol_step, tol_res, tau_root, lambda0, tol_step32, tol_res32, polish_gate;
+};
+
+// Everything a solver kernel needs, passed by value.
+struct KParams {
+    SceneDev s;
+    BatchDev b;
+    OutDev out;
+    OptsDev o;
+    const double *x0_learned;  // [15][n] network start points (world)
+    const int *bin_cnt;        // [5] solves per order
+    const int *perm;           // [n] solve ids grouped by order
+    int *head;                 // [10] work counters: bins, fallback lists
+    int *pol_cnt;              // [5]
+    int *pol_list;             // [n] polish lists (bin-relative slots)
+    int *fb_cnt;               // [5]
+    int *fb_list;              // [n] fallback lists (bin-relative slots)
+};
+
+void launch_pack(const double *raw, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c, hipStream_t st);
+void launch_zero(int *p, int n, hipStream_t st);
+void launch_bin(const BatchDev &b, const OutDev &out, int n_all, int *cnt, int *cursor, int *perm, hipStream_t st);
+const void *lm_kernel(int mode, int order);
+void launch_lm(int mode, int order, const KParams &kp, int grid, int block, hipStream_t st);
+const void *polish_kernel();
+void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
+void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
+                   uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st);
+
+}  // namespace mpt

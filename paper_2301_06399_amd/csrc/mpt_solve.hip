@@ -1,0 +1,778 @@
+// Solver kernels of the batched Min-Path-Tracing solve (gfx950, wave64).
+//
+//  k_pack            scene records -> packed FP64 world + FP32 TX-local records
+//  k_bin_count       histogram of path orders (invalid solves finished here)
+//  k_bin_scatter     solve ids grouped by order (one bin per order)
+//  k_lm              persistent Levenberg-Marquardt over the bins, one lane per
+//                    path, lanes refilled from a per-wave chunk of the bin as
+//                    soon as their path finishes (FP64 plain, FP32 stage or FP64
+//                    fallback)
+//  k_polish          FP64 Gauss-Newton polish of the FP32 end points
+//  k_accept_*        FP64 acceptance test and ordered compaction
+#include "mpt_internal.hpp"
+
+namespace mpt {
+
+// ------------------------------------------------------------------ pack
+// Ortho-normal pair across a unit vector (Duff et al., "Building an
+// orthonormal basis, revisited", JCGT 2017).
+__device__ inline void onb(const double *n, double *u1, double *u2)
+{
+    const double sgn = n[2] >= 0.0 ? 1.0 : -1.0;
+    const double a = -1.0 / (sgn + n[2]);
+    const double b = n[0] * n[1] * a;
+    u1[0] = 1.0 + sgn * n[0] * n[0] * a; u1[1] = sgn * b; u1[2] = -sgn * n[0];
+    u2[0] = b; u2[1] = sgn + n[1] * n[1] * a; u2[2] = -n[1];
+}
+
+__global__ void k_pack(const double *__restrict__ raw, int n_pl, int n_ln, int n_q, int n_c, double tx0, double tx1,
+                       double tx2, double *__restrict__ rec64, float *__restrict__ rec32)
+{
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n_all = n_pl + n_ln + n_q + n_c;
+    if (id >= n_all) return;
+    const double tx[3] = {tx0, tx1, tx2};
+    double o[kRec];
+#pragma unroll
+    for (int i = 0; i < kRec; i++) o[i] = 0.0;
+    // raw arrays are concatenated type-major with their own widths
+    const int t = prim_type(id, n_pl, n_pl + n_ln, n_pl + n_ln + n_q);
+    size_t off;
+    if (t == TP) off = (size_t)id * 13;
+    else if (t == TL) off = (size_t)n_pl * 13 + (size_t)(id - n_pl) * 8;
+    else if (t == TQ) off = (size_t)n_pl * 13 + (size_t)n_ln * 8 + (size_t)(id - n_pl - n_ln) * 17;
+    else off = (size_t)n_pl * 13 + (size_t)n_ln * 8 + (size_t)n_q * 17 + (size_t)(id - n_pl - n_ln - n_q) * 7;
+    const double *r = raw + off;
+    const int w = (t == TP) ? 13 : (t == TL) ? 8 : (t == TQ) ? 17 : 7;
+    for (int i = 0; i < w; i++) o[i] = r[i];
+    if (t == TL) onb(r + 3, o + 8, o + 11);
+    for (int i = 0; i < kRec; i++) rec64[(size_t)id * kRec + i] = o[i];
+    // TX-local FP32 copy: positions shifted by TX, plane offsets adjusted
+    double l[kRec];
+    for (int i = 0; i < kRec; i++) l[i] = o[i];
+    if (t == TP) {
+        l[3] = o[3] - (o[0] * tx[0] + o[1] * tx[1] + o[2] * tx[2]);
+        for (int i = 0; i < 3; i++) l[4 + i] = o[4 + i] - tx[i];
+    } else {
+        for (int i = 0; i < 3; i++) l[i] = o[i] - tx[i];
+    }
+    for (int i = 0; i < kRec; i++) rec32[(size_t)id * kRec + i] = (float)l[i];
+}
+
+// ------------------------------------------------------------------ workspace counters
+__global__ void k_zero_i32(int *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// ------------------------------------------------------------------ binning
+__device__ inline bool finite3(const double *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+// Order of a solve, or -1 if the solve is invalid (order, receiver or ids).
+__device__ inline int valid_order(const BatchDev &b, int64_t i, int n_all)
+{
+    const int ord = b.order[i];
+    bool bad = ord < 1 || ord > kMaxN;
+    const int ri = b.rx_index[i];
+    bad = bad || ri < 0 || ri >= b.n_rx;
+    if (!bad) {
+        bad = !finite3(b.rx + 3 * (size_t)ri);
+        for (int k = 0; k < kMaxN; k++)
+            if (k < ord) {
+                const int id = b.prim[(size_t)k * b.n + i];
+                bad = bad || id < 0 || id >= n_all;
+            }
+    }
+    return bad ? -1 : ord;
+}
+
+__global__ void k_bin_count(BatchDev b, OutDev out, int n_all, int *__restrict__ cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int ord = -1;
+    if (i < b.n) {
+        ord = valid_order(b, i, n_all);
+        if (ord < 0) {
+            for (int j = 0; j < 3 * kMaxN; j++) out.x[(size_t)j * b.n + i] = 0.0;
+            out.cost[i] = __builtin_huge_val();
+            out.iters[i] = 0;
+            out.status[i] = ST_BAD;
+        }
+    }
+    // wave-aggregated histogram
+    for (int k = 1; k <= kMaxN; k++) {
+        const uint64_t m = __ballot(ord == k);
+        if (m && __lane_id() == (int)__builtin_ctzll(m)) atomicAdd(&cnt[k - 1], (int)__popcll(m));
+    }
+}
+
+__device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
+{
+    int off = 0;
+    for (int j = 1; j < k; j++) off += cnt[j - 1];
+    return off;
+}
+
+__global__ void k_bin_scatter(BatchDev b, int n_all, const int *__restrict__ cnt, int *__restrict__ cursor,
+                              int *__restrict__ perm)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ord = (i < b.n) ? valid_order(b, i, n_all) : -1;
+    for (int k = 1; k <= kMaxN; k++) {
+        const bool mine = (ord == k);
+        const uint64_t m = __ballot(mine);
+        if (!m) continue;
+        const int leader = (int)__builtin_ctzll(m);
+        int base = 0;
+        if (__lane_id() == leader) base = atomicAdd(&cursor[k - 1], (int)__popcll(m));
+        base = __shfl(base, leader);
+        if (mine) {
+            const int rank = (int)__popcll(m & ((1ull << __lane_id()) - 1ull));
+            perm[bin_offset(cnt, k) + base + rank] = (int)i;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ init
+// Projection of a point onto an object (FP64 world): the straight-line start
+// of each interaction is the projection of the point k/(N+1) of the way from
+// TX to RX.
+__device__ inline void project(int t, const double *r, const double *P, double *X)
+{
+    if (t == TP) {
+        const double f = r[0] * P[0] + r[1] * P[1] + r[2] * P[2] - r[3];
+        for (int i = 0; i < 3; i++) X[i] = P[i] - f * r[i];
+    } else if (t == TL) {
+        const double s = (P[0] - r[0]) * r[3] + (P[1] - r[1]) * r[4] + (P[2] - r[2]) * r[5];
+        for (int i = 0; i < 3; i++) X[i] = r[i] + s * r[3 + i];
+    } else if (t == TQ) {
+        // one Newton step towards f = 0 along grad f
+        const double w[3] = {P[0] - r[0], P[1] - r[1], P[2] - r[2]};
+        const double Aw0 = r[3] * w[0] + r[4] * w[1] + r[5] * w[2];
+        const double Aw1 = r[4] * w[0] + r[6] * w[1] + r[7] * w[2];
+        const double Aw2 = r[5] * w[0] + r[7] * w[1] + r[8] * w[2];
+        const double f = w[0] * Aw0 + w[1] * Aw1 + w[2] * Aw2 + r[9] * w[0] + r[10] * w[1] + r[11] * w[2] + r[12];
+        const double g[3] = {2.0 * Aw0 + r[9], 2.0 * Aw1 + r[10], 2.0 * Aw2 + r[11]};
+        const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        const double s = gg > 0.0 ? f / gg : 0.0;
+        for (int i = 0; i < 3; i++) X[i] = P[i] - s * g[i];
+    } else {
+        const double d[3] = {P[0] - r[0], P[1] - r[1], P[2] - r[2]};
+        const double h = d[0] * r[3] + d[1] * r[4] + d[2] * r[5];
+        double w[3] = {d[0] - h * r[3], d[1] - h * r[4], d[2] - h * r[5]};
+        double lw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        if (!(lw > 0.0)) {
+            double u2[3];
+            onb(r + 3, w, u2);
+            lw = 1.0;
+        }
+        for (int i = 0; i < 3; i++) X[i] = r[i] + r[6] * w[i] / lw;
+    }
+}
+
+__device__ inline bool in_guard(const SceneDev &s, const double *X, int n)
+{
+    bool ok = true;
+    for (int k = 0; k < n; k++)
+        for (int i = 0; i < 3; i++) ok = ok && (X[3 * k + i] >= s.glo[i]) && (X[3 * k + i] <= s.ghi[i]);
+    return ok;
+}
+
+// ------------------------------------------------------------------ LM lane state
+template <typename T>
+struct LMOpts {
+    int max_iter, win;
+    T frac, tol_step, tol_res, tau_root, lambda0;
+};
+
+template <typename T, int N>
+struct Lane {
+    T X[3 * N];
+    T lam, Cref, C, rinf;
+    int it;
+};
+
+// One Levenberg-Marquardt iteration on the cost of Eq. (12) with the
+// rescaled rows; returns ST_RUNNING or the final status.
+template <typename T, int N>
+__device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &p, Lane<T, N> &L,
+                                       const LMOpts<T> &o)
+{
+    constexpr int M = 3 * N;
+    L.it++;
+    T A[Band<N>::SIZE], g[M], C, rinf;
+    if (!assemble<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+    L.C = C;
+    L.rinf = rinf;
+    T dmax = T(0);
+#pragma unroll
+    for (int i = 0; i < M; i++) dmax = fmax(dmax, A[Band<N>::at(i, i)]);
+    if (L.it == 1) {
+        L.lam = o.lambda0 * dmax;
+        L.Cref = C;
+    }
+    if (rinf <= o.tol_res) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+    if (o.win > 0 && L.it > 1 && (L.it - 1) % o.win == 0) {
+        if (C > o.frac * L.Cref) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+        L.Cref = C;
+    }
+    const T floor_d = T(1e-12) * dmax;
+#pragma unroll
+    for (int i = 0; i < M; i++) A[Band<N>::at(i, i)] += L.lam * fmax(A[Band<N>::at(i, i)], floor_d);
+    if (!chol_band<T, N>(A)) {
+        L.lam *= T(10);
+        if (L.lam > T(1e12) * dmax) return ST_STALL;
+        return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+    }
+#pragma unroll
+    for (int i = 0; i < M; i++) g[i] = -g[i];
+    chol_solve_band<T, N>(A, g);  // g <- dx
+    T xinf = T(0), dinf = T(0);
+    bool guard = true;
+#pragma unroll
+    for (int k = 0; k < N; k++)
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            xinf = fmax(xinf, fabs(L.X[3 * k + i]));
+            dinf = fmax(dinf, fabs(g[3 * k + i]));
+            const T xt = L.X[3 * k + i] + g[3 * k + i];
+            guard = guard && (xt >= sc.glo[i]) && (xt <= sc.ghi[i]);
+        }
+    const bool small = dinf <= o.tol_step * (T(1) + xinf);
+    T Ct = T(0), rt = T(0);
+    bool okt = guard && eval_cost<T, N>(sc, p, L.X, g, Ct, rt);
+    if (okt && Ct < C) {
+#pragma unroll
+        for (int i = 0; i < M; i++) L.X[i] += g[i];
+        L.C = Ct;
+        L.rinf = rt;
+        L.lam = fmax(L.lam / T(10), T(1e-15) * dmax);
+        if (small) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+    } else {
+        if (small) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+        L.lam *= T(10);
+        if (L.lam > T(1e12) * dmax) return ST_STALL;
+    }
+    return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+}
+
+// ------------------------------------------------------------------ persistent LM kernel
+// Lane-refill loop for the bin of order N.  Each wave takes a chunk of the bin
+// with one atomic, and hands the chunk's ids to its idle lanes; a lane whose
+// path finishes is refilled at the next iteration, so lanes never wait for
+// the slowest path of their wave.
+template <int MODE> struct ModeT;
+template <> struct ModeT<MODE_PLAIN64> { using T = double; };
+template <> struct ModeT<MODE_FP32> { using T = float; };
+template <> struct ModeT<MODE_FALLBACK64> { using T = double; };
+
+template <int MODE, int N>
+__device__ void lm_bin(const KParams &kp)
+{
+    using T = typename ModeT<MODE>::T;
+    const int lane = __lane_id();
+    const int *cnt = (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
+    const int *list = (MODE == MODE_FALLBACK64) ? kp.fb_list : kp.perm;
+    int *head = kp.head + (MODE == MODE_FALLBACK64 ? 5 : 0) + (N - 1);
+    const int count = cnt[N - 1];
+    if (count == 0) return;
+    const int off = bin_offset(kp.bin_cnt, N);
+
+    SceneT<T> sc;
+    if (MODE == MODE_FP32) {
+        sc.rec = (const T *)kp.s.rec32;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            sc.tx[i] = T(0);
+            sc.glo[i] = (T)(kp.s.glo[i] - kp.s.tx[i]);
+            sc.ghi[i] = (T)(kp.s.ghi[i] - kp.s.tx[i]);
+        }
+    } else {
+        sc.rec = (const T *)kp.s.rec64;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            sc.tx[i] = (T)kp.s.tx[i];
+            sc.glo[i] = (T)kp.s.glo[i];
+            sc.ghi[i] = (T)kp.s.ghi[i];
+        }
+    }
+    LMOpts<T> o;
+    if (MODE == MODE_FP32) {
+        o.max_iter = kp.o.max_iter32;
+        o.tol_step = (T)kp.o.tol_step32;
+        o.tol_res = (T)kp.o.tol_res32;
+        o.tau_root = (T)kp.o.polish_gate;  // FP32 "root" = worth polishing
+    } else {
+        o.max_iter = kp.o.max_iter;
+        o.tol_step = (T)kp.o.tol_step;
+        o.tol_res = (T)kp.o.tol_res;
+        o.tau_root = (T)kp.o.tau_root;
+    }
+    o.win = kp.o.plateau_win;
+    o.frac = (T)kp.o.plateau_frac;
+    o.lambda0 = (T)kp.o.lambda0;
+
+    Lane<T, N> L;
+    PathIn<T, N> p;
+    int sid = -1;
+    bool active = false;
+    int cbase = 0, cend = 0;  // wave-uniform chunk [cbase, cend) of the bin
+    bool drained = false;
+    constexpr int CH = 64;
+
+    while (true) {
+        // ---- refill idle lanes from the wave's chunk
+        uint64_t need = __ballot(!active);
+        if (need && !drained) {
+            if (cbase >= cend) {
+                int b0 = 0;
+                if (lane == 0) b0 = atomicAdd(head, CH);
+                b0 = __shfl(b0, 0);
+                cbase = b0;
+                cend = min(b0 + CH, count);
+                if (cbase >= count) drained = true;
+            }
+            if (!drained) {
+                const int avail = cend - cbase;
+                const int rank = (int)__popcll(need & ((1ull << lane) - 1ull));
+                const int take = min((int)__popcll(need), avail);
+                if (!active && rank < take) {
+                    sid = list[off + cbase + rank];
+                    active = true;
+                    // ---- start of one path
+                    double rx[3], X0[3 * N];
+                    const int ri = kp.b.rx_index[sid];
+#pragma unroll
+                    for (int i = 0; i < 3; i++) rx[i] = kp.b.rx[3 * (size_t)ri + i];
+#pragma unroll
+                    for (int k = 0; k < N; k++) {
+                        p.id[k] = kp.b.prim[(size_t)k * kp.b.n + sid];
+                        p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
+                    }
+                    bool ok = true;
+                    const int init = (MODE == MODE_FALLBACK64) ? INIT_LINE : kp.o.init;
+                    if (init == INIT_LINE) {
+#pragma unroll
+                        for (int k = 0; k < N; k++) {
+                            const double a = (double)(k + 1) / (double)(N + 1);
+                            double P[3];
+#pragma unroll
+                            for (int i = 0; i < 3; i++) P[i] = kp.s.tx[i] + a * (rx[i] - kp.s.tx[i]);
+                            project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
+                        }
+                    } else {
+                        const double *x0 = (init == INIT_USER) ? kp.b.x0 : kp.x0_learned;
+#pragma unroll
+                        for (int j = 0; j < 3 * N; j++) {
+                            X0[j] = x0[(size_t)j * kp.b.n + sid];
+                            ok = ok && isfinite(X0[j]);
+                        }
+                        if (ok && init == INIT_LEARNED) {
+                            // the network's points are projected onto their objects
+#pragma unroll
+                            for (int k = 0; k < N; k++) {
+                                double P[3] = {X0[3 * k], X0[3 * k + 1], X0[3 * k + 2]};
+                                project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
+                            }
+                        }
+                    }
+                    int st0 = ST_RUNNING;
+                    if (!ok) st0 = ST_BAD;
+                    else if (!in_guard(kp.s, X0, N)) st0 = ST_DIVERGED;
+                    const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
+                                          MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
+#pragma unroll
+                    for (int i = 0; i < 3; i++) p.rx[i] = (T)(rx[i] - sh[i]);
+#pragma unroll
+                    for (int k = 0; k < N; k++)
+#pragma unroll
+                        for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(X0[3 * k + i] - sh[i]);
+                    L.it = 0;
+                    L.lam = T(0);
+                    L.C = T(__builtin_huge_val());
+                    L.rinf = T(__builtin_huge_val());
+                    L.Cref = L.C;
+                    if (st0 != ST_RUNNING) {
+                        // finished before the first iteration
+#pragma unroll
+                        for (int j = 0; j < 3 * kMaxN; j++)
+                            kp.out.x[(size_t)j * kp.b.n + sid] = (j < 3 * N && st0 != ST_BAD) ? X0[j < 3 * N ? j : 0] : 0.0;
+                        kp.out.cost[sid] = __builtin_huge_val();
+                        if (MODE != MODE_FALLBACK64) kp.out.iters[sid] = 0;
+                        kp.out.status[sid] = (uint8_t)(st0 | (MODE == MODE_FALLBACK64 ? 0x80 : 0));
+                        active = false;
+                    }
+                }
+                cbase += take;
+            }
+        }
+        if (!__any(active)) {
+            if (drained) break;
+            continue;
+        }
+        // ---- one iteration on every busy lane
+        if (active) {
+            const int st = lm_step<T, N>(sc, p, L, o);
+            if (st != ST_RUNNING) {
+                // ---- end of one path: write it (world frame)
+                const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
+                                      MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
+#pragma unroll
+                for (int j = 0; j < 3 * kMaxN; j++)
+                    kp.out.x[(size_t)j * kp.b.n + sid] = (j < 3 * N) ? (double)L.X[j < 3 * N ? j : 0] + sh[j % 3] : 0.0;
+                kp.out.cost[sid] = (double)L.C;
+                int it = L.it;
+                if (MODE == MODE_FALLBACK64) it += kp.out.iters[sid];
+                kp.out.iters[sid] = it;
+                int code = st;
+                if (MODE == MODE_FP32) {
+                    // route: polish points that look like roots, fall back on
+                    // numerical trouble, keep clear non-roots as they are
+                    const bool to_polish = (st == ST_CONV) ||
+                                           ((st == ST_MAXIT || st == ST_LOCALMIN) && (double)L.rinf <= kp.o.polish_gate);
+                    const bool to_fb = (st == ST_STALL || st == ST_DEGEN || st == ST_DIVERGED);
+                    if (to_polish) {
+                        const int q = atomicAdd(&kp.pol_cnt[N - 1], 1);
+                        kp.pol_list[off + q] = sid;
+                        code = ST_RUNNING;
+                    } else if (to_fb && kp.o.fallback) {
+                        const int q = atomicAdd(&kp.fb_cnt[N - 1], 1);
+                        kp.fb_list[off + q] = sid;
+                        code = ST_RUNNING;
+                    }
+                }
+                if (MODE == MODE_FALLBACK64) code |= 0x80;
+                kp.out.status[sid] = (uint8_t)code;
+                active = false;
+            }
+        }
+    }
+}
+
+// Register budget per lane: an order-N path keeps 3N points, the 3N x 3N
+// band (93 entries at N = 5) and its factor in registers, so the occupancy
+// target falls with the order and doubles from FP64 to FP32.
+template <int MODE, int N> struct Occ { static constexpr int W = 1; };
+template <> struct Occ<MODE_FP32, 1> { static constexpr int W = 8; };
+template <> struct Occ<MODE_FP32, 2> { static constexpr int W = 4; };
+template <> struct Occ<MODE_FP32, 3> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FP32, 4> { static constexpr int W = 2; };
+template <> struct Occ<MODE_FP32, 5> { static constexpr int W = 2; };
+template <> struct Occ<MODE_PLAIN64, 1> { static constexpr int W = 4; };
+template <> struct Occ<MODE_PLAIN64, 2> { static constexpr int W = 3; };
+template <> struct Occ<MODE_PLAIN64, 3> { static constexpr int W = 2; };
+template <> struct Occ<MODE_PLAIN64, 4> { static constexpr int W = 1; };
+template <> struct Occ<MODE_FALLBACK64, 1> { static constexpr int W = 4; };
+template <> struct Occ<MODE_FALLBACK64, 2> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FALLBACK64, 3> { static constexpr int W = 2; };
+template <> struct Occ<MODE_FALLBACK64, 4> { static constexpr int W = 1; };
+
+// One persistent launch over every order (register budget of order 5).
+template <int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<MODE, 5>::W, Occ<MODE, 5>::W)))
+k_lm(KParams kp)
+{
+    // long paths first so that the short ones fill the tail
+    lm_bin<MODE, 5>(kp);
+    lm_bin<MODE, 4>(kp);
+    lm_bin<MODE, 3>(kp);
+    lm_bin<MODE, 2>(kp);
+    lm_bin<MODE, 1>(kp);
+}
+
+// One persistent launch per order, each with its own register budget.
+template <int MODE, int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<MODE, N>::W, Occ<MODE, N>::W)))
+k_lm_one(KParams kp)
+{
+    lm_bin<MODE, N>(kp);
+}
+
+// ------------------------------------------------------------------ polish
+// Undamped FP64 Gauss-Newton from the FP32 end point (world frame).
+template <int N>
+__device__ void polish_bin(const KParams &kp)
+{
+    const int count = kp.pol_cnt[N - 1];
+    if (count == 0) return;
+    const int off = bin_offset(kp.bin_cnt, N);
+    SceneT<double> sc;
+    sc.rec = kp.s.rec64;
+#pragma unroll
+    for (int i = 0; i < 3; i++) { sc.tx[i] = kp.s.tx[i]; sc.glo[i] = kp.s.glo[i]; sc.ghi[i] = kp.s.ghi[i]; }
+    constexpr int M = 3 * N;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < count; q += gridDim.x * blockDim.x) {
+        const int sid = kp.pol_list[off + q];
+        PathIn<double, N> p;
+        const int ri = kp.b.rx_index[sid];
+#pragma unroll
+        for (int i = 0; i < 3; i++) p.rx[i] = kp.b.rx[3 * (size_t)ri + i];
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            p.id[k] = kp.b.prim[(size_t)k * kp.b.n + sid];
+            p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
+        }
+        double X[M];
+#pragma unroll
+        for (int j = 0; j < M; j++) X[j] = kp.out.x[(size_t)j * kp.b.n + sid];
+        bool ok = true, small = false;
+        int steps = 0;
+        for (int ps = 0; ps < kp.o.polish_steps && ok && !small; ps++) {
+            double A[Band<N>::SIZE], g[M], C, rinf;
+            ok = assemble<double, N>(sc, p, X, A, g, C, rinf);
+            if (!ok) break;
+            steps++;
+            if (rinf <= kp.o.tol_res) { small = true; break; }
+            double dmax = 0.0;
+#pragma unroll
+            for (int i = 0; i < M; i++) dmax = fmax(dmax, A[Band<N>::at(i, i)]);
+#pragma unroll
+            for (int i = 0; i < M; i++) A[Band<N>::at(i, i)] += 1e-15 * dmax;
+            ok = chol_band<double, N>(A);
+            if (!ok) break;
+#pragma unroll
+            for (int i = 0; i < M; i++) g[i] = -g[i];
+            chol_solve_band<double, N>(A, g);
+            double xinf = 0.0, dinf = 0.0;
+#pragma unroll
+            for (int i = 0; i < M; i++) {
+                xinf = fmax(xinf, fabs(X[i]));
+                dinf = fmax(dinf, fabs(g[i]));
+                X[i] += g[i];
+            }
+            small = dinf <= kp.o.tol_step * (1.0 + xinf);
+        }
+        double C = __builtin_huge_val(), rinf = __builtin_huge_val();
+        if (ok) ok = eval_cost<double, N>(sc, p, X, nullptr, C, rinf) && in_guard(kp.s, X, N);
+        const bool root = ok && rinf <= kp.o.tau_root;
+        kp.out.iters[sid] += steps;
+        if (root) {
+#pragma unroll
+            for (int j = 0; j < M; j++) kp.out.x[(size_t)j * kp.b.n + sid] = X[j];
+            kp.out.cost[sid] = C;
+            kp.out.status[sid] = ST_CONV;
+        } else if (kp.o.fallback) {
+            const int qq = atomicAdd(&kp.fb_cnt[N - 1], 1);
+            kp.fb_list[off + qq] = sid;
+        } else {
+            kp.out.status[sid] = ST_LOCALMIN;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_polish(KParams kp)
+{
+    polish_bin<5>(kp);
+    polish_bin<4>(kp);
+    polish_bin<3>(kp);
+    polish_bin<2>(kp);
+    polish_bin<1>(kp);
+}
+
+// ------------------------------------------------------------------ acceptance
+// The acceptance test of Alg. 1 in FP64: converged, |R|_inf <= tau_res, every
+// segment at least min_seg, every point inside its finite extent.
+template <int N>
+__device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, const int *ty, const double *X,
+                            double tau_res, double min_seg)
+{
+    SceneT<double> sc;
+    sc.rec = s.rec64;
+#pragma unroll
+    for (int i = 0; i < 3; i++) { sc.tx[i] = s.tx[i]; sc.glo[i] = s.glo[i]; sc.ghi[i] = s.ghi[i]; }
+    PathIn<double, N> p;
+#pragma unroll
+    for (int i = 0; i < 3; i++) p.rx[i] = rx[i];
+#pragma unroll
+    for (int k = 0; k < N; k++) { p.id[k] = id[k]; p.ty[k] = ty[k]; }
+    double C, rinf;
+    bool ok = eval_cost<double, N>(sc, p, X, nullptr, C, rinf) && (rinf <= tau_res);
+#pragma unroll
+    for (int k = 0; k <= N; k++) {
+        const double *P = (k == 0) ? s.tx : X + 3 * (k - 1);
+        const double *Q = (k == N) ? rx : X + 3 * k;
+        const double d[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+        ok = ok && (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= min_seg);
+    }
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const double *r = s.rec64 + (size_t)id[k] * kRec;
+        const double *x = X + 3 * k;
+        const double d[3] = {x[0] - r[0], x[1] - r[1], x[2] - r[2]};
+        if (ty[k] == TP) {
+            const double e[3] = {x[0] - r[4], x[1] - r[5], x[2] - r[6]};
+            const double a = e[0] * r[7] + e[1] * r[8] + e[2] * r[9];
+            const double b = e[0] * r[10] + e[1] * r[11] + e[2] * r[12];
+            const double la = r[7] * r[7] + r[8] * r[8] + r[9] * r[9];
+            const double lb = r[10] * r[10] + r[11] * r[11] + r[12] * r[12];
+            ok = ok && a >= 0.0 && a <= la && b >= 0.0 && b <= lb;
+        } else if (ty[k] == TL) {
+            const double sp = d[0] * r[3] + d[1] * r[4] + d[2] * r[5];
+            ok = ok && sp >= r[6] && sp <= r[7];
+        } else if (ty[k] == TQ) {
+            const double h = d[0] * r[13] + d[1] * r[14] + d[2] * r[15];
+            const double w[3] = {d[0] - h * r[13], d[1] - h * r[14], d[2] - h * r[15]};
+            ok = ok && (w[0] * w[0] + w[1] * w[1] + w[2] * w[2] <= r[16] * r[16]);
+        }
+    }
+    return ok;
+}
+
+__global__ void __launch_bounds__(256) k_accept_flags(SceneDev s, BatchDev b, OutDevC in, double tau_res,
+                                                       double min_seg, uint8_t *__restrict__ acc,
+                                                       int *__restrict__ block_cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool a = false;
+    if (i < b.n) {
+        const int ord = b.order[i];
+        const uint8_t st = in.status[i];
+        if (ord >= 1 && ord <= kMaxN && (st & 0x7f) == ST_CONV) {
+            const int ri = b.rx_index[i];
+            double rx[3], X[3 * kMaxN];
+            int id[kMaxN], ty[kMaxN];
+            for (int j = 0; j < 3; j++) rx[j] = b.rx[3 * (size_t)ri + j];
+            for (int j = 0; j < 3 * kMaxN; j++) X[j] = in.x[(size_t)j * b.n + i];
+            bool okid = true;
+            for (int k = 0; k < kMaxN; k++) {
+                id[k] = (k < ord) ? b.prim[(size_t)k * b.n + i] : 0;
+                okid = okid && id[k] >= 0 && id[k] < s.n_all;
+                ty[k] = prim_type(id[k], s.n_pl, s.n_pl_ln, s.n_pl_ln_q);
+            }
+            if (okid) {
+                switch (ord) {
+                case 1: a = accept_path<1>(s, rx, id, ty, X, tau_res, min_seg); break;
+                case 2: a = accept_path<2>(s, rx, id, ty, X, tau_res, min_seg); break;
+                case 3: a = accept_path<3>(s, rx, id, ty, X, tau_res, min_seg); break;
+                case 4: a = accept_path<4>(s, rx, id, ty, X, tau_res, min_seg); break;
+                default: a = accept_path<5>(s, rx, id, ty, X, tau_res, min_seg); break;
+                }
+            }
+        }
+        acc[i] = a ? 1 : 0;
+    }
+    __shared__ int wcnt[4];
+    const uint64_t m = __ballot(a);
+    if (__lane_id() == 0) wcnt[threadIdx.x >> 6] = (int)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += wcnt[w];
+        block_cnt[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the per-block counts by one block; total -> *count.
+__global__ void __launch_bounds__(1024) k_scan_blocks(int *__restrict__ block_cnt, int nblk, int *__restrict__ count)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (nblk + 1023) / 1024;
+    const int lo = t * per, hi = min(lo + per, nblk);
+    int s = 0;
+    for (int i = lo; i < hi; i++) s += block_cnt[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int v = (t >= d) ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = (t == 0) ? 0 : part[t - 1];
+    for (int i = lo; i < hi; i++) {
+        const int c = block_cnt[i];
+        block_cnt[i] = run;
+        run += c;
+    }
+    if (t == 1023) *count = part[1023];
+}
+
+__global__ void __launch_bounds__(256) k_accept_scatter(const uint8_t *__restrict__ acc, int64_t n,
+                                                         const int *__restrict__ block_off, int *__restrict__ idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool a = (i < n) && acc[i];
+    __shared__ int wcnt[4];
+    const uint64_t m = __ballot(a);
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0) wcnt[w] = (int)__popcll(m);
+    __syncthreads();
+    int base = block_off[blockIdx.x];
+    for (int j = 0; j < w; j++) base += wcnt[j];
+    if (a) idx[base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull))] = (int)i;
+}
+
+// ------------------------------------------------------------------ host launchers
+void launch_pack(const double *raw, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c, hipStream_t st)
+{
+    const int n = n_pl + n_ln + n_q + n_c;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_pack, dim3((n + 127) / 128), dim3(128), 0, st, raw, n_pl, n_ln, n_q, n_c, s.tx[0], s.tx[1],
+                       s.tx[2], (double *)s.rec64, (float *)s.rec32);
+}
+
+void launch_zero(int *p, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+}
+
+void launch_bin(const BatchDev &b, const OutDev &out, int n_all, int *cnt, int *cursor, int *perm, hipStream_t st)
+{
+    if (b.n == 0) return;
+    const unsigned g = (unsigned)((b.n + 255) / 256);
+    hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(256), 0, st, b, out, n_all, cnt);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(256), 0, st, b, n_all, cnt, cursor, perm);
+}
+
+template <int MODE>
+static const void *lm_kernel_t(int order)
+{
+    switch (order) {
+    case 0: return (const void *)k_lm<MODE>;
+    case 1: return (const void *)k_lm_one<MODE, 1>;
+    case 2: return (const void *)k_lm_one<MODE, 2>;
+    case 3: return (const void *)k_lm_one<MODE, 3>;
+    case 4: return (const void *)k_lm_one<MODE, 4>;
+    default: return (const void *)k_lm_one<MODE, 5>;
+    }
+}
+
+// order 0: the mixed-order kernel; 1..5: the per-order kernels
+const void *lm_kernel(int mode, int order)
+{
+    switch (mode) {
+    case MODE_PLAIN64: return lm_kernel_t<MODE_PLAIN64>(order);
+    case MODE_FP32: return lm_kernel_t<MODE_FP32>(order);
+    default: return lm_kernel_t<MODE_FALLBACK64>(order);
+    }
+}
+
+void launch_lm(int mode, int order, const KParams &kp, int grid, int block, hipStream_t st)
+{
+    void *args[] = {(void *)&kp};
+    hipLaunchKernel(lm_kernel(mode, order), dim3(grid), dim3(block), args, 0, st);
+}
+
+const void *polish_kernel() { return (const void *)k_polish; }
+
+void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_polish, dim3(grid), dim3(block), 0, st, kp);
+}
+
+void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
+                   uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st)
+{
+    const int nblk = (int)((b.n + 255) / 256);
+    if (nblk == 0) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, count, 1);
+        return;
+    }
+    hipLaunchKernelGGL(k_accept_flags, dim3(nblk), dim3(256), 0, st, s, b, in, tau_res, min_seg, acc, block_cnt);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_cnt, nblk, count);
+    hipLaunchKernelGGL(k_accept_scatter, dim3(nblk), dim3(256), 0, st, acc, b.n, block_cnt, idx);
+}
+
+}  // namespace mpt

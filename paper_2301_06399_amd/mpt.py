@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libmpt.so (include/mpt.h).
+
+Argument marshalling only: numpy inputs become torch device tensors, torch
+tensors are handed to the library as raw device pointers, and every step of
+the solve runs in the library's HIP kernels.  There is no CPU fallback: if
+the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmpt.so")
+
+MPT_OK = 0
+STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NO_SCENE",
+                5: "E_UNSUPPORTED", 6: "E_NO_MODEL"}
+CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7)
+FALLBACK = 0x80
+FP64_PLAIN, FP32_POLISH64 = 0, 1
+INIT_LINE, INIT_USER, INIT_LEARNED = 0, 1, 2
+SCHED_PER_ORDER, SCHED_PERSISTENT = 0, 1
+
+
+class MptError(RuntimeError):
+    pass
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("tx", C.c_double * 3), ("aabb_lo", C.c_double * 3), ("aabb_hi", C.c_double * 3),
+                ("n_planes", C.c_int32), ("n_lines", C.c_int32), ("n_quadrics", C.c_int32),
+                ("n_circles", C.c_int32), ("planes", C.c_void_p), ("lines", C.c_void_p),
+                ("quadrics", C.c_void_p), ("circles", C.c_void_p)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_rx", C.c_int32), ("rx", C.c_void_p), ("rx_index", C.c_void_p),
+                ("order", C.c_void_p), ("prim", C.c_void_p), ("x0", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("init", C.c_int32), ("max_iter", C.c_int32),
+                ("max_iter32", C.c_int32), ("polish_steps", C.c_int32), ("fallback", C.c_int32),
+                ("plateau_win", C.c_int32), ("sched", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
+                ("plateau_frac", C.c_double), ("tol_step", C.c_double), ("tol_res", C.c_double),
+                ("tau_root", C.c_double), ("lambda0", C.c_double), ("tol_step32", C.c_double),
+                ("tol_res32", C.c_double), ("polish_gate", C.c_double)]
+
+
+class SolveOut(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("cost", C.c_void_p), ("iters", C.c_void_p), ("status", C.c_void_p)]
+
+
+EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt_synchronize",
+           "mpt_scene_upload", "mpt_default_opts", "mpt_solve_batch", "mpt_accept", "mpt_mlp_init",
+           "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmpt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MptError(f"{path} is missing: build it with paper_2301_06399_amd.build.build()")
+    L = C.CDLL(path)
+    vp, st = C.c_void_p, C.c_int
+    L.mpt_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+    L.mpt_destroy.argtypes = [vp]
+    L.mpt_last_error.argtypes = [vp]
+    L.mpt_last_error.restype = C.c_char_p
+    L.mpt_set_stream.argtypes = [vp, vp]
+    L.mpt_synchronize.argtypes = [vp]
+    L.mpt_scene_upload.argtypes = [vp, C.POINTER(SceneDesc)]
+    L.mpt_default_opts.argtypes = [C.POINTER(SolveOpts)]
+    L.mpt_default_opts.restype = None
+    L.mpt_solve_batch.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut)]
+    L.mpt_accept.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOut), C.c_double, C.c_double, vp, vp, vp,
+                             C.POINTER(C.c_int64)]
+    L.mpt_mlp_init.argtypes = [vp, C.c_uint64]
+    L.mpt_mlp_train_step.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, C.c_float, vp]
+    L.mpt_mlp_predict.argtypes = [vp, C.POINTER(BatchDesc), vp]
+    L.mpt_mlp_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+    L.mpt_mlp_load.argtypes = [vp, vp, C.c_size_t]
+    L.mpt_last_timings.argtypes = [vp, C.POINTER(C.c_float)]
+    for f in EXPORTS:
+        getattr(L, f).restype = st if f not in ("mpt_last_error", "mpt_default_opts") else getattr(L, f).restype
+    _lib = L
+    return L
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load_library().mpt_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class DeviceBatch:
+    """A batch's arrays resident in device memory (torch tensors)."""
+
+    def __init__(self, batch, device="cuda"):
+        import torch
+        self.n = int(batch.n)
+        self.n_rx = int(len(batch.rx))
+        self.rx = torch.from_numpy(np.ascontiguousarray(batch.rx, np.float64)).to(device)
+        self.rx_index = torch.from_numpy(np.ascontiguousarray(batch.rx_index, np.int32)).to(device)
+        self.order = torch.from_numpy(np.ascontiguousarray(batch.order, np.int32)).to(device)
+        self.prim = torch.from_numpy(np.ascontiguousarray(batch.prim, np.int32)).to(device)
+        self.x0 = None if batch.x0 is None else torch.from_numpy(np.ascontiguousarray(batch.x0, np.float64)).to(device)
+
+    def desc(self) -> BatchDesc:
+        return BatchDesc(self.n, self.n_rx, _ptr(self.rx), _ptr(self.rx_index), _ptr(self.order), _ptr(self.prim),
+                         _ptr(self.x0))
+
+
+class DeviceOut:
+    def __init__(self, n, device="cuda"):
+        import torch
+        self.x = torch.empty((15, max(n, 0)), dtype=torch.float64, device=device)
+        self.cost = torch.empty(max(n, 0), dtype=torch.float64, device=device)
+        self.iters = torch.empty(max(n, 0), dtype=torch.int32, device=device)
+        self.status = torch.empty(max(n, 0), dtype=torch.uint8, device=device)
+
+    def desc(self) -> SolveOut:
+        return SolveOut(_ptr(self.x), _ptr(self.cost), _ptr(self.iters), _ptr(self.status))
+
+    def numpy(self):
+        return {"x": self.x.cpu().numpy(), "cost": self.cost.cpu().numpy(), "iters": self.iters.cpu().numpy(),
+                "status": self.status.cpu().numpy()}
+
+
+class Context:
+    """One library context on one GPU, enqueuing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.L = load_library()
+        if not torch.cuda.is_available():
+            raise MptError("no HIP device available")
+        self.torch = torch
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = C.c_void_p()
+        rc = self.L.mpt_create(device, C.c_void_p(s.cuda_stream), C.byref(h))
+        if rc != MPT_OK:
+            raise MptError(f"mpt_create failed: {STATUS_NAMES.get(rc, rc)}")
+        self.h = h
+
+    def _check(self, rc, what):
+        if rc != MPT_OK:
+            msg = self.L.mpt_last_error(self.h).decode()
+            raise MptError(f"{what}: {STATUS_NAMES.get(rc, rc)}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.mpt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload_scene(self, scene):
+        keep = [np.ascontiguousarray(getattr(scene, k), np.float64) for k in ("planes", "lines", "quadrics", "circles")]
+        d = SceneDesc()
+        d.tx[:] = list(map(float, scene.tx))
+        d.aabb_lo[:] = list(map(float, scene.aabb_lo))
+        d.aabb_hi[:] = list(map(float, scene.aabb_hi))
+        d.n_planes, d.n_lines, d.n_quadrics, d.n_circles = (len(a) for a in keep)
+        d.planes, d.lines, d.quadrics, d.circles = (a.ctypes.data if a.size else None for a in keep)
+        self._check(self.L.mpt_scene_upload(self.h, C.byref(d)), "mpt_scene_upload")
+
+    def solve(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None) -> DeviceOut:
+        out = out or DeviceOut(dbatch.n)
+        o = opts or default_opts()
+        bd, od = dbatch.desc(), out.desc()
+        self._check(self.L.mpt_solve_batch(self.h, C.byref(bd), C.byref(o), C.byref(od)), "mpt_solve_batch")
+        return out
+
+    def accept(self, dbatch: DeviceBatch, out: DeviceOut, tau_res=1e-9, min_seg=1e-6, sync=True):
+        torch = self.torch
+        n = dbatch.n
+        acc = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        idx = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+        hc = C.c_int64(0)
+        bd, od = dbatch.desc(), out.desc()
+        self._check(self.L.mpt_accept(self.h, C.byref(bd), C.byref(od), tau_res, min_seg, _ptr(acc), _ptr(idx),
+                                      _ptr(cnt), C.byref(hc) if sync else None), "mpt_accept")
+        k = int(hc.value) if sync else None
+        return acc[:n], (idx[:k] if sync else idx), (k if sync else cnt)
+
+    def synchronize(self):
+        self._check(self.L.mpt_synchronize(self.h), "mpt_synchronize")
+
+    def timings(self):
+        ms = (C.c_float * 4)()
+        self._check(self.L.mpt_last_timings(self.h, ms), "mpt_last_timings")
+        return {"bin": ms[0], "learned": ms[1], "solve": ms[2], "fallback": ms[3]}
+
+    # ---------------------------------------------------------------- network
+    def mlp_init(self, seed: int = 0):
+        self._check(self.L.mpt_mlp_init(self.h, C.c_uint64(seed)), "mpt_mlp_init")
+
+    def mlp_train_step(self, dbatch: DeviceBatch, target_x, use=None, lr=1e-3, loss=None):
+        bd = dbatch.desc()
+        self._check(self.L.mpt_mlp_train_step(self.h, C.byref(bd), _ptr(target_x), _ptr(use), C.c_float(lr),
+                                              _ptr(loss)), "mpt_mlp_train_step")
+
+    def mlp_predict(self, dbatch: DeviceBatch, x_out=None):
+        x_out = x_out if x_out is not None else self.torch.empty((15, dbatch.n), dtype=self.torch.float64,
+                                                                 device="cuda")
+        bd = dbatch.desc()
+        self._check(self.L.mpt_mlp_predict(self.h, C.byref(bd), _ptr(x_out)), "mpt_mlp_predict")
+        return x_out
+
+    def mlp_save(self) -> bytes:
+        n = C.c_size_t(0)
+        self._check(self.L.mpt_mlp_save(self.h, None, C.byref(n)), "mpt_mlp_save")
+        buf = (C.c_char * n.value)()
+        self._check(self.L.mpt_mlp_save(self.h, buf, C.byref(n)), "mpt_mlp_save")
+        return bytes(buf)
+
+    def mlp_load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self.L.mpt_mlp_load(self.h, buf, len(blob)), "mpt_mlp_load")

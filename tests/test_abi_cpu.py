@@ -1,0 +1,56 @@
+"""The C ABI library loads and exports every entry point include/mpt.h
+declares (CPU only: no call that needs a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mpt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("mpt_scene_upload", "mpt_solve_batch", "mpt_accept", "mpt_create", "mpt_destroy",
+                 "mpt_mlp_train_step", "mpt_mlp_predict"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2301_06399_amd import mpt
+    if not os.path.exists(mpt.LIB_PATH):
+        from paper_2301_06399_amd.build import build
+        build()
+    lib = C.CDLL(mpt.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(mpt.EXPORTS) == declared_functions()
+
+
+def test_default_options_are_host_only():
+    from paper_2301_06399_amd import mpt
+    o = mpt.default_opts()
+    assert o.precision == mpt.FP32_POLISH64 and o.max_iter == 200 and o.plateau_win == 10
+    assert o.tau_root == 1e-9 and o.tol_step == 1e-12 and o.polish_gate == 1e-2
+    with pytest.raises(KeyError):
+        mpt.default_opts(no_such_option=1)
+
+
+def test_oracle_library_is_independent_of_the_hip_library():
+    """The oracle shares no code with the HIP path: no include, no import."""
+    hip_dir = os.path.join(ROOT, "paper_2301_06399_amd")
+    for dp, _, fs in os.walk(hip_dir):
+        for f in fs:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                t = open(os.path.join(dp, f)).read()
+                assert not re.search(r"(import\s+oracle|from\s+oracle|mpt_oracle|orc_)", t), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".c", ".h", ".py")):
+            t = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_2301_06399_amd" not in t and "mpt_device" not in t, f
