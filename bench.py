@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched Min-Path-Tracing solve on one MI355X.
+
+One step = one pass of the whole hot path over the street-canyon workload
+(50 boxes, 651 primitives, 4096 receivers x 64 interaction lists of order
+1-3 = 262,144 solves): order binning, [learned start], FP32
+Levenberg-Marquardt, FP64 Gauss-Newton polish, FP64 fallback, FP64
+acceptance test with ordered compaction.  Inputs are resident on the GPU
+before timing starts.  `value` = accepted paths per second.
+
+Also reported: the plain FP64 solver (P) and FP32+polish without the learned
+start (S) on the same workload, the roofline of the dominant kernel (the
+first LM pass) with its time measured by HIP events on the library's stream,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12, "bf16": 2.5e15}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mpt_device.hpp", "mpt_solve.hip", "mpt_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2301_06399_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def type_codes(scene, batch):
+    """Base-4 code of each solve's primitive-type sequence."""
+    t = scene.type_of(np.maximum(batch.prim, 0))
+    code = np.zeros(batch.n, np.int64)
+    for k in range(5):
+        code += np.where(batch.order > k, t[k], 0).astype(np.int64) * (4 ** k)
+    return code
+
+
+def algorithmic_flops(table, order, code, iters, kind):
+    tot = 0
+    for n in range(1, 6):
+        m = order == n
+        if m.any():
+            tot += int((table[n][kind][code[m]] * iters[m].astype(np.int64)).sum())
+    return tot
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--n-rx", type=int, default=0, help="receivers (0: the configuration's own)")
+    ap.add_argument("--variant", default="auto", choices=["auto", "L", "S", "P"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: about 20 s of work)")
+    ap.add_argument("--train-steps", type=int, default=0, help="network training steps before timing (L)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2301_06399_amd import mpt
+    from paper_2301_06399_amd import workloads as W
+
+    t0 = time.time()
+    if args.config == 5:
+        scene, batch = W.config5(n_rx=args.n_rx or 1024)
+    elif args.n_rx:
+        scene, batch = W.CONFIGS[args.config](n_rx=args.n_rx)
+    else:
+        scene, batch = W.CONFIGS[args.config]()
+    names = {1: "room 10x10x3 m, 6 walls + 2 edges, 256 RX x 64 lists (order 1-2)",
+             2: "street canyon 50 boxes (251 facets + 400 edges), 4096 RX x 64 lists (order 1-3)",
+             3: "curved: 200 paraboloids + 100 circles, 16384 RX x 64 lists (order 1-5)",
+             5: "stress: street canyon + 30 paraboloids, lists of order 3-5 with >= 2 diffractions"}
+    print(f"# workload generated in {time.time() - t0:.1f}s: {batch.n} solves", file=sys.stderr, flush=True)
+
+    ctx = mpt.Context(0)
+    ctx.upload_scene(scene)
+    db = mpt.DeviceBatch(batch)
+    out = mpt.DeviceOut(batch.n, stages=True)
+    n = batch.n
+    acc = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+    import ctypes as C
+
+    learned_ok = False
+    variant = args.variant
+    if variant in ("auto", "L"):
+        try:
+            from paper_2301_06399_amd import learned
+            learned_ok = learned.prepare(ctx, scene, batch, steps=args.train_steps or None)
+        except (ImportError, mpt.MptError) as e:
+            print(f"# learned start unavailable: {e}", file=sys.stderr)
+            learned_ok = False
+        if variant == "L" and not learned_ok:
+            print(json.dumps({"error": "learned start requested but unavailable"}))
+            sys.exit(3)
+        variant = "L" if learned_ok else "S"
+
+    def opts_for(v):
+        if v == "P":
+            return mpt.default_opts(precision=mpt.FP64_PLAIN)
+        if v == "S":
+            return mpt.default_opts(precision=mpt.FP32_POLISH64)
+        return mpt.default_opts(precision=mpt.FP32_POLISH64, init=mpt.INIT_LEARNED)
+
+    def step(o):
+        ctx.solve(db, o, out)
+        bd, od = db.desc(), out.desc()
+        rc = ctx.L.mpt_accept(ctx.h, C.byref(bd), C.byref(od), 1e-9, 1e-6, mpt._ptr(acc), mpt._ptr(idx),
+                              mpt._ptr(cnt), None)
+        ctx._check(rc, "mpt_accept")
+
+    def timed(v, steps, warmup):
+        o = opts_for(v)
+        for _ in range(warmup):
+            step(o)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            step(o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        k = int(cnt.item())
+        # per-stage durations (events on the library's stream), averaged
+        st = {"bin": 0.0, "learned": 0.0, "lm": 0.0, "polish": 0.0, "fallback": 0.0}
+        reps = min(steps, 10)
+        for _ in range(reps):
+            ctx.solve(db, o, out)
+            tm = ctx.timings()
+            for key in st:
+                st[key] += tm[key] / reps
+        return dt, k, st
+
+    # launch choices picked by the autotuner (untimed)
+    tuned = {}
+    for v in ([variant] + [x for x in ("S", "P") if x != variant]):
+        tuned[v] = ctx.autotune(db, opts_for(v), out)
+        print(f"# autotune {v}: {tuned[v]}", file=sys.stderr, flush=True)
+
+    results = {}
+    for v in ([variant] + [x for x in ("S", "P") if x != variant]):
+        steps = args.steps if v == variant else max(5, args.steps // 4)
+        warm = args.warmup if v == variant else 1
+        dt, k, st = timed(v, steps, warm)
+        r = out.numpy()
+        results[v] = {"ms_per_step": dt * 1e3, "accepted": k, "paths_per_s": k / dt, "stage_ms": st,
+                      "fallback": int((r["status"] & 0x80).astype(bool).sum()),
+                      "iters_mean": float(r["iters"].mean()), "lm_iters_mean": float(r["stage"][0].mean()),
+                      "launch": tuned[v],
+                      "_r": r}
+        print(f"# {v}: {dt * 1e3:.3f} ms/step, {k} accepted, {k / dt:.4g} paths/s, stages {st}", file=sys.stderr,
+              flush=True)
+
+    main_r = results[variant]
+    r = main_r.pop("_r") if "_r" in main_r else None
+    # the last out is from the last variant run: recompute the main one's stages
+    ctx.solve(db, opts_for(variant), out)
+    ctx.synchronize()
+    r = out.numpy()
+    for v in results:
+        results[v].pop("_r", None)
+
+    # ---------------- roofline of the dominant kernel: the first LM pass
+    table = mpt.flops_table()
+    code = type_codes(scene, batch)
+    valid = (batch.order >= 1) & (batch.order <= 5)
+    flops_lm = algorithmic_flops(table, batch.order[valid], code[valid], r["stage"][0][valid], "lm")
+    lm_ms = main_r["stage_ms"]["lm"]
+    prec = "fp64" if variant == "P" else "fp32"
+    achieved = flops_lm / (lm_ms * 1e-3)
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"k_lm_{prec}_config{args.config}_traffic.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if tj.get("source_hash") == kernel_source_hash():
+            traffic = tj.get("bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[prec], "traffic": traffic, "kernel": f"k_lm<{prec}> (first LM pass)",
+                "flops_per_launch": flops_lm, "launch_ms": lm_ms}
+
+    # ---------------- parity on a sample and the CPU baseline (oracle)
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        O.lib()
+        ncores = os.cpu_count() or 1
+        try:
+            ncores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            pass
+        ncores = min(ncores, 16)
+        rng = np.random.default_rng(11)
+        m = args.cpu_sample or min(n, 12000 * ncores)
+        samp = np.sort(rng.choice(n, size=min(m, n), replace=False))
+        sb = batch.subset(samp)
+        t = time.perf_counter()
+        orc = O.solve_batch(scene, sb, nthreads=ncores)
+        oacc = O.accept_batch(scene, sb, orc["x"], orc["status"], nthreads=ncores)
+        dt = time.perf_counter() - t
+        cpu = {"value": float(oacc.sum()) / dt, "unit": "accepted paths/s", "cores": ncores, "kind": "oracle",
+               "sample": f"{len(samp)} of {n} solves (seeded uniform sample), solve + accept, {dt:.1f} s",
+               "solves_per_s": len(samp) / dt}
+        gacc = acc[:n].cpu().numpy()[samp]
+        both = (gacc == 1) & (oacc == 1)
+        err = 0.0
+        for i in np.where(both)[0]:
+            o_ = sb.order[i]
+            d = (r["x"][:3 * o_, samp[i]] - orc["x"][:3 * o_, i]).reshape(o_, 3)
+            err = max(err, float(np.linalg.norm(d, axis=1).max()))
+        parity = {"sample": int(len(samp)), "flag_mismatches": int((gacc != oacc).sum()),
+                  "gpu_only": int(((gacc == 1) & (oacc == 0)).sum()),
+                  "oracle_only": int(((gacc == 0) & (oacc == 1)).sum()), "max_point_err_m": err}
+
+    value = main_r["paths_per_s"]
+    line = {
+        "metric": "accepted paths/sec at 1e-6 m point error vs FP64 oracle (learned+FP32 vs plain)",
+        "value": value,
+        "unit": "accepted paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if variant != "P" else "f64",
+        "data": "synthetic (seeded generators)",
+        "config": {"workload": names[args.config], "config_index": args.config - 1, "solves": int(n),
+                   "variant": {"L": "learned start + FP32 LM + FP64 polish + fallback",
+                               "S": "straight-line start + FP32 LM + FP64 polish + fallback",
+                               "P": "plain FP64 LM"}[variant]},
+        "variants": {v: {k: (round(x, 6) if isinstance(x, float) else x) for k, x in d.items()}
+                     for v, d in results.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -125,7 +125,10 @@ typedef struct {
 enum { MPT_FP64_PLAIN = 0, MPT_FP32_POLISH64 = 1 };
 enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2 };
 enum { MPT_FALLBACK_NONE = 0, MPT_FALLBACK_GPU_FP64 = 1 };
-enum { MPT_SCHED_GRID = 0, MPT_SCHED_PERSISTENT = 1 };
+/* MPT_SCHED_PERSISTENT: one persistent launch runs every order's bin;
+ * MPT_SCHED_PER_ORDER: one persistent launch per order, with its own
+ * register budget, all five running concurrently on forked streams. */
+enum { MPT_SCHED_PER_ORDER = 0, MPT_SCHED_PERSISTENT = 1, MPT_SCHED_AUTO = 2 };
 
 /* Solver options; mpt_default_opts fills the defaults noted here. */
 typedef struct {
@@ -137,9 +140,12 @@ typedef struct {
     int32_t polish_steps;  /* 5    FP64 Gauss-Newton polish steps at most       */
     int32_t fallback;      /* MPT_FALLBACK_GPU_FP64                             */
     int32_t plateau_win;   /* 10   window of the plateau test (0: off)          */
-    int32_t sched;         /* MPT_SCHED_PERSISTENT                              */
-    int32_t block;         /* 0: autotuned threads per block                    */
-    int32_t grid;          /* 0: autotuned blocks (persistent schedule)         */
+    int32_t sched;         /* MPT_SCHED_AUTO: the autotuner's choice            */
+    int32_t block;         /* 0: the autotuner's threads per block (64..256)    */
+    int32_t grid;          /* 0: all blocks that fit on the device at once      */
+    int32_t graph;         /* 0: launch directly; 1: capture the whole solve in
+                              a HIP graph once per (batch, options, outputs,
+                              scene) and replay it (stage timings unavailable) */
     double plateau_frac;   /* 0.999 the cost must fall below frac x its value
                               one window earlier, else the descent ends         */
     double tol_step;       /* 1e-12 stop when |dx|_inf <= tol_step (1+|x|_inf)  */
@@ -148,21 +154,26 @@ typedef struct {
     double lambda0;        /* 1e-3  initial damping / max diag(J^T J)           */
     double tol_step32;     /* 1e-6  FP32 stage step tolerance (relative)        */
     double tol_res32;      /* 1e-5  FP32 stage residual tolerance (metres)      */
+    double tau_root32;     /* 1e-4  an FP32 end point this close is a root: if
+                              its FP64 polish fails, FP64 re-solves the path    */
     double polish_gate;    /* 1e-2  FP32 end points with |R|_inf above this are
                               final (no path); below it they are polished       */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 
 /* Outputs, DEVICE pointers owned by the caller:
- *   x      [15][n] FP64 points (component-major, zero beyond 3*order)
- *   cost   [n] FP64 final cost C = |R|^2 (Eq. 12 with the rescaled rows)
- *   iters  [n] int32 iterations run (FP32 + polish + fallback)
- *   status [n] uint8 MPT_PATH_* code, bit 7 = fallback used               */
+ *   x           [15][n] FP64 points (component-major, zero beyond 3*order)
+ *   cost        [n] FP64 final cost C = |R|^2 (Eq. 12 with the rescaled rows)
+ *   iters       [n] int32 iterations run (FP32 + polish + fallback)
+ *   status      [n] uint8 MPT_PATH_* code, bit 7 = fallback used
+ *   stage_iters [3][n] int32 or NULL: iterations of the first LM pass (FP32
+ *               or plain FP64), polish steps, fallback iterations           */
 typedef struct {
     double *x;
     double *cost;
     int32_t *iters;
     uint8_t *status;
+    int32_t *stage_iters;
 } mpt_solve_out;
 
 /*
@@ -177,6 +188,19 @@ typedef struct {
  */
 mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_opts *opts,
                            const mpt_solve_out *out);
+
+/*
+ * Autotuner of the launch choices that do not change results (the schedule -
+ * one mixed-order launch or concurrent per-order launches - and the block
+ * size): runs the first LM pass of the given batch with each candidate
+ * (writing the outputs), keeps the fastest and uses it for later solves of
+ * the same precision, size class (floor log2 n) and scene size.  With the
+ * environment variable MPT_AUTOTUNE_CACHE set to a file path, choices are
+ * loaded from and saved to that file (one line per entry).  Synchronises.
+ * best_* (host, may be NULL) receive the choice and its time in ms.
+ */
+mpt_status mpt_autotune(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_opts *opts,
+                        const mpt_solve_out *out, int32_t *best_sched, int32_t *best_block, float *best_ms);
 
 /*
  * The acceptance test of Alg. 1 ("C < threshold and X is valid") in FP64 on
@@ -203,13 +227,35 @@ mpt_status mpt_accept(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve
  */
 /* Initialise the network with seeded random weights. */
 mpt_status mpt_mlp_init(mpt_ctx *ctx, uint64_t seed);
-/* One Adam step of the masked mean-squared error between the predicted and
- * the target points of the given solves (targets: x [15][n] FP64 device, the
- * solver's converged points; mask: rows beyond each order and solves whose
- * `use` flag (uint8 [n], may be NULL = all) is zero are ignored).  *d_loss
- * (device FP32, may be NULL) receives the loss before the step. */
+/* One Adam step (FP32 master weights, beta 0.9 / 0.999, eps 1e-8) on the
+ * masked mean-squared error between the predicted and the target points,
+ * in frame units, of the minibatch `rows` (device int32 [n_rows] ids into the
+ * batch; NULL = every solve).  target_x: [15][n] FP64 device, for example the
+ * solver's converged points; coordinates beyond a path's order and solves
+ * whose `use` flag (uint8 [n], NULL = all) is zero are masked out.
+ * *d_loss (device FP32, may be NULL) receives the loss before the step.  */
 mpt_status mpt_mlp_train_step(mpt_ctx *ctx, const mpt_batch_desc *batch, const double *target_x,
-                              const uint8_t *use, float lr, float *d_loss);
+                              const uint8_t *use, const int32_t *rows, int32_t n_rows, float lr,
+                              float *d_loss);
+/* The same loss and its gradient with respect to every parameter, without
+ * an update: d_grad (device FP32, mpt_mlp_param_count values, in the order
+ * of the saved blob's weights).  For gradient checks. */
+mpt_status mpt_mlp_grad(mpt_ctx *ctx, const mpt_batch_desc *batch, const double *target_x,
+                        const uint8_t *use, const int32_t *rows, int32_t n_rows, float *d_loss,
+                        float *d_grad);
+/* The 96 input features of every solve, FP32 [n][96] device (before the
+ * BF16 rounding the network applies). */
+mpt_status mpt_mlp_features(mpt_ctx *ctx, const mpt_batch_desc *batch, float *d_feat);
+/* Number of FP32 parameters (W1 [256][96], b1, W2 [256][256], b2, W3, b3,
+ * W4 [16][256] with row 15 unused, b4 [16]). */
+mpt_status mpt_mlp_param_count(size_t *count);
+/* Check of the matrix-core GEMM the network uses: C = A B with A [M][K]
+ * (a_trans: stored [K][M]) and B [K][N] (b_trans: stored [N][K]), FP32
+ * device inputs rounded to BF16, FP32 accumulation, K split `splits` ways.
+ * Synchronises. */
+mpt_status mpt_gemm_bf16_check(mpt_ctx *ctx, int32_t M, int32_t N, int32_t K, const float *A,
+                               int32_t a_trans, const float *B, int32_t b_trans, float *C,
+                               int32_t splits);
 /* Predicted points [15][n] FP64 world frame (device, caller-owned). */
 mpt_status mpt_mlp_predict(mpt_ctx *ctx, const mpt_batch_desc *batch, double *x_out);
 /* Serialise / restore the network (FP32 master weights and Adam state).
@@ -217,9 +263,23 @@ mpt_status mpt_mlp_predict(mpt_ctx *ctx, const mpt_batch_desc *batch, double *x_
 mpt_status mpt_mlp_save(mpt_ctx *ctx, void *blob, size_t *bytes);
 mpt_status mpt_mlp_load(mpt_ctx *ctx, const void *blob, size_t bytes);
 
-/* Per-stage timings of the last mpt_solve_batch in milliseconds (HIP
- * events; synchronises): [0] bin, [1] learned start, [2] solve, [3] fallback. */
-mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[4]);
+/* Algorithmic floating-point work of the solver for one path of `order`
+ * interactions whose primitive types are types[0..order-1] (MPT_PLANE ..
+ * MPT_CIRCLE), counted on the host by running the solver's own arithmetic
+ * with a counting scalar that skips operations on structural zeros:
+ *   out[0] one Levenberg-Marquardt iteration (residual, Jacobian, banded
+ *          normal equations, damping, banded Cholesky, solve, trial cost)
+ *   out[1] one Gauss-Newton polish step (no trial cost)
+ *   out[2] one residual evaluation (the acceptance test's arithmetic)
+ *   out[3] square roots and divisions inside out[0]
+ * Host only (no device work).  MPT_E_INVALID_ARG for a bad order or type. */
+mpt_status mpt_flops_per_iter(int order, const int32_t *types, int64_t out[4]);
+
+/* Per-stage timings of the last mpt_solve_batch in milliseconds (HIP events
+ * on the context's stream; synchronises): [0] order binning, [1] learned
+ * start, [2] first LM pass (FP32 or plain FP64), [3] FP64 polish,
+ * [4] FP64 fallback. */
+mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[5]);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/mpt.h.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -10,6 +11,7 @@
 #include "../../include/mpt.h"
 #include "mpt_internal.hpp"
 #include "mpt_mlp.hpp"
+#include "mpt_flops.hpp"
 
 using namespace mpt;
 
@@ -19,6 +21,7 @@ struct mpt_ctx {
     hipStream_t own = nullptr;
     std::string err;
     int cu = 256;
+    size_t lds_max = 65536;  // dynamic LDS a block may use
     // scene
     double *raw = nullptr, *rec64 = nullptr;
     float *rec32 = nullptr;
@@ -32,9 +35,19 @@ struct mpt_ctx {
     size_t blk_cap = 0;
     double *x0l = nullptr;
     size_t x0l_cap = 0;
-    hipEvent_t ev[5] = {};
+    hipEvent_t ev[6] = {};
+    hipStream_t aux[MPT_MAX_ORDER] = {};  // per-order launches run concurrently
+    hipEvent_t fork = nullptr, join[MPT_MAX_ORDER] = {};
     bool timed = false;
     MlpState *mlp = nullptr;
+    // autotuned launch choices: key -> (sched, block)
+    struct Tune { int prec, nbucket, n_all, sched, block; float ms; };
+    std::vector<Tune> tune;
+    bool tune_loaded = false;
+    // captured graph of the last solve (replayed while the key matches)
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey;
 };
 
 static const int kCounters = 32;  // bin_cnt 0..4, cursor 5..9, head 10..19, pol_cnt 20..24, fb_cnt 25..29
@@ -83,7 +96,12 @@ mpt_status mpt_create(int device, void *hip_stream, mpt_ctx **out)
     mpt_ctx *c = new mpt_ctx();
     c->device = device;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->cu = prop.multiProcessorCount;
+        // leave room for the static LDS of the kernels
+        const size_t per_cu = prop.maxSharedMemoryPerMultiProcessor;
+        if (per_cu > 4096) c->lds_max = per_cu - 4096;
+    }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
@@ -94,6 +112,11 @@ mpt_status mpt_create(int device, void *hip_stream, mpt_ctx **out)
         c->stream = c->own;
     }
     for (auto &e : c->ev) hipEventCreate(&e);
+    for (int i = 0; i < MPT_MAX_ORDER; i++) {
+        hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking);
+        hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming);
+    }
+    hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     *out = c;
     return MPT_OK;
 }
@@ -111,6 +134,13 @@ mpt_status mpt_destroy(mpt_ctx *c)
     hipFree(c->x0l);
     mlp_free(c->mlp);
     for (auto &e : c->ev) hipEventDestroy(e);
+    for (int i = 0; i < MPT_MAX_ORDER; i++) {
+        if (c->aux[i]) hipStreamSynchronize(c->aux[i]), hipStreamDestroy(c->aux[i]);
+        if (c->join[i]) hipEventDestroy(c->join[i]);
+    }
+    if (c->fork) hipEventDestroy(c->fork);
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->cap) hipStreamDestroy(c->cap);
     if (c->own) hipStreamDestroy(c->own);
     delete c;
     return MPT_OK;
@@ -219,9 +249,10 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->polish_steps = 5;
     o->fallback = MPT_FALLBACK_GPU_FP64;
     o->plateau_win = 10;
-    o->sched = MPT_SCHED_PERSISTENT;
+    o->sched = MPT_SCHED_AUTO;
     o->block = 0;
     o->grid = 0;
+    o->graph = 0;
     o->plateau_frac = 0.999;
     o->tol_step = 1e-12;
     o->tol_res = 1e-13;
@@ -229,6 +260,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->lambda0 = 1e-3;
     o->tol_step32 = 1e-6;
     o->tol_res32 = 1e-5;
+    o->tau_root32 = 1e-4;
     o->polish_gate = 1e-2;
 }
 
@@ -250,19 +282,76 @@ static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)
 }
 
 // Blocks of a persistent launch: as many as can be resident at once.
-static int resident_grid(mpt_ctx *c, const void *kern, int block, int64_t n)
+static int resident_grid(mpt_ctx *c, const void *kern, int block, int64_t n, size_t lds = 0)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
     int64_t g = (int64_t)per_cu * c->cu;
     const int64_t need = (n + block - 1) / block;
     if (need < g) g = need;
     return (int)(g < 1 ? 1 : g);
 }
 
-mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out)
+}  // extern "C"
+
+// ---------------------------------------------------------------- launch choices
+// Default launch choices before (or without) tuning, from measurements on
+// MI355X: FP32 passes run one launch per order concurrently (each order
+// keeps its own register budget), FP64 passes one mixed-order launch.
+static void default_choice(int prec, int &sched, int &block)
 {
-    if (!c) return MPT_E_INVALID_ARG;
+    if (prec == MPT_FP32_POLISH64) { sched = MPT_SCHED_PER_ORDER; block = 128; }
+    else { sched = MPT_SCHED_PERSISTENT; block = 256; }
+}
+
+static int nbucket(int64_t n)
+{
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n) b++;
+    return b;
+}
+
+static void tune_load(mpt_ctx *c)
+{
+    if (c->tune_loaded) return;
+    c->tune_loaded = true;
+    const char *path = getenv("MPT_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    // one entry per line: prec nbucket n_all sched block ms
+    mpt_ctx::Tune t;
+    while (fscanf(f, "%d %d %d %d %d %f", &t.prec, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.ms) == 6)
+        c->tune.push_back(t);
+    fclose(f);
+}
+
+static void tune_save(mpt_ctx *c)
+{
+    const char *path = getenv("MPT_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    for (auto &t : c->tune) fprintf(f, "%d %d %d %d %d %.6f\n", t.prec, t.nbucket, t.n_all, t.sched, t.block, t.ms);
+    fclose(f);
+}
+
+static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block)
+{
+    default_choice(o->precision, sched, block);
+    tune_load(c);
+    for (auto &t : c->tune)
+        if (t.prec == o->precision && t.nbucket == nbucket(n) && t.n_all == c->s.n_all) {
+            sched = t.sched;
+            block = t.block;
+        }
+    if (o->sched != MPT_SCHED_AUTO) sched = o->sched;
+    if (o->block) block = o->block;
+}
+
+static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out)
+{
     if (!opts || !out) return fail(c, MPT_E_INVALID_ARG, "null options or outputs");
     if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
     BatchDev bd;
@@ -281,16 +370,30 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
         return fail(c, MPT_E_INVALID_ARG, "negative iteration option");
     if (opts->block != 0 && (opts->block % 64 != 0 || opts->block > 256 || opts->block < 64))
         return fail(c, MPT_E_INVALID_ARG, "block must be 64, 128, 192 or 256");
-    hipSetDevice(c->device);
+    if (opts->sched < MPT_SCHED_PER_ORDER || opts->sched > MPT_SCHED_AUTO)
+        return fail(c, MPT_E_UNSUPPORTED, "sched %d", opts->sched);
+    if (opts->grid < 0) return fail(c, MPT_E_INVALID_ARG, "negative grid");
+    return MPT_OK;
+}
+
+// Enqueue the whole solve on stream s (no host synchronisation).  With
+// `timed`, HIP events mark the stage boundaries (not inside graph capture).
+static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts,
+                                const mpt_solve_out *out, hipStream_t s, bool timed, int sched, int block)
+{
+    BatchDev bd;
+    mpt_status st = batch_dev(c, b, bd);
+    if (st) return st;
     const int64_t n = b->n;
     if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 3 * (size_t)(n > 0 ? n : 1), sizeof(int)))) return st;
-    if (opts->init == MPT_INIT_LEARNED && (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * (size_t)n, sizeof(double))))
+    if (opts->init == MPT_INIT_LEARNED &&
+        (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * (size_t)(n > 0 ? n : 1), sizeof(double))))
         return st;
     int *ctr = c->ws;
     KParams kp{};
     kp.s = c->s;
     kp.b = bd;
-    kp.out = OutDev{out->x, out->cost, out->iters, out->status};
+    kp.out = OutDev{out->x, out->cost, out->iters, out->status, out->stage_iters};
     kp.o.init = opts->init;
     kp.o.max_iter = opts->max_iter;
     kp.o.max_iter32 = opts->max_iter32;
@@ -304,6 +407,7 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     kp.o.lambda0 = opts->lambda0;
     kp.o.tol_step32 = opts->tol_step32;
     kp.o.tol_res32 = opts->tol_res32;
+    kp.o.tau_root32 = opts->tau_root32;
     kp.o.polish_gate = opts->polish_gate;
     kp.x0_learned = c->x0l;
     kp.bin_cnt = ctr + 0;
@@ -314,51 +418,229 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     kp.pol_list = ctr + kCounters + n;
     kp.fb_list = ctr + kCounters + 2 * n;
 
-    hipStream_t s = c->stream;
-    hipEventRecord(c->ev[0], s);
+    if (timed) hipEventRecord(c->ev[0], s);
     launch_zero(ctr, kCounters, s);
     launch_bin(bd, kp.out, c->s.n_all, ctr + 0, ctr + 5, (int *)kp.perm, s);
-    hipEventRecord(c->ev[1], s);
+    if (timed) hipEventRecord(c->ev[1], s);
     if (opts->init == MPT_INIT_LEARNED && n > 0) {
         if ((st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s))) return fail(c, st, "network forward failed");
     }
-    hipEventRecord(c->ev[2], s);
-    const int block = opts->block ? opts->block : 256;
+    if (timed) hipEventRecord(c->ev[2], s);
     const int mode = (opts->precision == MPT_FP64_PLAIN) ? MODE_PLAIN64 : MODE_FP32;
-    auto run_lm = [&](int md) {
-        if (opts->sched == MPT_SCHED_PERSISTENT) {
-            const void *k = lm_kernel(md, 0);
-            const int g = opts->grid ? opts->grid : resident_grid(c, k, block, n);
-            launch_lm(md, 0, kp, g, block, s);
+    auto run_lm = [&](int md, int sch, int blk) {
+        // stage the scene in LDS when it fits
+        const size_t rec_bytes = (size_t)c->s.n_all * kRec * (md == MODE_FP32 ? sizeof(float) : sizeof(double));
+        const bool lds = rec_bytes <= c->lds_max;
+        auto go = [&](int ord, hipStream_t where) {
+            const void *k = lm_kernel(md, ord, lds);
+            if (lds) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rec_bytes);
+            int g = opts->grid;
+            if (!g) g = resident_grid(c, k, blk, n, lds ? rec_bytes : 0);
+            launch_lm(md, ord, lds, rec_bytes, kp, g, blk, where);
+        };
+        if (sch == MPT_SCHED_PERSISTENT) {
+            go(0, s);
         } else {
+            // one launch per order, each on its own stream (fork / join on
+            // the stream s): the waves of a later order fill the CUs an
+            // earlier order's drained bin leaves idle
+            hipEventRecord(c->fork, s);
             for (int ord = MPT_MAX_ORDER; ord >= 1; ord--) {
-                const void *k = lm_kernel(md, ord);
-                const int g = opts->grid ? opts->grid : resident_grid(c, k, block, n);
-                launch_lm(md, ord, kp, g, block, s);
+                hipStreamWaitEvent(c->aux[ord - 1], c->fork, 0);
+                go(ord, c->aux[ord - 1]);
+                hipEventRecord(c->join[ord - 1], c->aux[ord - 1]);
             }
+            for (int ord = 1; ord <= MPT_MAX_ORDER; ord++) hipStreamWaitEvent(s, c->join[ord - 1], 0);
         }
     };
-    if (n > 0) {
-        run_lm(mode);
-        if (mode == MODE_FP32) {
-            const int g = resident_grid(c, polish_kernel(), 256, n);
-            launch_polish(kp, g, 256, s);
-        }
-    }
-    hipEventRecord(c->ev[3], s);
-    if (n > 0 && mode == MODE_FP32 && opts->fallback) run_lm(MODE_FALLBACK64);
-    hipEventRecord(c->ev[4], s);
-    c->timed = true;
+    if (n > 0) run_lm(mode, sched, block);
+    if (timed) hipEventRecord(c->ev[3], s);
+    if (n > 0 && mode == MODE_FP32) launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
+    if (timed) hipEventRecord(c->ev[4], s);
+    // the fallback handles a handful of paths: one mixed-order launch
+    if (n > 0 && mode == MODE_FP32 && opts->fallback) run_lm(MODE_FALLBACK64, MPT_SCHED_PERSISTENT, 256);
+    if (timed) hipEventRecord(c->ev[5], s);
+    if (timed) c->timed = true;
     HIPCHK(c, hipGetLastError());
     return MPT_OK;
 }
 
-mpt_status mpt_last_timings(mpt_ctx *c, float ms[4])
+static std::vector<unsigned char> graph_key(const mpt_batch_desc *b, const mpt_solve_opts *o, const mpt_solve_out *out,
+                                            int sched, int block, const SceneDev &s)
+{
+    std::vector<unsigned char> k(sizeof *b + sizeof *o + sizeof *out + 2 * sizeof(int) + sizeof s);
+    unsigned char *p = k.data();
+    memcpy(p, b, sizeof *b), p += sizeof *b;
+    memcpy(p, o, sizeof *o), p += sizeof *o;
+    memcpy(p, out, sizeof *out), p += sizeof *out;
+    memcpy(p, &sched, sizeof sched), p += sizeof sched;
+    memcpy(p, &block, sizeof block), p += sizeof block;
+    memcpy(p, &s, sizeof s);
+    return k;
+}
+
+extern "C" {
+
+mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    mpt_status st = check_opts(c, b, opts, out);
+    if (st) return st;
+    hipSetDevice(c->device);
+    int sched, block;
+    choose(c, opts, b->n, sched, block);
+    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block);
+
+    // graph mode: capture once per (batch, options, outputs, scene) and replay
+    std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, c->s);
+    if (!c->gexec || key != c->gkey) {
+        if (c->gexec) hipGraphExecDestroy(c->gexec), c->gexec = nullptr;
+        if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        // buffers are sized before capture: no allocation inside it
+        if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 3 * (size_t)(b->n > 0 ? b->n : 1), sizeof(int))))
+            return st;
+        HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        st = enqueue_solve(c, b, opts, out, c->cap, false, sched, block);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap, &g);
+        if (st) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, MPT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(c, MPT_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+        c->gkey = key;
+    }
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    return MPT_OK;
+}
+
+mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out,
+                        int32_t *best_sched, int32_t *best_block, float *best_ms)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    mpt_status st = check_opts(c, b, opts, out);
+    if (st) return st;
+    hipSetDevice(c->device);
+    tune_load(c);
+    const int scheds[2] = {MPT_SCHED_PER_ORDER, MPT_SCHED_PERSISTENT};
+    const int blocks[3] = {64, 128, 256};
+    float best = 1e30f;
+    int bs = 0, bb = 0;
+    for (int si = 0; si < 2; si++)
+        for (int bi = 0; bi < 3; bi++) {
+            float tot = 0.0f;
+            for (int rep = 0; rep < 3; rep++) {
+                if ((st = enqueue_solve(c, b, opts, out, c->stream, true, scheds[si], blocks[bi]))) return st;
+                HIPCHK(c, hipEventSynchronize(c->ev[5]));
+                float ms = 0.0f;
+                HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+                if (rep > 0) tot += ms;  // the first run warms up
+            }
+            if (tot < best) best = tot, bs = scheds[si], bb = blocks[bi];
+        }
+    best *= 0.5f;
+    bool found = false;
+    for (auto &t : c->tune)
+        if (t.prec == opts->precision && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
+            t.sched = bs, t.block = bb, t.ms = best, found = true;
+    if (!found) c->tune.push_back({opts->precision, nbucket(b->n), c->s.n_all, bs, bb, best});
+    tune_save(c);
+    if (best_sched) *best_sched = bs;
+    if (best_block) *best_block = bb;
+    if (best_ms) *best_ms = best;
+    return MPT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- FLOP count
+template <int N>
+static void count_one(const int32_t *types, int64_t out[4])
+{
+    // a small synthetic scene: one record per interaction with generic
+    // (non-zero, non-special) values, so no operation is skipped by accident
+    uint64_t st = 0x9e3779b97f4a7c15ull;
+    auto rnd = [&]() {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        return 0.25 + 0.5 * (double)((st >> 11) & ((1ull << 53) - 1)) / (double)(1ull << 53);
+    };
+    Cnt rec[N * kRec];
+    int np = 0, nl = 0, nq = 0;
+    for (int k = 0; k < N; k++) {
+        if (types[k] == MPT_PLANE) np++;
+        else if (types[k] == MPT_LINE) nl++;
+        else if (types[k] == MPT_QUADRIC) nq++;
+    }
+    PathIn<Cnt, N> p;
+    int next[4] = {0, np, np + nl, np + nl + nq};
+    for (int k = 0; k < N; k++) {
+        const int id = next[types[k]]++;
+        p.id[k] = id;
+        p.ty[k] = types[k];
+        for (int i = 0; i < kRec; i++) rec[id * kRec + i] = Cnt(rnd());
+    }
+    SceneT<Cnt> sc;
+    sc.rec = rec;
+    for (int i = 0; i < 3; i++) {
+        sc.tx[i] = Cnt(rnd());
+        sc.glo[i] = Cnt(-1e9);
+        sc.ghi[i] = Cnt(1e9);
+        p.rx[i] = Cnt(rnd() + 5.0);
+    }
+    Cnt X[3 * N], A[Band<N>::SIZE], g[3 * N], C, rinf;
+    for (int i = 0; i < 3 * N; i++) X[i] = Cnt(rnd() + i);
+    constexpr int M = 3 * N;
+    // one LM iteration
+    tally() = FlopTally();
+    assemble<Cnt, N>(sc, p, X, A, g, C, rinf);
+    Cnt lam(rnd()), dmax(rnd());
+    for (int i = 0; i < M; i++) A[Band<N>::at(i, i)] += lam * fmax(A[Band<N>::at(i, i)], Cnt(1e-12) * dmax);
+    chol_band<Cnt, N>(A);
+    chol_solve_band<Cnt, N>(A, g);
+    Cnt Ct, rt;
+    eval_cost<Cnt, N>(sc, p, X, g, Ct, rt);
+    for (int i = 0; i < M; i++) X[i] += g[i];
+    out[0] = tally().flops();
+    out[3] = tally().sqrt + tally().div;
+    // one polish step
+    tally() = FlopTally();
+    assemble<Cnt, N>(sc, p, X, A, g, C, rinf);
+    chol_band<Cnt, N>(A);
+    chol_solve_band<Cnt, N>(A, g);
+    for (int i = 0; i < M; i++) X[i] += g[i];
+    out[1] = tally().flops();
+    // one residual evaluation
+    tally() = FlopTally();
+    eval_cost<Cnt, N>(sc, p, X, nullptr, C, rinf);
+    out[2] = tally().flops();
+}
+
+extern "C" mpt_status mpt_flops_per_iter(int order, const int32_t *types, int64_t out[4])
+{
+    if (!types || !out || order < 1 || order > MPT_MAX_ORDER) return MPT_E_INVALID_ARG;
+    for (int k = 0; k < order; k++)
+        if (types[k] < MPT_PLANE || types[k] > MPT_CIRCLE) return MPT_E_INVALID_ARG;
+    switch (order) {
+    case 1: count_one<1>(types, out); break;
+    case 2: count_one<2>(types, out); break;
+    case 3: count_one<3>(types, out); break;
+    case 4: count_one<4>(types, out); break;
+    default: count_one<5>(types, out); break;
+    }
+    return MPT_OK;
+}
+
+extern "C" {
+
+mpt_status mpt_last_timings(mpt_ctx *c, float ms[5])
 {
     if (!c || !ms) return MPT_E_INVALID_ARG;
     if (!c->timed) return fail(c, MPT_E_INVALID_ARG, "no solve recorded");
-    HIPCHK(c, hipEventSynchronize(c->ev[4]));
-    for (int i = 0; i < 4; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
+    HIPCHK(c, hipEventSynchronize(c->ev[5]));
+    for (int i = 0; i < 5; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
     return MPT_OK;
 }
 
@@ -402,7 +684,7 @@ mpt_status mpt_mlp_init(mpt_ctx *c, uint64_t seed)
 }
 
 mpt_status mpt_mlp_train_step(mpt_ctx *c, const mpt_batch_desc *b, const double *target_x, const uint8_t *use,
-                              float lr, float *d_loss)
+                              const int32_t *rows, int32_t n_rows, float lr, float *d_loss)
 {
     if (!c) return MPT_E_INVALID_ARG;
     if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
@@ -412,9 +694,58 @@ mpt_status mpt_mlp_train_step(mpt_ctx *c, const mpt_batch_desc *b, const double 
     if (st) return st;
     if (b->n > 0 && !target_x) return fail(c, MPT_E_INVALID_ARG, "null targets");
     if (!(lr >= 0.0f)) return fail(c, MPT_E_INVALID_ARG, "negative learning rate");
+    const int nr = rows ? n_rows : (int)b->n;
+    if (nr <= 0 || (rows && (int64_t)n_rows > b->n)) return fail(c, MPT_E_INVALID_ARG, "bad row count");
     hipSetDevice(c->device);
-    st = mlp_train_step_dev(c->mlp, c->s, bd, target_x, use, lr, d_loss, c->stream);
+    st = mlp_train_step_dev(c->mlp, c->s, bd, rows, nr, target_x, use, lr, d_loss, c->stream);
     return st ? fail(c, st, "training step failed") : MPT_OK;
+}
+
+mpt_status mpt_mlp_grad(mpt_ctx *c, const mpt_batch_desc *b, const double *target_x, const uint8_t *use,
+                        const int32_t *rows, int32_t n_rows, float *d_loss, float *d_grad)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
+    if (!mlp_ready(c->mlp)) return fail(c, MPT_E_NO_MODEL, "no network initialised");
+    BatchDev bd;
+    mpt_status st = batch_dev(c, b, bd);
+    if (st) return st;
+    if (b->n > 0 && !target_x) return fail(c, MPT_E_INVALID_ARG, "null targets");
+    const int nr = rows ? n_rows : (int)b->n;
+    if (nr <= 0 || (rows && (int64_t)n_rows > b->n)) return fail(c, MPT_E_INVALID_ARG, "bad row count");
+    hipSetDevice(c->device);
+    st = mlp_grad_dev(c->mlp, c->s, bd, rows, nr, target_x, use, d_loss, d_grad, c->stream);
+    return st ? fail(c, st, "gradient failed") : MPT_OK;
+}
+
+mpt_status mpt_mlp_features(mpt_ctx *c, const mpt_batch_desc *b, float *d_feat)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
+    BatchDev bd;
+    mpt_status st = batch_dev(c, b, bd);
+    if (st) return st;
+    if (b->n > 0 && !d_feat) return fail(c, MPT_E_INVALID_ARG, "null output");
+    hipSetDevice(c->device);
+    st = mlp_features_dev(c->s, bd, d_feat, c->stream);
+    return st ? fail(c, st, "features failed") : MPT_OK;
+}
+
+mpt_status mpt_mlp_param_count(size_t *count)
+{
+    if (!count) return MPT_E_INVALID_ARG;
+    *count = mlp_param_count();
+    return MPT_OK;
+}
+
+mpt_status mpt_gemm_bf16_check(mpt_ctx *c, int32_t M, int32_t N, int32_t K, const float *A, int32_t a_trans,
+                               const float *B, int32_t b_trans, float *C, int32_t splits)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    if (M < 1 || N < 1 || K < 1 || splits < 1 || !A || !B || !C) return fail(c, MPT_E_INVALID_ARG, "bad GEMM args");
+    hipSetDevice(c->device);
+    mpt_status st = gemm_test_dev(M, N, K, A, a_trans, B, b_trans, C, splits, c->stream);
+    return st ? fail(c, st, "GEMM check failed") : MPT_OK;
 }
 
 mpt_status mpt_mlp_predict(mpt_ctx *c, const mpt_batch_desc *b, double *x_out)

@@ -36,18 +36,17 @@ struct SceneT {
     T glo[3], ghi[3];  // guard box
 };
 
-__device__ __forceinline__ int prim_type(int id, int a, int b, int c)
+__host__ __device__ __forceinline__ int prim_type(int id, int a, int b, int c)
 {
     return (id < a) ? TP : (id < b) ? TL : (id < c) ? TQ : TC;
 }
 
-template <typename T> __device__ __forceinline__ T dsqrt(T x);
-template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
-template <typename T> __device__ __forceinline__ T drcp(T x) { return T(1) / x; }
+__host__ __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+template <typename T> __host__ __device__ __forceinline__ T drcp(T x) { return T(1) / x; }
 
 template <typename T>
-__device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__host__ __device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 // -------------------------------------------------------------------------
 // Rows of one interaction (5 slots: 0..2 law rows, 3..4 object rows; unused
@@ -63,7 +62,7 @@ __device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0] * b[0] +
 // Returns false when a direction is undefined (degenerate).
 // -------------------------------------------------------------------------
 template <typename T, bool WITH_J>
-__device__ __forceinline__ bool interaction_rows(int t, const T *__restrict__ r, const T *Xp, const T *Xk,
+__host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__restrict__ r, const T *Xp, const T *Xk,
                                                  const T *Xn, T u[5], T Jp[3][3], T Jk[5][3], T Jn[3][3])
 {
     // No early exits: an undefined direction sets valid = false and the
@@ -227,7 +226,7 @@ struct PathIn {
 // Points of interaction k for the residual evaluated at X + dx (dx may be
 // null): X_0 = TX, X_{N+1} = RX.
 template <typename T, int N>
-__device__ __forceinline__ void point_at(int k, const T *X, const T *dx, const T *tx, const T *rx, T out[3])
+__host__ __device__ __forceinline__ void point_at(int k, const T *X, const T *dx, const T *tx, const T *rx, T out[3])
 {
     if (k < 0) { out[0] = tx[0]; out[1] = tx[1]; out[2] = tx[2]; return; }
     if (k >= N) { out[0] = rx[0]; out[1] = rx[1]; out[2] = rx[2]; return; }
@@ -237,7 +236,7 @@ __device__ __forceinline__ void point_at(int k, const T *X, const T *dx, const T
 
 // Residual cost and inf-norm at X (+dx).  Returns false if degenerate.
 template <typename T, int N>
-__device__ __forceinline__ bool eval_cost(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X, const T *dx,
+__host__ __device__ __forceinline__ bool eval_cost(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X, const T *dx,
                                           T &C, T &rinf)
 {
     C = T(0);
@@ -263,7 +262,7 @@ __device__ __forceinline__ bool eval_cost(const SceneT<T> &sc, const PathIn<T, N
 
 // Residual, J^T J (in-band, packed lower) and g = J^T R at X.
 template <typename T, int N>
-__device__ __forceinline__ bool assemble(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X,
+__host__ __device__ __forceinline__ bool assemble(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X,
                                          T *A, T *g, T &C, T &rinf)
 {
     constexpr int M = 3 * N;
@@ -335,7 +334,7 @@ __device__ __forceinline__ bool assemble(const SceneT<T> &sc, const PathIn<T, N>
 
 // In-place banded Cholesky of the packed lower band; false if not SPD.
 template <typename T, int N>
-__device__ __forceinline__ bool chol_band(T *A)
+__host__ __device__ __forceinline__ bool chol_band(T *A)
 {
     constexpr int M = 3 * N;
     bool ok = true;
@@ -364,7 +363,7 @@ __device__ __forceinline__ bool chol_band(T *A)
 
 // Solve L L^T x = b in place (b -> x).
 template <typename T, int N>
-__device__ __forceinline__ void chol_solve_band(const T *L, T *b)
+__host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
 {
     constexpr int M = 3 * N;
 #pragma unroll

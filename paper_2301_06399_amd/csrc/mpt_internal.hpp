@@ -8,6 +8,8 @@ namespace mpt {
 
 enum : int { MODE_PLAIN64 = 0, MODE_FP32 = 1, MODE_FALLBACK64 = 2 };
 enum : int { INIT_LINE = 0, INIT_USER = 1, INIT_LEARNED = 2 };
+// transient status codes between the FP32 pass and the polish
+enum : int { ROUTE_POLISH_FB = 254, ROUTE_POLISH_MAXIT = 253, ROUTE_POLISH_LOCALMIN = 252 };
 
 // Scene as the kernels see it (device pointers).
 struct SceneDev {
@@ -33,6 +35,7 @@ struct OutDev {
     double *cost;
     int *iters;
     uint8_t *status;
+    int *stage;  // [3][n] or null
 };
 
 struct OutDevC {
@@ -44,7 +47,7 @@ struct OutDevC {
 
 struct OptsDev {
     int init, max_iter, max_iter32, polish_steps, fallback, plateau_win;
-    double plateau_frac, tol_step, tol_res, tau_root, lambda0, tol_step32, tol_res32, polish_gate;
+    double plateau_frac, tol_step, tol_res, tau_root, lambda0, tol_step32, tol_res32, tau_root32, polish_gate;
 };
 
 // Everything a solver kernel needs, passed by value.
@@ -66,8 +69,9 @@ struct KParams {
 void launch_pack(const double *raw, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c, hipStream_t st);
 void launch_zero(int *p, int n, hipStream_t st);
 void launch_bin(const BatchDev &b, const OutDev &out, int n_all, int *cnt, int *cursor, int *perm, hipStream_t st);
-const void *lm_kernel(int mode, int order);
-void launch_lm(int mode, int order, const KParams &kp, int grid, int block, hipStream_t st);
+const void *lm_kernel(int mode, int order, bool lds);
+void launch_lm(int mode, int order, bool lds, size_t lds_bytes, const KParams &kp, int grid, int block,
+               hipStream_t st);
 const void *polish_kernel();
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,

@@ -1,22 +1,748 @@
-// Learned warm start (placeholder until the network kernels land).
+// Learned warm start: a small MLP that predicts the interaction points of a
+// path from TX, RX and its objects (replacing the random guess of the
+// paper's algorithm), trained on the GPU on solver outputs.
+//
+//   features (96) -> 256 -> 256 -> 256 -> 15, GELU (erf form) after the
+//   hidden layers; BF16 weights and activations, FP32 accumulation on the
+//   matrix cores (v_mfma_f32_32x32x8bf16_1k), FP32 master weights + Adam.
+//
+// Kernels: k_features (per path), k_gemm (LDS-tiled MFMA GEMM with bias /
+// GELU / GELU' epilogues and split-K partials), k_reduce_splits, k_colsum
+// (bias gradients), k_loss (masked MSE and its gradient), k_adam, k_decode.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string>
+#include <vector>
+
 #include "mpt_mlp.hpp"
 
 namespace mpt {
 
-struct MlpState {
-    int dummy;
+constexpr int F_IN = 96, HID = 256, F_OUT = 15, F_OUTP = 16;
+constexpr int SLOT = 17;  // per-interaction feature slot: one-hot 4, params 12, present 1
+
+// ------------------------------------------------------------------ bf16
+typedef uint16_t bf16;
+__device__ __forceinline__ bf16 f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ------------------------------------------------------------------ features
+// Frame: origin TX, scale 1/L with L = |RX - TX|.  Per interaction slot k:
+// one-hot type, then the object in the frame - plane: n, (d - n.TX)/L;
+// straight edge: e, the edge point nearest TX; quadric: anchor, L A, b;
+// circle: centre, normal, R/L - then a present bit.  Unused slots are zero.
+__global__ void k_features(SceneDev s, BatchDev b, const int *__restrict__ rows, int nrows, float *__restrict__ fout,
+                           bf16 *__restrict__ xout)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const int i = rows ? rows[r] : r;
+    float f[F_IN];
+#pragma unroll
+    for (int j = 0; j < F_IN; j++) f[j] = 0.0f;
+    const int ord = b.order[i];
+    const int ri = b.rx_index[i];
+    const bool ok_rx = ri >= 0 && ri < b.n_rx;
+    double rx[3] = {0, 0, 0};
+    if (ok_rx)
+        for (int c = 0; c < 3; c++) rx[c] = b.rx[3 * (size_t)ri + c];
+    double L = sqrt((rx[0] - s.tx[0]) * (rx[0] - s.tx[0]) + (rx[1] - s.tx[1]) * (rx[1] - s.tx[1]) +
+                    (rx[2] - s.tx[2]) * (rx[2] - s.tx[2]));
+    if (!(L > 0.0) || !isfinite(L)) L = 1.0;
+    const double is = 1.0 / L;
+    for (int c = 0; c < 3; c++) f[c] = (float)((rx[c] - s.tx[c]) * is);
+#pragma unroll
+    for (int k = 0; k < kMaxN; k++) {
+        if (k >= ord) continue;
+        const int id = b.prim[(size_t)k * b.n + i];
+        if (id < 0 || id >= s.n_all) continue;
+        const int t = prim_type(id, s.n_pl, s.n_pl_ln, s.n_pl_ln_q);
+        const double *q = s.rec64 + (size_t)id * kRec;
+        const int base = 6 + SLOT * k;
+        float p[12];
+#pragma unroll
+        for (int j = 0; j < 12; j++) p[j] = 0.0f;
+        if (t == TP) {
+            for (int c = 0; c < 3; c++) p[c] = (float)q[c];
+            p[3] = (float)((q[3] - (q[0] * s.tx[0] + q[1] * s.tx[1] + q[2] * s.tx[2])) * is);
+        } else if (t == TL) {
+            const double w = (s.tx[0] - q[0]) * q[3] + (s.tx[1] - q[1]) * q[4] + (s.tx[2] - q[2]) * q[5];
+            for (int c = 0; c < 3; c++) {
+                p[c] = (float)q[3 + c];
+                p[3 + c] = (float)((q[c] + w * q[3 + c] - s.tx[c]) * is);
+            }
+        } else if (t == TQ) {
+            for (int c = 0; c < 3; c++) p[c] = (float)((q[c] - s.tx[c]) * is);
+            for (int c = 0; c < 6; c++) p[3 + c] = (float)(q[3 + c] * L);
+            for (int c = 0; c < 3; c++) p[9 + c] = (float)q[9 + c];
+        } else {
+            for (int c = 0; c < 3; c++) {
+                p[c] = (float)((q[c] - s.tx[c]) * is);
+                p[3 + c] = (float)q[3 + c];
+            }
+            p[6] = (float)(q[6] * is);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; tt++) f[base + tt] = (t == tt) ? 1.0f : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 12; j++) f[base + 4 + j] = p[j];
+        f[base + 16] = 1.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < F_IN; j++) {
+        const bf16 h = f2bf(f[j]);
+        if (xout) xout[(size_t)r * F_IN + j] = h;
+        if (fout) fout[(size_t)r * F_IN + j] = f[j];
+    }
+}
+
+// ------------------------------------------------------------------ GEMM
+// C[M x N] = A[M x K] B[K x N], BF16 operands, FP32 accumulation.
+// A(m,k) = AT ? A[k*lda + m] : A[m*lda + k];  B(k,n) = BT ? B[n*ldb + k] : B[k*ldb + n].
+// Block tile 64 x 64 x 32 staged in LDS; 4 waves, each one 32 x 32 MFMA tile.
+// blockIdx.z splits K into chunks of kps (multiple of 32).
+enum : int { EPI_BIAS_GELU = 0, EPI_BIAS = 1, EPI_DGELU = 2, EPI_F32 = 3 };
+
+struct Epi {
+    const float *bias;   // [N]
+    float *zout;         // [M][ldc] pre-activation (EPI_BIAS_GELU, optional)
+    bf16 *hout;          // [M][ldc] bf16 output (EPI_BIAS_GELU, EPI_DGELU)
+    float *fout;         // [splits][M][ldc] fp32 output (EPI_BIAS, EPI_F32)
+    const float *zin;    // [M][ldc] pre-activation to differentiate (EPI_DGELU)
+    int ldc;
 };
 
-bool mlp_ready(const MlpState *m) { return m != nullptr; }
-void mlp_free(MlpState *m) { delete m; }
-mpt_status mlp_init(MlpState **, uint64_t, hipStream_t) { return MPT_E_UNSUPPORTED; }
-mpt_status mlp_predict_dev(MlpState *, const SceneDev &, const BatchDev &, double *, hipStream_t) { return MPT_E_UNSUPPORTED; }
-mpt_status mlp_train_step_dev(MlpState *, const SceneDev &, const BatchDev &, const double *, const uint8_t *, float,
-                              float *, hipStream_t)
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+constexpr int GT = 64, GK = 32, GPAD = 8;
+
+template <bool AT, bool BT, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const bf16 *__restrict__ A, int lda,
+                                               const bf16 *__restrict__ B, int ldb, Epi e, int kps)
 {
-    return MPT_E_UNSUPPORTED;
+    __shared__ __align__(16) bf16 As[GT][GK + GPAD];
+    __shared__ __align__(16) bf16 Bs[GT][GK + GPAD];  // [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+    const int kb = blockIdx.z * kps, ke = min(K, kb + kps);
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    float16_t acc;
+#pragma unroll
+    for (int v = 0; v < 16; v++) acc[v] = 0.0f;
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+        // stage A: 64 x 32 (8 elements per thread)
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            int mm, kk;
+            if (!AT) { mm = tid >> 2; kk = (tid & 3) * 8 + j; }
+            else { kk = tid >> 3; mm = (tid & 7) * 8 + j; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            bf16 v = 0;
+            if (gm < M && gk < ke) v = AT ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+            As[mm][kk] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            int nn, kk;
+            if (BT) { nn = tid >> 2; kk = (tid & 3) * 8 + j; }
+            else { kk = tid >> 3; nn = (tid & 7) * 8 + j; }
+            const int gn = n0 + nn, gk = k0 + kk;
+            bf16 v = 0;
+            if (gn < N && gk < ke) v = BT ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
+            Bs[nn][kk] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GK; ks += 8) {
+            // A(i,k): lane = i + 32 (k / 4), element k % 4; B(k,j): lane = j + 32 (k / 4)
+            const int kk = ks + 4 * (lane >> 5);
+            short4_t a, bb;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                a[q] = (short)As[wm + (lane & 31)][kk + q];
+                bb[q] = (short)Bs[wn + (lane & 31)][kk + q];
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D(i,j): lane = j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8)
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+        const int row = m0 + wm + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int col = n0 + wn + (lane & 31);
+        if (row >= M || col >= N) continue;
+        const float x = acc[v];
+        const size_t o = (size_t)row * e.ldc + col;
+        if (EPI == EPI_BIAS_GELU) {
+            const float z = x + e.bias[col];
+            if (e.zout) e.zout[o] = z;
+            e.hout[o] = f2bf(gelu(z));
+        } else if (EPI == EPI_BIAS) {
+            e.fout[o] = x + e.bias[col];
+        } else if (EPI == EPI_DGELU) {
+            e.hout[o] = f2bf(x * gelu_d(e.zin[o]));
+        } else {
+            e.fout[(size_t)blockIdx.z * M * e.ldc + o] = x;
+        }
+    }
 }
-mpt_status mlp_save(MlpState *, void *, size_t *, hipStream_t) { return MPT_E_UNSUPPORTED; }
-mpt_status mlp_load(MlpState **, const void *, size_t, hipStream_t) { return MPT_E_UNSUPPORTED; }
+
+// out[i] = sum over splits of part[s][i] (fixed order: deterministic)
+__global__ void k_reduce_splits(const float *__restrict__ part, int splits, size_t n, float *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int q = 0; q < splits; q++) s += part[(size_t)q * n + i];
+    out[i] = s;
+}
+
+// column sums of a [M][N] bf16 matrix (bias gradients), one block per column
+__global__ void k_colsum(const bf16 *__restrict__ X, int M, int N, int ld, float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int col = blockIdx.x;
+    float s = 0.0f;
+    for (int r = threadIdx.x; r < M; r += blockDim.x) s += bf2f(X[(size_t)r * ld + col]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[col] = red[0];
+}
+
+// ------------------------------------------------------------------ loss
+// Masked mean squared error between the network's points Y (frame units) and
+// the targets, over the coordinates of the first `order` points of the rows
+// whose use flag is set.  dY = d loss / d Y (bf16, [nrows][16]).
+__global__ void k_loss_partial(SceneDev s, BatchDev b, const int *__restrict__ rows, int nrows,
+                               const float *__restrict__ Y, const double *__restrict__ target,
+                               const uint8_t *__restrict__ use, float *__restrict__ diff, float *__restrict__ part,
+                               int *__restrict__ cnt_part)
+{
+    __shared__ float red[256];
+    __shared__ int redc[256];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    float sum = 0.0f;
+    int cnt = 0;
+    if (r < nrows) {
+        const int i = rows ? rows[r] : r;
+        const int ord = b.order[i];
+        const bool u = (!use || use[i]) && ord >= 1 && ord <= kMaxN;
+        const int ri = b.rx_index[i];
+        double L = 1.0;
+        if (ri >= 0 && ri < b.n_rx) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; c++) {
+                const double d = b.rx[3 * (size_t)ri + c] - s.tx[c];
+                d2 += d * d;
+            }
+            if (d2 > 0.0 && isfinite(d2)) L = sqrt(d2);
+        }
+        for (int j = 0; j < F_OUTP; j++) {
+            float dd = 0.0f;
+            if (u && j < 3 * ord) {
+                const double t = (target[(size_t)j * b.n + i] - s.tx[j % 3]) / L;
+                dd = Y[(size_t)r * F_OUTP + j] - (float)t;
+                if (!isfinite(dd)) dd = 0.0f;
+                sum += dd * dd;
+                cnt++;
+            }
+            diff[(size_t)r * F_OUTP + j] = dd;
+        }
+    }
+    red[threadIdx.x] = sum;
+    redc[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            red[threadIdx.x] += red[threadIdx.x + d];
+            redc[threadIdx.x] += redc[threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = red[0];
+        cnt_part[blockIdx.x] = redc[0];
+    }
+}
+
+// total loss and dY = 2 diff / count (bf16)
+__global__ void k_loss_final(const float *__restrict__ part, const int *__restrict__ cnt_part, int nblk,
+                             const float *__restrict__ diff, int nrows, bf16 *__restrict__ dY, float *__restrict__ loss)
+{
+    __shared__ float tot_s;
+    __shared__ int tot_c;
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        int c = 0;
+        for (int q = 0; q < nblk; q++) t += part[q], c += cnt_part[q];
+        tot_s = t;
+        tot_c = c;
+        if (loss) *loss = c ? t / c : 0.0f;
+    }
+    __syncthreads();
+    const float sc = tot_c ? 2.0f / tot_c : 0.0f;
+    for (int i = threadIdx.x; i < nrows * F_OUTP; i += blockDim.x) dY[i] = f2bf(sc * diff[i]);
+}
+
+// ------------------------------------------------------------------ Adam
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, bf16 *__restrict__ wb, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ w, bf16 *__restrict__ wb, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = f2bf(w[i]);
+}
+
+// ------------------------------------------------------------------ decode
+// World points X_k = TX + L Y_k for the first `order` points (zero beyond).
+__global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restrict__ Y, double *__restrict__ x)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    const int ord = b.order[i];
+    const int ri = b.rx_index[i];
+    double L = 1.0;
+    if (ri >= 0 && ri < b.n_rx) {
+        double d2 = 0.0;
+        for (int c = 0; c < 3; c++) {
+            const double d = b.rx[3 * (size_t)ri + c] - s.tx[c];
+            d2 += d * d;
+        }
+        if (d2 > 0.0 && isfinite(d2)) L = sqrt(d2);
+    }
+    for (int j = 0; j < F_OUT; j++)
+        x[(size_t)j * b.n + i] = (j < 3 * ord) ? s.tx[j % 3] + L * (double)Y[(size_t)i * F_OUTP + j] : 0.0;
+}
+
+// ------------------------------------------------------------------ state
+// Parameter layout (FP32 master, one flat array): W1 [256][96], b1 [256],
+// W2 [256][256], b2, W3 [256][256], b3, W4 [16][256] (row 15 unused, kept
+// zero), b4 [16].  Weights are [out][in].
+constexpr size_t OW1 = 0, OB1 = OW1 + (size_t)HID * F_IN, OW2 = OB1 + HID, OB2 = OW2 + (size_t)HID * HID,
+                 OW3 = OB2 + HID, OB3 = OW3 + (size_t)HID * HID, OW4 = OB3 + HID, OB4 = OW4 + (size_t)F_OUTP * HID,
+                 NPAR = OB4 + F_OUTP;
+
+struct MlpState {
+    float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    bf16 *wb = nullptr;  // bf16 copy of the weights (same layout)
+    int64_t step = 0;
+    uint64_t seed = 0;
+    // activation workspace for up to cap rows
+    size_t cap = 0;
+    bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *H3 = nullptr, *dY = nullptr, *dA = nullptr, *dB = nullptr;
+    float *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *Y = nullptr, *diff = nullptr, *part = nullptr,
+          *lpart = nullptr;
+    int *lcnt = nullptr;
+    size_t part_cap = 0;
+};
+
+bool mlp_ready(const MlpState *m) { return m != nullptr && m->w != nullptr; }
+
+static void free_ws(MlpState *m)
+{
+    for (void *p : {(void *)m->X, (void *)m->H1, (void *)m->H2, (void *)m->H3, (void *)m->dY, (void *)m->dA,
+                    (void *)m->dB, (void *)m->Z1, (void *)m->Z2, (void *)m->Z3, (void *)m->Y, (void *)m->diff,
+                    (void *)m->lpart, (void *)m->lcnt})
+        if (p) hipFree(p);
+    m->X = m->H1 = m->H2 = m->H3 = m->dY = m->dA = m->dB = nullptr;
+    m->Z1 = m->Z2 = m->Z3 = m->Y = m->diff = m->lpart = nullptr;
+    m->lcnt = nullptr;
+    m->cap = 0;
+}
+
+void mlp_free(MlpState *m)
+{
+    if (!m) return;
+    free_ws(m);
+    hipFree(m->w);
+    hipFree(m->m);
+    hipFree(m->v);
+    hipFree(m->g);
+    hipFree(m->wb);
+    hipFree(m->part);
+    delete m;
+}
+
+static mpt_status ensure_ws(MlpState *m, size_t rows, bool train)
+{
+    if (rows <= m->cap && (!train || m->dY)) return MPT_OK;
+    free_ws(m);
+    size_t cap = rows < 1024 ? 1024 : rows;
+    bool ok = true;
+    auto A = [&](void **p, size_t bytes) { ok = ok && hipMalloc(p, bytes) == hipSuccess; };
+    A((void **)&m->X, cap * F_IN * sizeof(bf16));
+    A((void **)&m->H1, cap * HID * sizeof(bf16));
+    A((void **)&m->H2, cap * HID * sizeof(bf16));
+    A((void **)&m->H3, cap * HID * sizeof(bf16));
+    A((void **)&m->Y, cap * F_OUTP * sizeof(float));
+    if (train) {
+        A((void **)&m->Z1, cap * HID * sizeof(float));
+        A((void **)&m->Z2, cap * HID * sizeof(float));
+        A((void **)&m->Z3, cap * HID * sizeof(float));
+        A((void **)&m->dY, cap * F_OUTP * sizeof(bf16));
+        A((void **)&m->dA, cap * HID * sizeof(bf16));
+        A((void **)&m->dB, cap * HID * sizeof(bf16));
+        A((void **)&m->diff, cap * F_OUTP * sizeof(float));
+        A((void **)&m->lpart, ((cap + 255) / 256) * sizeof(float));
+        A((void **)&m->lcnt, ((cap + 255) / 256) * sizeof(int));
+    }
+    if (!ok) {
+        free_ws(m);
+        return MPT_E_NOMEM;
+    }
+    m->cap = cap;
+    return MPT_OK;
+}
+
+// host-side seeded initialisation (SplitMix64 -> uniform), Kaiming-uniform
+// style bounds sqrt(6 / fan_in) for weights, zero biases
+static uint64_t splitmix(uint64_t &x)
+{
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static void init_host(std::vector<float> &w, uint64_t seed)
+{
+    w.assign(NPAR, 0.0f);
+    uint64_t st = seed;
+    auto uni = [&]() { return (float)((splitmix(st) >> 11) * (1.0 / 9007199254740992.0)) * 2.0f - 1.0f; };
+    auto fill = [&](size_t off, int rows, int cols, int valid_rows) {
+        const float bound = sqrtf(6.0f / (float)cols);
+        for (int r = 0; r < rows; r++)
+            for (int c = 0; c < cols; c++) w[off + (size_t)r * cols + c] = (r < valid_rows) ? bound * uni() : 0.0f;
+    };
+    fill(OW1, HID, F_IN, HID);
+    fill(OW2, HID, HID, HID);
+    fill(OW3, HID, HID, HID);
+    fill(OW4, F_OUTP, HID, F_OUT);
+    // the last layer starts small so that the first predictions sit near the
+    // origin of the frame
+    for (size_t i = OW4; i < OB4; i++) w[i] *= 0.1f;
+}
+
+static mpt_status alloc_params(MlpState *m)
+{
+    bool ok = hipMalloc((void **)&m->w, NPAR * 4) == hipSuccess && hipMalloc((void **)&m->m, NPAR * 4) == hipSuccess &&
+              hipMalloc((void **)&m->v, NPAR * 4) == hipSuccess && hipMalloc((void **)&m->g, NPAR * 4) == hipSuccess &&
+              hipMalloc((void **)&m->wb, NPAR * 2) == hipSuccess;
+    return ok ? MPT_OK : MPT_E_NOMEM;
+}
+
+mpt_status mlp_init(MlpState **pm, uint64_t seed, hipStream_t st)
+{
+    if (!*pm) *pm = new MlpState();
+    MlpState *m = *pm;
+    if (!m->w && alloc_params(m)) return MPT_E_NOMEM;
+    std::vector<float> h;
+    init_host(h, seed);
+    std::vector<float> z(NPAR, 0.0f);
+    if (hipMemcpyAsync(m->w, h.data(), NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess) return MPT_E_DEVICE;
+    if (hipMemcpyAsync(m->m, z.data(), NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess) return MPT_E_DEVICE;
+    if (hipMemcpyAsync(m->v, z.data(), NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess) return MPT_E_DEVICE;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->wb, (int)NPAR);
+    if (hipStreamSynchronize(st) != hipSuccess) return MPT_E_DEVICE;
+    m->step = 0;
+    m->seed = seed;
+    return MPT_OK;
+}
+
+// ------------------------------------------------------------------ launch helpers
+template <bool AT, bool BT, int EPI>
+static void gemm(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb, const Epi &e, int splits,
+                 hipStream_t st)
+{
+    int kps = (K + splits - 1) / splits;
+    kps = ((kps + GK - 1) / GK) * GK;
+    splits = (K + kps - 1) / kps;
+    dim3 grid((M + GT - 1) / GT, (N + GT - 1) / GT, splits);
+    hipLaunchKernelGGL((k_gemm<AT, BT, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, e, kps);
+}
+
+// forward over `nrows` rows already featurised in m->X; with train, keep Z
+static void forward(MlpState *m, int nrows, bool train, hipStream_t st)
+{
+    Epi e{};
+    e.ldc = HID;
+    e.bias = m->w + OB1;
+    e.zout = train ? m->Z1 : nullptr;
+    e.hout = m->H1;
+    gemm<false, true, EPI_BIAS_GELU>(nrows, HID, F_IN, m->X, F_IN, m->wb + OW1, F_IN, e, 1, st);
+    e.bias = m->w + OB2;
+    e.zout = train ? m->Z2 : nullptr;
+    e.hout = m->H2;
+    gemm<false, true, EPI_BIAS_GELU>(nrows, HID, HID, m->H1, HID, m->wb + OW2, HID, e, 1, st);
+    e.bias = m->w + OB3;
+    e.zout = train ? m->Z3 : nullptr;
+    e.hout = m->H3;
+    gemm<false, true, EPI_BIAS_GELU>(nrows, HID, HID, m->H2, HID, m->wb + OW3, HID, e, 1, st);
+    Epi e4{};
+    e4.ldc = F_OUTP;
+    e4.bias = m->w + OB4;
+    e4.fout = m->Y;
+    gemm<false, true, EPI_BIAS>(nrows, F_OUTP, HID, m->H3, HID, m->wb + OW4, HID, e4, 1, st);
+}
+
+mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, double *x_out, hipStream_t st)
+{
+    if (!mlp_ready(m)) return MPT_E_NO_MODEL;
+    if (b.n == 0) return MPT_OK;
+    // chunks of at most 1M rows bound the activation workspace
+    const int64_t chunk = 1 << 20;
+    if (ensure_ws(m, (size_t)(b.n < chunk ? b.n : chunk), false)) return MPT_E_NOMEM;
+    for (int64_t c0 = 0; c0 < b.n; c0 += chunk) {
+        const int nr = (int)((b.n - c0) < chunk ? (b.n - c0) : chunk);
+        // a view of the batch starting at c0 (component-major arrays keep stride n)
+        BatchDev v = b;
+        v.rx_index = b.rx_index + c0;
+        v.order = b.order + c0;
+        v.prim = b.prim + c0;
+        // k_features / k_decode index prim as prim[k * n + i]: keep n, shift i
+        hipLaunchKernelGGL(k_features, dim3((nr + 127) / 128), dim3(128), 0, st, s, v, nullptr, nr, nullptr, m->X);
+        forward(m, nr, false, st);
+        hipLaunchKernelGGL(k_decode, dim3((nr + 255) / 256), dim3(256), 0, st, s, v, nr, m->Y, x_out + c0);
+        // k_decode writes x[j * v.n + i]: with v.n = b.n and x_out + c0 the
+        // component-major layout of the whole batch is kept
+    }
+    return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
+}
+
+// loss, gradient into m->g (no update); rows = minibatch ids (may be null)
+static mpt_status grad_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,
+                           const double *target, const uint8_t *use, float *d_loss, hipStream_t st)
+{
+    if (ensure_ws(m, (size_t)nrows, true)) return MPT_E_NOMEM;
+    hipLaunchKernelGGL(k_features, dim3((nrows + 127) / 128), dim3(128), 0, st, s, b, rows, nrows, nullptr, m->X);
+    forward(m, nrows, true, st);
+    const int nblk = (nrows + 255) / 256;
+    hipLaunchKernelGGL(k_loss_partial, dim3(nblk), dim3(256), 0, st, s, b, rows, nrows, m->Y, target, use, m->diff,
+                       m->lpart, m->lcnt);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, m->lpart, m->lcnt, nblk, m->diff, nrows, m->dY,
+                       d_loss);
+    // split-K partial buffer for the weight gradients
+    const int splits = nrows >= 4096 ? 16 : (nrows >= 1024 ? 4 : 1);
+    const size_t need = (size_t)splits * HID * HID;
+    if (m->part_cap < need) {
+        if (m->part) hipFree(m->part);
+        m->part = nullptr;
+        if (hipMalloc((void **)&m->part, need * 4) != hipSuccess) return MPT_E_NOMEM;
+        m->part_cap = need;
+    }
+    auto wgrad = [&](int Mo, int Ni, const bf16 *dZ, int ldz, const bf16 *Xin, int ldx, float *gout) {
+        // dW[o][i] = sum_r dZ[r][o] X[r][i]: A = dZ^T (AT), B = X (row-major)
+        Epi e{};
+        e.ldc = Ni;
+        e.fout = m->part;
+        int kps = (nrows + splits - 1) / splits;
+        kps = ((kps + GK - 1) / GK) * GK;
+        const int sp = (nrows + kps - 1) / kps;
+        gemm<true, false, EPI_F32>(Mo, Ni, nrows, dZ, ldz, Xin, ldx, e, splits, st);
+        const size_t n = (size_t)Mo * Ni;
+        hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m->part, sp, n, gout);
+    };
+    // layer 4: dW4, db4, dH3 = dY W4
+    wgrad(F_OUTP, HID, m->dY, F_OUTP, m->H3, HID, m->g + OW4);
+    hipLaunchKernelGGL(k_colsum, dim3(F_OUTP), dim3(256), 0, st, m->dY, nrows, F_OUTP, F_OUTP, m->g + OB4);
+    Epi e{};
+    e.ldc = HID;
+    e.zin = m->Z3;
+    e.hout = m->dA;  // dZ3
+    gemm<false, false, EPI_DGELU>(nrows, HID, F_OUTP, m->dY, F_OUTP, m->wb + OW4, HID, e, 1, st);
+    // layer 3
+    wgrad(HID, HID, m->dA, HID, m->H2, HID, m->g + OW3);
+    hipLaunchKernelGGL(k_colsum, dim3(HID), dim3(256), 0, st, m->dA, nrows, HID, HID, m->g + OB3);
+    e.zin = m->Z2;
+    e.hout = m->dB;  // dZ2
+    gemm<false, false, EPI_DGELU>(nrows, HID, HID, m->dA, HID, m->wb + OW3, HID, e, 1, st);
+    // layer 2
+    wgrad(HID, HID, m->dB, HID, m->H1, HID, m->g + OW2);
+    hipLaunchKernelGGL(k_colsum, dim3(HID), dim3(256), 0, st, m->dB, nrows, HID, HID, m->g + OB2);
+    e.zin = m->Z1;
+    e.hout = m->dA;  // dZ1
+    gemm<false, false, EPI_DGELU>(nrows, HID, HID, m->dB, HID, m->wb + OW2, HID, e, 1, st);
+    // layer 1
+    wgrad(HID, F_IN, m->dA, HID, m->X, F_IN, m->g + OW1);
+    hipLaunchKernelGGL(k_colsum, dim3(HID), dim3(256), 0, st, m->dA, nrows, HID, HID, m->g + OB1);
+    return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
+}
+
+mpt_status mlp_grad_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,
+                        const double *target, const uint8_t *use, float *d_loss, float *d_grad, hipStream_t st)
+{
+    if (!mlp_ready(m)) return MPT_E_NO_MODEL;
+    if (nrows <= 0) return MPT_E_INVALID_ARG;
+    mpt_status r = grad_dev(m, s, b, rows, nrows, target, use, d_loss, st);
+    if (r) return r;
+    if (d_grad && hipMemcpyAsync(d_grad, m->g, NPAR * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return MPT_E_DEVICE;
+    return MPT_OK;
+}
+
+mpt_status mlp_train_step_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,
+                              const double *target, const uint8_t *use, float lr, float *d_loss, hipStream_t st)
+{
+    if (!mlp_ready(m)) return MPT_E_NO_MODEL;
+    if (nrows <= 0) return MPT_E_INVALID_ARG;
+    mpt_status r = grad_dev(m, s, b, rows, nrows, target, use, d_loss, st);
+    if (r) return r;
+    m->step++;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)m->step), c2 = 1.0f - powf(b2, (float)m->step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->m, m->v, m->g, m->wb,
+                       (int)NPAR, lr, b1, b2, 1e-8f, c1, c2);
+    return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
+}
+
+mpt_status mlp_features_dev(const SceneDev &s, const BatchDev &b, float *fout, hipStream_t st)
+{
+    if (b.n == 0) return MPT_OK;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((b.n + 127) / 128)), dim3(128), 0, st, s, b, nullptr, (int)b.n,
+                       fout, nullptr);
+    return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
+}
+
+// ------------------------------------------------------------------ GEMM self-test entry
+// C[M][N] (fp32) = A[M][K] B[K][N] with bf16 inputs given as fp32 (rounded
+// here); layouts as the flags say.  Used by the tests of the MFMA tile code.
+__global__ void k_f2bf_arr(const float *x, bf16 *y, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+mpt_status gemm_test_dev(int M, int N, int K, const float *A, int at, const float *B, int bt, float *C, int splits,
+                         hipStream_t st)
+{
+    bf16 *Ab = nullptr, *Bb = nullptr;
+    float *part = nullptr;
+    const size_t na = (size_t)M * K, nb = (size_t)K * N;
+    if (hipMalloc((void **)&Ab, na * 2) != hipSuccess || hipMalloc((void **)&Bb, nb * 2) != hipSuccess ||
+        hipMalloc((void **)&part, (size_t)(splits < 1 ? 1 : splits) * M * N * 4) != hipSuccess) {
+        hipFree(Ab), hipFree(Bb), hipFree(part);
+        return MPT_E_NOMEM;
+    }
+    hipLaunchKernelGGL(k_f2bf_arr, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, A, Ab, na);
+    hipLaunchKernelGGL(k_f2bf_arr, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, B, Bb, nb);
+    Epi e{};
+    e.ldc = N;
+    e.fout = part;
+    const int lda = at ? M : K, ldb = bt ? K : N;
+    int kps = (K + splits - 1) / splits;
+    kps = ((kps + GK - 1) / GK) * GK;
+    const int sp = (K + kps - 1) / kps;
+    if (!at && !bt) gemm<false, false, EPI_F32>(M, N, K, Ab, lda, Bb, ldb, e, splits, st);
+    else if (!at && bt) gemm<false, true, EPI_F32>(M, N, K, Ab, lda, Bb, ldb, e, splits, st);
+    else if (at && !bt) gemm<true, false, EPI_F32>(M, N, K, Ab, lda, Bb, ldb, e, splits, st);
+    else gemm<true, true, EPI_F32>(M, N, K, Ab, lda, Bb, ldb, e, splits, st);
+    const size_t n = (size_t)M * N;
+    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, sp, n, C);
+    hipError_t err = hipStreamSynchronize(st);
+    hipFree(Ab), hipFree(Bb), hipFree(part);
+    return err == hipSuccess ? MPT_OK : MPT_E_DEVICE;
+}
+
+// ------------------------------------------------------------------ save / load
+// Blob: "MPTMLP01", uint32 header length, JSON header, then FP32 arrays
+// (weights, Adam first and second moments), each NPAR long.
+mpt_status mlp_save(MlpState *m, void *blob, size_t *bytes, hipStream_t st)
+{
+    if (!mlp_ready(m)) return MPT_E_NO_MODEL;
+    char hdr[512];
+    const int hl = snprintf(hdr, sizeof hdr,
+                            "{\"format\": \"mpt-mlp\", \"version\": 1, \"layers\": [%d, %d, %d, %d, %d], "
+                            "\"out_padded\": %d, \"params\": %zu, \"dtype\": \"f32\", \"activation\": \"gelu-erf\", "
+                            "\"step\": %lld, \"seed\": %llu, \"arrays\": [\"w\", \"adam_m\", \"adam_v\"]}",
+                            F_IN, HID, HID, HID, F_OUT, F_OUTP, (size_t)NPAR, (long long)m->step,
+                            (unsigned long long)m->seed);
+    const size_t need = 8 + 4 + (size_t)hl + 3 * NPAR * 4;
+    if (!blob) {
+        *bytes = need;
+        return MPT_OK;
+    }
+    if (*bytes < need) {
+        *bytes = need;
+        return MPT_E_INVALID_ARG;
+    }
+    unsigned char *p = (unsigned char *)blob;
+    memcpy(p, "MPTMLP01", 8);
+    const uint32_t h32 = (uint32_t)hl;
+    memcpy(p + 8, &h32, 4);
+    memcpy(p + 12, hdr, hl);
+    unsigned char *d = p + 12 + hl;
+    if (hipMemcpyAsync(d, m->w, NPAR * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(d + NPAR * 4, m->m, NPAR * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(d + 2 * NPAR * 4, m->v, NPAR * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MPT_E_DEVICE;
+    *bytes = need;
+    return MPT_OK;
+}
+
+mpt_status mlp_load(MlpState **pm, const void *blob, size_t bytes, hipStream_t st)
+{
+    const unsigned char *p = (const unsigned char *)blob;
+    if (bytes < 12 || memcmp(p, "MPTMLP01", 8) != 0) return MPT_E_INVALID_ARG;
+    uint32_t hl;
+    memcpy(&hl, p + 8, 4);
+    if (bytes != 12 + (size_t)hl + 3 * NPAR * 4) return MPT_E_INVALID_ARG;
+    std::string hdr((const char *)p + 12, hl);
+    long long step = 0;
+    unsigned long long seed = 0;
+    const size_t ps = hdr.find("\"step\": "), pd = hdr.find("\"seed\": ");
+    if (ps != std::string::npos) step = atoll(hdr.c_str() + ps + 8);
+    if (pd != std::string::npos) seed = strtoull(hdr.c_str() + pd + 8, nullptr, 10);
+    if (!*pm) *pm = new MlpState();
+    MlpState *m = *pm;
+    if (!m->w && alloc_params(m)) return MPT_E_NOMEM;
+    const unsigned char *d = p + 12 + hl;
+    if (hipMemcpyAsync(m->w, d, NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(m->m, d + NPAR * 4, NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(m->v, d + 2 * NPAR * 4, NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MPT_E_DEVICE;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->wb, (int)NPAR);
+    if (hipStreamSynchronize(st) != hipSuccess) return MPT_E_DEVICE;
+    m->step = step;
+    m->seed = seed;
+    return MPT_OK;
+}
+
+size_t mlp_param_count() { return NPAR; }
 
 }  // namespace mpt

@@ -87,24 +87,42 @@ __device__ inline int valid_order(const BatchDev &b, int64_t i, int n_all)
     return bad ? -1 : ord;
 }
 
-__global__ void k_bin_count(BatchDev b, OutDev out, int n_all, int *__restrict__ cnt)
+// Binning: each block owns a contiguous range of solves, counts its orders in
+// LDS and touches the global counters once per order.
+constexpr int kBinBlock = 256;
+constexpr int kBinItems = 8;  // solves per thread
+
+__global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out, int n_all, int *__restrict__ cnt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int ord = -1;
-    if (i < b.n) {
-        ord = valid_order(b, i, n_all);
+    __shared__ int loc[kMaxN];
+    if (threadIdx.x < kMaxN) loc[threadIdx.x] = 0;
+    __syncthreads();
+    int mine[kMaxN] = {0, 0, 0, 0, 0};
+    const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
+    for (int j = 0; j < kBinItems; j++) {
+        const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
+        if (i >= b.n) break;
+        const int ord = valid_order(b, i, n_all);
         if (ord < 0) {
-            for (int j = 0; j < 3 * kMaxN; j++) out.x[(size_t)j * b.n + i] = 0.0;
+            for (int q = 0; q < 3 * kMaxN; q++) out.x[(size_t)q * b.n + i] = 0.0;
             out.cost[i] = __builtin_huge_val();
             out.iters[i] = 0;
             out.status[i] = ST_BAD;
+            if (out.stage)
+                for (int q = 0; q < 3; q++) out.stage[(size_t)q * b.n + i] = 0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kMaxN; k++) mine[k] += (ord == k + 1);
         }
     }
-    // wave-aggregated histogram
-    for (int k = 1; k <= kMaxN; k++) {
-        const uint64_t m = __ballot(ord == k);
-        if (m && __lane_id() == (int)__builtin_ctzll(m)) atomicAdd(&cnt[k - 1], (int)__popcll(m));
+#pragma unroll
+    for (int k = 0; k < kMaxN; k++) {
+        int v = mine[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (__lane_id() == 0 && v) atomicAdd(&loc[k], v);
     }
+    __syncthreads();
+    if (threadIdx.x < kMaxN && loc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], loc[threadIdx.x]);
 }
 
 __device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
@@ -114,22 +132,52 @@ __device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
     return off;
 }
 
-__global__ void k_bin_scatter(BatchDev b, int n_all, const int *__restrict__ cnt, int *__restrict__ cursor,
-                              int *__restrict__ perm)
+__global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all, const int *__restrict__ cnt,
+                                                            int *__restrict__ cursor, int *__restrict__ perm)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ord = (i < b.n) ? valid_order(b, i, n_all) : -1;
-    for (int k = 1; k <= kMaxN; k++) {
-        const bool mine = (ord == k);
-        const uint64_t m = __ballot(mine);
-        if (!m) continue;
-        const int leader = (int)__builtin_ctzll(m);
-        int base = 0;
-        if (__lane_id() == leader) base = atomicAdd(&cursor[k - 1], (int)__popcll(m));
-        base = __shfl(base, leader);
-        if (mine) {
-            const int rank = (int)__popcll(m & ((1ull << __lane_id()) - 1ull));
-            perm[bin_offset(cnt, k) + base + rank] = (int)i;
+    // pass 1: per-wave counts of each order over the block's range
+    __shared__ int wc[kBinBlock / 64][kMaxN];
+    __shared__ int bbase[kMaxN];
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
+    int ordv[kBinItems];
+    int mine[kMaxN] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+        const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
+        ordv[j] = (i < b.n) ? valid_order(b, i, n_all) : -1;
+#pragma unroll
+        for (int k = 0; k < kMaxN; k++) mine[k] += (ordv[j] == k + 1);
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxN; k++) {
+        int v = mine[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wc[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxN) {
+        int t = 0;
+        for (int q = 0; q < kBinBlock / 64; q++) t += wc[q][threadIdx.x];
+        bbase[threadIdx.x] = t ? atomicAdd(&cursor[threadIdx.x], t) : 0;
+    }
+    __syncthreads();
+    // pass 2: slots = bin offset + block base + earlier waves + earlier lanes
+    int run[kMaxN];
+#pragma unroll
+    for (int k = 0; k < kMaxN; k++) {
+        int pre = 0;
+        for (int q = 0; q < w; q++) pre += wc[q][k];
+        run[k] = bin_offset(cnt, k + 1) + bbase[k] + pre;
+    }
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+        const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < kMaxN; k++) {
+            const uint64_t m = __ballot(ordv[j] == k + 1);
+            if (ordv[j] == k + 1) perm[run[k] + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int)i;
+            run[k] += (int)__popcll(m);
         }
     }
 }
@@ -268,7 +316,7 @@ template <> struct ModeT<MODE_FP32> { using T = float; };
 template <> struct ModeT<MODE_FALLBACK64> { using T = double; };
 
 template <int MODE, int N>
-__device__ void lm_bin(const KParams &kp)
+__device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restrict__ srec)
 {
     using T = typename ModeT<MODE>::T;
     const int lane = __lane_id();
@@ -280,8 +328,8 @@ __device__ void lm_bin(const KParams &kp)
     const int off = bin_offset(kp.bin_cnt, N);
 
     SceneT<T> sc;
+    sc.rec = srec;
     if (MODE == MODE_FP32) {
-        sc.rec = (const T *)kp.s.rec32;
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             sc.tx[i] = T(0);
@@ -289,7 +337,6 @@ __device__ void lm_bin(const KParams &kp)
             sc.ghi[i] = (T)(kp.s.ghi[i] - kp.s.tx[i]);
         }
     } else {
-        sc.rec = (const T *)kp.s.rec64;
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             sc.tx[i] = (T)kp.s.tx[i];
@@ -302,7 +349,7 @@ __device__ void lm_bin(const KParams &kp)
         o.max_iter = kp.o.max_iter32;
         o.tol_step = (T)kp.o.tol_step32;
         o.tol_res = (T)kp.o.tol_res32;
-        o.tau_root = (T)kp.o.polish_gate;  // FP32 "root" = worth polishing
+        o.tau_root = (T)kp.o.tau_root32;  // an FP32 point this close is taken for a root
     } else {
         o.max_iter = kp.o.max_iter;
         o.tol_step = (T)kp.o.tol_step;
@@ -400,6 +447,12 @@ __device__ void lm_bin(const KParams &kp)
                             kp.out.x[(size_t)j * kp.b.n + sid] = (j < 3 * N && st0 != ST_BAD) ? X0[j < 3 * N ? j : 0] : 0.0;
                         kp.out.cost[sid] = __builtin_huge_val();
                         if (MODE != MODE_FALLBACK64) kp.out.iters[sid] = 0;
+                        if (kp.out.stage) {
+                            if (MODE != MODE_FALLBACK64) {
+#pragma unroll
+                                for (int j = 0; j < 3; j++) kp.out.stage[(size_t)j * kp.b.n + sid] = 0;
+                            }
+                        }
                         kp.out.status[sid] = (uint8_t)(st0 | (MODE == MODE_FALLBACK64 ? 0x80 : 0));
                         active = false;
                     }
@@ -425,17 +478,34 @@ __device__ void lm_bin(const KParams &kp)
                 int it = L.it;
                 if (MODE == MODE_FALLBACK64) it += kp.out.iters[sid];
                 kp.out.iters[sid] = it;
+                if (kp.out.stage) {
+                    if (MODE == MODE_FALLBACK64) {
+                        kp.out.stage[(size_t)2 * kp.b.n + sid] = L.it;
+                    } else {
+                        kp.out.stage[sid] = L.it;
+                        kp.out.stage[(size_t)kp.b.n + sid] = 0;
+                        kp.out.stage[(size_t)2 * kp.b.n + sid] = 0;
+                    }
+                }
                 int code = st;
                 if (MODE == MODE_FP32) {
-                    // route: polish points that look like roots, fall back on
-                    // numerical trouble, keep clear non-roots as they are
-                    const bool to_polish = (st == ST_CONV) ||
-                                           ((st == ST_MAXIT || st == ST_LOCALMIN) && (double)L.rinf <= kp.o.polish_gate);
-                    const bool to_fb = (st == ST_STALL || st == ST_DEGEN || st == ST_DIVERGED);
+                    // route: FP32 end points whose residual is below the gate
+                    // look like roots and are polished in FP64; the others
+                    // are final (no path).  FP64 re-solves the path from the
+                    // straight-line start only on numerical trouble in FP32:
+                    // a degenerate iterate, or - decided by the polish - a
+                    // converged or stalled FP32 point that does not polish
+                    const bool small_res = (double)L.rinf <= kp.o.polish_gate;
+                    const bool to_polish = small_res && (st == ST_CONV || st == ST_MAXIT || st == ST_LOCALMIN ||
+                                                         st == ST_STALL);
+                    const bool to_fb = (st == ST_DEGEN);
                     if (to_polish) {
                         const int q = atomicAdd(&kp.pol_cnt[N - 1], 1);
                         kp.pol_list[off + q] = sid;
-                        code = ST_RUNNING;
+                        const bool rootlike = (double)L.rinf <= kp.o.tau_root32;
+                        code = (rootlike && (st == ST_CONV || st == ST_STALL)) ? ROUTE_POLISH_FB
+                               : (st == ST_MAXIT)                             ? ROUTE_POLISH_MAXIT
+                                                                              : ROUTE_POLISH_LOCALMIN;
                     } else if (to_fb && kp.o.fallback) {
                         const int q = atomicAdd(&kp.fb_cnt[N - 1], 1);
                         kp.fb_list[off + q] = sid;
@@ -454,39 +524,50 @@ __device__ void lm_bin(const KParams &kp)
 // band (93 entries at N = 5) and its factor in registers, so the occupancy
 // target falls with the order and doubles from FP64 to FP32.
 template <int MODE, int N> struct Occ { static constexpr int W = 1; };
-template <> struct Occ<MODE_FP32, 1> { static constexpr int W = 8; };
-template <> struct Occ<MODE_FP32, 2> { static constexpr int W = 4; };
-template <> struct Occ<MODE_FP32, 3> { static constexpr int W = 3; };
-template <> struct Occ<MODE_FP32, 4> { static constexpr int W = 2; };
-template <> struct Occ<MODE_FP32, 5> { static constexpr int W = 2; };
-template <> struct Occ<MODE_PLAIN64, 1> { static constexpr int W = 4; };
-template <> struct Occ<MODE_PLAIN64, 2> { static constexpr int W = 3; };
-template <> struct Occ<MODE_PLAIN64, 3> { static constexpr int W = 2; };
-template <> struct Occ<MODE_PLAIN64, 4> { static constexpr int W = 1; };
-template <> struct Occ<MODE_FALLBACK64, 1> { static constexpr int W = 4; };
-template <> struct Occ<MODE_FALLBACK64, 2> { static constexpr int W = 3; };
-template <> struct Occ<MODE_FALLBACK64, 3> { static constexpr int W = 2; };
-template <> struct Occ<MODE_FALLBACK64, 4> { static constexpr int W = 1; };
+template <> struct Occ<MODE_FP32, 1> { static constexpr int W = 4; };
+template <> struct Occ<MODE_FP32, 2> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FP32, 3> { static constexpr int W = 2; };
+template <> struct Occ<MODE_PLAIN64, 1> { static constexpr int W = 3; };
+template <> struct Occ<MODE_PLAIN64, 2> { static constexpr int W = 2; };
+template <> struct Occ<MODE_FALLBACK64, 1> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FALLBACK64, 2> { static constexpr int W = 2; };
+
+// Scene records staged in LDS by every block of a persistent launch (the
+// whole scene: 651 primitives x 18 floats = 47 KB for the street canyon).
+template <int MODE, bool LDS>
+__device__ __forceinline__ const typename ModeT<MODE>::T *stage_scene(const KParams &kp)
+{
+    using T = typename ModeT<MODE>::T;
+    const T *g = (MODE == MODE_FP32) ? (const T *)kp.s.rec32 : (const T *)kp.s.rec64;
+    if (!LDS) return g;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *l = reinterpret_cast<T *>(smem_raw);
+    const int total = kp.s.n_all * kRec;
+    for (int i = threadIdx.x; i < total; i += blockDim.x) l[i] = g[i];
+    __syncthreads();
+    return l;
+}
 
 // One persistent launch over every order (register budget of order 5).
-template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<MODE, 5>::W, Occ<MODE, 5>::W)))
-k_lm(KParams kp)
+template <int MODE, bool LDS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_lm(KParams kp)
 {
+    const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     // long paths first so that the short ones fill the tail
-    lm_bin<MODE, 5>(kp);
-    lm_bin<MODE, 4>(kp);
-    lm_bin<MODE, 3>(kp);
-    lm_bin<MODE, 2>(kp);
-    lm_bin<MODE, 1>(kp);
+    lm_bin<MODE, 5>(kp, rec);
+    lm_bin<MODE, 4>(kp, rec);
+    lm_bin<MODE, 3>(kp, rec);
+    lm_bin<MODE, 2>(kp, rec);
+    lm_bin<MODE, 1>(kp, rec);
 }
 
 // One persistent launch per order, each with its own register budget.
-template <int MODE, int N>
+template <int MODE, int N, bool LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<MODE, N>::W, Occ<MODE, N>::W)))
 k_lm_one(KParams kp)
 {
-    lm_bin<MODE, N>(kp);
+    const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
+    lm_bin<MODE, N>(kp, rec);
 }
 
 // ------------------------------------------------------------------ polish
@@ -547,16 +628,21 @@ __device__ void polish_bin(const KParams &kp)
         if (ok) ok = eval_cost<double, N>(sc, p, X, nullptr, C, rinf) && in_guard(kp.s, X, N);
         const bool root = ok && rinf <= kp.o.tau_root;
         kp.out.iters[sid] += steps;
+        if (kp.out.stage) kp.out.stage[(size_t)kp.b.n + sid] = steps;
         if (root) {
 #pragma unroll
             for (int j = 0; j < M; j++) kp.out.x[(size_t)j * kp.b.n + sid] = X[j];
             kp.out.cost[sid] = C;
             kp.out.status[sid] = ST_CONV;
-        } else if (kp.o.fallback) {
-            const int qq = atomicAdd(&kp.fb_cnt[N - 1], 1);
-            kp.fb_list[off + qq] = sid;
         } else {
-            kp.out.status[sid] = ST_LOCALMIN;
+            const int route = kp.out.status[sid];
+            if (route == ROUTE_POLISH_FB && kp.o.fallback) {
+                const int qq = atomicAdd(&kp.fb_cnt[N - 1], 1);
+                kp.fb_list[off + qq] = sid;
+                kp.out.status[sid] = ST_RUNNING;
+            } else {
+                kp.out.status[sid] = (route == ROUTE_POLISH_MAXIT) ? ST_MAXIT : ST_LOCALMIN;
+            }
         }
     }
 }
@@ -721,38 +807,40 @@ void launch_zero(int *p, int n, hipStream_t st)
 void launch_bin(const BatchDev &b, const OutDev &out, int n_all, int *cnt, int *cursor, int *perm, hipStream_t st)
 {
     if (b.n == 0) return;
-    const unsigned g = (unsigned)((b.n + 255) / 256);
-    hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(256), 0, st, b, out, n_all, cnt);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(256), 0, st, b, n_all, cnt, cursor, perm);
+    const unsigned g = (unsigned)((b.n + kBinBlock * kBinItems - 1) / (kBinBlock * kBinItems));
+    hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kBinBlock), 0, st, b, out, n_all, cnt);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), 0, st, b, n_all, cnt, cursor, perm);
 }
 
-template <int MODE>
+template <int MODE, bool LDS>
 static const void *lm_kernel_t(int order)
 {
     switch (order) {
-    case 0: return (const void *)k_lm<MODE>;
-    case 1: return (const void *)k_lm_one<MODE, 1>;
-    case 2: return (const void *)k_lm_one<MODE, 2>;
-    case 3: return (const void *)k_lm_one<MODE, 3>;
-    case 4: return (const void *)k_lm_one<MODE, 4>;
-    default: return (const void *)k_lm_one<MODE, 5>;
+    case 0: return (const void *)k_lm<MODE, LDS>;
+    case 1: return (const void *)k_lm_one<MODE, 1, LDS>;
+    case 2: return (const void *)k_lm_one<MODE, 2, LDS>;
+    case 3: return (const void *)k_lm_one<MODE, 3, LDS>;
+    case 4: return (const void *)k_lm_one<MODE, 4, LDS>;
+    default: return (const void *)k_lm_one<MODE, 5, LDS>;
     }
 }
 
 // order 0: the mixed-order kernel; 1..5: the per-order kernels
-const void *lm_kernel(int mode, int order)
+const void *lm_kernel(int mode, int order, bool lds)
 {
     switch (mode) {
-    case MODE_PLAIN64: return lm_kernel_t<MODE_PLAIN64>(order);
-    case MODE_FP32: return lm_kernel_t<MODE_FP32>(order);
-    default: return lm_kernel_t<MODE_FALLBACK64>(order);
+    case MODE_PLAIN64: return lds ? lm_kernel_t<MODE_PLAIN64, true>(order) : lm_kernel_t<MODE_PLAIN64, false>(order);
+    case MODE_FP32: return lds ? lm_kernel_t<MODE_FP32, true>(order) : lm_kernel_t<MODE_FP32, false>(order);
+    default:
+        return lds ? lm_kernel_t<MODE_FALLBACK64, true>(order) : lm_kernel_t<MODE_FALLBACK64, false>(order);
     }
 }
 
-void launch_lm(int mode, int order, const KParams &kp, int grid, int block, hipStream_t st)
+void launch_lm(int mode, int order, bool lds, size_t lds_bytes, const KParams &kp, int grid, int block,
+               hipStream_t st)
 {
     void *args[] = {(void *)&kp};
-    hipLaunchKernel(lm_kernel(mode, order), dim3(grid), dim3(block), args, 0, st);
+    hipLaunchKernel(lm_kernel(mode, order, lds), dim3(grid), dim3(block), args, lds ? lds_bytes : 0, st);
 }
 
 const void *polish_kernel() { return (const void *)k_polish; }

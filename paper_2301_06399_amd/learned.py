@@ -1,0 +1,64 @@
+"""Training of the learned warm start (network kernels in libmpt.so).
+
+The network is trained on the GPU by the library's own forward, backward and
+Adam kernels on solver outputs: problems drawn from the workload's generator
+on the "train" seed stream (the same scene, other receivers and lists) are
+solved by the plain FP64 solver, and the converged points are the targets.
+Only index shuffling of minibatches is done with torch.
+"""
+from __future__ import annotations
+
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import mpt
+from . import workloads as W
+
+
+def train(ctx, scene, train_batch, steps=3000, batch_rows=4096, lr=1e-3, seed=1, log=None):
+    """Solve `train_batch` with the plain FP64 solver, then train for `steps`
+    Adam steps with cosine-decayed learning rate.  Returns the loss history."""
+    import torch
+    ctx.upload_scene(scene)
+    db = mpt.DeviceBatch(train_batch)
+    out = ctx.solve(db, mpt.default_opts(precision=mpt.FP64_PLAIN))
+    use = (out.status == mpt.CONVERGED).to(torch.uint8)
+    ctx.mlp_init(seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    n = train_batch.n
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    perm = torch.randperm(n, device="cuda", generator=gen).to(torch.int32)
+    pos = 0
+    for it in range(steps):
+        if pos + batch_rows > n:
+            perm = torch.randperm(n, device="cuda", generator=gen).to(torch.int32)
+            pos = 0
+        rows = perm[pos:pos + batch_rows]
+        pos += batch_rows
+        a = lr * 0.5 * (1.0 + math.cos(math.pi * it / max(1, steps)))
+        ctx.mlp_train_step(db, out.x, use=use, lr=a, loss=loss, rows=rows)
+        if it % 200 == 0 or it == steps - 1:
+            hist.append((it, float(loss.item())))
+            if log:
+                print(f"# train step {it}: loss {hist[-1][1]:.5f}", file=log, flush=True)
+    return hist
+
+
+def prepare(ctx, scene, batch, steps=None, n_rx=8192, log=sys.stderr):
+    """Train the network for the workload of `scene` (configurations 2 and 3)
+    on held-apart problems; returns True when the learned start is ready."""
+    cfg = 3 if len(scene.quadrics) or len(scene.circles) else 2
+    t = time.time()
+    sc, tb = W.training_batch(cfg, n_rx=n_rx)
+    if not (np.allclose(sc.planes, scene.planes) and np.allclose(sc.quadrics, scene.quadrics)):
+        return False
+    hist = train(ctx, sc, tb, steps=steps or 3000, log=log)
+    ctx.upload_scene(scene)
+    if log:
+        print(f"# learned start trained in {time.time() - t:.1f}s, final loss {hist[-1][1]:.5f}", file=log, flush=True)
+    return True

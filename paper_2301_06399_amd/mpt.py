@@ -22,7 +22,7 @@ CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7
 FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
 INIT_LINE, INIT_USER, INIT_LEARNED = 0, 1, 2
-SCHED_PER_ORDER, SCHED_PERSISTENT = 0, 1
+SCHED_PER_ORDER, SCHED_PERSISTENT, SCHED_AUTO = 0, 1, 2
 
 
 class MptError(RuntimeError):
@@ -45,18 +45,22 @@ class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("init", C.c_int32), ("max_iter", C.c_int32),
                 ("max_iter32", C.c_int32), ("polish_steps", C.c_int32), ("fallback", C.c_int32),
                 ("plateau_win", C.c_int32), ("sched", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
+                ("graph", C.c_int32),
                 ("plateau_frac", C.c_double), ("tol_step", C.c_double), ("tol_res", C.c_double),
                 ("tau_root", C.c_double), ("lambda0", C.c_double), ("tol_step32", C.c_double),
-                ("tol_res32", C.c_double), ("polish_gate", C.c_double)]
+                ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double)]
 
 
 class SolveOut(C.Structure):
-    _fields_ = [("x", C.c_void_p), ("cost", C.c_void_p), ("iters", C.c_void_p), ("status", C.c_void_p)]
+    _fields_ = [("x", C.c_void_p), ("cost", C.c_void_p), ("iters", C.c_void_p), ("status", C.c_void_p),
+                ("stage_iters", C.c_void_p)]
 
 
 EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt_synchronize",
            "mpt_scene_upload", "mpt_default_opts", "mpt_solve_batch", "mpt_accept", "mpt_mlp_init",
-           "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings"]
+           "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings",
+           "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
+           "mpt_gemm_bf16_check"]
 
 _lib = None
 
@@ -83,11 +87,19 @@ def load_library(path: str = LIB_PATH):
     L.mpt_accept.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOut), C.c_double, C.c_double, vp, vp, vp,
                              C.POINTER(C.c_int64)]
     L.mpt_mlp_init.argtypes = [vp, C.c_uint64]
-    L.mpt_mlp_train_step.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, C.c_float, vp]
+    L.mpt_mlp_train_step.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, C.c_float, vp]
+    L.mpt_mlp_grad.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, vp, vp]
+    L.mpt_mlp_features.argtypes = [vp, C.POINTER(BatchDesc), vp]
+    L.mpt_mlp_param_count.argtypes = [C.POINTER(C.c_size_t)]
+    L.mpt_gemm_bf16_check.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int32, vp, C.c_int32, vp,
+                                      C.c_int32]
     L.mpt_mlp_predict.argtypes = [vp, C.POINTER(BatchDesc), vp]
     L.mpt_mlp_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.mpt_mlp_load.argtypes = [vp, vp, C.c_size_t]
     L.mpt_last_timings.argtypes = [vp, C.POINTER(C.c_float)]
+    L.mpt_flops_per_iter.argtypes = [C.c_int, vp, vp]
+    L.mpt_autotune.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     for f in EXPORTS:
         getattr(L, f).restype = st if f not in ("mpt_last_error", "mpt_default_opts") else getattr(L, f).restype
     _lib = L
@@ -127,23 +139,61 @@ class DeviceBatch:
 
 
 class DeviceOut:
-    def __init__(self, n, device="cuda"):
+    def __init__(self, n, device="cuda", stages=False):
         import torch
         self.x = torch.empty((15, max(n, 0)), dtype=torch.float64, device=device)
         self.cost = torch.empty(max(n, 0), dtype=torch.float64, device=device)
         self.iters = torch.empty(max(n, 0), dtype=torch.int32, device=device)
         self.status = torch.empty(max(n, 0), dtype=torch.uint8, device=device)
+        self.stage = torch.empty((3, max(n, 0)), dtype=torch.int32, device=device) if stages else None
 
     def desc(self) -> SolveOut:
-        return SolveOut(_ptr(self.x), _ptr(self.cost), _ptr(self.iters), _ptr(self.status))
+        return SolveOut(_ptr(self.x), _ptr(self.cost), _ptr(self.iters), _ptr(self.status), _ptr(self.stage))
 
     def numpy(self):
-        return {"x": self.x.cpu().numpy(), "cost": self.cost.cpu().numpy(), "iters": self.iters.cpu().numpy(),
-                "status": self.status.cpu().numpy()}
+        r = {"x": self.x.cpu().numpy(), "cost": self.cost.cpu().numpy(), "iters": self.iters.cpu().numpy(),
+             "status": self.status.cpu().numpy()}
+        if self.stage is not None:
+            r["stage"] = self.stage.cpu().numpy()
+        return r
+
+
+def flops_per_iter(types) -> dict:
+    """Algorithmic FLOPs of one LM iteration / polish step / residual
+    evaluation for a path with the given primitive types (host only)."""
+    L = load_library()
+    t = np.ascontiguousarray(types, np.int32)
+    out = np.zeros(4, np.int64)
+    rc = L.mpt_flops_per_iter(len(t), t.ctypes.data, out.ctypes.data)
+    if rc != MPT_OK:
+        raise MptError(f"mpt_flops_per_iter: {STATUS_NAMES.get(rc, rc)}")
+    return {"lm": int(out[0]), "polish": int(out[1]), "residual": int(out[2]), "sqrt_div": int(out[3])}
+
+
+def flops_table() -> dict:
+    """FLOPs per iteration for every order 1..5 and type combination, as
+    dense arrays indexed by the base-4 code sum(type_k * 4**k)."""
+    tab = {}
+    for n in range(1, 6):
+        lm = np.zeros(4 ** n, np.int64)
+        po = np.zeros(4 ** n, np.int64)
+        re_ = np.zeros(4 ** n, np.int64)
+        for code in range(4 ** n):
+            types = [(code // 4 ** k) % 4 for k in range(n)]
+            f = flops_per_iter(types)
+            lm[code], po[code], re_[code] = f["lm"], f["polish"], f["residual"]
+        tab[n] = {"lm": lm, "polish": po, "residual": re_}
+    return tab
 
 
 class Context:
-    """One library context on one GPU, enqueuing on torch's current stream."""
+    """One library context on one GPU.
+
+    The library enqueues on a stream of its own (a torch stream of default
+    priority).  Every call first makes that stream wait for the caller's
+    current stream (inputs written by torch) and afterwards makes the
+    caller's current stream wait for it (outputs read by torch), so torch
+    code sees the results in order without host synchronisation."""
 
     def __init__(self, device: int = 0, stream=None):
         import torch
@@ -152,13 +202,20 @@ class Context:
             raise MptError("no HIP device available")
         self.torch = torch
         self.device = device
-        s = stream if stream is not None else torch.cuda.current_stream(device)
-        self.stream = s
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
+        if self.stream.cuda_stream == 0:
+            raise MptError("the library needs a stream other than the null stream")
         h = C.c_void_p()
-        rc = self.L.mpt_create(device, C.c_void_p(s.cuda_stream), C.byref(h))
+        rc = self.L.mpt_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != MPT_OK:
             raise MptError(f"mpt_create failed: {STATUS_NAMES.get(rc, rc)}")
         self.h = h
+
+    def _enter(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
     def _check(self, rc, what):
         if rc != MPT_OK:
@@ -177,6 +234,7 @@ class Context:
             pass
 
     def upload_scene(self, scene):
+        self._enter()
         keep = [np.ascontiguousarray(getattr(scene, k), np.float64) for k in ("planes", "lines", "quadrics", "circles")]
         d = SceneDesc()
         d.tx[:] = list(map(float, scene.tx))
@@ -190,7 +248,10 @@ class Context:
         out = out or DeviceOut(dbatch.n)
         o = opts or default_opts()
         bd, od = dbatch.desc(), out.desc()
-        self._check(self.L.mpt_solve_batch(self.h, C.byref(bd), C.byref(o), C.byref(od)), "mpt_solve_batch")
+        self._enter()
+        rc = self.L.mpt_solve_batch(self.h, C.byref(bd), C.byref(o), C.byref(od))
+        self._leave()
+        self._check(rc, "mpt_solve_batch")
         return out
 
     def accept(self, dbatch: DeviceBatch, out: DeviceOut, tau_res=1e-9, min_seg=1e-6, sync=True):
@@ -201,33 +262,99 @@ class Context:
         cnt = torch.empty(1, dtype=torch.int32, device="cuda")
         hc = C.c_int64(0)
         bd, od = dbatch.desc(), out.desc()
-        self._check(self.L.mpt_accept(self.h, C.byref(bd), C.byref(od), tau_res, min_seg, _ptr(acc), _ptr(idx),
-                                      _ptr(cnt), C.byref(hc) if sync else None), "mpt_accept")
+        self._enter()
+        rc = self.L.mpt_accept(self.h, C.byref(bd), C.byref(od), tau_res, min_seg, _ptr(acc), _ptr(idx),
+                               _ptr(cnt), C.byref(hc) if sync else None)
+        self._leave()
+        self._check(rc, "mpt_accept")
         k = int(hc.value) if sync else None
         return acc[:n], (idx[:k] if sync else idx), (k if sync else cnt)
+
+    def autotune(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None):
+        out = out or DeviceOut(dbatch.n)
+        o = opts or default_opts()
+        sch, blk, ms = C.c_int32(), C.c_int32(), C.c_float()
+        bd, od = dbatch.desc(), out.desc()
+        self._enter()
+        rc = self.L.mpt_autotune(self.h, C.byref(bd), C.byref(o), C.byref(od), C.byref(sch), C.byref(blk),
+                                 C.byref(ms))
+        self._leave()
+        self._check(rc, "mpt_autotune")
+        return {"sched": sch.value, "block": blk.value, "lm_ms": ms.value}
 
     def synchronize(self):
         self._check(self.L.mpt_synchronize(self.h), "mpt_synchronize")
 
     def timings(self):
-        ms = (C.c_float * 4)()
+        ms = (C.c_float * 5)()
         self._check(self.L.mpt_last_timings(self.h, ms), "mpt_last_timings")
-        return {"bin": ms[0], "learned": ms[1], "solve": ms[2], "fallback": ms[3]}
+        return {"bin": ms[0], "learned": ms[1], "lm": ms[2], "polish": ms[3], "fallback": ms[4]}
 
     # ---------------------------------------------------------------- network
     def mlp_init(self, seed: int = 0):
-        self._check(self.L.mpt_mlp_init(self.h, C.c_uint64(seed)), "mpt_mlp_init")
+        self._enter()
+        rc = self.L.mpt_mlp_init(self.h, C.c_uint64(seed))
+        self._leave()
+        self._check(rc, "mpt_mlp_init")
 
-    def mlp_train_step(self, dbatch: DeviceBatch, target_x, use=None, lr=1e-3, loss=None):
+    def mlp_train_step(self, dbatch: DeviceBatch, target_x, use=None, lr=1e-3, loss=None, rows=None):
         bd = dbatch.desc()
-        self._check(self.L.mpt_mlp_train_step(self.h, C.byref(bd), _ptr(target_x), _ptr(use), C.c_float(lr),
-                                              _ptr(loss)), "mpt_mlp_train_step")
+        nr = int(rows.numel()) if rows is not None else dbatch.n
+        self._enter()
+        rc = self.L.mpt_mlp_train_step(self.h, C.byref(bd), _ptr(target_x), _ptr(use), _ptr(rows), nr,
+                                       C.c_float(lr), _ptr(loss))
+        self._leave()
+        self._check(rc, "mpt_mlp_train_step")
+
+    def mlp_grad(self, dbatch: DeviceBatch, target_x, use=None, rows=None):
+        torch = self.torch
+        n = C.c_size_t(0)
+        self.L.mpt_mlp_param_count(C.byref(n))
+        g = torch.empty(n.value, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        bd = dbatch.desc()
+        nr = int(rows.numel()) if rows is not None else dbatch.n
+        self._enter()
+        rc = self.L.mpt_mlp_grad(self.h, C.byref(bd), _ptr(target_x), _ptr(use), _ptr(rows), nr, _ptr(loss),
+                                 _ptr(g))
+        self._leave()
+        self._check(rc, "mpt_mlp_grad")
+        return float(loss.item()), g
+
+    def mlp_features(self, dbatch: DeviceBatch):
+        f = self.torch.empty((dbatch.n, 96), dtype=self.torch.float32, device="cuda")
+        bd = dbatch.desc()
+        self._enter()
+        rc = self.L.mpt_mlp_features(self.h, C.byref(bd), _ptr(f))
+        self._leave()
+        self._check(rc, "mpt_mlp_features")
+        return f
+
+    def gemm_bf16_check(self, A, B, a_trans=False, b_trans=False, splits=1):
+        """C = A B on the matrix cores (inputs rounded to BF16, FP32 sums).
+        A, B: float32 CUDA tensors laid out as the flags say."""
+        torch = self.torch
+        if a_trans:
+            K, M = A.shape
+        else:
+            M, K = A.shape
+        N = B.shape[0] if b_trans else B.shape[1]
+        Cm = torch.empty((M, N), dtype=torch.float32, device="cuda")
+        self._enter()
+        rc = self.L.mpt_gemm_bf16_check(self.h, M, N, K, _ptr(A.contiguous()), int(a_trans), _ptr(B.contiguous()),
+                                        int(b_trans), _ptr(Cm), splits)
+        self._leave()
+        self._check(rc, "mpt_gemm_bf16_check")
+        return Cm
 
     def mlp_predict(self, dbatch: DeviceBatch, x_out=None):
         x_out = x_out if x_out is not None else self.torch.empty((15, dbatch.n), dtype=self.torch.float64,
                                                                  device="cuda")
         bd = dbatch.desc()
-        self._check(self.L.mpt_mlp_predict(self.h, C.byref(bd), _ptr(x_out)), "mpt_mlp_predict")
+        self._enter()
+        rc = self.L.mpt_mlp_predict(self.h, C.byref(bd), _ptr(x_out))
+        self._leave()
+        self._check(rc, "mpt_mlp_predict")
         return x_out
 
     def mlp_save(self) -> bytes:
@@ -239,4 +366,7 @@ class Context:
 
     def mlp_load(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
-        self._check(self.L.mpt_mlp_load(self.h, buf, len(blob)), "mpt_mlp_load")
+        self._enter()
+        rc = self.L.mpt_mlp_load(self.h, buf, len(blob))
+        self._leave()
+        self._check(rc, "mpt_mlp_load")

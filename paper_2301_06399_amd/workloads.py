@@ -420,4 +420,32 @@ def random_init(scene: Scene, batch: Batch, cfg: int, restart: int = 0) -> np.nd
     return x0
 
 
+def training_batch(cfg: int, n_rx: int, per_rx: int = 64, stream: str = "train") -> tuple[Scene, Batch]:
+    """Problems for the learned start: the same scene as configuration `cfg`
+    (2: street canyon, 3: curved), receivers and interaction lists drawn from
+    the separate seed stream `stream` ("train" or "heldout")."""
+    if cfg == 2:
+        sc = street_canyon_scene(2)
+        rng = np.random.default_rng(seed(2, stream))
+        xy = sc._free_xy(rng, n_rx)
+        rx = np.column_stack([xy, np.full(n_rx, 1.5)])
+        lo, hi = 1, 4
+    elif cfg == 3:
+        sc = curved_scene(3)
+        rng = np.random.default_rng(seed(3, stream))
+        rx = rng.uniform(sc.aabb_lo, sc.aabb_hi, (n_rx, 3))
+        lo, hi = 1, 6
+    else:
+        raise ValueError("training batches exist for configurations 2 and 3")
+    rs = np.random.default_rng(seed(cfg, stream) + 500)
+    n = n_rx * per_rx
+    order = rs.integers(lo, hi, n).astype(np.int32)
+    pool = np.arange(sc.n_prims, dtype=np.int32)
+    prim = _no_repeat_sequences(rs, n, order, lambda k: pool)
+    rx_index = np.repeat(np.arange(n_rx, dtype=np.int32), per_rx)
+    if cfg == 2:
+        prim = _resample_near(sc, rx, rx_index, prim, order, rs, lambda k: pool)
+    return sc, Batch(rx, rx_index, order, prim)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}

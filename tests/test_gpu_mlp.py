@@ -1,0 +1,131 @@
+"""The learned start's kernels on the GPU: the matrix-core GEMM, the
+features, the gradients (against the FP64 reference), training, save/load,
+and the learned start inside the solver."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp_ref as R
+from paper_2301_06399_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2301_06399_amd import mpt
+    c = mpt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("at,bt", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("M,N,K,splits", [(100, 70, 77, 1), (64, 64, 32, 1), (33, 257, 300, 3), (256, 16, 4096, 16)])
+def test_mfma_gemm_matches_cpu(ctx, at, bt, M, N, K, splits):
+    """C = A B on the matrix cores with BF16 inputs: equal to the FP64 product
+    of the BF16-rounded inputs up to FP32 accumulation error (this also pins
+    the MFMA operand and result lane layout)."""
+    import torch
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.normal(size=(K, M) if at else (M, K)).astype(np.float32)
+    B = rng.normal(size=(N, K) if bt else (K, N)).astype(np.float32)
+    Cg = ctx.gemm_bf16_check(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), bool(at), bool(bt), splits)
+    Ar, Br = R.bf16(A), R.bf16(B)
+    Cr = (Ar.T if at else Ar) @ (Br.T if bt else Br)
+    err = np.abs(Cg.cpu().numpy() - Cr).max()
+    assert err <= 1e-5 * np.sqrt(K) * max(1.0, np.abs(Cr).max()), err
+
+
+def test_features_match_reference(ctx):
+    from paper_2301_06399_amd import mpt
+    for cfg in (2, 3):
+        sc, b = W.training_batch(cfg, n_rx=8, per_rx=64)
+        ctx.upload_scene(sc)
+        f = ctx.mlp_features(mpt.DeviceBatch(b)).cpu().numpy()
+        np.testing.assert_allclose(f, R.features(sc, b), atol=2e-6, rtol=1e-6)
+
+
+def solved_training_set(ctx, cfg, n_rx):
+    from paper_2301_06399_amd import mpt
+    sc, b = W.training_batch(cfg, n_rx=n_rx, per_rx=64)
+    ctx.upload_scene(sc)
+    db = mpt.DeviceBatch(b)
+    out = ctx.solve(db, mpt.default_opts(precision=mpt.FP64_PLAIN))
+    return sc, b, db, out
+
+
+def test_gradients_match_fp64_reference(ctx):
+    """Loss and gradient of the BF16 kernels against the FP64 reference: to
+    FP32-accumulation precision when the reference rounds where the kernels
+    store BF16, and to BF16 precision against the exact FP64 network."""
+    import torch
+    from paper_2301_06399_amd import mpt
+    sc, b, db, out = solved_training_set(ctx, 2, 32)
+    use = (out.status == 0).to(torch.uint8)
+    ctx.mlp_init(7)
+    rows = torch.arange(0, 2000, dtype=torch.int32, device="cuda")
+    loss_g, g = ctx.mlp_grad(db, out.x, use=use, rows=rows)
+    hdr, w, _, _ = R.parse_blob(ctx.mlp_save())
+    P = R.unpack(w)
+    sb = b.subset(np.arange(2000))
+    X = R.features(sc, sb)
+    T = R.targets(sc, sb, out.x.cpu().numpy()[:, :2000])
+    mask = np.zeros((2000, 16))
+    u = use.cpu().numpy()[:2000]
+    for i in range(2000):
+        mask[i, :3 * sb.order[i]] = u[i]
+    G_gpu = R.unpack(g.cpu().numpy())
+    for rounding, tol, ltol in ((True, 5e-3, 1e-4), (False, 3e-2, 1e-2)):
+        loss_r, G, _ = R.loss_and_grad(P, X, T, mask, rounding=rounding)
+        assert abs(loss_g - loss_r) <= ltol * loss_r, (rounding, loss_g, loss_r)
+        for k in G:
+            rel = np.linalg.norm(G_gpu[k] - G[k]) / max(np.linalg.norm(G[k]), 1e-30)
+            assert rel <= tol, (rounding, k, rel)
+
+
+def test_training_lowers_loss_and_blob_roundtrip(ctx):
+    import torch
+    from paper_2301_06399_amd import learned, mpt
+    sc, b = W.training_batch(2, n_rx=256, per_rx=64)
+    hist = learned.train(ctx, sc, b, steps=300, batch_rows=2048)
+    assert hist[-1][1] < 0.5 * hist[0][1], hist
+    db = mpt.DeviceBatch(b)
+    p1 = ctx.mlp_predict(db).cpu().numpy()
+    blob = ctx.mlp_save()
+    hdr, w, m, v = R.parse_blob(blob)
+    assert hdr["step"] == 300 and hdr["layers"] == [96, 256, 256, 256, 15]
+    ctx.mlp_init(99)
+    assert not np.array_equal(ctx.mlp_predict(db).cpu().numpy(), p1)
+    ctx.mlp_load(blob)
+    assert np.array_equal(ctx.mlp_predict(db).cpu().numpy(), p1)
+    # predictions are finite world points, zero beyond each order
+    for i in range(0, b.n, 97):
+        assert np.isfinite(p1[:3 * b.order[i], i]).all() and (p1[3 * b.order[i]:, i] == 0).all()
+
+
+def test_learned_start_keeps_parity(ctx):
+    """Started from the network's points, the solver still reaches the
+    oracle's accept flags on planes and edges (unique roots)."""
+    from paper_2301_06399_amd import learned, mpt
+    sc, tb = W.training_batch(2, n_rx=512, per_rx=64)
+    learned.train(ctx, sc, tb, steps=400, batch_rows=4096)
+    hsc, hb = W.training_batch(2, n_rx=128, per_rx=64, stream="heldout")
+    ctx.upload_scene(hsc)
+    db = mpt.DeviceBatch(hb)
+    out = ctx.solve(db, mpt.default_opts(init=mpt.INIT_LEARNED))
+    acc, idx, k = ctx.accept(db, out)
+    g = out.numpy()
+    gacc = acc.cpu().numpy()
+    orc = O.solve_batch(hsc, hb)
+    oacc = O.accept_batch(hsc, hb, orc["x"], orc["status"])
+    missed = np.where((gacc == 0) & (oacc == 1))[0]
+    extra = np.where((gacc == 1) & (oacc == 0))[0]
+    assert len(missed) <= 0.002 * max(1, oacc.sum()), missed[:10]
+    for i in extra:  # a root the oracle's straight-line run did not reach
+        n = hb.order[i]
+        X, c, it, st = O.solve_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], x0=g["x"][:3 * n, i])
+        assert st == O.CONVERGED and np.abs(X - g["x"][:3 * n, i]).max() <= 1e-6
+    both = (gacc == 1) & (oacc == 1)
+    for i in np.where(both)[0]:
+        n = hb.order[i]
+        assert np.abs(g["x"][:3 * n, i] - orc["x"][:3 * n, i]).max() <= 1e-6
