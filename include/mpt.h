@@ -143,6 +143,8 @@ typedef struct {
     int32_t sched;         /* MPT_SCHED_AUTO: the autotuner's choice            */
     int32_t block;         /* 0: the autotuner's threads per block (64..256)    */
     int32_t grid;          /* 0: all blocks that fit on the device at once      */
+    int32_t max_iter_fb;   /* 50   FP64 fallback cap (it restarts from the FP32
+                              end point, which is already root-like)          */
     int32_t graph;         /* 0: launch directly; 1: capture the whole solve in
                               a HIP graph once per (batch, options, outputs,
                               scene) and replay it (stage timings unavailable) */
@@ -258,6 +260,10 @@ mpt_status mpt_gemm_bf16_check(mpt_ctx *ctx, int32_t M, int32_t N, int32_t K, co
                                int32_t splits);
 /* Predicted points [15][n] FP64 world frame (device, caller-owned). */
 mpt_status mpt_mlp_predict(mpt_ctx *ctx, const mpt_batch_desc *batch, double *x_out);
+/* The same prediction through the layer-by-layer GEMM kernels training
+ * uses (activations in device memory) instead of the fused kernel; for
+ * checking the fused kernel. */
+mpt_status mpt_mlp_predict_unfused(mpt_ctx *ctx, const mpt_batch_desc *batch, double *x_out);
 /* Serialise / restore the network (FP32 master weights and Adam state).
  * mpt_mlp_save with blob = NULL stores the needed size in *bytes. */
 mpt_status mpt_mlp_save(mpt_ctx *ctx, void *blob, size_t *bytes);
@@ -280,6 +286,10 @@ mpt_status mpt_flops_per_iter(int order, const int32_t *types, int64_t out[4]);
  * start, [2] first LM pass (FP32 or plain FP64), [3] FP64 polish,
  * [4] FP64 fallback. */
 mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[5]);
+/* Durations (ms) of the per-order kernels of the first LM pass of the last
+ * mpt_solve_batch run with MPT_SCHED_PER_ORDER, index = order - 1 (HIP
+ * events on the forked streams; synchronises). */
+mpt_status mpt_last_lm_timings(mpt_ctx *ctx, float ms[5]);
 
 #ifdef __cplusplus
 }

@@ -38,10 +38,12 @@ struct mpt_ctx {
     hipEvent_t ev[6] = {};
     hipStream_t aux[MPT_MAX_ORDER] = {};  // per-order launches run concurrently
     hipEvent_t fork = nullptr, join[MPT_MAX_ORDER] = {};
+    hipEvent_t kev[MPT_MAX_ORDER][2] = {};  // per-order kernel start / end of the first LM pass
+    bool kev_valid = false;
     bool timed = false;
     MlpState *mlp = nullptr;
     // autotuned launch choices: key -> (sched, block)
-    struct Tune { int prec, nbucket, n_all, sched, block; float ms; };
+    struct Tune { int prec, nbucket, n_all, sched, block, gdiv; float ms; };
     std::vector<Tune> tune;
     bool tune_loaded = false;
     // captured graph of the last solve (replayed while the key matches)
@@ -50,7 +52,8 @@ struct mpt_ctx {
     std::vector<unsigned char> gkey;
 };
 
-static const int kCounters = 32;  // bin_cnt 0..4, cursor 5..9, head 10..19, pol_cnt 20..24, fb_cnt 25..29
+// bin_cnt 0..4, (5..9 unused), head 10..19, pol_cnt 20..24, fb_cnt 25..29, then 3 x 1364 key counters
+static const int kCounters = 32 + 3 * 1364;
 
 static mpt_status fail(mpt_ctx *c, mpt_status st, const char *fmt, ...)
 {
@@ -117,6 +120,8 @@ mpt_status mpt_create(int device, void *hip_stream, mpt_ctx **out)
         hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming);
     }
     hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    for (int i = 0; i < MPT_MAX_ORDER; i++)
+        for (int j = 0; j < 2; j++) hipEventCreate(&c->kev[i][j]);
     *out = c;
     return MPT_OK;
 }
@@ -139,6 +144,9 @@ mpt_status mpt_destroy(mpt_ctx *c)
         if (c->join[i]) hipEventDestroy(c->join[i]);
     }
     if (c->fork) hipEventDestroy(c->fork);
+    for (int i = 0; i < MPT_MAX_ORDER; i++)
+        for (int j = 0; j < 2; j++)
+            if (c->kev[i][j]) hipEventDestroy(c->kev[i][j]);
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->cap) hipStreamDestroy(c->cap);
     if (c->own) hipStreamDestroy(c->own);
@@ -253,6 +261,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->block = 0;
     o->grid = 0;
     o->graph = 0;
+    o->max_iter_fb = 50;
     o->plateau_frac = 0.999;
     o->tol_step = 1e-12;
     o->tol_res = 1e-13;
@@ -299,8 +308,9 @@ static int resident_grid(mpt_ctx *c, const void *kern, int block, int64_t n, siz
 // Default launch choices before (or without) tuning, from measurements on
 // MI355X: FP32 passes run one launch per order concurrently (each order
 // keeps its own register budget), FP64 passes one mixed-order launch.
-static void default_choice(int prec, int &sched, int &block)
+static void default_choice(int prec, int &sched, int &block, int &gdiv)
 {
+    gdiv = 1;
     if (prec == MPT_FP32_POLISH64) { sched = MPT_SCHED_PER_ORDER; block = 128; }
     else { sched = MPT_SCHED_PERSISTENT; block = 256; }
 }
@@ -320,9 +330,9 @@ static void tune_load(mpt_ctx *c)
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    // one entry per line: prec nbucket n_all sched block ms
+    // one entry per line: prec nbucket n_all sched block gdiv ms
     mpt_ctx::Tune t;
-    while (fscanf(f, "%d %d %d %d %d %f", &t.prec, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.ms) == 6)
+    while (fscanf(f, "%d %d %d %d %d %d %f", &t.prec, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.gdiv, &t.ms) == 7)
         c->tune.push_back(t);
     fclose(f);
 }
@@ -333,18 +343,20 @@ static void tune_save(mpt_ctx *c)
     if (!path) return;
     FILE *f = fopen(path, "w");
     if (!f) return;
-    for (auto &t : c->tune) fprintf(f, "%d %d %d %d %d %.6f\n", t.prec, t.nbucket, t.n_all, t.sched, t.block, t.ms);
+    for (auto &t : c->tune)
+        fprintf(f, "%d %d %d %d %d %d %.6f\n", t.prec, t.nbucket, t.n_all, t.sched, t.block, t.gdiv, t.ms);
     fclose(f);
 }
 
-static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block)
+static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv)
 {
-    default_choice(o->precision, sched, block);
+    default_choice(o->precision, sched, block, gdiv);
     tune_load(c);
     for (auto &t : c->tune)
         if (t.prec == o->precision && t.nbucket == nbucket(n) && t.n_all == c->s.n_all) {
             sched = t.sched;
             block = t.block;
+            gdiv = t.gdiv;
         }
     if (o->sched != MPT_SCHED_AUTO) sched = o->sched;
     if (o->block) block = o->block;
@@ -366,7 +378,8 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
     if (opts->init == MPT_INIT_USER && b->n > 0 && !b->x0) return fail(c, MPT_E_INVALID_ARG, "user start without x0");
     if (opts->init == MPT_INIT_LEARNED && !mlp_ready(c->mlp))
         return fail(c, MPT_E_NO_MODEL, "learned start requested but no network initialised");
-    if (opts->max_iter < 0 || opts->max_iter32 < 0 || opts->polish_steps < 0 || opts->plateau_win < 0)
+    if (opts->max_iter < 0 || opts->max_iter32 < 0 || opts->max_iter_fb < 0 || opts->polish_steps < 0 ||
+        opts->plateau_win < 0)
         return fail(c, MPT_E_INVALID_ARG, "negative iteration option");
     if (opts->block != 0 && (opts->block % 64 != 0 || opts->block > 256 || opts->block < 64))
         return fail(c, MPT_E_INVALID_ARG, "block must be 64, 128, 192 or 256");
@@ -379,7 +392,8 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
 // Enqueue the whole solve on stream s (no host synchronisation).  With
 // `timed`, HIP events mark the stage boundaries (not inside graph capture).
 static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts,
-                                const mpt_solve_out *out, hipStream_t s, bool timed, int sched, int block)
+                                const mpt_solve_out *out, hipStream_t s, bool timed, int sched, int block,
+                                int gdiv = 1)
 {
     BatchDev bd;
     mpt_status st = batch_dev(c, b, bd);
@@ -397,6 +411,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.o.init = opts->init;
     kp.o.max_iter = opts->max_iter;
     kp.o.max_iter32 = opts->max_iter32;
+    kp.o.max_iter_fb = opts->max_iter_fb;
     kp.o.polish_steps = opts->polish_steps;
     kp.o.fallback = opts->fallback;
     kp.o.plateau_win = opts->plateau_win;
@@ -420,14 +435,14 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
 
     if (timed) hipEventRecord(c->ev[0], s);
     launch_zero(ctr, kCounters, s);
-    launch_bin(bd, kp.out, c->s.n_all, ctr + 0, ctr + 5, (int *)kp.perm, s);
+    launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, s);
     if (timed) hipEventRecord(c->ev[1], s);
     if (opts->init == MPT_INIT_LEARNED && n > 0) {
         if ((st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s))) return fail(c, st, "network forward failed");
     }
     if (timed) hipEventRecord(c->ev[2], s);
     const int mode = (opts->precision == MPT_FP64_PLAIN) ? MODE_PLAIN64 : MODE_FP32;
-    auto run_lm = [&](int md, int sch, int blk) {
+    auto run_lm = [&](int md, int sch, int blk, bool first) {
         // stage the scene in LDS when it fits
         const size_t rec_bytes = (size_t)c->s.n_all * kRec * (md == MODE_FP32 ? sizeof(float) : sizeof(double));
         const bool lds = rec_bytes <= c->lds_max;
@@ -435,7 +450,12 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
             const void *k = lm_kernel(md, ord, lds);
             if (lds) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rec_bytes);
             int g = opts->grid;
-            if (!g) g = resident_grid(c, k, blk, n, lds ? rec_bytes : 0);
+            if (!g) {
+                // all resident blocks, divided by gdiv for the concurrent
+                // per-order launches (fewer waves per SIMD in their tails)
+                g = resident_grid(c, k, blk, n, lds ? rec_bytes : 0);
+                if (first && gdiv > 1) g = (g + gdiv - 1) / gdiv;
+            }
             launch_lm(md, ord, lds, rec_bytes, kp, g, blk, where);
         };
         if (sch == MPT_SCHED_PERSISTENT) {
@@ -447,18 +467,21 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
             hipEventRecord(c->fork, s);
             for (int ord = MPT_MAX_ORDER; ord >= 1; ord--) {
                 hipStreamWaitEvent(c->aux[ord - 1], c->fork, 0);
+                if (timed && first) hipEventRecord(c->kev[ord - 1][0], c->aux[ord - 1]);
                 go(ord, c->aux[ord - 1]);
+                if (timed && first) hipEventRecord(c->kev[ord - 1][1], c->aux[ord - 1]);
                 hipEventRecord(c->join[ord - 1], c->aux[ord - 1]);
             }
             for (int ord = 1; ord <= MPT_MAX_ORDER; ord++) hipStreamWaitEvent(s, c->join[ord - 1], 0);
         }
     };
-    if (n > 0) run_lm(mode, sched, block);
+    if (timed) c->kev_valid = (n > 0) && sched == MPT_SCHED_PER_ORDER;
+    if (n > 0) run_lm(mode, sched, block, true);
     if (timed) hipEventRecord(c->ev[3], s);
     if (n > 0 && mode == MODE_FP32) launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
     if (timed) hipEventRecord(c->ev[4], s);
     // the fallback handles a handful of paths: one mixed-order launch
-    if (n > 0 && mode == MODE_FP32 && opts->fallback) run_lm(MODE_FALLBACK64, MPT_SCHED_PERSISTENT, 256);
+    if (n > 0 && mode == MODE_FP32 && opts->fallback) run_lm(MODE_FALLBACK64, MPT_SCHED_PERSISTENT, 256, false);
     if (timed) hipEventRecord(c->ev[5], s);
     if (timed) c->timed = true;
     HIPCHK(c, hipGetLastError());
@@ -466,15 +489,16 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
 }
 
 static std::vector<unsigned char> graph_key(const mpt_batch_desc *b, const mpt_solve_opts *o, const mpt_solve_out *out,
-                                            int sched, int block, const SceneDev &s)
+                                            int sched, int block, int gdiv, const SceneDev &s)
 {
-    std::vector<unsigned char> k(sizeof *b + sizeof *o + sizeof *out + 2 * sizeof(int) + sizeof s);
+    std::vector<unsigned char> k(sizeof *b + sizeof *o + sizeof *out + 3 * sizeof(int) + sizeof s);
     unsigned char *p = k.data();
     memcpy(p, b, sizeof *b), p += sizeof *b;
     memcpy(p, o, sizeof *o), p += sizeof *o;
     memcpy(p, out, sizeof *out), p += sizeof *out;
     memcpy(p, &sched, sizeof sched), p += sizeof sched;
     memcpy(p, &block, sizeof block), p += sizeof block;
+    memcpy(p, &gdiv, sizeof gdiv), p += sizeof gdiv;
     memcpy(p, &s, sizeof s);
     return k;
 }
@@ -487,12 +511,12 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     mpt_status st = check_opts(c, b, opts, out);
     if (st) return st;
     hipSetDevice(c->device);
-    int sched, block;
-    choose(c, opts, b->n, sched, block);
-    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block);
+    int sched, block, gdiv;
+    choose(c, opts, b->n, sched, block, gdiv);
+    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block, gdiv);
 
     // graph mode: capture once per (batch, options, outputs, scene) and replay
-    std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, c->s);
+    std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, gdiv, c->s);
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) hipGraphExecDestroy(c->gexec), c->gexec = nullptr;
         if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
@@ -500,7 +524,7 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
         if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 3 * (size_t)(b->n > 0 ? b->n : 1), sizeof(int))))
             return st;
         HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-        st = enqueue_solve(c, b, opts, out, c->cap, false, sched, block);
+        st = enqueue_solve(c, b, opts, out, c->cap, false, sched, block, gdiv);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap, &g);
         if (st) {
@@ -525,28 +549,33 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     if (st) return st;
     hipSetDevice(c->device);
     tune_load(c);
-    const int scheds[2] = {MPT_SCHED_PER_ORDER, MPT_SCHED_PERSISTENT};
-    const int blocks[3] = {64, 128, 256};
+    // candidates: schedule x block size x grid divisor (per-order only)
+    struct Cand { int sched, block, gdiv; };
+    std::vector<Cand> cands;
+    for (int blk : {64, 128, 256}) {
+        cands.push_back({MPT_SCHED_PERSISTENT, blk, 1});
+        for (int gd : {1, 2, 4}) cands.push_back({MPT_SCHED_PER_ORDER, blk, gd});
+    }
     float best = 1e30f;
-    int bs = 0, bb = 0;
-    for (int si = 0; si < 2; si++)
-        for (int bi = 0; bi < 3; bi++) {
-            float tot = 0.0f;
-            for (int rep = 0; rep < 3; rep++) {
-                if ((st = enqueue_solve(c, b, opts, out, c->stream, true, scheds[si], blocks[bi]))) return st;
-                HIPCHK(c, hipEventSynchronize(c->ev[5]));
-                float ms = 0.0f;
-                HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
-                if (rep > 0) tot += ms;  // the first run warms up
-            }
-            if (tot < best) best = tot, bs = scheds[si], bb = blocks[bi];
+    Cand bc = cands[0];
+    for (const Cand &cd : cands) {
+        float tot = 0.0f;
+        for (int rep = 0; rep < 3; rep++) {
+            if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv))) return st;
+            HIPCHK(c, hipEventSynchronize(c->ev[5]));
+            float ms = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[5]));  // LM, polish and fallback passes
+            if (rep > 0) tot += ms;  // the first run warms up
         }
+        if (tot < best) best = tot, bc = cd;
+    }
     best *= 0.5f;
+    const int bs = bc.sched, bb = bc.block;
     bool found = false;
     for (auto &t : c->tune)
         if (t.prec == opts->precision && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
-            t.sched = bs, t.block = bb, t.ms = best, found = true;
-    if (!found) c->tune.push_back({opts->precision, nbucket(b->n), c->s.n_all, bs, bb, best});
+            t.sched = bs, t.block = bb, t.gdiv = bc.gdiv, t.ms = best, found = true;
+    if (!found) c->tune.push_back({opts->precision, nbucket(b->n), c->s.n_all, bs, bb, bc.gdiv, best});
     tune_save(c);
     if (best_sched) *best_sched = bs;
     if (best_block) *best_block = bb;
@@ -641,6 +670,15 @@ mpt_status mpt_last_timings(mpt_ctx *c, float ms[5])
     if (!c->timed) return fail(c, MPT_E_INVALID_ARG, "no solve recorded");
     HIPCHK(c, hipEventSynchronize(c->ev[5]));
     for (int i = 0; i < 5; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
+    return MPT_OK;
+}
+
+mpt_status mpt_last_lm_timings(mpt_ctx *c, float ms[5])
+{
+    if (!c || !ms) return MPT_E_INVALID_ARG;
+    if (!c->timed || !c->kev_valid) return fail(c, MPT_E_INVALID_ARG, "no per-order solve recorded");
+    HIPCHK(c, hipEventSynchronize(c->ev[5]));
+    for (int i = 0; i < MPT_MAX_ORDER; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->kev[i][0], c->kev[i][1]));
     return MPT_OK;
 }
 
@@ -759,6 +797,20 @@ mpt_status mpt_mlp_predict(mpt_ctx *c, const mpt_batch_desc *b, double *x_out)
     if (b->n > 0 && !x_out) return fail(c, MPT_E_INVALID_ARG, "null output");
     hipSetDevice(c->device);
     st = mlp_predict_dev(c->mlp, c->s, bd, x_out, c->stream);
+    return st ? fail(c, st, "network forward failed") : MPT_OK;
+}
+
+mpt_status mpt_mlp_predict_unfused(mpt_ctx *c, const mpt_batch_desc *b, double *x_out)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
+    if (!mlp_ready(c->mlp)) return fail(c, MPT_E_NO_MODEL, "no network initialised");
+    BatchDev bd;
+    mpt_status st = batch_dev(c, b, bd);
+    if (st) return st;
+    if (b->n > 0 && !x_out) return fail(c, MPT_E_INVALID_ARG, "null output");
+    hipSetDevice(c->device);
+    st = mlp_predict_unfused(c->mlp, c->s, bd, x_out, c->stream);
     return st ? fail(c, st, "network forward failed") : MPT_OK;
 }
 

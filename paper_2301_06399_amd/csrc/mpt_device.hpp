@@ -81,31 +81,24 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
 #pragma unroll
     for (int i = 0; i < 3; i++) { ih[i] = a[i] * ia; rh[i] = b[i] * ib; }
     const T S = T(0.5) * (la + lb);
-    const bool surf = (t == TP) || (t == TQ);
-    const bool quad = (t == TQ);
-
-    if (surf) {
+    if (t == TP || t == TQ) {
         // plane: g = n, f = n.X - d.  quadric: w = X - p, g = 2 A w + b,
-        // f = w^T A w + b^T w + c.  A = [[a0 a1 a2][a1 a3 a4][a2 a4 a5]]
-        const T a0 = quad ? r[3] : T(0), a1 = quad ? r[4] : T(0), a2 = quad ? r[5] : T(0);
-        const T a3 = quad ? r[6] : T(0), a4 = quad ? r[7] : T(0), a5 = quad ? r[8] : T(0);
+        // f = w^T A w + b^T w + c, with A = [[a0 a1 a2][a1 a3 a4][a2 a4 a5]]
         T g[3], f;
-        {
+        if (t == TQ) {
             const T w0 = Xk[0] - r[0], w1 = Xk[1] - r[1], w2 = Xk[2] - r[2];
-            const T Aw0 = a0 * w0 + a1 * w1 + a2 * w2;
-            const T Aw1 = a1 * w0 + a3 * w1 + a4 * w2;
-            const T Aw2 = a2 * w0 + a4 * w1 + a5 * w2;
-            if (quad) {
-                f = w0 * Aw0 + w1 * Aw1 + w2 * Aw2 + r[9] * w0 + r[10] * w1 + r[11] * w2 + r[12];
-                g[0] = T(2) * Aw0 + r[9];
-                g[1] = T(2) * Aw1 + r[10];
-                g[2] = T(2) * Aw2 + r[11];
-            } else {
-                f = r[0] * Xk[0] + r[1] * Xk[1] + r[2] * Xk[2] - r[3];
-                g[0] = r[0];
-                g[1] = r[1];
-                g[2] = r[2];
-            }
+            const T Aw0 = r[3] * w0 + r[4] * w1 + r[5] * w2;
+            const T Aw1 = r[4] * w0 + r[6] * w1 + r[7] * w2;
+            const T Aw2 = r[5] * w0 + r[7] * w1 + r[8] * w2;
+            f = w0 * Aw0 + w1 * Aw1 + w2 * Aw2 + r[9] * w0 + r[10] * w1 + r[11] * w2 + r[12];
+            g[0] = T(2) * Aw0 + r[9];
+            g[1] = T(2) * Aw1 + r[10];
+            g[2] = T(2) * Aw2 + r[11];
+        } else {
+            f = r[0] * Xk[0] + r[1] * Xk[1] + r[2] * Xk[2] - r[3];
+            g[0] = r[0];
+            g[1] = r[1];
+            g[2] = r[2];
         }
         T lg2 = dot3(g, g);
         valid = valid && (lg2 > T(0));
@@ -125,58 +118,78 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
             T m[3];
 #pragma unroll
             for (int j = 0; j < 3; j++) m[j] = T(2) * (nh[j] - s * ih[j]) * ia;
-            // curvature: Nm = (I - nh nh^T) B, B = 2A/|g|; TN = 2 (nh ih^T + s I) Nm
-            //   = 2 nh q^T + 2 s (B - nh v^T), v = B nh, q = B ih - s v
-            const T c2 = T(2) * ig;
-            const T b0 = c2 * a0, b1 = c2 * a1, b2 = c2 * a2, b3 = c2 * a3, b4 = c2 * a4, b5 = c2 * a5;
-            const T v[3] = {b0 * nh[0] + b1 * nh[1] + b2 * nh[2], b1 * nh[0] + b3 * nh[1] + b4 * nh[2],
-                            b2 * nh[0] + b4 * nh[1] + b5 * nh[2]};
-            const T q[3] = {b0 * ih[0] + b1 * ih[1] + b2 * ih[2] - s * v[0],
-                            b1 * ih[0] + b3 * ih[1] + b4 * ih[2] - s * v[1],
-                            b2 * ih[0] + b4 * ih[1] + b5 * ih[2] - s * v[2]};
-            const T Bm[3][3] = {{b0, b1, b2}, {b1, b3, b4}, {b2, b4, b5}};
-            const T s2 = T(2) * s;
+            // curvature of a quadric: Nm = (I - nh nh^T) B, B = 2A/|g|;
+            // TN = 2 (nh ih^T + s I) Nm = 2 nh q^T + 2 s (B - nh v^T),
+            // v = B nh, q = B ih - s v.  A plane has no curvature.
+            T TN[3][3];
+            if (t == TQ) {
+                const T c2 = T(2) * ig;
+                const T b0 = c2 * r[3], b1 = c2 * r[4], b2 = c2 * r[5], b3 = c2 * r[6], b4 = c2 * r[7],
+                        b5 = c2 * r[8];
+                const T v[3] = {b0 * nh[0] + b1 * nh[1] + b2 * nh[2], b1 * nh[0] + b3 * nh[1] + b4 * nh[2],
+                                b2 * nh[0] + b4 * nh[1] + b5 * nh[2]};
+                const T q[3] = {b0 * ih[0] + b1 * ih[1] + b2 * ih[2] - s * v[0],
+                                b1 * ih[0] + b3 * ih[1] + b4 * ih[2] - s * v[1],
+                                b2 * ih[0] + b4 * ih[1] + b5 * ih[2] - s * v[2]};
+                const T Bm[3][3] = {{b0, b1, b2}, {b1, b3, b4}, {b2, b4, b5}};
+                const T s2 = T(2) * s;
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+#pragma unroll
+                    for (int j = 0; j < 3; j++) TN[i][j] = T(2) * nh[i] * q[j] + s2 * (Bm[i][j] - nh[i] * v[j]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+#pragma unroll
+                    for (int j = 0; j < 3; j++) TN[i][j] = T(0);
+            }
 #pragma unroll
             for (int i = 0; i < 3; i++) {
 #pragma unroll
                 for (int j = 0; j < 3; j++) {
-                    const T tn = T(2) * nh[i] * q[j] + s2 * (Bm[i][j] - nh[i] * v[j]);
                     const T pa = ((i == j) ? ia : T(0)) - ih[i] * ih[j] * ia;
                     const T pb = ((i == j) ? ib : T(0)) - rh[i] * rh[j] * ib;
                     const T qpa = pa - nh[i] * m[j];
                     // product rule with dS: dS/dX_{k-1} = -ih/2, dS/dX_k = (ih - rh)/2, dS/dX_{k+1} = rh/2
                     Jp[i][j] = S * qpa - T(0.5) * ul[i] * ih[j];
                     Jn[i][j] = S * pb + T(0.5) * ul[i] * rh[j];
-                    Jk[i][j] = S * (tn - pb - qpa) + T(0.5) * ul[i] * (ih[j] - rh[j]);
+                    Jk[i][j] = S * (TN[i][j] - pb - qpa) + T(0.5) * ul[i] * (ih[j] - rh[j]);
                 }
             }
 #pragma unroll
             for (int j = 0; j < 3; j++) { Jk[3][j] = g[j]; Jk[4][j] = T(0); }
         }
     } else {
-        const bool circ = (t == TC);
         const T d[3] = {Xk[0] - r[0], Xk[1] - r[1], Xk[2] - r[2]};
         const T dv[3] = {ih[0] - rh[0], ih[1] - rh[1], ih[2] - rh[2]};
-        // line: e fixed, rows across the line.  circle: e = n x d / |n x d|,
-        // rows <d,n> and (|d|^2 - R^2)/(2R)
-        const T n0 = r[3], n1 = r[4], n2 = r[5];
-        const T w[3] = {n1 * d[2] - n2 * d[1], n2 * d[0] - n0 * d[2], n0 * d[1] - n1 * d[0]};
-        T lw2 = dot3(w, w);
-        valid = valid && (!circ || (lw2 > T(0)));
-        lw2 = (lw2 > T(0)) ? lw2 : T(1);
-        const T iw = drcp(dsqrt(lw2));
-        T e[3];
+        T e[3], go0[3], go1[3], o0, o1, iw = T(0);
+        if (t == TL) {
+            // straight edge: fixed e, rows across the line
 #pragma unroll
-        for (int i = 0; i < 3; i++) e[i] = circ ? w[i] * iw : r[3 + i];
-        const T R = circ ? r[6] : T(1), iR = drcp(R);
-        T go0[3], go1[3];
+            for (int j = 0; j < 3; j++) {
+                e[j] = r[3 + j];
+                go0[j] = r[8 + j];
+                go1[j] = r[11 + j];
+            }
+            o0 = dot3(d, go0);
+            o1 = dot3(d, go1);
+        } else {
+            // circle: e = n x d / |n x d|, rows <d,n> and (|d|^2 - R^2)/(2R)
+            const T w[3] = {r[4] * d[2] - r[5] * d[1], r[5] * d[0] - r[3] * d[2], r[3] * d[1] - r[4] * d[0]};
+            T lw2 = dot3(w, w);
+            valid = valid && (lw2 > T(0));
+            lw2 = (lw2 > T(0)) ? lw2 : T(1);
+            iw = drcp(dsqrt(lw2));
+            const T R = r[6], iR = drcp(R);
 #pragma unroll
-        for (int j = 0; j < 3; j++) {
-            go0[j] = circ ? r[3 + j] : r[8 + j];
-            go1[j] = circ ? d[j] * iR : r[11 + j];
+            for (int j = 0; j < 3; j++) {
+                e[j] = w[j] * iw;
+                go0[j] = r[3 + j];
+                go1[j] = d[j] * iR;
+            }
+            o0 = dot3(d, go0);
+            o1 = (dot3(d, d) - R * R) * (T(0.5) * iR);
         }
-        const T o0 = dot3(d, go0);
-        const T o1 = circ ? (dot3(d, d) - R * R) * (T(0.5) * iR) : dot3(d, go1);
         const T u0 = dot3(dv, e);
         u[0] = S * u0;
         u[1] = T(0);
@@ -184,18 +197,23 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
         u[3] = o0;
         u[4] = o1;
         if (WITH_J) {
-            // circle: dv^T de/dX = (dv x n - <dv,e> (e x n)) / |w|; line: 0
-            const T dxn[3] = {dv[1] * n2 - dv[2] * n1, dv[2] * n0 - dv[0] * n2, dv[0] * n1 - dv[1] * n0};
-            const T exn[3] = {e[1] * n2 - e[2] * n1, e[2] * n0 - e[0] * n2, e[0] * n1 - e[1] * n0};
+            // circle: dv^T de/dX = (dv x n - <dv,e> (e x n)) / |w|; straight edge: 0
+            T dvE[3] = {T(0), T(0), T(0)};
+            if (t == TC) {
+                const T n0 = r[3], n1 = r[4], n2 = r[5];
+                const T dxn[3] = {dv[1] * n2 - dv[2] * n1, dv[2] * n0 - dv[0] * n2, dv[0] * n1 - dv[1] * n0};
+                const T exn[3] = {e[1] * n2 - e[2] * n1, e[2] * n0 - e[0] * n2, e[0] * n1 - e[1] * n0};
+#pragma unroll
+                for (int j = 0; j < 3; j++) dvE[j] = (dxn[j] - u0 * exn[j]) * iw;
+            }
             const T ei = dot3(e, ih), er = dot3(e, rh);
 #pragma unroll
             for (int j = 0; j < 3; j++) {
-                const T dvE = circ ? (dxn[j] - u0 * exn[j]) * iw : T(0);
                 const T ePa = (e[j] - ei * ih[j]) * ia;
                 const T ePb = (e[j] - er * rh[j]) * ib;
                 Jp[0][j] = -S * ePa - T(0.5) * u0 * ih[j];
                 Jn[0][j] = -S * ePb + T(0.5) * u0 * rh[j];
-                Jk[0][j] = S * (ePa + ePb + dvE) + T(0.5) * u0 * (ih[j] - rh[j]);
+                Jk[0][j] = S * (ePa + ePb + dvE[j]) + T(0.5) * u0 * (ih[j] - rh[j]);
 #pragma unroll
                 for (int i = 1; i < 3; i++) { Jp[i][j] = T(0); Jn[i][j] = T(0); Jk[i][j] = T(0); }
                 Jk[3][j] = go0[j];

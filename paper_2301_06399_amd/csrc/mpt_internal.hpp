@@ -46,7 +46,7 @@ struct OutDevC {
 };
 
 struct OptsDev {
-    int init, max_iter, max_iter32, polish_steps, fallback, plateau_win;
+    int init, max_iter, max_iter32, max_iter_fb, polish_steps, fallback, plateau_win;
     double plateau_frac, tol_step, tol_res, tau_root, lambda0, tol_step32, tol_res32, tau_root32, polish_gate;
 };
 
@@ -68,7 +68,9 @@ struct KParams {
 
 void launch_pack(const double *raw, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c, hipStream_t st);
 void launch_zero(int *p, int n, hipStream_t st);
-void launch_bin(const BatchDev &b, const OutDev &out, int n_all, int *cnt, int *cursor, int *perm, hipStream_t st);
+int bin_key_count();
+void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
+                hipStream_t st);
 const void *lm_kernel(int mode, int order, bool lds);
 void launch_lm(int mode, int order, bool lds, size_t lds_bytes, const KParams &kp, int grid, int block,
                hipStream_t st);

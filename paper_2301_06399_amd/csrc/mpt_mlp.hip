@@ -46,13 +46,8 @@ __device__ __forceinline__ float gelu_d(float z)
 // one-hot type, then the object in the frame - plane: n, (d - n.TX)/L;
 // straight edge: e, the edge point nearest TX; quadric: anchor, L A, b;
 // circle: centre, normal, R/L - then a present bit.  Unused slots are zero.
-__global__ void k_features(SceneDev s, BatchDev b, const int *__restrict__ rows, int nrows, float *__restrict__ fout,
-                           bf16 *__restrict__ xout)
+__device__ __forceinline__ void row_features(const SceneDev &s, const BatchDev &b, int i, float f[F_IN], double &Lout)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
-    const int i = rows ? rows[r] : r;
-    float f[F_IN];
 #pragma unroll
     for (int j = 0; j < F_IN; j++) f[j] = 0.0f;
     const int ord = b.order[i];
@@ -64,6 +59,7 @@ __global__ void k_features(SceneDev s, BatchDev b, const int *__restrict__ rows,
     double L = sqrt((rx[0] - s.tx[0]) * (rx[0] - s.tx[0]) + (rx[1] - s.tx[1]) * (rx[1] - s.tx[1]) +
                     (rx[2] - s.tx[2]) * (rx[2] - s.tx[2]));
     if (!(L > 0.0) || !isfinite(L)) L = 1.0;
+    Lout = L;
     const double is = 1.0 / L;
     for (int c = 0; c < 3; c++) f[c] = (float)((rx[c] - s.tx[c]) * is);
 #pragma unroll
@@ -103,6 +99,17 @@ __global__ void k_features(SceneDev s, BatchDev b, const int *__restrict__ rows,
         for (int j = 0; j < 12; j++) f[base + 4 + j] = p[j];
         f[base + 16] = 1.0f;
     }
+}
+
+__global__ void k_features(SceneDev s, BatchDev b, const int *__restrict__ rows, int nrows, float *__restrict__ fout,
+                           bf16 *__restrict__ xout)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const int i = rows ? rows[r] : r;
+    float f[F_IN];
+    double L;
+    row_features(s, b, i, f, L);
 #pragma unroll
     for (int j = 0; j < F_IN; j++) {
         const bf16 h = f2bf(f[j]);
@@ -349,6 +356,127 @@ __global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restr
         x[(size_t)j * b.n + i] = (j < 3 * ord) ? s.tx[j % 3] + L * (double)Y[(size_t)i * F_OUTP + j] : 0.0;
 }
 
+// ------------------------------------------------------------------ fused inference
+// One block = 64 paths: features -> three hidden layers -> output layer ->
+// world points, activations kept in LDS (two ping-pong buffers of
+// 64 x 256 BF16 with a 4-element row pad), weights read from L2.  Each of the
+// 4 waves computes 64 rows x 64 columns of a hidden layer as 2 x 2 MFMA tiles.
+constexpr int FR = 64, FLD = HID + 4;
+constexpr size_t OW1_ = 0, OB1_ = OW1_ + (size_t)HID * F_IN, OW2_ = OB1_ + HID, OB2_ = OW2_ + (size_t)HID * HID,
+                 OW3_ = OB2_ + HID, OB3_ = OW3_ + (size_t)HID * HID, OW4_ = OB3_ + HID,
+                 OB4_ = OW4_ + (size_t)F_OUTP * HID;
+
+__device__ __forceinline__ short4_t lds4(const bf16 *p)
+{
+    short4_t v;
+    const uint2 u = *reinterpret_cast<const uint2 *>(p);
+    v[0] = (short)(u.x & 0xffff);
+    v[1] = (short)(u.x >> 16);
+    v[2] = (short)(u.y & 0xffff);
+    v[3] = (short)(u.y >> 16);
+    return v;
+}
+
+// out[FR][FLD] = GELU(in[FR][K] W^T + b) for this wave's 64 columns
+template <int K>
+__device__ __forceinline__ void fused_layer(const bf16 *in, bf16 *out, const bf16 *__restrict__ W,
+                                            const float *__restrict__ bias, int wave, int lane)
+{
+    float16_t acc[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+        for (int ct = 0; ct < 2; ct++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[rt][ct][v] = 0.0f;
+    const int col0 = 64 * wave;
+    const int kq = 4 * (lane >> 5);
+#pragma unroll 4
+    for (int ks = 0; ks < K; ks += 8) {
+        short4_t a[2], bb[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++) a[rt] = lds4(in + (32 * rt + (lane & 31)) * FLD + ks + kq);
+#pragma unroll
+        for (int ct = 0; ct < 2; ct++) bb[ct] = lds4(W + (size_t)(col0 + 32 * ct + (lane & 31)) * K + ks + kq);
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+            for (int ct = 0; ct < 2; ct++)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[rt], bb[ct], acc[rt][ct], 0, 0, 0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+        for (int ct = 0; ct < 2; ct++) {
+            const int col = col0 + 32 * ct + (lane & 31);
+            const float bc = bias[col];
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int row = 32 * rt + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                out[row * FLD + col] = f2bf(gelu(acc[rt][ct][v] + bc));
+            }
+        }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, int nrows, const bf16 *__restrict__ wb,
+                                                    const float *__restrict__ w, double *__restrict__ x)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16 *bufA = reinterpret_cast<bf16 *>(smem);
+    bf16 *bufB = bufA + FR * FLD;
+    double *Ls = reinterpret_cast<double *>(bufB + FR * FLD);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row0 = blockIdx.x * FR;
+    if (tid < FR) {
+        float f[F_IN];
+        double L = 1.0;
+        const int i = row0 + tid;
+        if (i < nrows) row_features(s, b, i, f, L);
+        else
+            for (int j = 0; j < F_IN; j++) f[j] = 0.0f;
+        Ls[tid] = L;
+        for (int j = 0; j < F_IN; j++) bufA[tid * FLD + j] = f2bf(f[j]);
+    }
+    __syncthreads();
+    fused_layer<F_IN>(bufA, bufB, wb + OW1_, w + OB1_, wave, lane);
+    __syncthreads();
+    fused_layer<HID>(bufB, bufA, wb + OW2_, w + OB2_, wave, lane);
+    __syncthreads();
+    fused_layer<HID>(bufA, bufB, wb + OW3_, w + OB3_, wave, lane);
+    __syncthreads();
+    // output layer: waves 0 and 1 take 32 rows each; columns 16..31 are padding
+    if (wave < 2) {
+        float16_t acc;
+#pragma unroll
+        for (int v = 0; v < 16; v++) acc[v] = 0.0f;
+        const int kq = 4 * (lane >> 5);
+        const int n = lane & 31;
+#pragma unroll 4
+        for (int ks = 0; ks < HID; ks += 8) {
+            const short4_t a = lds4(bufB + (32 * wave + (lane & 31)) * FLD + ks + kq);
+            short4_t bb;
+            if (n < F_OUTP) {
+                bb = lds4(wb + OW4_ + (size_t)n * HID + ks + kq);
+            } else {
+                bb[0] = bb[1] = bb[2] = bb[3] = 0;
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
+        }
+        const int col = lane & 31;
+        if (col < F_OUT) {
+            const float bc = w[OB4_ + col];
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int r = 32 * wave + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                const int i = row0 + r;
+                if (i >= nrows) continue;
+                const int ord = b.order[i];
+                x[(size_t)col * b.n + i] = (col < 3 * ord) ? s.tx[col % 3] + Ls[r] * (double)(acc[v] + bc) : 0.0;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ state
 // Parameter layout (FP32 master, one flat array): W1 [256][96], b1 [256],
 // W2 [256][256], b2, W3 [256][256], b3, W4 [16][256] (row 15 unused, kept
@@ -524,7 +652,20 @@ mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, do
 {
     if (!mlp_ready(m)) return MPT_E_NO_MODEL;
     if (b.n == 0) return MPT_OK;
-    // chunks of at most 1M rows bound the activation workspace
+    static_assert(OW4_ == OW4 && OB4_ == OB4, "parameter layout");
+    const size_t lds = (size_t)2 * FR * FLD * sizeof(bf16) + FR * sizeof(double);
+    hipFuncSetAttribute((const void *)k_mlp_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const unsigned g = (unsigned)((b.n + FR - 1) / FR);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(256), lds, st, s, b, (int)b.n, m->wb, m->w, x_out);
+    return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
+}
+
+// Unfused forward through the GEMM kernels (the path training uses), kept
+// as a check of the fused kernel.
+mpt_status mlp_predict_unfused(MlpState *m, const SceneDev &s, const BatchDev &b, double *x_out, hipStream_t st)
+{
+    if (!mlp_ready(m)) return MPT_E_NO_MODEL;
+    if (b.n == 0) return MPT_OK;
     const int64_t chunk = 1 << 20;
     if (ensure_ws(m, (size_t)(b.n < chunk ? b.n : chunk), false)) return MPT_E_NOMEM;
     for (int64_t c0 = 0; c0 < b.n; c0 += chunk) {
@@ -534,12 +675,9 @@ mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, do
         v.rx_index = b.rx_index + c0;
         v.order = b.order + c0;
         v.prim = b.prim + c0;
-        // k_features / k_decode index prim as prim[k * n + i]: keep n, shift i
         hipLaunchKernelGGL(k_features, dim3((nr + 127) / 128), dim3(128), 0, st, s, v, nullptr, nr, nullptr, m->X);
         forward(m, nr, false, st);
         hipLaunchKernelGGL(k_decode, dim3((nr + 255) / 256), dim3(256), 0, st, s, v, nr, m->Y, x_out + c0);
-        // k_decode writes x[j * v.n + i]: with v.n = b.n and x_out + c0 the
-        // component-major layout of the whole batch is kept
     }
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
 }

@@ -87,17 +87,32 @@ __device__ inline int valid_order(const BatchDev &b, int64_t i, int n_all)
     return bad ? -1 : ord;
 }
 
-// Binning: each block owns a contiguous range of solves, counts its orders in
-// LDS and touches the global counters once per order.
+// Binning by (order, sequence of primitive types): solves of one order are
+// grouped, and within an order by the base-4 code of their type sequence, so
+// the lanes of a wave mostly follow one type path (no divergence between
+// reflection and diffraction code).  Key = kKeyBase[order] + code.
 constexpr int kBinBlock = 256;
 constexpr int kBinItems = 8;  // solves per thread
+constexpr int kNumKeys = 4 + 16 + 64 + 256 + 1024;
+__device__ __constant__ int kKeyBase[kMaxN + 1] = {0, 0, 4, 20, 84, 340};
 
-__global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out, int n_all, int *__restrict__ cnt)
+__device__ inline int bin_key(const BatchDev &b, int64_t i, int ord, int a, int bb, int c)
 {
-    __shared__ int loc[kMaxN];
-    if (threadIdx.x < kMaxN) loc[threadIdx.x] = 0;
+    int code = 0, mul = 1;
+    for (int k = 0; k < kMaxN; k++)
+        if (k < ord) {
+            code += prim_type(b.prim[(size_t)k * b.n + i], a, bb, c) * mul;
+            mul *= 4;
+        }
+    return kKeyBase[ord] + code;
+}
+
+__global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out, int n_all, int n_pl, int n_pl_ln,
+                                                          int n_pl_ln_q, int *__restrict__ key_cnt)
+{
+    __shared__ int loc[kNumKeys];
+    for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock) loc[k] = 0;
     __syncthreads();
-    int mine[kMaxN] = {0, 0, 0, 0, 0};
     const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
@@ -111,18 +126,44 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out,
             if (out.stage)
                 for (int q = 0; q < 3; q++) out.stage[(size_t)q * b.n + i] = 0;
         } else {
-#pragma unroll
-            for (int k = 0; k < kMaxN; k++) mine[k] += (ord == k + 1);
+            atomicAdd(&loc[bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q)], 1);
         }
     }
-#pragma unroll
-    for (int k = 0; k < kMaxN; k++) {
-        int v = mine[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (__lane_id() == 0 && v) atomicAdd(&loc[k], v);
-    }
     __syncthreads();
-    if (threadIdx.x < kMaxN && loc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], loc[threadIdx.x]);
+    for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock)
+        if (loc[k]) atomicAdd(&key_cnt[k], loc[k]);
+}
+
+// One block: exclusive scan of the key counts -> key offsets; per-order
+// totals -> bin counts (the bins of the LM kernels are the orders).
+__global__ void __launch_bounds__(1024) k_bin_offsets(const int *__restrict__ key_cnt, int *__restrict__ key_off,
+                                                       int *__restrict__ bin_cnt)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (kNumKeys + 1023) / 1024;
+    const int lo = t * per, hi = min(lo + per, kNumKeys);
+    int sum = 0;
+    for (int k = lo; k < hi; k++) sum += key_cnt[k];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int v = (t >= d) ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = (t == 0) ? 0 : part[t - 1];
+    for (int k = lo; k < hi; k++) {
+        key_off[k] = run;
+        run += key_cnt[k];
+    }
+    if (t < kMaxN) {
+        int c = 0;
+        const int kb = kKeyBase[t + 1], ke = (t + 1 < kMaxN) ? kKeyBase[t + 2] : kNumKeys;
+        for (int k = kb; k < ke; k++) c += key_cnt[k];
+        bin_cnt[t] = c;
+    }
 }
 
 __device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
@@ -132,53 +173,31 @@ __device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
     return off;
 }
 
-__global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all, const int *__restrict__ cnt,
-                                                            int *__restrict__ cursor, int *__restrict__ perm)
+__global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all, int n_pl, int n_pl_ln, int n_pl_ln_q,
+                                                            const int *__restrict__ key_off,
+                                                            int *__restrict__ key_cursor, int *__restrict__ perm)
 {
-    // pass 1: per-wave counts of each order over the block's range
-    __shared__ int wc[kBinBlock / 64][kMaxN];
-    __shared__ int bbase[kMaxN];
-    const int w = threadIdx.x >> 6, lane = __lane_id();
+    __shared__ int loc[kNumKeys];
+    __shared__ int gbase[kNumKeys];
+    for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock) loc[k] = 0;
+    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
-    int ordv[kBinItems];
-    int mine[kMaxN] = {0, 0, 0, 0, 0};
+    int key[kBinItems], rank[kBinItems];
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
-        ordv[j] = (i < b.n) ? valid_order(b, i, n_all) : -1;
-#pragma unroll
-        for (int k = 0; k < kMaxN; k++) mine[k] += (ordv[j] == k + 1);
-    }
-#pragma unroll
-    for (int k = 0; k < kMaxN; k++) {
-        int v = mine[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) wc[w][k] = v;
+        const int ord = (i < b.n) ? valid_order(b, i, n_all) : -1;
+        key[j] = (ord > 0) ? bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q) : -1;
+        rank[j] = (key[j] >= 0) ? atomicAdd(&loc[key[j]], 1) : 0;
     }
     __syncthreads();
-    if (threadIdx.x < kMaxN) {
-        int t = 0;
-        for (int q = 0; q < kBinBlock / 64; q++) t += wc[q][threadIdx.x];
-        bbase[threadIdx.x] = t ? atomicAdd(&cursor[threadIdx.x], t) : 0;
-    }
+    for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock)
+        gbase[k] = loc[k] ? key_off[k] + atomicAdd(&key_cursor[k], loc[k]) : 0;
     __syncthreads();
-    // pass 2: slots = bin offset + block base + earlier waves + earlier lanes
-    int run[kMaxN];
-#pragma unroll
-    for (int k = 0; k < kMaxN; k++) {
-        int pre = 0;
-        for (int q = 0; q < w; q++) pre += wc[q][k];
-        run[k] = bin_offset(cnt, k + 1) + bbase[k] + pre;
-    }
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
-#pragma unroll
-        for (int k = 0; k < kMaxN; k++) {
-            const uint64_t m = __ballot(ordv[j] == k + 1);
-            if (ordv[j] == k + 1) perm[run[k] + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int)i;
-            run[k] += (int)__popcll(m);
-        }
+        if (key[j] >= 0) perm[gbase[key[j]] + rank[j]] = (int)i;
     }
 }
 
@@ -351,7 +370,7 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
         o.tol_res = (T)kp.o.tol_res32;
         o.tau_root = (T)kp.o.tau_root32;  // an FP32 point this close is taken for a root
     } else {
-        o.max_iter = kp.o.max_iter;
+        o.max_iter = (MODE == MODE_FALLBACK64) ? kp.o.max_iter_fb : kp.o.max_iter;
         o.tol_step = (T)kp.o.tol_step;
         o.tol_res = (T)kp.o.tol_res;
         o.tau_root = (T)kp.o.tau_root;
@@ -398,7 +417,8 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                         p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
                     }
                     bool ok = true;
-                    const int init = (MODE == MODE_FALLBACK64) ? INIT_LINE : kp.o.init;
+                    // the fallback restarts from the FP32 end point (already root-like)
+                    const int init = (MODE == MODE_FALLBACK64) ? INIT_USER : kp.o.init;
                     if (init == INIT_LINE) {
 #pragma unroll
                         for (int k = 0; k < N; k++) {
@@ -409,7 +429,9 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                             project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
                         }
                     } else {
-                        const double *x0 = (init == INIT_USER) ? kp.b.x0 : kp.x0_learned;
+                        const double *x0 = (MODE == MODE_FALLBACK64) ? kp.out.x
+                                           : (init == INIT_USER)     ? kp.b.x0
+                                                                     : kp.x0_learned;
 #pragma unroll
                         for (int j = 0; j < 3 * N; j++) {
                             X0[j] = x0[(size_t)j * kp.b.n + sid];
@@ -552,6 +574,8 @@ __device__ __forceinline__ const typename ModeT<MODE>::T *stage_scene(const KPar
 template <int MODE, bool LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_lm(KParams kp)
 {
+    const int *cnt = (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
+    if (cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4] == 0) return;  // nothing to solve: skip the staging
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     // long paths first so that the short ones fill the tail
     lm_bin<MODE, 5>(kp, rec);
@@ -566,6 +590,7 @@ template <int MODE, int N, bool LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<MODE, N>::W, Occ<MODE, N>::W)))
 k_lm_one(KParams kp)
 {
+    if (((MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt)[N - 1] == 0) return;
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     lm_bin<MODE, N>(kp, rec);
 }
@@ -804,12 +829,20 @@ void launch_zero(int *p, int n, hipStream_t st)
     hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
 }
 
-void launch_bin(const BatchDev &b, const OutDev &out, int n_all, int *cnt, int *cursor, int *perm, hipStream_t st)
+int bin_key_count() { return kNumKeys; }
+
+// keys: [3][kNumKeys] ints (counts, offsets, cursors), zeroed by the caller
+void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
+                hipStream_t st)
 {
     if (b.n == 0) return;
     const unsigned g = (unsigned)((b.n + kBinBlock * kBinItems - 1) / (kBinBlock * kBinItems));
-    hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kBinBlock), 0, st, b, out, n_all, cnt);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), 0, st, b, n_all, cnt, cursor, perm);
+    int *kcnt = keys, *koff = keys + kNumKeys, *kcur = keys + 2 * kNumKeys;
+    hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kBinBlock), 0, st, b, out, s.n_all, s.n_pl, s.n_pl_ln, s.n_pl_ln_q,
+                       kcnt);
+    hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, kcnt, koff, bin_cnt);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), 0, st, b, s.n_all, s.n_pl, s.n_pl_ln, s.n_pl_ln_q,
+                       koff, kcur, perm);
 }
 
 template <int MODE, bool LDS>

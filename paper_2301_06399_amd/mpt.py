@@ -45,7 +45,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("init", C.c_int32), ("max_iter", C.c_int32),
                 ("max_iter32", C.c_int32), ("polish_steps", C.c_int32), ("fallback", C.c_int32),
                 ("plateau_win", C.c_int32), ("sched", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
-                ("graph", C.c_int32),
+                ("max_iter_fb", C.c_int32), ("graph", C.c_int32),
                 ("plateau_frac", C.c_double), ("tol_step", C.c_double), ("tol_res", C.c_double),
                 ("tau_root", C.c_double), ("lambda0", C.c_double), ("tol_step32", C.c_double),
                 ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double)]
@@ -60,7 +60,7 @@ EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt
            "mpt_scene_upload", "mpt_default_opts", "mpt_solve_batch", "mpt_accept", "mpt_mlp_init",
            "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings",
            "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
-           "mpt_gemm_bf16_check"]
+           "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused"]
 
 _lib = None
 
@@ -94,10 +94,12 @@ def load_library(path: str = LIB_PATH):
     L.mpt_gemm_bf16_check.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int32, vp, C.c_int32, vp,
                                       C.c_int32]
     L.mpt_mlp_predict.argtypes = [vp, C.POINTER(BatchDesc), vp]
+    L.mpt_mlp_predict_unfused.argtypes = [vp, C.POINTER(BatchDesc), vp]
     L.mpt_mlp_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.mpt_mlp_load.argtypes = [vp, vp, C.c_size_t]
     L.mpt_last_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_flops_per_iter.argtypes = [C.c_int, vp, vp]
+    L.mpt_last_lm_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_autotune.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut),
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     for f in EXPORTS:
@@ -290,6 +292,12 @@ class Context:
         self._check(self.L.mpt_last_timings(self.h, ms), "mpt_last_timings")
         return {"bin": ms[0], "learned": ms[1], "lm": ms[2], "polish": ms[3], "fallback": ms[4]}
 
+    def lm_timings(self):
+        """Per-order kernel durations (ms) of the last per-order LM pass."""
+        ms = (C.c_float * 5)()
+        self._check(self.L.mpt_last_lm_timings(self.h, ms), "mpt_last_lm_timings")
+        return [ms[i] for i in range(5)]
+
     # ---------------------------------------------------------------- network
     def mlp_init(self, seed: int = 0):
         self._enter()
@@ -346,6 +354,16 @@ class Context:
         self._leave()
         self._check(rc, "mpt_gemm_bf16_check")
         return Cm
+
+    def mlp_predict_unfused(self, dbatch: DeviceBatch, x_out=None):
+        x_out = x_out if x_out is not None else self.torch.zeros((15, dbatch.n), dtype=self.torch.float64,
+                                                                 device="cuda")
+        bd = dbatch.desc()
+        self._enter()
+        rc = self.L.mpt_mlp_predict_unfused(self.h, C.byref(bd), _ptr(x_out))
+        self._leave()
+        self._check(rc, "mpt_mlp_predict_unfused")
+        return x_out
 
     def mlp_predict(self, dbatch: DeviceBatch, x_out=None):
         x_out = x_out if x_out is not None else self.torch.empty((15, dbatch.n), dtype=self.torch.float64,

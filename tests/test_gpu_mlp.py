@@ -129,3 +129,28 @@ def test_learned_start_keeps_parity(ctx):
     for i in np.where(both)[0]:
         n = hb.order[i]
         assert np.abs(g["x"][:3 * n, i] - orc["x"][:3 * n, i]).max() <= 1e-6
+
+
+def test_fused_inference_matches_layerwise_and_reference(ctx):
+    """The fused inference kernel (activations in LDS) against the layer-by-
+    layer GEMM path and the FP64 reference with BF16 rounding."""
+    from paper_2301_06399_amd import learned, mpt
+    sc, b = W.training_batch(3, n_rx=64, per_rx=64)
+    learned.train(ctx, sc, b, steps=100, batch_rows=1024)
+    ctx.upload_scene(sc)
+    sb = b.subset(np.arange(b.n - 29))  # ragged last block
+    db = mpt.DeviceBatch(sb)
+    xf = ctx.mlp_predict(db).cpu().numpy()
+    xu = ctx.mlp_predict_unfused(db).cpu().numpy()
+    hdr, w, _, _ = R.parse_blob(ctx.mlp_save())
+    P = R.unpack(w)
+    X = R.features(sc, sb)
+    _, _, Y = R.loss_and_grad(P, X, np.zeros((sb.n, 16)), np.ones((sb.n, 16)), rounding=True)
+    L = np.linalg.norm(sb.rx[sb.rx_index] - sc.tx, axis=1)
+    for i in range(0, sb.n, 7):
+        n = sb.order[i]
+        yf = (xf[:3 * n, i] - np.tile(sc.tx, n)) / L[i]
+        yu = (xu[:3 * n, i] - np.tile(sc.tx, n)) / L[i]
+        assert np.abs(yf - yu).max() <= 2e-2 * (1 + np.abs(yu).max())
+        assert np.abs(yf - Y[i, :3 * n]).max() <= 2e-2 * (1 + np.abs(Y[i, :3 * n]).max())
+        assert (xf[3 * n:, i] == 0).all()
