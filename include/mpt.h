@@ -123,7 +123,11 @@ typedef struct {
 } mpt_batch_desc;
 
 enum { MPT_FP64_PLAIN = 0, MPT_FP32_POLISH64 = 1 };
-enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2 };
+/* MPT_INIT_LEARNED: the network's points for the paths that touch a curved
+ * object (paraboloid or circle), the straight-line start for the others
+ * (planes and straight edges converge from any start, paper Sec. III-B);
+ * MPT_INIT_LEARNED_ALL: the network's points for every path. */
+enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2, MPT_INIT_LEARNED_ALL = 3 };
 enum { MPT_FALLBACK_NONE = 0, MPT_FALLBACK_GPU_FP64 = 1 };
 /* MPT_SCHED_PERSISTENT: one persistent launch runs every order's bin;
  * MPT_SCHED_PER_ORDER: one persistent launch per order, with its own

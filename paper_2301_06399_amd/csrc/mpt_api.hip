@@ -52,7 +52,8 @@ struct mpt_ctx {
     std::vector<unsigned char> gkey;
 };
 
-// bin_cnt 0..4, (5..9 unused), head 10..19, pol_cnt 20..24, fb_cnt 25..29, then 3 x 1364 key counters
+// bin_cnt 0..4, (5..9 unused), head 10..19, pol_cnt 20..24, fb_cnt 25..29, curved rows 30, then
+// 3 x 1364 key counters
 static const int kCounters = 32 + 3 * 1364;
 
 static mpt_status fail(mpt_ctx *c, mpt_status st, const char *fmt, ...)
@@ -373,10 +374,10 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
         return fail(c, MPT_E_INVALID_ARG, "null output array");
     if (opts->precision != MPT_FP64_PLAIN && opts->precision != MPT_FP32_POLISH64)
         return fail(c, MPT_E_UNSUPPORTED, "precision %d", opts->precision);
-    if (opts->init < MPT_INIT_LINE || opts->init > MPT_INIT_LEARNED)
+    if (opts->init < MPT_INIT_LINE || opts->init > MPT_INIT_LEARNED_ALL)
         return fail(c, MPT_E_UNSUPPORTED, "init %d", opts->init);
     if (opts->init == MPT_INIT_USER && b->n > 0 && !b->x0) return fail(c, MPT_E_INVALID_ARG, "user start without x0");
-    if (opts->init == MPT_INIT_LEARNED && !mlp_ready(c->mlp))
+    if ((opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL) && !mlp_ready(c->mlp))
         return fail(c, MPT_E_NO_MODEL, "learned start requested but no network initialised");
     if (opts->max_iter < 0 || opts->max_iter32 < 0 || opts->max_iter_fb < 0 || opts->polish_steps < 0 ||
         opts->plateau_win < 0)
@@ -400,8 +401,8 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     if (st) return st;
     const int64_t n = b->n;
     if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 3 * (size_t)(n > 0 ? n : 1), sizeof(int)))) return st;
-    if (opts->init == MPT_INIT_LEARNED &&
-        (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * (size_t)(n > 0 ? n : 1), sizeof(double))))
+    const bool learned = opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL;
+    if (learned && (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * (size_t)(n > 0 ? n : 1), sizeof(double))))
         return st;
     int *ctr = c->ws;
     KParams kp{};
@@ -437,8 +438,17 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     launch_zero(ctr, kCounters, s);
     launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, s);
     if (timed) hipEventRecord(c->ev[1], s);
-    if (opts->init == MPT_INIT_LEARNED && n > 0) {
-        if ((st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s))) return fail(c, st, "network forward failed");
+    if (learned && n > 0) {
+        if (opts->init == MPT_INIT_LEARNED) {
+            // the network serves only the paths with a curved object: list
+            // them (the polish list is free until the FP32 pass) and predict
+            int *rows = (int *)kp.pol_list, *count = ctr + 30;
+            launch_curved_rows(bd, c->s, rows, count, s);
+            st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s, rows, count);
+        } else {
+            st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s);
+        }
+        if (st) return fail(c, st, "network forward failed");
     }
     if (timed) hipEventRecord(c->ev[2], s);
     const int mode = (opts->precision == MPT_FP64_PLAIN) ? MODE_PLAIN64 : MODE_FP32;

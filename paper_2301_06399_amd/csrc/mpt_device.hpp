@@ -43,7 +43,50 @@ __host__ __device__ __forceinline__ int prim_type(int id, int a, int b, int c)
 
 __host__ __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
 __host__ __device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
-template <typename T> __host__ __device__ __forceinline__ T drcp(T x) { return T(1) / x; }
+
+// Reciprocal and reciprocal square root.  FP32: the hardware approximations
+// (about 1 ulp; the FP32 pass only has to land close to a root, the FP64
+// polish restores full accuracy).  FP64: the hardware seed refined by
+// Newton steps (each doubles the number of correct bits) to within a few ulp,
+// instead of the IEEE division and square-root sequences.
+__host__ __device__ __forceinline__ float drcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ double drcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * (2.0 - x * r);
+    r = r * (2.0 - x * r);
+    return r;
+#else
+    return 1.0 / x;
+#endif
+}
+__host__ __device__ __forceinline__ float drsqrt(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+__host__ __device__ __forceinline__ double drsqrt(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * (1.5 - 0.5 * x * r * r);
+    r = r * (1.5 - 0.5 * x * r * r);
+    return r;
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
 
 template <typename T>
 __host__ __device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -75,8 +118,8 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
     valid = valid && (la2 > T(0)) && (lb2 > T(0));
     la2 = (la2 > T(0)) ? la2 : T(1);
     lb2 = (lb2 > T(0)) ? lb2 : T(1);
-    const T la = dsqrt(la2), lb = dsqrt(lb2);
-    const T ia = drcp(la), ib = drcp(lb);
+    const T ia = drsqrt(la2), ib = drsqrt(lb2);
+    const T la = la2 * ia, lb = lb2 * ib;
     T ih[3], rh[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) { ih[i] = a[i] * ia; rh[i] = b[i] * ib; }
@@ -103,7 +146,7 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
         T lg2 = dot3(g, g);
         valid = valid && (lg2 > T(0));
         lg2 = (lg2 > T(0)) ? lg2 : T(1);
-        const T ig = drcp(dsqrt(lg2));
+        const T ig = drsqrt(lg2);
         const T nh[3] = {g[0] * ig, g[1] * ig, g[2] * ig};
         const T s = dot3(ih, nh);
         T ul[3];
@@ -179,7 +222,7 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
             T lw2 = dot3(w, w);
             valid = valid && (lw2 > T(0));
             lw2 = (lw2 > T(0)) ? lw2 : T(1);
-            iw = drcp(dsqrt(lw2));
+            iw = drsqrt(lw2);
             const T R = r[6], iR = drcp(R);
 #pragma unroll
             for (int j = 0; j < 3; j++) {
@@ -350,7 +393,8 @@ __host__ __device__ __forceinline__ bool assemble(const SceneT<T> &sc, const Pat
     return ok;
 }
 
-// In-place banded Cholesky of the packed lower band; false if not SPD.
+// In-place banded Cholesky of the packed lower band; false if not SPD.  The
+// diagonal slots receive the INVERSE of L's diagonal (the solves multiply).
 template <typename T, int N>
 __host__ __device__ __forceinline__ bool chol_band(T *A)
 {
@@ -363,9 +407,8 @@ __host__ __device__ __forceinline__ bool chol_band(T *A)
         for (int k = 0; k < j; k++)
             if (Band<N>::in(j, k)) d -= A[Band<N>::at(j, k)] * A[Band<N>::at(j, k)];
         ok = ok && (d > T(0));
-        d = dsqrt(d > T(0) ? d : T(1));
-        A[Band<N>::at(j, j)] = d;
-        const T inv = drcp(d);
+        const T inv = drsqrt(d > T(0) ? d : T(1));
+        A[Band<N>::at(j, j)] = inv;
 #pragma unroll
         for (int i = j + 1; i < M; i++) {
             if (!Band<N>::in(i, j)) continue;
@@ -379,7 +422,7 @@ __host__ __device__ __forceinline__ bool chol_band(T *A)
     return ok;
 }
 
-// Solve L L^T x = b in place (b -> x).
+// Solve L L^T x = b in place (b -> x); the diagonal holds 1 / L_ii.
 template <typename T, int N>
 __host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
 {
@@ -390,7 +433,7 @@ __host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
 #pragma unroll
         for (int k = 0; k < i; k++)
             if (Band<N>::in(i, k)) v -= L[Band<N>::at(i, k)] * b[k];
-        b[i] = v / L[Band<N>::at(i, i)];
+        b[i] = v * L[Band<N>::at(i, i)];
     }
 #pragma unroll
     for (int i = M - 1; i >= 0; i--) {
@@ -398,7 +441,7 @@ __host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
 #pragma unroll
         for (int k = i + 1; k < M; k++)
             if (Band<N>::in(k, i)) v -= L[Band<N>::at(k, i)] * b[k];
-        b[i] = v / L[Band<N>::at(i, i)];
+        b[i] = v * L[Band<N>::at(i, i)];
     }
 }
 

@@ -43,5 +43,9 @@ inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
 inline Cnt fmax(Cnt a, Cnt b) { return Cnt(a.v > b.v ? a.v : b.v); }
 inline Cnt fabs(Cnt a) { return Cnt(a.v < 0 ? -a.v : a.v); }
 inline Cnt dsqrt(Cnt a) { if (nz(a)) tally().sqrt++; return Cnt(::sqrt(a.v)); }
+// 1/x and 1/sqrt(x) count as what they are algorithmically: a division and a
+// square root plus a division
+inline Cnt drcp(Cnt a) { if (nz(a)) tally().div++; return Cnt(1.0 / a.v); }
+inline Cnt drsqrt(Cnt a) { if (nz(a)) tally().sqrt++, tally().div++; return Cnt(1.0 / ::sqrt(a.v)); }
 
 }  // namespace mpt

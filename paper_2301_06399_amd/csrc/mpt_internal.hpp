@@ -7,7 +7,7 @@
 namespace mpt {
 
 enum : int { MODE_PLAIN64 = 0, MODE_FP32 = 1, MODE_FALLBACK64 = 2 };
-enum : int { INIT_LINE = 0, INIT_USER = 1, INIT_LEARNED = 2 };
+enum : int { INIT_LINE = 0, INIT_USER = 1, INIT_LEARNED = 2, INIT_LEARNED_ALL = 3 };
 // transient status codes between the FP32 pass and the polish
 enum : int { ROUTE_POLISH_FB = 254, ROUTE_POLISH_MAXIT = 253, ROUTE_POLISH_LOCALMIN = 252 };
 
@@ -75,6 +75,7 @@ const void *lm_kernel(int mode, int order, bool lds);
 void launch_lm(int mode, int order, bool lds, size_t lds_bytes, const KParams &kp, int grid, int block,
                hipStream_t st);
 const void *polish_kernel();
+void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st);
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
                    uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st);

@@ -26,19 +26,38 @@ constexpr int SLOT = 17;  // per-interaction feature slot: one-hot 4, params 12,
 
 // ------------------------------------------------------------------ bf16
 typedef uint16_t bf16;
-__device__ __forceinline__ bf16 f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    return (bf16)(u >> 16);
-}
+// hardware round-to-nearest-even conversion (v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ bf16 f2bf(float f) { return __builtin_bit_cast(bf16, (__bf16)f); }
 __device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU in its erf form, with erf from Abramowitz & Stegun 7.1.26 (Hastings'
+// rational approximation, |error| <= 1.5e-7, far below BF16 resolution):
+// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+// t = 1 / (1 + p x), x >= 0, odd extension.  One exponential serves both
+// GELU(z) = z Phi(z) and GELU'(z) = Phi(z) + z phi(z).
+__device__ __forceinline__ void gelu_both(float z, float &g, float &gd)
+{
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+    const float poly =
+        t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+    const float e = __expf(-x * x);  // exp(-z^2/2)
+    const float ea = 1.0f - poly * e;
+    const float phi_c = 0.5f * (1.0f + (z < 0.0f ? -ea : ea));
+    g = z * phi_c;
+    gd = phi_c + z * e * 0.39894228040143268f;
+}
+__device__ __forceinline__ float gelu(float z)
+{
+    float g, gd;
+    gelu_both(z, g, gd);
+    return g;
+}
 __device__ __forceinline__ float gelu_d(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    float g, gd;
+    gelu_both(z, g, gd);
+    return gd;
 }
 
 // ------------------------------------------------------------------ features
@@ -366,22 +385,17 @@ constexpr size_t OW1_ = 0, OB1_ = OW1_ + (size_t)HID * F_IN, OW2_ = OB1_ + HID, 
                  OW3_ = OB2_ + HID, OB3_ = OW3_ + (size_t)HID * HID, OW4_ = OB3_ + HID,
                  OB4_ = OW4_ + (size_t)F_OUTP * HID;
 
-__device__ __forceinline__ short4_t lds4(const bf16 *p)
-{
-    short4_t v;
-    const uint2 u = *reinterpret_cast<const uint2 *>(p);
-    v[0] = (short)(u.x & 0xffff);
-    v[1] = (short)(u.x >> 16);
-    v[2] = (short)(u.y & 0xffff);
-    v[3] = (short)(u.y >> 16);
-    return v;
-}
+__device__ __forceinline__ short4_t lds4(const bf16 *p) { return *reinterpret_cast<const short4_t *>(p); }
 
-// out[FR][FLD] = GELU(in[FR][K] W^T + b) for this wave's 64 columns
+// out[FR][FLD] = GELU(in[FR][K] W^T + b) for this wave's 64 columns.
+// The weight fragments of the next 32-deep k group are loaded while the 16
+// MFMAs of the current group run (register double buffer).
 template <int K>
 __device__ __forceinline__ void fused_layer(const bf16 *in, bf16 *out, const bf16 *__restrict__ W,
                                             const float *__restrict__ bias, int wave, int lane)
 {
+    constexpr int G = 4, NG = K / (8 * G);
+    static_assert(K % (8 * G) == 0, "K must be a multiple of 32");
     float16_t acc[2][2];
 #pragma unroll
     for (int rt = 0; rt < 2; rt++)
@@ -391,18 +405,38 @@ __device__ __forceinline__ void fused_layer(const bf16 *in, bf16 *out, const bf1
             for (int v = 0; v < 16; v++) acc[rt][ct][v] = 0.0f;
     const int col0 = 64 * wave;
     const int kq = 4 * (lane >> 5);
-#pragma unroll 4
-    for (int ks = 0; ks < K; ks += 8) {
-        short4_t a[2], bb[2];
+    const bf16 *wrow[2] = {W + (size_t)(col0 + (lane & 31)) * K + kq, W + (size_t)(col0 + 32 + (lane & 31)) * K + kq};
+    short4_t bcur[G][2], bnxt[G][2];
 #pragma unroll
-        for (int rt = 0; rt < 2; rt++) a[rt] = lds4(in + (32 * rt + (lane & 31)) * FLD + ks + kq);
+    for (int j = 0; j < G; j++)
 #pragma unroll
-        for (int ct = 0; ct < 2; ct++) bb[ct] = lds4(W + (size_t)(col0 + 32 * ct + (lane & 31)) * K + ks + kq);
+        for (int ct = 0; ct < 2; ct++) bcur[j][ct] = lds4(wrow[ct] + 8 * j);
 #pragma unroll
-        for (int rt = 0; rt < 2; rt++)
+    for (int g = 0; g < NG; g++) {
+        if (g + 1 < NG) {
 #pragma unroll
-            for (int ct = 0; ct < 2; ct++)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[rt], bb[ct], acc[rt][ct], 0, 0, 0);
+            for (int j = 0; j < G; j++)
+#pragma unroll
+                for (int ct = 0; ct < 2; ct++) bnxt[j][ct] = lds4(wrow[ct] + 32 * (g + 1) + 8 * j);
+        }
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const int ks = 32 * g + 8 * j;
+            short4_t a[2];
+#pragma unroll
+            for (int rt = 0; rt < 2; rt++) a[rt] = lds4(in + (32 * rt + (lane & 31)) * FLD + ks + kq);
+#pragma unroll
+            for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+                for (int ct = 0; ct < 2; ct++)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[rt], bcur[j][ct], acc[rt][ct], 0, 0, 0);
+        }
+        if (g + 1 < NG) {
+#pragma unroll
+            for (int j = 0; j < G; j++)
+#pragma unroll
+                for (int ct = 0; ct < 2; ct++) bcur[j][ct] = bnxt[j][ct];
+        }
     }
 #pragma unroll
     for (int rt = 0; rt < 2; rt++)
@@ -418,23 +452,30 @@ __device__ __forceinline__ void fused_layer(const bf16 *in, bf16 *out, const bf1
         }
 }
 
-__global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, int nrows, const bf16 *__restrict__ wb,
+// rows (may be null): solve ids to predict, *count of them; else all b.n
+__global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, const int *__restrict__ rows,
+                                                    const int *__restrict__ count, const bf16 *__restrict__ wb,
                                                     const float *__restrict__ w, double *__restrict__ x)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     bf16 *bufA = reinterpret_cast<bf16 *>(smem);
     bf16 *bufB = bufA + FR * FLD;
     double *Ls = reinterpret_cast<double *>(bufB + FR * FLD);
+    int *ids = reinterpret_cast<int *>(Ls + FR);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row0 = blockIdx.x * FR;
+    const int nrows = rows ? *count : (int)b.n;
+    if (row0 >= nrows) return;  // block-uniform
     if (tid < FR) {
         float f[F_IN];
         double L = 1.0;
-        const int i = row0 + tid;
-        if (i < nrows) row_features(s, b, i, f, L);
+        const int r = row0 + tid;
+        const int i = (r < nrows) ? (rows ? rows[r] : r) : -1;
+        if (i >= 0) row_features(s, b, i, f, L);
         else
             for (int j = 0; j < F_IN; j++) f[j] = 0.0f;
         Ls[tid] = L;
+        ids[tid] = i;
         for (int j = 0; j < F_IN; j++) bufA[tid * FLD + j] = f2bf(f[j]);
     }
     __syncthreads();
@@ -468,8 +509,8 @@ __global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, int n
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int r = 32 * wave + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-                const int i = row0 + r;
-                if (i >= nrows) continue;
+                const int i = ids[r];
+                if (i < 0) continue;
                 const int ord = b.order[i];
                 x[(size_t)col * b.n + i] = (col < 3 * ord) ? s.tx[col % 3] + Ls[r] * (double)(acc[v] + bc) : 0.0;
             }
@@ -648,15 +689,16 @@ static void forward(MlpState *m, int nrows, bool train, hipStream_t st)
     gemm<false, true, EPI_BIAS>(nrows, F_OUTP, HID, m->H3, HID, m->wb + OW4, HID, e4, 1, st);
 }
 
-mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, double *x_out, hipStream_t st)
+mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, double *x_out, hipStream_t st,
+                           const int *rows, const int *count)
 {
     if (!mlp_ready(m)) return MPT_E_NO_MODEL;
     if (b.n == 0) return MPT_OK;
     static_assert(OW4_ == OW4 && OB4_ == OB4, "parameter layout");
-    const size_t lds = (size_t)2 * FR * FLD * sizeof(bf16) + FR * sizeof(double);
+    const size_t lds = (size_t)2 * FR * FLD * sizeof(bf16) + FR * (sizeof(double) + sizeof(int));
     hipFuncSetAttribute((const void *)k_mlp_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const unsigned g = (unsigned)((b.n + FR - 1) / FR);
-    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(256), lds, st, s, b, (int)b.n, m->wb, m->w, x_out);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(256), lds, st, s, b, rows, count, m->wb, m->w, x_out);
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
 }
 

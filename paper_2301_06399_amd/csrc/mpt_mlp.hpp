@@ -12,7 +12,8 @@ struct MlpState;
 bool mlp_ready(const MlpState *m);
 void mlp_free(MlpState *m);
 mpt_status mlp_init(MlpState **m, uint64_t seed, hipStream_t st);
-mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, double *x_out, hipStream_t st);
+mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, double *x_out, hipStream_t st,
+                           const int *rows = nullptr, const int *count = nullptr);
 mpt_status mlp_predict_unfused(MlpState *m, const SceneDev &s, const BatchDev &b, double *x_out, hipStream_t st);
 mpt_status mlp_train_step_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,
                               const double *target, const uint8_t *use, float lr, float *d_loss, hipStream_t st);

@@ -201,6 +201,27 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
     }
 }
 
+// Ids of the valid solves whose list holds a quadric or a circle (the paths
+// the learned start serves), appended with wave-aggregated atomics.
+__global__ void __launch_bounds__(256) k_curved_rows(BatchDev b, int n_all, int n_pl_ln, int *__restrict__ rows,
+                                                      int *__restrict__ count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool mine = false;
+    if (i < b.n) {
+        const int ord = valid_order(b, i, n_all);
+        for (int k = 0; k < kMaxN; k++)
+            if (k < ord) mine = mine || b.prim[(size_t)k * b.n + i] >= n_pl_ln;
+    }
+    const uint64_t m = __ballot(mine);
+    if (!m) return;
+    const int leader = (int)__builtin_ctzll(m);
+    int base = 0;
+    if (__lane_id() == leader) base = atomicAdd(count, (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (mine) rows[base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull))] = (int)i;
+}
+
 // ------------------------------------------------------------------ init
 // Projection of a point onto an object (FP64 world): the straight-line start
 // of each interaction is the projection of the point k/(N+1) of the way from
@@ -419,7 +440,12 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                     bool ok = true;
                     // the fallback restarts from the FP32 end point (already root-like)
                     const int init = (MODE == MODE_FALLBACK64) ? INIT_USER : kp.o.init;
-                    if (init == INIT_LINE) {
+                    // the learned start serves the paths with a curved object;
+                    // planes and straight edges keep the straight-line start
+                    bool use_net = (init == INIT_LEARNED_ALL);
+                    if (init == INIT_LEARNED)
+                        for (int k = 0; k < N; k++) use_net = use_net || p.ty[k] == TQ || p.ty[k] == TC;
+                    if (init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
 #pragma unroll
                         for (int k = 0; k < N; k++) {
                             const double a = (double)(k + 1) / (double)(N + 1);
@@ -437,7 +463,7 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                             X0[j] = x0[(size_t)j * kp.b.n + sid];
                             ok = ok && isfinite(X0[j]);
                         }
-                        if (ok && init == INIT_LEARNED) {
+                        if (ok && use_net) {
                             // the network's points are projected onto their objects
 #pragma unroll
                             for (int k = 0; k < N; k++) {
@@ -877,6 +903,13 @@ void launch_lm(int mode, int order, bool lds, size_t lds_bytes, const KParams &k
 }
 
 const void *polish_kernel() { return (const void *)k_polish; }
+
+void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st)
+{
+    if (b.n == 0) return;
+    hipLaunchKernelGGL(k_curved_rows, dim3((unsigned)((b.n + 255) / 256)), dim3(256), 0, st, b, s.n_all, s.n_pl_ln,
+                       rows, count);
+}
 
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
 {

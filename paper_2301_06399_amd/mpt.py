@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_
 CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7)
 FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
-INIT_LINE, INIT_USER, INIT_LEARNED = 0, 1, 2
+INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL = 0, 1, 2, 3
 SCHED_PER_ORDER, SCHED_PERSISTENT, SCHED_AUTO = 0, 1, 2
 
 

@@ -104,15 +104,15 @@ def test_training_lowers_loss_and_blob_roundtrip(ctx):
 
 
 def test_learned_start_keeps_parity(ctx):
-    """Started from the network's points, the solver still reaches the
-    oracle's accept flags on planes and edges (unique roots)."""
+    """Started from the network's points (for every path), the solver still
+    reaches the oracle's accept flags on planes and edges (unique roots)."""
     from paper_2301_06399_amd import learned, mpt
     sc, tb = W.training_batch(2, n_rx=512, per_rx=64)
     learned.train(ctx, sc, tb, steps=400, batch_rows=4096)
     hsc, hb = W.training_batch(2, n_rx=128, per_rx=64, stream="heldout")
     ctx.upload_scene(hsc)
     db = mpt.DeviceBatch(hb)
-    out = ctx.solve(db, mpt.default_opts(init=mpt.INIT_LEARNED))
+    out = ctx.solve(db, mpt.default_opts(init=mpt.INIT_LEARNED_ALL))
     acc, idx, k = ctx.accept(db, out)
     g = out.numpy()
     gacc = acc.cpu().numpy()
@@ -154,3 +154,27 @@ def test_fused_inference_matches_layerwise_and_reference(ctx):
         assert np.abs(yf - yu).max() <= 2e-2 * (1 + np.abs(yu).max())
         assert np.abs(yf - Y[i, :3 * n]).max() <= 2e-2 * (1 + np.abs(Y[i, :3 * n]).max())
         assert (xf[3 * n:, i] == 0).all()
+
+
+def test_learned_start_on_curved_paths(ctx):
+    """On paraboloids and circles the learned start serves every path: each
+    GPU-accepted root is a root the oracle confirms from the GPU point, and
+    the roots the oracle's straight-line run finds are mostly found too."""
+    from paper_2301_06399_amd import learned, mpt
+    sc, tb = W.training_batch(3, n_rx=512, per_rx=64)
+    learned.train(ctx, sc, tb, steps=400, batch_rows=4096)
+    hsc, hb = W.training_batch(3, n_rx=48, per_rx=64, stream="heldout")
+    ctx.upload_scene(hsc)
+    db = mpt.DeviceBatch(hb)
+    out = ctx.solve(db, mpt.default_opts(init=mpt.INIT_LEARNED))
+    acc, idx, k = ctx.accept(db, out)
+    g = out.numpy()
+    gacc = acc.cpu().numpy()
+    orc = O.solve_batch(hsc, hb)
+    oacc = O.accept_batch(hsc, hb, orc["x"], orc["status"])
+    for i in np.where(gacc == 1)[0]:
+        n = hb.order[i]
+        X, c, it, st = O.solve_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], x0=g["x"][:3 * n, i])
+        assert st == O.CONVERGED and np.abs(X - g["x"][:3 * n, i]).max() <= 1e-6
+        assert O.accept_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], X, st)
+    assert ((gacc == 0) & (oacc == 1)).sum() <= 0.1 * max(1, oacc.sum())
