@@ -126,8 +126,16 @@ enum { MPT_FP64_PLAIN = 0, MPT_FP32_POLISH64 = 1 };
 /* MPT_INIT_LEARNED: the network's points for the paths that touch a curved
  * object (paraboloid or circle), the straight-line start for the others
  * (planes and straight edges converge from any start, paper Sec. III-B);
- * MPT_INIT_LEARNED_ALL: the network's points for every path. */
-enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2, MPT_INIT_LEARNED_ALL = 3 };
+ * MPT_INIT_LEARNED_ALL: the network's points for every path.
+ * MPT_INIT_RANDOM: the random start of Alg. 1 - each interaction's point is
+ * the projection onto its object of a point drawn uniformly in the scene box
+ * (aabb_lo..aabb_hi).  Draw number c = 15 i + 3 k + axis of solve i,
+ * interaction k is the (c+1)-th output of SplitMix64 (Steele, Lea & Flood,
+ * OOPSLA 2014) started from state opts.seed, as u = (output >> 11) * 2^-53.
+ * Restarts are further solves of the same candidate (other i) or other
+ * seeds. */
+enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2, MPT_INIT_LEARNED_ALL = 3,
+       MPT_INIT_RANDOM = 4 };
 enum { MPT_FALLBACK_NONE = 0, MPT_FALLBACK_GPU_FP64 = 1 };
 /* MPT_SCHED_PERSISTENT: one persistent launch runs every order's bin;
  * MPT_SCHED_PER_ORDER: one persistent launch per order, with its own
@@ -164,6 +172,7 @@ typedef struct {
                               its FP64 polish fails, FP64 re-solves the path    */
     double polish_gate;    /* 1e-2  FP32 end points with |R|_inf above this are
                               final (no path); below it they are polished       */
+    uint64_t seed;         /* 0     state of the MPT_INIT_RANDOM draws          */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 

@@ -56,6 +56,10 @@ def lib():
         L.orc_residual.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp]
         L.orc_residual.restype = C.c_int
         L.orc_init_line.argtypes = [vp, vp, C.c_int, vp, vp]
+        L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_splitmix64.restype = C.c_uint64
+        L.orc_init_random.argtypes = [vp, C.c_uint64, i64, C.c_int, vp, vp]
+        L.orc_init_random_batch.argtypes = [vp, C.c_uint64, i64, vp, vp, vp]
         L.orc_solve_one.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, vp]
         L.orc_solve_one.restype = C.c_int
         L.orc_accept_one.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int, d, d]
@@ -115,6 +119,28 @@ def init_line(scene, rx, ids):
     X = np.zeros(3 * len(ids))
     lib().orc_init_line(os_.ref, _p(np.ascontiguousarray(rx, dtype=np.float64)), len(ids), _p(ids), _p(X))
     return X
+
+
+def splitmix64(seed, c):
+    """Output number c+1 of SplitMix64 started from state `seed`."""
+    return int(lib().orc_splitmix64(seed & (2**64 - 1), c))
+
+
+def init_random(scene, seed, sid, ids):
+    """Random start of solve `sid`: projections of box-uniform points."""
+    os_ = scene if isinstance(scene, OracleScene) else OracleScene(scene)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    X = np.zeros(3 * len(ids))
+    lib().orc_init_random(os_.ref, seed, sid, len(ids), _p(ids), _p(X))
+    return X
+
+
+def init_random_batch(scene, batch, seed):
+    """[15, n] random starts of every solve of a workloads.Batch."""
+    os_ = OracleScene(scene)
+    x = np.zeros((15, batch.n))
+    lib().orc_init_random_batch(os_.ref, seed, batch.n, _p(batch.order), _p(batch.prim), _p(x))
+    return x
 
 
 def solve_one(scene, rx, ids, x0=None, opts=None):

@@ -311,6 +311,59 @@ void orc_init_line(const orc_scene *s, const double rx[3], int n, const int32_t 
     }
 }
 
+/* Random start of Alg. 1 (the paper draws X_0 at random).  Reading: each
+ * interaction's point is the projection onto its object of a point drawn
+ * uniformly in the scene box, the same projection the straight-line start
+ * uses.  The draws come from SplitMix64 (Steele, Lea & Flood, "Fast
+ * splittable pseudorandom number generators", OOPSLA 2014) used as a counter
+ * generator: value c (0-based) is the generator's (c+1)-th output from state
+ * `seed`; a uniform double is its top 53 bits times 2^-53.  Solve i,
+ * interaction k, axis j uses counter 15 i + 3 k + j. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1u) * 0x9e3779b97f4a7c15ull;  /* state after c+1 steps */
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static double uniform01(uint64_t seed, uint64_t c)
+{
+    return (double)(orc_splitmix64(seed, c) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+void orc_init_random(const orc_scene *s, uint64_t seed, int64_t sid, int n, const int32_t *ids, double *X)
+{
+    for (int k = 0; k < n; k++) {
+        const double *rec;
+        int t = prim_type(s, ids[k], &rec);
+        double P[3];
+        for (int j = 0; j < 3; j++) {
+            double u = uniform01(seed, 15u * (uint64_t)sid + 3u * (uint64_t)k + (uint64_t)j);
+            P[j] = s->lo[j] + u * (s->hi[j] - s->lo[j]);
+        }
+        project(t, rec, P, X + 3 * k);
+    }
+}
+
+void orc_init_random_batch(const orc_scene *s, uint64_t seed, int64_t nb, const int32_t *order,
+                           const int32_t *prim, double *x)
+{
+    for (int64_t i = 0; i < nb; i++) {
+        int n = order[i];
+        double X[15] = {0};
+        int32_t ids[5] = {-1, -1, -1, -1, -1};
+        int ok = n >= 1 && n <= 5;
+        for (int k = 0; ok && k < n; k++) {
+            const double *rec;
+            ids[k] = prim[(size_t)k * nb + i];
+            ok = prim_type(s, ids[k], &rec) >= 0;
+        }
+        if (ok) orc_init_random(s, seed, i, n, ids, X);
+        for (int j = 0; j < 15; j++) x[(size_t)j * nb + i] = (ok && j < 3 * n) ? X[j] : 0.0;
+    }
+}
+
 /* ------------------------------------------------------------ LM */
 /* In-place Cholesky of the dense SPD matrix M (lower triangle); 0 on success. */
 static int cholesky(double *M, int m)

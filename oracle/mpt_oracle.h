@@ -28,7 +28,9 @@
  *  - the minimiser is Levenberg-Marquardt with Marquardt's diagonal scaling
  *    (the paper only says "gradient descent");
  *  - initial points: each object's projection of the point k/(n+1) of the
- *    way along the TX -> RX segment, or caller-given points.
+ *    way along the TX -> RX segment, or of a point drawn uniformly in the
+ *    scene box (the random start of Alg. 1, SplitMix64 counter draws), or
+ *    caller-given points.
  *
  * Parity status: every function here is pinned by the CPU tests (closed
  * forms of the image method and of the Keller point, the paper's Fig. 5
@@ -77,6 +79,16 @@ int orc_residual(const orc_scene *s, const double rx[3], int n, const int32_t *i
 
 /* Straight-line initial points (3n values). */
 void orc_init_line(const orc_scene *s, const double rx[3], int n, const int32_t *ids, double *X);
+
+/* Random initial points (3n values) of solve `sid`: each object's projection
+ * of a point uniform in the scene box, drawn with SplitMix64 from `seed`
+ * (counter 15 sid + 3 k + axis).  orc_splitmix64 is the generator's output
+ * number c+1 from state seed.  The batch form writes [15][nb], zero past
+ * 3 order (and for invalid paths). */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t c);
+void orc_init_random(const orc_scene *s, uint64_t seed, int64_t sid, int n, const int32_t *ids, double *X);
+void orc_init_random_batch(const orc_scene *s, uint64_t seed, int64_t nb, const int32_t *order,
+                           const int32_t *prim, double *x);
 
 /* One solve; x0 may be NULL (straight-line start).  Returns the status. */
 int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,

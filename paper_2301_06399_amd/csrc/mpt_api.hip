@@ -238,6 +238,8 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
         const double h = 10.0 * 0.5 * (d->aabb_hi[i] - d->aabb_lo[i]) + 1.0;
         s.glo[i] = ctr - h;
         s.ghi[i] = ctr + h;
+        s.lo[i] = d->aabb_lo[i];
+        s.hi[i] = d->aabb_hi[i];
     }
     launch_pack(c->raw, s, np, nl, nq, nc, c->stream);
     HIPCHK(c, hipGetLastError());
@@ -272,6 +274,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->tol_res32 = 1e-5;
     o->tau_root32 = 1e-4;
     o->polish_gate = 1e-2;
+    o->seed = 0;
 }
 
 static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)
@@ -374,7 +377,7 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
         return fail(c, MPT_E_INVALID_ARG, "null output array");
     if (opts->precision != MPT_FP64_PLAIN && opts->precision != MPT_FP32_POLISH64)
         return fail(c, MPT_E_UNSUPPORTED, "precision %d", opts->precision);
-    if (opts->init < MPT_INIT_LINE || opts->init > MPT_INIT_LEARNED_ALL)
+    if (opts->init < MPT_INIT_LINE || opts->init > MPT_INIT_RANDOM)
         return fail(c, MPT_E_UNSUPPORTED, "init %d", opts->init);
     if (opts->init == MPT_INIT_USER && b->n > 0 && !b->x0) return fail(c, MPT_E_INVALID_ARG, "user start without x0");
     if ((opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL) && !mlp_ready(c->mlp))
@@ -425,6 +428,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.o.tol_res32 = opts->tol_res32;
     kp.o.tau_root32 = opts->tau_root32;
     kp.o.polish_gate = opts->polish_gate;
+    kp.o.seed = opts->seed;
     kp.x0_learned = c->x0l;
     kp.bin_cnt = ctr + 0;
     kp.head = ctr + 10;
@@ -569,17 +573,17 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     float best = 1e30f;
     Cand bc = cands[0];
     for (const Cand &cd : cands) {
-        float tot = 0.0f;
-        for (int rep = 0; rep < 3; rep++) {
+        // the fastest of five timed runs after one warm-up run
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 6; rep++) {
             if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv))) return st;
             HIPCHK(c, hipEventSynchronize(c->ev[5]));
             float ms = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[5]));  // LM, polish and fallback passes
-            if (rep > 0) tot += ms;  // the first run warms up
+            if (rep > 0 && ms < tmin) tmin = ms;
         }
-        if (tot < best) best = tot, bc = cd;
+        if (tmin < best) best = tmin, bc = cd;
     }
-    best *= 0.5f;
     const int bs = bc.sched, bb = bc.block;
     bool found = false;
     for (auto &t : c->tune)

@@ -7,7 +7,7 @@
 namespace mpt {
 
 enum : int { MODE_PLAIN64 = 0, MODE_FP32 = 1, MODE_FALLBACK64 = 2 };
-enum : int { INIT_LINE = 0, INIT_USER = 1, INIT_LEARNED = 2, INIT_LEARNED_ALL = 3 };
+enum : int { INIT_LINE = 0, INIT_USER = 1, INIT_LEARNED = 2, INIT_LEARNED_ALL = 3, INIT_RANDOM = 4 };
 // transient status codes between the FP32 pass and the polish
 enum : int { ROUTE_POLISH_FB = 254, ROUTE_POLISH_MAXIT = 253, ROUTE_POLISH_LOCALMIN = 252 };
 
@@ -17,7 +17,8 @@ struct SceneDev {
     const float *rec32;   // [n_all][kRec] TX-local frame
     int n_pl, n_pl_ln, n_pl_ln_q, n_all;
     double tx[3];
-    double glo[3], ghi[3];
+    double glo[3], ghi[3];  // guard box
+    double lo[3], hi[3];    // scene box (random starts)
 };
 
 struct BatchDev {
@@ -48,6 +49,7 @@ struct OutDevC {
 struct OptsDev {
     int init, max_iter, max_iter32, max_iter_fb, polish_steps, fallback, plateau_win;
     double plateau_frac, tol_step, tol_res, tau_root, lambda0, tol_step32, tol_res32, tau_root32, polish_gate;
+    uint64_t seed;
 };
 
 // Everything a solver kernel needs, passed by value.

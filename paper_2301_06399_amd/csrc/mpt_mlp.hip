@@ -324,11 +324,13 @@ __global__ void k_loss_final(const float *__restrict__ part, const int *__restri
         for (int q = 0; q < nblk; q++) t += part[q], c += cnt_part[q];
         tot_s = t;
         tot_c = c;
-        if (loss) *loss = c ? t / c : 0.0f;
+        if (loss && blockIdx.x == 0) *loss = c ? t / c : 0.0f;
     }
     __syncthreads();
+    // every block sums the few partials itself and scales its own slice
     const float sc = tot_c ? 2.0f / tot_c : 0.0f;
-    for (int i = threadIdx.x; i < nrows * F_OUTP; i += blockDim.x) dY[i] = f2bf(sc * diff[i]);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrows * F_OUTP; i += gridDim.x * blockDim.x)
+        dY[i] = f2bf(sc * diff[i]);
 }
 
 // ------------------------------------------------------------------ Adam
@@ -734,7 +736,7 @@ static mpt_status grad_dev(MlpState *m, const SceneDev &s, const BatchDev &b, co
     const int nblk = (nrows + 255) / 256;
     hipLaunchKernelGGL(k_loss_partial, dim3(nblk), dim3(256), 0, st, s, b, rows, nrows, m->Y, target, use, m->diff,
                        m->lpart, m->lcnt);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, m->lpart, m->lcnt, nblk, m->diff, nrows, m->dY,
+    hipLaunchKernelGGL(k_loss_final, dim3(std::min(256, (nrows * F_OUTP + 255) / 256)), dim3(256), 0, st, m->lpart, m->lcnt, nblk, m->diff, nrows, m->dY,
                        d_loss);
     // split-K partial buffer for the weight gradients
     const int splits = nrows >= 4096 ? 16 : (nrows >= 1024 ? 4 : 1);

@@ -92,7 +92,7 @@ __device__ inline int valid_order(const BatchDev &b, int64_t i, int n_all)
 // the lanes of a wave mostly follow one type path (no divergence between
 // reflection and diffraction code).  Key = kKeyBase[order] + code.
 constexpr int kBinBlock = 256;
-constexpr int kBinItems = 8;  // solves per thread
+constexpr int kBinItems = 2;  // solves per thread (enough blocks to fill the chip)
 constexpr int kNumKeys = 4 + 16 + 64 + 256 + 1024;
 __device__ __constant__ int kKeyBase[kMaxN + 1] = {0, 0, 4, 20, 84, 340};
 
@@ -126,6 +126,12 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out,
             if (out.stage)
                 for (int q = 0; q < 3; q++) out.stage[(size_t)q * b.n + i] = 0;
         } else {
+            // the rows past the path's own points and the later stages'
+            // iteration counts are zero: written here, coalesced, so that the
+            // solver kernels store only what a path produces
+            for (int q = 3 * ord; q < 3 * kMaxN; q++) out.x[(size_t)q * b.n + i] = 0.0;
+            if (out.stage)
+                for (int q = 1; q < 3; q++) out.stage[(size_t)q * b.n + i] = 0;
             atomicAdd(&loc[bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q)], 1);
         }
     }
@@ -140,11 +146,16 @@ __global__ void __launch_bounds__(1024) k_bin_offsets(const int *__restrict__ ke
                                                        int *__restrict__ bin_cnt)
 {
     __shared__ int part[1024];
+    __shared__ int offs[kNumKeys + 1];
     const int t = threadIdx.x;
     const int per = (kNumKeys + 1023) / 1024;
     const int lo = t * per, hi = min(lo + per, kNumKeys);
-    int sum = 0;
-    for (int k = lo; k < hi; k++) sum += key_cnt[k];
+    int c[per], sum = 0;
+#pragma unroll
+    for (int q = 0; q < per; q++) {
+        c[q] = (lo + q < hi) ? key_cnt[lo + q] : 0;
+        sum += c[q];
+    }
     part[t] = sum;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
@@ -154,15 +165,19 @@ __global__ void __launch_bounds__(1024) k_bin_offsets(const int *__restrict__ ke
         __syncthreads();
     }
     int run = (t == 0) ? 0 : part[t - 1];
-    for (int k = lo; k < hi; k++) {
-        key_off[k] = run;
-        run += key_cnt[k];
-    }
+#pragma unroll
+    for (int q = 0; q < per; q++)
+        if (lo + q < hi) {
+            key_off[lo + q] = run;
+            offs[lo + q] = run;
+            run += c[q];
+        }
+    if (t == 1023) offs[kNumKeys] = part[1023];
+    __syncthreads();
+    // per-order totals: the keys of one order are contiguous
     if (t < kMaxN) {
-        int c = 0;
         const int kb = kKeyBase[t + 1], ke = (t + 1 < kMaxN) ? kKeyBase[t + 2] : kNumKeys;
-        for (int k = kb; k < ke; k++) c += key_cnt[k];
-        bin_cnt[t] = c;
+        bin_cnt[t] = offs[ke] - offs[kb];
     }
 }
 
@@ -223,9 +238,22 @@ __global__ void __launch_bounds__(256) k_curved_rows(BatchDev b, int n_all, int 
 }
 
 // ------------------------------------------------------------------ init
+// Uniform double in [0,1) from draw number c of SplitMix64 (Steele, Lea &
+// Flood, OOPSLA 2014) started from state `seed`: the state after c+1
+// golden-ratio increments, mixed, top 53 bits.
+__device__ inline double splitmix_uniform(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1u) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
 // Projection of a point onto an object (FP64 world): the straight-line start
 // of each interaction is the projection of the point k/(N+1) of the way from
-// TX to RX.
+// TX to RX; the random start (Alg. 1) projects a point uniform in the scene
+// box, draw 15 i + 3 k + axis for solve i.
 __device__ inline void project(int t, const double *r, const double *P, double *X)
 {
     if (t == TP) {
@@ -445,7 +473,18 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                     bool use_net = (init == INIT_LEARNED_ALL);
                     if (init == INIT_LEARNED)
                         for (int k = 0; k < N; k++) use_net = use_net || p.ty[k] == TQ || p.ty[k] == TC;
-                    if (init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
+                    if (init == INIT_RANDOM) {
+#pragma unroll
+                        for (int k = 0; k < N; k++) {
+                            double P[3];
+#pragma unroll
+                            for (int i = 0; i < 3; i++) {
+                                const double u = splitmix_uniform(kp.o.seed, 15u * (uint64_t)sid + 3u * k + i);
+                                P[i] = kp.s.lo[i] + u * (kp.s.hi[i] - kp.s.lo[i]);
+                            }
+                            project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
+                        }
+                    } else if (init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
 #pragma unroll
                         for (int k = 0; k < N; k++) {
                             const double a = (double)(k + 1) / (double)(N + 1);
@@ -491,15 +530,11 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                     if (st0 != ST_RUNNING) {
                         // finished before the first iteration
 #pragma unroll
-                        for (int j = 0; j < 3 * kMaxN; j++)
-                            kp.out.x[(size_t)j * kp.b.n + sid] = (j < 3 * N && st0 != ST_BAD) ? X0[j < 3 * N ? j : 0] : 0.0;
+                        for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (st0 != ST_BAD) ? X0[j] : 0.0;
                         kp.out.cost[sid] = __builtin_huge_val();
-                        if (MODE != MODE_FALLBACK64) kp.out.iters[sid] = 0;
-                        if (kp.out.stage) {
-                            if (MODE != MODE_FALLBACK64) {
-#pragma unroll
-                                for (int j = 0; j < 3; j++) kp.out.stage[(size_t)j * kp.b.n + sid] = 0;
-                            }
+                        if (MODE != MODE_FALLBACK64) {
+                            kp.out.iters[sid] = 0;
+                            if (kp.out.stage) kp.out.stage[sid] = 0;
                         }
                         kp.out.status[sid] = (uint8_t)(st0 | (MODE == MODE_FALLBACK64 ? 0x80 : 0));
                         active = false;
@@ -520,20 +555,14 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                 const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
                                       MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
 #pragma unroll
-                for (int j = 0; j < 3 * kMaxN; j++)
-                    kp.out.x[(size_t)j * kp.b.n + sid] = (j < 3 * N) ? (double)L.X[j < 3 * N ? j : 0] + sh[j % 3] : 0.0;
+                for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j] + sh[j % 3];
                 kp.out.cost[sid] = (double)L.C;
                 int it = L.it;
                 if (MODE == MODE_FALLBACK64) it += kp.out.iters[sid];
                 kp.out.iters[sid] = it;
                 if (kp.out.stage) {
-                    if (MODE == MODE_FALLBACK64) {
-                        kp.out.stage[(size_t)2 * kp.b.n + sid] = L.it;
-                    } else {
-                        kp.out.stage[sid] = L.it;
-                        kp.out.stage[(size_t)kp.b.n + sid] = 0;
-                        kp.out.stage[(size_t)2 * kp.b.n + sid] = 0;
-                    }
+                    if (MODE == MODE_FALLBACK64) kp.out.stage[(size_t)2 * kp.b.n + sid] = L.it;
+                    else kp.out.stage[sid] = L.it;
                 }
                 int code = st;
                 if (MODE == MODE_FP32) {

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_
 CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7)
 FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
-INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL = 0, 1, 2, 3
+INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL, INIT_RANDOM = 0, 1, 2, 3, 4
 SCHED_PER_ORDER, SCHED_PERSISTENT, SCHED_AUTO = 0, 1, 2
 
 
@@ -48,7 +48,8 @@ class SolveOpts(C.Structure):
                 ("max_iter_fb", C.c_int32), ("graph", C.c_int32),
                 ("plateau_frac", C.c_double), ("tol_step", C.c_double), ("tol_res", C.c_double),
                 ("tau_root", C.c_double), ("lambda0", C.c_double), ("tol_step32", C.c_double),
-                ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double)]
+                ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class SolveOut(C.Structure):

@@ -254,3 +254,31 @@ def test_autotuner_choice_keeps_parity(ctx):
     orc = O.solve_batch(sc, b)
     orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
     compare_planar(sc, b, g, orc_acc, orc)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_random_start_matches_oracle(ctx, prec):
+    """Random start of Alg. 1 (SplitMix64 draws, projections of box points):
+    the oracle solves from its own random starts of the same definition.
+    Planes and straight edges (room and street canyon): flags bitwise equal,
+    points within 1e-6 m.  Curved: GPU roots the oracle did not reach are
+    verified from the GPU point."""
+    from paper_2301_06399_amd import mpt
+    for sc, b in (W.config1(n_rx=128), W.config2(n_rx=128, per_rx=64)):
+        x0 = O.init_random_batch(sc, b, 987654321)
+        orc = O.solve_batch(sc, b, x0=x0)
+        orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
+        g = gpu_solve(ctx, sc, b, precision=prec, init=mpt.INIT_RANDOM, seed=987654321)
+        compare_planar(sc, b, g, orc_acc, orc)
+        assert orc_acc.sum() > 50
+    sc, b = W.config3(n_rx=64, per_rx=64)
+    x0 = O.init_random_batch(sc, b, 42)
+    orc = O.solve_batch(sc, b, x0=x0)
+    orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
+    g = gpu_solve(ctx, sc, b, precision=prec, init=mpt.INIT_RANDOM, seed=42)
+    assert np.mean(g["accept"] == orc_acc) > 0.97
+    verify_extra_roots(sc, b, g, orc_acc)
+    both = (g["accept"] == 1) & (orc_acc == 1)
+    for i in np.where(both)[0]:
+        n = b.order[i]
+        assert O.accept_one(sc, b.rx[b.rx_index[i]], b.prim[:n, i], g["x"][:3 * n, i], O.CONVERGED)

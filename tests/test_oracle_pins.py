@@ -529,3 +529,87 @@ def test_room_counts_and_statuses():
     # a determinism check independent of the thread count
     r1 = O.solve_batch(sc, b, nthreads=1)
     assert np.array_equal(r1["x"], r["x"]) and np.array_equal(r1["status"], r["status"])
+
+
+# ---------------------------------------------------------------- random start (Alg. 1)
+def test_splitmix64_published_outputs():
+    """The counter generator behind the random start is SplitMix64 (Steele,
+    Lea & Flood 2014); started from state 0 its first outputs are the
+    published 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F."""
+    assert [O.splitmix64(0, c) for c in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                       0x06C45D188009454F]
+
+
+def test_random_start_uniform_and_on_objects():
+    """Random start points: the box-uniform draws pass a Kolmogorov-Smirnov
+    test, and each start lies on its (infinite) plane, straight line or
+    circle; one Newton step brings a box point closer to a paraboloid."""
+    from scipy.stats import kstest
+    u = np.array([(O.splitmix64(12345, c) >> 11) * 2.0 ** -53 for c in range(20000)])
+    assert kstest(u, "uniform").pvalue > 1e-3
+    sc, b = W.config1(n_rx=4)
+    seen = 0
+    for i in range(b.n):
+        n = b.order[i]
+        X = O.init_random(sc, 77, i, b.prim[:n, i]).reshape(n, 3)
+        for k in range(n):
+            pid = b.prim[k, i]
+            if pid < len(sc.planes):
+                p = sc.planes[pid]
+                assert abs(p[0:3] @ X[k] - p[3]) < 1e-12 * (1 + abs(p[3]))
+            else:
+                ln = sc.lines[pid - len(sc.planes)]
+                d = X[k] - ln[0:3]
+                assert np.linalg.norm(d - (d @ ln[3:6]) * ln[3:6]) < 1e-12 * (1 + np.linalg.norm(d))
+            seen += 1
+    assert seen > 100
+    sc3, b3 = W.config3(n_rx=2)
+    c0 = len(sc3.planes) + len(sc3.lines) + len(sc3.quadrics)
+    circ = closer = 0
+    for i in range(b3.n):
+        for k in range(b3.order[i]):
+            pid = int(b3.prim[k, i])
+            X = O.init_random(sc3, 5, i, [pid])
+            if pid >= c0:
+                c = sc3.circles[pid - c0]
+                d = X - c[0:3]
+                assert abs(d @ c[3:6]) < 1e-9 and abs(np.linalg.norm(d) - c[6]) < 1e-9
+                circ += 1
+            else:
+                # the box point before projection: same draws, axis by axis
+                P = np.array([sc3.aabb_lo[j] + (O.splitmix64(5, 15 * i + j) >> 11) * 2.0 ** -53 *
+                              (sc3.aabb_hi[j] - sc3.aabb_lo[j]) for j in range(3)])
+                q = sc3.quadrics[pid - len(sc3.planes) - len(sc3.lines)]
+                A = np.array([[q[3], q[4], q[5]], [q[4], q[6], q[7]], [q[5], q[7], q[8]]])
+
+                def f(x):
+                    y = x - q[0:3]
+                    return y @ A @ y + q[9:12] @ y + q[12]
+                closer += abs(f(X)) < abs(f(P))
+    assert circ > 10 and closer > 10
+
+
+def test_random_starts_reach_the_unique_planar_root():
+    """Sec. III-B: with planes only the path is unique and is reached from
+    any start.  From seeded random starts (Alg. 1) every converged solve is
+    the image-method point, a converged solve implies the image-method path
+    exists, and at least 90% of the starts of existing paths find it."""
+    found = conv = 0
+    for order in (1, 2, 3):
+        rng = np.random.default_rng(200 + order)
+        for trial in range(60):
+            planes = [big_plane(unit(rng.normal(size=3)), rng.uniform(-5, 5)) for _ in range(order)]
+            tx, rx = rng.uniform(-3, 3, 3), rng.uniform(-3, 3, 3)
+            sc = W.Scene(tx=tx, planes=np.array(planes), aabb_lo=-10 * np.ones(3), aabb_hi=10 * np.ones(3))
+            ids = np.arange(order)
+            Xim, ts, I = image_method(tx, rx, planes)
+            exists = bool(np.all((ts > 1e-6) & (ts < 1 - 1e-6)))
+            for seed in range(4):
+                X, c, it, st = O.solve_one(sc, rx, ids, x0=O.init_random(sc, seed, trial, ids),
+                                           opts=O.default_opts(400, 0, 1.0))
+                found += exists
+                if st == O.CONVERGED:
+                    assert exists
+                    np.testing.assert_allclose(X.reshape(-1, 3), Xim, atol=1e-9 * (1 + np.abs(Xim).max()))
+                    conv += 1
+    assert found >= 100 and conv >= 0.9 * found
