@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the batched Min-Path-Tracing solve on one MI355X.
 
-One step = one pass of the whole hot path over the street-canyon workload
-(50 boxes, 651 primitives, 4096 receivers x 64 interaction lists of order
-1-3 = 262,144 solves): order binning, [learned start], FP32
-Levenberg-Marquardt, FP64 Gauss-Newton polish, FP64 fallback, FP64
-acceptance test with ordered compaction.  Inputs are resident on the GPU
-before timing starts.  `value` = accepted paths per second.
+One step = one pass of the whole hot path over one batch: order binning,
+[learned start], FP32 Levenberg-Marquardt, FP64 Gauss-Newton polish, FP64
+fallback, FP64 acceptance test with ordered compaction.  Inputs are resident
+on the GPU before timing starts.  `value` = accepted paths per second.
+
+Default workload: the street canyon (50 boxes, 651 primitives, 4096
+receivers x 64 interaction lists of order 1-3 = 262,144 solves).
+--config 1 / 3 / 5 select the room, the curved scene and the multi-
+diffraction stress workload; --config 4 is the learned-start evaluation (one
+network trained on 2 M solver outputs of the street-canyon and curved
+generators, timed on 1 M held-out problems).
 
 Also reported: the plain FP64 solver (P) and FP32+polish without the learned
-start (S) on the same workload, the roofline of the dominant kernel (the
-first LM pass) with its time measured by HIP events on the library's stream,
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+start (S) on the same workload, the roofline of the dominant kernel with its
+time measured by HIP events on the stream it runs on, and the FP64 CPU oracle
+timed on the same workload (or a bounded sample of it).
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import hashlib
 import json
 import os
@@ -27,8 +33,22 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WKEY = {1: "room", 2: "street_canyon", 3: "curved", 5: "stress"}
+WKEY = {1: "room", 2: "street_canyon", 3: "curved", 4: "learned_heldout", 5: "stress"}
+NAMES = {1: "room 10x10x3 m, 6 walls + 2 edges, 256 RX x 64 lists (order 1-2)",
+         2: "street canyon 50 boxes (251 facets + 400 edges), 4096 RX x 64 lists (order 1-3)",
+         3: "curved: 200 paraboloids + 100 circles, 16384 RX x 64 lists (order 1-5)",
+         4: "learned start, held-out: street canyon 8192 RX x 64 (order 1-3) + curved 8192 RX x 64 (order 1-5)",
+         5: "stress: street canyon + 30 paraboloids, 16384 RX x 1024 lists of order 3-5 with >= 2 diffractions"}
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12, "bf16": 2.5e15}
+MLP_FLOPS_PER_ROW = 2 * (96 * 256 + 256 * 256 + 256 * 256 + 256 * 15)
+VARIANT_TEXT = {"L": "learned start (paths with curved objects) + FP32 LM + FP64 polish + fallback",
+                "A": "learned start (every path) + FP32 LM + FP64 polish + fallback",
+                "S": "straight-line start + FP32 LM + FP64 polish + fallback",
+                "P": "plain FP64 LM from the straight-line start"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -56,159 +76,92 @@ def algorithmic_flops(table, order, code, iters, kind):
     return tot
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
-    ap.add_argument("--n-rx", type=int, default=0, help="receivers (0: the configuration's own)")
-    ap.add_argument("--variant", default="auto", choices=["auto", "L", "S", "P"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: about 20 s of work)")
-    ap.add_argument("--train-steps", type=int, default=0, help="network training steps before timing (L)")
-    ap.add_argument("--only-main", action="store_true", help="time only the headline variant")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the tuner: launch choices from MPT_AUTOTUNE_CACHE, else the defaults")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
+def opts_for(mpt, v):
+    if v == "P":
+        return mpt.default_opts(precision=mpt.FP64_PLAIN)
+    if v == "S":
+        return mpt.default_opts(precision=mpt.FP32_POLISH64)
+    if v == "A":
+        return mpt.default_opts(precision=mpt.FP32_POLISH64, init=mpt.INIT_LEARNED_ALL)
+    return mpt.default_opts(precision=mpt.FP32_POLISH64, init=mpt.INIT_LEARNED)
 
-    import torch
-    from paper_2301_06399_amd import mpt
-    from paper_2301_06399_amd import workloads as W
 
-    t0 = time.time()
-    if args.config == 5:
-        scene, batch = W.config5(n_rx=args.n_rx or 1024)
-    elif args.n_rx:
-        scene, batch = W.CONFIGS[args.config](n_rx=args.n_rx)
-    else:
-        scene, batch = W.CONFIGS[args.config]()
-    names = {1: "room 10x10x3 m, 6 walls + 2 edges, 256 RX x 64 lists (order 1-2)",
-             2: "street canyon 50 boxes (251 facets + 400 edges), 4096 RX x 64 lists (order 1-3)",
-             3: "curved: 200 paraboloids + 100 circles, 16384 RX x 64 lists (order 1-5)",
-             5: "stress: street canyon + 30 paraboloids, lists of order 3-5 with >= 2 diffractions"}
-    print(f"# workload generated in {time.time() - t0:.1f}s: {batch.n} solves", file=sys.stderr, flush=True)
+class Runner:
+    """A resident workload on the GPU: batch, outputs and accept buffers."""
 
-    ctx = mpt.Context(0)
-    ctx.upload_scene(scene)
-    db = mpt.DeviceBatch(batch)
-    out = mpt.DeviceOut(batch.n, stages=True)
-    n = batch.n
-    acc = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
-    idx = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
-    cnt = torch.empty(1, dtype=torch.int32, device="cuda")
-    import ctypes as C
+    def __init__(self, torch, mpt, ctx, scene, batch):
+        self.torch, self.mpt, self.ctx, self.scene, self.batch = torch, mpt, ctx, scene, batch
+        self.db = mpt.DeviceBatch(batch)
+        self.out = mpt.DeviceOut(batch.n, stages=True)
+        n = max(batch.n, 1)
+        self.acc = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self.idx = torch.empty(n, dtype=torch.int32, device="cuda")
+        self.cnt = torch.empty(1, dtype=torch.int32, device="cuda")
 
-    learned_ok = False
-    variant = args.variant
-    if variant in ("auto", "L"):
-        try:
-            from paper_2301_06399_amd import learned
-            learned_ok = learned.prepare(ctx, scene, batch, steps=args.train_steps or None)
-        except (ImportError, mpt.MptError) as e:
-            print(f"# learned start unavailable: {e}", file=sys.stderr)
-            learned_ok = False
-        if variant == "L" and not learned_ok:
-            print(json.dumps({"error": "learned start requested but unavailable"}))
-            sys.exit(3)
-        variant = "L" if learned_ok else "S"
-
-    def opts_for(v):
-        if v == "P":
-            return mpt.default_opts(precision=mpt.FP64_PLAIN)
-        if v == "S":
-            return mpt.default_opts(precision=mpt.FP32_POLISH64)
-        return mpt.default_opts(precision=mpt.FP32_POLISH64, init=mpt.INIT_LEARNED)
-
-    def step(o):
-        ctx.solve(db, o, out)
-        bd, od = db.desc(), out.desc()
-        rc = ctx.L.mpt_accept(ctx.h, C.byref(bd), C.byref(od), 1e-9, 1e-6, mpt._ptr(acc), mpt._ptr(idx),
-                              mpt._ptr(cnt), None)
+    def step(self, o):
+        ctx, mpt = self.ctx, self.mpt
+        ctx.solve(self.db, o, self.out)
+        bd, od = self.db.desc(), self.out.desc()
+        rc = ctx.L.mpt_accept(ctx.h, C.byref(bd), C.byref(od), 1e-9, 1e-6, mpt._ptr(self.acc),
+                              mpt._ptr(self.idx), mpt._ptr(self.cnt), None)
         ctx._check(rc, "mpt_accept")
 
-    def timed(v, steps, warmup):
-        o = opts_for(v)
+    def run(self, v, steps, warmup, tune):
+        """Autotune (optional, untimed), then time `steps` steps after
+        `warmup`; stage and per-order durations from the library's events."""
+        torch, ctx, mpt = self.torch, self.ctx, self.mpt
+        o = opts_for(mpt, v)
+        launch = ctx.autotune(self.db, o, self.out) if tune else None
         for _ in range(warmup):
-            step(o)
+            self.step(o)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            step(o)
+            self.step(o)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        k = int(cnt.item())
-        # per-stage durations (events on the library's stream), averaged
-        st = {"bin": 0.0, "learned": 0.0, "lm": 0.0, "polish": 0.0, "fallback": 0.0}
+        k = int(self.cnt.item())
+        st = {"bin": 0.0, "learned": 0.0, "lm": 0.0, "resume": 0.0, "polish": 0.0, "fallback": 0.0}
         per_order = [0.0] * 5
-        reps = min(steps, 10)
+        reps = min(max(steps, 1), 10)
         for _ in range(reps):
-            ctx.solve(db, o, out)
+            ctx.solve(self.db, o, self.out)
             tm = ctx.timings()
             for key in st:
                 st[key] += tm[key] / reps
             try:
-                po = ctx.lm_timings()
-                per_order = [a + b / reps for a, b in zip(per_order, po)]
+                per_order = [a + b / reps for a, b in zip(per_order, ctx.lm_timings())]
             except mpt.MptError:
                 per_order = None
         st["lm_per_order"] = per_order
-        return dt, k, st
-
-    if args.copy_mib:
-        # a plain copy of known size: what the HBM byte counters read for it
-        # calibrates them for the solver kernels
-        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.add(src, 1.0, out=dst)  # one elementwise kernel: reads and writes copy_mib MiB
+        self.step(o)  # leave this variant's outputs and flags in place
         torch.cuda.synchronize()
-        del src, dst
+        r = self.out.numpy()
+        res = {"ms_per_step": dt * 1e3, "accepted": k, "paths_per_s": k / dt, "stage_ms": st,
+               "fallback": int((r["status"] & 0x80).astype(bool).sum()),
+               "iters_mean": float(r["iters"].mean()), "lm_iters_mean": float(r["stage"][0].mean()),
+               "polished": int((r["stage"][1] > 0).sum()), "launch": launch}
+        log(f"# {v}: {dt * 1e3:.3f} ms/step, {k} accepted, {k / dt:.4g} paths/s, LM iters "
+            f"{res['lm_iters_mean']:.2f}, stages { {a: round(b, 4) for a, b in st.items() if a != 'lm_per_order'} }")
+        return res, r
 
-    variants = [variant] if args.only_main else [variant] + [x for x in ("S", "P") if x != variant]
-    # launch choices picked by the autotuner (untimed)
-    tuned = {}
-    for v in variants:
-        tuned[v] = None if args.no_autotune else ctx.autotune(db, opts_for(v), out)
-        print(f"# autotune {v}: {tuned[v]}", file=sys.stderr, flush=True)
+    def flags(self):
+        return self.acc[:self.batch.n].cpu().numpy()
 
-    results = {}
-    for v in variants:
-        steps = args.steps if v == variant else max(5, args.steps // 4)
-        warm = args.warmup if v == variant else 1
-        dt, k, st = timed(v, steps, warm)
-        r = out.numpy()
-        results[v] = {"ms_per_step": dt * 1e3, "accepted": k, "paths_per_s": k / dt, "stage_ms": st,
-                      "fallback": int((r["status"] & 0x80).astype(bool).sum()),
-                      "iters_mean": float(r["iters"].mean()), "lm_iters_mean": float(r["stage"][0].mean()),
-                      "launch": tuned[v],
-                      "_r": r}
-        print(f"# {v}: {dt * 1e3:.3f} ms/step, {k} accepted, {k / dt:.4g} paths/s, stages {st}", file=sys.stderr,
-              flush=True)
 
-    main_r = results[variant]
-    r = main_r.pop("_r") if "_r" in main_r else None
-    # the last out is from the last variant run: recompute the main one's stages
-    step(opts_for(variant))
-    ctx.synchronize()
-    r = out.numpy()
-    for v in results:
-        results[v].pop("_r", None)
-
-    # ---------------- roofline of the dominant kernel (first LM pass)
+def lm_roofline(scene, batch, r, st, prec, cfg, mpt):
+    """Roofline of the dominant solver kernel: algorithmic FLOPs of the first
+    LM pass (iterations actually run in it x FLOPs per iteration of each
+    path's order and types) over its measured duration."""
     table = mpt.flops_table()
     code = type_codes(scene, batch)
-    prec = "fp64" if variant == "P" else "fp32"
+    it1 = r["stage"][0] - r["stage"][3]   # iterations before a straggler was parked
     per_order_flops = []
     for nn in range(1, 6):
         m = batch.order == nn
-        per_order_flops.append(algorithmic_flops(table, batch.order[m], code[m], r["stage"][0][m], "lm"))
+        per_order_flops.append(algorithmic_flops(table, batch.order[m], code[m], it1[m], "lm"))
     flops_pass = sum(per_order_flops)
-    st = main_r["stage_ms"]
+    flops_resume = algorithmic_flops(table, batch.order, code, r["stage"][3], "lm")
     mode = 1 if prec == "fp32" else 0
     if st.get("lm_per_order"):
         # concurrent per-order launches: the dominant one is the order with
@@ -223,82 +176,86 @@ def main():
     # HBM bytes per launch from the committed counter summary of this kernel
     # and workload, valid while the solver sources are unchanged
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"hbm_{kfile}_{WKEY[args.config]}.txt")
+    tfile = os.path.join(ROOT, "profiles", f"hbm_{kfile}_{WKEY[cfg]}.txt")
     if os.path.exists(tfile):
         kv = dict(l.split(":", 1) for l in open(tfile).read().splitlines() if ":" in l and not l.startswith("#"))
         kv = {k.strip(): v.strip() for k, v in kv.items()}
         if kv.get("source_hash") == kernel_source_hash():
             traffic = float(kv["hbm_bytes_per_launch"])
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[prec], "traffic": traffic, "kernel": kname,
-                "flops_per_launch": flops_dom, "launch_ms": ms_dom,
-                "lm_pass": {"flops": flops_pass, "ms": st["lm"], "tflops": flops_pass / (st["lm"] * 1e-3) / 1e12,
-                            "flops_per_order": per_order_flops, "ms_per_order": st.get("lm_per_order")}}
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK[prec], "traffic": traffic, "kernel": kname,
+            "flops_per_launch": flops_dom, "launch_ms": ms_dom,
+            "lm_pass": {"flops": flops_pass, "ms": st["lm"], "tflops": flops_pass / (st["lm"] * 1e-3) / 1e12,
+                        "flops_per_order": per_order_flops, "ms_per_order": st.get("lm_per_order"),
+                        "straggler_flops": flops_resume, "straggler_ms": st["resume"]}}
 
-    # ---------------- parity on a sample and the CPU baseline (oracle)
-    cpu = None
-    parity = None
-    if not args.no_cpu_baseline:
-        import oracle as O
-        O.lib()
-        ncores = os.cpu_count() or 1
-        try:
-            ncores = len(os.sched_getaffinity(0))
-        except AttributeError:
-            pass
-        ncores = min(ncores, 16)
-        # the whole workload when it is small enough (else a seeded uniform
-        # sample), solved and accepted again until about 10 s of CPU work
-        m = min(n, args.cpu_sample or 2_000_000)
-        samp = np.arange(n) if m == n else np.sort(np.random.default_rng(11).choice(n, size=m, replace=False))
-        sb = batch.subset(samp) if m < n else batch
-        reps, t_cpu, acc_cpu = 0, 0.0, 0
-        while reps < 1 or (t_cpu < 10.0 and reps < 64):
-            t = time.perf_counter()
-            o_ = O.solve_batch(scene, sb, nthreads=ncores)
-            a_ = O.accept_batch(scene, sb, o_["x"], o_["status"], nthreads=ncores)
-            t_cpu += time.perf_counter() - t
-            acc_cpu += int(a_.sum())
-            if reps == 0:
-                orc, oacc = o_, a_
-            reps += 1
-        what = "the whole workload" if m == n else f"a seeded uniform sample of {m} of the {n} solves"
-        cpu = {"value": acc_cpu / t_cpu, "unit": "accepted paths/s", "cores": ncores, "kind": "oracle",
-               "sample": f"{what} ({m} solves), solve + accept, {reps} passes, {t_cpu:.1f} s",
-               "solves_per_s": reps * m / t_cpu}
-        gacc = acc[:n].cpu().numpy()[samp]
-        curved = np.zeros(len(samp), bool)
-        for k in range(5):
-            curved |= (sb.order > k) & np.isin(scene.type_of(np.maximum(sb.prim[k], 0)), (2, 3))
-        both = (gacc == 1) & (oacc == 1)
-        errs, other_root, unverified = [], 0, 0
-        for i in np.where(both | ((gacc == 1) & curved))[0]:
-            o_ = sb.order[i]
-            xg = r["x"][:3 * o_, samp[i]]
-            e = np.inf
-            if oacc[i]:
-                e = float(np.linalg.norm((xg - orc["x"][:3 * o_, i]).reshape(o_, 3), axis=1).max())
-            if e <= 1e-6 or not curved[i]:
-                errs.append(e)
-                continue
-            # a curved path may have several roots: the GPU's is verified by an
-            # oracle polish from the GPU point (same root, accepted)
-            X, c_, it_, st_ = O.solve_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], x0=xg)
-            ok = st_ == O.CONVERGED and O.accept_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], X, st_) and \
-                np.linalg.norm((X - xg).reshape(o_, 3), axis=1).max() <= 1e-6
-            other_root += int(ok)
-            unverified += int(not ok)
-        errs = np.array(errs) if errs else np.zeros(1)
-        flat = ~curved
-        parity = {"sample": int(len(samp)),
-                  "flag_mismatches_planar": int((gacc[flat] != oacc[flat]).sum()),
-                  "gpu_only": int(((gacc == 1) & (oacc == 0)).sum()),
-                  "oracle_only": int(((gacc == 0) & (oacc == 1)).sum()),
-                  "curved_other_root_verified": other_root, "curved_unverified": unverified,
-                  "point_err_m": {"max": float(errs.max()), "p50": float(np.percentile(errs, 50)),
-                                  "p99": float(np.percentile(errs, 99))}}
 
-    value = main_r["paths_per_s"]
+def ncores():
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:
+        c = os.cpu_count() or 1
+    return min(c, 16)
+
+
+def oracle_run(O, scene, batch, cores, budget_s, max_n):
+    """The oracle (solve + accept) on the whole workload or a seeded uniform
+    sample of at most max_n solves, repeated until about budget_s seconds."""
+    n = batch.n
+    m = min(n, max_n)
+    samp = np.arange(n) if m == n else np.sort(np.random.default_rng(11).choice(n, size=m, replace=False))
+    sb = batch.subset(samp) if m < n else batch
+    reps, t_cpu, acc_cpu = 0, 0.0, 0
+    while reps < 1 or (t_cpu < budget_s and reps < 64):
+        t = time.perf_counter()
+        o_ = O.solve_batch(scene, sb, nthreads=cores)
+        a_ = O.accept_batch(scene, sb, o_["x"], o_["status"], nthreads=cores)
+        t_cpu += time.perf_counter() - t
+        acc_cpu += int(a_.sum())
+        if reps == 0:
+            orc, oacc = o_, a_
+        reps += 1
+    return {"samp": samp, "sb": sb, "orc": orc, "oacc": oacc, "reps": reps, "t": t_cpu, "acc": acc_cpu, "m": m}
+
+
+def parity(O, scene, run, r, gacc):
+    """GPU flags and points against the oracle's on the same solves.  Planes
+    and straight edges: flags must match and points agree; curved paths may
+    have several roots, so a GPU root that differs from the oracle's is
+    verified by an oracle solve started at the GPU point."""
+    samp, sb, orc, oacc = run["samp"], run["sb"], run["orc"], run["oacc"]
+    gacc = gacc[samp]
+    curved = np.zeros(len(samp), bool)
+    for k in range(5):
+        curved |= (sb.order > k) & np.isin(scene.type_of(np.maximum(sb.prim[k], 0)), (2, 3))
+    both = (gacc == 1) & (oacc == 1)
+    errs, other_root, unverified = [], 0, 0
+    for i in np.where(both | ((gacc == 1) & curved))[0]:
+        o_ = sb.order[i]
+        xg = r["x"][:3 * o_, samp[i]]
+        e = np.inf
+        if oacc[i]:
+            e = float(np.linalg.norm((xg - orc["x"][:3 * o_, i]).reshape(o_, 3), axis=1).max())
+        if e <= 1e-6 or not curved[i]:
+            errs.append(e)
+            continue
+        X, c_, it_, st_ = O.solve_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], x0=xg)
+        ok = st_ == O.CONVERGED and O.accept_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], X, st_) and \
+            np.linalg.norm((X - xg).reshape(o_, 3), axis=1).max() <= 1e-6
+        other_root += int(ok)
+        unverified += int(not ok)
+    errs = np.array(errs) if errs else np.zeros(1)
+    flat = ~curved
+    return {"sample": int(len(samp)),
+            "flag_mismatches_planar": int((gacc[flat] != oacc[flat]).sum()),
+            "gpu_only": int(((gacc == 1) & (oacc == 0)).sum()),
+            "oracle_only": int(((gacc == 0) & (oacc == 1)).sum()),
+            "curved_other_root_verified": other_root, "curved_unverified": unverified,
+            "point_err_m": {"max": float(errs.max()), "p50": float(np.percentile(errs, 50)),
+                            "p99": float(np.percentile(errs, 99))}}
+
+
+def emit(args, value, ms, variant, dtype, workload, n, variants, roofline, cpu, par, extra=None):
     line = {
         "metric": "accepted paths/sec at 1e-6 m point error vs FP64 oracle (learned+FP32 vs plain)",
         "value": value,
@@ -306,23 +263,176 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": main_r["ms_per_step"],
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if variant != "P" else "f64",
+        "dtype": dtype,
         "data": "synthetic (seeded generators)",
-        "config": {"workload": names[args.config], "solves": int(n),
-                   "variant": {"L": "learned start + FP32 LM + FP64 polish + fallback",
-                               "S": "straight-line start + FP32 LM + FP64 polish + fallback",
-                               "P": "plain FP64 LM"}[variant]},
+        "config": {"workload": workload, "solves": int(n), "variant": VARIANT_TEXT[variant]},
         "variants": {v: {k: (round(x, 6) if isinstance(x, float) else x) for k, x in d.items()}
-                     for v, d in results.items()},
+                     for v, d in variants.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "parity_sample": parity,
+        "parity_sample": par,
     }
+    if extra:
+        line.update(extra)
     print(json.dumps(line))
+
+
+def main_single(args, torch, mpt, W):
+    t0 = time.time()
+    if args.config == 5:
+        scene, batch = W.config5(n_rx=args.n_rx or 16384)
+    elif args.n_rx:
+        scene, batch = W.CONFIGS[args.config](n_rx=args.n_rx)
+    else:
+        scene, batch = W.CONFIGS[args.config]()
+    n = batch.n
+    log(f"# workload generated in {time.time() - t0:.1f}s: {n} solves")
+    ctx = mpt.Context(0)
+    ctx.upload_scene(scene)
+
+    variant = args.variant
+    if variant in ("auto", "L", "A"):
+        ok = False
+        try:
+            from paper_2301_06399_amd import learned
+            ok = learned.prepare(ctx, scene, batch, steps=args.train_steps or None)
+        except (ImportError, mpt.MptError) as e:
+            log(f"# learned start unavailable: {e}")
+        if variant in ("L", "A") and not ok:
+            print(json.dumps({"error": "learned start requested but unavailable"}))
+            sys.exit(3)
+        variant = variant if variant != "auto" else ("L" if ok else "S")
+
+    if args.copy_mib:
+        # a plain copy of known size: what the HBM byte counters read for it
+        # calibrates them for the solver kernels
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 1.0, out=dst)  # one elementwise kernel: reads and writes copy_mib MiB
+        torch.cuda.synchronize()
+        del src, dst
+
+    run = Runner(torch, mpt, ctx, scene, batch)
+    variants = [variant] if args.only_main else [variant] + [x for x in ("S", "P") if x != variant]
+    results, outs, flags = {}, {}, {}
+    for v in variants:
+        steps = args.steps if v == variant else max(5, args.steps // 4)
+        warm = args.warmup if v == variant else 1
+        results[v], outs[v] = run.run(v, steps, warm, tune=not args.no_autotune)
+        flags[v] = run.flags()
+    main_r, r = results[variant], outs[variant]
+    prec = "fp64" if variant == "P" else "fp32"
+    roof = lm_roofline(scene, batch, r, main_r["stage_ms"], prec, args.config, mpt)
+
+    cpu = par = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        O.lib()
+        cores = ncores()
+        orun = oracle_run(O, scene, batch, cores, 10.0, args.cpu_sample or 2_000_000)
+        what = "the whole workload" if orun["m"] == n else f"a seeded uniform sample of the {n} solves"
+        cpu = {"value": orun["acc"] / orun["t"], "unit": "accepted paths/s", "cores": cores, "kind": "oracle",
+               "sample": f"{what} ({orun['m']} solves), solve + accept, {orun['reps']} passes, {orun['t']:.1f} s",
+               "solves_per_s": orun["reps"] * orun["m"] / orun["t"]}
+        par = parity(O, scene, orun, r, flags[variant])
+    emit(args, main_r["paths_per_s"], main_r["ms_per_step"], variant, "f32+f64" if variant != "P" else "f64",
+         NAMES[args.config], n, results, roof, cpu, par)
+
+
+def main_learned(args, torch, mpt, W):
+    """Learned-start evaluation: one network trained on the outputs of the
+    plain FP64 solver for 2 M problems (half street canyon, half curved, the
+    "train" seed stream), then L / A / S / P timed on 1 M held-out problems
+    (the "heldout" stream), each half with its scene resident."""
+    from paper_2301_06399_amd import learned
+    n_rx = args.n_rx or 16384
+    t0 = time.time()
+    train = [W.training_batch(2, n_rx=n_rx), W.training_batch(3, n_rx=n_rx)]
+    held = [W.training_batch(2, n_rx=n_rx // 2, stream="heldout"),
+            W.training_batch(3, n_rx=n_rx // 2, stream="heldout")]
+    log(f"# workloads generated in {time.time() - t0:.1f}s: train {sum(b.n for _, b in train)}, "
+        f"held-out {sum(b.n for _, b in held)}")
+    ctx = mpt.Context(0)
+    t0 = time.time()
+    hist = learned.train_joint(ctx, train, steps=args.train_steps or 6000, log=sys.stderr)
+    log(f"# joint training {time.time() - t0:.1f}s, final losses {hist[-2:]}")
+    del train
+    variants = ["L", "A", "S", "P"]
+    per = {v: [] for v in variants}
+    outs, flags = {}, {}
+    for h, (sc, b) in enumerate(held):
+        ctx.upload_scene(sc)
+        run = Runner(torch, mpt, ctx, sc, b)
+        for v in variants:
+            res, r = run.run(v, args.steps, args.warmup, tune=not args.no_autotune)
+            per[v].append(res)
+            outs[(h, v)], flags[(h, v)] = r, run.flags()
+    results = {}
+    for v in variants:
+        ms = sum(x["ms_per_step"] for x in per[v])
+        k = sum(x["accepted"] for x in per[v])
+        results[v] = {"ms_per_step": ms, "accepted": k, "paths_per_s": k / (ms * 1e-3),
+                      "halves": [{kk: x[kk] for kk in ("ms_per_step", "accepted", "lm_iters_mean", "iters_mean",
+                                                        "polished", "fallback", "stage_ms")} for x in per[v]]}
+    # the network kernel on the curved half (every path served): MFMA roofline
+    rows = held[1][1].n
+    ms_net = per["L"][1]["stage_ms"]["learned"]
+    ach = MLP_FLOPS_PER_ROW * rows / (ms_net * 1e-3)
+    roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s",
+            "frac": ach / PEAK["bf16"], "traffic": None, "kernel": "k_mlp_fused (curved half, every row)",
+            "flops_per_launch": MLP_FLOPS_PER_ROW * rows, "launch_ms": ms_net}
+    cpu = par = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        O.lib()
+        cores = ncores()
+        tot_t = tot_acc = tot_m = 0
+        par = []
+        for h, (sc, b) in enumerate(held):
+            orun = oracle_run(O, sc, b, cores, 5.0, args.cpu_sample or 2_000_000)
+            tot_t += orun["t"]
+            tot_acc += orun["acc"]
+            tot_m += orun["m"] * orun["reps"]
+            par.append(parity(O, sc, orun, outs[(h, "L")], flags[(h, "L")]))
+        cpu = {"value": tot_acc / tot_t, "unit": "accepted paths/s", "cores": cores, "kind": "oracle",
+               "sample": f"the whole held-out set (both halves), solve + accept, {tot_t:.1f} s",
+               "solves_per_s": tot_m / tot_t}
+    n = sum(b.n for _, b in held)
+    emit(args, results["L"]["paths_per_s"], results["L"]["ms_per_step"], "L", "bf16+f32+f64", NAMES[4], n,
+         results, roof, cpu, par, extra={"training": {"problems": 2 * n_rx * 64, "loss_history": hist[-4:]}})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--n-rx", type=int, default=0, help="receivers (0: the configuration's own)")
+    ap.add_argument("--variant", default="auto", choices=["auto", "L", "A", "S", "P"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="largest oracle sample (0: 2,000,000 solves)")
+    ap.add_argument("--train-steps", type=int, default=0, help="network training steps before timing")
+    ap.add_argument("--only-main", action="store_true", help="time only the headline variant")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the tuner: launch choices from MPT_AUTOTUNE_CACHE, else the defaults")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2301_06399_amd import mpt
+    from paper_2301_06399_amd import workloads as W
+    if args.config == 4:
+        main_learned(args, torch, mpt, W)
+    else:
+        main_single(args, torch, mpt, W)
 
 
 if __name__ == "__main__":

@@ -173,6 +173,11 @@ typedef struct {
     double polish_gate;    /* 1e-2  FP32 end points with |R|_inf above this are
                               final (no path); below it they are polished       */
     uint64_t seed;         /* 0     state of the MPT_INIT_RANDOM draws          */
+    int32_t spill;         /* -1: the autotuner's choice; 0: off; 1..64: once an
+                              order's queue is empty, a wave with at most this
+                              many busy lanes parks them for a second, densely
+                              packed launch (results are unchanged)           */
+    int32_t reserved;      /* 0 */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 
@@ -181,8 +186,9 @@ void mpt_default_opts(mpt_solve_opts *opts);
  *   cost        [n] FP64 final cost C = |R|^2 (Eq. 12 with the rescaled rows)
  *   iters       [n] int32 iterations run (FP32 + polish + fallback)
  *   status      [n] uint8 MPT_PATH_* code, bit 7 = fallback used
- *   stage_iters [3][n] int32 or NULL: iterations of the first LM pass (FP32
- *               or plain FP64), polish steps, fallback iterations           */
+ *   stage_iters [4][n] int32 or NULL: iterations of the first LM pass (FP32
+ *               or plain FP64), polish steps, fallback iterations, and the
+ *               part of the first count run by the straggler launch        */
 typedef struct {
     double *x;
     double *cost;
@@ -206,16 +212,19 @@ mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_
 
 /*
  * Autotuner of the launch choices that do not change results (the schedule -
- * one mixed-order launch or concurrent per-order launches - and the block
- * size): runs the first LM pass of the given batch with each candidate
- * (writing the outputs), keeps the fastest and uses it for later solves of
- * the same precision, size class (floor log2 n) and scene size.  With the
+ * one mixed-order launch or concurrent per-order launches -, the block size,
+ * the grid divisor of the per-order launches and the straggler threshold
+ * `spill`): runs the LM, polish and fallback passes of the given batch with
+ * each candidate (writing the outputs), keeps the fastest and uses it for
+ * later solves of the same precision, size class (floor log2 n) and scene
+ * size.  With the
  * environment variable MPT_AUTOTUNE_CACHE set to a file path, choices are
  * loaded from and saved to that file (one line per entry).  Synchronises.
  * best_* (host, may be NULL) receive the choice and its time in ms.
  */
 mpt_status mpt_autotune(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_opts *opts,
-                        const mpt_solve_out *out, int32_t *best_sched, int32_t *best_block, float *best_ms);
+                        const mpt_solve_out *out, int32_t *best_sched, int32_t *best_block, float *best_ms,
+                        int32_t *best_gdiv, int32_t *best_spill);
 
 /*
  * The acceptance test of Alg. 1 ("C < threshold and X is valid") in FP64 on
@@ -296,9 +305,9 @@ mpt_status mpt_flops_per_iter(int order, const int32_t *types, int64_t out[4]);
 
 /* Per-stage timings of the last mpt_solve_batch in milliseconds (HIP events
  * on the context's stream; synchronises): [0] order binning, [1] learned
- * start, [2] first LM pass (FP32 or plain FP64), [3] FP64 polish,
- * [4] FP64 fallback. */
-mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[5]);
+ * start, [2] first LM pass (FP32 or plain FP64), [3] its straggler launch,
+ * [4] FP64 polish, [5] FP64 fallback. */
+mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[6]);
 /* Durations (ms) of the per-order kernels of the first LM pass of the last
  * mpt_solve_batch run with MPT_SCHED_PER_ORDER, index = order - 1 (HIP
  * events on the forked streams; synchronises). */

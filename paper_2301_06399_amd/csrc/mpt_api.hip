@@ -35,7 +35,9 @@ struct mpt_ctx {
     size_t blk_cap = 0;
     double *x0l = nullptr;
     size_t x0l_cap = 0;
-    hipEvent_t ev[6] = {};
+    double *spf = nullptr;  // parked stragglers: damping and plateau reference [2][n]
+    size_t spf_cap = 0;
+    hipEvent_t ev[7] = {};
     hipStream_t aux[MPT_MAX_ORDER] = {};  // per-order launches run concurrently
     hipEvent_t fork = nullptr, join[MPT_MAX_ORDER] = {};
     hipEvent_t kev[MPT_MAX_ORDER][2] = {};  // per-order kernel start / end of the first LM pass
@@ -43,7 +45,7 @@ struct mpt_ctx {
     bool timed = false;
     MlpState *mlp = nullptr;
     // autotuned launch choices: key -> (sched, block)
-    struct Tune { int prec, nbucket, n_all, sched, block, gdiv; float ms; };
+    struct Tune { int prec, nbucket, n_all, sched, block, gdiv, spill; float ms; };
     std::vector<Tune> tune;
     bool tune_loaded = false;
     // captured graph of the last solve (replayed while the key matches)
@@ -53,8 +55,10 @@ struct mpt_ctx {
 };
 
 // bin_cnt 0..4, (5..9 unused), head 10..19, pol_cnt 20..24, fb_cnt 25..29, curved rows 30, then
-// 3 x 1364 key counters
-static const int kCounters = 32 + 3 * 1364;
+// 3 x 1364 key counters, then spill_cnt 0..4 and spill_head 5..9
+static const int kKeyCounters = 3 * 1364;
+static const int kSpillCounters = 32 + kKeyCounters;
+static const int kCounters = kSpillCounters + 16;
 
 static mpt_status fail(mpt_ctx *c, mpt_status st, const char *fmt, ...)
 {
@@ -138,6 +142,7 @@ mpt_status mpt_destroy(mpt_ctx *c)
     hipFree(c->ws);
     hipFree(c->blk);
     hipFree(c->x0l);
+    hipFree(c->spf);
     mlp_free(c->mlp);
     for (auto &e : c->ev) hipEventDestroy(e);
     for (int i = 0; i < MPT_MAX_ORDER; i++) {
@@ -275,6 +280,8 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->tau_root32 = 1e-4;
     o->polish_gate = 1e-2;
     o->seed = 0;
+    o->spill = -1;
+    o->reserved = 0;
 }
 
 static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)
@@ -311,11 +318,13 @@ static int resident_grid(mpt_ctx *c, const void *kern, int block, int64_t n, siz
 // ---------------------------------------------------------------- launch choices
 // Default launch choices before (or without) tuning, from measurements on
 // MI355X: FP32 passes run one launch per order concurrently (each order
-// keeps its own register budget), FP64 passes one mixed-order launch.
-static void default_choice(int prec, int &sched, int &block, int &gdiv)
+// keeps its own register budget), FP64 passes one mixed-order launch; no
+// straggler launch (it pays on long curved chains, which the tuner finds).
+static void default_choice(int prec, int &sched, int &block, int &gdiv, int &spill)
 {
     gdiv = 1;
-    if (prec == MPT_FP32_POLISH64) { sched = MPT_SCHED_PER_ORDER; block = 128; }
+    spill = 0;
+    if (prec == MPT_FP32_POLISH64) { sched = MPT_SCHED_PER_ORDER; block = 256; }
     else { sched = MPT_SCHED_PERSISTENT; block = 256; }
 }
 
@@ -334,9 +343,10 @@ static void tune_load(mpt_ctx *c)
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    // one entry per line: prec nbucket n_all sched block gdiv ms
+    // one entry per line: prec nbucket n_all sched block gdiv spill ms
     mpt_ctx::Tune t;
-    while (fscanf(f, "%d %d %d %d %d %d %f", &t.prec, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.gdiv, &t.ms) == 7)
+    while (fscanf(f, "%d %d %d %d %d %d %d %f", &t.prec, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.gdiv, &t.spill,
+                  &t.ms) == 8)
         c->tune.push_back(t);
     fclose(f);
 }
@@ -348,22 +358,24 @@ static void tune_save(mpt_ctx *c)
     FILE *f = fopen(path, "w");
     if (!f) return;
     for (auto &t : c->tune)
-        fprintf(f, "%d %d %d %d %d %d %.6f\n", t.prec, t.nbucket, t.n_all, t.sched, t.block, t.gdiv, t.ms);
+        fprintf(f, "%d %d %d %d %d %d %d %.6f\n", t.prec, t.nbucket, t.n_all, t.sched, t.block, t.gdiv, t.spill, t.ms);
     fclose(f);
 }
 
-static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv)
+static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv, int &spill)
 {
-    default_choice(o->precision, sched, block, gdiv);
+    default_choice(o->precision, sched, block, gdiv, spill);
     tune_load(c);
     for (auto &t : c->tune)
         if (t.prec == o->precision && t.nbucket == nbucket(n) && t.n_all == c->s.n_all) {
             sched = t.sched;
             block = t.block;
             gdiv = t.gdiv;
+            spill = t.spill;
         }
     if (o->sched != MPT_SCHED_AUTO) sched = o->sched;
     if (o->block) block = o->block;
+    if (o->spill >= 0) spill = o->spill;
 }
 
 static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out)
@@ -390,6 +402,18 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
     if (opts->sched < MPT_SCHED_PER_ORDER || opts->sched > MPT_SCHED_AUTO)
         return fail(c, MPT_E_UNSUPPORTED, "sched %d", opts->sched);
     if (opts->grid < 0) return fail(c, MPT_E_INVALID_ARG, "negative grid");
+    if (opts->spill < -1 || opts->spill > 64) return fail(c, MPT_E_INVALID_ARG, "spill must be -1..64");
+    return MPT_OK;
+}
+
+// Work buffers of a solve of n paths (sized before any graph capture).
+static mpt_status size_buffers(mpt_ctx *c, int64_t n, bool learned)
+{
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    mpt_status st;
+    if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 4 * m, sizeof(int)))) return st;
+    if ((st = ensure(c, (void **)&c->spf, &c->spf_cap, 2 * m, sizeof(double)))) return st;
+    if (learned && (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * m, sizeof(double)))) return st;
     return MPT_OK;
 }
 
@@ -397,16 +421,14 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
 // `timed`, HIP events mark the stage boundaries (not inside graph capture).
 static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts,
                                 const mpt_solve_out *out, hipStream_t s, bool timed, int sched, int block,
-                                int gdiv = 1)
+                                int gdiv, int spill)
 {
     BatchDev bd;
     mpt_status st = batch_dev(c, b, bd);
     if (st) return st;
     const int64_t n = b->n;
-    if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 3 * (size_t)(n > 0 ? n : 1), sizeof(int)))) return st;
     const bool learned = opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL;
-    if (learned && (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * (size_t)(n > 0 ? n : 1), sizeof(double))))
-        return st;
+    if ((st = size_buffers(c, n, learned))) return st;
     int *ctr = c->ws;
     KParams kp{};
     kp.s = c->s;
@@ -437,6 +459,11 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.perm = ctr + kCounters;
     kp.pol_list = ctr + kCounters + n;
     kp.fb_list = ctr + kCounters + 2 * n;
+    kp.spill_t = spill;
+    kp.spill_cnt = ctr + kSpillCounters;
+    kp.spill_head = ctr + kSpillCounters + 5;
+    kp.spill_list = ctr + kCounters + 3 * n;
+    kp.spill_f = c->spf;
 
     if (timed) hipEventRecord(c->ev[0], s);
     launch_zero(ctr, kCounters, s);
@@ -492,20 +519,27 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     if (timed) c->kev_valid = (n > 0) && sched == MPT_SCHED_PER_ORDER;
     if (n > 0) run_lm(mode, sched, block, true);
     if (timed) hipEventRecord(c->ev[3], s);
-    if (n > 0 && mode == MODE_FP32) launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
+    if (n > 0 && spill > 0) {
+        // the parked stragglers: the same kernels, launched again to resume
+        kp.resume = 1;
+        run_lm(mode, sched, block, false);
+        kp.resume = 0;
+    }
     if (timed) hipEventRecord(c->ev[4], s);
+    if (n > 0 && mode == MODE_FP32) launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
+    if (timed) hipEventRecord(c->ev[5], s);
     // the fallback handles a handful of paths: one mixed-order launch
     if (n > 0 && mode == MODE_FP32 && opts->fallback) run_lm(MODE_FALLBACK64, MPT_SCHED_PERSISTENT, 256, false);
-    if (timed) hipEventRecord(c->ev[5], s);
+    if (timed) hipEventRecord(c->ev[6], s);
     if (timed) c->timed = true;
     HIPCHK(c, hipGetLastError());
     return MPT_OK;
 }
 
 static std::vector<unsigned char> graph_key(const mpt_batch_desc *b, const mpt_solve_opts *o, const mpt_solve_out *out,
-                                            int sched, int block, int gdiv, const SceneDev &s)
+                                            int sched, int block, int gdiv, int spill, const SceneDev &s)
 {
-    std::vector<unsigned char> k(sizeof *b + sizeof *o + sizeof *out + 3 * sizeof(int) + sizeof s);
+    std::vector<unsigned char> k(sizeof *b + sizeof *o + sizeof *out + 4 * sizeof(int) + sizeof s);
     unsigned char *p = k.data();
     memcpy(p, b, sizeof *b), p += sizeof *b;
     memcpy(p, o, sizeof *o), p += sizeof *o;
@@ -513,6 +547,7 @@ static std::vector<unsigned char> graph_key(const mpt_batch_desc *b, const mpt_s
     memcpy(p, &sched, sizeof sched), p += sizeof sched;
     memcpy(p, &block, sizeof block), p += sizeof block;
     memcpy(p, &gdiv, sizeof gdiv), p += sizeof gdiv;
+    memcpy(p, &spill, sizeof spill), p += sizeof spill;
     memcpy(p, &s, sizeof s);
     return k;
 }
@@ -525,20 +560,20 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     mpt_status st = check_opts(c, b, opts, out);
     if (st) return st;
     hipSetDevice(c->device);
-    int sched, block, gdiv;
-    choose(c, opts, b->n, sched, block, gdiv);
-    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block, gdiv);
+    int sched, block, gdiv, spill;
+    choose(c, opts, b->n, sched, block, gdiv, spill);
+    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block, gdiv, spill);
 
     // graph mode: capture once per (batch, options, outputs, scene) and replay
-    std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, gdiv, c->s);
+    std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, gdiv, spill, c->s);
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) hipGraphExecDestroy(c->gexec), c->gexec = nullptr;
         if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
         // buffers are sized before capture: no allocation inside it
-        if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 3 * (size_t)(b->n > 0 ? b->n : 1), sizeof(int))))
-            return st;
+        const bool learned = opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL;
+        if ((st = size_buffers(c, b->n, learned))) return st;
         HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-        st = enqueue_solve(c, b, opts, out, c->cap, false, sched, block, gdiv);
+        st = enqueue_solve(c, b, opts, out, c->cap, false, sched, block, gdiv, spill);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap, &g);
         if (st) {
@@ -556,44 +591,52 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
 }
 
 mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out,
-                        int32_t *best_sched, int32_t *best_block, float *best_ms)
+                        int32_t *best_sched, int32_t *best_block, float *best_ms, int32_t *best_gdiv,
+                        int32_t *best_spill)
 {
     if (!c) return MPT_E_INVALID_ARG;
     mpt_status st = check_opts(c, b, opts, out);
     if (st) return st;
     hipSetDevice(c->device);
     tune_load(c);
-    // candidates: schedule x block size x grid divisor (per-order only)
-    struct Cand { int sched, block, gdiv; };
+    // candidates: schedule x block size x grid divisor (per-order only) x
+    // straggler threshold
+    struct Cand { int sched, block, gdiv, spill; };
     std::vector<Cand> cands;
-    for (int blk : {64, 128, 256}) {
-        cands.push_back({MPT_SCHED_PERSISTENT, blk, 1});
-        for (int gd : {1, 2, 4}) cands.push_back({MPT_SCHED_PER_ORDER, blk, gd});
-    }
+    for (int sp : {0, 8, 16, 32})
+        for (int blk : {128, 256}) cands.push_back({MPT_SCHED_PERSISTENT, blk, 1, sp});
+    for (int sp : {0, 16})
+        for (int blk : {64, 128, 256})
+            for (int gd : {1, 2}) cands.push_back({MPT_SCHED_PER_ORDER, blk, gd, sp});
     float best = 1e30f;
     Cand bc = cands[0];
     for (const Cand &cd : cands) {
-        // the fastest of five timed runs after one warm-up run
+        // the fastest of the timed runs after one warm-up run (five runs,
+        // two when one run takes more than 20 ms)
         float tmin = 1e30f;
-        for (int rep = 0; rep < 6; rep++) {
-            if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv))) return st;
-            HIPCHK(c, hipEventSynchronize(c->ev[5]));
+        for (int rep = 0, reps = 6; rep < reps; rep++) {
+            if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv, cd.spill)))
+                return st;
+            HIPCHK(c, hipEventSynchronize(c->ev[6]));
             float ms = 0.0f;
-            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[5]));  // LM, polish and fallback passes
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[6]));  // LM, stragglers, polish and fallback
+            if (rep == 0 && ms > 20.0f) reps = 3;
             if (rep > 0 && ms < tmin) tmin = ms;
         }
         if (tmin < best) best = tmin, bc = cd;
     }
-    const int bs = bc.sched, bb = bc.block;
     bool found = false;
     for (auto &t : c->tune)
         if (t.prec == opts->precision && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
-            t.sched = bs, t.block = bb, t.gdiv = bc.gdiv, t.ms = best, found = true;
-    if (!found) c->tune.push_back({opts->precision, nbucket(b->n), c->s.n_all, bs, bb, bc.gdiv, best});
+            t.sched = bc.sched, t.block = bc.block, t.gdiv = bc.gdiv, t.spill = bc.spill, t.ms = best, found = true;
+    if (!found)
+        c->tune.push_back({opts->precision, nbucket(b->n), c->s.n_all, bc.sched, bc.block, bc.gdiv, bc.spill, best});
     tune_save(c);
-    if (best_sched) *best_sched = bs;
-    if (best_block) *best_block = bb;
+    if (best_sched) *best_sched = bc.sched;
+    if (best_block) *best_block = bc.block;
     if (best_ms) *best_ms = best;
+    if (best_gdiv) *best_gdiv = bc.gdiv;
+    if (best_spill) *best_spill = bc.spill;
     return MPT_OK;
 }
 
@@ -678,12 +721,12 @@ extern "C" mpt_status mpt_flops_per_iter(int order, const int32_t *types, int64_
 
 extern "C" {
 
-mpt_status mpt_last_timings(mpt_ctx *c, float ms[5])
+mpt_status mpt_last_timings(mpt_ctx *c, float ms[6])
 {
     if (!c || !ms) return MPT_E_INVALID_ARG;
     if (!c->timed) return fail(c, MPT_E_INVALID_ARG, "no solve recorded");
-    HIPCHK(c, hipEventSynchronize(c->ev[5]));
-    for (int i = 0; i < 5; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
+    HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    for (int i = 0; i < 6; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
     return MPT_OK;
 }
 
@@ -691,7 +734,7 @@ mpt_status mpt_last_lm_timings(mpt_ctx *c, float ms[5])
 {
     if (!c || !ms) return MPT_E_INVALID_ARG;
     if (!c->timed || !c->kev_valid) return fail(c, MPT_E_INVALID_ARG, "no per-order solve recorded");
-    HIPCHK(c, hipEventSynchronize(c->ev[5]));
+    HIPCHK(c, hipEventSynchronize(c->ev[6]));
     for (int i = 0; i < MPT_MAX_ORDER; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->kev[i][0], c->kev[i][1]));
     return MPT_OK;
 }

@@ -66,6 +66,12 @@ struct KParams {
     int *pol_list;             // [n] polish lists (bin-relative slots)
     int *fb_cnt;               // [5]
     int *fb_list;              // [n] fallback lists (bin-relative slots)
+    int spill_t;               // park a drained bin's busy lanes when at most this many (0: never)
+    int resume;                // 1: this launch finishes the parked paths
+    int *spill_cnt;            // [5] parked paths per order
+    int *spill_head;           // [5] work counters of the straggler pass
+    int *spill_list;           // [n] parked paths (bin-relative slots)
+    double *spill_f;           // [2][n] damping and plateau reference of a parked path
 };
 
 void launch_pack(const double *raw, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c, hipStream_t st);

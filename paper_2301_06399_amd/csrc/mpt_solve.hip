@@ -124,14 +124,14 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out,
             out.iters[i] = 0;
             out.status[i] = ST_BAD;
             if (out.stage)
-                for (int q = 0; q < 3; q++) out.stage[(size_t)q * b.n + i] = 0;
+                for (int q = 0; q < 4; q++) out.stage[(size_t)q * b.n + i] = 0;
         } else {
             // the rows past the path's own points and the later stages'
             // iteration counts are zero: written here, coalesced, so that the
             // solver kernels store only what a path produces
             for (int q = 3 * ord; q < 3 * kMaxN; q++) out.x[(size_t)q * b.n + i] = 0.0;
             if (out.stage)
-                for (int q = 1; q < 3; q++) out.stage[(size_t)q * b.n + i] = 0;
+                for (int q = 1; q < 4; q++) out.stage[(size_t)q * b.n + i] = 0;
             atomicAdd(&loc[bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q)], 1);
         }
     }
@@ -383,17 +383,29 @@ template <> struct ModeT<MODE_PLAIN64> { using T = double; };
 template <> struct ModeT<MODE_FP32> { using T = float; };
 template <> struct ModeT<MODE_FALLBACK64> { using T = double; };
 
+//
+// Stragglers.  Iteration counts are bimodal (a root converges in a handful of
+// iterations, a path without one creeps until the plateau test ends it), so
+// once the bin's queue is empty a wave would idle most of its lanes while its
+// slowest paths finish.  Instead, when no more than spill_t lanes are still
+// busy, the wave parks their state (points, iteration count, damping,
+// plateau reference) and leaves; a second launch of the same kernel
+// (kp.resume) packs the parked paths densely and finishes them.  The same
+// machine code runs every iteration of a path, from the exact state it was
+// parked in, so the results are identical bit for bit.
 template <int MODE, int N>
 __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restrict__ srec)
 {
     using T = typename ModeT<MODE>::T;
     const int lane = __lane_id();
-    const int *cnt = (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
-    const int *list = (MODE == MODE_FALLBACK64) ? kp.fb_list : kp.perm;
-    int *head = kp.head + (MODE == MODE_FALLBACK64 ? 5 : 0) + (N - 1);
+    const bool resume = kp.resume != 0;
+    const int *cnt = resume ? kp.spill_cnt : (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
+    const int *list = resume ? kp.spill_list : (MODE == MODE_FALLBACK64) ? kp.fb_list : kp.perm;
+    int *head = resume ? kp.spill_head + (N - 1) : kp.head + (MODE == MODE_FALLBACK64 ? 5 : 0) + (N - 1);
     const int count = cnt[N - 1];
     if (count == 0) return;
     const int off = bin_offset(kp.bin_cnt, N);
+    const bool may_spill = !resume && MODE != MODE_FALLBACK64 && kp.spill_t > 0;
 
     SceneT<T> sc;
     sc.rec = srec;
@@ -431,6 +443,7 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
     Lane<T, N> L;
     PathIn<T, N> p;
     int sid = -1;
+    int it0 = 0;  // iteration count at the start of a resumed path
     bool active = false;
     int cbase = 0, cend = 0;  // wave-uniform chunk [cbase, cend) of the bin
     bool drained = false;
@@ -465,6 +478,21 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                         p.id[k] = kp.b.prim[(size_t)k * kp.b.n + sid];
                         p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
                     }
+                    const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
+                                          MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
+#pragma unroll
+                    for (int i = 0; i < 3; i++) p.rx[i] = (T)(rx[i] - sh[i]);
+                    if (resume) {
+                        // a parked path: its state exactly as it was left
+#pragma unroll
+                        for (int j = 0; j < 3 * N; j++) L.X[j] = (T)kp.out.x[(size_t)j * kp.b.n + sid];
+                        L.it = kp.out.iters[sid];
+                        it0 = L.it;
+                        L.lam = (T)kp.spill_f[sid];
+                        L.Cref = (T)kp.spill_f[(size_t)kp.b.n + sid];
+                        L.C = T(__builtin_huge_val());
+                        L.rinf = T(__builtin_huge_val());
+                    } else {
                     bool ok = true;
                     // the fallback restarts from the FP32 end point (already root-like)
                     const int init = (MODE == MODE_FALLBACK64) ? INIT_USER : kp.o.init;
@@ -473,24 +501,23 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                     bool use_net = (init == INIT_LEARNED_ALL);
                     if (init == INIT_LEARNED)
                         for (int k = 0; k < N; k++) use_net = use_net || p.ty[k] == TQ || p.ty[k] == TC;
-                    if (init == INIT_RANDOM) {
-#pragma unroll
-                        for (int k = 0; k < N; k++) {
-                            double P[3];
-#pragma unroll
-                            for (int i = 0; i < 3; i++) {
-                                const double u = splitmix_uniform(kp.o.seed, 15u * (uint64_t)sid + 3u * k + i);
-                                P[i] = kp.s.lo[i] + u * (kp.s.hi[i] - kp.s.lo[i]);
-                            }
-                            project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
-                        }
-                    } else if (init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
+                    if (init == INIT_RANDOM || init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
+                        // the projection onto each object of a point on the
+                        // TX -> RX segment, or of a random point of the scene box
+                        const bool rnd = init == INIT_RANDOM;
 #pragma unroll
                         for (int k = 0; k < N; k++) {
                             const double a = (double)(k + 1) / (double)(N + 1);
                             double P[3];
 #pragma unroll
-                            for (int i = 0; i < 3; i++) P[i] = kp.s.tx[i] + a * (rx[i] - kp.s.tx[i]);
+                            for (int i = 0; i < 3; i++) {
+                                if (rnd) {
+                                    const double u = splitmix_uniform(kp.o.seed, 15u * (uint64_t)sid + 3u * k + i);
+                                    P[i] = kp.s.lo[i] + u * (kp.s.hi[i] - kp.s.lo[i]);
+                                } else {
+                                    P[i] = kp.s.tx[i] + a * (rx[i] - kp.s.tx[i]);
+                                }
+                            }
                             project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
                         }
                     } else {
@@ -514,10 +541,6 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                     int st0 = ST_RUNNING;
                     if (!ok) st0 = ST_BAD;
                     else if (!in_guard(kp.s, X0, N)) st0 = ST_DIVERGED;
-                    const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
-                                          MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
-#pragma unroll
-                    for (int i = 0; i < 3; i++) p.rx[i] = (T)(rx[i] - sh[i]);
 #pragma unroll
                     for (int k = 0; k < N; k++)
 #pragma unroll
@@ -539,6 +562,7 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                         kp.out.status[sid] = (uint8_t)(st0 | (MODE == MODE_FALLBACK64 ? 0x80 : 0));
                         active = false;
                     }
+                    }  // not RESUME
                 }
                 cbase += take;
             }
@@ -547,10 +571,21 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
             if (drained) break;
             continue;
         }
+        // the bin is drained and few lanes are busy: park them (wave-uniform)
+        const bool park = may_spill && drained && (int)__popcll(__ballot(active)) <= kp.spill_t;
         // ---- one iteration on every busy lane
         if (active) {
-            const int st = lm_step<T, N>(sc, p, L, o);
-            if (st != ST_RUNNING) {
+            const int st = park ? ST_PARKED : lm_step<T, N>(sc, p, L, o);
+            if (st == ST_PARKED) {
+                // ---- a parked path: its exact state, for the straggler launch
+#pragma unroll
+                for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j];
+                kp.out.iters[sid] = L.it;
+                kp.spill_f[sid] = (double)L.lam;
+                kp.spill_f[(size_t)kp.b.n + sid] = (double)L.Cref;
+                kp.spill_list[off + atomicAdd(&kp.spill_cnt[N - 1], 1)] = sid;
+                active = false;
+            } else if (st != ST_RUNNING) {
                 // ---- end of one path: write it (world frame)
                 const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
                                       MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
@@ -563,6 +598,7 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                 if (kp.out.stage) {
                     if (MODE == MODE_FALLBACK64) kp.out.stage[(size_t)2 * kp.b.n + sid] = L.it;
                     else kp.out.stage[sid] = L.it;
+                    if (resume) kp.out.stage[(size_t)3 * kp.b.n + sid] = L.it - it0;
                 }
                 int code = st;
                 if (MODE == MODE_FP32) {
@@ -609,6 +645,9 @@ template <> struct Occ<MODE_PLAIN64, 2> { static constexpr int W = 2; };
 template <> struct Occ<MODE_FALLBACK64, 1> { static constexpr int W = 3; };
 template <> struct Occ<MODE_FALLBACK64, 2> { static constexpr int W = 2; };
 
+// The mixed-order kernel keeps the register budget of its largest order.
+template <int MODE> struct OccAll { static constexpr int W = 1; };
+
 // Scene records staged in LDS by every block of a persistent launch (the
 // whole scene: 651 primitives x 18 floats = 47 KB for the street canyon).
 template <int MODE, bool LDS>
@@ -627,9 +666,9 @@ __device__ __forceinline__ const typename ModeT<MODE>::T *stage_scene(const KPar
 
 // One persistent launch over every order (register budget of order 5).
 template <int MODE, bool LDS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_lm(KParams kp)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OccAll<MODE>::W, OccAll<MODE>::W))) k_lm(KParams kp)
 {
-    const int *cnt = (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
+    const int *cnt = kp.resume ? kp.spill_cnt : (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
     if (cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4] == 0) return;  // nothing to solve: skip the staging
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     // long paths first so that the short ones fill the tail
@@ -645,7 +684,7 @@ template <int MODE, int N, bool LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<MODE, N>::W, Occ<MODE, N>::W)))
 k_lm_one(KParams kp)
 {
-    if (((MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt)[N - 1] == 0) return;
+    if ((kp.resume ? kp.spill_cnt : (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt)[N - 1] == 0) return;
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     lm_bin<MODE, N>(kp, rec);
 }

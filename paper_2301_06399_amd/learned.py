@@ -49,12 +49,50 @@ def train(ctx, scene, train_batch, steps=3000, batch_rows=4096, lr=1e-3, seed=1,
     return hist
 
 
+def train_joint(ctx, parts, steps=4000, batch_rows=4096, lr=1e-3, seed=1, log=None):
+    """One network for several scenes: `parts` is a list of (scene, batch);
+    each part's problems are solved by the plain FP64 solver (targets), then
+    the Adam steps cycle through the parts, uploading each part's scene
+    before its minibatch.  Returns the loss history (step, part, loss)."""
+    import torch
+    data = []
+    for sc, tb in parts:
+        ctx.upload_scene(sc)
+        db = mpt.DeviceBatch(tb)
+        out = ctx.solve(db, mpt.default_opts(precision=mpt.FP64_PLAIN))
+        use = (out.status == mpt.CONVERGED).to(torch.uint8)
+        data.append((sc, db, out, use))
+    ctx.mlp_init(seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    for it in range(steps):
+        j = it % len(data)
+        sc, db, out, use = data[j]
+        if len(data) > 1 or it == 0:
+            ctx.upload_scene(sc)
+        rows = torch.randint(0, db.n, (batch_rows,), device="cuda", generator=gen, dtype=torch.int32)
+        a = lr * 0.5 * (1.0 + math.cos(math.pi * it / max(1, steps)))
+        ctx.mlp_train_step(db, out.x, use=use, lr=a, loss=loss, rows=rows)
+        if it % 250 < len(data) or it == steps - 1:
+            hist.append((it, j, float(loss.item())))
+            if log:
+                print(f"# train step {it} (scene {j}): loss {hist[-1][2]:.5f}", file=log, flush=True)
+    return hist
+
+
 def prepare(ctx, scene, batch, steps=None, n_rx=8192, log=sys.stderr):
     """Train the network for the workload of `scene` (configurations 2 and 3)
     on held-apart problems; returns True when the learned start is ready."""
-    cfg = 3 if len(scene.quadrics) or len(scene.circles) else 2
+    if len(scene.lines) and len(scene.quadrics):
+        cfg, n_rx, per_rx = 5, max(1, n_rx // 16), 1024   # the stress scene
+    elif len(scene.quadrics) or len(scene.circles):
+        cfg, per_rx = 3, 64
+    else:
+        cfg, per_rx = 2, 64
     t = time.time()
-    sc, tb = W.training_batch(cfg, n_rx=n_rx)
+    sc, tb = W.training_batch(cfg, n_rx=n_rx, per_rx=per_rx)
     if not (np.allclose(sc.planes, scene.planes) and np.allclose(sc.quadrics, scene.quadrics)):
         return False
     hist = train(ctx, sc, tb, steps=steps or 3000, log=log)

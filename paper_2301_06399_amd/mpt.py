@@ -49,7 +49,7 @@ class SolveOpts(C.Structure):
                 ("plateau_frac", C.c_double), ("tol_step", C.c_double), ("tol_res", C.c_double),
                 ("tau_root", C.c_double), ("lambda0", C.c_double), ("tol_step32", C.c_double),
                 ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("spill", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveOut(C.Structure):
@@ -102,7 +102,8 @@ def load_library(path: str = LIB_PATH):
     L.mpt_flops_per_iter.argtypes = [C.c_int, vp, vp]
     L.mpt_last_lm_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_autotune.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut),
-                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     for f in EXPORTS:
         getattr(L, f).restype = st if f not in ("mpt_last_error", "mpt_default_opts") else getattr(L, f).restype
     _lib = L
@@ -148,7 +149,7 @@ class DeviceOut:
         self.cost = torch.empty(max(n, 0), dtype=torch.float64, device=device)
         self.iters = torch.empty(max(n, 0), dtype=torch.int32, device=device)
         self.status = torch.empty(max(n, 0), dtype=torch.uint8, device=device)
-        self.stage = torch.empty((3, max(n, 0)), dtype=torch.int32, device=device) if stages else None
+        self.stage = torch.empty((4, max(n, 0)), dtype=torch.int32, device=device) if stages else None
 
     def desc(self) -> SolveOut:
         return SolveOut(_ptr(self.x), _ptr(self.cost), _ptr(self.iters), _ptr(self.status), _ptr(self.stage))
@@ -276,22 +277,22 @@ class Context:
     def autotune(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None):
         out = out or DeviceOut(dbatch.n)
         o = opts or default_opts()
-        sch, blk, ms = C.c_int32(), C.c_int32(), C.c_float()
+        sch, blk, ms, gd, sp = C.c_int32(), C.c_int32(), C.c_float(), C.c_int32(), C.c_int32()
         bd, od = dbatch.desc(), out.desc()
         self._enter()
         rc = self.L.mpt_autotune(self.h, C.byref(bd), C.byref(o), C.byref(od), C.byref(sch), C.byref(blk),
-                                 C.byref(ms))
+                                 C.byref(ms), C.byref(gd), C.byref(sp))
         self._leave()
         self._check(rc, "mpt_autotune")
-        return {"sched": sch.value, "block": blk.value, "lm_ms": ms.value}
+        return {"sched": sch.value, "block": blk.value, "gdiv": gd.value, "spill": sp.value, "ms": ms.value}
 
     def synchronize(self):
         self._check(self.L.mpt_synchronize(self.h), "mpt_synchronize")
 
     def timings(self):
-        ms = (C.c_float * 5)()
+        ms = (C.c_float * 6)()
         self._check(self.L.mpt_last_timings(self.h, ms), "mpt_last_timings")
-        return {"bin": ms[0], "learned": ms[1], "lm": ms[2], "polish": ms[3], "fallback": ms[4]}
+        return {"bin": ms[0], "learned": ms[1], "lm": ms[2], "resume": ms[3], "polish": ms[4], "fallback": ms[5]}
 
     def lm_timings(self):
         """Per-order kernel durations (ms) of the last per-order LM pass."""

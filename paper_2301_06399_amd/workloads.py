@@ -359,27 +359,22 @@ def stress_scene() -> Scene:
     return out
 
 
-def config5(n_rx: int = 16384, per_rx: int = 1024) -> tuple[Scene, Batch]:
-    """Orders 3-5 with at least two diffractions; diffractions on the box edges,
-    reflections on the facets and the paraboloids."""
-    sc = stress_scene()
-    rng = np.random.default_rng(seed(5, "rx"))
-    xy = sc._free_xy(rng, n_rx)
-    rx = np.column_stack([xy, np.full(n_rx, 1.5)])
-    rs = np.random.default_rng(seed(5, "seq"))
-    n = n_rx * per_rx
+def _stress_lists(sc: Scene, rs, n: int):
+    """Lists of order 3-5 with at least two diffractions at random slots:
+    diffractions on the box edges, reflections on the facets and the
+    paraboloids, no immediate repeat."""
     order = rs.integers(3, 6, n).astype(np.int32)
     nd = (rs.random(n) * (order - 1)).astype(np.int32) + 2       # U{2..order}
     npl, nln, nq, _ = sc.counts
-    edges = np.arange(npl, npl + nln, dtype=np.int32)
-    refl = np.concatenate([np.arange(npl, dtype=np.int32),
-                           np.arange(npl + nln, npl + nln + nq, dtype=np.int32)])
+    dpool = np.arange(npl, npl + nln, dtype=np.int32)
+    rpool = np.concatenate([np.arange(npl, dtype=np.int32),
+                            np.arange(npl + nln, npl + nln + nq, dtype=np.int32)])
     # choose which slots diffract: random permutation keys, the nd smallest
     keys = rs.random((MAX_ORDER, n))
     keys[np.arange(MAX_ORDER)[:, None] >= order[None, :]] = 2.0
     rank = np.argsort(np.argsort(keys, axis=0), axis=0)
     is_d = rank < nd[None, :]
-    dpool, rpool = edges, refl
+    del keys, rank
 
     def slot_pool(k):
         def draw(m):
@@ -387,7 +382,19 @@ def config5(n_rx: int = 16384, per_rx: int = 1024) -> tuple[Scene, Batch]:
             b = rpool[rs.integers(0, len(rpool), n)]
             return np.where(is_d[k], a, b)
         return draw
-    prim = _no_repeat_sequences(rs, n, order, slot_pool)
+    return order, _no_repeat_sequences(rs, n, order, slot_pool)
+
+
+def config5(n_rx: int = 16384, per_rx: int = 1024, stream: str = "rx") -> tuple[Scene, Batch]:
+    """Orders 3-5 with at least two diffractions; diffractions on the box edges,
+    reflections on the facets and the paraboloids.  `stream` "train" or
+    "heldout" draws other receivers and lists for the learned start."""
+    sc = stress_scene()
+    rng = np.random.default_rng(seed(5, stream))
+    xy = sc._free_xy(rng, n_rx)
+    rx = np.column_stack([xy, np.full(n_rx, 1.5)])
+    rs = np.random.default_rng(seed(5, "seq") if stream == "rx" else seed(5, stream) + 500)
+    order, prim = _stress_lists(sc, rs, n_rx * per_rx)
     return sc, Batch(rx, np.repeat(np.arange(n_rx, dtype=np.int32), per_rx), order, prim)
 
 
@@ -435,8 +442,10 @@ def training_batch(cfg: int, n_rx: int, per_rx: int = 64, stream: str = "train")
         rng = np.random.default_rng(seed(3, stream))
         rx = rng.uniform(sc.aabb_lo, sc.aabb_hi, (n_rx, 3))
         lo, hi = 1, 6
+    elif cfg == 5:
+        return config5(n_rx=n_rx, per_rx=per_rx, stream=stream)
     else:
-        raise ValueError("training batches exist for configurations 2 and 3")
+        raise ValueError("training batches exist for configurations 2, 3 and 5")
     rs = np.random.default_rng(seed(cfg, stream) + 500)
     n = n_rx * per_rx
     order = rs.integers(lo, hi, n).astype(np.int32)

@@ -178,3 +178,24 @@ def test_learned_start_on_curved_paths(ctx):
         assert st == O.CONVERGED and np.abs(X - g["x"][:3 * n, i]).max() <= 1e-6
         assert O.accept_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], X, st)
     assert ((gacc == 0) & (oacc == 1)).sum() <= 0.1 * max(1, oacc.sum())
+
+
+def test_learned_start_gain_over_straight_line(ctx):
+    """What the trained network buys on held-out curved problems: fewer FP32
+    iterations than the straight-line start, and no fewer accepted paths."""
+    from paper_2301_06399_amd import learned, mpt
+    sc, tb = W.training_batch(3, n_rx=2048, per_rx=64)
+    learned.train(ctx, sc, tb, steps=1500, batch_rows=4096)
+    hsc, hb = W.training_batch(3, n_rx=256, per_rx=64, stream="heldout")
+    ctx.upload_scene(hsc)
+    db = mpt.DeviceBatch(hb)
+    res = {}
+    for name, init in (("line", mpt.INIT_LINE), ("learned", mpt.INIT_LEARNED)):
+        out = mpt.DeviceOut(hb.n, stages=True)
+        ctx.solve(db, mpt.default_opts(init=init), out)
+        acc, idx, k = ctx.accept(db, out)
+        r = out.numpy()
+        res[name] = (float(r["stage"][0].mean()), k)
+    print("FP32 iterations and accepted paths, straight line vs learned:", res)
+    assert res["learned"][0] <= 0.95 * res["line"][0]
+    assert res["learned"][1] >= 0.99 * res["line"][1]

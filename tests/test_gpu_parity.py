@@ -142,12 +142,12 @@ def test_schedules_give_identical_results(ctx):
     sc, b = W.config3(n_rx=64, per_rx=64)
     g1 = gpu_solve(ctx, sc, b, precision=1, sched=1)
     g3 = gpu_solve(ctx, sc, b, precision=1, sched=1, block=64)
-    g4 = gpu_solve(ctx, sc, b, precision=1, sched=1)
+    g4 = gpu_solve(ctx, sc, b, precision=1, sched=1, spill=0)
     for k in ("x", "cost", "iters", "status", "accept"):
         assert np.array_equal(g1[k], g3[k]), k
         assert np.array_equal(g1[k], g4[k]), k
     g2 = gpu_solve(ctx, sc, b, precision=1, sched=0)
-    g5 = gpu_solve(ctx, sc, b, precision=1, sched=0, block=128)
+    g5 = gpu_solve(ctx, sc, b, precision=1, sched=0, block=128, spill=32)
     for k in ("x", "cost", "iters", "status", "accept"):
         assert np.array_equal(g2[k], g5[k]), k
     assert np.mean(g1["accept"] == g2["accept"]) > 0.995
@@ -249,7 +249,8 @@ def test_autotuner_choice_keeps_parity(ctx):
     ctx.upload_scene(sc)
     db = mpt.DeviceBatch(b)
     choice = ctx.autotune(db, mpt.default_opts())
-    assert choice["sched"] in (0, 1) and choice["block"] in (64, 128, 256) and choice["lm_ms"] > 0
+    assert choice["sched"] in (0, 1) and choice["block"] in (64, 128, 256) and choice["ms"] > 0
+    assert choice["gdiv"] in (1, 2) and choice["spill"] in (0, 8, 16, 32)
     g = gpu_solve(ctx, sc, b)
     orc = O.solve_batch(sc, b)
     orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
@@ -282,3 +283,31 @@ def test_random_start_matches_oracle(ctx, prec):
     for i in np.where(both)[0]:
         n = b.order[i]
         assert O.accept_one(sc, b.rx[b.rx_index[i]], b.prim[:n, i], g["x"][:3 * n, i], O.CONVERGED)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_straggler_pass_changes_nothing(ctx, prec):
+    """Parking a drained bin's slowest paths and finishing them in a second
+    launch of the same kernel continues each path from its exact state with
+    the same machine code: every output is bit-identical to the run without
+    parking, and the second launch does run iterations when asked to park."""
+    from paper_2301_06399_amd import mpt
+    for sc, b in (W.config2(n_rx=256, per_rx=64), W.config3(n_rx=64, per_rx=64)):
+        ctx.upload_scene(sc)
+        db = mpt.DeviceBatch(b)
+        res = {}
+        for sched in (mpt.SCHED_PERSISTENT, mpt.SCHED_PER_ORDER):
+            for spill in (0, 8, 32, 64):
+                out = mpt.DeviceOut(b.n, stages=True)
+                ctx.solve(db, mpt.default_opts(precision=prec, sched=sched, spill=spill), out)
+                res[(sched, spill)] = out.numpy()
+        for sched in (mpt.SCHED_PERSISTENT, mpt.SCHED_PER_ORDER):
+            ref = res[(sched, 0)]
+            assert (ref["stage"][3] == 0).all()
+            for spill in (8, 32, 64):
+                g = res[(sched, spill)]
+                for k in ("x", "cost", "iters", "status"):
+                    assert np.array_equal(g[k], ref[k]), (sched, spill, k)
+                assert np.array_equal(g["stage"][:3], ref["stage"][:3])
+                assert (g["stage"][3] <= g["stage"][0]).all()
+            assert res[(sched, 64)]["stage"][3].sum() > 0
