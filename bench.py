@@ -112,9 +112,13 @@ class Runner:
         torch, ctx, mpt = self.torch, self.ctx, self.mpt
         o = opts_for(mpt, v)
         launch = ctx.autotune(self.db, o, self.out) if tune else None
-        for _ in range(warmup):
+        # untimed warm-up: the requested steps, and at least 0.3 s of them
+        t = time.perf_counter()
+        w = 0
+        while w < warmup or (time.perf_counter() - t < 0.3 and w < 1000):
             self.step(o)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            w += 1
         t = time.perf_counter()
         for _ in range(steps):
             self.step(o)
@@ -229,7 +233,7 @@ def parity(O, scene, run, r, gacc):
     for k in range(5):
         curved |= (sb.order > k) & np.isin(scene.type_of(np.maximum(sb.prim[k], 0)), (2, 3))
     both = (gacc == 1) & (oacc == 1)
-    errs, other_root, unverified = [], 0, 0
+    errs, other_root, unverified, n_ok = [], 0, 0, 0
     for i in np.where(both | ((gacc == 1) & curved))[0]:
         o_ = sb.order[i]
         xg = r["x"][:3 * o_, samp[i]]
@@ -238,15 +242,22 @@ def parity(O, scene, run, r, gacc):
             e = float(np.linalg.norm((xg - orc["x"][:3 * o_, i]).reshape(o_, 3), axis=1).max())
         if e <= 1e-6 or not curved[i]:
             errs.append(e)
+            n_ok += int(e <= 1e-6)
             continue
         X, c_, it_, st_ = O.solve_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], x0=xg)
         ok = st_ == O.CONVERGED and O.accept_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], X, st_) and \
             np.linalg.norm((X - xg).reshape(o_, 3), axis=1).max() <= 1e-6
         other_root += int(ok)
         unverified += int(not ok)
+        n_ok += int(ok)
+    # n_ok: GPU-accepted paths that meet the bar (the oracle's root within
+    # 1e-6 m, or a verified other root of a curved path)
+    n_gpu = int((gacc == 1).sum())
+    over = int((np.array(errs) > 1e-6).sum()) if errs else 0
     errs = np.array(errs) if errs else np.zeros(1)
     flat = ~curved
-    return {"sample": int(len(samp)),
+    return {"sample": int(len(samp)), "gpu_accepted": n_gpu, "accepted_within_bar": n_ok,
+            "over_1e-6_m": over,
             "flag_mismatches_planar": int((gacc[flat] != oacc[flat]).sum()),
             "gpu_only": int(((gacc == 1) & (oacc == 0)).sum()),
             "oracle_only": int(((gacc == 0) & (oacc == 1)).sum()),
@@ -339,7 +350,13 @@ def main_single(args, torch, mpt, W):
                "sample": f"{what} ({orun['m']} solves), solve + accept, {orun['reps']} passes, {orun['t']:.1f} s",
                "solves_per_s": orun["reps"] * orun["m"] / orun["t"]}
         par = parity(O, scene, orun, r, flags[variant])
-    emit(args, main_r["paths_per_s"], main_r["ms_per_step"], variant, "f32+f64" if variant != "P" else "f64",
+    # the metric counts the accepted paths that meet the 1e-6 m bar against
+    # the oracle: exact when the whole workload was checked, else the
+    # checked sample's share
+    value = main_r["paths_per_s"]
+    if par and par["gpu_accepted"]:
+        value *= par["accepted_within_bar"] / par["gpu_accepted"]
+    emit(args, value, main_r["ms_per_step"], variant, "f32+f64" if variant != "P" else "f64",
          NAMES[args.config], n, results, roof, cpu, par)
 
 
@@ -402,7 +419,10 @@ def main_learned(args, torch, mpt, W):
                "sample": f"the whole held-out set (both halves), solve + accept, {tot_t:.1f} s",
                "solves_per_s": tot_m / tot_t}
     n = sum(b.n for _, b in held)
-    emit(args, results["L"]["paths_per_s"], results["L"]["ms_per_step"], "L", "bf16+f32+f64", NAMES[4], n,
+    value = results["L"]["paths_per_s"]
+    if par and sum(p["gpu_accepted"] for p in par):
+        value *= sum(p["accepted_within_bar"] for p in par) / sum(p["gpu_accepted"] for p in par)
+    emit(args, value, results["L"]["ms_per_step"], "L", "bf16+f32+f64", NAMES[4], n,
          results, roof, cpu, par, extra={"training": {"problems": 2 * n_rx * 64, "loss_history": hist[-4:]}})
 
 

@@ -469,7 +469,10 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     launch_zero(ctr, kCounters, s);
     launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, s);
     if (timed) hipEventRecord(c->ev[1], s);
-    if (learned && n > 0) {
+    // the network serves the paths with a curved object: none without
+    // paraboloids and circles in the scene
+    const bool net = learned && n > 0 && (opts->init == MPT_INIT_LEARNED_ALL || c->s.n_pl_ln < c->s.n_all);
+    if (net) {
         if (opts->init == MPT_INIT_LEARNED) {
             // the network serves only the paths with a curved object: list
             // them (the polish list is free until the FP32 pass) and predict
