@@ -65,6 +65,11 @@ def lib():
         L.orc_accept_one.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int, d, d]
         L.orc_accept_one.restype = C.c_int
         L.orc_solve_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
+        L.orc_solve_batch_param.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
+        L.orc_solve_one_param.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, vp]
+        L.orc_solve_one_param.restype = C.c_int
+        L.orc_param_residual.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
+        L.orc_param_residual.restype = C.c_int
         L.orc_accept_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, d, d, vp, C.c_int]
         _lib = L
     return _lib
@@ -143,8 +148,25 @@ def init_random_batch(scene, batch, seed):
     return x
 
 
-def solve_one(scene, rx, ids, x0=None, opts=None):
-    """Returns (X, cost, iters, status) for one candidate path."""
+def param_residual(scene, rx, ids, U, jac=True):
+    """Parametric form: law rows R at X(U), J = dR/dU, and X(U)."""
+    os_ = scene if isinstance(scene, OracleScene) else OracleScene(scene)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    n = len(ids)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    R = np.zeros(20)
+    J = np.zeros(20 * len(U)) if jac else None
+    X = np.zeros(3 * n)
+    m = lib().orc_param_residual(os_.ref, _p(np.ascontiguousarray(rx, dtype=np.float64)), n, _p(ids), _p(U),
+                                 _p(R), _p(J) if jac else None, _p(X))
+    if m < 0:
+        return None, None, None
+    return R[:m].copy(), (J[: m * len(U)].reshape(m, len(U)).copy() if jac else None), X
+
+
+def solve_one(scene, rx, ids, x0=None, opts=None, form="implicit"):
+    """Returns (X, cost, iters, status) for one candidate path; form
+    "implicit" (Eq. 12) or "param" (Eq. 15)."""
     os_ = scene if isinstance(scene, OracleScene) else OracleScene(scene)
     ids = np.ascontiguousarray(ids, dtype=np.int32)
     n = len(ids)
@@ -153,8 +175,9 @@ def solve_one(scene, rx, ids, x0=None, opts=None):
     it = C.c_int32()
     o = opts or default_opts()
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
-    st = lib().orc_solve_one(os_.ref, _p(np.ascontiguousarray(rx, dtype=np.float64)), n, _p(ids),
-                             _p(x0a), C.byref(o), _p(X), C.byref(c), C.byref(it))
+    f = lib().orc_solve_one_param if form == "param" else lib().orc_solve_one
+    st = f(os_.ref, _p(np.ascontiguousarray(rx, dtype=np.float64)), n, _p(ids),
+           _p(x0a), C.byref(o), _p(X), C.byref(c), C.byref(it))
     return X[: 3 * n].copy(), c.value, it.value, st
 
 
@@ -166,9 +189,9 @@ def accept_one(scene, rx, ids, X, status, tau_res=TAU_RES, min_seg=MIN_SEG):
                                      _p(ids), _p(X), int(status), tau_res, min_seg))
 
 
-def solve_batch(scene, batch, x0=None, opts=None, nthreads=0):
+def solve_batch(scene, batch, x0=None, opts=None, nthreads=0, form="implicit"):
     """Solve every candidate of a workloads.Batch; returns dict of arrays
-    x [15, n], cost, iters, status."""
+    x [15, n], cost, iters, status.  form "implicit" or "param"."""
     os_ = OracleScene(scene)
     nb = batch.n
     x = np.zeros((15, nb))
@@ -178,9 +201,10 @@ def solve_batch(scene, batch, x0=None, opts=None, nthreads=0):
     o = opts or default_opts()
     x0 = batch.x0 if x0 is None else x0
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
-    lib().orc_solve_batch(os_.ref, nb, _p(batch.rx), _p(batch.rx_index), _p(batch.order),
-                          _p(batch.prim), _p(x0a), C.byref(o), _p(x), _p(cost), _p(iters),
-                          _p(status), int(nthreads))
+    f = lib().orc_solve_batch_param if form == "param" else lib().orc_solve_batch
+    f(os_.ref, nb, _p(batch.rx), _p(batch.rx_index), _p(batch.order),
+      _p(batch.prim), _p(x0a), C.byref(o), _p(x), _p(cost), _p(iters),
+      _p(status), int(nthreads))
     return {"x": x, "cost": cost, "iters": iters, "status": status}
 
 

@@ -517,6 +517,243 @@ int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *
     return status;
 }
 
+/* ------------------------------------------------------------ parametric form */
+/*
+ * Eqs. (13)-(15): with a parametric expression of every object the points
+ * are functions X(U) of 2 parameters per surface and 1 per edge, the object
+ * rows vanish identically and only the law rows of Eqs. (8), (9) remain.
+ * Parameters (all in metres):
+ *   plane      (s, t)  X = o + s e1 + t e2,  e1 = eu/|eu|, e2 = n x e1
+ *   line       (s)     X = p + s e
+ *   paraboloid (s, t)  X = p + s e1 + t e2 + kappa (s^2 + t^2) ax, with
+ *                      (e1, e2) orthonormal across the axis; the record must
+ *                      be a paraboloid of revolution, A = kappa (I - ax ax^T),
+ *                      b = -ax, c = 0, so kappa = trace(A)/2
+ *   circle     (phi)   X = c + R (cos(phi/R) u1 + sin(phi/R) u2), arc length
+ * Any orthonormal pair gives the same points (the objects are symmetric
+ * about their axis / normal), only the parameter origin turns.
+ */
+static int param_dim(int t) { return (t == TP || t == TQ) ? 2 : 1; }
+
+/* Frame of an object's parameters; -1 if the record cannot be parametrised. */
+static int param_frame(int t, const double *r, double o[3], double e1[3], double e2[3], double *k)
+{
+    if (t == TP) {
+        double l = norm3(r + 7);
+        if (!(l > 0)) return -1;
+        for (int i = 0; i < 3; i++) { o[i] = r[4 + i]; e1[i] = r[7 + i] / l; }
+        cross3(r, e1, e2);
+        *k = 0.0;
+    } else if (t == TL) {
+        for (int i = 0; i < 3; i++) { o[i] = r[i]; e1[i] = r[3 + i]; e2[i] = 0.0; }
+        *k = 0.0;
+    } else if (t == TQ) {
+        const double *ax = r + 13;
+        double kap = 0.5 * (r[3] + r[6] + r[8]);
+        double A[3][3], err = fabs(r[12]);
+        quad_A(r, A);
+        for (int i = 0; i < 3; i++) {
+            err = fmax(err, fabs(r[9 + i] + ax[i]));
+            for (int j = 0; j < 3; j++)
+                err = fmax(err, fabs(A[i][j] - kap * ((i == j ? 1.0 : 0.0) - ax[i] * ax[j])));
+        }
+        if (!(kap > 0) || err > 1e-9 * (1.0 + kap)) return -1;
+        for (int i = 0; i < 3; i++) o[i] = r[i];
+        across(ax, e1, e2);
+        *k = kap;
+    } else {
+        for (int i = 0; i < 3; i++) o[i] = r[i];
+        across(r + 3, e1, e2);
+        *k = r[6];
+    }
+    return 0;
+}
+
+/* X(U) and its tangent columns dX/dU (T[.][1] unused for edges). */
+static int param_map(int t, const double *r, const double *U, double X[3], double T[3][2])
+{
+    double o[3], e1[3], e2[3], k;
+    if (param_frame(t, r, o, e1, e2, &k)) return -1;
+    if (t == TP) {
+        for (int i = 0; i < 3; i++) {
+            X[i] = o[i] + U[0] * e1[i] + U[1] * e2[i];
+            T[i][0] = e1[i];
+            T[i][1] = e2[i];
+        }
+    } else if (t == TL) {
+        for (int i = 0; i < 3; i++) {
+            X[i] = o[i] + U[0] * e1[i];
+            T[i][0] = e1[i];
+            T[i][1] = 0.0;
+        }
+    } else if (t == TQ) {
+        const double *ax = r + 13;
+        double h = k * (U[0] * U[0] + U[1] * U[1]);
+        for (int i = 0; i < 3; i++) {
+            X[i] = o[i] + U[0] * e1[i] + U[1] * e2[i] + h * ax[i];
+            T[i][0] = e1[i] + 2.0 * k * U[0] * ax[i];
+            T[i][1] = e2[i] + 2.0 * k * U[1] * ax[i];
+        }
+    } else {
+        double R = k, a = U[0] / R, ca = cos(a), sa = sin(a);
+        for (int i = 0; i < 3; i++) {
+            X[i] = o[i] + R * (ca * e1[i] + sa * e2[i]);
+            T[i][0] = -sa * e1[i] + ca * e2[i];
+            T[i][1] = 0.0;
+        }
+    }
+    return 0;
+}
+
+/* Parameters of a point (the start points are first put on the object). */
+static int param_of(int t, const double *r, const double X[3], double U[2])
+{
+    double o[3], e1[3], e2[3], k, d[3];
+    if (param_frame(t, r, o, e1, e2, &k)) return -1;
+    sub3(X, o, d);
+    U[1] = 0.0;
+    if (t == TP || t == TQ) {
+        U[0] = dot3(d, e1);
+        U[1] = dot3(d, e2);
+    } else if (t == TL) {
+        U[0] = dot3(d, e1);
+    } else {
+        U[0] = k * atan2(dot3(d, e2), dot3(d, e1));
+    }
+    return 0;
+}
+
+/* Law rows at X(U) and J = dI/dU ([rows][nu], nu = sum of the dims), built
+ * from the implicit residual's law rows and its Jacobian by the chain rule;
+ * returns the row count, or -1 (degenerate or not parametrisable). */
+int orc_param_residual(const orc_scene *s, const double rx[3], int n, const int32_t *ids, const double *U,
+                       double *R, double *J, double *Xout)
+{
+    double X[MAXU], T[MAXN][3][2];
+    int off[MAXN + 1], ty[MAXN];
+    off[0] = 0;
+    for (int k = 0; k < n; k++) {
+        const double *rec;
+        ty[k] = prim_type(s, ids[k], &rec);
+        if (ty[k] < 0 || param_map(ty[k], rec, U + off[k], X + 3 * k, T[k])) return -1;
+        off[k + 1] = off[k] + param_dim(ty[k]);
+    }
+    int nu = off[n];
+    double Rf[MAXR], Jf[MAXR * MAXU];
+    int mf = orc_residual(s, rx, n, ids, X, Rf, J ? Jf : NULL);
+    if (mf < 0) return -1;
+    if (J) memset(J, 0, sizeof(double) * (size_t)MAXR * nu);
+    int row = 0, rowf = 0;
+    for (int k = 0; k < n; k++) {
+        int surf = (ty[k] == TP || ty[k] == TQ);
+        int nl = surf ? 3 : 1, no = surf ? 1 : 2;
+        for (int i = 0; i < nl; i++, row++) {
+            R[row] = Rf[rowf + i];
+            if (!J) continue;
+            for (int b = k - 1; b <= k + 1; b++) {
+                if (b < 0 || b >= n) continue;
+                for (int c = 0; c < param_dim(ty[b]); c++) {
+                    double v = 0.0;
+                    for (int j = 0; j < 3; j++) v += Jf[(size_t)(rowf + i) * (3 * n) + 3 * b + j] * T[b][j][c];
+                    J[(size_t)row * nu + off[b] + c] = v;
+                }
+            }
+        }
+        rowf += nl + no;
+    }
+    if (Xout)
+        for (int j = 0; j < 3 * n; j++) Xout[j] = X[j];
+    return row;
+}
+
+int orc_solve_one_param(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                        const double *x0, const orc_lm_opts *o, double *X, double *cost, int32_t *iters)
+{
+    *iters = 0;
+    *cost = INFINITY;
+    if (!ids_ok(s, n, ids)) return ORC_BAD_INPUT;
+    for (int i = 0; i < 3; i++)
+        if (!isfinite(rx[i])) return ORC_BAD_INPUT;
+    double X0[MAXU], U[MAXU];
+    if (x0) {
+        for (int i = 0; i < 3 * n; i++) {
+            X0[i] = x0[i];
+            if (!isfinite(X0[i])) return ORC_BAD_INPUT;
+        }
+    } else {
+        orc_init_line(s, rx, n, ids, X0);
+    }
+    int nu = 0;
+    for (int k = 0; k < n; k++) {
+        const double *rec;
+        int t = prim_type(s, ids[k], &rec);
+        if (param_of(t, rec, X0 + 3 * k, U + nu)) return ORC_BAD_INPUT;
+        nu += param_dim(t);
+    }
+    double R[MAXR], J[MAXR * MAXU], A[MAXU * MAXU], g[MAXU], M[MAXU * MAXU], du[MAXU], mg[MAXU];
+    double Ut[MAXU], Rt[MAXR], Xt[MAXU];
+    double lam = 0, C = INFINITY, C_ref = INFINITY, rinf = INFINITY;
+    int status = ORC_MAXITER, small = 0;
+    for (int k = 0, off = 0; k < n; k++) {
+        const double *rec;
+        int t = prim_type(s, ids[k], &rec);
+        double T[3][2];
+        param_map(t, rec, U + off, X + 3 * k, T);
+        off += param_dim(t);
+    }
+    if (outside_guard(s, X, n)) return ORC_DIVERGED;
+    for (int it = 1; it <= o->max_iter; it++) {
+        *iters = it;
+        int m = orc_param_residual(s, rx, n, ids, U, R, J, X);
+        if (m < 0) { status = ORC_DEGENERATE; break; }
+        C = 0;
+        for (int r = 0; r < m; r++) C += R[r] * R[r];
+        rinf = inf_norm(R, m);
+        normal_eq(J, R, m, nu, A, g);
+        double dmax = 0;
+        for (int i = 0; i < nu; i++) dmax = fmax(dmax, A[i * nu + i]);
+        if (it == 1) { lam = o->lambda0 * dmax; C_ref = C; }
+        if (rinf <= o->tol_res) { small = 1; break; }
+        if (o->plateau_win > 0 && it > 1 && (it - 1) % o->plateau_win == 0) {
+            if (C > o->plateau_frac * C_ref) { small = 1; break; }
+            C_ref = C;
+        }
+        for (int i = 0; i < nu * nu; i++) M[i] = A[i];
+        for (int i = 0; i < nu; i++) M[i * nu + i] += lam * fmax(A[i * nu + i], 1e-12 * dmax);
+        if (cholesky(M, nu)) {
+            lam *= 10.0;
+            if (lam > 1e12 * dmax) { status = ORC_STALLED; break; }
+            continue;
+        }
+        for (int i = 0; i < nu; i++) mg[i] = -g[i];
+        chol_solve(M, nu, mg, du);
+        for (int i = 0; i < nu; i++) Ut[i] = U[i] + du[i];
+        int is_small = inf_norm(du, nu) <= o->tol_step * (1.0 + inf_norm(U, nu));
+        int mt = orc_param_residual(s, rx, n, ids, Ut, Rt, NULL, Xt);
+        if (mt == m && outside_guard(s, Xt, n)) mt = -1;
+        double Ct = INFINITY;
+        if (mt == m) {
+            Ct = 0;
+            for (int r = 0; r < m; r++) Ct += Rt[r] * Rt[r];
+        }
+        if (Ct < C) {
+            for (int i = 0; i < nu; i++) U[i] = Ut[i];
+            for (int j = 0; j < 3 * n; j++) X[j] = Xt[j];
+            C = Ct;
+            rinf = inf_norm(Rt, m);
+            lam = fmax(lam / 10.0, 1e-15 * dmax);
+            if (is_small) { small = 1; break; }
+        } else {
+            if (is_small) { small = 1; break; }
+            lam *= 10.0;
+            if (lam > 1e12 * dmax) { status = ORC_STALLED; break; }
+        }
+    }
+    *cost = C;
+    if (small) status = (rinf <= o->tau_root) ? ORC_CONVERGED : ORC_LOCALMIN;
+    return status;
+}
+
 /* ------------------------------------------------------------ acceptance */
 static int in_extent(int t, const double *r, const double *X)
 {
@@ -587,6 +824,35 @@ void orc_solve_batch(const orc_scene *s, int64_t nb, const double *rx, const int
                      : ORC_BAD_INPUT;
         if (!(n >= 1 && n <= MAXN)) { c = INFINITY; it = 0; }
         for (int j = 0; j < MAXU; j++) x[j * nb + i] = (j < 3 * n) ? X[j] : 0.0;
+        cost[i] = c;
+        iters[i] = it;
+        status[i] = (uint8_t)st;
+    }
+}
+
+void orc_solve_batch_param(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                           const int32_t *order, const int32_t *prim, const double *x0,
+                           const orc_lm_opts *o, double *x, double *cost, int32_t *iters,
+                           uint8_t *status, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < nb; i++) {
+        int n = order[i];
+        int32_t ids[MAXN];
+        double X[MAXU], X0[MAXU];
+        for (int k = 0; k < MAXN; k++) ids[k] = prim[k * nb + i];
+        if (x0)
+            for (int j = 0; j < MAXU; j++) X0[j] = x0[j * nb + i];
+        for (int j = 0; j < MAXU; j++) X[j] = 0.0;
+        double c = INFINITY;
+        int32_t it = 0;
+        int st = (n >= 1 && n <= MAXN)
+                     ? orc_solve_one_param(s, rx + 3 * (size_t)rx_index[i], n, ids, x0 ? X0 : NULL, o, X, &c, &it)
+                     : ORC_BAD_INPUT;
+        for (int j = 0; j < MAXU; j++) x[j * nb + i] = (n >= 1 && n <= MAXN && j < 3 * n) ? X[j] : 0.0;
         cost[i] = c;
         iters[i] = it;
         status[i] = (uint8_t)st;

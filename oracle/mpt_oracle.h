@@ -94,6 +94,23 @@ void orc_init_random_batch(const orc_scene *s, uint64_t seed, int64_t nb, const 
 int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
                   const double *x0, const orc_lm_opts *o, double *X, double *cost, int32_t *iters);
 
+/* Parametric form (Eqs. (13)-(15)): unknowns are 2 parameters per surface
+ * and 1 per edge, only the law rows remain.  orc_param_residual returns the
+ * law rows at X(U) and J = dI/dU ([rows][nu]), and X(U) in Xout (may be
+ * NULL).  orc_solve_one_param solves from the parameters of the start
+ * points x0 (or of the straight-line start) with the same Levenberg-
+ * Marquardt rules, and returns X(U).  Paraboloids must be of revolution
+ * (A = kappa (I - ax ax^T), b = -ax, c = 0); other quadrics give
+ * ORC_BAD_INPUT. */
+int orc_param_residual(const orc_scene *s, const double rx[3], int n, const int32_t *ids, const double *U,
+                       double *R, double *J, double *Xout);
+int orc_solve_one_param(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
+                        const double *x0, const orc_lm_opts *o, double *X, double *cost, int32_t *iters);
+void orc_solve_batch_param(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                           const int32_t *order, const int32_t *prim, const double *x0,
+                           const orc_lm_opts *o, double *x, double *cost, int32_t *iters,
+                           uint8_t *status, int nthreads);
+
 /* Finite-object acceptance of a solved path (1 accepted / 0 rejected). */
 int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
                    const double *X, int status, double tau_res, double min_seg);

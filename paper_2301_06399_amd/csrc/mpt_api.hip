@@ -7,6 +7,7 @@
 #include <string.h>
 #include <string>
 #include <vector>
+#include <algorithm>
 
 #include "../../include/mpt.h"
 #include "mpt_internal.hpp"
@@ -614,19 +615,23 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     float best = 1e30f;
     Cand bc = cands[0];
     for (const Cand &cd : cands) {
-        // the fastest of the timed runs after one warm-up run (five runs,
-        // two when one run takes more than 20 ms)
-        float tmin = 1e30f;
+        // the median of the timed runs after one warm-up run (five runs,
+        // three when one run takes more than 20 ms): concurrent launches
+        // vary more from run to run, and the typical run is what counts
+        float t[5];
+        int nt = 0;
         for (int rep = 0, reps = 6; rep < reps; rep++) {
             if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv, cd.spill)))
                 return st;
             HIPCHK(c, hipEventSynchronize(c->ev[6]));
             float ms = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[6]));  // LM, stragglers, polish and fallback
-            if (rep == 0 && ms > 20.0f) reps = 3;
-            if (rep > 0 && ms < tmin) tmin = ms;
+            if (rep == 0 && ms > 20.0f) reps = 4;
+            if (rep > 0) t[nt++] = ms;
         }
-        if (tmin < best) best = tmin, bc = cd;
+        std::sort(t, t + nt);
+        const float med = t[nt / 2];
+        if (med < best) best = med, bc = cd;
     }
     bool found = false;
     for (auto &t : c->tune)

@@ -93,8 +93,10 @@ def prepare(ctx, scene, batch, steps=None, n_rx=8192, log=sys.stderr):
         cfg, per_rx = 2, 64
     t = time.time()
     sc, tb = W.training_batch(cfg, n_rx=n_rx, per_rx=per_rx)
-    if not (np.allclose(sc.planes, scene.planes) and np.allclose(sc.quadrics, scene.quadrics)):
-        return False
+    same = all(np.shape(getattr(sc, k)) == np.shape(getattr(scene, k)) and
+               np.allclose(getattr(sc, k), getattr(scene, k)) for k in ("planes", "lines", "quadrics", "circles"))
+    if not same:
+        return False  # no training generator for this scene
     hist = train(ctx, sc, tb, steps=steps or 3000, log=log)
     ctx.upload_scene(scene)
     if log:
