@@ -137,6 +137,8 @@ enum { MPT_FP64_PLAIN = 0, MPT_FP32_POLISH64 = 1 };
 enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2, MPT_INIT_LEARNED_ALL = 3,
        MPT_INIT_RANDOM = 4 };
 enum { MPT_FALLBACK_NONE = 0, MPT_FALLBACK_GPU_FP64 = 1 };
+/* Formulation of the minimisation (paper Sec. III-B). */
+enum { MPT_FORM_IMPLICIT = 0, MPT_FORM_PARAMETRIC = 1 };
 /* MPT_SCHED_PERSISTENT: one persistent launch runs every order's bin;
  * MPT_SCHED_PER_ORDER: one persistent launch per order, with its own
  * register budget, all five running concurrently on forked streams. */
@@ -177,7 +179,13 @@ typedef struct {
                               order's queue is empty, a wave with at most this
                               many busy lanes parks them for a second, densely
                               packed launch (results are unchanged)           */
-    int32_t reserved;      /* 0 */
+    int32_t form;          /* MPT_FORM_IMPLICIT: the points are the unknowns
+                              (Eq. 12); MPT_FORM_PARAMETRIC: 2 parameters per
+                              surface, 1 per edge (Eqs. 13-15), for the first
+                              LM pass (the polish and the fallback stay
+                              implicit).  Paraboloids must be of revolution
+                              (A = k (I - ax ax^T), b = -ax, c = 0); another
+                              quadric makes its paths MPT_PATH_BAD_INPUT     */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 
@@ -300,8 +308,11 @@ mpt_status mpt_mlp_load(mpt_ctx *ctx, const void *blob, size_t bytes);
  *   out[1] one Gauss-Newton polish step (no trial cost)
  *   out[2] one residual evaluation (the acceptance test's arithmetic)
  *   out[3] square roots and divisions inside out[0]
- * Host only (no device work).  MPT_E_INVALID_ARG for a bad order or type. */
-mpt_status mpt_flops_per_iter(int order, const int32_t *types, int64_t out[4]);
+ * With form = MPT_FORM_PARAMETRIC, out[0], out[2] and out[3] are those of the
+ * parametric form (out[1], the polish, is implicit in both).
+ * Host only (no device work).  MPT_E_INVALID_ARG for a bad order, type or
+ * form. */
+mpt_status mpt_flops_per_iter(int order, const int32_t *types, int32_t form, int64_t out[4]);
 
 /* Per-stage timings of the last mpt_solve_batch in milliseconds (HIP events
  * on the context's stream; synchronises): [0] order binning, [1] learned

@@ -531,9 +531,25 @@ int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *
  *                      b = -ax, c = 0, so kappa = trace(A)/2
  *   circle     (phi)   X = c + R (cos(phi/R) u1 + sin(phi/R) u2), arc length
  * Any orthonormal pair gives the same points (the objects are symmetric
- * about their axis / normal), only the parameter origin turns.
+ * about their axis / normal), only the parameter origin turns; the pair is
+ * Duff et al.'s construction.
  */
 static int param_dim(int t) { return (t == TP || t == TQ) ? 2 : 1; }
+
+/* Orthonormal pair across a unit vector a, by the branch-free construction
+ * of Duff et al., "Building an Orthonormal Basis, Revisited" (JCGT 2017). */
+static void onb_duff(const double *a, double u1[3], double u2[3])
+{
+    double sg = a[2] >= 0.0 ? 1.0 : -1.0;
+    double q = -1.0 / (sg + a[2]);
+    double b = a[0] * a[1] * q;
+    u1[0] = 1.0 + sg * a[0] * a[0] * q;
+    u1[1] = sg * b;
+    u1[2] = -sg * a[0];
+    u2[0] = b;
+    u2[1] = sg + a[1] * a[1] * q;
+    u2[2] = -a[1];
+}
 
 /* Frame of an object's parameters; -1 if the record cannot be parametrised. */
 static int param_frame(int t, const double *r, double o[3], double e1[3], double e2[3], double *k)
@@ -559,11 +575,11 @@ static int param_frame(int t, const double *r, double o[3], double e1[3], double
         }
         if (!(kap > 0) || err > 1e-9 * (1.0 + kap)) return -1;
         for (int i = 0; i < 3; i++) o[i] = r[i];
-        across(ax, e1, e2);
+        onb_duff(ax, e1, e2);
         *k = kap;
     } else {
         for (int i = 0; i < 3; i++) o[i] = r[i];
-        across(r + 3, e1, e2);
+        onb_duff(r + 3, e1, e2);
         *k = r[6];
     }
     return 0;

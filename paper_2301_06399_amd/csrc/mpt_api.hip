@@ -46,7 +46,7 @@ struct mpt_ctx {
     bool timed = false;
     MlpState *mlp = nullptr;
     // autotuned launch choices: key -> (sched, block)
-    struct Tune { int prec, nbucket, n_all, sched, block, gdiv, spill; float ms; };
+    struct Tune { int prec, form, nbucket, n_all, sched, block, gdiv, spill; float ms; };
     std::vector<Tune> tune;
     bool tune_loaded = false;
     // captured graph of the last solve (replayed while the key matches)
@@ -282,7 +282,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->polish_gate = 1e-2;
     o->seed = 0;
     o->spill = -1;
-    o->reserved = 0;
+    o->form = MPT_FORM_IMPLICIT;
 }
 
 static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)
@@ -344,10 +344,10 @@ static void tune_load(mpt_ctx *c)
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    // one entry per line: prec nbucket n_all sched block gdiv spill ms
+    // one entry per line: prec form nbucket n_all sched block gdiv spill ms
     mpt_ctx::Tune t;
-    while (fscanf(f, "%d %d %d %d %d %d %d %f", &t.prec, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.gdiv, &t.spill,
-                  &t.ms) == 8)
+    while (fscanf(f, "%d %d %d %d %d %d %d %d %f", &t.prec, &t.form, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.gdiv,
+                  &t.spill, &t.ms) == 9)
         c->tune.push_back(t);
     fclose(f);
 }
@@ -359,7 +359,8 @@ static void tune_save(mpt_ctx *c)
     FILE *f = fopen(path, "w");
     if (!f) return;
     for (auto &t : c->tune)
-        fprintf(f, "%d %d %d %d %d %d %d %.6f\n", t.prec, t.nbucket, t.n_all, t.sched, t.block, t.gdiv, t.spill, t.ms);
+        fprintf(f, "%d %d %d %d %d %d %d %d %.6f\n", t.prec, t.form, t.nbucket, t.n_all, t.sched, t.block, t.gdiv,
+                t.spill, t.ms);
     fclose(f);
 }
 
@@ -368,7 +369,7 @@ static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, i
     default_choice(o->precision, sched, block, gdiv, spill);
     tune_load(c);
     for (auto &t : c->tune)
-        if (t.prec == o->precision && t.nbucket == nbucket(n) && t.n_all == c->s.n_all) {
+        if (t.prec == o->precision && t.form == o->form && t.nbucket == nbucket(n) && t.n_all == c->s.n_all) {
             sched = t.sched;
             block = t.block;
             gdiv = t.gdiv;
@@ -404,6 +405,8 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
         return fail(c, MPT_E_UNSUPPORTED, "sched %d", opts->sched);
     if (opts->grid < 0) return fail(c, MPT_E_INVALID_ARG, "negative grid");
     if (opts->spill < -1 || opts->spill > 64) return fail(c, MPT_E_INVALID_ARG, "spill must be -1..64");
+    if (opts->form != MPT_FORM_IMPLICIT && opts->form != MPT_FORM_PARAMETRIC)
+        return fail(c, MPT_E_UNSUPPORTED, "form %d", opts->form);
     return MPT_OK;
 }
 
@@ -492,7 +495,8 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
         const size_t rec_bytes = (size_t)c->s.n_all * kRec * (md == MODE_FP32 ? sizeof(float) : sizeof(double));
         const bool lds = rec_bytes <= c->lds_max;
         auto go = [&](int ord, hipStream_t where) {
-            const void *k = lm_kernel(md, ord, lds);
+            const int form = (md == MODE_FALLBACK64) ? MPT_FORM_IMPLICIT : opts->form;
+            const void *k = lm_kernel(md, ord, lds, form);
             if (lds) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rec_bytes);
             int g = opts->grid;
             if (!g) {
@@ -501,7 +505,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
                 g = resident_grid(c, k, blk, n, lds ? rec_bytes : 0);
                 if (first && gdiv > 1) g = (g + gdiv - 1) / gdiv;
             }
-            launch_lm(md, ord, lds, rec_bytes, kp, g, blk, where);
+            launch_lm(md, ord, lds, form, rec_bytes, kp, g, blk, where);
         };
         if (sch == MPT_SCHED_PERSISTENT) {
             go(0, s);
@@ -635,10 +639,11 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     }
     bool found = false;
     for (auto &t : c->tune)
-        if (t.prec == opts->precision && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
+        if (t.prec == opts->precision && t.form == opts->form && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
             t.sched = bc.sched, t.block = bc.block, t.gdiv = bc.gdiv, t.spill = bc.spill, t.ms = best, found = true;
     if (!found)
-        c->tune.push_back({opts->precision, nbucket(b->n), c->s.n_all, bc.sched, bc.block, bc.gdiv, bc.spill, best});
+        c->tune.push_back({opts->precision, opts->form, nbucket(b->n), c->s.n_all, bc.sched, bc.block, bc.gdiv,
+                           bc.spill, best});
     tune_save(c);
     if (best_sched) *best_sched = bc.sched;
     if (best_block) *best_block = bc.block;
@@ -652,7 +657,7 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
 
 // ---------------------------------------------------------------- FLOP count
 template <int N>
-static void count_one(const int32_t *types, int64_t out[4])
+static void count_one(const int32_t *types, int64_t out[4], bool param)
 {
     // a small synthetic scene: one record per interaction with generic
     // (non-zero, non-special) values, so no operation is skipped by accident
@@ -710,19 +715,45 @@ static void count_one(const int32_t *types, int64_t out[4])
     tally() = FlopTally();
     eval_cost<Cnt, N>(sc, p, X, nullptr, C, rinf);
     out[2] = tally().flops();
+    if (!param) return;
+    // the parametric form: one iteration over the 2N parameters (the polish
+    // stays implicit); an edge's placeholder parameter costs nothing
+    Cnt U[2 * N], Ap[Band<N, 2>::SIZE], gp[2 * N];
+    for (int k = 0; k < N; k++) {
+        U[2 * k] = Cnt(rnd());
+        U[2 * k + 1] = (types[k] == MPT_PLANE || types[k] == MPT_QUADRIC) ? Cnt(rnd()) : Cnt(0.0);
+    }
+    tally() = FlopTally();
+    assemble_param<Cnt, N>(sc, p, U, Ap, gp, C, rinf);
+    for (int i = 0; i < 2 * N; i++) {
+        const bool real = (i % 2 == 0) || types[i / 2] == MPT_PLANE || types[i / 2] == MPT_QUADRIC;
+        Cnt &d = Ap[Band<N, 2>::at(i, i)];
+        d = real ? d + lam * fmax(d, Cnt(1e-12) * dmax) : Cnt(1.0);
+    }
+    chol_band<Cnt, N, 2>(Ap);
+    chol_solve_band<Cnt, N, 2>(Ap, gp);
+    bool guard;
+    eval_cost_param<Cnt, N>(sc, p, U, gp, Ct, rt, guard);
+    out[0] = tally().flops();
+    out[3] = tally().sqrt + tally().div;
+    tally() = FlopTally();
+    eval_cost_param<Cnt, N>(sc, p, U, nullptr, C, rinf, guard);
+    out[2] = tally().flops();
 }
 
-extern "C" mpt_status mpt_flops_per_iter(int order, const int32_t *types, int64_t out[4])
+extern "C" mpt_status mpt_flops_per_iter(int order, const int32_t *types, int32_t form, int64_t out[4])
 {
     if (!types || !out || order < 1 || order > MPT_MAX_ORDER) return MPT_E_INVALID_ARG;
+    if (form != MPT_FORM_IMPLICIT && form != MPT_FORM_PARAMETRIC) return MPT_E_INVALID_ARG;
     for (int k = 0; k < order; k++)
         if (types[k] < MPT_PLANE || types[k] > MPT_CIRCLE) return MPT_E_INVALID_ARG;
+    const bool param = form == MPT_FORM_PARAMETRIC;
     switch (order) {
-    case 1: count_one<1>(types, out); break;
-    case 2: count_one<2>(types, out); break;
-    case 3: count_one<3>(types, out); break;
-    case 4: count_one<4>(types, out); break;
-    default: count_one<5>(types, out); break;
+    case 1: count_one<1>(types, out, param); break;
+    case 2: count_one<2>(types, out, param); break;
+    case 3: count_one<3>(types, out, param); break;
+    case 4: count_one<4>(types, out, param); break;
+    default: count_one<5>(types, out, param); break;
     }
     return MPT_OK;
 }

@@ -268,11 +268,15 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
 }
 
 // ------------------------------------------------------------------ band
-template <int N>
+// Packed lower band of J^T J for N interactions of B unknowns each (B = 3:
+// the points, B = 2: the parameters of the parametric form); an interaction's
+// rows couple its own block and its two neighbours, so block (I, J) is
+// nonzero only for |I - J| <= 2.
+template <int N, int B = 3>
 struct Band {
-    static constexpr int M = 3 * N;
+    static constexpr int M = B * N;
     static constexpr int SIZE = M * (M + 1) / 2;
-    __host__ __device__ static constexpr bool in(int i, int j) { return i >= j && (i / 3 - j / 3) <= 2; }
+    __host__ __device__ static constexpr bool in(int i, int j) { return i >= j && (i / B - j / B) <= 2; }
     __host__ __device__ static constexpr int at(int i, int j) { return i * (i + 1) / 2 + j; }
 };
 
@@ -393,55 +397,262 @@ __host__ __device__ __forceinline__ bool assemble(const SceneT<T> &sc, const Pat
     return ok;
 }
 
+// ------------------------------------------------------------------ parametric form
+// Eqs. (13)-(15): two parameters per interaction (metres), the points are
+// X(U) and only the law rows remain.  An edge has one parameter; its second
+// slot is a placeholder with a zero Jacobian column.
+//   plane      X = o + s e1 + t e2          (e1 packed in slots 13..15, e2 = n x e1)
+//   line       X = p + s e
+//   paraboloid X = p + s e1 + t e2 + kappa (s^2 + t^2) ax, (e1, e2) across the
+//              axis, kappa packed in slot 17 (negative: not parametrisable)
+//   circle     X = c + R (cos(s/R) u1 + sin(s/R) u2), (u1, u2) packed in slots 7..12
+// Returns false if the record has no such parametrisation.
+template <typename T>
+__host__ __device__ __forceinline__ void across_dir(const T *a, T u1[3], T u2[3])
+{
+    // branch-free orthonormal pair across a unit vector (Duff et al. 2017)
+    const T sg = a[2] >= T(0) ? T(1) : T(-1);
+    const T q = T(-1) / (sg + a[2]);
+    const T b = a[0] * a[1] * q;
+    u1[0] = T(1) + sg * a[0] * a[0] * q;
+    u1[1] = sg * b;
+    u1[2] = -sg * a[0];
+    u2[0] = b;
+    u2[1] = sg + a[1] * a[1] * q;
+    u2[2] = -a[1];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ bool param_map(int t, const T *__restrict__ r, T s, T u, T X[3], T Tm[3][2])
+{
+    bool ok = true;
+    if (t == TP) {
+        const T e2[3] = {r[1] * r[15] - r[2] * r[14], r[2] * r[13] - r[0] * r[15], r[0] * r[14] - r[1] * r[13]};
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            X[i] = r[4 + i] + s * r[13 + i] + u * e2[i];
+            Tm[i][0] = r[13 + i];
+            Tm[i][1] = e2[i];
+        }
+    } else if (t == TL) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            X[i] = r[i] + s * r[3 + i];
+            Tm[i][0] = r[3 + i];
+            Tm[i][1] = T(0);
+        }
+    } else if (t == TQ) {
+        T e1[3], e2[3];
+        across_dir(r + 13, e1, e2);
+        const T k = r[17];
+        ok = k > T(0);
+        const T h = k * (s * s + u * u), k2 = T(2) * k;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            X[i] = r[i] + s * e1[i] + u * e2[i] + h * r[13 + i];
+            Tm[i][0] = e1[i] + k2 * s * r[13 + i];
+            Tm[i][1] = e2[i] + k2 * u * r[13 + i];
+        }
+    } else {
+        const T R = r[6], a = s * drcp(R);
+        const T ca = cos(a), sa = sin(a);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            X[i] = r[i] + R * (ca * r[7 + i] + sa * r[10 + i]);
+            Tm[i][0] = -sa * r[7 + i] + ca * r[10 + i];
+            Tm[i][1] = T(0);
+        }
+    }
+    return ok;
+}
+
+// Parameters of a point of an object (the start points, already put on it).
+__host__ __device__ __forceinline__ bool param_of(int t, const double *__restrict__ r, const double X[3],
+                                                  double U[2])
+{
+    U[1] = 0.0;
+    if (t == TP) {
+        const double d[3] = {X[0] - r[4], X[1] - r[5], X[2] - r[6]};
+        const double e2[3] = {r[1] * r[15] - r[2] * r[14], r[2] * r[13] - r[0] * r[15], r[0] * r[14] - r[1] * r[13]};
+        U[0] = d[0] * r[13] + d[1] * r[14] + d[2] * r[15];
+        U[1] = dot3(d, e2);
+        return true;
+    }
+    const double d[3] = {X[0] - r[0], X[1] - r[1], X[2] - r[2]};
+    if (t == TL) {
+        U[0] = d[0] * r[3] + d[1] * r[4] + d[2] * r[5];
+        return true;
+    }
+    if (t == TQ) {
+        double e1[3], e2[3];
+        across_dir(r + 13, e1, e2);
+        U[0] = dot3(d, e1);
+        U[1] = dot3(d, e2);
+        return r[17] > 0.0;
+    }
+    U[0] = r[6] * atan2(d[0] * r[10] + d[1] * r[11] + d[2] * r[12], d[0] * r[7] + d[1] * r[8] + d[2] * r[9]);
+    return true;
+}
+
+// Law rows of the parametric form at X(U + dU) (dU may be null): cost, inf
+// norm, and whether every trial point stays in the guard box.
+template <typename T, int N>
+__host__ __device__ __forceinline__ bool eval_cost_param(const SceneT<T> &sc, const PathIn<T, N> &p, const T *U,
+                                                const T *dU, T &C, T &rinf, bool &guard)
+{
+    T X[3 * N], Tm[3][2];
+    bool ok = true;
+    guard = true;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const T s = U[2 * k] + (dU ? dU[2 * k] : T(0)), u = U[2 * k + 1] + (dU ? dU[2 * k + 1] : T(0));
+        ok = param_map<T>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, s, u, X + 3 * k, Tm) && ok;
+#pragma unroll
+        for (int i = 0; i < 3; i++) guard = guard && (X[3 * k + i] >= sc.glo[i]) && (X[3 * k + i] <= sc.ghi[i]);
+    }
+    C = T(0);
+    rinf = T(0);
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        T Xp[3], Xn[3], u[5];
+        point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
+        point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
+        const bool okk = interaction_rows<T, false>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
+                                                    nullptr, nullptr, nullptr);
+        ok = ok && okk;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            C += u[i] * u[i];
+            rinf = fmax(rinf, fabs(u[i]));
+        }
+    }
+    return ok;
+}
+
+// Normal equations of the parametric form: band of J^T J (2 x 2 blocks) and
+// J^T I, with J = dI/dX . dX/dU by the chain rule.
+template <typename T, int N>
+__host__ __device__ __forceinline__ bool assemble_param(const SceneT<T> &sc, const PathIn<T, N> &p, const T *U, T *A,
+                                               T *g, T &C, T &rinf)
+{
+    constexpr int M = 2 * N;
+#pragma unroll
+    for (int i = 0; i < M; i++)
+#pragma unroll
+        for (int j = 0; j <= i; j++)
+            if (Band<N, 2>::in(i, j)) A[Band<N, 2>::at(i, j)] = T(0);
+#pragma unroll
+    for (int i = 0; i < M; i++) g[i] = T(0);
+    T X[3 * N], Tm[N][3][2];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; k++)
+        ok = param_map<T>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, U[2 * k], U[2 * k + 1], X + 3 * k, Tm[k]) && ok;
+    C = T(0);
+    rinf = T(0);
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        T Xp[3], Xn[3], u[5], Jp[3][3], Jk[5][3], Jn[3][3];
+        point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
+        point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
+        const bool okk = interaction_rows<T, true>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
+                                                   Jp, Jk, Jn);
+        ok = ok && okk;
+#pragma unroll
+        for (int row = 0; row < 3; row++) {
+            C += u[row] * u[row];
+            rinf = fmax(rinf, fabs(u[row]));
+            // the row's derivatives with respect to the parameters of
+            // interactions k-1, k, k+1
+            T jr[6];
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                T vp = T(0), vk = T(0), vn = T(0);
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    if (k > 0) vp += Jp[row][j] * Tm[k > 0 ? k - 1 : 0][j][c];
+                    vk += Jk[row][j] * Tm[k][j][c];
+                    if (k + 1 < N) vn += Jn[row][j] * Tm[k + 1 < N ? k + 1 : 0][j][c];
+                }
+                jr[c] = vp;
+                jr[2 + c] = vk;
+                jr[4 + c] = vn;
+            }
+#pragma unroll
+            for (int bi = 0; bi < 3; bi++) {
+                const int Bi = k - 1 + bi;
+                if (Bi < 0 || Bi >= N) continue;
+#pragma unroll
+                for (int ci = 0; ci < 2; ci++) {
+                    const int gi = 2 * Bi + ci;
+                    g[gi] += jr[2 * bi + ci] * u[row];
+#pragma unroll
+                    for (int bj = 0; bj < 3; bj++) {
+                        const int Bj = k - 1 + bj;
+                        if (Bj < 0 || Bj >= N) continue;
+#pragma unroll
+                        for (int cj = 0; cj < 2; cj++) {
+                            const int gj = 2 * Bj + cj;
+                            if (gj > gi) continue;
+                            A[Band<N, 2>::at(gi, gj)] += jr[2 * bi + ci] * jr[2 * bj + cj];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return ok;
+}
+
 // In-place banded Cholesky of the packed lower band; false if not SPD.  The
 // diagonal slots receive the INVERSE of L's diagonal (the solves multiply).
-template <typename T, int N>
+template <typename T, int N, int B = 3>
 __host__ __device__ __forceinline__ bool chol_band(T *A)
 {
-    constexpr int M = 3 * N;
+    constexpr int M = B * N;
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < M; j++) {
-        T d = A[Band<N>::at(j, j)];
+        T d = A[Band<N, B>::at(j, j)];
 #pragma unroll
         for (int k = 0; k < j; k++)
-            if (Band<N>::in(j, k)) d -= A[Band<N>::at(j, k)] * A[Band<N>::at(j, k)];
+            if (Band<N, B>::in(j, k)) d -= A[Band<N, B>::at(j, k)] * A[Band<N, B>::at(j, k)];
         ok = ok && (d > T(0));
         const T inv = drsqrt(d > T(0) ? d : T(1));
-        A[Band<N>::at(j, j)] = inv;
+        A[Band<N, B>::at(j, j)] = inv;
 #pragma unroll
         for (int i = j + 1; i < M; i++) {
-            if (!Band<N>::in(i, j)) continue;
-            T v = A[Band<N>::at(i, j)];
+            if (!Band<N, B>::in(i, j)) continue;
+            T v = A[Band<N, B>::at(i, j)];
 #pragma unroll
             for (int k = 0; k < j; k++)
-                if (Band<N>::in(i, k) && Band<N>::in(j, k)) v -= A[Band<N>::at(i, k)] * A[Band<N>::at(j, k)];
-            A[Band<N>::at(i, j)] = v * inv;
+                if (Band<N, B>::in(i, k) && Band<N, B>::in(j, k)) v -= A[Band<N, B>::at(i, k)] * A[Band<N, B>::at(j, k)];
+            A[Band<N, B>::at(i, j)] = v * inv;
         }
     }
     return ok;
 }
 
 // Solve L L^T x = b in place (b -> x); the diagonal holds 1 / L_ii.
-template <typename T, int N>
+template <typename T, int N, int B = 3>
 __host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
 {
-    constexpr int M = 3 * N;
+    constexpr int M = B * N;
 #pragma unroll
     for (int i = 0; i < M; i++) {
         T v = b[i];
 #pragma unroll
         for (int k = 0; k < i; k++)
-            if (Band<N>::in(i, k)) v -= L[Band<N>::at(i, k)] * b[k];
-        b[i] = v * L[Band<N>::at(i, i)];
+            if (Band<N, B>::in(i, k)) v -= L[Band<N, B>::at(i, k)] * b[k];
+        b[i] = v * L[Band<N, B>::at(i, i)];
     }
 #pragma unroll
     for (int i = M - 1; i >= 0; i--) {
         T v = b[i];
 #pragma unroll
         for (int k = i + 1; k < M; k++)
-            if (Band<N>::in(k, i)) v -= L[Band<N>::at(k, i)] * b[k];
-        b[i] = v * L[Band<N>::at(i, i)];
+            if (Band<N, B>::in(k, i)) v -= L[Band<N, B>::at(k, i)] * b[k];
+        b[i] = v * L[Band<N, B>::at(i, i)];
     }
 }
 

@@ -47,5 +47,9 @@ inline Cnt dsqrt(Cnt a) { if (nz(a)) tally().sqrt++; return Cnt(::sqrt(a.v)); }
 // square root plus a division
 inline Cnt drcp(Cnt a) { if (nz(a)) tally().div++; return Cnt(1.0 / a.v); }
 inline Cnt drsqrt(Cnt a) { if (nz(a)) tally().sqrt++, tally().div++; return Cnt(1.0 / ::sqrt(a.v)); }
+// the sine and cosine of the circle's parametrisation count as one
+// operation each (counted with the square roots and divisions)
+inline Cnt sin(Cnt a) { tally().sqrt++; return Cnt(::sin(a.v)); }
+inline Cnt cos(Cnt a) { tally().sqrt++; return Cnt(::cos(a.v)); }
 
 }  // namespace mpt

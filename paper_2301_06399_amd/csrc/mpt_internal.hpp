@@ -79,8 +79,8 @@ void launch_zero(int *p, int n, hipStream_t st);
 int bin_key_count();
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
                 hipStream_t st);
-const void *lm_kernel(int mode, int order, bool lds);
-void launch_lm(int mode, int order, bool lds, size_t lds_bytes, const KParams &kp, int grid, int block,
+const void *lm_kernel(int mode, int order, bool lds, int form);
+void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const KParams &kp, int grid, int block,
                hipStream_t st);
 const void *polish_kernel();
 void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st);

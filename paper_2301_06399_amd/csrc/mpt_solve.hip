@@ -16,15 +16,6 @@ namespace mpt {
 // ------------------------------------------------------------------ pack
 // Ortho-normal pair across a unit vector (Duff et al., "Building an
 // orthonormal basis, revisited", JCGT 2017).
-__device__ inline void onb(const double *n, double *u1, double *u2)
-{
-    const double sgn = n[2] >= 0.0 ? 1.0 : -1.0;
-    const double a = -1.0 / (sgn + n[2]);
-    const double b = n[0] * n[1] * a;
-    u1[0] = 1.0 + sgn * n[0] * n[0] * a; u1[1] = sgn * b; u1[2] = -sgn * n[0];
-    u2[0] = b; u2[1] = sgn + n[1] * n[1] * a; u2[2] = -n[1];
-}
-
 __global__ void k_pack(const double *__restrict__ raw, int n_pl, int n_ln, int n_q, int n_c, double tx0, double tx1,
                        double tx2, double *__restrict__ rec64, float *__restrict__ rec32)
 {
@@ -45,7 +36,25 @@ __global__ void k_pack(const double *__restrict__ raw, int n_pl, int n_ln, int n
     const double *r = raw + off;
     const int w = (t == TP) ? 13 : (t == TL) ? 8 : (t == TQ) ? 17 : 7;
     for (int i = 0; i < w; i++) o[i] = r[i];
-    if (t == TL) onb(r + 3, o + 8, o + 11);
+    if (t == TL) across_dir(r + 3, o + 8, o + 11);
+    // frames of the parametric form
+    if (t == TP) {
+        const double l = sqrt(r[7] * r[7] + r[8] * r[8] + r[9] * r[9]);
+        for (int i = 0; i < 3; i++) o[13 + i] = l > 0.0 ? r[7 + i] / l : 0.0;
+    }
+    if (t == TC) across_dir(r + 3, o + 7, o + 10);
+    if (t == TQ) {
+        // a paraboloid of revolution: A = kappa (I - ax ax^T), b = -ax, c = 0
+        const double kap = 0.5 * (r[3] + r[6] + r[8]);
+        const double *ax = r + 13;
+        const double Am[3][3] = {{r[3], r[4], r[5]}, {r[4], r[6], r[7]}, {r[5], r[7], r[8]}};
+        double err = fabs(r[12]);
+        for (int i = 0; i < 3; i++) {
+            err = fmax(err, fabs(r[9 + i] + ax[i]));
+            for (int j = 0; j < 3; j++) err = fmax(err, fabs(Am[i][j] - kap * ((i == j ? 1.0 : 0.0) - ax[i] * ax[j])));
+        }
+        o[17] = (kap > 0.0 && err <= 1e-9 * (1.0 + kap)) ? kap : -1.0;
+    }
     for (int i = 0; i < kRec; i++) rec64[(size_t)id * kRec + i] = o[i];
     // TX-local FP32 copy: positions shifted by TX, plane offsets adjusted
     double l[kRec];
@@ -280,7 +289,7 @@ __device__ inline void project(int t, const double *r, const double *P, double *
         double lw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
         if (!(lw > 0.0)) {
             double u2[3];
-            onb(r + 3, w, u2);
+            across_dir(r + 3, w, u2);
             lw = 1.0;
         }
         for (int i = 0; i < 3; i++) X[i] = r[i] + r[6] * w[i] / lw;
@@ -302,9 +311,11 @@ struct LMOpts {
     T frac, tol_step, tol_res, tau_root, lambda0;
 };
 
-template <typename T, int N>
+// State of one lane's path: the unknowns (D = 3N points, or 2N parameters
+// in the parametric form) and the Levenberg-Marquardt scalars.
+template <typename T, int N, int D = 3 * N>
 struct Lane {
-    T X[3 * N];
+    T X[D];
     T lam, Cref, C, rinf;
     int it;
 };
@@ -373,6 +384,75 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
     return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
 }
 
+// One Levenberg-Marquardt iteration of the parametric form (Eq. (15)), with
+// the same rules; the placeholder parameter of an edge is held fixed.
+template <typename T, int N>
+__device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T, N> &p, Lane<T, N, 2 * N> &L,
+                                             const LMOpts<T> &o)
+{
+    constexpr int M = 2 * N;
+    L.it++;
+    T A[Band<N, 2>::SIZE], g[M], C, rinf;
+    if (!assemble_param<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+    L.C = C;
+    L.rinf = rinf;
+    bool real[M];
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        real[2 * k] = true;
+        real[2 * k + 1] = p.ty[k] == TP || p.ty[k] == TQ;
+    }
+    T dmax = T(0);
+#pragma unroll
+    for (int i = 0; i < M; i++) dmax = real[i] ? fmax(dmax, A[Band<N, 2>::at(i, i)]) : dmax;
+    if (L.it == 1) {
+        L.lam = o.lambda0 * dmax;
+        L.Cref = C;
+    }
+    if (rinf <= o.tol_res) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+    if (o.win > 0 && L.it > 1 && (L.it - 1) % o.win == 0) {
+        if (C > o.frac * L.Cref) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+        L.Cref = C;
+    }
+    const T floor_d = T(1e-12) * dmax;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        const T a = A[Band<N, 2>::at(i, i)];
+        A[Band<N, 2>::at(i, i)] = real[i] ? a + L.lam * fmax(a, floor_d) : T(1);
+    }
+    if (!chol_band<T, N, 2>(A)) {
+        L.lam *= T(10);
+        if (L.lam > T(1e12) * dmax) return ST_STALL;
+        return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+    }
+#pragma unroll
+    for (int i = 0; i < M; i++) g[i] = -g[i];
+    chol_solve_band<T, N, 2>(A, g);  // g <- dU (zero on the placeholders)
+    T xinf = T(0), dinf = T(0);
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        xinf = fmax(xinf, fabs(L.X[i]));
+        dinf = fmax(dinf, fabs(g[i]));
+    }
+    const bool small = dinf <= o.tol_step * (T(1) + xinf);
+    T Ct = T(0), rt = T(0);
+    bool guard = true;
+    bool okt = eval_cost_param<T, N>(sc, p, L.X, g, Ct, rt, guard) && guard;
+    if (okt && Ct < C) {
+#pragma unroll
+        for (int i = 0; i < M; i++) L.X[i] += g[i];
+        L.C = Ct;
+        L.rinf = rt;
+        L.lam = fmax(L.lam / T(10), T(1e-15) * dmax);
+        if (small) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+    } else {
+        if (small) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+        L.lam *= T(10);
+        if (L.lam > T(1e12) * dmax) return ST_STALL;
+    }
+    return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+}
+
 // ------------------------------------------------------------------ persistent LM kernel
 // Lane-refill loop for the bin of order N.  Each wave takes a chunk of the bin
 // with one atomic, and hands the chunk's ids to its idle lanes; a lane whose
@@ -393,10 +473,11 @@ template <> struct ModeT<MODE_FALLBACK64> { using T = double; };
 // (kp.resume) packs the parked paths densely and finishes them.  The same
 // machine code runs every iteration of a path, from the exact state it was
 // parked in, so the results are identical bit for bit.
-template <int MODE, int N>
-__device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restrict__ srec)
+template <int MODE, int N, int FORM = 0>
+__device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restrict__ srec)
 {
     using T = typename ModeT<MODE>::T;
+    constexpr int D = FORM ? 2 * N : 3 * N;  // unknowns: points, or parameters
     const int lane = __lane_id();
     const bool resume = kp.resume != 0;
     const int *cnt = resume ? kp.spill_cnt : (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
@@ -440,7 +521,7 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
     o.frac = (T)kp.o.plateau_frac;
     o.lambda0 = (T)kp.o.lambda0;
 
-    Lane<T, N> L;
+    Lane<T, N, D> L;
     PathIn<T, N> p;
     int sid = -1;
     int it0 = 0;  // iteration count at the start of a resumed path
@@ -485,7 +566,7 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                     if (resume) {
                         // a parked path: its state exactly as it was left
 #pragma unroll
-                        for (int j = 0; j < 3 * N; j++) L.X[j] = (T)kp.out.x[(size_t)j * kp.b.n + sid];
+                        for (int j = 0; j < D; j++) L.X[j] = (T)kp.out.x[(size_t)j * kp.b.n + sid];
                         L.it = kp.out.iters[sid];
                         it0 = L.it;
                         L.lam = (T)kp.spill_f[sid];
@@ -539,12 +620,39 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                         }
                     }
                     int st0 = ST_RUNNING;
-                    if (!ok) st0 = ST_BAD;
-                    else if (!in_guard(kp.s, X0, N)) st0 = ST_DIVERGED;
+                    if constexpr (FORM) {
+                        // the parameters of the start points; the path starts
+                        // at X(U), which must lie in the guard box
+                        double U[2 * N];
 #pragma unroll
-                    for (int k = 0; k < N; k++)
+                        for (int k = 0; k < N; k++) {
+                            const double *r64 = kp.s.rec64 + (size_t)p.id[k] * kRec;
+                            double u2[2];
+                            ok = param_of(p.ty[k], r64, X0 + 3 * k, u2) && ok;
+                            U[2 * k] = u2[0];
+                            U[2 * k + 1] = u2[1];
+                            if (p.ty[k] == TQ) {
+                                // the start point lifted onto the paraboloid
+                                double e1[3], e2[3];
+                                across_dir(r64 + 13, e1, e2);
+                                const double h = r64[17] * (u2[0] * u2[0] + u2[1] * u2[1]);
 #pragma unroll
-                        for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(X0[3 * k + i] - sh[i]);
+                                for (int i = 0; i < 3; i++)
+                                    X0[3 * k + i] = r64[i] + u2[0] * e1[i] + u2[1] * e2[i] + h * r64[13 + i];
+                            }
+                        }
+                        if (!ok) st0 = ST_BAD;
+                        else if (!in_guard(kp.s, X0, N)) st0 = ST_DIVERGED;
+#pragma unroll
+                        for (int j = 0; j < D; j++) L.X[j] = (T)U[j];
+                    } else {
+                        if (!ok) st0 = ST_BAD;
+                        else if (!in_guard(kp.s, X0, N)) st0 = ST_DIVERGED;
+#pragma unroll
+                        for (int k = 0; k < N; k++)
+#pragma unroll
+                            for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(X0[3 * k + i] - sh[i]);
+                    }
                     L.it = 0;
                     L.lam = T(0);
                     L.C = T(__builtin_huge_val());
@@ -575,11 +683,15 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
         const bool park = may_spill && drained && (int)__popcll(__ballot(active)) <= kp.spill_t;
         // ---- one iteration on every busy lane
         if (active) {
-            const int st = park ? ST_PARKED : lm_step<T, N>(sc, p, L, o);
+            int st = ST_PARKED;
+            if (!park) {
+                if constexpr (FORM) st = lm_step_param<T, N>(sc, p, L, o);
+                else st = lm_step<T, N>(sc, p, L, o);
+            }
             if (st == ST_PARKED) {
                 // ---- a parked path: its exact state, for the straggler launch
 #pragma unroll
-                for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j];
+                for (int j = 0; j < D; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j];
                 kp.out.iters[sid] = L.it;
                 kp.spill_f[sid] = (double)L.lam;
                 kp.spill_f[(size_t)kp.b.n + sid] = (double)L.Cref;
@@ -589,8 +701,19 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
                 // ---- end of one path: write it (world frame)
                 const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
                                       MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
+                if constexpr (FORM) {
+                    // the points X(U) in the solver's frame, then world
 #pragma unroll
-                for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j] + sh[j % 3];
+                    for (int k = 0; k < N; k++) {
+                        T Xk[3], Tm[3][2];
+                        param_map<T>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, L.X[2 * k], L.X[2 * k + 1], Xk, Tm);
+#pragma unroll
+                        for (int i = 0; i < 3; i++) kp.out.x[(size_t)(3 * k + i) * kp.b.n + sid] = (double)Xk[i] + sh[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j] + sh[j % 3];
+                }
                 kp.out.cost[sid] = (double)L.C;
                 int it = L.it;
                 if (MODE == MODE_FALLBACK64) it += kp.out.iters[sid];
@@ -636,17 +759,24 @@ __device__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restr
 // Register budget per lane: an order-N path keeps 3N points, the 3N x 3N
 // band (93 entries at N = 5) and its factor in registers, so the occupancy
 // target falls with the order and doubles from FP64 to FP32.
-template <int MODE, int N> struct Occ { static constexpr int W = 1; };
-template <> struct Occ<MODE_FP32, 1> { static constexpr int W = 4; };
-template <> struct Occ<MODE_FP32, 2> { static constexpr int W = 3; };
-template <> struct Occ<MODE_FP32, 3> { static constexpr int W = 2; };
-template <> struct Occ<MODE_PLAIN64, 1> { static constexpr int W = 3; };
-template <> struct Occ<MODE_PLAIN64, 2> { static constexpr int W = 2; };
-template <> struct Occ<MODE_FALLBACK64, 1> { static constexpr int W = 3; };
-template <> struct Occ<MODE_FALLBACK64, 2> { static constexpr int W = 2; };
+template <int MODE, int N, int FORM = 0> struct Occ { static constexpr int W = 1; };
+template <> struct Occ<MODE_FP32, 1, 0> { static constexpr int W = 4; };
+template <> struct Occ<MODE_FP32, 2, 0> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FP32, 3, 0> { static constexpr int W = 2; };
+template <> struct Occ<MODE_PLAIN64, 1, 0> { static constexpr int W = 3; };
+template <> struct Occ<MODE_PLAIN64, 2, 0> { static constexpr int W = 2; };
+template <> struct Occ<MODE_FALLBACK64, 1, 0> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FALLBACK64, 2, 0> { static constexpr int W = 2; };
+// the parametric form holds 2N unknowns and a band of 2 x 2 blocks
+template <> struct Occ<MODE_FP32, 1, 1> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FP32, 2, 1> { static constexpr int W = 3; };
+template <> struct Occ<MODE_FP32, 3, 1> { static constexpr int W = 2; };
+template <> struct Occ<MODE_FP32, 4, 1> { static constexpr int W = 2; };
+template <> struct Occ<MODE_PLAIN64, 1, 1> { static constexpr int W = 2; };
+template <> struct Occ<MODE_PLAIN64, 2, 1> { static constexpr int W = 2; };
 
 // The mixed-order kernel keeps the register budget of its largest order.
-template <int MODE> struct OccAll { static constexpr int W = 1; };
+template <int MODE, int FORM> struct OccAll { static constexpr int W = 1; };
 
 // Scene records staged in LDS by every block of a persistent launch (the
 // whole scene: 651 primitives x 18 floats = 47 KB for the street canyon).
@@ -665,28 +795,30 @@ __device__ __forceinline__ const typename ModeT<MODE>::T *stage_scene(const KPar
 }
 
 // One persistent launch over every order (register budget of order 5).
-template <int MODE, bool LDS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OccAll<MODE>::W, OccAll<MODE>::W))) k_lm(KParams kp)
+// FORM 0: the implicit form (points as unknowns); 1: the parametric form.
+template <int MODE, bool LDS, int FORM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OccAll<MODE, FORM>::W, OccAll<MODE, FORM>::W)))
+k_lm(KParams kp)
 {
     const int *cnt = kp.resume ? kp.spill_cnt : (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
     if (cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4] == 0) return;  // nothing to solve: skip the staging
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     // long paths first so that the short ones fill the tail
-    lm_bin<MODE, 5>(kp, rec);
-    lm_bin<MODE, 4>(kp, rec);
-    lm_bin<MODE, 3>(kp, rec);
-    lm_bin<MODE, 2>(kp, rec);
-    lm_bin<MODE, 1>(kp, rec);
+    lm_bin<MODE, 5, FORM>(kp, rec);
+    lm_bin<MODE, 4, FORM>(kp, rec);
+    lm_bin<MODE, 3, FORM>(kp, rec);
+    lm_bin<MODE, 2, FORM>(kp, rec);
+    lm_bin<MODE, 1, FORM>(kp, rec);
 }
 
 // One persistent launch per order, each with its own register budget.
-template <int MODE, int N, bool LDS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<MODE, N>::W, Occ<MODE, N>::W)))
-k_lm_one(KParams kp)
+template <int MODE, int N, bool LDS, int FORM>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(Occ<MODE, N, FORM>::W, Occ<MODE, N, FORM>::W))) k_lm_one(KParams kp)
 {
     if ((kp.resume ? kp.spill_cnt : (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt)[N - 1] == 0) return;
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
-    lm_bin<MODE, N>(kp, rec);
+    lm_bin<MODE, N, FORM>(kp, rec);
 }
 
 // ------------------------------------------------------------------ polish
@@ -939,35 +1071,40 @@ void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bi
                        koff, kcur, perm);
 }
 
-template <int MODE, bool LDS>
+template <int MODE, bool LDS, int FORM>
 static const void *lm_kernel_t(int order)
 {
     switch (order) {
-    case 0: return (const void *)k_lm<MODE, LDS>;
-    case 1: return (const void *)k_lm_one<MODE, 1, LDS>;
-    case 2: return (const void *)k_lm_one<MODE, 2, LDS>;
-    case 3: return (const void *)k_lm_one<MODE, 3, LDS>;
-    case 4: return (const void *)k_lm_one<MODE, 4, LDS>;
-    default: return (const void *)k_lm_one<MODE, 5, LDS>;
+    case 0: return (const void *)k_lm<MODE, LDS, FORM>;
+    case 1: return (const void *)k_lm_one<MODE, 1, LDS, FORM>;
+    case 2: return (const void *)k_lm_one<MODE, 2, LDS, FORM>;
+    case 3: return (const void *)k_lm_one<MODE, 3, LDS, FORM>;
+    case 4: return (const void *)k_lm_one<MODE, 4, LDS, FORM>;
+    default: return (const void *)k_lm_one<MODE, 5, LDS, FORM>;
     }
 }
 
 // order 0: the mixed-order kernel; 1..5: the per-order kernels
-const void *lm_kernel(int mode, int order, bool lds)
+// The fallback always runs the implicit form (from the FP32 end point).
+const void *lm_kernel(int mode, int order, bool lds, int form)
 {
     switch (mode) {
-    case MODE_PLAIN64: return lds ? lm_kernel_t<MODE_PLAIN64, true>(order) : lm_kernel_t<MODE_PLAIN64, false>(order);
-    case MODE_FP32: return lds ? lm_kernel_t<MODE_FP32, true>(order) : lm_kernel_t<MODE_FP32, false>(order);
+    case MODE_PLAIN64:
+        if (form) return lds ? lm_kernel_t<MODE_PLAIN64, true, 1>(order) : lm_kernel_t<MODE_PLAIN64, false, 1>(order);
+        return lds ? lm_kernel_t<MODE_PLAIN64, true, 0>(order) : lm_kernel_t<MODE_PLAIN64, false, 0>(order);
+    case MODE_FP32:
+        if (form) return lds ? lm_kernel_t<MODE_FP32, true, 1>(order) : lm_kernel_t<MODE_FP32, false, 1>(order);
+        return lds ? lm_kernel_t<MODE_FP32, true, 0>(order) : lm_kernel_t<MODE_FP32, false, 0>(order);
     default:
-        return lds ? lm_kernel_t<MODE_FALLBACK64, true>(order) : lm_kernel_t<MODE_FALLBACK64, false>(order);
+        return lds ? lm_kernel_t<MODE_FALLBACK64, true, 0>(order) : lm_kernel_t<MODE_FALLBACK64, false, 0>(order);
     }
 }
 
-void launch_lm(int mode, int order, bool lds, size_t lds_bytes, const KParams &kp, int grid, int block,
+void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const KParams &kp, int grid, int block,
                hipStream_t st)
 {
     void *args[] = {(void *)&kp};
-    hipLaunchKernel(lm_kernel(mode, order, lds), dim3(grid), dim3(block), args, lds ? lds_bytes : 0, st);
+    hipLaunchKernel(lm_kernel(mode, order, lds, form), dim3(grid), dim3(block), args, lds ? lds_bytes : 0, st);
 }
 
 const void *polish_kernel() { return (const void *)k_polish; }

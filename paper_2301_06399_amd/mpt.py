@@ -22,6 +22,7 @@ CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7
 FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
 INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL, INIT_RANDOM = 0, 1, 2, 3, 4
+FORM_IMPLICIT, FORM_PARAMETRIC = 0, 1
 SCHED_PER_ORDER, SCHED_PERSISTENT, SCHED_AUTO = 0, 1, 2
 
 
@@ -49,7 +50,7 @@ class SolveOpts(C.Structure):
                 ("plateau_frac", C.c_double), ("tol_step", C.c_double), ("tol_res", C.c_double),
                 ("tau_root", C.c_double), ("lambda0", C.c_double), ("tol_step32", C.c_double),
                 ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double),
-                ("seed", C.c_uint64), ("spill", C.c_int32), ("reserved", C.c_int32)]
+                ("seed", C.c_uint64), ("spill", C.c_int32), ("form", C.c_int32)]
 
 
 class SolveOut(C.Structure):
@@ -99,7 +100,7 @@ def load_library(path: str = LIB_PATH):
     L.mpt_mlp_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.mpt_mlp_load.argtypes = [vp, vp, C.c_size_t]
     L.mpt_last_timings.argtypes = [vp, C.POINTER(C.c_float)]
-    L.mpt_flops_per_iter.argtypes = [C.c_int, vp, vp]
+    L.mpt_flops_per_iter.argtypes = [C.c_int, vp, C.c_int32, vp]
     L.mpt_last_lm_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_autotune.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut),
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float),
@@ -162,19 +163,19 @@ class DeviceOut:
         return r
 
 
-def flops_per_iter(types) -> dict:
+def flops_per_iter(types, form=FORM_IMPLICIT) -> dict:
     """Algorithmic FLOPs of one LM iteration / polish step / residual
     evaluation for a path with the given primitive types (host only)."""
     L = load_library()
     t = np.ascontiguousarray(types, np.int32)
     out = np.zeros(4, np.int64)
-    rc = L.mpt_flops_per_iter(len(t), t.ctypes.data, out.ctypes.data)
+    rc = L.mpt_flops_per_iter(len(t), t.ctypes.data, int(form), out.ctypes.data)
     if rc != MPT_OK:
         raise MptError(f"mpt_flops_per_iter: {STATUS_NAMES.get(rc, rc)}")
     return {"lm": int(out[0]), "polish": int(out[1]), "residual": int(out[2]), "sqrt_div": int(out[3])}
 
 
-def flops_table() -> dict:
+def flops_table(form=FORM_IMPLICIT) -> dict:
     """FLOPs per iteration for every order 1..5 and type combination, as
     dense arrays indexed by the base-4 code sum(type_k * 4**k)."""
     tab = {}
@@ -184,7 +185,7 @@ def flops_table() -> dict:
         re_ = np.zeros(4 ** n, np.int64)
         for code in range(4 ** n):
             types = [(code // 4 ** k) % 4 for k in range(n)]
-            f = flops_per_iter(types)
+            f = flops_per_iter(types, form)
             lm[code], po[code], re_[code] = f["lm"], f["polish"], f["residual"]
         tab[n] = {"lm": lm, "polish": po, "residual": re_}
     return tab
