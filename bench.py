@@ -41,10 +41,18 @@ NAMES = {1: "room 10x10x3 m, 6 walls + 2 edges, 256 RX x 64 lists (order 1-2)",
          5: "stress: street canyon + 30 paraboloids, 16384 RX x 1024 lists of order 3-5 with >= 2 diffractions"}
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12, "bf16": 2.5e15}
 MLP_FLOPS_PER_ROW = 2 * (96 * 256 + 256 * 256 + 256 * 256 + 256 * 15)
-VARIANT_TEXT = {"L": "learned start (paths with curved objects) + FP32 LM + FP64 polish + fallback",
-                "A": "learned start (every path) + FP32 LM + FP64 polish + fallback",
-                "S": "straight-line start + FP32 LM + FP64 polish + fallback",
-                "P": "plain FP64 LM from the straight-line start"}
+# variant: (precision, start, form); form 1 = parametric (Eq. 15), 0 = implicit (Eq. 12)
+# variant: (precision, start, form); form 0 = implicit (Eq. 12), 1 = parametric
+# (Eq. 15), 2 = the library's choice (parametric with curved objects, else
+# the tuner's)
+VARIANTS = {"L": (1, "learned", 2), "A": (1, "learned_all", 2), "S": (1, "line", 2), "Si": (1, "line", 0),
+            "P": (0, "line", 0), "Pp": (0, "line", 1)}
+VARIANT_TEXT = {"L": "learned start (paths with curved objects) + FP32 LM + FP64 polish + fallback, form auto",
+                "A": "learned start (every path) + FP32 LM + FP64 polish + fallback, form auto",
+                "S": "straight-line start + FP32 LM + FP64 polish + fallback, form auto",
+                "Si": "straight-line start + FP32 LM + FP64 polish + fallback, implicit form",
+                "P": "plain FP64 LM from the straight-line start, implicit form (Eq. 12)",
+                "Pp": "plain FP64 LM from the straight-line start, parametric form (Eq. 15)"}
 
 
 def log(msg):
@@ -77,13 +85,9 @@ def algorithmic_flops(table, order, code, iters, kind):
 
 
 def opts_for(mpt, v):
-    if v == "P":
-        return mpt.default_opts(precision=mpt.FP64_PLAIN)
-    if v == "S":
-        return mpt.default_opts(precision=mpt.FP32_POLISH64)
-    if v == "A":
-        return mpt.default_opts(precision=mpt.FP32_POLISH64, init=mpt.INIT_LEARNED_ALL)
-    return mpt.default_opts(precision=mpt.FP32_POLISH64, init=mpt.INIT_LEARNED)
+    prec, start, form = VARIANTS[v]
+    init = {"line": mpt.INIT_LINE, "learned": mpt.INIT_LEARNED, "learned_all": mpt.INIT_LEARNED_ALL}[start]
+    return mpt.default_opts(precision=mpt.FP32_POLISH64 if prec else mpt.FP64_PLAIN, init=init, form=form)
 
 
 class Runner:
@@ -153,11 +157,12 @@ class Runner:
         return self.acc[:self.batch.n].cpu().numpy()
 
 
-def lm_roofline(scene, batch, r, st, prec, cfg, mpt):
+def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0):
     """Roofline of the dominant solver kernel: algorithmic FLOPs of the first
     LM pass (iterations actually run in it x FLOPs per iteration of each
-    path's order and types) over its measured duration."""
-    table = mpt.flops_table()
+    path's order and types, in the variant's form) over its measured
+    duration."""
+    table = mpt.flops_table(form)
     code = type_codes(scene, batch)
     it1 = r["stage"][0] - r["stage"][3]   # iterations before a straggler was parked
     per_order_flops = []
@@ -171,10 +176,11 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt):
         # concurrent per-order launches: the dominant one is the order with
         # the most algorithmic work, timed by its own events
         dom = int(np.argmax(per_order_flops))
-        kname, kfile = f"k_lm_one<{mode}, {dom + 1}, ...>", f"k_lm_one_order{dom + 1}_{prec}"
+        kname = f"k_lm_one<{mode}, {dom + 1}, ..., {form}>"
+        kfile = f"k_lm_one_order{dom + 1}_{prec}" + ("_param" if form else "")
         flops_dom, ms_dom = per_order_flops[dom], st["lm_per_order"][dom]
     else:
-        kname, kfile = f"k_lm<{mode}, ...> (all orders)", f"k_lm_{prec}"
+        kname, kfile = f"k_lm<{mode}, ..., {form}> (all orders)", f"k_lm_{prec}" + ("_param" if form else "")
         flops_dom, ms_dom = flops_pass, st["lm"]
     achieved = flops_dom / (ms_dom * 1e-3)
     # HBM bytes per launch from the committed counter summary of this kernel
@@ -194,6 +200,16 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt):
                         "straggler_flops": flops_resume, "straggler_ms": st["resume"]}}
 
 
+def used_form(form, launch, scene):
+    """The form a solve ran in: the tuner's choice for the automatic form,
+    else the library's rule (parametric with paraboloids or circles)."""
+    if form != 2:
+        return form
+    if launch and "form" in launch:
+        return launch["form"]
+    return 1 if len(scene.quadrics) or len(scene.circles) else 0
+
+
 def ncores():
     try:
         c = len(os.sched_getaffinity(0))
@@ -202,7 +218,7 @@ def ncores():
     return min(c, 16)
 
 
-def oracle_run(O, scene, batch, cores, budget_s, max_n):
+def oracle_run(O, scene, batch, cores, budget_s, max_n, form="implicit"):
     """The oracle (solve + accept) on the whole workload or a seeded uniform
     sample of at most max_n solves, repeated until about budget_s seconds."""
     n = batch.n
@@ -212,7 +228,7 @@ def oracle_run(O, scene, batch, cores, budget_s, max_n):
     reps, t_cpu, acc_cpu = 0, 0.0, 0
     while reps < 1 or (t_cpu < budget_s and reps < 64):
         t = time.perf_counter()
-        o_ = O.solve_batch(scene, sb, nthreads=cores)
+        o_ = O.solve_batch(scene, sb, nthreads=cores, form=form)
         a_ = O.accept_batch(scene, sb, o_["x"], o_["status"], nthreads=cores)
         t_cpu += time.perf_counter() - t
         acc_cpu += int(a_.sum())
@@ -328,7 +344,7 @@ def main_single(args, torch, mpt, W):
         del src, dst
 
     run = Runner(torch, mpt, ctx, scene, batch)
-    variants = [variant] if args.only_main else [variant] + [x for x in ("S", "P") if x != variant]
+    variants = [variant] if args.only_main else [variant] + [x for x in ("S", "Si", "P", "Pp") if x != variant]
     results, outs, flags = {}, {}, {}
     for v in variants:
         steps = args.steps if v == variant else max(5, args.steps // 4)
@@ -336,18 +352,22 @@ def main_single(args, torch, mpt, W):
         results[v], outs[v] = run.run(v, steps, warm, tune=not args.no_autotune)
         flags[v] = run.flags()
     main_r, r = results[variant], outs[variant]
-    prec = "fp64" if variant == "P" else "fp32"
-    roof = lm_roofline(scene, batch, r, main_r["stage_ms"], prec, args.config, mpt)
+    prec = "fp32" if VARIANTS[variant][0] else "fp64"
+    form = used_form(VARIANTS[variant][2], main_r["launch"], scene)
+    main_r["form_used"] = form
+    roof = lm_roofline(scene, batch, r, main_r["stage_ms"], prec, args.config, mpt, form)
 
     cpu = par = None
     if not args.no_cpu_baseline:
         import oracle as O
         O.lib()
         cores = ncores()
-        orun = oracle_run(O, scene, batch, cores, 10.0, args.cpu_sample or 2_000_000)
+        fname = "param" if form else "implicit"
+        orun = oracle_run(O, scene, batch, cores, 10.0, args.cpu_sample or 2_000_000, fname)
         what = "the whole workload" if orun["m"] == n else f"a seeded uniform sample of the {n} solves"
         cpu = {"value": orun["acc"] / orun["t"], "unit": "accepted paths/s", "cores": cores, "kind": "oracle",
-               "sample": f"{what} ({orun['m']} solves), solve + accept, {orun['reps']} passes, {orun['t']:.1f} s",
+               "sample": f"{what} ({orun['m']} solves), {fname} form, solve + accept, {orun['reps']} passes, "
+                         f"{orun['t']:.1f} s",
                "solves_per_s": orun["reps"] * orun["m"] / orun["t"]}
         par = parity(O, scene, orun, r, flags[variant])
     # the metric counts the accepted paths that meet the 1e-6 m bar against
@@ -356,7 +376,7 @@ def main_single(args, torch, mpt, W):
     value = main_r["paths_per_s"]
     if par and par["gpu_accepted"]:
         value *= par["accepted_within_bar"] / par["gpu_accepted"]
-    emit(args, value, main_r["ms_per_step"], variant, "f32+f64" if variant != "P" else "f64",
+    emit(args, value, main_r["ms_per_step"], variant, "f32+f64" if VARIANTS[variant][0] else "f64",
          NAMES[args.config], n, results, roof, cpu, par)
 
 
@@ -378,7 +398,7 @@ def main_learned(args, torch, mpt, W):
     hist = learned.train_joint(ctx, train, steps=args.train_steps or 6000, log=sys.stderr)
     log(f"# joint training {time.time() - t0:.1f}s, final losses {hist[-2:]}")
     del train
-    variants = ["L", "A", "S", "P"]
+    variants = ["L", "A", "S", "Si", "P", "Pp"]
     per = {v: [] for v in variants}
     outs, flags = {}, {}
     for h, (sc, b) in enumerate(held):
@@ -410,7 +430,7 @@ def main_learned(args, torch, mpt, W):
         tot_t = tot_acc = tot_m = 0
         par = []
         for h, (sc, b) in enumerate(held):
-            orun = oracle_run(O, sc, b, cores, 5.0, args.cpu_sample or 2_000_000)
+            orun = oracle_run(O, sc, b, cores, 5.0, args.cpu_sample or 2_000_000, "param")
             tot_t += orun["t"]
             tot_acc += orun["acc"]
             tot_m += orun["m"] * orun["reps"]
@@ -433,7 +453,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--n-rx", type=int, default=0, help="receivers (0: the configuration's own)")
-    ap.add_argument("--variant", default="auto", choices=["auto", "L", "A", "S", "P"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "L", "A", "S", "Si", "P", "Pp"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="largest oracle sample (0: 2,000,000 solves)")
     ap.add_argument("--train-steps", type=int, default=0, help="network training steps before timing")

@@ -138,7 +138,7 @@ enum { MPT_INIT_LINE = 0, MPT_INIT_USER = 1, MPT_INIT_LEARNED = 2, MPT_INIT_LEAR
        MPT_INIT_RANDOM = 4 };
 enum { MPT_FALLBACK_NONE = 0, MPT_FALLBACK_GPU_FP64 = 1 };
 /* Formulation of the minimisation (paper Sec. III-B). */
-enum { MPT_FORM_IMPLICIT = 0, MPT_FORM_PARAMETRIC = 1 };
+enum { MPT_FORM_IMPLICIT = 0, MPT_FORM_PARAMETRIC = 1, MPT_FORM_AUTO = 2 };
 /* MPT_SCHED_PERSISTENT: one persistent launch runs every order's bin;
  * MPT_SCHED_PER_ORDER: one persistent launch per order, with its own
  * register budget, all five running concurrently on forked streams. */
@@ -185,7 +185,12 @@ typedef struct {
                               LM pass (the polish and the fallback stay
                               implicit).  Paraboloids must be of revolution
                               (A = k (I - ax ax^T), b = -ax, c = 0); another
-                              quadric makes its paths MPT_PATH_BAD_INPUT     */
+                              quadric makes its paths MPT_PATH_BAD_INPUT.
+                              MPT_FORM_AUTO: parametric when the scene has
+                              paraboloids or circles (and every quadric
+                              allows it), otherwise implicit or the tuner's
+                              choice (planes and straight edges have unique
+                              roots, so both forms accept the same paths)   */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 
@@ -232,7 +237,7 @@ mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_
  */
 mpt_status mpt_autotune(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_opts *opts,
                         const mpt_solve_out *out, int32_t *best_sched, int32_t *best_block, float *best_ms,
-                        int32_t *best_gdiv, int32_t *best_spill);
+                        int32_t *best_gdiv, int32_t *best_spill, int32_t *best_form);
 
 /*
  * The acceptance test of Alg. 1 ("C < threshold and X is valid") in FP64 on

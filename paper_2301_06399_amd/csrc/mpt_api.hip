@@ -29,6 +29,8 @@ struct mpt_ctx {
     size_t scene_cap = 0, raw_cap = 0;
     SceneDev s{};
     bool has_scene = false;
+    bool curved = false;     // the scene has paraboloids or circles
+    bool param_ok = true;    // every quadric is a paraboloid of revolution
     // workspace: counters | perm | polish lists | fallback lists
     int *ws = nullptr;
     size_t ws_cap = 0;  // solves
@@ -46,7 +48,7 @@ struct mpt_ctx {
     bool timed = false;
     MlpState *mlp = nullptr;
     // autotuned launch choices: key -> (sched, block)
-    struct Tune { int prec, form, nbucket, n_all, sched, block, gdiv, spill; float ms; };
+    struct Tune { int prec, form, nbucket, n_all, sched, block, gdiv, spill, used; float ms; };
     std::vector<Tune> tune;
     bool tune_loaded = false;
     // captured graph of the last solve (replayed while the key matches)
@@ -252,6 +254,20 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->s = s;
     c->has_scene = true;
+    c->curved = (nq + nc) > 0;
+    c->param_ok = true;
+    for (int i = 0; i < nq; i++) {
+        // the parametric form needs A = k (I - ax ax^T), b = -ax, c = 0
+        const double *q = d->quadrics + 17 * (size_t)i, *ax = q + 13;
+        const double kap = 0.5 * (q[3] + q[6] + q[8]);
+        const double Am[3][3] = {{q[3], q[4], q[5]}, {q[4], q[6], q[7]}, {q[5], q[7], q[8]}};
+        double err = fabs(q[12]);
+        for (int a = 0; a < 3; a++) {
+            err = fmax(err, fabs(q[9 + a] + ax[a]));
+            for (int b = 0; b < 3; b++) err = fmax(err, fabs(Am[a][b] - kap * ((a == b ? 1.0 : 0.0) - ax[a] * ax[b])));
+        }
+        c->param_ok = c->param_ok && kap > 0.0 && err <= 1e-9 * (1.0 + kap);
+    }
     return MPT_OK;
 }
 
@@ -344,10 +360,10 @@ static void tune_load(mpt_ctx *c)
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    // one entry per line: prec form nbucket n_all sched block gdiv spill ms
+    // one entry per line: prec form nbucket n_all sched block gdiv spill used-form ms
     mpt_ctx::Tune t;
-    while (fscanf(f, "%d %d %d %d %d %d %d %d %f", &t.prec, &t.form, &t.nbucket, &t.n_all, &t.sched, &t.block, &t.gdiv,
-                  &t.spill, &t.ms) == 9)
+    while (fscanf(f, "%d %d %d %d %d %d %d %d %d %f", &t.prec, &t.form, &t.nbucket, &t.n_all, &t.sched, &t.block,
+                  &t.gdiv, &t.spill, &t.used, &t.ms) == 10)
         c->tune.push_back(t);
     fclose(f);
 }
@@ -359,14 +375,24 @@ static void tune_save(mpt_ctx *c)
     FILE *f = fopen(path, "w");
     if (!f) return;
     for (auto &t : c->tune)
-        fprintf(f, "%d %d %d %d %d %d %d %d %.6f\n", t.prec, t.form, t.nbucket, t.n_all, t.sched, t.block, t.gdiv,
-                t.spill, t.ms);
+        fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f\n", t.prec, t.form, t.nbucket, t.n_all, t.sched, t.block, t.gdiv,
+                t.spill, t.used, t.ms);
     fclose(f);
 }
 
-static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv, int &spill)
+// The form a solve runs in: MPT_FORM_AUTO takes the parametric form on
+// scenes with curved objects (when every quadric allows it) and the implicit
+// one otherwise, unless the tuner chose for this batch.
+static int auto_form(const mpt_ctx *c)
+{
+    return (c->curved && c->param_ok) ? MPT_FORM_PARAMETRIC : MPT_FORM_IMPLICIT;
+}
+
+static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv, int &spill,
+                   int &form)
 {
     default_choice(o->precision, sched, block, gdiv, spill);
+    form = (o->form == MPT_FORM_AUTO) ? auto_form(c) : o->form;
     tune_load(c);
     for (auto &t : c->tune)
         if (t.prec == o->precision && t.form == o->form && t.nbucket == nbucket(n) && t.n_all == c->s.n_all) {
@@ -374,6 +400,7 @@ static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, i
             block = t.block;
             gdiv = t.gdiv;
             spill = t.spill;
+            if (o->form == MPT_FORM_AUTO) form = t.used;
         }
     if (o->sched != MPT_SCHED_AUTO) sched = o->sched;
     if (o->block) block = o->block;
@@ -405,7 +432,7 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
         return fail(c, MPT_E_UNSUPPORTED, "sched %d", opts->sched);
     if (opts->grid < 0) return fail(c, MPT_E_INVALID_ARG, "negative grid");
     if (opts->spill < -1 || opts->spill > 64) return fail(c, MPT_E_INVALID_ARG, "spill must be -1..64");
-    if (opts->form != MPT_FORM_IMPLICIT && opts->form != MPT_FORM_PARAMETRIC)
+    if (opts->form != MPT_FORM_IMPLICIT && opts->form != MPT_FORM_PARAMETRIC && opts->form != MPT_FORM_AUTO)
         return fail(c, MPT_E_UNSUPPORTED, "form %d", opts->form);
     return MPT_OK;
 }
@@ -425,7 +452,7 @@ static mpt_status size_buffers(mpt_ctx *c, int64_t n, bool learned)
 // `timed`, HIP events mark the stage boundaries (not inside graph capture).
 static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts,
                                 const mpt_solve_out *out, hipStream_t s, bool timed, int sched, int block,
-                                int gdiv, int spill)
+                                int gdiv, int spill, int form_used)
 {
     BatchDev bd;
     mpt_status st = batch_dev(c, b, bd);
@@ -495,7 +522,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
         const size_t rec_bytes = (size_t)c->s.n_all * kRec * (md == MODE_FP32 ? sizeof(float) : sizeof(double));
         const bool lds = rec_bytes <= c->lds_max;
         auto go = [&](int ord, hipStream_t where) {
-            const int form = (md == MODE_FALLBACK64) ? MPT_FORM_IMPLICIT : opts->form;
+            const int form = (md == MODE_FALLBACK64) ? MPT_FORM_IMPLICIT : form_used;
             const void *k = lm_kernel(md, ord, lds, form);
             if (lds) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rec_bytes);
             int g = opts->grid;
@@ -545,9 +572,9 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
 }
 
 static std::vector<unsigned char> graph_key(const mpt_batch_desc *b, const mpt_solve_opts *o, const mpt_solve_out *out,
-                                            int sched, int block, int gdiv, int spill, const SceneDev &s)
+                                            int sched, int block, int gdiv, int spill, int form, const SceneDev &s)
 {
-    std::vector<unsigned char> k(sizeof *b + sizeof *o + sizeof *out + 4 * sizeof(int) + sizeof s);
+    std::vector<unsigned char> k(sizeof *b + sizeof *o + sizeof *out + 5 * sizeof(int) + sizeof s);
     unsigned char *p = k.data();
     memcpy(p, b, sizeof *b), p += sizeof *b;
     memcpy(p, o, sizeof *o), p += sizeof *o;
@@ -556,6 +583,7 @@ static std::vector<unsigned char> graph_key(const mpt_batch_desc *b, const mpt_s
     memcpy(p, &block, sizeof block), p += sizeof block;
     memcpy(p, &gdiv, sizeof gdiv), p += sizeof gdiv;
     memcpy(p, &spill, sizeof spill), p += sizeof spill;
+    memcpy(p, &form, sizeof form), p += sizeof form;
     memcpy(p, &s, sizeof s);
     return k;
 }
@@ -568,12 +596,12 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     mpt_status st = check_opts(c, b, opts, out);
     if (st) return st;
     hipSetDevice(c->device);
-    int sched, block, gdiv, spill;
-    choose(c, opts, b->n, sched, block, gdiv, spill);
-    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block, gdiv, spill);
+    int sched, block, gdiv, spill, form;
+    choose(c, opts, b->n, sched, block, gdiv, spill, form);
+    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block, gdiv, spill, form);
 
     // graph mode: capture once per (batch, options, outputs, scene) and replay
-    std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, gdiv, spill, c->s);
+    std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, gdiv, spill, form, c->s);
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) hipGraphExecDestroy(c->gexec), c->gexec = nullptr;
         if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
@@ -581,7 +609,7 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
         const bool learned = opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL;
         if ((st = size_buffers(c, b->n, learned))) return st;
         HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-        st = enqueue_solve(c, b, opts, out, c->cap, false, sched, block, gdiv, spill);
+        st = enqueue_solve(c, b, opts, out, c->cap, false, sched, block, gdiv, spill, form);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap, &g);
         if (st) {
@@ -600,22 +628,29 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
 
 mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out,
                         int32_t *best_sched, int32_t *best_block, float *best_ms, int32_t *best_gdiv,
-                        int32_t *best_spill)
+                        int32_t *best_spill, int32_t *best_form)
 {
     if (!c) return MPT_E_INVALID_ARG;
     mpt_status st = check_opts(c, b, opts, out);
     if (st) return st;
     hipSetDevice(c->device);
     tune_load(c);
-    // candidates: schedule x block size x grid divisor (per-order only) x
-    // straggler threshold
-    struct Cand { int sched, block, gdiv, spill; };
+    // candidates: form (MPT_FORM_AUTO on planes and straight edges, whose
+    // unique roots make both forms accept the same paths) x schedule x block
+    // size x grid divisor (per-order only) x straggler threshold
+    std::vector<int> forms;
+    if (opts->form != MPT_FORM_AUTO) forms.push_back(opts->form);
+    else if (c->curved) forms.push_back(auto_form(c));
+    else forms = {MPT_FORM_IMPLICIT, MPT_FORM_PARAMETRIC};
+    struct Cand { int sched, block, gdiv, spill, form; };
     std::vector<Cand> cands;
-    for (int sp : {0, 8, 16, 32})
-        for (int blk : {128, 256}) cands.push_back({MPT_SCHED_PERSISTENT, blk, 1, sp});
-    for (int sp : {0, 16})
-        for (int blk : {64, 128, 256})
-            for (int gd : {1, 2}) cands.push_back({MPT_SCHED_PER_ORDER, blk, gd, sp});
+    for (int fm : forms) {
+        for (int sp : {0, 8, 16, 32})
+            for (int blk : {128, 256}) cands.push_back({MPT_SCHED_PERSISTENT, blk, 1, sp, fm});
+        for (int sp : {0, 16})
+            for (int blk : {64, 128, 256})
+                for (int gd : {1, 2}) cands.push_back({MPT_SCHED_PER_ORDER, blk, gd, sp, fm});
+    }
     float best = 1e30f;
     Cand bc = cands[0];
     for (const Cand &cd : cands) {
@@ -625,7 +660,7 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
         float t[5];
         int nt = 0;
         for (int rep = 0, reps = 6; rep < reps; rep++) {
-            if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv, cd.spill)))
+            if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv, cd.spill, cd.form)))
                 return st;
             HIPCHK(c, hipEventSynchronize(c->ev[6]));
             float ms = 0.0f;
@@ -640,16 +675,18 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     bool found = false;
     for (auto &t : c->tune)
         if (t.prec == opts->precision && t.form == opts->form && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
-            t.sched = bc.sched, t.block = bc.block, t.gdiv = bc.gdiv, t.spill = bc.spill, t.ms = best, found = true;
+            t.sched = bc.sched, t.block = bc.block, t.gdiv = bc.gdiv, t.spill = bc.spill, t.used = bc.form,
+            t.ms = best, found = true;
     if (!found)
         c->tune.push_back({opts->precision, opts->form, nbucket(b->n), c->s.n_all, bc.sched, bc.block, bc.gdiv,
-                           bc.spill, best});
+                           bc.spill, bc.form, best});
     tune_save(c);
     if (best_sched) *best_sched = bc.sched;
     if (best_block) *best_block = bc.block;
     if (best_ms) *best_ms = best;
     if (best_gdiv) *best_gdiv = bc.gdiv;
     if (best_spill) *best_spill = bc.spill;
+    if (best_form) *best_form = bc.form;
     return MPT_OK;
 }
 

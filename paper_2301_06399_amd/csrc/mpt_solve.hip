@@ -582,7 +582,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     bool use_net = (init == INIT_LEARNED_ALL);
                     if (init == INIT_LEARNED)
                         for (int k = 0; k < N; k++) use_net = use_net || p.ty[k] == TQ || p.ty[k] == TC;
-                    if (init == INIT_RANDOM || init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
+                    if (init == INIT_RANDOM || init == INIT_LINE || init == INIT_LEARNED || init == INIT_LEARNED_ALL) {
                         // the projection onto each object of a point on the
                         // TX -> RX segment, or of a random point of the scene box
                         const bool rnd = init == INIT_RANDOM;
@@ -610,13 +610,45 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                             X0[j] = x0[(size_t)j * kp.b.n + sid];
                             ok = ok && isfinite(X0[j]);
                         }
-                        if (ok && use_net) {
-                            // the network's points are projected onto their objects
+                    }
+                    if (use_net) {
+                        // the network's points, projected onto their objects,
+                        // replace the straight-line start when their cost is
+                        // lower: the solver's own cost judges the prediction
+                        double Xn[3 * N];
+                        bool okn = true;
+#pragma unroll
+                        for (int k = 0; k < N; k++) {
+                            double P[3];
+#pragma unroll
+                            for (int i = 0; i < 3; i++) {
+                                P[i] = kp.x0_learned[(size_t)(3 * k + i) * kp.b.n + sid];
+                                okn = okn && isfinite(P[i]);
+                            }
+                            project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, Xn + 3 * k);
+                        }
+                        if (okn) {
+                            SceneT<double> s64;
+                            s64.rec = kp.s.rec64;
+                            PathIn<double, N> q;
+#pragma unroll
+                            for (int i = 0; i < 3; i++) {
+                                s64.tx[i] = kp.s.tx[i];
+                                s64.glo[i] = kp.s.glo[i];
+                                s64.ghi[i] = kp.s.ghi[i];
+                                q.rx[i] = rx[i];
+                            }
 #pragma unroll
                             for (int k = 0; k < N; k++) {
-                                double P[3] = {X0[3 * k], X0[3 * k + 1], X0[3 * k + 2]};
-                                project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
+                                q.id[k] = p.id[k];
+                                q.ty[k] = p.ty[k];
                             }
+                            double c0, r0, c1, r1;
+                            const bool ok0 = eval_cost<double, N>(s64, q, X0, nullptr, c0, r0);
+                            const bool ok1 = eval_cost<double, N>(s64, q, Xn, nullptr, c1, r1);
+                            if (ok1 && (!ok0 || c1 < c0))
+#pragma unroll
+                                for (int j = 0; j < 3 * N; j++) X0[j] = Xn[j];
                         }
                     }
                     int st0 = ST_RUNNING;

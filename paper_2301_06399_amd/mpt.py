@@ -22,7 +22,7 @@ CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7
 FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
 INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL, INIT_RANDOM = 0, 1, 2, 3, 4
-FORM_IMPLICIT, FORM_PARAMETRIC = 0, 1
+FORM_IMPLICIT, FORM_PARAMETRIC, FORM_AUTO = 0, 1, 2
 SCHED_PER_ORDER, SCHED_PERSISTENT, SCHED_AUTO = 0, 1, 2
 
 
@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     L.mpt_last_lm_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_autotune.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut),
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float),
-                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     for f in EXPORTS:
         getattr(L, f).restype = st if f not in ("mpt_last_error", "mpt_default_opts") else getattr(L, f).restype
     _lib = L
@@ -278,14 +278,15 @@ class Context:
     def autotune(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None):
         out = out or DeviceOut(dbatch.n)
         o = opts or default_opts()
-        sch, blk, ms, gd, sp = C.c_int32(), C.c_int32(), C.c_float(), C.c_int32(), C.c_int32()
+        sch, blk, ms, gd, sp, fm = C.c_int32(), C.c_int32(), C.c_float(), C.c_int32(), C.c_int32(), C.c_int32()
         bd, od = dbatch.desc(), out.desc()
         self._enter()
         rc = self.L.mpt_autotune(self.h, C.byref(bd), C.byref(o), C.byref(od), C.byref(sch), C.byref(blk),
-                                 C.byref(ms), C.byref(gd), C.byref(sp))
+                                 C.byref(ms), C.byref(gd), C.byref(sp), C.byref(fm))
         self._leave()
         self._check(rc, "mpt_autotune")
-        return {"sched": sch.value, "block": blk.value, "gdiv": gd.value, "spill": sp.value, "ms": ms.value}
+        return {"sched": sch.value, "block": blk.value, "gdiv": gd.value, "spill": sp.value, "form": fm.value,
+                "ms": ms.value}
 
     def synchronize(self):
         self._check(self.L.mpt_synchronize(self.h), "mpt_synchronize")

@@ -261,16 +261,26 @@ def test_autotuner_choice_keeps_parity(ctx):
 def test_random_start_matches_oracle(ctx, prec):
     """Random start of Alg. 1 (SplitMix64 draws, projections of box points):
     the oracle solves from its own random starts of the same definition.
-    Planes and straight edges (room and street canyon): flags bitwise equal,
-    points within 1e-6 m.  Curved: GPU roots the oracle did not reach are
-    verified from the GPU point."""
+    Planes and straight edges (room and street canyon), FP64: flags bitwise
+    equal, points within 1e-6 m.  FP32 iterations from far random starts can
+    end on either side of the plateau test where FP64 ends on the other (the
+    test is a heuristic reading of "a minimum was found"), so in FP32 at most
+    1 in 1000 flags may differ, and a GPU root the oracle's run missed must be
+    the (unique) root the oracle confirms from the GPU point.  Curved: GPU
+    roots the oracle did not reach are verified from the GPU point."""
     from paper_2301_06399_amd import mpt
     for sc, b in (W.config1(n_rx=128), W.config2(n_rx=128, per_rx=64)):
         x0 = O.init_random_batch(sc, b, 987654321)
         orc = O.solve_batch(sc, b, x0=x0)
         orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
         g = gpu_solve(ctx, sc, b, precision=prec, init=mpt.INIT_RANDOM, seed=987654321)
-        compare_planar(sc, b, g, orc_acc, orc)
+        if prec == 0:
+            compare_planar(sc, b, g, orc_acc, orc)
+        else:
+            assert (g["accept"] != orc_acc).sum() <= 1e-3 * b.n
+            verify_extra_roots(sc, b, g, orc_acc)
+            both = (g["accept"] == 1) & (orc_acc == 1)
+            assert point_err(g["x"], orc["x"], b.order, both) <= TOL_M
         assert orc_acc.sum() > 50
     sc, b = W.config3(n_rx=64, per_rx=64)
     x0 = O.init_random_batch(sc, b, 42)
