@@ -191,6 +191,14 @@ typedef struct {
                               allows it), otherwise implicit or the tuner's
                               choice (planes and straight edges have unique
                               roots, so both forms accept the same paths)   */
+    double stat_tol;       /* 0.02  paths of planes and straight edges only
+                              (their root is unique and reached from any
+                              start, Sec. III-B): the descent has stalled,
+                              and the path is classified by its residual,
+                              when the damped model's predicted decrease is
+                              below stat_tol x the cost ...                 */
+    int32_t stat_win;      /* 3     ... this many iterations in a row (0: off) */
+    int32_t reserved;      /* 0                                            */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 

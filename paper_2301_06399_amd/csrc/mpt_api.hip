@@ -38,7 +38,7 @@ struct mpt_ctx {
     size_t blk_cap = 0;
     double *x0l = nullptr;
     size_t x0l_cap = 0;
-    double *spf = nullptr;  // parked stragglers: damping and plateau reference [2][n]
+    double *spf = nullptr;  // parked stragglers: damping, plateau reference, stall count [3][n]
     size_t spf_cap = 0;
     hipEvent_t ev[7] = {};
     hipStream_t aux[MPT_MAX_ORDER] = {};  // per-order launches run concurrently
@@ -299,6 +299,9 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->seed = 0;
     o->spill = -1;
     o->form = MPT_FORM_IMPLICIT;
+    o->stat_tol = 0.02;
+    o->stat_win = 3;
+    o->reserved = 0;
 }
 
 static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)
@@ -432,6 +435,7 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
         return fail(c, MPT_E_UNSUPPORTED, "sched %d", opts->sched);
     if (opts->grid < 0) return fail(c, MPT_E_INVALID_ARG, "negative grid");
     if (opts->spill < -1 || opts->spill > 64) return fail(c, MPT_E_INVALID_ARG, "spill must be -1..64");
+    if (opts->stat_win < 0 || !(opts->stat_tol >= 0.0)) return fail(c, MPT_E_INVALID_ARG, "bad stall test options");
     if (opts->form != MPT_FORM_IMPLICIT && opts->form != MPT_FORM_PARAMETRIC && opts->form != MPT_FORM_AUTO)
         return fail(c, MPT_E_UNSUPPORTED, "form %d", opts->form);
     return MPT_OK;
@@ -443,7 +447,7 @@ static mpt_status size_buffers(mpt_ctx *c, int64_t n, bool learned)
     const size_t m = (size_t)(n > 0 ? n : 1);
     mpt_status st;
     if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 4 * m, sizeof(int)))) return st;
-    if ((st = ensure(c, (void **)&c->spf, &c->spf_cap, 2 * m, sizeof(double)))) return st;
+    if ((st = ensure(c, (void **)&c->spf, &c->spf_cap, 3 * m, sizeof(double)))) return st;
     if (learned && (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * m, sizeof(double)))) return st;
     return MPT_OK;
 }
@@ -482,6 +486,8 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.o.tau_root32 = opts->tau_root32;
     kp.o.polish_gate = opts->polish_gate;
     kp.o.seed = opts->seed;
+    kp.o.stat_tol = opts->stat_tol;
+    kp.o.stat_win = opts->stat_win;
     kp.x0_learned = c->x0l;
     kp.bin_cnt = ctr + 0;
     kp.head = ctr + 10;
@@ -711,6 +717,7 @@ static void count_one(const int32_t *types, int64_t out[4], bool param)
         else if (types[k] == MPT_QUADRIC) nq++;
     }
     PathIn<Cnt, N> p;
+    p.planar = false;
     int next[4] = {0, np, np + nl, np + nl + nq};
     for (int k = 0; k < N; k++) {
         const int id = next[types[k]]++;

@@ -286,6 +286,7 @@ struct PathIn {
     T rx[3];
     int id[N];
     int ty[N];
+    bool planar;  // planes and straight edges only (a unique root)
 };
 
 // Points of interaction k for the residual evaluated at X + dx (dx may be
@@ -634,10 +635,13 @@ __host__ __device__ __forceinline__ bool chol_band(T *A)
 }
 
 // Solve L L^T x = b in place (b -> x); the diagonal holds 1 / L_ii.
+// Returns |y|^2 of the forward substitution L y = b: with b = -g this is
+// -g^T x, the decrease the damped model predicts for the step x.
 template <typename T, int N, int B = 3>
-__host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
+__host__ __device__ __forceinline__ T chol_solve_band(const T *L, T *b)
 {
     constexpr int M = B * N;
+    T ysq = T(0);
 #pragma unroll
     for (int i = 0; i < M; i++) {
         T v = b[i];
@@ -645,6 +649,7 @@ __host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
         for (int k = 0; k < i; k++)
             if (Band<N, B>::in(i, k)) v -= L[Band<N, B>::at(i, k)] * b[k];
         b[i] = v * L[Band<N, B>::at(i, i)];
+        ysq += b[i] * b[i];
     }
 #pragma unroll
     for (int i = M - 1; i >= 0; i--) {
@@ -654,6 +659,7 @@ __host__ __device__ __forceinline__ void chol_solve_band(const T *L, T *b)
             if (Band<N, B>::in(k, i)) v -= L[Band<N, B>::at(k, i)] * b[k];
         b[i] = v * L[Band<N, B>::at(i, i)];
     }
+    return ysq;
 }
 
 }  // namespace mpt

@@ -307,8 +307,8 @@ __device__ inline bool in_guard(const SceneDev &s, const double *X, int n)
 // ------------------------------------------------------------------ LM lane state
 template <typename T>
 struct LMOpts {
-    int max_iter, win;
-    T frac, tol_step, tol_res, tau_root, lambda0;
+    int max_iter, win, stat_win;
+    T frac, tol_step, tol_res, tau_root, lambda0, stat_tol;
 };
 
 // State of one lane's path: the unknowns (D = 3N points, or 2N parameters
@@ -317,7 +317,7 @@ template <typename T, int N, int D = 3 * N>
 struct Lane {
     T X[D];
     T lam, Cref, C, rinf;
-    int it;
+    int it, stat;
 };
 
 // One Levenberg-Marquardt iteration on the cost of Eq. (12) with the
@@ -354,7 +354,13 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
     }
 #pragma unroll
     for (int i = 0; i < M; i++) g[i] = -g[i];
-    chol_solve_band<T, N>(A, g);  // g <- dx
+    const T pred = chol_solve_band<T, N>(A, g);  // g <- dx; pred = -g^T dx
+    if (o.stat_win > 0 && p.planar) {
+        // planes and straight edges: the descent has stalled when the damped
+        // model predicts too small a decrease several iterations in a row
+        L.stat = (pred < o.stat_tol * C) ? L.stat + 1 : 0;
+        if (L.stat >= o.stat_win) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+    }
     T xinf = T(0), dinf = T(0);
     bool guard = true;
 #pragma unroll
@@ -427,7 +433,11 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
     }
 #pragma unroll
     for (int i = 0; i < M; i++) g[i] = -g[i];
-    chol_solve_band<T, N, 2>(A, g);  // g <- dU (zero on the placeholders)
+    const T pred = chol_solve_band<T, N, 2>(A, g);  // g <- dU (zero on the placeholders)
+    if (o.stat_win > 0 && p.planar) {
+        L.stat = (pred < o.stat_tol * C) ? L.stat + 1 : 0;
+        if (L.stat >= o.stat_win) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
+    }
     T xinf = T(0), dinf = T(0);
 #pragma unroll
     for (int i = 0; i < M; i++) {
@@ -520,6 +530,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
     o.win = kp.o.plateau_win;
     o.frac = (T)kp.o.plateau_frac;
     o.lambda0 = (T)kp.o.lambda0;
+    o.stat_win = (MODE == MODE_FALLBACK64) ? 0 : kp.o.stat_win;
+    o.stat_tol = (T)kp.o.stat_tol;
 
     Lane<T, N, D> L;
     PathIn<T, N> p;
@@ -554,10 +566,12 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     const int ri = kp.b.rx_index[sid];
 #pragma unroll
                     for (int i = 0; i < 3; i++) rx[i] = kp.b.rx[3 * (size_t)ri + i];
+                    p.planar = true;
 #pragma unroll
                     for (int k = 0; k < N; k++) {
                         p.id[k] = kp.b.prim[(size_t)k * kp.b.n + sid];
                         p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
+                        p.planar = p.planar && (p.ty[k] == TP || p.ty[k] == TL);
                     }
                     const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
                                           MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
@@ -571,6 +585,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                         it0 = L.it;
                         L.lam = (T)kp.spill_f[sid];
                         L.Cref = (T)kp.spill_f[(size_t)kp.b.n + sid];
+                        L.stat = (int)kp.spill_f[(size_t)2 * kp.b.n + sid];
                         L.C = T(__builtin_huge_val());
                         L.rinf = T(__builtin_huge_val());
                     } else {
@@ -686,6 +701,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                             for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(X0[3 * k + i] - sh[i]);
                     }
                     L.it = 0;
+                    L.stat = 0;
                     L.lam = T(0);
                     L.C = T(__builtin_huge_val());
                     L.rinf = T(__builtin_huge_val());
@@ -727,6 +743,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                 kp.out.iters[sid] = L.it;
                 kp.spill_f[sid] = (double)L.lam;
                 kp.spill_f[(size_t)kp.b.n + sid] = (double)L.Cref;
+                kp.spill_f[(size_t)2 * kp.b.n + sid] = (double)L.stat;
                 kp.spill_list[off + atomicAdd(&kp.spill_cnt[N - 1], 1)] = sid;
                 active = false;
             } else if (st != ST_RUNNING) {
