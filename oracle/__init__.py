@@ -72,6 +72,9 @@ def lib():
         L.orc_param_residual.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
         L.orc_param_residual.restype = C.c_int
         L.orc_accept_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, d, d, vp, C.c_int]
+        L.orc_visible_one.argtypes = [vp, vp, C.c_int, vp, vp, d]
+        L.orc_visible_one.restype = C.c_int
+        L.orc_visible_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, d, vp, C.c_int]
         _lib = L
     return _lib
 
@@ -217,3 +220,24 @@ def accept_batch(scene, batch, x, status, tau_res=TAU_RES, min_seg=MIN_SEG, nthr
     lib().orc_accept_batch(os_.ref, batch.n, _p(batch.rx), _p(batch.rx_index), _p(batch.order),
                            _p(batch.prim), _p(x), _p(status), tau_res, min_seg, _p(acc), int(nthreads))
     return acc
+
+
+def visible_one(scene, rx, ids, X, min_seg=MIN_SEG):
+    """Physical validation of one path: no segment crosses another facet or
+    paraboloid patch."""
+    os_ = scene if isinstance(scene, OracleScene) else OracleScene(scene)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    return bool(lib().orc_visible_one(os_.ref, _p(np.ascontiguousarray(rx, dtype=np.float64)), len(ids), _p(ids),
+                                      _p(X), min_seg))
+
+
+def visible_batch(scene, batch, x, accept, min_seg=MIN_SEG, nthreads=0):
+    """Visibility flags of the accepted paths of a batch (0 for the others)."""
+    os_ = OracleScene(scene)
+    vis = np.zeros(batch.n, np.uint8)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    accept = np.ascontiguousarray(accept, dtype=np.uint8)
+    lib().orc_visible_batch(os_.ref, batch.n, _p(batch.rx), _p(batch.rx_index), _p(batch.order),
+                            _p(batch.prim), _p(x), _p(accept), min_seg, _p(vis), int(nthreads))
+    return vis

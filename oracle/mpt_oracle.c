@@ -841,6 +841,97 @@ int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t 
     return 1;
 }
 
+/* ------------------------------------------------------------ physical validation */
+/*
+ * Alg. 1 keeps a path when its points are valid "a posteriori" (Sec. II):
+ * beyond the finite extent of each interaction object (the acceptance test
+ * above), no segment of the path may pass through another object.  A
+ * segment P -> Q is blocked by a rectangle facet or a paraboloid patch it
+ * crosses strictly inside, more than min_seg from both ends.  The objects a
+ * segment starts or ends on are not tested; edges and circles have no area
+ * and block nothing; a segment parallel to a facet's plane is not blocked.
+ */
+static int seg_hits_plane(const double *r, const double P[3], const double d[3], double tmin, double tmax)
+{
+    double den = dot3(r, d);
+    if (den == 0.0) return 0;
+    double t = (r[3] - dot3(r, P)) / den;
+    if (!(t > tmin && t < tmax)) return 0;
+    double w[3];
+    for (int i = 0; i < 3; i++) w[i] = (P[i] + t * d[i]) - r[4 + i];
+    double a = dot3(w, r + 7), b = dot3(w, r + 10);
+    return a >= 0.0 && a <= dot3(r + 7, r + 7) && b >= 0.0 && b <= dot3(r + 10, r + 10);
+}
+
+static int in_patch(const double *r, const double H[3])
+{
+    double w[3];
+    sub3(H, r, w);
+    double h = dot3(w, r + 13), v[3];
+    for (int i = 0; i < 3; i++) v[i] = w[i] - h * r[13 + i];
+    return dot3(v, v) <= r[16] * r[16];
+}
+
+/* f(P + t d) = a t^2 + b t + c for a quadric; its roots inside (tmin, tmax)
+ * that lie on the patch block the segment. */
+static int seg_hits_quadric(const double *r, const double P[3], const double d[3], double tmin, double tmax)
+{
+    double A[3][3], w[3], Ad[3], Aw[3];
+    quad_A(r, A);
+    sub3(P, r, w);
+    for (int i = 0; i < 3; i++) {
+        Ad[i] = A[i][0] * d[0] + A[i][1] * d[1] + A[i][2] * d[2];
+        Aw[i] = A[i][0] * w[0] + A[i][1] * w[1] + A[i][2] * w[2];
+    }
+    double a = dot3(d, Ad);
+    double b = 2.0 * dot3(w, Ad) + dot3(r + 9, d);
+    double c = dot3(w, Aw) + dot3(r + 9, w) + r[12];
+    double ts[2];
+    int nt = 0;
+    if (a == 0.0) {
+        if (b != 0.0) ts[nt++] = -c / b;
+    } else {
+        double disc = b * b - 4.0 * a * c;
+        if (disc < 0.0) return 0;
+        double sq = sqrt(disc);
+        /* the stable pair of roots: q = -(b + sign(b) sq)/2, t = q/a, c/q */
+        double q = -0.5 * (b + (b >= 0.0 ? sq : -sq));
+        ts[nt++] = q / a;
+        if (q != 0.0) ts[nt++] = c / q;
+    }
+    for (int j = 0; j < nt; j++) {
+        double t = ts[j];
+        if (!(t > tmin && t < tmax)) continue;
+        double H[3];
+        for (int i = 0; i < 3; i++) H[i] = P[i] + t * d[i];
+        if (in_patch(r, H)) return 1;
+    }
+    return 0;
+}
+
+int orc_visible_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids, const double *X,
+                    double min_seg)
+{
+    if (!ids_ok(s, n, ids)) return 0;
+    for (int k = 0; k <= n; k++) {
+        const double *P = (k == 0) ? s->tx : X + 3 * (k - 1);
+        const double *Q = (k == n) ? rx : X + 3 * k;
+        const int ip = (k == 0) ? -1 : ids[k - 1], iq = (k == n) ? -1 : ids[k];
+        double d[3];
+        sub3(Q, P, d);
+        double L = norm3(d);
+        if (!(L > 0.0)) return 0;
+        double tmin = min_seg / L, tmax = 1.0 - tmin;
+        for (int j = 0; j < s->n_pl; j++)
+            if (j != ip && j != iq && seg_hits_plane(s->pl + 13 * (size_t)j, P, d, tmin, tmax)) return 0;
+        for (int j = 0; j < s->n_q; j++) {
+            int gid = s->n_pl + s->n_ln + j;
+            if (gid != ip && gid != iq && seg_hits_quadric(s->q + 17 * (size_t)j, P, d, tmin, tmax)) return 0;
+        }
+    }
+    return 1;
+}
+
 /* ------------------------------------------------------------ batches */
 void orc_solve_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
                      const int32_t *order, const int32_t *prim, const double *x0,
@@ -898,6 +989,26 @@ void orc_solve_batch_param(const orc_scene *s, int64_t nb, const double *rx, con
         cost[i] = c;
         iters[i] = it;
         status[i] = (uint8_t)st;
+    }
+}
+
+void orc_visible_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                       const int32_t *order, const int32_t *prim, const double *x, const uint8_t *accept,
+                       double min_seg, uint8_t *visible, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < nb; i++) {
+        int n = order[i];
+        int32_t ids[MAXN];
+        double X[MAXU];
+        for (int k = 0; k < MAXN; k++) ids[k] = prim[k * nb + i];
+        for (int j = 0; j < MAXU; j++) X[j] = x[j * nb + i];
+        visible[i] = (accept[i] && n >= 1 && n <= MAXN)
+                         ? (uint8_t)orc_visible_one(s, rx + 3 * (size_t)rx_index[i], n, ids, X, min_seg)
+                         : 0;
     }
 }
 

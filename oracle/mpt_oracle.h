@@ -122,6 +122,15 @@ void orc_solve_batch_param(const orc_scene *s, int64_t nb, const double *rx, con
 int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
                    const double *X, int status, double tau_res, double min_seg);
 
+/* Physical validation of an accepted path (1 visible / 0 blocked): no
+ * segment may cross a rectangle facet or paraboloid patch other than the
+ * objects it starts and ends on, more than min_seg inside its ends. */
+int orc_visible_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids, const double *X,
+                    double min_seg);
+void orc_visible_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
+                       const int32_t *order, const int32_t *prim, const double *x, const uint8_t *accept,
+                       double min_seg, uint8_t *visible, int nthreads);
+
 /* Batched forms, component-major [15][nb] point arrays; OpenMP over solves.
  * x0 may be NULL. */
 void orc_solve_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
