@@ -352,6 +352,18 @@ def main_single(args, torch, mpt, W):
         results[v], outs[v] = run.run(v, steps, warm, tune=not args.no_autotune)
         flags[v] = run.flags()
     main_r, r = results[variant], outs[variant]
+    # physical validation of the headline variant's accepted paths (after
+    # the step; reported beside it, not part of the metric)
+    acc_t = torch.from_numpy(flags[variant]).to("cuda")
+    out_v = mpt.DeviceOut(n)
+    out_v.x.copy_(torch.from_numpy(r["x"]).to("cuda"))
+    vis, nvis = ctx.visible(run.db, out_v, acc_t)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        ctx.visible(run.db, out_v, acc_t, sync=False)
+    torch.cuda.synchronize()
+    validation = {"visible": nvis, "ms": (time.perf_counter() - t) * 100.0}
     prec = "fp32" if VARIANTS[variant][0] else "fp64"
     form = used_form(VARIANTS[variant][2], main_r["launch"], scene)
     main_r["form_used"] = form
@@ -370,6 +382,8 @@ def main_single(args, torch, mpt, W):
                          f"{orun['t']:.1f} s",
                "solves_per_s": orun["reps"] * orun["m"] / orun["t"]}
         par = parity(O, scene, orun, r, flags[variant])
+        ovis = O.visible_batch(scene, batch, r["x"], flags[variant], nthreads=cores)
+        validation["oracle_flag_mismatches"] = int((ovis != vis.cpu().numpy()).sum())
     # the metric counts the accepted paths that meet the 1e-6 m bar against
     # the oracle: exact when the whole workload was checked, else the
     # checked sample's share
@@ -377,7 +391,7 @@ def main_single(args, torch, mpt, W):
     if par and par["gpu_accepted"]:
         value *= par["accepted_within_bar"] / par["gpu_accepted"]
     emit(args, value, main_r["ms_per_step"], variant, "f32+f64" if VARIANTS[variant][0] else "f64",
-         NAMES[args.config], n, results, roof, cpu, par)
+         NAMES[args.config], n, results, roof, cpu, par, extra={"validation": validation})
 
 
 def main_learned(args, torch, mpt, W):

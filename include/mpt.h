@@ -263,6 +263,21 @@ mpt_status mpt_accept(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve
                       int32_t *d_count, int64_t *h_count);
 
 /*
+ * Physical validation of the accepted paths (Alg. 1 keeps a path whose points
+ * are valid; between interactions a ray travels in free space, Sec. II): a
+ * path stays when none of its segments crosses a rectangle facet or a
+ * paraboloid patch other than the objects it starts and ends on, more than
+ * min_seg (metres) inside its ends.  Edges and circles have no area and
+ * block nothing; a segment parallel to a facet is not blocked.  accept [n]
+ * uint8 (from mpt_accept) selects the paths; writes visible [n] uint8 (0 for
+ * the others) and their count into d_count (device int32); with h_count not
+ * NULL the call synchronises and stores the count there.  The arithmetic is
+ * IEEE FP64 without contraction.  Device pointers owned by the caller.
+ */
+mpt_status mpt_visible(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_out *in, const uint8_t *accept,
+                       double min_seg, uint8_t *visible, int32_t *d_count, int64_t *h_count);
+
+/*
  * Learned warm start (replaces the random guess of Alg. 1 by a network's
  * prediction).  Network: 96 features -> 256 -> 256 -> 256 -> 15 with GELU,
  * BF16 weights and activations, FP32 accumulation on the matrix cores; FP32

@@ -848,6 +848,30 @@ mpt_status mpt_accept(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_out *
     return MPT_OK;
 }
 
+mpt_status mpt_visible(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_out *in, const uint8_t *accept,
+                       double min_seg, uint8_t *visible, int32_t *d_count, int64_t *h_count)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
+    BatchDev bd;
+    mpt_status st = batch_dev(c, b, bd);
+    if (st) return st;
+    if (!in || !d_count || (b->n > 0 && (!in->x || !accept || !visible)))
+        return fail(c, MPT_E_INVALID_ARG, "null visibility argument");
+    if (!(min_seg >= 0)) return fail(c, MPT_E_INVALID_ARG, "negative segment margin");
+    hipSetDevice(c->device);
+    OutDevC ic{in->x, in->cost, in->iters, in->status};
+    launch_visible(c->s, bd, ic, accept, min_seg, visible, d_count, c->lds_max, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (h_count) {
+        int32_t v = 0;
+        HIPCHK(c, hipMemcpyAsync(&v, d_count, sizeof v, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *h_count = v;
+    }
+    return MPT_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- network entry points

@@ -87,6 +87,8 @@ void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const 
 const void *polish_kernel();
 void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st);
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
+void launch_visible(const SceneDev &s, const BatchDev &b, const OutDevC &in, const uint8_t *acc, double min_seg,
+                    uint8_t *vis, int *count, size_t lds_max, hipStream_t st);
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
                    uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st);
 

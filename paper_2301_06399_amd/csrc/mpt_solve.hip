@@ -1170,6 +1170,128 @@ void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
     hipLaunchKernelGGL(k_polish, dim3(grid), dim3(block), 0, st, kp);
 }
 
+// ------------------------------------------------------------------ physical validation
+// A kept path's segments may not pass through another object: a rectangle
+// facet or a paraboloid patch crossed strictly inside a segment (more than
+// min_seg from its ends) blocks it; the objects a segment starts or ends on
+// are not tested; edges and circles have no area.  The arithmetic is plain
+// IEEE FP64 in a fixed order with no contraction, so each decision is the
+// one a plain FP64 implementation of the same test takes.
+__device__ inline double vdot(const double *a, const double *b)
+{
+#pragma clang fp contract(off)
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ inline bool vis_plane(const double *r, const double P[3], const double d[3], double tmin, double tmax)
+{
+#pragma clang fp contract(off)
+    const double den = vdot(r, d);
+    if (den == 0.0) return false;
+    const double t = (r[3] - vdot(r, P)) / den;
+    if (!(t > tmin && t < tmax)) return false;
+    double w[3];
+    for (int i = 0; i < 3; i++) w[i] = (P[i] + t * d[i]) - r[4 + i];
+    const double a = vdot(w, r + 7), b = vdot(w, r + 10);
+    return a >= 0.0 && a <= vdot(r + 7, r + 7) && b >= 0.0 && b <= vdot(r + 10, r + 10);
+}
+
+__device__ inline bool vis_quadric(const double *r, const double P[3], const double d[3], double tmin, double tmax)
+{
+#pragma clang fp contract(off)
+    const double A[3][3] = {{r[3], r[4], r[5]}, {r[4], r[6], r[7]}, {r[5], r[7], r[8]}};
+    const double w[3] = {P[0] - r[0], P[1] - r[1], P[2] - r[2]};
+    double Ad[3], Aw[3];
+    for (int i = 0; i < 3; i++) {
+        Ad[i] = A[i][0] * d[0] + A[i][1] * d[1] + A[i][2] * d[2];
+        Aw[i] = A[i][0] * w[0] + A[i][1] * w[1] + A[i][2] * w[2];
+    }
+    const double a = vdot(d, Ad);
+    const double b = 2.0 * vdot(w, Ad) + vdot(r + 9, d);
+    const double c = vdot(w, Aw) + vdot(r + 9, w) + r[12];
+    double ts[2];
+    int nt = 0;
+    if (a == 0.0) {
+        if (b != 0.0) ts[nt++] = -c / b;
+    } else {
+        const double disc = b * b - 4.0 * a * c;
+        if (disc < 0.0) return false;
+        const double sq = sqrt(disc);
+        const double q = -0.5 * (b + (b >= 0.0 ? sq : -sq));
+        ts[nt++] = q / a;
+        if (q != 0.0) ts[nt++] = c / q;
+    }
+    for (int j = 0; j < nt; j++) {
+        const double t = ts[j];
+        if (!(t > tmin && t < tmax)) continue;
+        double v[3];
+        for (int i = 0; i < 3; i++) v[i] = (P[i] + t * d[i]) - r[i];
+        const double h = vdot(v, r + 13);
+        for (int i = 0; i < 3; i++) v[i] = v[i] - h * r[13 + i];
+        if (vdot(v, v) <= r[16] * r[16]) return true;
+    }
+    return false;
+}
+
+// One thread per solve: visible[i] = accept[i] and no segment is blocked.
+// Plane and quadric records are staged in LDS when `lds` is set.
+__global__ void __launch_bounds__(256) k_visible(SceneDev s, BatchDev b, OutDevC in, const uint8_t *__restrict__ acc,
+                                                 double min_seg, uint8_t *__restrict__ vis, int *__restrict__ count,
+                                                 int lds)
+{
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *srec = reinterpret_cast<double *>(smem_raw);
+    const int npl = s.n_pl, nq = s.n_pl_ln_q - s.n_pl_ln;
+    if (lds) {
+        for (int j = threadIdx.x; j < npl * kRec; j += blockDim.x) srec[j] = s.rec64[j];
+        for (int j = threadIdx.x; j < nq * kRec; j += blockDim.x)
+            srec[(size_t)npl * kRec + j] = s.rec64[(size_t)s.n_pl_ln * kRec + j];
+        __syncthreads();
+    }
+    const double *prec = lds ? srec : s.rec64;
+    const double *qrec = lds ? srec + (size_t)npl * kRec : s.rec64 + (size_t)s.n_pl_ln * kRec;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.n; i += (int64_t)gridDim.x * blockDim.x) {
+        bool ok = acc[i] != 0;
+        const int n = ok ? b.order[i] : 0;
+        const double *rx = b.rx + 3 * (size_t)(ok ? b.rx_index[i] : 0);
+        for (int k = 0; ok && k <= n; k++) {
+            double P[3], Q[3], d[3];
+            for (int c = 0; c < 3; c++) {
+                P[c] = (k == 0) ? s.tx[c] : in.x[(size_t)(3 * (k - 1) + c) * b.n + i];
+                Q[c] = (k == n) ? rx[c] : in.x[(size_t)(3 * k + c) * b.n + i];
+                d[c] = Q[c] - P[c];
+            }
+            const int ip = (k == 0) ? -1 : b.prim[(size_t)(k - 1) * b.n + i];
+            const int iq = (k == n) ? -1 : b.prim[(size_t)k * b.n + i];
+            const double L = sqrt(vdot(d, d));
+            if (!(L > 0.0)) { ok = false; break; }
+            const double tmin = min_seg / L, tmax = 1.0 - tmin;
+            for (int j = 0; ok && j < npl; j++)
+                if (j != ip && j != iq && vis_plane(prec + (size_t)j * kRec, P, d, tmin, tmax)) ok = false;
+            for (int j = 0; ok && j < nq; j++) {
+                const int gid = s.n_pl_ln + j;
+                if (gid != ip && gid != iq && vis_quadric(qrec + (size_t)j * kRec, P, d, tmin, tmax)) ok = false;
+            }
+        }
+        vis[i] = ok ? 1 : 0;
+        const uint64_t m = __ballot(ok);
+        if (m && __lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(count, (int)__popcll(m));
+    }
+}
+
+void launch_visible(const SceneDev &s, const BatchDev &b, const OutDevC &in, const uint8_t *acc, double min_seg,
+                    uint8_t *vis, int *count, size_t lds_max, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, count, 1);
+    if (b.n == 0) return;
+    const size_t bytes = (size_t)(s.n_pl + (s.n_pl_ln_q - s.n_pl_ln)) * kRec * sizeof(double);
+    const int lds = bytes <= lds_max && bytes <= 64 * 1024;
+    if (lds) hipFuncSetAttribute((const void *)k_visible, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const unsigned g = (unsigned)std::min<int64_t>((b.n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_visible, dim3(g), dim3(256), lds ? bytes : 0, st, s, b, in, acc, min_seg, vis, count, lds);
+}
+
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
                    uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st)
 {

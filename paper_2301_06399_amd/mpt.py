@@ -63,7 +63,7 @@ EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt
            "mpt_scene_upload", "mpt_default_opts", "mpt_solve_batch", "mpt_accept", "mpt_mlp_init",
            "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings",
            "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
-           "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused"]
+           "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused", "mpt_visible"]
 
 _lib = None
 
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     L.mpt_solve_batch.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut)]
     L.mpt_accept.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOut), C.c_double, C.c_double, vp, vp, vp,
                              C.POINTER(C.c_int64)]
+    L.mpt_visible.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOut), vp, C.c_double, vp, vp,
+                              C.POINTER(C.c_int64)]
     L.mpt_mlp_init.argtypes = [vp, C.c_uint64]
     L.mpt_mlp_train_step.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, C.c_float, vp]
     L.mpt_mlp_grad.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, vp, vp]
@@ -275,6 +277,21 @@ class Context:
         self._check(rc, "mpt_accept")
         k = int(hc.value) if sync else None
         return acc[:n], (idx[:k] if sync else idx), (k if sync else cnt)
+
+    def visible(self, dbatch: DeviceBatch, out: DeviceOut, accept, min_seg=1e-6, sync=True):
+        """Physical validation of the accepted paths: returns (visible flags
+        [n] uint8 device tensor, count or None)."""
+        torch = self.torch
+        vis = torch.empty(max(dbatch.n, 1), dtype=torch.uint8, device="cuda")
+        cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+        hc = C.c_int64(0)
+        bd, od = dbatch.desc(), out.desc()
+        self._enter()
+        rc = self.L.mpt_visible(self.h, C.byref(bd), C.byref(od), _ptr(accept), min_seg, _ptr(vis), _ptr(cnt),
+                                C.byref(hc) if sync else None)
+        self._leave()
+        self._check(rc, "mpt_visible")
+        return vis[:dbatch.n], (hc.value if sync else None)
 
     def autotune(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None):
         out = out or DeviceOut(dbatch.n)
