@@ -61,7 +61,10 @@ enum { MPT_PLANE = 0, MPT_LINE = 1, MPT_QUADRIC = 2, MPT_CIRCLE = 3 };
 enum { MPT_MAX_ORDER = 5 };
 
 /* Record widths (doubles) of the host scene arrays. */
-enum { MPT_PLANE_W = 13, MPT_LINE_W = 8, MPT_QUADRIC_W = 17, MPT_CIRCLE_W = 7 };
+enum { MPT_PLANE_W = 13, MPT_LINE_W = 8, MPT_QUADRIC_W = 17, MPT_CIRCLE_W = 7, MPT_WEDGE_W = 7 };
+/* Kind of a straight edge's wedge: no solid, the outer corner of a solid,
+ * an inner corner (the free space is the wedge between the faces). */
+enum { MPT_WEDGE_NONE = 0, MPT_WEDGE_OUTER = 1, MPT_WEDGE_INNER = 2 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
  * enqueue on (for example the caller's current stream), or NULL for a
@@ -87,17 +90,22 @@ mpt_status mpt_synchronize(mpt_ctx *ctx);
  *                             b(3), c with f = (x-p)^T A (x-p) + b^T(x-p) + c,
  *                             ax(3) patch axis, r_ap patch radius about ax
  *   circles  [n_circles][7]   c(3) centre, n(3) unit plane normal, R
+ *   wedges   [n_lines][7]     optional (NULL: none): m1(3), m2(3) unit
+ *                             normals of the two faces meeting at the edge,
+ *                             pointing into free space, kind (MPT_WEDGE_*)
  * Global primitive ids are type-major: planes, lines, quadrics, circles.
  * aabb_lo/hi bound the scene; the guard box is that box scaled 10x about
  * its centre plus 1 m.  The arrays are copied (and packed by a device
  * kernel into the solver's FP64 and TX-local FP32 records); the caller keeps
  * ownership.  Errors: MPT_E_INVALID_ARG for non-finite values, non-unit
- * directions (|1-|v|| > 1e-9) or a non-positive radius.  Synchronises. */
+ * directions (|1-|v|| > 1e-9), a non-positive radius or a wedge kind other
+ * than 0, 1, 2.  Synchronises. */
 typedef struct {
     double tx[3];
     double aabb_lo[3], aabb_hi[3];
     int32_t n_planes, n_lines, n_quadrics, n_circles;
     const double *planes, *lines, *quadrics, *circles;
+    const double *wedges;  /* [n_lines][7] or NULL (used by mpt_visible only) */
 } mpt_scene_desc;
 mpt_status mpt_scene_upload(mpt_ctx *ctx, const mpt_scene_desc *scene);
 
@@ -268,7 +276,11 @@ mpt_status mpt_accept(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve
  * path stays when none of its segments crosses a rectangle facet or a
  * paraboloid patch other than the objects it starts and ends on, more than
  * min_seg (metres) inside its ends.  Edges and circles have no area and
- * block nothing; a segment parallel to a facet is not blocked.  accept [n]
+ * block nothing; a segment parallel to a facet is not blocked.  At a
+ * straight edge with a wedge (scene upload) both segments must leave the
+ * edge point X into free space: with d the direction to the neighbouring
+ * point, an outer corner blocks d when <d,m1> < 0 and <d,m2> < 0, an inner
+ * corner when either is negative.  accept [n]
  * uint8 (from mpt_accept) selects the paths; writes visible [n] uint8 (0 for
  * the others) and their count into d_count (device int32); with h_count not
  * NULL the call synchronises and stores the count there.  The arithmetic is

@@ -34,7 +34,8 @@ def build() -> str:
 class _Scene(C.Structure):
     _fields_ = [("tx", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("n_pl", C.c_int32), ("n_ln", C.c_int32), ("n_q", C.c_int32), ("n_c", C.c_int32),
-                ("pl", C.c_void_p), ("ln", C.c_void_p), ("q", C.c_void_p), ("c", C.c_void_p)]
+                ("pl", C.c_void_p), ("ln", C.c_void_p), ("q", C.c_void_p), ("c", C.c_void_p),
+                ("wd", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -89,12 +90,15 @@ class OracleScene:
     def __init__(self, scene):
         self.keep = [np.ascontiguousarray(getattr(scene, k), dtype=np.float64)
                      for k in ("planes", "lines", "quadrics", "circles")]
+        wd = getattr(scene, "wedges", None)
+        self.wd = np.ascontiguousarray(wd, dtype=np.float64) if wd is not None and len(wd) else None
         s = _Scene()
         s.tx[:] = list(scene.tx)
         s.lo[:] = list(scene.aabb_lo)
         s.hi[:] = list(scene.aabb_hi)
         s.n_pl, s.n_ln, s.n_q, s.n_c = (len(a) for a in self.keep)
         s.pl, s.ln, s.q, s.c = (_p(a) for a in self.keep)
+        s.wd = _p(self.wd)
         self.s = s
 
     @property

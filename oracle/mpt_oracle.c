@@ -909,10 +909,35 @@ static int seg_hits_quadric(const double *r, const double P[3], const double d[3
     return 0;
 }
 
+/* A diffracted ray leaves its edge into free space (Sec. II: rays travel in
+   free space between interactions).  The faces meeting at the edge bound the
+   solid near the edge point X: with their normals m1, m2 pointing into free
+   space, the direction d from X towards a neighbouring point of the path
+   enters the solid when both <d,m1> and <d,m2> are negative at an outer
+   corner (kind 1), or when either is negative at an inner corner (kind 2). */
+static int wedge_blocks(const double *w, const double *X, const double *Q)
+{
+    double d[3];
+    sub3(Q, X, d);
+    double a1 = dot3(d, w), a2 = dot3(d, w + 3);
+    if (w[6] == 1.0) return a1 < 0.0 && a2 < 0.0;
+    if (w[6] == 2.0) return a1 < 0.0 || a2 < 0.0;
+    return 0;
+}
+
 int orc_visible_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids, const double *X,
                     double min_seg)
 {
     if (!ids_ok(s, n, ids)) return 0;
+    if (s->wd)
+        for (int k = 0; k < n; k++) {
+            int j = ids[k] - s->n_pl;
+            if (j < 0 || j >= s->n_ln) continue;
+            const double *P = (k == 0) ? s->tx : X + 3 * (k - 1);
+            const double *Q = (k == n - 1) ? rx : X + 3 * (k + 1);
+            const double *w = s->wd + 7 * (size_t)j;
+            if (wedge_blocks(w, X + 3 * k, P) || wedge_blocks(w, X + 3 * k, Q)) return 0;
+        }
     for (int k = 0; k <= n; k++) {
         const double *P = (k == 0) ? s->tx : X + 3 * (k - 1);
         const double *Q = (k == n) ? rx : X + 3 * k;

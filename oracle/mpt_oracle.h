@@ -61,6 +61,10 @@ typedef struct {
     const double *ln;              /* [n_ln][8]  p, e, s0, s1               */
     const double *q;               /* [n_q][17]  p, A(6), b, c, ax, r_ap     */
     const double *c;               /* [n_c][7]   c, n, R                    */
+    const double *wd;              /* [n_ln][7]  wedge of each straight edge:
+                                      m1, m2 face normals into free space, kind
+                                      (0 none, 1 outer corner, 2 inner corner);
+                                      NULL: no wedges                          */
 } orc_scene;
 
 typedef struct {
@@ -124,7 +128,8 @@ int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t 
 
 /* Physical validation of an accepted path (1 visible / 0 blocked): no
  * segment may cross a rectangle facet or paraboloid patch other than the
- * objects it starts and ends on, more than min_seg inside its ends. */
+ * objects it starts and ends on, more than min_seg inside its ends, and no
+ * segment at a straight edge with a wedge may leave it into the solid. */
 int orc_visible_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids, const double *X,
                     double min_seg);
 void orc_visible_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,

@@ -24,9 +24,9 @@ struct mpt_ctx {
     int cu = 256;
     size_t lds_max = 65536;  // dynamic LDS a block may use
     // scene
-    double *raw = nullptr, *rec64 = nullptr;
+    double *raw = nullptr, *rec64 = nullptr, *wd = nullptr;
     float *rec32 = nullptr;
-    size_t scene_cap = 0, raw_cap = 0;
+    size_t scene_cap = 0, raw_cap = 0, wd_cap = 0;
     SceneDev s{};
     bool has_scene = false;
     bool curved = false;     // the scene has paraboloids or circles
@@ -142,6 +142,7 @@ mpt_status mpt_destroy(mpt_ctx *c)
     hipFree(c->raw);
     hipFree(c->rec64);
     hipFree(c->rec32);
+    hipFree(c->wd);
     hipFree(c->ws);
     hipFree(c->blk);
     hipFree(c->x0l);
@@ -217,6 +218,16 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
         if (!unit3(d->circles + 7 * (size_t)i + 3)) return fail(c, MPT_E_INVALID_ARG, "circle %d: normal not unit", i);
         if (!(d->circles[7 * (size_t)i + 6] > 0)) return fail(c, MPT_E_INVALID_ARG, "circle %d: radius <= 0", i);
     }
+    if (d->wedges) {
+        if (!finite_all(d->wedges, (size_t)nl * 7)) return fail(c, MPT_E_INVALID_ARG, "non-finite wedge value");
+        for (int i = 0; i < nl; i++) {
+            const double *w = d->wedges + 7 * (size_t)i;
+            if (w[6] != 0.0 && w[6] != 1.0 && w[6] != 2.0)
+                return fail(c, MPT_E_INVALID_ARG, "wedge %d: kind is not 0, 1 or 2", i);
+            if (w[6] != 0.0 && !(unit3(w) && unit3(w + 3)))
+                return fail(c, MPT_E_INVALID_ARG, "wedge %d: face normal not unit", i);
+        }
+    }
     const size_t n_all = (size_t)np + nl + nq + nc;
     const size_t raw_n = (size_t)np * 13 + (size_t)nl * 8 + (size_t)nq * 17 + (size_t)nc * 7;
     hipSetDevice(c->device);
@@ -233,7 +244,14 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
     memcpy(host.data() + o, d->quadrics, (size_t)nq * 17 * 8), o += (size_t)nq * 17;
     memcpy(host.data() + o, d->circles, (size_t)nc * 7 * 8), o += (size_t)nc * 7;
     HIPCHK(c, hipMemcpyAsync(c->raw, host.data(), raw_n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const bool wedges = d->wedges && nl > 0;
+    if (wedges) {
+        if ((st = ensure(c, (void **)&c->wd, &c->wd_cap, (size_t)nl * 7, sizeof(double)))) return st;
+        HIPCHK(c, hipMemcpyAsync(c->wd, d->wedges, (size_t)nl * 7 * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+    }
     SceneDev s{};
+    s.wedge = wedges ? c->wd : nullptr;
     s.rec64 = c->rec64;
     s.rec32 = c->rec32;
     s.n_pl = np;
@@ -516,8 +534,10 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
             int *rows = (int *)kp.pol_list, *count = ctr + 30;
             launch_curved_rows(bd, c->s, rows, count, s);
             st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s, rows, count);
+            if (!st) launch_learned_choose(c->s, bd, rows, count, false, c->x0l, s);
         } else {
             st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s);
+            if (!st) launch_learned_choose(c->s, bd, nullptr, nullptr, true, c->x0l, s);
         }
         if (st) return fail(c, st, "network forward failed");
     }

@@ -19,6 +19,7 @@ struct SceneDev {
     double tx[3];
     double glo[3], ghi[3];  // guard box
     double lo[3], hi[3];    // scene box (random starts)
+    const double *wedge;    // [n_pl_ln - n_pl][7] wedges of the straight edges, or null
 };
 
 struct BatchDev {
@@ -86,6 +87,8 @@ void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const 
                hipStream_t st);
 const void *polish_kernel();
 void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st);
+void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
+                           double *x0l, hipStream_t st);
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
 void launch_visible(const SceneDev &s, const BatchDev &b, const OutDevC &in, const uint8_t *acc, double min_seg,
                     uint8_t *vis, int *count, size_t lds_max, hipStream_t st);

@@ -304,6 +304,73 @@ __device__ inline bool in_guard(const SceneDev &s, const double *X, int n)
     return ok;
 }
 
+// ------------------------------------------------------------------ learned start
+// The network's points, projected onto their objects, replace the
+// straight-line start of a path only when their FP64 cost is lower: the
+// solver's own cost judges the prediction.  Writes the chosen start points
+// into x0l (rows of the path; one thread per served path).
+template <int N>
+__device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, double *__restrict__ x0l)
+{
+    SceneT<double> s64;
+    s64.rec = s.rec64;
+    PathIn<double, N> q;
+    const int ri = b.rx_index[i];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        s64.tx[c] = s.tx[c];
+        s64.glo[c] = s.glo[c];
+        s64.ghi[c] = s.ghi[c];
+        q.rx[c] = b.rx[3 * (size_t)ri + c];
+    }
+    q.planar = false;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        q.id[k] = b.prim[(size_t)k * b.n + i];
+        q.ty[k] = prim_type(q.id[k], s.n_pl, s.n_pl_ln, s.n_pl_ln_q);
+    }
+    double X0[3 * N], Xn[3 * N];
+    bool okn = true;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const double a = (double)(k + 1) / (double)(N + 1);
+        double P[3], Pn[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            P[c] = s.tx[c] + a * (q.rx[c] - s.tx[c]);
+            Pn[c] = x0l[(size_t)(3 * k + c) * b.n + i];
+            okn = okn && isfinite(Pn[c]);
+        }
+        const double *r = s.rec64 + (size_t)q.id[k] * kRec;
+        project(q.ty[k], r, P, X0 + 3 * k);
+        project(q.ty[k], r, okn ? Pn : P, Xn + 3 * k);
+    }
+    double c0 = 0.0, r0 = 0.0, c1 = 0.0, r1 = 0.0;
+    const bool ok0 = eval_cost<double, N>(s64, q, X0, nullptr, c0, r0);
+    const bool ok1 = okn && eval_cost<double, N>(s64, q, Xn, nullptr, c1, r1);
+    const bool net = ok1 && (!ok0 || c1 < c0);
+#pragma unroll
+    for (int j = 0; j < 3 * N; j++) x0l[(size_t)j * b.n + i] = net ? Xn[j] : X0[j];
+}
+
+__global__ void __launch_bounds__(256) k_learned_choose(SceneDev s, BatchDev b, const int *__restrict__ rows,
+                                                        const int *__restrict__ count, int all,
+                                                        double *__restrict__ x0l)
+{
+    const int64_t m = all ? b.n : (int64_t)*count;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = all ? t : rows[t];
+        switch (valid_order(b, i, s.n_all)) {
+        case 1: choose_start<1>(s, b, i, x0l); break;
+        case 2: choose_start<2>(s, b, i, x0l); break;
+        case 3: choose_start<3>(s, b, i, x0l); break;
+        case 4: choose_start<4>(s, b, i, x0l); break;
+        case 5: choose_start<5>(s, b, i, x0l); break;
+        default: break;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ LM lane state
 template <typename T>
 struct LMOpts {
@@ -597,7 +664,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     bool use_net = (init == INIT_LEARNED_ALL);
                     if (init == INIT_LEARNED)
                         for (int k = 0; k < N; k++) use_net = use_net || p.ty[k] == TQ || p.ty[k] == TC;
-                    if (init == INIT_RANDOM || init == INIT_LINE || init == INIT_LEARNED || init == INIT_LEARNED_ALL) {
+                    if (init == INIT_RANDOM || init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
                         // the projection onto each object of a point on the
                         // TX -> RX segment, or of a random point of the scene box
                         const bool rnd = init == INIT_RANDOM;
@@ -617,6 +684,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                             project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
                         }
                     } else {
+                        // the fallback's FP32 end point, the caller's points,
+                        // or the learned start chosen before the LM pass
                         const double *x0 = (MODE == MODE_FALLBACK64) ? kp.out.x
                                            : (init == INIT_USER)     ? kp.b.x0
                                                                      : kp.x0_learned;
@@ -624,46 +693,6 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                         for (int j = 0; j < 3 * N; j++) {
                             X0[j] = x0[(size_t)j * kp.b.n + sid];
                             ok = ok && isfinite(X0[j]);
-                        }
-                    }
-                    if (use_net) {
-                        // the network's points, projected onto their objects,
-                        // replace the straight-line start when their cost is
-                        // lower: the solver's own cost judges the prediction
-                        double Xn[3 * N];
-                        bool okn = true;
-#pragma unroll
-                        for (int k = 0; k < N; k++) {
-                            double P[3];
-#pragma unroll
-                            for (int i = 0; i < 3; i++) {
-                                P[i] = kp.x0_learned[(size_t)(3 * k + i) * kp.b.n + sid];
-                                okn = okn && isfinite(P[i]);
-                            }
-                            project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, Xn + 3 * k);
-                        }
-                        if (okn) {
-                            SceneT<double> s64;
-                            s64.rec = kp.s.rec64;
-                            PathIn<double, N> q;
-#pragma unroll
-                            for (int i = 0; i < 3; i++) {
-                                s64.tx[i] = kp.s.tx[i];
-                                s64.glo[i] = kp.s.glo[i];
-                                s64.ghi[i] = kp.s.ghi[i];
-                                q.rx[i] = rx[i];
-                            }
-#pragma unroll
-                            for (int k = 0; k < N; k++) {
-                                q.id[k] = p.id[k];
-                                q.ty[k] = p.ty[k];
-                            }
-                            double c0, r0, c1, r1;
-                            const bool ok0 = eval_cost<double, N>(s64, q, X0, nullptr, c0, r0);
-                            const bool ok1 = eval_cost<double, N>(s64, q, Xn, nullptr, c1, r1);
-                            if (ok1 && (!ok0 || c1 < c0))
-#pragma unroll
-                                for (int j = 0; j < 3 * N; j++) X0[j] = Xn[j];
                         }
                     }
                     int st0 = ST_RUNNING;
@@ -1165,6 +1194,14 @@ void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *co
                        rows, count);
 }
 
+void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
+                           double *x0l, hipStream_t st)
+{
+    if (b.n == 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>((b.n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_learned_choose, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l);
+}
+
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
 {
     hipLaunchKernelGGL(k_polish, dim3(grid), dim3(block), 0, st, kp);
@@ -1233,6 +1270,20 @@ __device__ inline bool vis_quadric(const double *r, const double P[3], const dou
     return false;
 }
 
+// A segment at a straight edge with a wedge may not leave the edge point X
+// into the solid: m1, m2 are the normals of the faces meeting at the edge,
+// pointing into free space; at an outer corner (kind 1) the solid is where
+// both <d, m> are negative, at an inner corner (kind 2) where either is.
+__device__ inline bool vis_wedge(const double *w, const double X[3], const double Q[3])
+{
+#pragma clang fp contract(off)
+    const double d[3] = {Q[0] - X[0], Q[1] - X[1], Q[2] - X[2]};
+    const double a1 = vdot(d, w), a2 = vdot(d, w + 3);
+    if (w[6] == 1.0) return a1 < 0.0 && a2 < 0.0;
+    if (w[6] == 2.0) return a1 < 0.0 || a2 < 0.0;
+    return false;
+}
+
 // One thread per solve: visible[i] = accept[i] and no segment is blocked.
 // Plane and quadric records are staged in LDS when `lds` is set.
 __global__ void __launch_bounds__(256) k_visible(SceneDev s, BatchDev b, OutDevC in, const uint8_t *__restrict__ acc,
@@ -1273,6 +1324,11 @@ __global__ void __launch_bounds__(256) k_visible(SceneDev s, BatchDev b, OutDevC
                 const int gid = s.n_pl_ln + j;
                 if (gid != ip && gid != iq && vis_quadric(qrec + (size_t)j * kRec, P, d, tmin, tmax)) ok = false;
             }
+            // the segment's ends on straight edges: both leave into free space
+            if (ok && s.wedge && ip >= npl && ip < s.n_pl_ln && vis_wedge(s.wedge + 7 * (size_t)(ip - npl), P, Q))
+                ok = false;
+            if (ok && s.wedge && iq >= npl && iq < s.n_pl_ln && vis_wedge(s.wedge + 7 * (size_t)(iq - npl), Q, P))
+                ok = false;
         }
         vis[i] = ok ? 1 : 0;
         const uint64_t m = __ballot(ok);

@@ -34,7 +34,7 @@ class SceneDesc(C.Structure):
     _fields_ = [("tx", C.c_double * 3), ("aabb_lo", C.c_double * 3), ("aabb_hi", C.c_double * 3),
                 ("n_planes", C.c_int32), ("n_lines", C.c_int32), ("n_quadrics", C.c_int32),
                 ("n_circles", C.c_int32), ("planes", C.c_void_p), ("lines", C.c_void_p),
-                ("quadrics", C.c_void_p), ("circles", C.c_void_p)]
+                ("quadrics", C.c_void_p), ("circles", C.c_void_p), ("wedges", C.c_void_p)]
 
 
 class BatchDesc(C.Structure):
@@ -250,6 +250,12 @@ class Context:
         d.aabb_hi[:] = list(map(float, scene.aabb_hi))
         d.n_planes, d.n_lines, d.n_quadrics, d.n_circles = (len(a) for a in keep)
         d.planes, d.lines, d.quadrics, d.circles = (a.ctypes.data if a.size else None for a in keep)
+        wd = getattr(scene, "wedges", None)
+        if wd is not None and len(wd):
+            wd = np.ascontiguousarray(wd, np.float64)
+            if wd.shape != (len(keep[1]), 7):
+                raise ValueError("wedges: one record of 7 values per straight edge")
+            d.wedges = wd.ctypes.data
         self._check(self.L.mpt_scene_upload(self.h, C.byref(d)), "mpt_scene_upload")
 
     def solve(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None) -> DeviceOut:

@@ -19,6 +19,13 @@ then circular edges.
                  f(x) = (x-p)^T A (x-p) + b^T (x-p) + c
   circle   (7) : c(3) centre, n(3) unit normal of its plane, R radius
 
+Optional wedge of each straight edge (7 values, empty array: none): m1(3),
+m2(3) unit normals of the two faces that meet at the edge, pointing into
+free space, and a kind: 0 a free edge, 1 the outer corner of a solid (the
+solid lies where both <x - X, m1> and <x - X, m2> are negative), 2 an inner
+corner (the solid lies where either is negative).  Physical validation uses
+it to keep diffracted rays out of the solids.
+
 All seeds derive from S = 230106399 as S + 1000*cfg + stream with the
 streams scene=1, rx=2, seq=3, init=4, train=5, heldout=6.
 """
@@ -30,7 +37,7 @@ import numpy as np
 SEED_BASE = 230106399
 STREAM = {"scene": 1, "rx": 2, "seq": 3, "init": 4, "train": 5, "heldout": 6}
 
-PLANE_W, LINE_W, QUAD_W, CIRC_W = 13, 8, 17, 7
+PLANE_W, LINE_W, QUAD_W, CIRC_W, WEDGE_W = 13, 8, 17, 7, 7
 T_PLANE, T_LINE, T_QUAD, T_CIRC = 0, 1, 2, 3
 MAX_ORDER = 5
 
@@ -46,13 +53,16 @@ class Scene:
     lines: np.ndarray = field(default_factory=lambda: np.zeros((0, LINE_W)))
     quadrics: np.ndarray = field(default_factory=lambda: np.zeros((0, QUAD_W)))
     circles: np.ndarray = field(default_factory=lambda: np.zeros((0, CIRC_W)))
+    wedges: np.ndarray = field(default_factory=lambda: np.zeros((0, WEDGE_W)))
     aabb_lo: np.ndarray = field(default_factory=lambda: np.zeros(3))
     aabb_hi: np.ndarray = field(default_factory=lambda: np.zeros(3))
 
     def __post_init__(self):
         self.tx = np.ascontiguousarray(self.tx, dtype=np.float64)
-        for k in ("planes", "lines", "quadrics", "circles"):
+        for k in ("planes", "lines", "quadrics", "circles", "wedges"):
             setattr(self, k, np.ascontiguousarray(getattr(self, k), dtype=np.float64))
+        if len(self.wedges) and self.wedges.shape != (len(self.lines), WEDGE_W):
+            raise ValueError("wedges: one record of 7 values per straight edge, or none")
         self.aabb_lo = np.ascontiguousarray(self.aabb_lo, dtype=np.float64)
         self.aabb_hi = np.ascontiguousarray(self.aabb_hi, dtype=np.float64)
 
@@ -127,6 +137,10 @@ def paraboloid(vertex, axis, focal):
                            -ax, [0.0], ax, [2.0 * focal]])
 
 
+def wedge(m1, m2, kind):
+    return np.concatenate([np.asarray(m1, float), np.asarray(m2, float), [float(kind)]])
+
+
 def circle(c, n, R):
     return np.concatenate([np.asarray(c, float), np.asarray(n, float), [float(R)]])
 
@@ -197,7 +211,9 @@ def room_scene() -> Scene:
         line_seg([0, 0, 0], [0, 0, 1], 0.0, H),      # vertical corner x=0,y=0
         line_seg([0, W, H], [1, 0, 0], 0.0, L),      # y=10 wall / ceiling junction
     ])
-    return Scene(tx=np.array([2.0, 3.0, 1.5]), planes=planes, lines=lines,
+    # inner corners: the room is the free space
+    wedges = np.stack([wedge([1, 0, 0], [0, 1, 0], 2), wedge([0, -1, 0], [0, 0, -1], 2)])
+    return Scene(tx=np.array([2.0, 3.0, 1.5]), planes=planes, lines=lines, wedges=wedges,
                  aabb_lo=np.zeros(3), aabb_hi=np.array([L, W, H]))
 
 
@@ -239,7 +255,7 @@ def street_canyon_scene(cfg: int = 2, n_boxes: int = 50, tx_height: float = 30.0
                for b in boxes):
             boxes.append((cx, cy, w, d, h))
     planes = [plane_rect([0, 0, 1], 0.0, [0, 0, 0], [size, 0, 0], [0, size, 0])]
-    lines = []
+    lines, wedges = [], []
     for cx, cy, w, d, h in boxes:
         x0, x1, y0, y1 = cx - w / 2, cx + w / 2, cy - d / 2, cy + d / 2
         planes += [
@@ -249,10 +265,14 @@ def street_canyon_scene(cfg: int = 2, n_boxes: int = 50, tx_height: float = 30.0
             plane_rect([0, 1, 0], y1, [x0, y1, 0], [w, 0, 0], [0, 0, h]),
             plane_rect([0, 0, 1], h, [x0, y0, h], [w, 0, 0], [0, d, 0]),
         ]
-        for (x, y) in ((x0, y0), (x1, y0), (x1, y1), (x0, y1)):
+        for (x, y, sx, sy) in ((x0, y0, -1, -1), (x1, y0, 1, -1), (x1, y1, 1, 1), (x0, y1, -1, 1)):
             lines.append(line_seg([x, y, 0], [0, 0, 1], 0.0, h))
+            wedges.append(wedge([sx, 0, 0], [0, sy, 0], 1))
         lines += [line_seg([x0, y0, h], [1, 0, 0], 0.0, w), line_seg([x0, y1, h], [1, 0, 0], 0.0, w),
                   line_seg([x0, y0, h], [0, 1, 0], 0.0, d), line_seg([x1, y0, h], [0, 1, 0], 0.0, d)]
+        # roof edges: a wall and the roof meet there (outer corners of the box)
+        wedges += [wedge([0, -1, 0], [0, 0, 1], 1), wedge([0, 1, 0], [0, 0, 1], 1),
+                   wedge([-1, 0, 0], [0, 0, 1], 1), wedge([1, 0, 0], [0, 0, 1], 1)]
     boxes = np.array(boxes)
 
     def free_xy(r, n, margin=1.0):
@@ -267,7 +287,7 @@ def street_canyon_scene(cfg: int = 2, n_boxes: int = 50, tx_height: float = 30.0
 
     txy = free_xy(rng, 1)[0]
     sc = Scene(tx=np.array([txy[0], txy[1], tx_height]), planes=np.array(planes),
-               lines=np.array(lines), aabb_lo=np.zeros(3),
+               lines=np.array(lines), wedges=np.array(wedges), aabb_lo=np.zeros(3),
                aabb_hi=np.array([size, size, max(40.0, boxes[:, 4].max())]))
     sc._boxes = boxes
     sc._free_xy = free_xy
@@ -353,7 +373,7 @@ def config3(n_rx: int = 16384, per_rx: int = 64) -> tuple[Scene, Batch]:
 def stress_scene() -> Scene:
     sc = street_canyon_scene(5)
     q = curved_scene(5, n_quad=30, n_circ=0, rng=np.random.default_rng(seed(5, "scene") + 77))
-    out = Scene(tx=sc.tx, planes=sc.planes, lines=sc.lines, quadrics=q.quadrics,
+    out = Scene(tx=sc.tx, planes=sc.planes, lines=sc.lines, quadrics=q.quadrics, wedges=sc.wedges,
                 aabb_lo=sc.aabb_lo, aabb_hi=sc.aabb_hi)
     out._boxes, out._free_xy = sc._boxes, sc._free_xy
     return out

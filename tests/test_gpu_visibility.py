@@ -55,6 +55,21 @@ def test_visibility_full_pipeline_against_oracle(ctx):
         assert np.array_equal(vis, ovis)
 
 
+def test_visibility_wedges_match_oracle(ctx):
+    """Double diffractions through the buildings (the wedges decide), and
+    the room's inner corners: the same flags as the oracle on the GPU's
+    points, and none of the through-building paths kept."""
+    from test_oracle_visibility import diagonal_edge_batch
+    sc = W.street_canyon_scene(2)
+    b = diagonal_edge_batch(sc)
+    g, acc, vis, nv = run(ctx, sc, b)
+    assert acc.sum() > 200
+    assert np.array_equal(vis, O.visible_batch(sc, b, g["x"], acc))
+    sc, b = W.config1()
+    g, acc, vis, nv = run(ctx, sc, b)
+    assert np.array_equal(vis, O.visible_batch(sc, b, g["x"], acc))
+
+
 def test_visibility_edge_cases(ctx):
     """An empty batch; a margin longer than every segment keeps every
     accepted path (nothing can be crossed strictly inside)."""

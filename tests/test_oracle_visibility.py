@@ -2,9 +2,10 @@
 pass through another object (Alg. 1 keeps paths whose points are valid, and
 Sec. II's rays travel in free space between interactions).
 
-The facet-by-facet test of the oracle is checked against an independent
-slab-method segment/box test on the street-canyon buildings, and against
-closed forms for a paraboloid dish.
+The facet-by-facet test of the oracle, with the wedges of the building
+edges, is checked against an independent slab-method segment/box test on
+the street-canyon buildings, and against closed forms for a paraboloid dish
+and the room's inner corners.
 """
 import numpy as np
 
@@ -26,6 +27,96 @@ def segment_enters_box(P, Q, lo, hi, margin):
         a, b = (lo[i] - P[i]) / d[i], (hi[i] - P[i]) / d[i]
         t0, t1 = max(t0, min(a, b)), min(t1, max(a, b))
     return t0 < t1
+
+
+def segments_enter_boxes(P, Q, boxes, margin):
+    """The slab test of one segment against every box at once."""
+    lo = np.column_stack([boxes[:, 0] - boxes[:, 2] / 2, boxes[:, 1] - boxes[:, 3] / 2, np.zeros(len(boxes))])
+    hi = np.column_stack([boxes[:, 0] + boxes[:, 2] / 2, boxes[:, 1] + boxes[:, 3] / 2, boxes[:, 4]])
+    d = Q - P
+    L = np.linalg.norm(d)
+    t0 = np.full(len(boxes), margin / L)
+    t1 = np.full(len(boxes), 1.0 - margin / L)
+    inside = np.ones(len(boxes), bool)
+    for i in range(3):
+        if abs(d[i]) < 1e-300:
+            inside &= (lo[:, i] < P[i]) & (P[i] < hi[:, i])
+            continue
+        a, b = (lo[:, i] - P[i]) / d[i], (hi[:, i] - P[i]) / d[i]
+        t0, t1 = np.maximum(t0, np.minimum(a, b)), np.minimum(t1, np.maximum(a, b))
+    return bool((inside & (t0 < t1)).any())
+
+
+def path_enters_boxes(sc, rx, n, X, boxes, margin=1e-6):
+    pts = [sc.tx] + [X[3 * k:3 * k + 3] for k in range(n)] + [rx]
+    return any(segments_enter_boxes(pts[k], pts[k + 1], boxes, margin) for k in range(n + 1))
+
+
+def diagonal_edge_batch(sc, n_per=4, seed=7):
+    """Double diffractions on two diagonally opposite vertical edges of one
+    box (the segment between them runs through the box), TX -> E -> E' -> RX,
+    for every box of the street canyon."""
+    rng = np.random.default_rng(seed)
+    npl = len(sc.planes)
+    ids, rxs = [], []
+    for bi in range(len(sc._boxes)):
+        base = npl + 8 * bi
+        for a, c in ((0, 2), (1, 3), (2, 0), (3, 1)):
+            for _ in range(n_per):
+                ids.append([base + a, base + c])
+                rxs.append(np.append(sc._free_xy(rng, 1)[0], rng.uniform(0.5, 45.0)))
+    n = len(ids)
+    prim = np.full((5, n), -1, np.int32)
+    prim[:2] = np.array(ids, np.int32).T
+    return W.Batch(np.array(rxs), np.arange(n, dtype=np.int32), np.full(n, 2, np.int32), prim)
+
+
+def test_wedges_keep_diffracted_rays_out_of_the_buildings():
+    """Keller roots on two diagonal edges of one box: the facet test alone
+    keeps some paths whose middle segment runs through the building; with
+    the wedges the oracle's flags are exactly those of the slab test."""
+    sc = W.street_canyon_scene(2)
+    b = diagonal_edge_batch(sc)
+    r = O.solve_batch(sc, b)
+    acc = O.accept_batch(sc, b, r["x"], r["status"])
+    vis = O.visible_batch(sc, b, r["x"], acc)
+    bare = W.Scene(tx=sc.tx, planes=sc.planes, lines=sc.lines, aabb_lo=sc.aabb_lo, aabb_hi=sc.aabb_hi)
+    vis_bare = O.visible_batch(bare, b, r["x"], acc)
+    assert acc.sum() > 200
+    slab = np.array([acc[i] == 1 and not path_enters_boxes(sc, b.rx[i], 2, r["x"][:6, i], sc._boxes)
+                     for i in range(b.n)])
+    assert np.array_equal(vis == 1, slab)
+    assert ((vis_bare == 1) & ~slab).sum() >= 10
+
+
+def test_visibility_matches_slab_test_on_street_canyon_paths():
+    """Every accepted root of a street-canyon subset (reflections on walls,
+    roofs and the ground, diffractions on the box edges, orders 1-3): the
+    oracle's flags equal the slab test against all 50 buildings."""
+    sc, b = W.config2(n_rx=256, per_rx=64)
+    r = O.solve_batch(sc, b)
+    acc = O.accept_batch(sc, b, r["x"], r["status"])
+    vis = O.visible_batch(sc, b, r["x"], acc)
+    idx = np.where(acc == 1)[0]
+    assert len(idx) > 1000
+    slab = np.array([not path_enters_boxes(sc, b.rx[b.rx_index[i]], b.order[i], r["x"][:, i], sc._boxes)
+                     for i in idx])
+    assert np.array_equal(vis[idx] == 1, slab)
+    assert 0 < slab.sum() < len(idx)
+
+
+def test_room_inner_corners():
+    """The room's junction edges are inner corners: a segment from the
+    vertical corner into the room is free, one leaving the room is blocked,
+    one along a wall is free."""
+    sc = W.room_scene()
+    E1 = 6  # the first straight edge (global ids: 6 walls, then the edges)
+    X = np.array([0.0, 0.0, 1.0])
+    assert O.visible_one(sc, np.array([5.0, 5.0, 1.5]), [E1], X)
+    sc.tx = np.array([-1.0, 2.0, 1.5])
+    assert not O.visible_one(sc, np.array([5.0, 5.0, 1.5]), [E1], X)
+    sc.tx = np.array([0.0, 2.0, 1.5])
+    assert O.visible_one(sc, np.array([5.0, 5.0, 1.5]), [E1], X)
 
 
 def test_visibility_matches_slab_test_on_buildings():
