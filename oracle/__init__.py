@@ -35,7 +35,7 @@ class _Scene(C.Structure):
     _fields_ = [("tx", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("n_pl", C.c_int32), ("n_ln", C.c_int32), ("n_q", C.c_int32), ("n_c", C.c_int32),
                 ("pl", C.c_void_p), ("ln", C.c_void_p), ("q", C.c_void_p), ("c", C.c_void_p),
-                ("wd", C.c_void_p)]
+                ("wd", C.c_void_p), ("sd", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -76,6 +76,12 @@ def lib():
         L.orc_visible_one.argtypes = [vp, vp, C.c_int, vp, vp, d]
         L.orc_visible_one.restype = C.c_int
         L.orc_visible_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, d, vp, C.c_int]
+        L.orc_samples.argtypes = [vp, C.c_int, C.c_int, vp]
+        L.orc_samples.restype = C.c_int
+        L.orc_visibility.argtypes = [vp, C.c_int, d, vp, vp, C.c_int]
+        L.orc_visibility_rx.argtypes = [vp, vp, C.c_int, C.c_int, d, vp, vp, C.c_int]
+        L.orc_candidates.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, i64, vp, vp, vp]
+        L.orc_candidates.restype = i64
         _lib = L
     return _lib
 
@@ -92,6 +98,8 @@ class OracleScene:
                      for k in ("planes", "lines", "quadrics", "circles")]
         wd = getattr(scene, "wedges", None)
         self.wd = np.ascontiguousarray(wd, dtype=np.float64) if wd is not None and len(wd) else None
+        sd = getattr(scene, "sides", None)
+        self.sd = np.ascontiguousarray(sd, dtype=np.float64) if sd is not None and len(sd) else None
         s = _Scene()
         s.tx[:] = list(scene.tx)
         s.lo[:] = list(scene.aabb_lo)
@@ -99,6 +107,7 @@ class OracleScene:
         s.n_pl, s.n_ln, s.n_q, s.n_c = (len(a) for a in self.keep)
         s.pl, s.ln, s.q, s.c = (_p(a) for a in self.keep)
         s.wd = _p(self.wd)
+        s.sd = _p(self.sd)
         self.s = s
 
     @property
@@ -245,3 +254,55 @@ def visible_batch(scene, batch, x, accept, min_seg=MIN_SEG, nthreads=0):
     lib().orc_visible_batch(os_.ref, batch.n, _p(batch.rx), _p(batch.rx_index), _p(batch.order),
                             _p(batch.prim), _p(x), _p(accept), min_seg, _p(vis), int(nthreads))
     return vis
+
+
+# ------------------------------------------------------------ candidate generation
+def samples(scene, g, k):
+    """Sample points [m, 3] of object g with k per side."""
+    os_ = scene if isinstance(scene, OracleScene) else OracleScene(scene)
+    pts = np.zeros((k * k + 2 * k, 3))
+    m = lib().orc_samples(os_.ref, int(g), int(k), _p(pts))
+    return pts[:m]
+
+
+def visibility(scene, k=4, min_seg=MIN_SEG, nthreads=0):
+    """Visibility matrix V [n, n] (bool, symmetric) and BS row B [n] of Alg. 1."""
+    os_ = OracleScene(scene)
+    n = scene.n_prims
+    V = np.zeros((n, n), np.uint8)
+    B = np.zeros(n, np.uint8)
+    lib().orc_visibility(os_.ref, int(k), float(min_seg), _p(V), _p(B), int(nthreads))
+    return V.astype(bool), B.astype(bool)
+
+
+def visibility_rx(scene, rx, k=4, min_seg=MIN_SEG, nthreads=0):
+    """UE columns U [n_rx, n] (object j sees receiver r) and line of sight [n_rx]."""
+    os_ = OracleScene(scene)
+    rx = np.ascontiguousarray(rx, dtype=np.float64).reshape(-1, 3)
+    n = scene.n_prims
+    U = np.zeros((len(rx), n), np.uint8)
+    los = np.zeros(len(rx), np.uint8)
+    lib().orc_visibility_rx(os_.ref, _p(rx), len(rx), int(k), float(min_seg), _p(U), _p(los), int(nthreads))
+    return U.astype(bool), los.astype(bool)
+
+
+def candidates(scene, rx, V, B, U, max_order, edge_last=False):
+    """Interaction lists of Alg. 1: every simple path BS -> objects -> UE with
+    1..max_order objects, receiver by receiver, order by order, in increasing
+    object ids: dict of rx_index [m], order [m], prim [5, m]."""
+    os_ = OracleScene(scene)
+    V8 = np.ascontiguousarray(V, dtype=np.uint8)
+    B8 = np.ascontiguousarray(B, dtype=np.uint8)
+    U8 = np.ascontiguousarray(U, dtype=np.uint8)
+    rx = np.ascontiguousarray(rx, dtype=np.float64).reshape(-1, 3)
+    L = lib()
+    total = L.orc_candidates(os_.ref, _p(V8), _p(B8), _p(U8), len(rx), int(max_order), int(edge_last), 0,
+                             None, None, None)
+    if total < 0:
+        raise ValueError("bad candidate arguments")
+    ri = np.zeros(max(total, 1), np.int32)
+    order = np.zeros(max(total, 1), np.int32)
+    prim = np.full((5, max(total, 1)), -1, np.int32)
+    L.orc_candidates(os_.ref, _p(V8), _p(B8), _p(U8), len(rx), int(max_order), int(edge_last), int(total),
+                     _p(ri), _p(order), _p(prim))
+    return {"rx_index": ri[:total], "order": order[:total], "prim": np.ascontiguousarray(prim[:, :total])}

@@ -1057,3 +1057,279 @@ void orc_accept_batch(const orc_scene *s, int64_t nb, const double *rx, const in
                         : 0;
     }
 }
+
+/* ------------------------------------------------------------ candidate generation
+ * Alg. 1 starts from a visibility matrix of the objects and an adjacency
+ * matrix that adds BS (TX) and UE (RX), and takes every simple path from BS
+ * to UE through at most n_t objects as an interaction list (Sec. II-C,
+ * Figs. 3-4).  Object i sees object j when some segment between a sample
+ * point of i and one of j leaves both objects into free space and crosses
+ * no other facet or paraboloid patch.  Sample points, per side count k:
+ *   rectangle   the k x k cell centres o + u eu + v ev, u, v = (2a+1)/(2k)
+ *   edge        s0 + (2a+1)/(2k) (s1 - s0) along the edge
+ *   paraboloid  the points of the k x k grid (2a+1-k)/k r_ap across the axis
+ *               strictly inside the aperture, lifted onto the surface (a
+ *               quadric of another kind: its anchor point only)
+ *   circle      2k points from the rational parametrisation of the circle,
+ *               t = (2a+1-k)/k and the antipodes
+ * Each is computed in the order written here, in IEEE FP64 without
+ * contraction. */
+static int obj_type(const orc_scene *s, int g)
+{
+    if (g < s->n_pl) return TP;
+    if (g < s->n_pl + s->n_ln) return TL;
+    if (g < s->n_pl + s->n_ln + s->n_q) return TQ;
+    return TC;
+}
+
+static const double *obj_rec(const orc_scene *s, int g)
+{
+    if (g < s->n_pl) return s->pl + 13 * (size_t)g;
+    g -= s->n_pl;
+    if (g < s->n_ln) return s->ln + 8 * (size_t)g;
+    g -= s->n_ln;
+    if (g < s->n_q) return s->q + 17 * (size_t)g;
+    return s->c + 7 * (size_t)(g - s->n_q);
+}
+
+/* A paraboloid of revolution (A = kap (I - ax ax^T), b = -ax, c = 0):
+   returns kap, or -1 for another quadric. */
+static double revolution_kappa(const double *r)
+{
+    const double *ax = r + 13;
+    double kap = 0.5 * (r[3] + r[6] + r[8]);
+    const double A[3][3] = {{r[3], r[4], r[5]}, {r[4], r[6], r[7]}, {r[5], r[7], r[8]}};
+    double err = fabs(r[12]);
+    for (int i = 0; i < 3; i++) {
+        err = fmax(err, fabs(r[9 + i] + ax[i]));
+        for (int j = 0; j < 3; j++) err = fmax(err, fabs(A[i][j] - kap * ((i == j ? 1.0 : 0.0) - ax[i] * ax[j])));
+    }
+    return (kap > 0.0 && err <= 1e-9 * (1.0 + kap)) ? kap : -1.0;
+}
+
+int orc_samples(const orc_scene *s, int g, int k, double *pts)
+{
+    const double *r = obj_rec(s, g);
+    int t = obj_type(s, g), m = 0;
+    if (t == TP) {
+        for (int a = 0; a < k; a++)
+            for (int b = 0; b < k; b++) {
+                double u = (double)(2 * a + 1) / (double)(2 * k), v = (double)(2 * b + 1) / (double)(2 * k);
+                for (int c = 0; c < 3; c++) pts[3 * m + c] = (r[4 + c] + u * r[7 + c]) + v * r[10 + c];
+                m++;
+            }
+    } else if (t == TL) {
+        for (int a = 0; a < k; a++) {
+            double f = (double)(2 * a + 1) / (double)(2 * k);
+            double sp = r[6] + f * (r[7] - r[6]);
+            for (int c = 0; c < 3; c++) pts[3 * m + c] = r[c] + sp * r[3 + c];
+            m++;
+        }
+    } else if (t == TQ) {
+        double kap = revolution_kappa(r);
+        if (kap < 0.0) {
+            for (int c = 0; c < 3; c++) pts[c] = r[c];
+            return 1;
+        }
+        double e1[3], e2[3];
+        onb_duff(r + 13, e1, e2);
+        for (int a = 0; a < k; a++)
+            for (int b = 0; b < k; b++) {
+                int ia = 2 * a + 1 - k, ib = 2 * b + 1 - k;
+                if (ia * ia + ib * ib >= k * k) continue;
+                double u = r[16] * ((double)ia / (double)k), v = r[16] * ((double)ib / (double)k);
+                double h = kap * (u * u + v * v);
+                for (int c = 0; c < 3; c++) pts[3 * m + c] = ((r[c] + u * e1[c]) + v * e2[c]) + h * r[13 + c];
+                m++;
+            }
+    } else {
+        double u1[3], u2[3];
+        onb_duff(r + 3, u1, u2);
+        for (int a = 0; a < k; a++) {
+            double tt = (double)(2 * a + 1 - k) / (double)k;
+            double den = 1.0 + tt * tt;
+            double x = (1.0 - tt * tt) / den, y = (2.0 * tt) / den;
+            for (int c = 0; c < 3; c++) {
+                pts[3 * m + c] = r[c] + r[6] * (x * u1[c] + y * u2[c]);
+                pts[3 * (m + 1) + c] = r[c] + r[6] * ((-x) * u1[c] + (-y) * u2[c]);
+            }
+            m += 2;
+        }
+    }
+    return m;
+}
+
+/* Does a segment from the point X of object g in direction d leave g into
+   free space (strictly)?  A facet with a side: d points to that side; a
+   two-sided facet or a paraboloid: d is not tangent; an edge with a wedge:
+   d points strictly outside the solid; other edges and circles: always. */
+static int leaves_obj(const orc_scene *s, int g, const double *X, const double *d)
+{
+    int t = obj_type(s, g);
+    const double *r = obj_rec(s, g);
+    if (t == TP) {
+        double a = dot3(d, r), sd = s->sd ? s->sd[g] : 0.0;
+        if (sd > 0.0) return a > 0.0;
+        if (sd < 0.0) return a < 0.0;
+        return a != 0.0;
+    }
+    if (t == TL) {
+        if (!s->wd) return 1;
+        const double *w = s->wd + 7 * (size_t)(g - s->n_pl);
+        double a1 = dot3(d, w), a2 = dot3(d, w + 3);
+        if (w[6] == 1.0) return a1 > 0.0 || a2 > 0.0;
+        if (w[6] == 2.0) return a1 > 0.0 && a2 > 0.0;
+        return 1;
+    }
+    if (t == TQ) {
+        const double A[3][3] = {{r[3], r[4], r[5]}, {r[4], r[6], r[7]}, {r[5], r[7], r[8]}};
+        double w[3], gr[3];
+        sub3(X, r, w);
+        for (int i = 0; i < 3; i++) gr[i] = 2.0 * (A[i][0] * w[0] + A[i][1] * w[1] + A[i][2] * w[2]) + r[9 + i];
+        return dot3(d, gr) != 0.0;
+    }
+    return 1;
+}
+
+/* The segment P -> Q crosses a facet or paraboloid patch other than gi, gj
+   strictly inside (more than min_seg from its ends). */
+static int seg_blocked(const orc_scene *s, const double *P, const double *Q, int gi, int gj, double min_seg)
+{
+    double d[3];
+    sub3(Q, P, d);
+    double L = norm3(d);
+    if (!(L > 0.0)) return 1;
+    double tmin = min_seg / L, tmax = 1.0 - tmin;
+    for (int j = 0; j < s->n_pl; j++)
+        if (j != gi && j != gj && seg_hits_plane(s->pl + 13 * (size_t)j, P, d, tmin, tmax)) return 1;
+    for (int j = 0; j < s->n_q; j++) {
+        int gid = s->n_pl + s->n_ln + j;
+        if (gid != gi && gid != gj && seg_hits_quadric(s->q + 17 * (size_t)j, P, d, tmin, tmax)) return 1;
+    }
+    return 0;
+}
+
+#define SAMPLE_CAP(k) ((k) * (k) + 2 * (k))
+
+void orc_visibility(const orc_scene *s, int k, double min_seg, uint8_t *V, uint8_t *B, int nthreads)
+{
+    int n = s->n_pl + s->n_ln + s->n_q + s->n_c;
+    memset(V, 0, (size_t)n * n);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int i = 0; i < n; i++) {
+        double Si[3 * SAMPLE_CAP(16)], Sj[3 * SAMPLE_CAP(16)];
+        int mi = orc_samples(s, i, k, Si);
+        /* BS row: a segment from BS to a sample of i */
+        B[i] = 0;
+        for (int a = 0; a < mi && !B[i]; a++) {
+            double d[3];
+            sub3(s->tx, Si + 3 * a, d);
+            if (leaves_obj(s, i, Si + 3 * a, d) && !seg_blocked(s, s->tx, Si + 3 * a, -1, i, min_seg)) B[i] = 1;
+        }
+        for (int j = i + 1; j < n; j++) {
+            int mj = orc_samples(s, j, k, Sj), vis = 0;
+            for (int a = 0; a < mi && !vis; a++)
+                for (int b = 0; b < mj && !vis; b++) {
+                    const double *p = Si + 3 * a, *q = Sj + 3 * b;
+                    double d[3], e[3];
+                    sub3(q, p, d);
+                    sub3(p, q, e);
+                    if (leaves_obj(s, i, p, d) && leaves_obj(s, j, q, e) && !seg_blocked(s, p, q, i, j, min_seg))
+                        vis = 1;
+                }
+            V[(size_t)i * n + j] = V[(size_t)j * n + i] = (uint8_t)vis;
+        }
+    }
+}
+
+void orc_visibility_rx(const orc_scene *s, const double *rx, int n_rx, int k, double min_seg, uint8_t *U,
+                       uint8_t *los, int nthreads)
+{
+    int n = s->n_pl + s->n_ln + s->n_q + s->n_c;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int ri = 0; ri < n_rx; ri++) {
+        const double *R = rx + 3 * (size_t)ri;
+        double S[3 * SAMPLE_CAP(16)];
+        los[ri] = (uint8_t)!seg_blocked(s, s->tx, R, -1, -1, min_seg);
+        for (int j = 0; j < n; j++) {
+            int m = orc_samples(s, j, k, S), vis = 0;
+            for (int a = 0; a < m && !vis; a++) {
+                double d[3];
+                sub3(R, S + 3 * a, d);
+                if (leaves_obj(s, j, S + 3 * a, d) && !seg_blocked(s, S + 3 * a, R, j, -1, min_seg)) vis = 1;
+            }
+            U[(size_t)ri * n + j] = (uint8_t)vis;
+        }
+    }
+}
+
+/* Depth-first enumeration in increasing object id of the simple paths
+   BS -> v1 -> ... -> v_ord -> UE of one receiver. */
+typedef struct {
+    int n, ord, edge_last;
+    const uint8_t *V, *B, *U, *edge;
+    int32_t path[MAXN];
+    int64_t count, cap;
+    int32_t rxi, *rx_index, *order, *prim;
+} orc_dfs;
+
+static void dfs_step(orc_dfs *D, int depth)
+{
+    for (int v = 0; v < D->n; v++) {
+        if (depth == 0) {
+            if (!D->B[v]) continue;
+        } else {
+            int u = D->path[depth - 1];
+            if (!D->V[(size_t)u * D->n + v] || (D->edge_last && D->edge[u])) continue;
+            int seen = 0;
+            for (int q = 0; q < depth; q++) seen |= D->path[q] == v;
+            if (seen) continue;
+        }
+        D->path[depth] = v;
+        if (depth + 1 < D->ord) {
+            dfs_step(D, depth + 1);
+        } else if (D->U[v]) {
+            if (D->count < D->cap) {
+                D->rx_index[D->count] = D->rxi;
+                D->order[D->count] = D->ord;
+                for (int q = 0; q < MAXN; q++) D->prim[(size_t)q * D->cap + D->count] = q < D->ord ? D->path[q] : -1;
+            }
+            D->count++;
+        }
+    }
+}
+
+int64_t orc_candidates(const orc_scene *s, const uint8_t *V, const uint8_t *B, const uint8_t *U, int n_rx,
+                       int max_order, int edge_last, int64_t cap, int32_t *rx_index, int32_t *order, int32_t *prim)
+{
+    int n = s->n_pl + s->n_ln + s->n_q + s->n_c;
+    uint8_t edge[4096];
+    if (n > 4096 || max_order < 1 || max_order > MAXN) return -1;
+    for (int g = 0; g < n; g++) edge[g] = (uint8_t)(obj_type(s, g) == TL || obj_type(s, g) == TC);
+    orc_dfs D;
+    D.n = n;
+    D.V = V;
+    D.B = B;
+    D.edge = edge;
+    D.edge_last = edge_last;
+    D.count = 0;
+    D.cap = cap;
+    D.rx_index = rx_index;
+    D.order = order;
+    D.prim = prim;
+    for (int ri = 0; ri < n_rx; ri++) {
+        D.U = U + (size_t)ri * n;
+        D.rxi = ri;
+        for (int o = 1; o <= max_order; o++) {
+            D.ord = o;
+            dfs_step(&D, 0);
+        }
+    }
+    return D.count;
+}

@@ -65,6 +65,9 @@ typedef struct {
                                       m1, m2 face normals into free space, kind
                                       (0 none, 1 outer corner, 2 inner corner);
                                       NULL: no wedges                          */
+    const double *sd;              /* [n_pl] side of each facet that faces free
+                                      space: +1 along n, -1 against n, 0 both;
+                                      NULL: every facet two-sided              */
 } orc_scene;
 
 typedef struct {
@@ -135,6 +138,23 @@ int orc_visible_one(const orc_scene *s, const double rx[3], int n, const int32_t
 void orc_visible_batch(const orc_scene *s, int64_t nb, const double *rx, const int32_t *rx_index,
                        const int32_t *order, const int32_t *prim, const double *x, const uint8_t *accept,
                        double min_seg, uint8_t *visible, int nthreads);
+
+/* Candidate generation (Alg. 1: visibility matrix, adjacency matrix, all
+ * simple paths from BS to UE).  orc_samples writes the sample points of
+ * object g (at most k*k + 2k) and returns their count.  orc_visibility
+ * fills V [n][n] (symmetric, zero diagonal) and the BS row B [n];
+ * orc_visibility_rx fills U [n_rx][n] (object j sees receiver r) and the
+ * line of sight los [n_rx].  orc_candidates enumerates, receiver by
+ * receiver, order by order, in increasing object ids, the simple paths
+ * with 1..max_order objects (edges only last when edge_last); it writes the
+ * first min(total, cap) into rx_index, order [cap] and prim [5][cap] and
+ * returns the total (-1 for bad arguments). */
+int orc_samples(const orc_scene *s, int g, int k, double *pts);
+void orc_visibility(const orc_scene *s, int k, double min_seg, uint8_t *V, uint8_t *B, int nthreads);
+void orc_visibility_rx(const orc_scene *s, const double *rx, int n_rx, int k, double min_seg, uint8_t *U,
+                       uint8_t *los, int nthreads);
+int64_t orc_candidates(const orc_scene *s, const uint8_t *V, const uint8_t *B, const uint8_t *U, int n_rx,
+                       int max_order, int edge_last, int64_t cap, int32_t *rx_index, int32_t *order, int32_t *prim);
 
 /* Batched forms, component-major [15][nb] point arrays; OpenMP over solves.
  * x0 may be NULL. */

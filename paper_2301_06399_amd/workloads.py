@@ -26,6 +26,11 @@ solid lies where both <x - X, m1> and <x - X, m2> are negative), 2 an inner
 corner (the solid lies where either is negative).  Physical validation uses
 it to keep diffracted rays out of the solids.
 
+Optional side of each plane facet (one value, empty array: none): +1 free
+space lies on the side the normal points to, -1 on the other side, 0 on
+both (a thin two-sided surface).  The visibility matrix of the candidate
+generation uses it.
+
 All seeds derive from S = 230106399 as S + 1000*cfg + stream with the
 streams scene=1, rx=2, seq=3, init=4, train=5, heldout=6.
 """
@@ -54,15 +59,18 @@ class Scene:
     quadrics: np.ndarray = field(default_factory=lambda: np.zeros((0, QUAD_W)))
     circles: np.ndarray = field(default_factory=lambda: np.zeros((0, CIRC_W)))
     wedges: np.ndarray = field(default_factory=lambda: np.zeros((0, WEDGE_W)))
+    sides: np.ndarray = field(default_factory=lambda: np.zeros(0))
     aabb_lo: np.ndarray = field(default_factory=lambda: np.zeros(3))
     aabb_hi: np.ndarray = field(default_factory=lambda: np.zeros(3))
 
     def __post_init__(self):
         self.tx = np.ascontiguousarray(self.tx, dtype=np.float64)
-        for k in ("planes", "lines", "quadrics", "circles", "wedges"):
+        for k in ("planes", "lines", "quadrics", "circles", "wedges", "sides"):
             setattr(self, k, np.ascontiguousarray(getattr(self, k), dtype=np.float64))
         if len(self.wedges) and self.wedges.shape != (len(self.lines), WEDGE_W):
             raise ValueError("wedges: one record of 7 values per straight edge, or none")
+        if len(self.sides) and self.sides.shape != (len(self.planes),):
+            raise ValueError("sides: one value per plane facet, or none")
         self.aabb_lo = np.ascontiguousarray(self.aabb_lo, dtype=np.float64)
         self.aabb_hi = np.ascontiguousarray(self.aabb_hi, dtype=np.float64)
 
@@ -213,7 +221,8 @@ def room_scene() -> Scene:
     ])
     # inner corners: the room is the free space
     wedges = np.stack([wedge([1, 0, 0], [0, 1, 0], 2), wedge([0, -1, 0], [0, 0, -1], 2)])
-    return Scene(tx=np.array([2.0, 3.0, 1.5]), planes=planes, lines=lines, wedges=wedges,
+    sides = np.array([1.0, -1.0, 1.0, -1.0, 1.0, -1.0])  # the walls face the room
+    return Scene(tx=np.array([2.0, 3.0, 1.5]), planes=planes, lines=lines, wedges=wedges, sides=sides,
                  aabb_lo=np.zeros(3), aabb_hi=np.array([L, W, H]))
 
 
@@ -255,6 +264,7 @@ def street_canyon_scene(cfg: int = 2, n_boxes: int = 50, tx_height: float = 30.0
                for b in boxes):
             boxes.append((cx, cy, w, d, h))
     planes = [plane_rect([0, 0, 1], 0.0, [0, 0, 0], [size, 0, 0], [0, size, 0])]
+    sides = [1.0]  # the ground faces up, the box faces outwards
     lines, wedges = [], []
     for cx, cy, w, d, h in boxes:
         x0, x1, y0, y1 = cx - w / 2, cx + w / 2, cy - d / 2, cy + d / 2
@@ -265,6 +275,7 @@ def street_canyon_scene(cfg: int = 2, n_boxes: int = 50, tx_height: float = 30.0
             plane_rect([0, 1, 0], y1, [x0, y1, 0], [w, 0, 0], [0, 0, h]),
             plane_rect([0, 0, 1], h, [x0, y0, h], [w, 0, 0], [0, d, 0]),
         ]
+        sides += [-1.0, 1.0, -1.0, 1.0, 1.0]
         for (x, y, sx, sy) in ((x0, y0, -1, -1), (x1, y0, 1, -1), (x1, y1, 1, 1), (x0, y1, -1, 1)):
             lines.append(line_seg([x, y, 0], [0, 0, 1], 0.0, h))
             wedges.append(wedge([sx, 0, 0], [0, sy, 0], 1))
@@ -287,7 +298,7 @@ def street_canyon_scene(cfg: int = 2, n_boxes: int = 50, tx_height: float = 30.0
 
     txy = free_xy(rng, 1)[0]
     sc = Scene(tx=np.array([txy[0], txy[1], tx_height]), planes=np.array(planes),
-               lines=np.array(lines), wedges=np.array(wedges), aabb_lo=np.zeros(3),
+               lines=np.array(lines), wedges=np.array(wedges), sides=np.array(sides), aabb_lo=np.zeros(3),
                aabb_hi=np.array([size, size, max(40.0, boxes[:, 4].max())]))
     sc._boxes = boxes
     sc._free_xy = free_xy
@@ -373,7 +384,7 @@ def config3(n_rx: int = 16384, per_rx: int = 64) -> tuple[Scene, Batch]:
 def stress_scene() -> Scene:
     sc = street_canyon_scene(5)
     q = curved_scene(5, n_quad=30, n_circ=0, rng=np.random.default_rng(seed(5, "scene") + 77))
-    out = Scene(tx=sc.tx, planes=sc.planes, lines=sc.lines, quadrics=q.quadrics, wedges=sc.wedges,
+    out = Scene(tx=sc.tx, planes=sc.planes, lines=sc.lines, quadrics=q.quadrics, wedges=sc.wedges, sides=sc.sides,
                 aabb_lo=sc.aabb_lo, aabb_hi=sc.aabb_hi)
     out._boxes, out._free_xy = sc._boxes, sc._free_xy
     return out
@@ -433,6 +444,44 @@ def fig5_scene() -> tuple[Scene, Batch]:
     b = Batch(np.array([[2.0, 4.0, 0.0]]), np.array([0]), np.array([2]),
               np.array([[0], [1], [-1], [-1], [-1]]))
     return sc, b
+
+
+def fig3_scene(height: float = 5.0) -> tuple[Scene, np.ndarray]:
+    """The two-triangle scenario of the visibility figure (Figs. 3-4),
+    extruded along z over [-height, height]: triangle 1 with corners
+    e1 (-1, .5), e2 (0, .5), e3 (-1, 1.5) and sides s1 = e1e2, s2 = e2e3,
+    s3 = e3e1; triangle 2 with e4 (2, -.5), e5 (3.5, -.5), e6 (3.5, 1) and
+    s4 = e4e5, s5 = e5e6, s6 = e6e4; BS (-.3, -.5), UE (2, 2) at z = 0.
+    Sides are facets facing out of their triangle, corners are vertical
+    edges with the wedges of their two sides.  Object ids: s1..s6 = 0..5,
+    e1..e6 = 6..11.  Returns the scene and the UE position."""
+    tri = [np.array([[-1.0, 0.5], [0.0, 0.5], [-1.0, 1.5]]), np.array([[2.0, -0.5], [3.5, -0.5], [3.5, 1.0]])]
+    planes, sides, lines, wedges = [], [], [], []
+    outward = []
+    for T in tri:
+        ctr = T.mean(axis=0)
+        nrm = []
+        for a in range(3):
+            p, q = T[a], T[(a + 1) % 3]
+            t = (q - p) / np.linalg.norm(q - p)
+            n2 = np.array([t[1], -t[0]])
+            if (p - ctr) @ n2 < 0:
+                n2 = -n2
+            n3 = np.array([n2[0], n2[1], 0.0])
+            planes.append(plane_rect(n3, n3[:2] @ p, [p[0], p[1], -height], [q[0] - p[0], q[1] - p[1], 0],
+                                     [0, 0, 2 * height]))
+            sides.append(1.0)
+            nrm.append(n3)
+        outward.append(nrm)
+    for T, nrm in zip(tri, outward):
+        for a in range(3):
+            # corner a joins side a-1 (ending there) and side a (starting there)
+            lines.append(line_seg([T[a][0], T[a][1], -height], [0, 0, 1], 0.0, 2 * height))
+            wedges.append(wedge(nrm[(a - 1) % 3], nrm[a], 1))
+    sc = Scene(tx=np.array([-0.3, -0.5, 0.0]), planes=np.array(planes), lines=np.array(lines),
+               wedges=np.array(wedges), sides=np.array(sides),
+               aabb_lo=np.array([-2.0, -2.0, -height]), aabb_hi=np.array([5.0, 3.0, height]))
+    return sc, np.array([2.0, 2.0, 0.0])
 
 
 def random_init(scene: Scene, batch: Batch, cfg: int, restart: int = 0) -> np.ndarray:
