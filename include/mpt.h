@@ -41,7 +41,8 @@ typedef enum {
     MPT_E_DEVICE = 3,        /* a HIP call failed                               */
     MPT_E_NO_SCENE = 4,      /* solve/accept before mpt_scene_upload            */
     MPT_E_UNSUPPORTED = 5,   /* option value not implemented                    */
-    MPT_E_NO_MODEL = 6       /* learned start requested without a network       */
+    MPT_E_NO_MODEL = 6,      /* learned start requested without a network       */
+    MPT_E_CAPACITY = 7       /* output arrays smaller than the result           */
 } mpt_status;
 
 /* Per-solve status codes (uint8).  Bit 7 (MPT_PATH_FALLBACK) marks a solve
@@ -93,19 +94,23 @@ mpt_status mpt_synchronize(mpt_ctx *ctx);
  *   wedges   [n_lines][7]     optional (NULL: none): m1(3), m2(3) unit
  *                             normals of the two faces meeting at the edge,
  *                             pointing into free space, kind (MPT_WEDGE_*)
+ *   sides    [n_planes]       optional (NULL: all 0): the side of each facet
+ *                             that faces free space, +1 along n, -1 against
+ *                             n, 0 both (a thin two-sided surface)
  * Global primitive ids are type-major: planes, lines, quadrics, circles.
  * aabb_lo/hi bound the scene; the guard box is that box scaled 10x about
  * its centre plus 1 m.  The arrays are copied (and packed by a device
  * kernel into the solver's FP64 and TX-local FP32 records); the caller keeps
  * ownership.  Errors: MPT_E_INVALID_ARG for non-finite values, non-unit
- * directions (|1-|v|| > 1e-9), a non-positive radius or a wedge kind other
- * than 0, 1, 2.  Synchronises. */
+ * directions (|1-|v|| > 1e-9), a non-positive radius, a wedge kind other
+ * than 0, 1, 2 or a side other than -1, 0, 1.  Synchronises. */
 typedef struct {
     double tx[3];
     double aabb_lo[3], aabb_hi[3];
     int32_t n_planes, n_lines, n_quadrics, n_circles;
     const double *planes, *lines, *quadrics, *circles;
-    const double *wedges;  /* [n_lines][7] or NULL (used by mpt_visible only) */
+    const double *wedges;  /* [n_lines][7] or NULL (validation, visibility)     */
+    const double *sides;   /* [n_planes] or NULL (visibility matrix only)        */
 } mpt_scene_desc;
 mpt_status mpt_scene_upload(mpt_ctx *ctx, const mpt_scene_desc *scene);
 
@@ -288,6 +293,53 @@ mpt_status mpt_accept(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve
  */
 mpt_status mpt_visible(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_out *in, const uint8_t *accept,
                        double min_seg, uint8_t *visible, int32_t *d_count, int64_t *h_count);
+
+/*
+ * Candidate generation (Alg. 1, before the solves; Sec. II-C, Figs. 3-4): the
+ * visibility matrix of the objects, the adjacency matrix that adds BS (TX)
+ * and UE (RX), and every simple path BS -> objects -> UE through at most
+ * max_order objects as an interaction list.
+ *
+ * Object i sees object j (i != j) when some segment between a sample point
+ * of i and a sample point of j leaves both objects strictly into free space
+ * (a facet with a side: towards that side; a two-sided facet or a
+ * paraboloid: not tangent; an edge with a wedge: strictly outside the solid;
+ * other edges and circles: any direction) and crosses no other facet or
+ * paraboloid patch more than min_seg inside its ends.  BS sees j, and j sees
+ * a receiver, by the same rule with the single point.  Sample points, k per
+ * side (1 <= k <= 16): a rectangle's k x k cell centres o + u eu + v ev with
+ * u, v = (2a+1)/(2k); an edge's points s0 + (2a+1)/(2k) (s1 - s0); a
+ * paraboloid of revolution's points (2a+1-k)/k r_ap of the k x k grid
+ * across its axis with (2a+1-k)^2 + (2b+1-k)^2 < k^2, lifted onto the
+ * surface (another quadric: its anchor point); a circle's 2k rational points
+ * c + R (x u1 + y u2), (x, y) = ((1-t^2), 2t)/(1+t^2), t = (2a+1-k)/k, and
+ * their antipodes, (u1, u2) the pair of Duff et al. (JCGT 2017) across n.
+ * All in IEEE FP64 without contraction.
+ *
+ * Bit matrices: W = (n_all + 31) / 32 words per row; bit j of a row is word
+ * j / 32, bit j % 32.  All array pointers are device pointers owned by the
+ * caller; scene objects are limited to 4096.
+ *
+ * mpt_visibility: vis [n_all][W] (symmetric, zero diagonal) and the BS row
+ *   bs [W].  mpt_visibility_rx: ue [n_rx][W] (row r: the objects that see
+ *   receiver r, rx [n_rx][3] FP64) and los [n_rx] uint8 (TX sees RX; may be
+ *   NULL).
+ * mpt_candidates: the paths of every receiver, receiver by receiver, order
+ *   1..max_order, each order in increasing object ids (lexicographic);
+ *   with edge_last, an edge (straight or circular) is only allowed as the
+ *   last interaction (the pruning of Fig. 4).  *h_total receives the number
+ *   of paths (the call synchronises).  With cap >= total the paths are
+ *   written: rx_index [cap], order [cap], prim [5][cap] (stride cap, -1
+ *   beyond the order), ready as a batch of cap == total solves; with cap ==
+ *   0 only the total is returned; with 0 < cap < total nothing is written and
+ *   the status is MPT_E_CAPACITY.
+ */
+mpt_status mpt_visibility(mpt_ctx *ctx, int32_t k, double min_seg, uint32_t *vis, uint32_t *bs);
+mpt_status mpt_visibility_rx(mpt_ctx *ctx, const double *rx, int32_t n_rx, int32_t k, double min_seg,
+                             uint32_t *ue, uint8_t *los);
+mpt_status mpt_candidates(mpt_ctx *ctx, const uint32_t *vis, const uint32_t *bs, const uint32_t *ue, int32_t n_rx,
+                          int32_t max_order, int32_t edge_last, int64_t cap, int32_t *rx_index, int32_t *order,
+                          int32_t *prim, int64_t *h_total);
 
 /*
  * Learned warm start (replaces the random guess of Alg. 1 by a network's

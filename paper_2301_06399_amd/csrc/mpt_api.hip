@@ -24,9 +24,14 @@ struct mpt_ctx {
     int cu = 256;
     size_t lds_max = 65536;  // dynamic LDS a block may use
     // scene
-    double *raw = nullptr, *rec64 = nullptr, *wd = nullptr;
+    double *raw = nullptr, *rec64 = nullptr, *wd = nullptr, *sd = nullptr;
     float *rec32 = nullptr;
-    size_t scene_cap = 0, raw_cap = 0, wd_cap = 0;
+    size_t scene_cap = 0, raw_cap = 0, wd_cap = 0, sd_cap = 0;
+    // candidate generation: sample points, their counts, path counts / offsets
+    double *samp = nullptr;
+    int *scnt = nullptr;
+    int64_t *ccnt = nullptr, *csum = nullptr;
+    size_t samp_cap = 0, scnt_cap = 0, ccnt_cap = 0, csum_cap = 0;
     SceneDev s{};
     bool has_scene = false;
     bool curved = false;     // the scene has paraboloids or circles
@@ -143,6 +148,11 @@ mpt_status mpt_destroy(mpt_ctx *c)
     hipFree(c->rec64);
     hipFree(c->rec32);
     hipFree(c->wd);
+    hipFree(c->sd);
+    hipFree(c->samp);
+    hipFree(c->scnt);
+    hipFree(c->ccnt);
+    hipFree(c->csum);
     hipFree(c->ws);
     hipFree(c->blk);
     hipFree(c->x0l);
@@ -228,6 +238,10 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
                 return fail(c, MPT_E_INVALID_ARG, "wedge %d: face normal not unit", i);
         }
     }
+    if (d->sides)
+        for (int i = 0; i < np; i++)
+            if (d->sides[i] != -1.0 && d->sides[i] != 0.0 && d->sides[i] != 1.0)
+                return fail(c, MPT_E_INVALID_ARG, "plane %d: side is not -1, 0 or 1", i);
     const size_t n_all = (size_t)np + nl + nq + nc;
     const size_t raw_n = (size_t)np * 13 + (size_t)nl * 8 + (size_t)nq * 17 + (size_t)nc * 7;
     hipSetDevice(c->device);
@@ -250,8 +264,14 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
         HIPCHK(c, hipMemcpyAsync(c->wd, d->wedges, (size_t)nl * 7 * sizeof(double), hipMemcpyHostToDevice,
                                  c->stream));
     }
+    const bool sides = d->sides && np > 0;
+    if (sides) {
+        if ((st = ensure(c, (void **)&c->sd, &c->sd_cap, (size_t)np, sizeof(double)))) return st;
+        HIPCHK(c, hipMemcpyAsync(c->sd, d->sides, (size_t)np * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    }
     SceneDev s{};
     s.wedge = wedges ? c->wd : nullptr;
+    s.side = sides ? c->sd : nullptr;
     s.rec64 = c->rec64;
     s.rec32 = c->rec32;
     s.n_pl = np;
@@ -1013,6 +1033,88 @@ mpt_status mpt_mlp_load(mpt_ctx *c, const void *blob, size_t bytes)
     hipSetDevice(c->device);
     mpt_status st = mlp_load(&c->mlp, blob, bytes, c->stream);
     return st ? fail(c, st, "network load failed (bad blob)") : MPT_OK;
+}
+
+static mpt_status cand_samples(mpt_ctx *c, int k)
+{
+    mpt_status st;
+    const size_t n = (size_t)c->s.n_all;
+    if ((st = ensure(c, (void **)&c->samp, &c->samp_cap, n * (size_t)(k * k + 2 * k) * 3, sizeof(double)))) return st;
+    if ((st = ensure(c, (void **)&c->scnt, &c->scnt_cap, n, sizeof(int)))) return st;
+    launch_samples(c->s, k, c->samp, c->scnt, c->stream);
+    return MPT_OK;
+}
+
+static mpt_status cand_check(mpt_ctx *c, int k, double min_seg)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
+    if (k < 1 || k > 16) return fail(c, MPT_E_INVALID_ARG, "samples per side %d outside 1..16", k);
+    if (!(min_seg >= 0)) return fail(c, MPT_E_INVALID_ARG, "negative segment margin");
+    if (c->s.n_all > 4096) return fail(c, MPT_E_UNSUPPORTED, "more than 4096 objects");
+    return MPT_OK;
+}
+
+mpt_status mpt_visibility(mpt_ctx *c, int32_t k, double min_seg, uint32_t *vis, uint32_t *bs)
+{
+    mpt_status st = cand_check(c, k, min_seg);
+    if (st) return st;
+    if (!vis || !bs) return fail(c, MPT_E_INVALID_ARG, "null visibility output");
+    hipSetDevice(c->device);
+    if ((st = cand_samples(c, k))) return st;
+    const int W = (c->s.n_all + 31) / 32;
+    launch_visibility(c->s, k, min_seg, c->samp, c->scnt, vis, bs, W, c->lds_max, c->cu, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MPT_OK;
+}
+
+mpt_status mpt_visibility_rx(mpt_ctx *c, const double *rx, int32_t n_rx, int32_t k, double min_seg, uint32_t *ue,
+                             uint8_t *los)
+{
+    mpt_status st = cand_check(c, k, min_seg);
+    if (st) return st;
+    if (n_rx < 0) return fail(c, MPT_E_INVALID_ARG, "negative receiver count");
+    if (n_rx > 0 && (!rx || !ue)) return fail(c, MPT_E_INVALID_ARG, "null receiver argument");
+    hipSetDevice(c->device);
+    if ((st = cand_samples(c, k))) return st;
+    const int W = (c->s.n_all + 31) / 32;
+    launch_visibility_rx(c->s, k, min_seg, c->samp, c->scnt, rx, n_rx, ue, los, W, c->lds_max, c->cu, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MPT_OK;
+}
+
+mpt_status mpt_candidates(mpt_ctx *c, const uint32_t *vis, const uint32_t *bs, const uint32_t *ue, int32_t n_rx,
+                          int32_t max_order, int32_t edge_last, int64_t cap, int32_t *rx_index, int32_t *order,
+                          int32_t *prim, int64_t *h_total)
+{
+    mpt_status st = cand_check(c, 1, 0.0);
+    if (st) return st;
+    if (!h_total) return fail(c, MPT_E_INVALID_ARG, "null total");
+    *h_total = 0;
+    if (max_order < 1 || max_order > MPT_MAX_ORDER) return fail(c, MPT_E_INVALID_ARG, "max_order outside 1..5");
+    if (n_rx < 0 || cap < 0) return fail(c, MPT_E_INVALID_ARG, "negative receiver count or capacity");
+    if (n_rx > 0 && (!vis || !bs || !ue)) return fail(c, MPT_E_INVALID_ARG, "null visibility input");
+    if (cap > 0 && (!rx_index || !order || !prim)) return fail(c, MPT_E_INVALID_ARG, "null candidate output");
+    const int64_t n = (int64_t)n_rx * c->s.n_all * max_order;
+    if (n == 0) return MPT_OK;
+    hipSetDevice(c->device);
+    const int W = (c->s.n_all + 31) / 32;
+    const int64_t nb = (n + 1023) / 1024;
+    if ((st = ensure(c, (void **)&c->ccnt, &c->ccnt_cap, (size_t)n, sizeof(int64_t)))) return st;
+    if ((st = ensure(c, (void **)&c->csum, &c->csum_cap, (size_t)nb + 1, sizeof(int64_t)))) return st;
+    launch_cand_count(c->s, vis, bs, ue, W, n_rx, max_order, edge_last ? 1 : 0, c->ccnt, c->csum, c->cu, c->stream);
+    HIPCHK(c, hipGetLastError());
+    int64_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, c->csum + nb, sizeof total, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *h_total = total;
+    if (cap == 0 || total == 0) return MPT_OK;
+    if (cap < total) return fail(c, MPT_E_CAPACITY, "%lld candidates do not fit in %lld", (long long)total,
+                                 (long long)cap);
+    launch_cand_fill(c->s, vis, bs, ue, W, n_rx, max_order, edge_last ? 1 : 0, c->ccnt, cap, rx_index, order, prim,
+                     c->cu, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MPT_OK;
 }
 
 }  // extern "C"

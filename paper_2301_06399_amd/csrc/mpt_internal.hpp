@@ -20,6 +20,7 @@ struct SceneDev {
     double glo[3], ghi[3];  // guard box
     double lo[3], hi[3];    // scene box (random starts)
     const double *wedge;    // [n_pl_ln - n_pl][7] wedges of the straight edges, or null
+    const double *side;     // [n_pl] free side of each facet (+1, -1, 0), or null
 };
 
 struct BatchDev {
@@ -90,6 +91,17 @@ void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *co
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
                            double *x0l, hipStream_t st);
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
+void launch_samples(const SceneDev &s, int k, double *samp, int *cnt, hipStream_t st);
+void launch_visibility(const SceneDev &s, int k, double min_seg, const double *samp, const int *cnt, uint32_t *V,
+                       uint32_t *B, int W, size_t lds_max, int cu, hipStream_t st);
+void launch_visibility_rx(const SceneDev &s, int k, double min_seg, const double *samp, const int *cnt,
+                          const double *rx, int n_rx, uint32_t *U, uint8_t *los, int W, size_t lds_max, int cu,
+                          hipStream_t st);
+void launch_cand_count(const SceneDev &s, const uint32_t *V, const uint32_t *B, const uint32_t *U, int W, int n_rx,
+                       int maxo, int edge_last, int64_t *cnt, int64_t *sums, int cu, hipStream_t st);
+void launch_cand_fill(const SceneDev &s, const uint32_t *V, const uint32_t *B, const uint32_t *U, int W, int n_rx,
+                      int maxo, int edge_last, const int64_t *off, int64_t cap, int32_t *rx_index, int32_t *order,
+                      int32_t *prim, int cu, hipStream_t st);
 void launch_visible(const SceneDev &s, const BatchDev &b, const OutDevC &in, const uint8_t *acc, double min_seg,
                     uint8_t *vis, int *count, size_t lds_max, hipStream_t st);
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,

@@ -10,6 +10,7 @@
 //  k_polish          FP64 Gauss-Newton polish of the FP32 end points
 //  k_accept_*        FP64 acceptance test and ordered compaction
 #include "mpt_internal.hpp"
+#include "mpt_geom.hpp"
 
 namespace mpt {
 
@@ -1208,81 +1209,7 @@ void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
 }
 
 // ------------------------------------------------------------------ physical validation
-// A kept path's segments may not pass through another object: a rectangle
-// facet or a paraboloid patch crossed strictly inside a segment (more than
-// min_seg from its ends) blocks it; the objects a segment starts or ends on
-// are not tested; edges and circles have no area.  The arithmetic is plain
-// IEEE FP64 in a fixed order with no contraction, so each decision is the
-// one a plain FP64 implementation of the same test takes.
-__device__ inline double vdot(const double *a, const double *b)
-{
-#pragma clang fp contract(off)
-    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
-
-__device__ inline bool vis_plane(const double *r, const double P[3], const double d[3], double tmin, double tmax)
-{
-#pragma clang fp contract(off)
-    const double den = vdot(r, d);
-    if (den == 0.0) return false;
-    const double t = (r[3] - vdot(r, P)) / den;
-    if (!(t > tmin && t < tmax)) return false;
-    double w[3];
-    for (int i = 0; i < 3; i++) w[i] = (P[i] + t * d[i]) - r[4 + i];
-    const double a = vdot(w, r + 7), b = vdot(w, r + 10);
-    return a >= 0.0 && a <= vdot(r + 7, r + 7) && b >= 0.0 && b <= vdot(r + 10, r + 10);
-}
-
-__device__ inline bool vis_quadric(const double *r, const double P[3], const double d[3], double tmin, double tmax)
-{
-#pragma clang fp contract(off)
-    const double A[3][3] = {{r[3], r[4], r[5]}, {r[4], r[6], r[7]}, {r[5], r[7], r[8]}};
-    const double w[3] = {P[0] - r[0], P[1] - r[1], P[2] - r[2]};
-    double Ad[3], Aw[3];
-    for (int i = 0; i < 3; i++) {
-        Ad[i] = A[i][0] * d[0] + A[i][1] * d[1] + A[i][2] * d[2];
-        Aw[i] = A[i][0] * w[0] + A[i][1] * w[1] + A[i][2] * w[2];
-    }
-    const double a = vdot(d, Ad);
-    const double b = 2.0 * vdot(w, Ad) + vdot(r + 9, d);
-    const double c = vdot(w, Aw) + vdot(r + 9, w) + r[12];
-    double ts[2];
-    int nt = 0;
-    if (a == 0.0) {
-        if (b != 0.0) ts[nt++] = -c / b;
-    } else {
-        const double disc = b * b - 4.0 * a * c;
-        if (disc < 0.0) return false;
-        const double sq = sqrt(disc);
-        const double q = -0.5 * (b + (b >= 0.0 ? sq : -sq));
-        ts[nt++] = q / a;
-        if (q != 0.0) ts[nt++] = c / q;
-    }
-    for (int j = 0; j < nt; j++) {
-        const double t = ts[j];
-        if (!(t > tmin && t < tmax)) continue;
-        double v[3];
-        for (int i = 0; i < 3; i++) v[i] = (P[i] + t * d[i]) - r[i];
-        const double h = vdot(v, r + 13);
-        for (int i = 0; i < 3; i++) v[i] = v[i] - h * r[13 + i];
-        if (vdot(v, v) <= r[16] * r[16]) return true;
-    }
-    return false;
-}
-
-// A segment at a straight edge with a wedge may not leave the edge point X
-// into the solid: m1, m2 are the normals of the faces meeting at the edge,
-// pointing into free space; at an outer corner (kind 1) the solid is where
-// both <d, m> are negative, at an inner corner (kind 2) where either is.
-__device__ inline bool vis_wedge(const double *w, const double X[3], const double Q[3])
-{
-#pragma clang fp contract(off)
-    const double d[3] = {Q[0] - X[0], Q[1] - X[1], Q[2] - X[2]};
-    const double a1 = vdot(d, w), a2 = vdot(d, w + 3);
-    if (w[6] == 1.0) return a1 < 0.0 && a2 < 0.0;
-    if (w[6] == 2.0) return a1 < 0.0 || a2 < 0.0;
-    return false;
-}
+// The geometric tests (facet, patch and wedge) are in mpt_geom.hpp.
 
 // One thread per solve: visible[i] = accept[i] and no segment is blocked.
 // Plane and quadric records are staged in LDS when `lds` is set.

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libmpt.so")
 
 MPT_OK = 0
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NO_SCENE",
-                5: "E_UNSUPPORTED", 6: "E_NO_MODEL"}
+                5: "E_UNSUPPORTED", 6: "E_NO_MODEL", 7: "E_CAPACITY"}
 CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7)
 FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
@@ -34,7 +34,8 @@ class SceneDesc(C.Structure):
     _fields_ = [("tx", C.c_double * 3), ("aabb_lo", C.c_double * 3), ("aabb_hi", C.c_double * 3),
                 ("n_planes", C.c_int32), ("n_lines", C.c_int32), ("n_quadrics", C.c_int32),
                 ("n_circles", C.c_int32), ("planes", C.c_void_p), ("lines", C.c_void_p),
-                ("quadrics", C.c_void_p), ("circles", C.c_void_p), ("wedges", C.c_void_p)]
+                ("quadrics", C.c_void_p), ("circles", C.c_void_p), ("wedges", C.c_void_p),
+                ("sides", C.c_void_p)]
 
 
 class BatchDesc(C.Structure):
@@ -63,7 +64,8 @@ EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt
            "mpt_scene_upload", "mpt_default_opts", "mpt_solve_batch", "mpt_accept", "mpt_mlp_init",
            "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings",
            "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
-           "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused", "mpt_visible"]
+           "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused", "mpt_visible",
+           "mpt_visibility", "mpt_visibility_rx", "mpt_candidates"]
 
 _lib = None
 
@@ -91,6 +93,10 @@ def load_library(path: str = LIB_PATH):
                              C.POINTER(C.c_int64)]
     L.mpt_visible.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOut), vp, C.c_double, vp, vp,
                               C.POINTER(C.c_int64)]
+    L.mpt_visibility.argtypes = [vp, C.c_int32, C.c_double, vp, vp]
+    L.mpt_visibility_rx.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_double, vp, vp]
+    L.mpt_candidates.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int64, vp, vp, vp,
+                                 C.POINTER(C.c_int64)]
     L.mpt_mlp_init.argtypes = [vp, C.c_uint64]
     L.mpt_mlp_train_step.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, C.c_float, vp]
     L.mpt_mlp_grad.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, vp, vp]
@@ -144,6 +150,22 @@ class DeviceBatch:
     def desc(self) -> BatchDesc:
         return BatchDesc(self.n, self.n_rx, _ptr(self.rx), _ptr(self.rx_index), _ptr(self.order), _ptr(self.prim),
                          _ptr(self.x0))
+
+
+def unpack_bits(words, n: int) -> np.ndarray:
+    """Bit words (a tensor or array [..., W]) -> bool array [..., n]."""
+    w = words.cpu().numpy() if hasattr(words, "cpu") else np.asarray(words)
+    w = np.ascontiguousarray(w).view(np.uint32)
+    bits = (w[..., :, None] >> np.arange(32, dtype=np.uint32)) & 1
+    return bits.reshape(*w.shape[:-1], -1)[..., :n].astype(bool)
+
+
+def device_batch(rx, rx_index, order, prim):
+    """A DeviceBatch over device tensors already in place (e.g. candidates)."""
+    db = DeviceBatch.__new__(DeviceBatch)
+    db.n, db.n_rx = int(rx_index.shape[0]), int(rx.shape[0])
+    db.rx, db.rx_index, db.order, db.prim, db.x0 = rx, rx_index, order, prim, None
+    return db
 
 
 class DeviceOut:
@@ -256,7 +278,14 @@ class Context:
             if wd.shape != (len(keep[1]), 7):
                 raise ValueError("wedges: one record of 7 values per straight edge")
             d.wedges = wd.ctypes.data
+        sd = getattr(scene, "sides", None)
+        if sd is not None and len(sd):
+            sd = np.ascontiguousarray(sd, np.float64)
+            if sd.shape != (len(keep[0]),):
+                raise ValueError("sides: one value per plane facet")
+            d.sides = sd.ctypes.data
         self._check(self.L.mpt_scene_upload(self.h, C.byref(d)), "mpt_scene_upload")
+        self.n_all = int(sum(len(a) for a in keep))
 
     def solve(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None) -> DeviceOut:
         out = out or DeviceOut(dbatch.n)
@@ -298,6 +327,54 @@ class Context:
         self._leave()
         self._check(rc, "mpt_visible")
         return vis[:dbatch.n], (hc.value if sync else None)
+
+    def visibility(self, k=4, min_seg=1e-6):
+        """Visibility matrix of the uploaded scene's objects and the BS row, as
+        int32 tensors of bit words [n_all, W] and [W] (W = (n_all + 31) // 32)."""
+        torch = self.torch
+        W = (self.n_all + 31) // 32
+        V = torch.empty((max(self.n_all, 1), W), dtype=torch.int32, device="cuda")
+        B = torch.empty(W, dtype=torch.int32, device="cuda")
+        self._enter()
+        rc = self.L.mpt_visibility(self.h, int(k), float(min_seg), _ptr(V), _ptr(B))
+        self._leave()
+        self._check(rc, "mpt_visibility")
+        return V[:self.n_all], B
+
+    def visibility_rx(self, rx, k=4, min_seg=1e-6):
+        """The objects each receiver sees (bit words [n_rx, W]) and the line
+        of sight [n_rx] uint8; rx is a [n_rx, 3] float64 device tensor."""
+        torch = self.torch
+        W = (self.n_all + 31) // 32
+        n_rx = int(rx.shape[0])
+        U = torch.empty((max(n_rx, 1), W), dtype=torch.int32, device="cuda")
+        los = torch.empty(max(n_rx, 1), dtype=torch.uint8, device="cuda")
+        self._enter()
+        rc = self.L.mpt_visibility_rx(self.h, _ptr(rx), n_rx, int(k), float(min_seg), _ptr(U), _ptr(los))
+        self._leave()
+        self._check(rc, "mpt_visibility_rx")
+        return U[:n_rx], los[:n_rx]
+
+    def candidates(self, V, B, U, max_order, edge_last=False):
+        """Every simple path BS -> objects -> UE (Alg. 1) per receiver row of
+        U: device tensors rx_index [m], order [m], prim [5, m] int32."""
+        torch = self.torch
+        n_rx = int(U.shape[0])
+        tot = C.c_int64(0)
+        self._enter()
+        rc = self.L.mpt_candidates(self.h, _ptr(V), _ptr(B), _ptr(U), n_rx, int(max_order), int(edge_last), 0,
+                                   None, None, None, C.byref(tot))
+        self._check(rc, "mpt_candidates")
+        m = tot.value
+        ri = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        order = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        prim = torch.empty((5, max(m, 1)), dtype=torch.int32, device="cuda")
+        if m > 0:
+            rc = self.L.mpt_candidates(self.h, _ptr(V), _ptr(B), _ptr(U), n_rx, int(max_order), int(edge_last), m,
+                                       _ptr(ri), _ptr(order), _ptr(prim), C.byref(tot))
+        self._leave()
+        self._check(rc, "mpt_candidates")
+        return ri[:m], order[:m], prim[:, :m]
 
     def autotune(self, dbatch: DeviceBatch, opts: SolveOpts | None = None, out: DeviceOut | None = None):
         out = out or DeviceOut(dbatch.n)
