@@ -71,8 +71,9 @@ def test_visibility_wedges_match_oracle(ctx):
 
 
 def test_visibility_edge_cases(ctx):
-    """An empty batch; a margin longer than every segment keeps every
-    accepted path (nothing can be crossed strictly inside)."""
+    """An empty batch; a margin longer than every segment leaves only the
+    wedges to decide (nothing can be crossed strictly inside): without wedges
+    every accepted path is kept, with them the oracle's flags."""
     from paper_2301_06399_amd import mpt
     sc, b = W.config2(n_rx=16, per_rx=64)
     e = b.subset(np.arange(0))
@@ -86,4 +87,10 @@ def test_visibility_edge_cases(ctx):
     out = ctx.solve(db, mpt.default_opts())
     acc, idx, k = ctx.accept(db, out)
     vis, nv = ctx.visible(db, out, acc, min_seg=1e4)
-    assert nv == k and np.array_equal(vis.cpu().numpy(), acc.cpu().numpy())
+    g, a = out.numpy(), acc.cpu().numpy()
+    assert np.array_equal(vis.cpu().numpy(), O.visible_batch(sc, b, g["x"], a, min_seg=1e4))
+    assert 0 < nv < k
+    bare = W.Scene(tx=sc.tx, planes=sc.planes, lines=sc.lines, aabb_lo=sc.aabb_lo, aabb_hi=sc.aabb_hi)
+    ctx.upload_scene(bare)
+    vis, nv = ctx.visible(db, out, acc, min_seg=1e4)
+    assert nv == k and np.array_equal(vis.cpu().numpy(), a)
