@@ -460,6 +460,100 @@ def main_learned(args, torch, mpt, W):
          results, roof, cpu, par, extra={"training": {"problems": 2 * n_rx * 64, "loss_history": hist[-4:]}})
 
 
+def main_alg1(args, torch, mpt, W):
+    """Alg. 1 end to end on the street canyon for a block of receivers:
+    visibility matrix, UE columns, every simple path up to max_order objects
+    as candidates, then the solve (FP32 + polish + fallback), acceptance and
+    physical validation.  One step = the whole chain for every receiver."""
+    import oracle as O
+    scene, full = W.config2()
+    n_rx = args.n_rx or 64
+    rx = np.ascontiguousarray(full.rx[:n_rx])
+    k, mo = args.samples, args.max_order
+    ctx = mpt.Context(0)
+    ctx.upload_scene(scene)
+    R = torch.from_numpy(rx).cuda()
+    opts = mpt.default_opts(form=2)
+
+    def step(sync_each=False, t=None):
+        def mark(name):
+            if sync_each:
+                torch.cuda.synchronize()
+                t[name] = time.perf_counter()
+        mark("start")
+        V, B = ctx.visibility(k)
+        mark("visibility")
+        U, los = ctx.visibility_rx(R, k)
+        mark("ue_columns")
+        ri, order, prim = ctx.candidates(V, B, U, mo)
+        mark("candidates")
+        db = mpt.device_batch(R, ri, order, prim)
+        out = ctx.solve(db, opts)
+        mark("solve")
+        acc, idx, na = ctx.accept(db, out)
+        mark("accept")
+        vis, nv = ctx.visible(db, out, acc)
+        mark("validate")
+        return V, B, U, db, out, acc, vis, na, nv
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        V, B, U, db, out, acc, vis, na, nv = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    marks = {}
+    step(True, marks)
+    names = ["visibility", "ue_columns", "candidates", "solve", "accept", "validate"]
+    prev, stages = marks["start"], {}
+    for nm in names:
+        stages[nm] = round((marks[nm] - prev) * 1e3, 4)
+        prev = marks[nm]
+    m = db.n
+    # the candidate fill writes rx_index, order and prim (28 B per path)
+    cand_ms = stages["candidates"]
+    fill_bytes = 28.0 * m
+    roof = {"bound": "hbm", "achieved": fill_bytes / (cand_ms * 1e-3) / 1e9, "peak": PEAK["hbm"] / 1e9,
+            "unit": "GB/s", "frac": fill_bytes / (cand_ms * 1e-3) / PEAK["hbm"], "traffic": None,
+            "kernel": "mpt_candidates (count + scan + fill), sync to sync", "bytes_per_launch": fill_bytes}
+    # parity: the oracle's visibility and lists for the first receivers, and
+    # its chain on their candidates
+    nr = min(n_rx, 2)
+    Vb, Bb, Ub = mpt.unpack_bits(V, scene.n_prims), mpt.unpack_bits(B, scene.n_prims), mpt.unpack_bits(U, scene.n_prims)
+    t = time.perf_counter()
+    oV, oB = O.visibility(scene, k=k, nthreads=ncores())
+    oU, _ = O.visibility_rx(scene, rx[:nr], k=k, nthreads=ncores())
+    oc = O.candidates(scene, rx[:nr], oV, oB, oU, mo)
+    sel = np.where(db.rx_index.cpu().numpy() < nr)[0]
+    ob = W.Batch(rx[:nr], oc["rx_index"], oc["order"], oc["prim"])
+    orc = O.solve_batch(scene, ob, nthreads=ncores())
+    oacc = O.accept_batch(scene, ob, orc["x"], orc["status"], nthreads=ncores())
+    ovis = O.visible_batch(scene, ob, orc["x"], oacc, nthreads=ncores())
+    t_cpu = time.perf_counter() - t
+    same_lists = (np.array_equal(db.prim.cpu().numpy()[:, sel], oc["prim"]) and
+                  np.array_equal(db.order.cpu().numpy()[sel], oc["order"]))
+    par = {"receivers": nr, "visibility_equal": bool(np.array_equal(Vb, oV) and np.array_equal(Bb, oB)),
+           "ue_equal": bool(np.array_equal(Ub[:nr], oU)), "candidate_lists_equal": bool(same_lists),
+           "accept_equal": bool(np.array_equal(acc.cpu().numpy()[sel], oacc)),
+           "kept_equal": bool(np.array_equal(vis.cpu().numpy()[sel], ovis))}
+    cpu = {"value": int(ovis.sum()) / t_cpu, "unit": "kept paths/s", "cores": ncores(), "kind": "oracle",
+           "sample": f"Alg. 1 for the first {nr} receivers (visibility matrix, their UE columns, "
+                     f"{len(oc['order'])} candidates solved, accepted and validated)"}
+    line = {
+        "metric": "Alg. 1 kept paths/sec (visibility + candidates + solve + accept + validation)",
+        "value": nv / (ms * 1e-3), "unit": "kept paths/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic (seeded generators)",
+        "config": {"workload": f"street canyon 50 boxes (651 objects), {n_rx} receivers, simple paths of "
+                               f"1-{mo} objects, {k} samples per side", "receivers": n_rx, "max_order": mo,
+                   "samples_per_side": k},
+        "candidates": m, "candidates_per_s": m / (ms * 1e-3), "accepted": na, "kept": nv, "stages_ms": stages,
+        "roofline": roof, "cpu_baseline": cpu, "parity_sample": par}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -474,6 +568,10 @@ def main():
     ap.add_argument("--only-main", action="store_true", help="time only the headline variant")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the tuner: launch choices from MPT_AUTOTUNE_CACHE, else the defaults")
+    ap.add_argument("--alg1", action="store_true",
+                    help="Alg. 1 end to end: visibility, candidates, solve, accept, validation")
+    ap.add_argument("--max-order", type=int, default=3, help="Alg. 1: most objects per candidate path")
+    ap.add_argument("--samples", type=int, default=4, help="Alg. 1: sample points per side of an object")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -483,7 +581,9 @@ def main():
     import torch
     from paper_2301_06399_amd import mpt
     from paper_2301_06399_amd import workloads as W
-    if args.config == 4:
+    if args.alg1:
+        main_alg1(args, torch, mpt, W)
+    elif args.config == 4:
         main_learned(args, torch, mpt, W)
     else:
         main_single(args, torch, mpt, W)
