@@ -248,13 +248,15 @@ mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_
  * Autotuner of the launch choices that do not change results (the schedule -
  * one mixed-order launch or concurrent per-order launches -, the block size,
  * the grid divisor of the per-order launches and the straggler threshold
- * `spill`): runs the LM, polish and fallback passes of the given batch with
- * each candidate (writing the outputs), keeps the fastest and uses it for
- * later solves of the same precision, size class (floor log2 n) and scene
- * size.  With the
+ * `spill`, and on scenes of planes and straight edges the form): runs whole
+ * solves of the given batch back to back with each candidate (writing the
+ * outputs; the median of three groups of runs), keeps the fastest and uses
+ * it for later solves of the same precision, form option, size class
+ * (floor log2 n) and scene size.  With the
  * environment variable MPT_AUTOTUNE_CACHE set to a file path, choices are
  * loaded from and saved to that file (one line per entry).  Synchronises.
- * best_* (host, may be NULL) receive the choice and its time in ms.
+ * best_* (host, may be NULL) receive the choice and its time per solve in
+ * ms.
  */
 mpt_status mpt_autotune(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_opts *opts,
                         const mpt_solve_out *out, int32_t *best_sched, int32_t *best_block, float *best_ms,

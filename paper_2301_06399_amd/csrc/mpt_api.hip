@@ -699,25 +699,45 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     }
     float best = 1e30f;
     Cand bc = cands[0];
-    for (const Cand &cd : cands) {
-        // the median of the timed runs after one warm-up run (five runs,
-        // three when one run takes more than 20 ms): concurrent launches
-        // vary more from run to run, and the typical run is what counts
-        float t[5];
-        int nt = 0;
-        for (int rep = 0, reps = 6; rep < reps; rep++) {
-            if ((st = enqueue_solve(c, b, opts, out, c->stream, true, cd.sched, cd.block, cd.gdiv, cd.spill, cd.form)))
-                return st;
-            HIPCHK(c, hipEventSynchronize(c->ev[6]));
-            float ms = 0.0f;
-            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[6]));  // LM, stragglers, polish and fallback
-            if (rep == 0 && ms > 20.0f) reps = 4;
-            if (rep > 0) t[nt++] = ms;
-        }
-        std::sort(t, t + nt);
-        const float med = t[nt / 2];
-        if (med < best) best = med, bc = cd;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(c, MPT_E_DEVICE, "event creation failed");
     }
+    for (const Cand &cd : cands) {
+        // whole solves back to back, as a caller runs them: after one
+        // warm-up solve, three groups of runs (four each, two when a solve
+        // takes more than 20 ms), each timed from its first launch to its
+        // last; the median group mean counts
+        if ((st = enqueue_solve(c, b, opts, out, c->stream, false, cd.sched, cd.block, cd.gdiv, cd.spill, cd.form)))
+            break;
+        hipEventRecord(e0, c->stream);
+        if ((st = enqueue_solve(c, b, opts, out, c->stream, false, cd.sched, cd.block, cd.gdiv, cd.spill, cd.form)))
+            break;
+        hipEventRecord(e1, c->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) { st = fail(c, MPT_E_DEVICE, "tuning run failed"); break; }
+        float one = 0.0f;
+        hipEventElapsedTime(&one, e0, e1);
+        const int per = one > 20.0f ? 2 : 4;
+        float t[3];
+        for (int g = 0; g < 3 && !st; g++) {
+            hipEventRecord(e0, c->stream);
+            for (int r = 0; r < per && !st; r++)
+                st = enqueue_solve(c, b, opts, out, c->stream, false, cd.sched, cd.block, cd.gdiv, cd.spill, cd.form);
+            hipEventRecord(e1, c->stream);
+            if (!st && hipEventSynchronize(e1) != hipSuccess) st = fail(c, MPT_E_DEVICE, "tuning run failed");
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            t[g] = ms / per;
+        }
+        if (st) break;
+        std::sort(t, t + 3);
+        if (t[1] < best) best = t[1], bc = cd;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
     bool found = false;
     for (auto &t : c->tune)
         if (t.prec == opts->precision && t.form == opts->form && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
