@@ -32,6 +32,9 @@ struct mpt_ctx {
     int *scnt = nullptr;
     int64_t *ccnt = nullptr, *csum = nullptr;
     size_t samp_cap = 0, scnt_cap = 0, ccnt_cap = 0, csum_cap = 0;
+    // physical validation: count and list of the accepted solves
+    int *vlist = nullptr;
+    size_t vlist_cap = 0;
     SceneDev s{};
     bool has_scene = false;
     bool curved = false;     // the scene has paraboloids or circles
@@ -153,6 +156,7 @@ mpt_status mpt_destroy(mpt_ctx *c)
     hipFree(c->scnt);
     hipFree(c->ccnt);
     hipFree(c->csum);
+    hipFree(c->vlist);
     hipFree(c->ws);
     hipFree(c->blk);
     hipFree(c->x0l);
@@ -921,7 +925,8 @@ mpt_status mpt_visible(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_out 
     if (!(min_seg >= 0)) return fail(c, MPT_E_INVALID_ARG, "negative segment margin");
     hipSetDevice(c->device);
     OutDevC ic{in->x, in->cost, in->iters, in->status};
-    launch_visible(c->s, bd, ic, accept, min_seg, visible, d_count, c->lds_max, c->stream);
+    if ((st = ensure(c, (void **)&c->vlist, &c->vlist_cap, (size_t)b->n + 1, sizeof(int)))) return st;
+    launch_visible(c->s, bd, ic, accept, min_seg, visible, d_count, c->vlist, c->lds_max, c->cu, c->stream);
     HIPCHK(c, hipGetLastError());
     if (h_count) {
         int32_t v = 0;

@@ -361,8 +361,42 @@ __global__ void __launch_bounds__(kCandBlock) k_cand_fill(CandGraph G, int n_rx,
                 }
                 const int64_t incl = block_scan_i64(c, red);
                 const int64_t chunk = red[blockDim.x - 1];
-                __syncthreads();
-                if (c > 0) {
+                if (o == 3) {
+                    // consecutive threads write consecutive paths: path q of
+                    // the chunk belongs to the first successor whose inclusive
+                    // count exceeds q, and is the rank-th object after it
+                    const int ne = min((int)blockDim.x, nl - e0);
+                    for (int64_t q = threadIdx.x; q < chunk; q += blockDim.x) {
+                        int lo = 0, hi = ne - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (red[mid] > q) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        const int w2 = list[e0 + lo];
+                        int64_t rank = q - (lo ? red[lo - 1] : 0);
+                        const uint32_t *row2 = G.V + (size_t)w2 * G.W;
+                        int v3 = -1;
+                        for (int w = 0; w < G.W && v3 < 0; w++) {
+                            uint32_t m = row2[w] & Ur[w];
+                            if ((v1 >> 5) == w) m &= ~(1u << (v1 & 31));
+                            const int pc = __popc(m);
+                            if (rank < pc) {
+                                for (int z = 0; z < (int)rank; z++) m &= m - 1u;
+                                v3 = (w << 5) + (__ffs(m) - 1);
+                            }
+                            rank -= pc;
+                        }
+                        const int64_t pos = base + q;
+                        rx_index[pos] = r;
+                        order[pos] = 3;
+                        prim[pos] = v1;
+                        prim[(size_t)cap + pos] = w2;
+                        prim[(size_t)2 * cap + pos] = v3;
+                        prim[(size_t)3 * cap + pos] = -1;
+                        prim[(size_t)4 * cap + pos] = -1;
+                    }
+                } else if (c > 0) {
                     int path[kMaxN] = {v1, v2};
                     const int64_t pos = base + incl - c;
                     if (o == 2) {
@@ -373,6 +407,7 @@ __global__ void __launch_bounds__(kCandBlock) k_cand_fill(CandGraph G, int n_rx,
                         walk_tail<true>(G, Ur, path, 2, o, r, pos, cap, rx_index, order, prim);
                     }
                 }
+                __syncthreads();  // red is read above; the next chunk rewrites it
                 base += chunk;
             }
         }

@@ -103,7 +103,7 @@ void launch_cand_fill(const SceneDev &s, const uint32_t *V, const uint32_t *B, c
                       int maxo, int edge_last, const int64_t *off, int64_t cap, int32_t *rx_index, int32_t *order,
                       int32_t *prim, int cu, hipStream_t st);
 void launch_visible(const SceneDev &s, const BatchDev &b, const OutDevC &in, const uint8_t *acc, double min_seg,
-                    uint8_t *vis, int *count, size_t lds_max, hipStream_t st);
+                    uint8_t *vis, int *count, int *list, size_t lds_max, int cu, hipStream_t st);
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
                    uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st);
 
