@@ -17,7 +17,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed FP32 instructions (v_pk_*_f32) anywhere
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
-SOURCES = ["mpt_solve.hip", "mpt_api.hip", "mpt_mlp.hip", "mpt_cand.hip"]
+SOURCES = ["mpt_solve.hip", "mpt_api.hip", "mpt_mlp.hip", "mpt_cand.hip", "mpt_valid.hip"]
 
 
 def _compile(src: str) -> str:
