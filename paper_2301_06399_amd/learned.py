@@ -90,7 +90,14 @@ def prepare(ctx, scene, batch, steps=None, n_rx=8192, log=sys.stderr):
     elif len(scene.quadrics) or len(scene.circles):
         cfg, per_rx = 3, 64
     else:
-        cfg, per_rx = 2, 64
+        # planes and straight edges only: the learned start serves no path
+        # (their roots are reached from the straight line), so the network
+        # is initialised but not trained
+        ctx.mlp_init(1)
+        if log:
+            print("# no curved objects: the learned start serves no path (network not trained)", file=log,
+                  flush=True)
+        return True
     t = time.time()
     sc, tb = W.training_batch(cfg, n_rx=n_rx, per_rx=per_rx)
     same = all(np.shape(getattr(sc, k)) == np.shape(getattr(scene, k)) and
