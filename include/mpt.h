@@ -267,7 +267,10 @@ mpt_status mpt_autotune(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_sol
  * solve outputs: accept[i] = 1 iff status is CONVERGED (bit 7 ignored),
  * |R(x)|_inf <= tau_res, every segment is at least min_seg long and every
  * point lies in its finite extent (closed sets: rectangle, edge segment,
- * paraboloid patch radius; a circle is its own extent).  Writes accept [n]
+ * paraboloid patch radius; a circle is its own extent) and no reflection
+ * grazes its surface (|cos| between the incoming direction and the normal
+ * at least 1e-9: a grazing ray passes along the surface unchanged, so the
+ * point could slide along it).  Writes accept [n]
  * uint8, the accepted ids in increasing order into accepted_idx [n] int32 and
  * their count into d_count (device int32).  If h_count is not NULL the call
  * synchronises and stores the count there.  All array pointers are device

@@ -837,6 +837,22 @@ int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t 
         const double *rec;
         int t = prim_type(s, ids[k], &rec);
         if (!in_extent(t, rec, X + 3 * k)) return 0;
+        /* a grazing reflection is degenerate: the ray passes along the
+           surface unchanged, so the point can slide along it */
+        if (t == TP || t == TQ) {
+            const double *P = (k == 0) ? s->tx : X + 3 * (k - 1);
+            double d[3], nr[3];
+            sub3(X + 3 * k, P, d);
+            if (t == TP) {
+                for (int i = 0; i < 3; i++) nr[i] = rec[i];
+            } else {
+                const double A[3][3] = {{rec[3], rec[4], rec[5]}, {rec[4], rec[6], rec[7]}, {rec[5], rec[7], rec[8]}};
+                double w[3];
+                sub3(X + 3 * k, rec, w);
+                for (int i = 0; i < 3; i++) nr[i] = 2.0 * (A[i][0] * w[0] + A[i][1] * w[1] + A[i][2] * w[2]) + rec[9 + i];
+            }
+            if (!(fabs(dot3(d, nr)) >= ORC_GRAZE * norm3(d) * norm3(nr))) return 0;
+        }
     }
     return 1;
 }

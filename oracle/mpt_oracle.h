@@ -125,7 +125,13 @@ void orc_solve_batch_param(const orc_scene *s, int64_t nb, const double *rx, con
                            const orc_lm_opts *o, double *x, double *cost, int32_t *iters,
                            uint8_t *status, int nthreads);
 
-/* Finite-object acceptance of a solved path (1 accepted / 0 rejected). */
+/* Smallest |cos| between a reflection's incoming direction and the surface
+ * normal that acceptance allows. */
+#define ORC_GRAZE 1e-9
+
+/* Finite-object acceptance of a solved path (1 accepted / 0 rejected):
+ * CONVERGED, |R|_inf <= tau_res, segments >= min_seg, points in their
+ * extents, and no grazing reflection (|cos| < ORC_GRAZE). */
 int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t *ids,
                    const double *X, int status, double tau_res, double min_seg);
 

@@ -988,6 +988,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 // ------------------------------------------------------------------ acceptance
 // The acceptance test of Alg. 1 in FP64: converged, |R|_inf <= tau_res, every
 // segment at least min_seg, every point inside its finite extent.
+// Smallest |cos| between a reflection's incoming direction and the surface
+// normal that acceptance allows.
+constexpr double kGraze = 1e-9;
+
 template <int N>
 __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, const int *ty, const double *X,
                             double tau_res, double min_seg)
@@ -1029,6 +1033,23 @@ __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, 
             const double h = d[0] * r[13] + d[1] * r[14] + d[2] * r[15];
             const double w[3] = {d[0] - h * r[13], d[1] - h * r[14], d[2] - h * r[15]};
             ok = ok && (w[0] * w[0] + w[1] * w[1] + w[2] * w[2] <= r[16] * r[16]);
+        }
+        if (ty[k] == TP || ty[k] == TQ) {
+            // a grazing reflection is degenerate: the ray passes along the
+            // surface unchanged and the point can slide along it
+            const double *P = (k == 0) ? s.tx : X + 3 * (k - 1);
+            const double v[3] = {x[0] - P[0], x[1] - P[1], x[2] - P[2]};
+            double nr[3];
+            if (ty[k] == TP) {
+                nr[0] = r[0], nr[1] = r[1], nr[2] = r[2];
+            } else {
+                const double A[3][3] = {{r[3], r[4], r[5]}, {r[4], r[6], r[7]}, {r[5], r[7], r[8]}};
+                for (int i = 0; i < 3; i++) nr[i] = 2.0 * (A[i][0] * d[0] + A[i][1] * d[1] + A[i][2] * d[2]) + r[9 + i];
+            }
+            const double vn = v[0] * nr[0] + v[1] * nr[1] + v[2] * nr[2];
+            const double lv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double ln = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+            ok = ok && (fabs(vn) >= kGraze * lv * ln);
         }
     }
     return ok;

@@ -321,3 +321,22 @@ def test_straggler_pass_changes_nothing(ctx, prec):
                 assert np.array_equal(g["stage"][:3], ref["stage"][:3])
                 assert (g["stage"][3] <= g["stage"][0]).all()
             assert res[(sched, 64)]["stage"][3].sum() > 0
+
+
+def test_grazing_continuum_rejected(ctx):
+    """A root on a grazing continuum (corner -> wall -> corner along the
+    wall) converges on the GPU in both precisions and both forms but is not
+    accepted, as in the oracle; the same candidate list with an angled
+    reflection is accepted."""
+    from test_oracle_grazing import corner_wall_scene
+    sc = corner_wall_scene()
+    b = W.Batch(np.array([[-5.0, -5.0, 1.0], [2.0, -3.0, 2.0]]), np.array([0, 1], np.int32),
+                np.array([3, 1], np.int32),
+                np.array([[1, 0], [0, -1], [2, -1], [-1, -1], [-1, -1]], np.int32))
+    orc = O.solve_batch(sc, b)
+    oacc = O.accept_batch(sc, b, orc["x"], orc["status"])
+    assert list(oacc) == [0, 1]
+    for prec in (0, 1):
+        for form in (0, 1):
+            g = gpu_solve(ctx, sc, b, precision=prec, form=form)
+            assert list(g["accept"]) == [0, 1], (prec, form)
