@@ -485,7 +485,7 @@ def main_alg1(args, torch, mpt, W):
         mark("visibility")
         U, los = ctx.visibility_rx(R, k)
         mark("ue_columns")
-        ri, order, prim = ctx.candidates(V, B, U, mo)
+        ri, order, prim = ctx.candidates(V, B, U, mo, args.edge_last)
         mark("candidates")
         db = mpt.device_batch(R, ri, order, prim)
         out = ctx.solve(db, opts)
@@ -525,7 +525,7 @@ def main_alg1(args, torch, mpt, W):
     t = time.perf_counter()
     oV, oB = O.visibility(scene, k=k, nthreads=ncores())
     oU, _ = O.visibility_rx(scene, rx[:nr], k=k, nthreads=ncores())
-    oc = O.candidates(scene, rx[:nr], oV, oB, oU, mo)
+    oc = O.candidates(scene, rx[:nr], oV, oB, oU, mo, args.edge_last)
     sel = np.where(db.rx_index.cpu().numpy() < nr)[0]
     ob = W.Batch(rx[:nr], oc["rx_index"], oc["order"], oc["prim"])
     orc = O.solve_batch(scene, ob, nthreads=ncores())
@@ -547,8 +547,9 @@ def main_alg1(args, torch, mpt, W):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic (seeded generators)",
         "config": {"workload": f"street canyon 50 boxes (651 objects), {n_rx} receivers, simple paths of "
-                               f"1-{mo} objects, {k} samples per side", "receivers": n_rx, "max_order": mo,
-                   "samples_per_side": k},
+                               f"1-{mo} objects, {k} samples per side" +
+                               (", edges only last" if args.edge_last else ""), "receivers": n_rx, "max_order": mo,
+                   "samples_per_side": k, "edge_last": bool(args.edge_last)},
         "candidates": m, "candidates_per_s": m / (ms * 1e-3), "accepted": na, "kept": nv, "stages_ms": stages,
         "roofline": roof, "cpu_baseline": cpu, "parity_sample": par}
     print(json.dumps(line))
@@ -572,6 +573,7 @@ def main():
                     help="Alg. 1 end to end: visibility, candidates, solve, accept, validation")
     ap.add_argument("--max-order", type=int, default=3, help="Alg. 1: most objects per candidate path")
     ap.add_argument("--samples", type=int, default=4, help="Alg. 1: sample points per side of an object")
+    ap.add_argument("--edge-last", action="store_true", help="Alg. 1: a diffraction only as the last interaction")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()

@@ -210,7 +210,7 @@ typedef struct {
                               and the path is classified by its residual,
                               when the damped model's predicted decrease is
                               below stat_tol x the cost ...                 */
-    int32_t stat_win;      /* 3     ... this many iterations in a row (0: off) */
+    int32_t stat_win;      /* 4     ... this many iterations in a row (0: off) */
     int32_t reserved;      /* 0                                            */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);

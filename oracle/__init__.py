@@ -115,7 +115,7 @@ class OracleScene:
         return C.byref(self.s)
 
 
-def default_opts(max_iter=200, plateau_win=10, plateau_frac=0.999, stat_tol=0.02, stat_win=3):
+def default_opts(max_iter=200, plateau_win=10, plateau_frac=0.999, stat_tol=0.02, stat_win=4):
     return _Opts(max_iter=max_iter, tol_step=1e-12, tol_res=1e-13, tau_root=TAU_RES, lambda0=1e-3,
                  plateau_win=plateau_win, plateau_frac=plateau_frac, stat_tol=stat_tol, stat_win=stat_win)
 

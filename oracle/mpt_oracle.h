@@ -29,7 +29,7 @@
  *    (the paper only says "gradient descent"); a descent ends at a root, at
  *    a plateau of the cost, or - on paths of planes and straight edges,
  *    which converge from any start (Sec. III-B) - when the damped model
- *    predicts a decrease below 2% of the cost three iterations in a row;
+ *    predicts a decrease below 2% of the cost four iterations in a row;
  *  - initial points: each object's projection of the point k/(n+1) of the
  *    way along the TX -> RX segment, or of a point drawn uniformly in the
  *    scene box (the random start of Alg. 1, SplitMix64 counter draws), or

@@ -342,7 +342,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->spill = -1;
     o->form = MPT_FORM_IMPLICIT;
     o->stat_tol = 0.02;
-    o->stat_win = 3;
+    o->stat_win = 4;
     o->reserved = 0;
 }
 
