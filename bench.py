@@ -266,15 +266,30 @@ def parity(O, scene, run, r, gacc):
         other_root += int(ok)
         unverified += int(not ok)
         n_ok += int(ok)
+    # planes and straight edges: a GPU root the oracle's straight-line run
+    # did not reach is checked by an oracle solve from the GPU point (the
+    # root is unique, so a confirmed point is that root)
+    flat = ~curved
+    planar_gpu_only = np.where(flat & (gacc == 1) & (oacc == 0))[0]
+    planar_confirmed = 0
+    for i in planar_gpu_only:
+        o_ = sb.order[i]
+        xg = r["x"][:3 * o_, samp[i]]
+        X, c_, it_, st_ = O.solve_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], x0=xg)
+        planar_confirmed += int(st_ == O.CONVERGED and
+                                O.accept_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], X, st_) and
+                                np.linalg.norm((X - xg).reshape(o_, 3), axis=1).max() <= 1e-6)
     # n_ok: GPU-accepted paths that meet the bar (the oracle's root within
     # 1e-6 m, or a verified other root of a curved path)
     n_gpu = int((gacc == 1).sum())
     over = int((np.array(errs) > 1e-6).sum()) if errs else 0
     errs = np.array(errs) if errs else np.zeros(1)
-    flat = ~curved
+    mism = np.where(flat & (gacc != oacc))[0]
     return {"sample": int(len(samp)), "gpu_accepted": n_gpu, "accepted_within_bar": n_ok,
             "over_1e-6_m": over,
-            "flag_mismatches_planar": int((gacc[flat] != oacc[flat]).sum()),
+            "flag_mismatches_planar": int(len(mism)),
+            "planar_mismatch_solves": [int(samp[i]) for i in mism[:8]],
+            "planar_gpu_only_confirmed_by_oracle": planar_confirmed,
             "gpu_only": int(((gacc == 1) & (oacc == 0)).sum()),
             "oracle_only": int(((gacc == 0) & (oacc == 1)).sum()),
             "curved_other_root_verified": other_root, "curved_unverified": unverified,
