@@ -280,7 +280,9 @@ def parity(O, scene, run, r, gacc):
                                 O.accept_one(scene, sb.rx[sb.rx_index[i]], sb.prim[:o_, i], X, st_) and
                                 np.linalg.norm((X - xg).reshape(o_, 3), axis=1).max() <= 1e-6)
     # n_ok: GPU-accepted paths that meet the bar (the oracle's root within
-    # 1e-6 m, or a verified other root of a curved path)
+    # 1e-6 m, a verified other root of a curved path, or a confirmed root of
+    # a planar path the oracle's straight-line run did not reach)
+    n_ok += planar_confirmed
     n_gpu = int((gacc == 1).sum())
     over = int((np.array(errs) > 1e-6).sum()) if errs else 0
     errs = np.array(errs) if errs else np.zeros(1)
