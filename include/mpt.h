@@ -154,8 +154,11 @@ enum { MPT_FALLBACK_NONE = 0, MPT_FALLBACK_GPU_FP64 = 1 };
 enum { MPT_FORM_IMPLICIT = 0, MPT_FORM_PARAMETRIC = 1, MPT_FORM_AUTO = 2 };
 /* MPT_SCHED_PERSISTENT: one persistent launch runs every order's bin;
  * MPT_SCHED_PER_ORDER: one persistent launch per order, with its own
- * register budget, all five running concurrently on forked streams. */
-enum { MPT_SCHED_PER_ORDER = 0, MPT_SCHED_PERSISTENT = 1, MPT_SCHED_AUTO = 2 };
+ * register budget, all five running concurrently on forked streams;
+ * MPT_SCHED_SPLIT: one persistent launch for orders 1-3 (the register
+ * budget of order 3) and one launch each for orders 4 and 5 beside it.
+ * Every schedule gives the same results. */
+enum { MPT_SCHED_PER_ORDER = 0, MPT_SCHED_PERSISTENT = 1, MPT_SCHED_AUTO = 2, MPT_SCHED_SPLIT = 3 };
 
 /* Solver options; mpt_default_opts fills the defaults noted here. */
 typedef struct {

@@ -378,16 +378,17 @@ static int resident_grid(mpt_ctx *c, const void *kern, int block, int64_t n, siz
 }  // extern "C"
 
 // ---------------------------------------------------------------- launch choices
-// Default launch choices before (or without) tuning, from measurements on
-// MI355X: FP32 passes run one launch per order concurrently (each order
-// keeps its own register budget), FP64 passes one mixed-order launch; no
-// straggler launch (it pays on long curved chains, which the tuner finds).
+// Default launch choices before (or without) tuning, from back-to-back
+// measurements on MI355X: one mixed-order launch of 256 threads per block
+// (the short orders fill the tail of the long ones); no straggler launch
+// (it pays on long curved chains, which the tuner finds).
 static void default_choice(int prec, int &sched, int &block, int &gdiv, int &spill)
 {
+    (void)prec;
     gdiv = 1;
     spill = 0;
-    if (prec == MPT_FP32_POLISH64) { sched = MPT_SCHED_PER_ORDER; block = 256; }
-    else { sched = MPT_SCHED_PERSISTENT; block = 256; }
+    sched = MPT_SCHED_PERSISTENT;
+    block = 256;
 }
 
 static int nbucket(int64_t n)
@@ -473,7 +474,7 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
         return fail(c, MPT_E_INVALID_ARG, "negative iteration option");
     if (opts->block != 0 && (opts->block % 64 != 0 || opts->block > 256 || opts->block < 64))
         return fail(c, MPT_E_INVALID_ARG, "block must be 64, 128, 192 or 256");
-    if (opts->sched < MPT_SCHED_PER_ORDER || opts->sched > MPT_SCHED_AUTO)
+    if (opts->sched < MPT_SCHED_PER_ORDER || opts->sched > MPT_SCHED_SPLIT)
         return fail(c, MPT_E_UNSUPPORTED, "sched %d", opts->sched);
     if (opts->grid < 0) return fail(c, MPT_E_INVALID_ARG, "negative grid");
     if (opts->spill < -1 || opts->spill > 64) return fail(c, MPT_E_INVALID_ARG, "spill must be -1..64");
@@ -586,6 +587,16 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
         };
         if (sch == MPT_SCHED_PERSISTENT) {
             go(0, s);
+        } else if (sch == MPT_SCHED_SPLIT) {
+            // orders 1-3 in one launch on s, orders 4 and 5 beside it
+            hipEventRecord(c->fork, s);
+            for (int ord = MPT_MAX_ORDER; ord >= 4; ord--) {
+                hipStreamWaitEvent(c->aux[ord - 1], c->fork, 0);
+                go(ord, c->aux[ord - 1]);
+                hipEventRecord(c->join[ord - 1], c->aux[ord - 1]);
+            }
+            go(6, s);
+            for (int ord = 4; ord <= MPT_MAX_ORDER; ord++) hipStreamWaitEvent(s, c->join[ord - 1], 0);
         } else {
             // one launch per order, each on its own stream (fork / join on
             // the stream s): the waves of a later order fill the CUs an
@@ -700,6 +711,8 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
         for (int sp : {0, 16})
             for (int blk : {64, 128, 256})
                 for (int gd : {1, 2}) cands.push_back({MPT_SCHED_PER_ORDER, blk, gd, sp, fm});
+        for (int sp : {0, 16})
+            for (int blk : {128, 256}) cands.push_back({MPT_SCHED_SPLIT, blk, 1, sp, fm});
     }
     float best = 1e30f;
     Cand bc = cands[0];

@@ -889,6 +889,21 @@ k_lm(KParams kp)
     lm_bin<MODE, 1, FORM>(kp, rec);
 }
 
+// One persistent launch over orders 3, 2, 1 with the register budget of
+// order 3 (twice the waves per SIMD of the all-order kernel in FP32); the
+// split schedule runs orders 4 and 5 beside it with their own launches.
+template <int MODE, bool LDS, int FORM>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(Occ<MODE, 3, FORM>::W, Occ<MODE, 3, FORM>::W))) k_lm_low(KParams kp)
+{
+    const int *cnt = kp.resume ? kp.spill_cnt : (MODE == MODE_FALLBACK64) ? kp.fb_cnt : kp.bin_cnt;
+    if (cnt[0] + cnt[1] + cnt[2] == 0) return;
+    const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
+    lm_bin<MODE, 3, FORM>(kp, rec);
+    lm_bin<MODE, 2, FORM>(kp, rec);
+    lm_bin<MODE, 1, FORM>(kp, rec);
+}
+
 // One persistent launch per order, each with its own register budget.
 template <int MODE, int N, bool LDS, int FORM>
 __global__ void __launch_bounds__(256)
@@ -1179,11 +1194,13 @@ static const void *lm_kernel_t(int order)
     case 2: return (const void *)k_lm_one<MODE, 2, LDS, FORM>;
     case 3: return (const void *)k_lm_one<MODE, 3, LDS, FORM>;
     case 4: return (const void *)k_lm_one<MODE, 4, LDS, FORM>;
-    default: return (const void *)k_lm_one<MODE, 5, LDS, FORM>;
+    case 5: return (const void *)k_lm_one<MODE, 5, LDS, FORM>;
+    default: return (const void *)k_lm_low<MODE, LDS, FORM>;
     }
 }
 
-// order 0: the mixed-order kernel; 1..5: the per-order kernels
+// order 0: the mixed-order kernel; 1..5: the per-order kernels; 6: the
+// kernel of orders 1-3
 // The fallback always runs the implicit form (from the FP32 end point).
 const void *lm_kernel(int mode, int order, bool lds, int form)
 {

@@ -23,7 +23,7 @@ FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
 INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL, INIT_RANDOM = 0, 1, 2, 3, 4
 FORM_IMPLICIT, FORM_PARAMETRIC, FORM_AUTO = 0, 1, 2
-SCHED_PER_ORDER, SCHED_PERSISTENT, SCHED_AUTO = 0, 1, 2
+SCHED_PER_ORDER, SCHED_PERSISTENT, SCHED_AUTO, SCHED_SPLIT = 0, 1, 2, 3
 
 
 class MptError(RuntimeError):

@@ -150,10 +150,15 @@ def test_schedules_give_identical_results(ctx):
     g5 = gpu_solve(ctx, sc, b, precision=1, sched=0, block=128, spill=32)
     for k in ("x", "cost", "iters", "status", "accept"):
         assert np.array_equal(g2[k], g5[k]), k
-    assert np.mean(g1["accept"] == g2["accept"]) > 0.995
-    both = (g1["accept"] == 1) & (g2["accept"] == 1)
-    close = [np.abs(g1["x"][:, i] - g2["x"][:, i]).max() <= TOL_M for i in np.where(both)[0]]
-    assert np.mean(close) > 0.99
+    g6 = gpu_solve(ctx, sc, b, precision=1, sched=3)
+    g7 = gpu_solve(ctx, sc, b, precision=1, sched=3, block=128, spill=16)
+    for k in ("x", "cost", "iters", "status", "accept"):
+        assert np.array_equal(g6[k], g7[k]), k
+    for g in (g2, g6):
+        assert np.mean(g1["accept"] == g["accept"]) > 0.995
+        both = (g1["accept"] == 1) & (g["accept"] == 1)
+        close = [np.abs(g1["x"][:, i] - g["x"][:, i]).max() <= TOL_M for i in np.where(both)[0]]
+        assert np.mean(close) > 0.99
 
 
 def test_edge_cases(ctx):
@@ -306,12 +311,12 @@ def test_straggler_pass_changes_nothing(ctx, prec):
         ctx.upload_scene(sc)
         db = mpt.DeviceBatch(b)
         res = {}
-        for sched in (mpt.SCHED_PERSISTENT, mpt.SCHED_PER_ORDER):
+        for sched in (mpt.SCHED_PERSISTENT, mpt.SCHED_PER_ORDER, mpt.SCHED_SPLIT):
             for spill in (0, 8, 32, 64):
                 out = mpt.DeviceOut(b.n, stages=True)
                 ctx.solve(db, mpt.default_opts(precision=prec, sched=sched, spill=spill), out)
                 res[(sched, spill)] = out.numpy()
-        for sched in (mpt.SCHED_PERSISTENT, mpt.SCHED_PER_ORDER):
+        for sched in (mpt.SCHED_PERSISTENT, mpt.SCHED_PER_ORDER, mpt.SCHED_SPLIT):
             ref = res[(sched, 0)]
             assert (ref["stage"][3] == 0).all()
             for spill in (8, 32, 64):
