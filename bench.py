@@ -157,7 +157,7 @@ class Runner:
         return self.acc[:self.batch.n].cpu().numpy()
 
 
-def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0):
+def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0, sched=None):
     """Roofline of the dominant solver kernel: algorithmic FLOPs of the first
     LM pass (iterations actually run in it x FLOPs per iteration of each
     path's order and types, in the variant's form) over its measured
@@ -179,15 +179,23 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0):
         kname = f"k_lm_one<{mode}, {dom + 1}, ..., {form}>"
         kfile = f"k_lm_one_order{dom + 1}_{prec}" + ("_param" if form else "")
         flops_dom, ms_dom = per_order_flops[dom], st["lm_per_order"][dom]
+    elif sched == mpt.SCHED_SPLIT and sum(per_order_flops[3:]) == 0:
+        # orders 1-3 in one launch; the launches of orders 4 and 5 found
+        # nothing to do
+        kname, kfile = f"k_lm_low<{mode}, ..., {form}> (orders 1-3)", f"k_lm_low_{prec}" + ("_param" if form else "")
+        flops_dom, ms_dom = flops_pass, st["lm"]
     else:
         kname, kfile = f"k_lm<{mode}, ..., {form}> (all orders)", f"k_lm_{prec}" + ("_param" if form else "")
+        if sched == mpt.SCHED_SPLIT:
+            kname = f"split launches k_lm_low + k_lm_one<{mode}, 4 / 5, ..., {form}> (all orders, concurrent)"
+            kfile = None
         flops_dom, ms_dom = flops_pass, st["lm"]
     achieved = flops_dom / (ms_dom * 1e-3)
     # HBM bytes per launch from the committed counter summary of this kernel
     # and workload, valid while the solver sources are unchanged
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"hbm_{kfile}_{WKEY[cfg]}.txt")
-    if os.path.exists(tfile):
+    tfile = os.path.join(ROOT, "profiles", f"hbm_{kfile}_{WKEY[cfg]}.txt") if kfile else ""
+    if kfile and os.path.exists(tfile):
         kv = dict(l.split(":", 1) for l in open(tfile).read().splitlines() if ":" in l and not l.startswith("#"))
         kv = {k.strip(): v.strip() for k, v in kv.items()}
         if kv.get("source_hash") == kernel_source_hash():
@@ -384,7 +392,8 @@ def main_single(args, torch, mpt, W):
     prec = "fp32" if VARIANTS[variant][0] else "fp64"
     form = used_form(VARIANTS[variant][2], main_r["launch"], scene)
     main_r["form_used"] = form
-    roof = lm_roofline(scene, batch, r, main_r["stage_ms"], prec, args.config, mpt, form)
+    roof = lm_roofline(scene, batch, r, main_r["stage_ms"], prec, args.config, mpt, form,
+                       (main_r.get("launch") or {}).get("sched"))
 
     cpu = par = None
     if not args.no_cpu_baseline:
