@@ -54,3 +54,20 @@ def test_oracle_library_is_independent_of_the_hip_library():
         if f.endswith((".c", ".h", ".py")):
             t = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2301_06399_amd" not in t and "mpt_device" not in t, f
+
+
+def test_bit_rows_unpack_like_the_header_says():
+    """Bit j of a row of W words is word j / 32, bit j % 32 (the layout of
+    the visibility matrix, BS row and UE columns)."""
+    import numpy as np
+    from paper_2301_06399_amd import mpt
+    rng = np.random.default_rng(3)
+    n = 77
+    bits = rng.random((5, n)) < 0.3
+    W = (n + 31) // 32
+    words = np.zeros((5, W), np.uint32)
+    for r in range(5):
+        for j in np.where(bits[r])[0]:
+            words[r, j // 32] |= np.uint32(1) << np.uint32(j % 32)
+    assert np.array_equal(mpt.unpack_bits(words.view(np.int32), n), bits)
+    assert np.array_equal(mpt.unpack_bits(words[0].view(np.int32), n), bits[0])
