@@ -214,7 +214,8 @@ typedef struct {
                               when the damped model's predicted decrease is
                               below stat_tol x the cost ...                 */
     int32_t stat_win;      /* 4     ... this many iterations in a row (0: off) */
-    int32_t reserved;      /* 0                                            */
+    int32_t refill;        /* 1     a wave takes new paths once at least this
+                              many of its 64 lanes are idle (1..64)          */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 

@@ -343,7 +343,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->form = MPT_FORM_IMPLICIT;
     o->stat_tol = 0.02;
     o->stat_win = 4;
-    o->reserved = 0;
+    o->refill = 1;
 }
 
 static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)
@@ -540,6 +540,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.pol_list = ctr + kCounters + n;
     kp.fb_list = ctr + kCounters + 2 * n;
     kp.spill_t = spill;
+    kp.refill = opts->refill > 1 ? (opts->refill < 64 ? opts->refill : 64) : 1;
     kp.spill_cnt = ctr + kSpillCounters;
     kp.spill_head = ctr + kSpillCounters + 5;
     kp.spill_list = ctr + kCounters + 3 * n;
@@ -622,7 +623,10 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
         kp.resume = 0;
     }
     if (timed) hipEventRecord(c->ev[4], s);
-    if (n > 0 && mode == MODE_FP32) launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
+    if (n > 0 && mode == MODE_FP32) {
+        launch_polish_list(kp, s);
+        launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
+    }
     if (timed) hipEventRecord(c->ev[5], s);
     // the fallback handles a handful of paths: one mixed-order launch
     if (n > 0 && mode == MODE_FP32 && opts->fallback) run_lm(MODE_FALLBACK64, MPT_SCHED_PERSISTENT, 256, false);

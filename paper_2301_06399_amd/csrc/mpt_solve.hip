@@ -611,8 +611,10 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
 
     while (true) {
         // ---- refill idle lanes from the wave's chunk
+        // (once enough lanes are idle: each refill stalls the wave on the
+        // dependent loads of the new paths' inputs)
         uint64_t need = __ballot(!active);
-        if (need && !drained) {
+        if (need && !drained && ((int)__popcll(need) >= kp.refill || need == ~0ull)) {
             if (cbase >= cend) {
                 int b0 = 0;
                 if (lane == 0) b0 = atomicAdd(head, CH);
@@ -814,8 +816,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                                                          st == ST_STALL);
                     const bool to_fb = (st == ST_DEGEN);
                     if (to_polish) {
-                        const int q = atomicAdd(&kp.pol_cnt[N - 1], 1);
-                        kp.pol_list[off + q] = sid;
+                        // listed for the polish after the LM passes (no
+                        // atomic with a return value in the iteration loop)
                         const bool rootlike = (double)L.rinf <= kp.o.tau_root32;
                         code = (rootlike && (st == ST_CONV || st == ST_STALL)) ? ROUTE_POLISH_FB
                                : (st == ST_MAXIT)                             ? ROUTE_POLISH_MAXIT
@@ -1238,6 +1240,38 @@ void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows
     if (b.n == 0) return;
     const unsigned g = (unsigned)std::min<int64_t>((b.n + 255) / 256, 2048);
     hipLaunchKernelGGL(k_learned_choose, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l);
+}
+
+// The polish list: the solves the FP32 passes routed to the polish, grouped
+// by order at the bins' offsets (one atomic per wave and order).
+__global__ void __launch_bounds__(256) k_polish_list(KParams kp)
+{
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < kp.b.n; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        int ord = 0;
+        if (i < kp.b.n) {
+            const int st = kp.out.status[i];
+            if (st == ROUTE_POLISH_FB || st == ROUTE_POLISH_MAXIT || st == ROUTE_POLISH_LOCALMIN) ord = kp.b.order[i];
+        }
+        for (int o = 1; o <= kMaxN; o++) {
+            const uint64_t m = __ballot(ord == o);
+            if (!m) continue;
+            const int leader = (int)__builtin_ctzll(m);
+            int base = 0;
+            if (__lane_id() == leader) base = atomicAdd(&kp.pol_cnt[o - 1], (int)__popcll(m));
+            base = __shfl(base, leader);
+            if (ord == o)
+                kp.pol_list[bin_offset(kp.bin_cnt, o) + base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull))] =
+                    (int)i;
+        }
+    }
+}
+
+void launch_polish_list(const KParams &kp, hipStream_t st)
+{
+    if (kp.b.n == 0) return;
+    hipLaunchKernelGGL(k_polish_list, dim3((unsigned)std::min<int64_t>((kp.b.n + 255) / 256, 4096)), dim3(256), 0, st,
+                       kp);
 }
 
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
