@@ -214,8 +214,9 @@ typedef struct {
                               when the damped model's predicted decrease is
                               below stat_tol x the cost ...                 */
     int32_t stat_win;      /* 4     ... this many iterations in a row (0: off) */
-    int32_t refill;        /* 1     a wave takes new paths once at least this
-                              many of its 64 lanes are idle (1..64)          */
+    int32_t refill;        /* 16    a wave takes new paths once at least this
+                              many of its 64 lanes are idle (1..64): each
+                              refill stalls the wave on the new paths' loads */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 

@@ -343,7 +343,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->form = MPT_FORM_IMPLICIT;
     o->stat_tol = 0.02;
     o->stat_win = 4;
-    o->refill = 1;
+    o->refill = 16;
 }
 
 static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)

@@ -1243,35 +1243,51 @@ void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows
 }
 
 // The polish list: the solves the FP32 passes routed to the polish, grouped
-// by order at the bins' offsets (one atomic per wave and order).
+// by order at the bins' offsets.  Each block counts its solves per order in
+// LDS and takes its slots with one global atomic per order, so that the
+// counters see a few hundred atomics rather than one per wave.
+constexpr int kPolListPer = 8;  // solves per thread
+
 __global__ void __launch_bounds__(256) k_polish_list(KParams kp)
 {
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < kp.b.n; i0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = i0 + threadIdx.x;
-        int ord = 0;
+    __shared__ int lcnt[kMaxN], lbase[kMaxN];
+    const int64_t b0 = (int64_t)blockIdx.x * blockDim.x * kPolListPer;
+    if (threadIdx.x < kMaxN) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    int ord[kPolListPer], slot[kPolListPer];
+    for (int q = 0; q < kPolListPer; q++) {
+        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+        ord[q] = 0;
         if (i < kp.b.n) {
             const int st = kp.out.status[i];
-            if (st == ROUTE_POLISH_FB || st == ROUTE_POLISH_MAXIT || st == ROUTE_POLISH_LOCALMIN) ord = kp.b.order[i];
+            if (st == ROUTE_POLISH_FB || st == ROUTE_POLISH_MAXIT || st == ROUTE_POLISH_LOCALMIN) ord[q] = kp.b.order[i];
         }
+        slot[q] = 0;
         for (int o = 1; o <= kMaxN; o++) {
-            const uint64_t m = __ballot(ord == o);
+            const uint64_t m = __ballot(ord[q] == o);
             if (!m) continue;
             const int leader = (int)__builtin_ctzll(m);
             int base = 0;
-            if (__lane_id() == leader) base = atomicAdd(&kp.pol_cnt[o - 1], (int)__popcll(m));
+            if (__lane_id() == leader) base = atomicAdd(&lcnt[o - 1], (int)__popcll(m));
             base = __shfl(base, leader);
-            if (ord == o)
-                kp.pol_list[bin_offset(kp.bin_cnt, o) + base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull))] =
-                    (int)i;
+            if (ord[q] == o) slot[q] = base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull));
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxN)
+        lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&kp.pol_cnt[threadIdx.x], lcnt[threadIdx.x]) : 0;
+    __syncthreads();
+    for (int q = 0; q < kPolListPer; q++) {
+        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+        if (ord[q] > 0) kp.pol_list[bin_offset(kp.bin_cnt, ord[q]) + lbase[ord[q] - 1] + slot[q]] = (int)i;
     }
 }
 
 void launch_polish_list(const KParams &kp, hipStream_t st)
 {
     if (kp.b.n == 0) return;
-    hipLaunchKernelGGL(k_polish_list, dim3((unsigned)std::min<int64_t>((kp.b.n + 255) / 256, 4096)), dim3(256), 0, st,
-                       kp);
+    const int64_t per_block = 256 * kPolListPer;
+    hipLaunchKernelGGL(k_polish_list, dim3((unsigned)((kp.b.n + per_block - 1) / per_block)), dim3(256), 0, st, kp);
 }
 
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
