@@ -608,13 +608,6 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
     int cbase = 0, cend = 0;  // wave-uniform chunk [cbase, cend) of the bin
     bool drained = false;
     constexpr int CH = 64;
-    // the chunk's inputs, loaded once when the wave takes it: lane j holds
-    // entry chunk0 + j (solve id, receiver, primitive ids); later refills
-    // from the chunk read them with lane shuffles instead of dependent loads
-    int chunk0 = 0, c_sid = -1, c_ri = 0;
-    int c_id[N];
-#pragma unroll
-    for (int k = 0; k < N; k++) c_id[k] = 0;
 
     while (true) {
         // ---- refill idle lanes from the wave's chunk
@@ -629,39 +622,23 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                 cbase = b0;
                 cend = min(b0 + CH, count);
                 if (cbase >= count) drained = true;
-                chunk0 = cbase;
-                if (!drained) {
-                    const int e = chunk0 + lane;
-                    c_sid = (e < cend) ? list[off + e] : -1;
-                    c_ri = (c_sid >= 0) ? kp.b.rx_index[c_sid] : 0;
-#pragma unroll
-                    for (int k = 0; k < N; k++) c_id[k] = (c_sid >= 0) ? kp.b.prim[(size_t)k * kp.b.n + c_sid] : 0;
-                }
             }
             if (!drained) {
                 const int avail = cend - cbase;
                 const int rank = (int)__popcll(need & ((1ull << lane) - 1ull));
                 const int take = min((int)__popcll(need), avail);
-                // every lane shuffles (the holder lanes must take part); a
-                // lane that takes nothing reads a clamped, unused entry
-                const int src = min(cbase - chunk0 + rank, CH - 1);
-                const int n_sid = __shfl(c_sid, src);
-                const int n_ri = __shfl(c_ri, src);
-                int n_id[N];
-#pragma unroll
-                for (int k = 0; k < N; k++) n_id[k] = __shfl(c_id[k], src);
                 if (!active && rank < take) {
-                    sid = n_sid;
+                    sid = list[off + cbase + rank];
                     active = true;
                     // ---- start of one path
                     double rx[3], X0[3 * N];
-                    const int ri = n_ri;
+                    const int ri = kp.b.rx_index[sid];
 #pragma unroll
                     for (int i = 0; i < 3; i++) rx[i] = kp.b.rx[3 * (size_t)ri + i];
                     p.planar = true;
 #pragma unroll
                     for (int k = 0; k < N; k++) {
-                        p.id[k] = n_id[k];
+                        p.id[k] = kp.b.prim[(size_t)k * kp.b.n + sid];
                         p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
                         p.planar = p.planar && (p.ty[k] == TP || p.ty[k] == TL);
                     }
