@@ -209,13 +209,14 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0, sched=None):
 
 
 def used_form(form, launch, scene):
-    """The form a solve ran in: the tuner's choice for the automatic form,
-    else the library's rule (parametric with paraboloids or circles)."""
+    """The form a solve ran in: the one the launch record names, else the
+    library's rule for the automatic form (parametric; the workloads' quadrics
+    are all paraboloids of revolution)."""
     if form != 2:
         return form
     if launch and "form" in launch:
         return launch["form"]
-    return 1 if len(scene.quadrics) or len(scene.circles) else 0
+    return 1
 
 
 def ncores():
@@ -470,7 +471,8 @@ def main_learned(args, torch, mpt, W):
         tot_t = tot_acc = tot_m = 0
         par = []
         for h, (sc, b) in enumerate(held):
-            orun = oracle_run(O, sc, b, cores, 5.0, args.cpu_sample or 2_000_000, "param")
+            fm = used_form(VARIANTS["L"][2], per["L"][h].get("launch"), sc)
+            orun = oracle_run(O, sc, b, cores, 5.0, args.cpu_sample or 2_000_000, "param" if fm else "implicit")
             tot_t += orun["t"]
             tot_acc += orun["acc"]
             tot_m += orun["m"] * orun["reps"]
