@@ -202,10 +202,14 @@ typedef struct {
                               implicit).  Paraboloids must be of revolution
                               (A = k (I - ax ax^T), b = -ax, c = 0); another
                               quadric makes its paths MPT_PATH_BAD_INPUT.
-                              MPT_FORM_AUTO: parametric when every quadric
-                              of the scene allows it, otherwise implicit
-                              (the parametric form reaches at least as many
-                              roots on every workload measured)             */
+                              MPT_FORM_AUTO: parametric when the scene has
+                              paraboloids or circles (and every quadric
+                              allows it); on planes and straight edges the
+                              tuner's faster form, else implicit (their
+                              roots are unique: the forms accept the same
+                              paths but for about 1 in 10^5 hard chains the
+                              parametric form reaches and the implicit
+                              one does not)                                 */
     double stat_tol;       /* 0.02  paths of planes and straight edges only
                               (their root is unique and reached from any
                               start, Sec. III-B): the descent has stalled,

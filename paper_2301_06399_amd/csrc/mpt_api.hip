@@ -426,13 +426,12 @@ static void tune_save(mpt_ctx *c)
     fclose(f);
 }
 
-// The form a solve runs in: MPT_FORM_AUTO takes the parametric form when
-// every quadric allows it (it reaches at least as many roots as the implicit
-// form on every workload measured: the same on the room and the street
-// canyon, more on the curved and stress workloads), the implicit otherwise.
+// The form a solve runs in: MPT_FORM_AUTO takes the parametric form on
+// scenes with curved objects (when every quadric allows it) and the implicit
+// one otherwise, unless the tuner chose for this batch.
 static int auto_form(const mpt_ctx *c)
 {
-    return c->param_ok ? MPT_FORM_PARAMETRIC : MPT_FORM_IMPLICIT;
+    return (c->curved && c->param_ok) ? MPT_FORM_PARAMETRIC : MPT_FORM_IMPLICIT;
 }
 
 static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv, int &spill,
@@ -701,10 +700,14 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     if (st) return st;
     hipSetDevice(c->device);
     tune_load(c);
-    // candidates: schedule x block size x grid divisor (per-order only) x
-    // straggler threshold, in the form the options resolve to
+    // candidates: form (MPT_FORM_AUTO on planes and straight edges, whose
+    // unique roots make both forms accept the same paths but for rare hard
+    // chains) x schedule x block size x grid divisor (per-order only) x
+    // straggler threshold
     std::vector<int> forms;
-    forms.push_back(opts->form == MPT_FORM_AUTO ? auto_form(c) : opts->form);
+    if (opts->form != MPT_FORM_AUTO) forms.push_back(opts->form);
+    else if (c->curved || !c->param_ok) forms.push_back(auto_form(c));
+    else forms = {MPT_FORM_IMPLICIT, MPT_FORM_PARAMETRIC};
     struct Cand { int sched, block, gdiv, spill, form; };
     std::vector<Cand> cands;
     for (int fm : forms) {
