@@ -41,16 +41,16 @@ NAMES = {1: "room 10x10x3 m, 6 walls + 2 edges, 256 RX x 64 lists (order 1-2)",
          5: "stress: street canyon + 30 paraboloids, 16384 RX x 1024 lists of order 3-5 with >= 2 diffractions"}
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12, "bf16": 2.5e15}
 MLP_FLOPS_PER_ROW = 2 * (96 * 256 + 256 * 256 + 256 * 256 + 256 * 15)
-# variant: (precision, start, form); form 1 = parametric (Eq. 15), 0 = implicit (Eq. 12)
 # variant: (precision, start, form); form 0 = implicit (Eq. 12), 1 = parametric
 # (Eq. 15), 2 = the library's choice (parametric with curved objects, else
 # the tuner's)
 VARIANTS = {"L": (1, "learned", 2), "A": (1, "learned_all", 2), "S": (1, "line", 2), "Si": (1, "line", 0),
-            "P": (0, "line", 0), "Pp": (0, "line", 1)}
+            "Sp": (1, "line", 1), "P": (0, "line", 0), "Pp": (0, "line", 1)}
 VARIANT_TEXT = {"L": "learned start (paths with curved objects) + FP32 LM + FP64 polish + fallback, form auto",
                 "A": "learned start (every path) + FP32 LM + FP64 polish + fallback, form auto",
                 "S": "straight-line start + FP32 LM + FP64 polish + fallback, form auto",
                 "Si": "straight-line start + FP32 LM + FP64 polish + fallback, implicit form",
+                "Sp": "straight-line start + FP32 LM + FP64 polish + fallback, parametric form",
                 "P": "plain FP64 LM from the straight-line start, implicit form (Eq. 12)",
                 "Pp": "plain FP64 LM from the straight-line start, parametric form (Eq. 15)"}
 
@@ -144,6 +144,7 @@ class Runner:
         st["lm_per_order"] = per_order
         self.step(o)  # leave this variant's outputs and flags in place
         torch.cuda.synchronize()
+        launch = dict(launch or {}, **ctx.last_launch())
         r = self.out.numpy()
         res = {"ms_per_step": dt * 1e3, "accepted": k, "paths_per_s": k / dt, "stage_ms": st,
                "fallback": int((r["status"] & 0x80).astype(bool).sum()),
@@ -209,14 +210,11 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0, sched=None):
 
 
 def used_form(form, launch, scene):
-    """The form a solve ran in: the one the launch record names, else the
-    library's rule for the automatic form (parametric; the workloads' quadrics
-    are all paraboloids of revolution)."""
+    """The form a solve ran in: the one the library reports for the variant's
+    last solve."""
     if form != 2:
         return form
-    if launch and "form" in launch:
-        return launch["form"]
-    return 1
+    return launch["form"]
 
 
 def ncores():
@@ -370,7 +368,7 @@ def main_single(args, torch, mpt, W):
         del src, dst
 
     run = Runner(torch, mpt, ctx, scene, batch)
-    variants = [variant] if args.only_main else [variant] + [x for x in ("S", "Si", "P", "Pp") if x != variant]
+    variants = [variant] if args.only_main else [variant] + [x for x in ("S", "Si", "Sp", "P", "Pp") if x != variant]
     results, outs, flags = {}, {}, {}
     for v in variants:
         steps = args.steps if v == variant else max(5, args.steps // 4)
@@ -590,7 +588,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--n-rx", type=int, default=0, help="receivers (0: the configuration's own)")
-    ap.add_argument("--variant", default="auto", choices=["auto", "L", "A", "S", "Si", "P", "Pp"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "L", "A", "S", "Si", "Sp", "P", "Pp"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="largest oracle sample (0: 2,000,000 solves)")
     ap.add_argument("--train-steps", type=int, default=0, help="network training steps before timing")

@@ -428,6 +428,12 @@ mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[6]);
  * mpt_solve_batch run with MPT_SCHED_PER_ORDER, index = order - 1 (HIP
  * events on the forked streams; synchronises). */
 mpt_status mpt_last_lm_timings(mpt_ctx *ctx, float ms[5]);
+/* The launch the last mpt_solve_batch used for its first LM pass, after the
+ * tuner's table and the options were applied: out[0] schedule (MPT_SCHED_*),
+ * out[1] block size, out[2] grid divisor, out[3] straggler threshold,
+ * out[4] form (MPT_FORM_IMPLICIT or MPT_FORM_PARAMETRIC, never AUTO).
+ * Host only, no device work.  MPT_E_INVALID_ARG before the first solve. */
+mpt_status mpt_last_launch(mpt_ctx *ctx, int32_t out[5]);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,8 @@ struct mpt_ctx {
     hipEvent_t kev[MPT_MAX_ORDER][2] = {};  // per-order kernel start / end of the first LM pass
     bool kev_valid = false;
     bool timed = false;
+    int32_t last_launch[5] = {};  // sched, block, gdiv, spill, form of the last solve
+    bool launched = false;
     MlpState *mlp = nullptr;
     // autotuned launch choices: key -> (sched, block)
     struct Tune { int prec, form, nbucket, n_all, sched, block, gdiv, spill, used; float ms; };
@@ -663,6 +665,9 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     hipSetDevice(c->device);
     int sched, block, gdiv, spill, form;
     choose(c, opts, b->n, sched, block, gdiv, spill, form);
+    const int32_t chosen[5] = {sched, block, gdiv, spill, form};
+    memcpy(c->last_launch, chosen, sizeof chosen);
+    c->launched = true;
     if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block, gdiv, spill, form);
 
     // graph mode: capture once per (batch, options, outputs, scene) and replay
@@ -892,6 +897,14 @@ mpt_status mpt_last_timings(mpt_ctx *c, float ms[6])
     if (!c->timed) return fail(c, MPT_E_INVALID_ARG, "no solve recorded");
     HIPCHK(c, hipEventSynchronize(c->ev[6]));
     for (int i = 0; i < 6; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
+    return MPT_OK;
+}
+
+mpt_status mpt_last_launch(mpt_ctx *c, int32_t out[5])
+{
+    if (!c || !out) return MPT_E_INVALID_ARG;
+    if (!c->launched) return fail(c, MPT_E_INVALID_ARG, "no solve recorded");
+    memcpy(out, c->last_launch, sizeof c->last_launch);
     return MPT_OK;
 }
 

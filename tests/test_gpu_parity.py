@@ -257,9 +257,20 @@ def test_autotuner_choice_keeps_parity(ctx):
     assert choice["sched"] in (0, 1, 3) and choice["block"] in (64, 128, 256) and choice["ms"] > 0
     assert choice["gdiv"] in (1, 2) and choice["spill"] in (0, 8, 16, 32)
     g = gpu_solve(ctx, sc, b)
-    orc = O.solve_batch(sc, b)
+    ran = ctx.last_launch()
+    assert {k: ran[k] for k in ("sched", "block", "gdiv", "spill", "form")} == \
+        {k: choice[k] for k in ("sched", "block", "gdiv", "spill", "form")}
+    orc = O.solve_batch(sc, b, form="param" if ran["form"] else "implicit")
     orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
     compare_planar(sc, b, g, orc_acc, orc)
+    # explicit options win over the table; curved scenes resolve the
+    # automatic form to the parametric one
+    gpu_solve(ctx, sc, b, form=0, sched=0, block=64)
+    ran = ctx.last_launch()
+    assert (ran["form"], ran["sched"], ran["block"]) == (0, 0, 64)
+    sc, b = W.config3(n_rx=32, per_rx=64)
+    gpu_solve(ctx, sc, b)
+    assert ctx.last_launch()["form"] == 1
 
 
 @pytest.mark.parametrize("prec", [0, 1])
