@@ -253,10 +253,10 @@ def test_autotuner_choice_keeps_parity(ctx):
     sc, b = W.config2(n_rx=256, per_rx=64)
     ctx.upload_scene(sc)
     db = mpt.DeviceBatch(b)
-    choice = ctx.autotune(db, mpt.default_opts())
-    assert choice["sched"] in (0, 1, 3) and choice["block"] in (64, 128, 256) and choice["ms"] > 0
+    choice = ctx.autotune(db, mpt.default_opts(form=mpt.FORM_AUTO))
+    assert choice["form"] in (0, 1) and choice["sched"] in (0, 1, 3) and choice["block"] in (64, 128, 256) and choice["ms"] > 0
     assert choice["gdiv"] in (1, 2) and choice["spill"] in (0, 8, 16, 32)
-    g = gpu_solve(ctx, sc, b)
+    g = gpu_solve(ctx, sc, b, form=mpt.FORM_AUTO)
     ran = ctx.last_launch()
     assert {k: ran[k] for k in ("sched", "block", "gdiv", "spill", "form")} == \
         {k: choice[k] for k in ("sched", "block", "gdiv", "spill", "form")}
@@ -269,8 +269,10 @@ def test_autotuner_choice_keeps_parity(ctx):
     ran = ctx.last_launch()
     assert (ran["form"], ran["sched"], ran["block"]) == (0, 0, 64)
     sc, b = W.config3(n_rx=32, per_rx=64)
-    gpu_solve(ctx, sc, b)
+    gpu_solve(ctx, sc, b, form=mpt.FORM_AUTO)
     assert ctx.last_launch()["form"] == 1
+    gpu_solve(ctx, sc, b)
+    assert ctx.last_launch()["form"] == 0  # the default options ask for the implicit form
 
 
 @pytest.mark.parametrize("prec", [0, 1])
