@@ -627,14 +627,9 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     if (timed) hipEventRecord(c->ev[4], s);
     if (n > 0 && mode == MODE_FP32) {
         launch_polish_list(kp, s);
-        // one launch per order, concurrent on the per-order streams
-        hipEventRecord(c->fork, s);
-        for (int ord = MPT_MAX_ORDER; ord >= 1; ord--) {
-            hipStreamWaitEvent(c->aux[ord - 1], c->fork, 0);
-            launch_polish(kp, ord, resident_grid(c, polish_kernel(ord), 256, n), 256, c->aux[ord - 1]);
-            hipEventRecord(c->join[ord - 1], c->aux[ord - 1]);
-        }
-        for (int ord = 1; ord <= MPT_MAX_ORDER; ord++) hipStreamWaitEvent(s, c->join[ord - 1], 0);
+        // one launch per order, back to back on the stream
+        for (int ord = MPT_MAX_ORDER; ord >= 1; ord--)
+            launch_polish(kp, ord, resident_grid(c, polish_kernel(ord), 256, n), 256, s);
     }
     if (timed) hipEventRecord(c->ev[5], s);
     // the fallback handles a handful of paths: one mixed-order launch
