@@ -627,9 +627,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     if (timed) hipEventRecord(c->ev[4], s);
     if (n > 0 && mode == MODE_FP32) {
         launch_polish_list(kp, s);
-        // one launch per order, back to back on the stream
-        for (int ord = MPT_MAX_ORDER; ord >= 1; ord--)
-            launch_polish(kp, ord, resident_grid(c, polish_kernel(ord), 256, n), 256, s);
+        launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
     }
     if (timed) hipEventRecord(c->ev[5], s);
     // the fallback handles a handful of paths: one mixed-order launch

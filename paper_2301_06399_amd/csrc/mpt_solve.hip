@@ -993,12 +993,15 @@ __device__ void polish_bin(const KParams &kp)
     }
 }
 
-// One kernel per order: each gets the registers its own order needs (a
-// mixed-order kernel spills at order 5 and runs one wave per SIMD for all).
-template <int N>
-__global__ void __launch_bounds__(256) k_polish(KParams kp)
+// One kernel for every order: measured faster than one launch per order
+// (back to back or concurrent), although order 5 sets its registers.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_polish(KParams kp)
 {
-    polish_bin<N>(kp);
+    polish_bin<5>(kp);
+    polish_bin<4>(kp);
+    polish_bin<3>(kp);
+    polish_bin<2>(kp);
+    polish_bin<1>(kp);
 }
 
 // ------------------------------------------------------------------ acceptance
@@ -1224,16 +1227,7 @@ void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const 
     hipLaunchKernel(lm_kernel(mode, order, lds, form), dim3(grid), dim3(block), args, lds ? lds_bytes : 0, st);
 }
 
-const void *polish_kernel(int order)
-{
-    switch (order) {
-    case 1: return (const void *)k_polish<1>;
-    case 2: return (const void *)k_polish<2>;
-    case 3: return (const void *)k_polish<3>;
-    case 4: return (const void *)k_polish<4>;
-    default: return (const void *)k_polish<5>;
-    }
-}
+const void *polish_kernel() { return (const void *)k_polish; }
 
 void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st)
 {
@@ -1298,10 +1292,9 @@ void launch_polish_list(const KParams &kp, hipStream_t st)
     hipLaunchKernelGGL(k_polish_list, dim3((unsigned)((kp.b.n + per_block - 1) / per_block)), dim3(256), 0, st, kp);
 }
 
-void launch_polish(const KParams &kp, int order, int grid, int block, hipStream_t st)
+void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
 {
-    void *args[] = {(void *)&kp};
-    hipLaunchKernel(polish_kernel(order), dim3(grid), dim3(block), args, 0, st);
+    hipLaunchKernelGGL(k_polish, dim3(grid), dim3(block), 0, st, kp);
 }
 
 // ------------------------------------------------------------------ physical validation
