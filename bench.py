@@ -116,6 +116,9 @@ class Runner:
         torch, ctx, mpt = self.torch, self.ctx, self.mpt
         o = opts_for(mpt, v)
         launch = ctx.autotune(self.db, o, self.out) if tune else None
+        # the timed steps record no stage events; the stage times come from
+        # separate timed solves below
+        ctx.set_timing(False)
         # untimed warm-up: the requested steps, and at least 0.3 s of them
         t = time.perf_counter()
         w = 0
@@ -132,6 +135,7 @@ class Runner:
         st = {"bin": 0.0, "learned": 0.0, "lm": 0.0, "resume": 0.0, "polish": 0.0, "fallback": 0.0}
         per_order = [0.0] * 5
         reps = min(max(steps, 1), 10)
+        ctx.set_timing(True)
         for _ in range(reps):
             ctx.solve(self.db, o, self.out)
             tm = ctx.timings()

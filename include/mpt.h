@@ -419,10 +419,17 @@ mpt_status mpt_mlp_load(mpt_ctx *ctx, const void *blob, size_t bytes);
  * form. */
 mpt_status mpt_flops_per_iter(int order, const int32_t *types, int32_t form, int64_t out[4]);
 
+/* Stage timing of mpt_solve_batch, on (1) by default: each solve then
+ * records 7 HIP events at its stage boundaries (a few microseconds each on
+ * the stream) for mpt_last_timings and mpt_last_lm_timings.  Off (0): no
+ * events, and those two calls fail until a timed solve.  Graph replays are
+ * never timed.  Host only.  MPT_E_INVALID_ARG for a null context. */
+mpt_status mpt_set_timing(mpt_ctx *ctx, int32_t on);
 /* Per-stage timings of the last mpt_solve_batch in milliseconds (HIP events
  * on the context's stream; synchronises): [0] order binning, [1] learned
  * start, [2] first LM pass (FP32 or plain FP64), [3] its straggler launch,
- * [4] FP64 polish, [5] FP64 fallback. */
+ * [4] FP64 polish, [5] FP64 fallback.  MPT_E_INVALID_ARG when the last solve
+ * was not timed. */
 mpt_status mpt_last_timings(mpt_ctx *ctx, float ms[6]);
 /* Durations (ms) of the per-order kernels of the first LM pass of the last
  * mpt_solve_batch run with MPT_SCHED_PER_ORDER, index = order - 1 (HIP

@@ -54,6 +54,7 @@ struct mpt_ctx {
     hipEvent_t kev[MPT_MAX_ORDER][2] = {};  // per-order kernel start / end of the first LM pass
     bool kev_valid = false;
     bool timed = false;
+    bool timing = true;  // record the stage events in mpt_solve_batch
     int32_t last_launch[5] = {};  // sched, block, gdiv, spill, form of the last solve
     bool launched = false;
     MlpState *mlp = nullptr;
@@ -509,6 +510,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     const int64_t n = b->n;
     const bool learned = opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL;
     if ((st = size_buffers(c, n, learned))) return st;
+    if (!timed) c->timed = c->kev_valid = false;  // no stale stage timings
     int *ctr = c->ws;
     KParams kp{};
     kp.s = c->s;
@@ -668,7 +670,7 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     const int32_t chosen[5] = {sched, block, gdiv, spill, form};
     memcpy(c->last_launch, chosen, sizeof chosen);
     c->launched = true;
-    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, true, sched, block, gdiv, spill, form);
+    if (!opts->graph) return enqueue_solve(c, b, opts, out, c->stream, c->timing, sched, block, gdiv, spill, form);
 
     // graph mode: capture once per (batch, options, outputs, scene) and replay
     std::vector<unsigned char> key = graph_key(b, opts, out, sched, block, gdiv, spill, form, c->s);
@@ -692,6 +694,7 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
         if (e != hipSuccess) return fail(c, MPT_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
         c->gkey = key;
     }
+    c->timed = c->kev_valid = false;  // a replay records no stage events
     HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     return MPT_OK;
 }
@@ -897,6 +900,13 @@ mpt_status mpt_last_timings(mpt_ctx *c, float ms[6])
     if (!c->timed) return fail(c, MPT_E_INVALID_ARG, "no solve recorded");
     HIPCHK(c, hipEventSynchronize(c->ev[6]));
     for (int i = 0; i < 6; i++) HIPCHK(c, hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
+    return MPT_OK;
+}
+
+mpt_status mpt_set_timing(mpt_ctx *c, int32_t on)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    c->timing = on != 0;
     return MPT_OK;
 }
 

@@ -65,7 +65,7 @@ EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt
            "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings",
            "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
            "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused", "mpt_visible",
-           "mpt_visibility", "mpt_visibility_rx", "mpt_candidates", "mpt_last_launch"]
+           "mpt_visibility", "mpt_visibility_rx", "mpt_candidates", "mpt_last_launch", "mpt_set_timing"]
 
 _lib = None
 
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     L.mpt_flops_per_iter.argtypes = [C.c_int, vp, C.c_int32, vp]
     L.mpt_last_lm_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_last_launch.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.mpt_set_timing.argtypes = [vp, C.c_int32]
     L.mpt_autotune.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut),
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float),
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
@@ -397,6 +398,11 @@ class Context:
         ms = (C.c_float * 6)()
         self._check(self.L.mpt_last_timings(self.h, ms), "mpt_last_timings")
         return {"bin": ms[0], "learned": ms[1], "lm": ms[2], "resume": ms[3], "polish": ms[4], "fallback": ms[5]}
+
+    def set_timing(self, on: bool):
+        """Stage events in every solve (on by default; off saves their cost
+        on the stream, and timings() then fails)."""
+        self._check(self.L.mpt_set_timing(self.h, 1 if on else 0), "mpt_set_timing")
 
     def last_launch(self):
         """Schedule, block, grid divisor, straggler threshold and resolved

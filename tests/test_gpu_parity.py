@@ -246,6 +246,34 @@ def test_graph_replay_matches_eager(ctx):
         ctx.synchronize()
 
 
+def test_stage_timing_switch(ctx):
+    """Stage events on and off give the same results; with them off the
+    stage timings are refused rather than stale; graph replays are never
+    timed."""
+    from paper_2301_06399_amd import mpt
+    sc, b = W.config2(n_rx=64, per_rx=64)
+    ctx.upload_scene(sc)
+    db = mpt.DeviceBatch(b)
+    ref = ctx.solve(db, mpt.default_opts()).numpy()
+    t = ctx.timings()
+    assert t["lm"] > 0 and all(v >= 0 for v in t.values())
+    ctx.set_timing(False)
+    try:
+        g = ctx.solve(db, mpt.default_opts()).numpy()
+        with pytest.raises(mpt.MptError):
+            ctx.timings()
+    finally:
+        ctx.set_timing(True)
+    for k in ("x", "cost", "iters", "status"):
+        assert np.array_equal(g[k], ref[k]), k
+    ctx.solve(db, mpt.default_opts())
+    assert ctx.timings()["lm"] > 0
+    ctx.solve(db, mpt.default_opts(graph=1))
+    ctx.synchronize()
+    with pytest.raises(mpt.MptError):
+        ctx.timings()
+
+
 def test_autotuner_choice_keeps_parity(ctx):
     """The autotuner picks among launch choices that do not change results;
     the tuned solve still matches the oracle."""
