@@ -731,6 +731,19 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
 #pragma unroll
                             for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(X0[3 * k + i] - sh[i]);
                     }
+                    if (N == 1 && MODE != MODE_FALLBACK64 && st0 == ST_RUNNING && p.ty[0] == TP) {
+                        // a single reflection between points strictly on
+                        // opposite sides of its plane has no root: the law
+                        // returns the ray to the side it came from
+                        const double *r64 = kp.s.rec64 + (size_t)p.id[0] * kRec;
+                        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                        for (int i = 0; i < 3; i++) {
+                            s1 += r64[i] * (kp.s.tx[i] - r64[4 + i]);
+                            s2 += r64[i] * (rx[i] - r64[4 + i]);
+                        }
+                        if ((s1 < 0.0 && s2 > 0.0) || (s1 > 0.0 && s2 < 0.0)) st0 = ST_LOCALMIN;
+                    }
                     L.it = 0;
                     L.stat = 0;
                     L.lam = T(0);

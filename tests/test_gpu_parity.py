@@ -246,6 +246,27 @@ def test_graph_replay_matches_eager(ctx):
         ctx.synchronize()
 
 
+@pytest.mark.parametrize("prec,form", [(0, 0), (1, 0), (1, 1)])
+def test_opposite_side_reflections_end_before_iterating(ctx, prec, form):
+    """Single plane reflections with TX and RX strictly on opposite sides of
+    the plane (no root exists) end as local minima with no iteration and an
+    infinite cost; every other solve, and the accept flags, still match the
+    oracle."""
+    from test_oracle_pins import opposite_side_reflections
+    sc, b = W.config2(n_rx=256, per_rx=64)
+    idx, opp = opposite_side_reflections(sc, b)
+    assert opp.sum() > 200
+    g = gpu_solve(ctx, sc, b, precision=prec, form=form)
+    sel = idx[opp]
+    assert (g["status"][sel] == O.LOCALMIN).all()
+    assert (g["iters"][sel] == 0).all() and np.isinf(g["cost"][sel]).all()
+    assert (g["status"][idx[~opp]] == O.CONVERGED).all()
+    fm = "param" if form else "implicit"
+    orc = O.solve_batch(sc, b, form=fm)
+    orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
+    compare_planar(sc, b, g, orc_acc, orc)
+
+
 def test_stage_timing_switch(ctx):
     """Stage events on and off give the same results; with them off the
     stage timings are refused rather than stale; graph replays are never

@@ -613,3 +613,31 @@ def test_random_starts_reach_the_unique_planar_root():
                     np.testing.assert_allclose(X.reshape(-1, 3), Xim, atol=1e-9 * (1 + np.abs(Xim).max()))
                     conv += 1
     assert found >= 100 and conv >= 0.9 * found
+
+
+def opposite_side_reflections(sc, b):
+    """Single plane reflections whose TX and RX lie strictly on opposite
+    sides of the plane: (ids, mask over them)."""
+    t = sc.type_of(np.maximum(b.prim, 0))
+    idx = np.where((b.order == 1) & (t[0] == 0))[0]
+    P = sc.planes[b.prim[0, idx]]
+    n, c = P[:, 0:3], P[:, 4:7]
+    s1 = ((sc.tx[None, :] - c) * n).sum(1)
+    s2 = ((b.rx[b.rx_index[idx]] - c) * n).sum(1)
+    return idx, s1 * s2 < 0
+
+
+@pytest.mark.parametrize("form", ["implicit", "param"])
+def test_opposite_side_single_reflection_has_no_root(form):
+    """The reflection law maps the incoming direction's normal component to
+    its negative, so the outgoing ray returns to the incoming side: a single
+    reflection between points strictly on opposite sides of the plane has no
+    root.  The oracle's descent, started as usual, ends without one on every
+    such street-canyon path, and finds the (image-method) root on every
+    same-side one; the solver may therefore skip the descent for them."""
+    sc, b = W.config2(n_rx=512, per_rx=64)
+    idx, opp = opposite_side_reflections(sc, b)
+    assert opp.sum() > 500 and (~opp).sum() > 500
+    r = O.solve_batch(sc, b.subset(idx), form=form)
+    assert (r["status"][opp] == O.LOCALMIN).all()
+    assert (r["status"][~opp] == O.CONVERGED).all()
