@@ -260,7 +260,7 @@ def test_opposite_side_reflections_end_before_iterating(ctx, prec, form):
     sel = idx[opp]
     assert (g["status"][sel] == O.LOCALMIN).all()
     assert (g["iters"][sel] == 0).all() and np.isinf(g["cost"][sel]).all()
-    assert (g["status"][idx[~opp]] == O.CONVERGED).all()
+    assert ((g["status"][idx[~opp]] & 0x7f) == O.CONVERGED).all()  # some via the FP64 fallback
     fm = "param" if form else "implicit"
     orc = O.solve_batch(sc, b, form=fm)
     orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
