@@ -56,10 +56,12 @@ enum {
     MPT_PATH_BAD_INPUT = 5,  /* order outside 1..5, bad id, non-finite input    */
     MPT_PATH_LOCALMIN = 6,   /* stationary but |R|_inf > tau_root: no path;
                                 also, with 0 iterations and an infinite cost,
-                                a single plane reflection whose TX and RX lie
-                                strictly on opposite sides of the plane (the
-                                law returns a ray to its own side, so no root
-                                exists)                                         */
+                                a path with a plane reflection whose previous
+                                and next points lie strictly on opposite sides
+                                of the plane for every position they can take
+                                (TX or RX, or a plane or straight edge exactly
+                                parallel to it): the law returns a ray to its
+                                own side, so no root exists                     */
     MPT_PATH_FALLBACK = 0x80
 };
 

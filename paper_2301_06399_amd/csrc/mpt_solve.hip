@@ -540,6 +540,54 @@ template <> struct ModeT<MODE_PLAIN64> { using T = double; };
 template <> struct ModeT<MODE_FP32> { using T = float; };
 template <> struct ModeT<MODE_FALLBACK64> { using T = double; };
 
+// A plane reflection sends the ray back to the side it came from (the law
+// negates the normal component of the direction), so at a root the points
+// before and after it lie strictly on the same side of its plane.  When each
+// of them is either fixed (TX, RX) or confined to an object that keeps one
+// side of the plane everywhere (a plane or straight edge exactly parallel to
+// it, off it by more than 1e-9 m), and the two sides differ, no root exists.
+// Plain IEEE FP64 without contraction: an exactly parallel pair is found
+// parallel whatever the scaling of its normals.
+__device__ __forceinline__ bool const_side(const SceneDev &s, int id, int ty, const double *n, const double *o,
+                                           double &side)
+{
+#pragma clang fp contract(off)
+    const double *r = s.rec64 + (size_t)id * kRec;
+    if (ty == TP) {
+        // normals parallel: every point of the other plane is n.(o' - o) off
+        if (n[1] * r[2] - n[2] * r[1] != 0.0 || n[2] * r[0] - n[0] * r[2] != 0.0 || n[0] * r[1] - n[1] * r[0] != 0.0)
+            return false;
+        side = n[0] * (r[4] - o[0]) + n[1] * (r[5] - o[1]) + n[2] * (r[6] - o[2]);
+    } else if (ty == TL) {
+        if (n[0] * r[3] + n[1] * r[4] + n[2] * r[5] != 0.0) return false;
+        side = n[0] * (r[0] - o[0]) + n[1] * (r[1] - o[1]) + n[2] * (r[2] - o[2]);
+    } else {
+        return false;
+    }
+    return fabs(side) > 1e-9;
+}
+
+template <int N>
+__device__ bool sides_forbid_root(const SceneDev &s, const int *id, const int *ty, const double *rx)
+{
+#pragma clang fp contract(off)
+    bool forbid = false;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        if (ty[k] != TP) continue;
+        const double *r = s.rec64 + (size_t)id[k] * kRec;
+        const double n[3] = {r[0], r[1], r[2]}, o[3] = {r[4], r[5], r[6]};
+        double a = 0.0, b = 0.0;
+        bool ka = true, kb = true;
+        if (k == 0) a = n[0] * (s.tx[0] - o[0]) + n[1] * (s.tx[1] - o[1]) + n[2] * (s.tx[2] - o[2]);
+        else ka = const_side(s, id[k - 1], ty[k - 1], n, o, a);
+        if (k == N - 1) b = n[0] * (rx[0] - o[0]) + n[1] * (rx[1] - o[1]) + n[2] * (rx[2] - o[2]);
+        else kb = const_side(s, id[k + 1], ty[k + 1], n, o, b);
+        forbid = forbid || (ka && kb && ((a < 0.0 && b > 0.0) || (a > 0.0 && b < 0.0)));
+    }
+    return forbid;
+}
+
 //
 // Stragglers.  Iteration counts are bimodal (a root converges in a handful of
 // iterations, a path without one creeps until the plateau test ends it), so
@@ -731,19 +779,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
 #pragma unroll
                             for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(X0[3 * k + i] - sh[i]);
                     }
-                    if (N == 1 && MODE != MODE_FALLBACK64 && st0 == ST_RUNNING && p.ty[0] == TP) {
-                        // a single reflection between points strictly on
-                        // opposite sides of its plane has no root: the law
-                        // returns the ray to the side it came from
-                        const double *r64 = kp.s.rec64 + (size_t)p.id[0] * kRec;
-                        double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                        for (int i = 0; i < 3; i++) {
-                            s1 += r64[i] * (kp.s.tx[i] - r64[4 + i]);
-                            s2 += r64[i] * (rx[i] - r64[4 + i]);
-                        }
-                        if ((s1 < 0.0 && s2 > 0.0) || (s1 > 0.0 && s2 < 0.0)) st0 = ST_LOCALMIN;
-                    }
+                    if (MODE != MODE_FALLBACK64 && st0 == ST_RUNNING && sides_forbid_root<N>(kp.s, p.id, p.ty, rx))
+                        st0 = ST_LOCALMIN;
                     L.it = 0;
                     L.stat = 0;
                     L.lam = T(0);
