@@ -385,6 +385,16 @@ struct Lane {
     T X[D];
     T lam, Cref, C, rinf;
     int it, stat;
+    // The normal equations, gradient and cost of the current point, kept
+    // after a rejected step: the point has not moved, so the next iteration
+    // would rebuild them bit for bit (only the damping changes).  FP32 and
+    // orders 1-3, whose copies fit in registers beside the order-5 code (the
+    // FP64 kernels already spill).
+    static constexpr bool kKeep = N <= 3 && sizeof(T) == 4;
+    static constexpr int kS = kKeep ? D * (D + 1) / 2 : 1;
+    static constexpr int kM = kKeep ? D : 1;
+    T A0[kS], g0[kM], C0, r0;
+    bool keep;
 };
 
 // One Levenberg-Marquardt iteration on the cost of Eq. (12) with the
@@ -394,9 +404,28 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
                                        const LMOpts<T> &o)
 {
     constexpr int M = 3 * N;
+    using LT = Lane<T, N>;
     L.it++;
     T A[Band<N>::SIZE], g[M], C, rinf;
-    if (!assemble<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+    if (LT::kKeep && L.keep) {
+#pragma unroll
+        for (int i = 0; i < Band<N>::SIZE; i++) A[i] = L.A0[i % LT::kS];
+#pragma unroll
+        for (int i = 0; i < M; i++) g[i] = L.g0[i % LT::kM];
+        C = L.C0;
+        rinf = L.r0;
+    } else {
+        if (!assemble<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+        if constexpr (LT::kKeep) {
+#pragma unroll
+            for (int i = 0; i < Band<N>::SIZE; i++) L.A0[i] = A[i];
+#pragma unroll
+            for (int i = 0; i < M; i++) L.g0[i] = g[i];
+            L.C0 = C;
+            L.r0 = rinf;
+        }
+    }
+    L.keep = false;
     L.C = C;
     L.rinf = rinf;
     T dmax = T(0);
@@ -417,6 +446,7 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
     if (!chol_band<T, N>(A)) {
         L.lam *= T(10);
         if (L.lam > T(1e12) * dmax) return ST_STALL;
+        L.keep = LT::kKeep;
         return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
     }
 #pragma unroll
@@ -453,6 +483,7 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
         if (small) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
         L.lam *= T(10);
         if (L.lam > T(1e12) * dmax) return ST_STALL;
+        L.keep = LT::kKeep;
     }
     return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
 }
@@ -464,9 +495,28 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
                                              const LMOpts<T> &o)
 {
     constexpr int M = 2 * N;
+    using LT = Lane<T, N, 2 * N>;
     L.it++;
     T A[Band<N, 2>::SIZE], g[M], C, rinf;
-    if (!assemble_param<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+    if (LT::kKeep && L.keep) {
+#pragma unroll
+        for (int i = 0; i < Band<N, 2>::SIZE; i++) A[i] = L.A0[i % LT::kS];
+#pragma unroll
+        for (int i = 0; i < M; i++) g[i] = L.g0[i % LT::kM];
+        C = L.C0;
+        rinf = L.r0;
+    } else {
+        if (!assemble_param<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+        if constexpr (LT::kKeep) {
+#pragma unroll
+            for (int i = 0; i < Band<N, 2>::SIZE; i++) L.A0[i] = A[i];
+#pragma unroll
+            for (int i = 0; i < M; i++) L.g0[i] = g[i];
+            L.C0 = C;
+            L.r0 = rinf;
+        }
+    }
+    L.keep = false;
     L.C = C;
     L.rinf = rinf;
     bool real[M];
@@ -496,6 +546,7 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
     if (!chol_band<T, N, 2>(A)) {
         L.lam *= T(10);
         if (L.lam > T(1e12) * dmax) return ST_STALL;
+        L.keep = LT::kKeep;
         return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
     }
 #pragma unroll
@@ -526,6 +577,7 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
         if (small) return (L.rinf <= o.tau_root) ? ST_CONV : ST_LOCALMIN;
         L.lam *= T(10);
         if (L.lam > T(1e12) * dmax) return ST_STALL;
+        L.keep = LT::kKeep;
     }
     return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
 }
@@ -703,6 +755,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                         L.lam = (T)kp.spill_f[sid];
                         L.Cref = (T)kp.spill_f[(size_t)kp.b.n + sid];
                         L.stat = (int)kp.spill_f[(size_t)2 * kp.b.n + sid];
+                        L.keep = false;
                         L.C = T(__builtin_huge_val());
                         L.rinf = T(__builtin_huge_val());
                     } else {
@@ -783,6 +836,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                         st0 = ST_LOCALMIN;
                     L.it = 0;
                     L.stat = 0;
+                    L.keep = false;
                     L.lam = T(0);
                     L.C = T(__builtin_huge_val());
                     L.rinf = T(__builtin_huge_val());
