@@ -387,7 +387,7 @@ struct Lane {
     int it, stat;
     // The normal equations, gradient and cost of the current point, kept
     // after a rejected step: the point has not moved, so the next iteration
-    // would rebuild them bit for bit (only the damping changes).  FP32 and
+    // would rebuild the same values (only the damping changes).  FP32 and
     // orders 1-3, whose copies fit in registers beside the order-5 code (the
     // FP64 kernels already spill).
     static constexpr bool kKeep = N <= 3 && sizeof(T) == 4;
