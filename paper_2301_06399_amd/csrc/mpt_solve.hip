@@ -650,7 +650,44 @@ __device__ bool sides_forbid_root(const SceneDev &s, const int *id, const int *t
 // (kp.resume) packs the parked paths densely and finishes them.  The same
 // machine code runs every iteration of a path, from the exact state it was
 // parked in, so the results are identical bit for bit.
-template <int MODE, int N, int FORM = 0>
+// One iteration with the path's primitive types fixed at compile time (digit
+// k of CODE, base 4: 0 plane, 1 straight edge), so that no per-type branch
+// or select is left in the code.  Bins are type-homogeneous, so most waves
+// hold one planar sequence; they run this instead of the generic step.
+template <typename T, int N, int FORM, int CODE>
+__device__ __forceinline__ int lm_step_fixed(const SceneT<T> &sc, const PathIn<T, N> &p,
+                                             Lane<T, N, FORM ? 2 * N : 3 * N> &L, const LMOpts<T> &o)
+{
+    PathIn<T, N> q = p;
+#pragma unroll
+    for (int k = 0; k < N; k++) q.ty[k] = (CODE >> (2 * k)) & 3;
+    q.planar = true;
+    if constexpr (FORM) return lm_step_param<T, N>(sc, q, L, o);
+    else return lm_step<T, N>(sc, q, L, o);
+}
+
+// The fixed-type step for a wave-uniform planar sequence `code` of orders
+// 1-3; -1 for any other sequence (the caller runs the generic step).
+template <typename T, int N, int FORM>
+__device__ __forceinline__ int lm_step_uniform(int code, const SceneT<T> &sc, const PathIn<T, N> &p,
+                                               Lane<T, N, FORM ? 2 * N : 3 * N> &L, const LMOpts<T> &o)
+{
+#define MPT_FIXED(c) \
+    case c: return lm_step_fixed<T, N, FORM, c>(sc, p, L, o);
+    if constexpr (N == 1) {
+        switch (code) { MPT_FIXED(0) MPT_FIXED(1) }
+    } else if constexpr (N == 2) {
+        switch (code) { MPT_FIXED(0) MPT_FIXED(1) MPT_FIXED(4) MPT_FIXED(5) }
+    } else if constexpr (N == 3) {
+        switch (code) {
+            MPT_FIXED(0) MPT_FIXED(1) MPT_FIXED(4) MPT_FIXED(5) MPT_FIXED(16) MPT_FIXED(17) MPT_FIXED(20) MPT_FIXED(21)
+        }
+    }
+#undef MPT_FIXED
+    return -1;
+}
+
+template <int MODE, int N, int FORM = 0, bool TYPED = false>
 __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restrict__ srec)
 {
     using T = typename ModeT<MODE>::T;
@@ -868,8 +905,19 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
         if (active) {
             int st = ST_PARKED;
             if (!park) {
-                if constexpr (FORM) st = lm_step_param<T, N>(sc, p, L, o);
-                else st = lm_step<T, N>(sc, p, L, o);
+                st = -1;
+                if constexpr (TYPED && MODE == MODE_FP32 && N <= 3) {
+                    // a wave whose busy lanes share one type sequence
+                    int code = 0;
+#pragma unroll
+                    for (int k = 0; k < N; k++) code |= p.ty[k] << (2 * k);
+                    const int c0 = __builtin_amdgcn_readfirstlane(code);
+                    if (__ballot(code != c0) == 0) st = lm_step_uniform<T, N, FORM>(c0, sc, p, L, o);
+                }
+                if (st == -1) {
+                    if constexpr (FORM) st = lm_step_param<T, N>(sc, p, L, o);
+                    else st = lm_step<T, N>(sc, p, L, o);
+                }
             }
             if (st == ST_PARKED) {
                 // ---- a parked path: its exact state, for the straggler launch
@@ -988,11 +1036,11 @@ k_lm(KParams kp)
     if (cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4] == 0) return;  // nothing to solve: skip the staging
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     // long paths first so that the short ones fill the tail
-    lm_bin<MODE, 5, FORM>(kp, rec);
-    lm_bin<MODE, 4, FORM>(kp, rec);
-    lm_bin<MODE, 3, FORM>(kp, rec);
-    lm_bin<MODE, 2, FORM>(kp, rec);
-    lm_bin<MODE, 1, FORM>(kp, rec);
+    lm_bin<MODE, 5, FORM, true>(kp, rec);
+    lm_bin<MODE, 4, FORM, true>(kp, rec);
+    lm_bin<MODE, 3, FORM, true>(kp, rec);
+    lm_bin<MODE, 2, FORM, true>(kp, rec);
+    lm_bin<MODE, 1, FORM, true>(kp, rec);
 }
 
 // One persistent launch over orders 3, 2, 1 with the register budget of
