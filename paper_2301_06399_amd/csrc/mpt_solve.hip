@@ -653,7 +653,7 @@ __device__ bool sides_forbid_root(const SceneDev &s, const int *id, const int *t
 // One iteration with the path's primitive types fixed at compile time (digit
 // k of CODE, base 4: 0 plane, 1 straight edge), so that no per-type branch
 // or select is left in the code.  Bins are type-homogeneous, so most waves
-// hold one planar sequence; they run this instead of the generic step.
+// hold one planar sequence and run one of these variants only.
 template <typename T, int N, int FORM, int CODE>
 __device__ __forceinline__ int lm_step_fixed(const SceneT<T> &sc, const PathIn<T, N> &p,
                                              Lane<T, N, FORM ? 2 * N : 3 * N> &L, const LMOpts<T> &o)
@@ -666,8 +666,8 @@ __device__ __forceinline__ int lm_step_fixed(const SceneT<T> &sc, const PathIn<T
     else return lm_step<T, N>(sc, q, L, o);
 }
 
-// The fixed-type step for a wave-uniform planar sequence `code` of orders
-// 1-3; -1 for any other sequence (the caller runs the generic step).
+// The fixed-type step for the planar sequence `code` of orders 1-3; -1 for
+// any other sequence (the caller runs the generic step).
 template <typename T, int N, int FORM>
 __device__ __forceinline__ int lm_step_uniform(int code, const SceneT<T> &sc, const PathIn<T, N> &p,
                                                Lane<T, N, FORM ? 2 * N : 3 * N> &L, const LMOpts<T> &o)
@@ -907,12 +907,13 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
             if (!park) {
                 st = -1;
                 if constexpr (TYPED && MODE == MODE_FP32 && N <= 3) {
-                    // a wave whose busy lanes share one type sequence
+                    // every planar path takes its fixed-type step, whatever
+                    // the other lanes of its wave hold, so that its result
+                    // does not depend on the schedule
                     int code = 0;
 #pragma unroll
                     for (int k = 0; k < N; k++) code |= p.ty[k] << (2 * k);
-                    const int c0 = __builtin_amdgcn_readfirstlane(code);
-                    if (__ballot(code != c0) == 0) st = lm_step_uniform<T, N, FORM>(c0, sc, p, L, o);
+                    st = lm_step_uniform<T, N, FORM>(code, sc, p, L, o);
                 }
                 if (st == -1) {
                     if constexpr (FORM) st = lm_step_param<T, N>(sc, p, L, o);
