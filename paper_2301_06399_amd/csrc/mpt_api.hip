@@ -39,7 +39,7 @@ struct mpt_ctx {
     bool has_scene = false;
     bool curved = false;     // the scene has paraboloids or circles
     bool param_ok = true;    // every quadric is a paraboloid of revolution
-    // workspace: counters | perm | network rows | fallback lists
+    // workspace: counters | perm | polish lists | fallback lists
     int *ws = nullptr;
     size_t ws_cap = 0;  // solves
     int *blk = nullptr;
@@ -68,7 +68,7 @@ struct mpt_ctx {
     std::vector<unsigned char> gkey;
 };
 
-// bin_cnt 0..4, (5..9 unused), head 10..19, (20..24 unused), fb_cnt 25..29, curved rows 30, then
+// bin_cnt 0..4, (5..9 unused), head 10..19, pol_cnt 20..24, fb_cnt 25..29, curved rows 30, then
 // 3 x 1364 key counters, then spill_cnt 0..4 and spill_head 5..9
 static const int kKeyCounters = 3 * 1364;
 static const int kSpillCounters = 32 + kKeyCounters;
@@ -538,9 +538,10 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.x0_learned = c->x0l;
     kp.bin_cnt = ctr + 0;
     kp.head = ctr + 10;
+    kp.pol_cnt = ctr + 20;
     kp.fb_cnt = ctr + 25;
     kp.perm = ctr + kCounters;
-    kp.net_rows = ctr + kCounters + n;
+    kp.pol_list = ctr + kCounters + n;
     kp.fb_list = ctr + kCounters + 2 * n;
     kp.spill_t = spill;
     kp.refill = opts->refill > 1 ? (opts->refill < 64 ? opts->refill : 64) : 1;
@@ -559,8 +560,8 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     if (net) {
         if (opts->init == MPT_INIT_LEARNED) {
             // the network serves only the paths with a curved object: list
-            // them and predict
-            int *rows = kp.net_rows, *count = ctr + 30;
+            // them (the polish list is free until the FP32 pass) and predict
+            int *rows = (int *)kp.pol_list, *count = ctr + 30;
             launch_curved_rows(bd, c->s, rows, count, s);
             st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s, rows, count);
             if (!st) launch_learned_choose(c->s, bd, rows, count, false, c->x0l, s);
@@ -627,6 +628,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     }
     if (timed) hipEventRecord(c->ev[4], s);
     if (n > 0 && mode == MODE_FP32) {
+        launch_polish_list(kp, s);
         launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
     }
     if (timed) hipEventRecord(c->ev[5], s);

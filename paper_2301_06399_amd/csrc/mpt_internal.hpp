@@ -66,7 +66,8 @@ struct KParams {
     const int *bin_cnt;        // [5] solves per order
     const int *perm;           // [n] solve ids grouped by order
     int *head;                 // [10] work counters: bins, fallback lists
-    int *net_rows;             // [n] the solves the network serves
+    int *pol_cnt;              // [5]
+    int *pol_list;             // [n] polish lists (bin-relative slots)
     int *fb_cnt;               // [5]
     int *fb_list;              // [n] fallback lists (bin-relative slots)
     int spill_t;               // park a drained bin's busy lanes when at most this many (0: never)
@@ -91,6 +92,7 @@ void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *co
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
                            double *x0l, hipStream_t st);
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
+void launch_polish_list(const KParams &kp, hipStream_t st);
 void launch_samples(const SceneDev &s, int k, double *samp, int *cnt, hipStream_t st);
 void launch_visibility(const SceneDev &s, int k, double min_seg, const double *samp, const int *cnt, uint32_t *V,
                        uint32_t *B, int W, size_t lds_max, int cu, hipStream_t st);

@@ -1073,13 +1073,11 @@ __attribute__((amdgpu_waves_per_eu(Occ<MODE, N, FORM>::W, Occ<MODE, N, FORM>::W)
 }
 
 // ------------------------------------------------------------------ polish
-// Undamped FP64 Gauss-Newton from the FP32 end point (world frame).  The
-// lanes walk the order's bin (grouped by type sequence, so a wave mostly
-// follows one code path) and polish the solves the FP32 pass routed here.
+// Undamped FP64 Gauss-Newton from the FP32 end point (world frame).
 template <int N>
 __device__ void polish_bin(const KParams &kp)
 {
-    const int count = kp.bin_cnt[N - 1];
+    const int count = kp.pol_cnt[N - 1];
     if (count == 0) return;
     const int off = bin_offset(kp.bin_cnt, N);
     SceneT<double> sc;
@@ -1088,9 +1086,7 @@ __device__ void polish_bin(const KParams &kp)
     for (int i = 0; i < 3; i++) { sc.tx[i] = kp.s.tx[i]; sc.glo[i] = kp.s.glo[i]; sc.ghi[i] = kp.s.ghi[i]; }
     constexpr int M = 3 * N;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < count; q += gridDim.x * blockDim.x) {
-        const int sid = kp.perm[off + q];
-        const int routed = kp.out.status[sid];
-        if (routed != ROUTE_POLISH_FB && routed != ROUTE_POLISH_MAXIT && routed != ROUTE_POLISH_LOCALMIN) continue;
+        const int sid = kp.pol_list[off + q];
         PathIn<double, N> p;
         const int ri = kp.b.rx_index[sid];
 #pragma unroll
@@ -1402,6 +1398,54 @@ void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows
     if (b.n == 0) return;
     const unsigned g = (unsigned)std::min<int64_t>((b.n + 255) / 256, 2048);
     hipLaunchKernelGGL(k_learned_choose, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l);
+}
+
+// The polish list: the solves the FP32 passes routed to the polish, grouped
+// by order at the bins' offsets.  Each block counts its solves per order in
+// LDS and takes its slots with one global atomic per order, so that the
+// counters see a few hundred atomics rather than one per wave.
+constexpr int kPolListPer = 8;  // solves per thread
+
+__global__ void __launch_bounds__(256) k_polish_list(KParams kp)
+{
+    __shared__ int lcnt[kMaxN], lbase[kMaxN];
+    const int64_t b0 = (int64_t)blockIdx.x * blockDim.x * kPolListPer;
+    if (threadIdx.x < kMaxN) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    int ord[kPolListPer], slot[kPolListPer];
+    for (int q = 0; q < kPolListPer; q++) {
+        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+        ord[q] = 0;
+        if (i < kp.b.n) {
+            const int st = kp.out.status[i];
+            if (st == ROUTE_POLISH_FB || st == ROUTE_POLISH_MAXIT || st == ROUTE_POLISH_LOCALMIN) ord[q] = kp.b.order[i];
+        }
+        slot[q] = 0;
+        for (int o = 1; o <= kMaxN; o++) {
+            const uint64_t m = __ballot(ord[q] == o);
+            if (!m) continue;
+            const int leader = (int)__builtin_ctzll(m);
+            int base = 0;
+            if (__lane_id() == leader) base = atomicAdd(&lcnt[o - 1], (int)__popcll(m));
+            base = __shfl(base, leader);
+            if (ord[q] == o) slot[q] = base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxN)
+        lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&kp.pol_cnt[threadIdx.x], lcnt[threadIdx.x]) : 0;
+    __syncthreads();
+    for (int q = 0; q < kPolListPer; q++) {
+        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+        if (ord[q] > 0) kp.pol_list[bin_offset(kp.bin_cnt, ord[q]) + lbase[ord[q] - 1] + slot[q]] = (int)i;
+    }
+}
+
+void launch_polish_list(const KParams &kp, hipStream_t st)
+{
+    if (kp.b.n == 0) return;
+    const int64_t per_block = 256 * kPolListPer;
+    hipLaunchKernelGGL(k_polish_list, dim3((unsigned)((kp.b.n + per_block - 1) / per_block)), dim3(256), 0, st, kp);
 }
 
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
