@@ -1401,11 +1401,9 @@ void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows
 }
 
 // The polish list: the solves the FP32 passes routed to the polish, grouped
-// by order at the bins' offsets.  The blocks walk the bins (solves grouped
-// by type sequence), so that a polish wave mostly follows one code path.
-// Each block counts its solves per order in LDS and takes its slots with one
-// global atomic per order, so that the counters see a few hundred atomics
-// rather than one per wave.
+// by order at the bins' offsets.  Each block counts its solves per order in
+// LDS and takes its slots with one global atomic per order, so that the
+// counters see a few hundred atomics rather than one per wave.
 constexpr int kPolListPer = 8;  // solves per thread
 
 __global__ void __launch_bounds__(256) k_polish_list(KParams kp)
@@ -1414,18 +1412,13 @@ __global__ void __launch_bounds__(256) k_polish_list(KParams kp)
     const int64_t b0 = (int64_t)blockIdx.x * blockDim.x * kPolListPer;
     if (threadIdx.x < kMaxN) lcnt[threadIdx.x] = 0;
     __syncthreads();
-    int ord[kPolListPer], slot[kPolListPer], sid[kPolListPer];
-    // solves in the bins (valid ones only)
-    const int64_t nb = (int64_t)kp.bin_cnt[0] + kp.bin_cnt[1] + kp.bin_cnt[2] + kp.bin_cnt[3] + kp.bin_cnt[4];
+    int ord[kPolListPer], slot[kPolListPer];
     for (int q = 0; q < kPolListPer; q++) {
-        const int64_t j = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
         ord[q] = 0;
-        sid[q] = 0;
-        if (j < nb) {
-            sid[q] = kp.perm[j];
-            const int st = kp.out.status[sid[q]];
-            if (st == ROUTE_POLISH_FB || st == ROUTE_POLISH_MAXIT || st == ROUTE_POLISH_LOCALMIN)
-                ord[q] = kp.b.order[sid[q]];
+        if (i < kp.b.n) {
+            const int st = kp.out.status[i];
+            if (st == ROUTE_POLISH_FB || st == ROUTE_POLISH_MAXIT || st == ROUTE_POLISH_LOCALMIN) ord[q] = kp.b.order[i];
         }
         slot[q] = 0;
         for (int o = 1; o <= kMaxN; o++) {
@@ -1442,8 +1435,10 @@ __global__ void __launch_bounds__(256) k_polish_list(KParams kp)
     if (threadIdx.x < kMaxN)
         lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&kp.pol_cnt[threadIdx.x], lcnt[threadIdx.x]) : 0;
     __syncthreads();
-    for (int q = 0; q < kPolListPer; q++)
-        if (ord[q] > 0) kp.pol_list[bin_offset(kp.bin_cnt, ord[q]) + lbase[ord[q] - 1] + slot[q]] = sid[q];
+    for (int q = 0; q < kPolListPer; q++) {
+        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+        if (ord[q] > 0) kp.pol_list[bin_offset(kp.bin_cnt, ord[q]) + lbase[ord[q] - 1] + slot[q]] = (int)i;
+    }
 }
 
 void launch_polish_list(const KParams &kp, hipStream_t st)
