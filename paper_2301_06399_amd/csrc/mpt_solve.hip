@@ -909,7 +909,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
             int st = ST_PARKED;
             if (!park) {
                 st = -1;
-                if constexpr (TYPED && MODE == MODE_FP32 && (FORM == 1 ? N <= 3 : N <= 2)) {
+                if constexpr (TYPED && MODE == MODE_FP32 && FORM == 1 && N <= 3) {
                     // every planar path takes its fixed-type step, whatever
                     // the other lanes of its wave hold, so that its result
                     // does not depend on the schedule
