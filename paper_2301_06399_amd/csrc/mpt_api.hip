@@ -324,6 +324,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->init = MPT_INIT_LINE;
     o->max_iter = 200;
     o->max_iter32 = 100;
+    o->max_iter32_planar = 60;
     o->polish_steps = 5;
     o->fallback = MPT_FALLBACK_GPU_FP64;
     o->plateau_win = 10;
@@ -472,8 +473,8 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
     if (opts->init == MPT_INIT_USER && b->n > 0 && !b->x0) return fail(c, MPT_E_INVALID_ARG, "user start without x0");
     if ((opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL) && !mlp_ready(c->mlp))
         return fail(c, MPT_E_NO_MODEL, "learned start requested but no network initialised");
-    if (opts->max_iter < 0 || opts->max_iter32 < 0 || opts->max_iter_fb < 0 || opts->polish_steps < 0 ||
-        opts->plateau_win < 0)
+    if (opts->max_iter < 0 || opts->max_iter32 < 0 || opts->max_iter32_planar < 0 || opts->max_iter_fb < 0 ||
+        opts->polish_steps < 0 || opts->plateau_win < 0)
         return fail(c, MPT_E_INVALID_ARG, "negative iteration option");
     if (opts->block != 0 && (opts->block % 64 != 0 || opts->block > 256 || opts->block < 64))
         return fail(c, MPT_E_INVALID_ARG, "block must be 64, 128, 192 or 256");
@@ -519,6 +520,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.o.init = opts->init;
     kp.o.max_iter = opts->max_iter;
     kp.o.max_iter32 = opts->max_iter32;
+    kp.o.max_iter32_planar = opts->max_iter32_planar < opts->max_iter32 ? opts->max_iter32_planar : opts->max_iter32;
     kp.o.max_iter_fb = opts->max_iter_fb;
     kp.o.polish_steps = opts->polish_steps;
     kp.o.fallback = opts->fallback;

@@ -49,7 +49,7 @@ struct OutDevC {
 };
 
 struct OptsDev {
-    int init, max_iter, max_iter32, max_iter_fb, polish_steps, fallback, plateau_win;
+    int init, max_iter, max_iter32, max_iter32_planar, max_iter_fb, polish_steps, fallback, plateau_win;
     double plateau_frac, tol_step, tol_res, tau_root, lambda0, tol_step32, tol_res32, tau_root32, polish_gate;
     uint64_t seed;
     double stat_tol;

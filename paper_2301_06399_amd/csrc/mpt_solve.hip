@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(256) k_learned_choose(SceneDev s, BatchDev b, 
 // ------------------------------------------------------------------ LM lane state
 template <typename T>
 struct LMOpts {
-    int max_iter, win, stat_win;
+    int max_iter, max_iter_planar, win, stat_win;
     T frac, tol_step, tol_res, tau_root, lambda0, stat_tol;
 };
 
@@ -447,7 +447,7 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
         L.lam *= T(10);
         if (L.lam > T(1e12) * dmax) return ST_STALL;
         L.keep = LT::kKeep;
-        return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+        return (L.it >= (p.planar ? o.max_iter_planar : o.max_iter)) ? ST_MAXIT : ST_RUNNING;
     }
 #pragma unroll
     for (int i = 0; i < M; i++) g[i] = -g[i];
@@ -485,7 +485,7 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
         if (L.lam > T(1e12) * dmax) return ST_STALL;
         L.keep = LT::kKeep;
     }
-    return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+    return (L.it >= (p.planar ? o.max_iter_planar : o.max_iter)) ? ST_MAXIT : ST_RUNNING;
 }
 
 // One Levenberg-Marquardt iteration of the parametric form (Eq. (15)), with
@@ -547,7 +547,7 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
         L.lam *= T(10);
         if (L.lam > T(1e12) * dmax) return ST_STALL;
         L.keep = LT::kKeep;
-        return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+        return (L.it >= (p.planar ? o.max_iter_planar : o.max_iter)) ? ST_MAXIT : ST_RUNNING;
     }
 #pragma unroll
     for (int i = 0; i < M; i++) g[i] = -g[i];
@@ -579,7 +579,7 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
         if (L.lam > T(1e12) * dmax) return ST_STALL;
         L.keep = LT::kKeep;
     }
-    return (L.it >= o.max_iter) ? ST_MAXIT : ST_RUNNING;
+    return (L.it >= (p.planar ? o.max_iter_planar : o.max_iter)) ? ST_MAXIT : ST_RUNNING;
 }
 
 // ------------------------------------------------------------------ persistent LM kernel
@@ -725,11 +725,13 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
     LMOpts<T> o;
     if (MODE == MODE_FP32) {
         o.max_iter = kp.o.max_iter32;
+        o.max_iter_planar = kp.o.max_iter32_planar;
         o.tol_step = (T)kp.o.tol_step32;
         o.tol_res = (T)kp.o.tol_res32;
         o.tau_root = (T)kp.o.tau_root32;  // an FP32 point this close is taken for a root
     } else {
         o.max_iter = (MODE == MODE_FALLBACK64) ? kp.o.max_iter_fb : kp.o.max_iter;
+        o.max_iter_planar = o.max_iter;
         o.tol_step = (T)kp.o.tol_step;
         o.tol_res = (T)kp.o.tol_res;
         o.tau_root = (T)kp.o.tau_root;

@@ -52,7 +52,8 @@ class SolveOpts(C.Structure):
                 ("tau_root", C.c_double), ("lambda0", C.c_double), ("tol_step32", C.c_double),
                 ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double),
                 ("seed", C.c_uint64), ("spill", C.c_int32), ("form", C.c_int32),
-                ("stat_tol", C.c_double), ("stat_win", C.c_int32), ("refill", C.c_int32)]
+                ("stat_tol", C.c_double), ("stat_win", C.c_int32), ("refill", C.c_int32),
+                ("max_iter32_planar", C.c_int32)]
 
 
 class SolveOut(C.Structure):
