@@ -266,6 +266,25 @@ def test_reflection_side_certificate_ends_before_iterating(ctx, prec, form):
     compare_planar(sc, b, g, orc_acc, orc)
 
 
+def test_planar_fp32_cap(ctx):
+    """The FP32 pass stops paths of planes and straight edges at
+    max_iter32_planar iterations and the others at max_iter32; the default
+    planar cap keeps the oracle's accepted set on the street canyon (the
+    other parity tests), and a cap above max_iter32 is clamped to it."""
+    from paper_2301_06399_amd import mpt
+    sc, b = W.config5(n_rx=64, per_rx=64)  # street canyon + paraboloids
+    ctx.upload_scene(sc)
+    db = mpt.DeviceBatch(b)
+    planar = np.all((sc.type_of(np.maximum(b.prim, 0)) <= 1) | (np.arange(5)[:, None] >= b.order[None, :]), axis=0)
+    assert planar.sum() > 100 and (~planar).sum() > 100
+    out = mpt.DeviceOut(b.n, stages=True)
+    ctx.solve(db, mpt.default_opts(max_iter32=40, max_iter32_planar=3), out)
+    it = out.numpy()["stage"][0]
+    assert it[planar].max() <= 3 and it[~planar].max() > 3 and it.max() <= 40
+    ctx.solve(db, mpt.default_opts(max_iter32=5, max_iter32_planar=60), out)
+    assert out.numpy()["stage"][0].max() <= 5
+
+
 def test_stage_timing_switch(ctx):
     """Stage events on and off give the same results; with them off the
     stage timings are refused rather than stale; graph replays are never
