@@ -227,7 +227,7 @@ typedef struct {
     int32_t refill;        /* 16    a wave takes new paths once at least this
                               many of its 64 lanes are idle (1..64): each
                               refill stalls the wave on the new paths' loads */
-    int32_t max_iter32_planar; /* 60  FP32 stage cap for paths of planes and
+    int32_t max_iter32_planar; /* 80  FP32 stage cap for paths of planes and
                               straight edges (1..max_iter32): their descents
                               converge in a few iterations from any start, so
                               one still running after this many has stalled;

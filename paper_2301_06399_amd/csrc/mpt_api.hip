@@ -324,7 +324,7 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->init = MPT_INIT_LINE;
     o->max_iter = 200;
     o->max_iter32 = 100;
-    o->max_iter32_planar = 60;
+    o->max_iter32_planar = 80;
     o->polish_steps = 5;
     o->fallback = MPT_FALLBACK_GPU_FP64;
     o->plateau_win = 10;
