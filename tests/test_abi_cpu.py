@@ -71,3 +71,37 @@ def test_bit_rows_unpack_like_the_header_says():
             words[r, j // 32] |= np.uint32(1) << np.uint32(j % 32)
     assert np.array_equal(mpt.unpack_bits(words.view(np.int32), n), bits)
     assert np.array_equal(mpt.unpack_bits(words[0].view(np.int32), n), bits[0])
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every field of the binding's ctypes structs sits at the offset and
+    has the size the C compiler gives it in include/mpt.h, and each struct
+    has the C size: the binding and the library read the same bytes."""
+    import subprocess
+    from paper_2301_06399_amd import mpt
+    structs = {"mpt_scene_desc": mpt.SceneDesc, "mpt_batch_desc": mpt.BatchDesc,
+               "mpt_solve_opts": mpt.SolveOpts, "mpt_solve_out": mpt.SolveOut}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mpt.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu %zu\\n", offsetof({cname}, {fname}), '
+                         f'sizeof((({cname} *)0)->{fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        parts = line.split()
+        if len(parts) == 3 and parts[1] == "size":
+            got[(parts[0], None)] = int(parts[2])
+        elif len(parts) == 4:
+            got[(parts[0], parts[1])] = (int(parts[2]), int(parts[3]))
+    for cname, py in structs.items():
+        assert got[(cname, None)] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            f = getattr(py, fname)
+            assert got[(cname, fname)] == (f.offset, f.size), (cname, fname)
