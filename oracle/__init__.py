@@ -41,8 +41,7 @@ class _Scene(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("tol_step", C.c_double), ("tol_res", C.c_double),
                 ("tau_root", C.c_double), ("lambda0", C.c_double),
-                ("plateau_win", C.c_int32), ("plateau_frac", C.c_double),
-                ("stat_tol", C.c_double), ("stat_win", C.c_int32)]
+                ("plateau_win", C.c_int32), ("plateau_frac", C.c_double)]
 
 
 _lib = None
@@ -115,9 +114,10 @@ class OracleScene:
         return C.byref(self.s)
 
 
-def default_opts(max_iter=200, plateau_win=10, plateau_frac=0.999, stat_tol=0.02, stat_win=4):
+def default_opts(max_iter=200, plateau_win=10, plateau_frac=0.999):
+    """The parity configuration: 200 iterations, plateau window 10 at 0.999."""
     return _Opts(max_iter=max_iter, tol_step=1e-12, tol_res=1e-13, tau_root=TAU_RES, lambda0=1e-3,
-                 plateau_win=plateau_win, plateau_frac=plateau_frac, stat_tol=stat_tol, stat_win=stat_win)
+                 plateau_win=plateau_win, plateau_frac=plateau_frac)
 
 
 def residual(scene, rx, ids, X, jac=True):

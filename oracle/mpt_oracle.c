@@ -416,17 +416,6 @@ static int outside_guard(const orc_scene *s, const double *X, int n)
     return 0;
 }
 
-/* Paths of planes and straight edges only (their root is unique). */
-static int planar_path(const orc_scene *s, int n, const int32_t *ids)
-{
-    for (int k = 0; k < n; k++) {
-        const double *rec;
-        int t = prim_type(s, ids[k], &rec);
-        if (t != TP && t != TL) return 0;
-    }
-    return 1;
-}
-
 static int ids_ok(const orc_scene *s, int n, const int32_t *ids)
 {
     int tot = s->n_pl + s->n_ln + s->n_q + s->n_c;
@@ -471,8 +460,7 @@ int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *
     double R[MAXR], J[MAXR * MAXU], A[MAXU * MAXU], g[MAXU], M[MAXU * MAXU], dx[MAXU], mg[MAXU];
     double Xt[MAXU], Rt[MAXR];
     double lam = 0, C = INFINITY, C_ref = INFINITY, rinf = INFINITY;
-    int status = ORC_MAXITER, small = 0, stat_cnt = 0;
-    const int stat_on = o->stat_win > 0 && planar_path(s, n, ids);
+    int status = ORC_MAXITER, small = 0;
     if (outside_guard(s, X, n)) return ORC_DIVERGED;
     for (int it = 1; it <= o->max_iter; it++) {
         *iters = it;
@@ -503,13 +491,6 @@ int orc_solve_one(const orc_scene *s, const double rx[3], int n, const int32_t *
         }
         for (int i = 0; i < nu; i++) mg[i] = -g[i];
         chol_solve(M, nu, mg, dx);
-        if (stat_on) {
-            /* decrease of the damped model at its minimiser, -g^T dx */
-            double pred = 0;
-            for (int i = 0; i < nu; i++) pred -= g[i] * dx[i];
-            stat_cnt = (pred < o->stat_tol * C) ? stat_cnt + 1 : 0;
-            if (stat_cnt >= o->stat_win) { small = 1; break; }
-        }
         for (int i = 0; i < nu; i++) Xt[i] = X[i] + dx[i];
         int is_small = inf_norm(dx, nu) <= o->tol_step * (1.0 + inf_norm(X, nu));
         /* a trial point outside the guard box counts as a cost increase */
@@ -728,8 +709,7 @@ int orc_solve_one_param(const orc_scene *s, const double rx[3], int n, const int
     double R[MAXR], J[MAXR * MAXU], A[MAXU * MAXU], g[MAXU], M[MAXU * MAXU], du[MAXU], mg[MAXU];
     double Ut[MAXU], Rt[MAXR], Xt[MAXU];
     double lam = 0, C = INFINITY, C_ref = INFINITY, rinf = INFINITY;
-    int status = ORC_MAXITER, small = 0, stat_cnt = 0;
-    const int stat_on = o->stat_win > 0 && planar_path(s, n, ids);
+    int status = ORC_MAXITER, small = 0;
     for (int k = 0, off = 0; k < n; k++) {
         const double *rec;
         int t = prim_type(s, ids[k], &rec);
@@ -763,12 +743,6 @@ int orc_solve_one_param(const orc_scene *s, const double rx[3], int n, const int
         }
         for (int i = 0; i < nu; i++) mg[i] = -g[i];
         chol_solve(M, nu, mg, du);
-        if (stat_on) {
-            double pred = 0;
-            for (int i = 0; i < nu; i++) pred -= g[i] * du[i];
-            stat_cnt = (pred < o->stat_tol * C) ? stat_cnt + 1 : 0;
-            if (stat_cnt >= o->stat_win) { small = 1; break; }
-        }
         for (int i = 0; i < nu; i++) Ut[i] = U[i] + du[i];
         int is_small = inf_norm(du, nu) <= o->tol_step * (1.0 + inf_norm(U, nu));
         int mt = orc_param_residual(s, rx, n, ids, Ut, Rt, NULL, Xt);

@@ -26,10 +26,10 @@
  *    the two coordinates across the line; a circle: distance to its plane
  *    and (|X-c|^2 - R^2)/(2R));
  *  - the minimiser is Levenberg-Marquardt with Marquardt's diagonal scaling
- *    (the paper only says "gradient descent"); a descent ends at a root, at
- *    a plateau of the cost, or - on paths of planes and straight edges,
- *    which converge from any start (Sec. III-B) - when the damped model
- *    predicts a decrease below 2% of the cost four iterations in a row;
+ *    (the paper only says "gradient descent"); a descent ends at a root
+ *    (small step or small residual), at a plateau of the cost (every 10
+ *    iterations the cost must fall below 0.999 of its value 10 iterations
+ *    before), when the damping blows up, or at the iteration cap;
  *  - initial points: each object's projection of the point k/(n+1) of the
  *    way along the TX -> RX segment, or of a point drawn uniformly in the
  *    scene box (the random start of Alg. 1, SplitMix64 counter draws), or
@@ -78,10 +78,6 @@ typedef struct {
     double  lambda0;       /* initial damping relative to max diag(J^T J) */
     int32_t plateau_win;   /* every plateau_win iterations the cost must have */
     double  plateau_frac;  /* dropped below plateau_frac x its value before   */
-    double  stat_tol;      /* paths of planes and straight edges only: the    */
-    int32_t stat_win;      /* descent has stalled when the damped model's     */
-                           /* decrease -g^T dx is below stat_tol x the cost    */
-                           /* stat_win iterations in a row (0: off)           */
 } orc_lm_opts;
 
 /* Residual rows (and, if J != NULL, the dense Jacobian, row-major
