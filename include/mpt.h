@@ -209,14 +209,14 @@ typedef struct {
                               implicit).  Paraboloids must be of revolution
                               (A = k (I - ax ax^T), b = -ax, c = 0); another
                               quadric makes its paths MPT_PATH_BAD_INPUT.
-                              MPT_FORM_AUTO: parametric when the scene has
-                              paraboloids or circles (and every quadric
-                              allows it); on planes and straight edges the
-                              tuner's faster form, else implicit (their
-                              roots are unique: the forms accept the same
-                              paths but for about 1 in 10^5 hard chains the
-                              parametric form reaches and the implicit
-                              one does not)                                 */
+                              MPT_FORM_AUTO: parametric when every object
+                              of the scene has a parametric expression
+                              (every quadric is a paraboloid of
+                              revolution), else implicit; a property of the
+                              scene, never a timing choice (the forms can
+                              accept different paths: about 1 in 10^5 hard
+                              chains of planes and straight edges ends at a
+                              non-root point in one form and not the other) */
     double stat_tol;       /* 0.02  paths of planes and straight edges only
                               (their root is unique and reached from any
                               start, Sec. III-B): the descent has stalled,
@@ -228,11 +228,13 @@ typedef struct {
                               many of its 64 lanes are idle (1..64): each
                               refill stalls the wave on the new paths' loads */
     int32_t max_iter32_planar; /* 80  FP32 stage cap for paths of planes and
-                              straight edges (1..max_iter32): their descents
-                              converge in a few iterations from any start, so
-                              one still running after this many has stalled;
-                              it ends as MAXIT and is polished when its
-                              residual is below polish_gate                  */
+                              straight edges (1..max_iter32, else
+                              MPT_E_INVALID_ARG): their descents converge in
+                              a few iterations from any start, so one still
+                              running after this many is slow; it is
+                              polished when its residual is below
+                              polish_gate, else re-solved by the FP64
+                              fallback from its FP32 end point               */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 
@@ -269,11 +271,12 @@ mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_
  * Autotuner of the launch choices that do not change results (the schedule -
  * one mixed-order launch or concurrent per-order launches -, the block size,
  * the grid divisor of the per-order launches and the straggler threshold
- * `spill`, and on scenes of planes and straight edges the form): runs whole
- * solves of the given batch back to back with each candidate (writing the
- * outputs; the median of three groups of runs), keeps the fastest and uses
- * it for later solves of the same precision, form option, size class
- * (floor log2 n) and scene size.  With the
+ * `spill`) in the form the options resolve to: runs whole solves of the
+ * given batch back to back with each candidate (writing the outputs; the
+ * median of three groups of runs), keeps the fastest and uses it for later
+ * solves of the same precision, form, size class (floor log2 n) and scene
+ * (a hash of the uploaded records, TX and box).  best_form receives the
+ * form.  With the
  * environment variable MPT_AUTOTUNE_CACHE set to a file path, choices are
  * loaded from and saved to that file (one line per entry).  Synchronises.
  * best_* (host, may be NULL) receive the choice and its time per solve in

@@ -18,11 +18,16 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
 SOURCES = ["mpt_solve.hip", "mpt_api.hip", "mpt_mlp.hip", "mpt_cand.hip", "mpt_valid.hip"]
+# The solver fuses a multiply and an add only inside one source expression
+# (fp-contract=on), never across statements: whether two operations fuse
+# then depends on the source alone, not on the kernel a path function is
+# inlined into, so every launch schedule runs the same per-path arithmetic.
+EXTRA = {"mpt_solve.hip": ["-ffp-contract=on"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -39,6 +39,7 @@ struct mpt_ctx {
     bool has_scene = false;
     bool curved = false;     // the scene has paraboloids or circles
     bool param_ok = true;    // every quadric is a paraboloid of revolution
+    uint64_t scene_hash = 0; // FNV-1a of the uploaded records and TX: the tuning key
     // workspace: counters | perm | polish lists | fallback lists
     int *ws = nullptr;
     size_t ws_cap = 0;  // solves
@@ -58,8 +59,9 @@ struct mpt_ctx {
     int32_t last_launch[5] = {};  // sched, block, gdiv, spill, form of the last solve
     bool launched = false;
     MlpState *mlp = nullptr;
-    // autotuned launch choices: key -> (sched, block)
-    struct Tune { int prec, form, nbucket, n_all, sched, block, gdiv, spill, used; float ms; };
+    // autotuned launch choices: key (precision, form run, size class, scene
+    // hash) -> (schedule, block, grid divisor, straggler threshold)
+    struct Tune { int prec, form, nbucket; uint64_t scene; int sched, block, gdiv, spill; float ms; };
     std::vector<Tune> tune;
     bool tune_loaded = false;
     // captured graph of the last solve (replayed while the key matches)
@@ -299,6 +301,20 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->s = s;
     c->has_scene = true;
+    // FNV-1a over the counts, TX, box and records: launch choices tuned on
+    // one scene are kept apart from another's
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&h](const void *p, size_t bytes) {
+        const unsigned char *q = (const unsigned char *)p;
+        for (size_t i = 0; i < bytes; i++) h = (h ^ q[i]) * 0x100000001b3ull;
+    };
+    const int32_t counts[4] = {np, nl, nq, nc};
+    mix(counts, sizeof counts);
+    mix(d->tx, 3 * sizeof(double));
+    mix(d->aabb_lo, 3 * sizeof(double));
+    mix(d->aabb_hi, 3 * sizeof(double));
+    mix(host.data(), raw_n * sizeof(double));
+    c->scene_hash = h;
     c->curved = (nq + nc) > 0;
     c->param_ok = true;
     for (int i = 0; i < nq; i++) {
@@ -410,11 +426,14 @@ static void tune_load(mpt_ctx *c)
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    // one entry per line: prec form nbucket n_all sched block gdiv spill used-form ms
+    // one entry per line: prec form nbucket scene-hash sched block gdiv spill ms
     mpt_ctx::Tune t;
-    while (fscanf(f, "%d %d %d %d %d %d %d %d %d %f", &t.prec, &t.form, &t.nbucket, &t.n_all, &t.sched, &t.block,
-                  &t.gdiv, &t.spill, &t.used, &t.ms) == 10)
+    unsigned long long h = 0;
+    while (fscanf(f, "%d %d %d %llx %d %d %d %d %f", &t.prec, &t.form, &t.nbucket, &h, &t.sched, &t.block, &t.gdiv,
+                  &t.spill, &t.ms) == 9) {
+        t.scene = (uint64_t)h;
         c->tune.push_back(t);
+    }
     fclose(f);
 }
 
@@ -425,32 +444,37 @@ static void tune_save(mpt_ctx *c)
     FILE *f = fopen(path, "w");
     if (!f) return;
     for (auto &t : c->tune)
-        fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f\n", t.prec, t.form, t.nbucket, t.n_all, t.sched, t.block, t.gdiv,
-                t.spill, t.used, t.ms);
+        fprintf(f, "%d %d %d %llx %d %d %d %d %.6f\n", t.prec, t.form, t.nbucket, (unsigned long long)t.scene, t.sched,
+                t.block, t.gdiv, t.spill, t.ms);
     fclose(f);
 }
 
-// The form a solve runs in: MPT_FORM_AUTO takes the parametric form on
-// scenes with curved objects (when every quadric allows it) and the implicit
-// one otherwise, unless the tuner chose for this batch.
+// The form a solve runs in: MPT_FORM_AUTO takes the parametric form
+// whenever every object of the scene has a parametric expression (every
+// quadric is a paraboloid of revolution), else the implicit one.  It is a
+// property of the scene, never a timing choice.
 static int auto_form(const mpt_ctx *c)
 {
-    return (c->curved && c->param_ok) ? MPT_FORM_PARAMETRIC : MPT_FORM_IMPLICIT;
+    return c->param_ok ? MPT_FORM_PARAMETRIC : MPT_FORM_IMPLICIT;
+}
+
+static int resolved_form(const mpt_ctx *c, const mpt_solve_opts *o)
+{
+    return (o->form == MPT_FORM_AUTO) ? auto_form(c) : o->form;
 }
 
 static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv, int &spill,
                    int &form)
 {
     default_choice(o->precision, sched, block, gdiv, spill);
-    form = (o->form == MPT_FORM_AUTO) ? auto_form(c) : o->form;
+    form = resolved_form(c, o);
     tune_load(c);
     for (auto &t : c->tune)
-        if (t.prec == o->precision && t.form == o->form && t.nbucket == nbucket(n) && t.n_all == c->s.n_all) {
+        if (t.prec == o->precision && t.form == form && t.nbucket == nbucket(n) && t.scene == c->scene_hash) {
             sched = t.sched;
             block = t.block;
             gdiv = t.gdiv;
             spill = t.spill;
-            if (o->form == MPT_FORM_AUTO) form = t.used;
         }
     if (o->sched != MPT_SCHED_AUTO) sched = o->sched;
     if (o->block) block = o->block;
@@ -473,9 +497,11 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
     if (opts->init == MPT_INIT_USER && b->n > 0 && !b->x0) return fail(c, MPT_E_INVALID_ARG, "user start without x0");
     if ((opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL) && !mlp_ready(c->mlp))
         return fail(c, MPT_E_NO_MODEL, "learned start requested but no network initialised");
-    if (opts->max_iter < 0 || opts->max_iter32 < 0 || opts->max_iter32_planar < 0 || opts->max_iter_fb < 0 ||
-        opts->polish_steps < 0 || opts->plateau_win < 0)
+    if (opts->max_iter < 0 || opts->max_iter32 < 0 || opts->max_iter_fb < 0 || opts->polish_steps < 0 ||
+        opts->plateau_win < 0)
         return fail(c, MPT_E_INVALID_ARG, "negative iteration option");
+    if (opts->max_iter32_planar < 1 || opts->max_iter32_planar > opts->max_iter32)
+        return fail(c, MPT_E_INVALID_ARG, "max_iter32_planar must be 1..max_iter32");
     if (opts->block != 0 && (opts->block % 64 != 0 || opts->block > 256 || opts->block < 64))
         return fail(c, MPT_E_INVALID_ARG, "block must be 64, 128, 192 or 256");
     if (opts->sched < MPT_SCHED_PER_ORDER || opts->sched > MPT_SCHED_SPLIT)
@@ -499,20 +525,34 @@ static mpt_status size_buffers(mpt_ctx *c, int64_t n, bool learned)
     return MPT_OK;
 }
 
+// Workspace of one solve: counters and lists (int32), parked straggler
+// state and network start points (FP64; null when unused).
+struct Work {
+    int *ws;
+    double *spf, *x0l;
+};
+
 // Enqueue the whole solve on stream s (no host synchronisation).  With
 // `timed`, HIP events mark the stage boundaries (not inside graph capture).
+// The workspace is the context's own (sized here) unless `w` brings one.
 static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts,
                                 const mpt_solve_out *out, hipStream_t s, bool timed, int sched, int block,
-                                int gdiv, int spill, int form_used)
+                                int gdiv, int spill, int form_used, const Work *w = nullptr)
 {
     BatchDev bd;
     mpt_status st = batch_dev(c, b, bd);
     if (st) return st;
     const int64_t n = b->n;
     const bool learned = opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL;
-    if ((st = size_buffers(c, n, learned))) return st;
+    Work own{nullptr, nullptr, nullptr};
+    if (!w) {
+        if ((st = size_buffers(c, n, learned))) return st;
+        own = Work{c->ws, c->spf, c->x0l};
+        w = &own;
+    }
+    if ((learned && !w->x0l) || (spill > 0 && !w->spf)) return fail(c, MPT_E_INVALID_ARG, "workspace too small");
     if (!timed) c->timed = c->kev_valid = false;  // no stale stage timings
-    int *ctr = c->ws;
+    int *ctr = w->ws;
     KParams kp{};
     kp.s = c->s;
     kp.b = bd;
@@ -520,7 +560,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.o.init = opts->init;
     kp.o.max_iter = opts->max_iter;
     kp.o.max_iter32 = opts->max_iter32;
-    kp.o.max_iter32_planar = opts->max_iter32_planar < opts->max_iter32 ? opts->max_iter32_planar : opts->max_iter32;
+    kp.o.max_iter32_planar = opts->max_iter32_planar;
     kp.o.max_iter_fb = opts->max_iter_fb;
     kp.o.polish_steps = opts->polish_steps;
     kp.o.fallback = opts->fallback;
@@ -537,7 +577,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.o.seed = opts->seed;
     kp.o.stat_tol = opts->stat_tol;
     kp.o.stat_win = opts->stat_win;
-    kp.x0_learned = c->x0l;
+    kp.x0_learned = w->x0l;
     kp.bin_cnt = ctr + 0;
     kp.head = ctr + 10;
     kp.pol_cnt = ctr + 20;
@@ -549,8 +589,8 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.refill = opts->refill > 1 ? (opts->refill < 64 ? opts->refill : 64) : 1;
     kp.spill_cnt = ctr + kSpillCounters;
     kp.spill_head = ctr + kSpillCounters + 5;
-    kp.spill_list = ctr + kCounters + 3 * n;
-    kp.spill_f = c->spf;
+    kp.spill_list = w->spf ? ctr + kCounters + 3 * n : nullptr;
+    kp.spill_f = w->spf;
 
     if (timed) hipEventRecord(c->ev[0], s);
     launch_zero(ctr, kCounters, s);
@@ -565,11 +605,11 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
             // them (the polish list is free until the FP32 pass) and predict
             int *rows = (int *)kp.pol_list, *count = ctr + 30;
             launch_curved_rows(bd, c->s, rows, count, s);
-            st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s, rows, count);
-            if (!st) launch_learned_choose(c->s, bd, rows, count, false, c->x0l, s);
+            st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s, rows, count);
+            if (!st) launch_learned_choose(c->s, bd, rows, count, false, w->x0l, s);
         } else {
-            st = mlp_predict_dev(c->mlp, c->s, bd, c->x0l, s);
-            if (!st) launch_learned_choose(c->s, bd, nullptr, nullptr, true, c->x0l, s);
+            st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s);
+            if (!st) launch_learned_choose(c->s, bd, nullptr, nullptr, true, w->x0l, s);
         }
         if (st) return fail(c, st, "network forward failed");
     }
@@ -710,14 +750,10 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     if (st) return st;
     hipSetDevice(c->device);
     tune_load(c);
-    // candidates: form (MPT_FORM_AUTO on planes and straight edges, whose
-    // unique roots make both forms accept the same paths but for rare hard
-    // chains) x schedule x block size x grid divisor (per-order only) x
-    // straggler threshold
-    std::vector<int> forms;
-    if (opts->form != MPT_FORM_AUTO) forms.push_back(opts->form);
-    else if (c->curved || !c->param_ok) forms.push_back(auto_form(c));
-    else forms = {MPT_FORM_IMPLICIT, MPT_FORM_PARAMETRIC};
+    // candidates: schedule x block size x grid divisor (per-order only) x
+    // straggler threshold, in the form the options resolve to (the form is
+    // never a timing choice: the forms can accept different paths)
+    std::vector<int> forms = {resolved_form(c, opts)};
     struct Cand { int sched, block, gdiv, spill, form; };
     std::vector<Cand> cands;
     for (int fm : forms) {
@@ -772,12 +808,11 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     if (st) return st;
     bool found = false;
     for (auto &t : c->tune)
-        if (t.prec == opts->precision && t.form == opts->form && t.nbucket == nbucket(b->n) && t.n_all == c->s.n_all)
-            t.sched = bc.sched, t.block = bc.block, t.gdiv = bc.gdiv, t.spill = bc.spill, t.used = bc.form,
-            t.ms = best, found = true;
+        if (t.prec == opts->precision && t.form == bc.form && t.nbucket == nbucket(b->n) && t.scene == c->scene_hash)
+            t.sched = bc.sched, t.block = bc.block, t.gdiv = bc.gdiv, t.spill = bc.spill, t.ms = best, found = true;
     if (!found)
-        c->tune.push_back({opts->precision, opts->form, nbucket(b->n), c->s.n_all, bc.sched, bc.block, bc.gdiv,
-                           bc.spill, bc.form, best});
+        c->tune.push_back({opts->precision, bc.form, nbucket(b->n), c->scene_hash, bc.sched, bc.block, bc.gdiv,
+                           bc.spill, best});
     tune_save(c);
     if (best_sched) *best_sched = bc.sched;
     if (best_block) *best_block = bc.block;

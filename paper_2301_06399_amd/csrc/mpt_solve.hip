@@ -965,14 +965,18 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                 if (MODE == MODE_FP32) {
                     // route: FP32 end points whose residual is below the gate
                     // look like roots and are polished in FP64; the others
-                    // are final (no path).  FP64 re-solves the path from the
-                    // straight-line start only on numerical trouble in FP32:
-                    // a degenerate iterate, or - decided by the polish - a
-                    // converged or stalled FP32 point that does not polish
+                    // are final (no path).  FP64 re-solves the path from its
+                    // FP32 end point on numerical trouble in FP32: a
+                    // degenerate iterate, a path of planes and straight
+                    // edges still far from a root at its iteration cap (such
+                    // descents reach their unique root quickly, so the cap
+                    // alone is no evidence that none exists), or - decided
+                    // by the polish - a converged or stalled FP32 point that
+                    // does not polish
                     const bool small_res = (double)L.rinf <= kp.o.polish_gate;
                     const bool to_polish = small_res && (st == ST_CONV || st == ST_MAXIT || st == ST_LOCALMIN ||
                                                          st == ST_STALL);
-                    const bool to_fb = (st == ST_DEGEN);
+                    const bool to_fb = (st == ST_DEGEN) || (st == ST_MAXIT && p.planar && !small_res);
                     if (to_polish) {
                         // listed for the polish after the LM passes (no
                         // atomic with a return value in the iteration loop)

@@ -300,6 +300,7 @@ class Context:
         self._check(rc, "mpt_solve_batch")
         return out
 
+
     def accept(self, dbatch: DeviceBatch, out: DeviceOut, tau_res=1e-9, min_seg=1e-6, sync=True):
         torch = self.torch
         n = dbatch.n

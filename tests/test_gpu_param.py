@@ -45,7 +45,10 @@ def test_param_planar_matches_oracle(ctx, prec):
         g = gpu_solve(ctx, sc, b, precision=prec, form=1)
         compare_planar(sc, b, g, orc_acc, orc)
         if prec == 0:
-            assert np.mean(g["status"] == orc["status"]) > 0.99
+            # the GPU-only stall test off: the same statuses as the oracle
+            g0 = gpu_solve(ctx, sc, b, precision=prec, form=1, stat_win=0)
+            compare_planar(sc, b, g0, orc_acc, orc)
+            assert np.mean(g0["status"] == orc["status"]) > 0.99
 
 
 @pytest.mark.parametrize("prec", [0, 1])
