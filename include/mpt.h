@@ -268,6 +268,29 @@ mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_
                            const mpt_solve_out *out);
 
 /*
+ * mpt_solve_batch without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * mpt_solve_batch with spill = 0.  Its counters and lists live in a static
+ * device scratch array of the library, sized for at most
+ * MPT_NOALLOC_MAX_SOLVES solves (12.6 MB, held by every GPU the library
+ * runs on until the process ends); the counters are cleared by a fill
+ * kernel at the start of every call.  Every call on one GPU shares that
+ * scratch, so calls that overlap on one GPU (other contexts or streams)
+ * race: the caller serialises them.  It calls no hipMalloc, hipFree or
+ * other allocating routine and reads no tuning cache file (tuned choices
+ * already in the context are used).
+ * Errors: those of mpt_solve_batch; MPT_E_INVALID_ARG when n exceeds
+ * MPT_NOALLOC_MAX_SOLVES; MPT_E_UNSUPPORTED for the learned starts (their
+ * start points need the context's workspace) and for graph = 1 (graph
+ * instantiation allocates); MPT_E_DEVICE when the scratch's device address
+ * could not be found when the context was created.
+ */
+enum { MPT_NOALLOC_MAX_SOLVES = 1 << 20 };
+mpt_status mpt_solve_batch_noalloc(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_solve_opts *opts,
+                                   const mpt_solve_out *out);
+
+/*
  * Autotuner of the launch choices that do not change results (the schedule -
  * one mixed-order launch or concurrent per-order launches -, the block size,
  * the grid divisor of the per-order launches and the straggler threshold

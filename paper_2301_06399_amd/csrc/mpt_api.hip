@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/mpt.h"
 #include "mpt_internal.hpp"
@@ -49,6 +50,8 @@ struct mpt_ctx {
     size_t x0l_cap = 0;
     double *spf = nullptr;  // parked stragglers: damping, plateau reference, stall count [3][n]
     size_t spf_cap = 0;
+    int *scratch = nullptr;  // this device's copy of the allocation-free solve's scratch (device address)
+    std::string scratch_err;
     hipEvent_t ev[7] = {};
     hipStream_t aux[MPT_MAX_ORDER] = {};  // per-order launches run concurrently
     hipEvent_t fork = nullptr, join[MPT_MAX_ORDER] = {};
@@ -75,6 +78,19 @@ struct mpt_ctx {
 static const int kKeyCounters = 3 * 1364;
 static const int kSpillCounters = 32 + kKeyCounters;
 static const int kCounters = kSpillCounters + 16;
+
+// Scratch of the allocation-free solve (mpt_solve_batch_noalloc): the
+// counters and the perm / polish / fallback lists of at most
+// MPT_NOALLOC_MAX_SOLVES solves (12.6 MB).  Every GPU the library runs on
+// holds its own copy until the process ends, and every such call on that
+// GPU shares it.  In host code `scratch` names a host-side stand-in: its
+// device address comes from hipGetSymbolAddress, once per device, when a
+// context is created there (scratch_setup).
+static const size_t kScratchInts = (size_t)kCounters + 3 * (size_t)MPT_NOALLOC_MAX_SOLVES;
+static __device__ __align__(256) int scratch[kScratchInts];
+static const int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static int *g_scratch_dev[kMaxDevices];
 
 static mpt_status fail(mpt_ctx *c, mpt_status st, const char *fmt, ...)
 {
@@ -106,6 +122,28 @@ static mpt_status ensure(mpt_ctx *c, void **p, size_t *cap, size_t need, size_t 
     }
     *cap = need;
     return MPT_OK;
+}
+
+// The device address of this device's scratch, looked up once per device
+// with that device current; a failure is kept and reported by the
+// allocation-free solve (the other entry points do not use the scratch).
+static void scratch_setup(mpt_ctx *c)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device >= kMaxDevices) {
+        c->scratch_err = "device index beyond the scratch table";
+        return;
+    }
+    if (!g_scratch_dev[c->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            c->scratch_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+            return;
+        }
+        g_scratch_dev[c->device] = (int *)p;
+    }
+    c->scratch = g_scratch_dev[c->device];
 }
 
 extern "C" {
@@ -143,6 +181,7 @@ mpt_status mpt_create(int device, void *hip_stream, mpt_ctx **out)
     hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     for (int i = 0; i < MPT_MAX_ORDER; i++)
         for (int j = 0; j < 2; j++) hipEventCreate(&c->kev[i][j]);
+    scratch_setup(c);
     *out = c;
     return MPT_OK;
 }
@@ -464,11 +503,11 @@ static int resolved_form(const mpt_ctx *c, const mpt_solve_opts *o)
 }
 
 static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, int &block, int &gdiv, int &spill,
-                   int &form)
+                   int &form, bool load = true)
 {
     default_choice(o->precision, sched, block, gdiv, spill);
     form = resolved_form(c, o);
-    tune_load(c);
+    if (load) tune_load(c);
     for (auto &t : c->tune)
         if (t.prec == o->precision && t.form == form && t.nbucket == nbucket(n) && t.scene == c->scene_hash) {
             sched = t.sched;
@@ -739,6 +778,32 @@ mpt_status mpt_solve_batch(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_
     c->timed = c->kev_valid = false;  // a replay records no stage events
     HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     return MPT_OK;
+}
+
+mpt_status mpt_solve_batch_noalloc(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts,
+                                   const mpt_solve_out *out)
+{
+    if (!c) return MPT_E_INVALID_ARG;
+    mpt_status st = check_opts(c, b, opts, out);
+    if (st) return st;
+    if (!c->scratch) return fail(c, MPT_E_DEVICE, "no scratch on this device: %s", c->scratch_err.c_str());
+    if (b->n > MPT_NOALLOC_MAX_SOLVES)
+        return fail(c, MPT_E_INVALID_ARG, "%lld solves exceed the allocation-free limit of %d", (long long)b->n,
+                    (int)MPT_NOALLOC_MAX_SOLVES);
+    if (opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL)
+        return fail(c, MPT_E_UNSUPPORTED, "the learned start needs the context's workspace");
+    if (opts->graph) return fail(c, MPT_E_UNSUPPORTED, "graph mode instantiates a graph (allocates)");
+    hipSetDevice(c->device);
+    // the tuned choices already in memory (no cache file is read); no
+    // straggler launch, whose parked state needs the context's workspace
+    int sched, block, gdiv, spill, form;
+    choose(c, opts, b->n, sched, block, gdiv, spill, form, false);
+    spill = 0;
+    const int32_t chosen[5] = {sched, block, gdiv, spill, form};
+    memcpy(c->last_launch, chosen, sizeof chosen);
+    c->launched = true;
+    const Work w{c->scratch, nullptr, nullptr};
+    return enqueue_solve(c, b, opts, out, c->stream, c->timing, sched, block, gdiv, spill, form, &w);
 }
 
 mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out,

@@ -66,7 +66,8 @@ EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt
            "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings",
            "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
            "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused", "mpt_visible",
-           "mpt_visibility", "mpt_visibility_rx", "mpt_candidates", "mpt_last_launch", "mpt_set_timing"]
+           "mpt_visibility", "mpt_visibility_rx", "mpt_candidates", "mpt_last_launch", "mpt_set_timing",
+           "mpt_solve_batch_noalloc"]
 
 _lib = None
 
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     L.mpt_default_opts.argtypes = [C.POINTER(SolveOpts)]
     L.mpt_default_opts.restype = None
     L.mpt_solve_batch.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut)]
+    L.mpt_solve_batch_noalloc.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOpts), C.POINTER(SolveOut)]
     L.mpt_accept.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOut), C.c_double, C.c_double, vp, vp, vp,
                              C.POINTER(C.c_int64)]
     L.mpt_visible.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(SolveOut), vp, C.c_double, vp, vp,
@@ -300,6 +302,15 @@ class Context:
         self._check(rc, "mpt_solve_batch")
         return out
 
+    def solve_noalloc(self, dbatch: DeviceBatch, opts: SolveOpts, out: DeviceOut) -> DeviceOut:
+        """mpt_solve_batch_noalloc: the caller's outputs, the library's static
+        scratch, no allocation."""
+        bd, od = dbatch.desc(), out.desc()
+        self._enter()
+        rc = self.L.mpt_solve_batch_noalloc(self.h, C.byref(bd), C.byref(opts), C.byref(od))
+        self._leave()
+        self._check(rc, "mpt_solve_batch_noalloc")
+        return out
 
     def accept(self, dbatch: DeviceBatch, out: DeviceOut, tau_res=1e-9, min_seg=1e-6, sync=True):
         torch = self.torch
