@@ -6,17 +6,20 @@ One step = one pass of the whole hot path over one batch: order binning,
 fallback, FP64 acceptance test with ordered compaction.  Inputs are resident
 on the GPU before timing starts.  `value` = accepted paths per second.
 
-Default workload: the street canyon (50 boxes, 651 primitives, 4096
-receivers x 64 interaction lists of order 1-3 = 262,144 solves).
---config 1 / 3 / 5 select the room, the curved scene and the multi-
-diffraction stress workload; --config 4 is the learned-start evaluation (one
-network trained on 2 M solver outputs of the street-canyon and curved
-generators, timed on 1 M held-out problems).
+Default workload: the multi-diffraction stress workload (the street canyon
+plus 30 paraboloids; 16,384 receivers x 1024 lists of order 3-5 with at
+least two diffractions = 16,777,216 solves), the largest configuration, with
+the learned start trained on held-apart problems of the same scene and the
+timed steps replayed from a captured HIP graph.  --config 1 / 2 / 3 select
+the room, the street canyon and the curved scene; --config 4 is the
+learned-start evaluation (one network trained on 2 M solver outputs of the
+street-canyon and curved generators, timed on 1 M held-out problems).
 
-Also reported: the plain FP64 solver (P) and FP32+polish without the learned
-start (S) on the same workload, the roofline of the dominant kernel with its
-time measured by HIP events on the stream it runs on, and the FP64 CPU oracle
-timed on the same workload (or a bounded sample of it).
+Also reported: the plain FP64 solver (P, Pp) and FP32+polish without the
+learned start (S, Si) on the same workload, the roofline of the dominant
+kernel with its time measured by HIP events on the stream it runs on, and
+the FP64 CPU oracle timed on the same workload (or a bounded sample of it)
+on the host's cores and on one thread.
 """
 from __future__ import annotations
 
@@ -84,10 +87,11 @@ def algorithmic_flops(table, order, code, iters, kind):
     return tot
 
 
-def opts_for(mpt, v):
+def opts_for(mpt, v, graph=0):
     prec, start, form = VARIANTS[v]
     init = {"line": mpt.INIT_LINE, "learned": mpt.INIT_LEARNED, "learned_all": mpt.INIT_LEARNED_ALL}[start]
-    return mpt.default_opts(precision=mpt.FP32_POLISH64 if prec else mpt.FP64_PLAIN, init=init, form=form)
+    return mpt.default_opts(precision=mpt.FP32_POLISH64 if prec else mpt.FP64_PLAIN, init=init, form=form,
+                            graph=graph)
 
 
 class Runner:
@@ -110,12 +114,14 @@ class Runner:
                               mpt._ptr(self.idx), mpt._ptr(self.cnt), None)
         ctx._check(rc, "mpt_accept")
 
-    def run(self, v, steps, warmup, tune):
+    def run(self, v, steps, warmup, tune, graph=True):
         """Autotune (optional, untimed), then time `steps` steps after
-        `warmup`; stage and per-order durations from the library's events."""
+        `warmup` (replayed from a captured HIP graph with `graph`); stage and
+        per-order durations from the library's events of separate solves."""
         torch, ctx, mpt = self.torch, self.ctx, self.mpt
         o = opts_for(mpt, v)
         launch = ctx.autotune(self.db, o, self.out) if tune else None
+        o_step = opts_for(mpt, v, graph=1 if graph else 0)
         # the timed steps record no stage events; the stage times come from
         # separate timed solves below
         ctx.set_timing(False)
@@ -123,12 +129,12 @@ class Runner:
         t = time.perf_counter()
         w = 0
         while w < warmup or (time.perf_counter() - t < 0.3 and w < 1000):
-            self.step(o)
+            self.step(o_step)
             torch.cuda.synchronize()
             w += 1
         t = time.perf_counter()
         for _ in range(steps):
-            self.step(o)
+            self.step(o_step)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
         k = int(self.cnt.item())
@@ -150,7 +156,7 @@ class Runner:
         torch.cuda.synchronize()
         launch = dict(launch or {}, **ctx.last_launch())
         r = self.out.numpy()
-        res = {"ms_per_step": dt * 1e3, "accepted": k, "paths_per_s": k / dt, "stage_ms": st,
+        res = {"ms_per_step": dt * 1e3, "graph": bool(graph), "accepted": k, "paths_per_s": k / dt, "stage_ms": st,
                "fallback": int((r["status"] & 0x80).astype(bool).sum()),
                "iters_mean": float(r["iters"].mean()), "lm_iters_mean": float(r["stage"][0].mean()),
                "polished": int((r["stage"][1] > 0).sum()), "launch": launch}
@@ -160,6 +166,19 @@ class Runner:
 
     def flags(self):
         return self.acc[:self.batch.n].cpu().numpy()
+
+    def ctx_form_auto_is_param(self):
+        """Whether every quadric of the scene is a paraboloid of revolution
+        (then the automatic form is the parametric one)."""
+        q = self.scene.quadrics
+        for r in q:
+            A = np.array([[r[3], r[4], r[5]], [r[4], r[6], r[7]], [r[5], r[7], r[8]]])
+            ax = r[13:16]
+            kap = 0.5 * np.trace(A)
+            if not (kap > 0 and np.abs(A - kap * (np.eye(3) - np.outer(ax, ax))).max() <= 1e-9 * (1 + kap)
+                    and np.abs(r[9:12] + ax).max() <= 1e-9 * (1 + kap) and abs(r[12]) <= 1e-9 * (1 + kap)):
+                return False
+        return True
 
 
 def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0, sched=None):
@@ -222,11 +241,16 @@ def used_form(form, launch, scene):
 
 
 def ncores():
+    """The host cores this process may use: its CPU affinity, or the thread
+    count the host allots it (OMP_NUM_THREADS) when that is smaller."""
     try:
         c = len(os.sched_getaffinity(0))
     except AttributeError:
         c = os.cpu_count() or 1
-    return min(c, 16)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        c = min(c, int(env))
+    return c
 
 
 def oracle_run(O, scene, batch, cores, budget_s, max_n, form="implicit"):
@@ -247,6 +271,21 @@ def oracle_run(O, scene, batch, cores, budget_s, max_n, form="implicit"):
             orc, oacc = o_, a_
         reps += 1
     return {"samp": samp, "sb": sb, "orc": orc, "oacc": oacc, "reps": reps, "t": t_cpu, "acc": acc_cpu, "m": m}
+
+
+def oracle_single_thread(O, scene, sb, budget_s, form):
+    """The oracle on one thread over the leading part of the sample, grown
+    until a pass takes about budget_s seconds."""
+    m = min(sb.n, 4096)
+    while True:
+        part = sb.subset(np.arange(m))
+        t = time.perf_counter()
+        o_ = O.solve_batch(scene, part, nthreads=1, form=form)
+        a_ = O.accept_batch(scene, part, o_["x"], o_["status"], nthreads=1)
+        dt = time.perf_counter() - t
+        if dt >= 0.5 * budget_s or m >= sb.n:
+            return {"value": int(a_.sum()) / dt, "solves_per_s": m / dt, "solves": m, "s": dt}
+        m = min(sb.n, int(m * max(2.0, budget_s / max(dt, 1e-3))))
 
 
 def parity(O, scene, run, r, gacc):
@@ -298,13 +337,19 @@ def parity(O, scene, run, r, gacc):
     over = int((np.array(errs) > 1e-6).sum()) if errs else 0
     errs = np.array(errs) if errs else np.zeros(1)
     mism = np.where(flat & (gacc != oacc))[0]
+    oracle_only = int(((gacc == 0) & (oacc == 1)).sum())
+    # misses: roots the oracle's straight-line run found and the GPU did not
+    # accept, GPU roots the oracle could not confirm (curved or planar), and
+    # points beyond the bar
+    misses = oracle_only + unverified + (len(planar_gpu_only) - planar_confirmed) + over
     return {"sample": int(len(samp)), "gpu_accepted": n_gpu, "accepted_within_bar": n_ok,
+            "misses": int(misses), "recall": n_ok / max(1, n_ok + oracle_only),
             "over_1e-6_m": over,
             "flag_mismatches_planar": int(len(mism)),
             "planar_mismatch_solves": [int(samp[i]) for i in mism[:8]],
             "planar_gpu_only_confirmed_by_oracle": planar_confirmed,
             "gpu_only": int(((gacc == 1) & (oacc == 0)).sum()),
-            "oracle_only": int(((gacc == 0) & (oacc == 1)).sum()),
+            "oracle_only": oracle_only,
             "curved_other_root_verified": other_root, "curved_unverified": unverified,
             "point_err_m": {"max": float(errs.max()), "p50": float(np.percentile(errs, 50)),
                             "p99": float(np.percentile(errs, 99))}}
@@ -372,12 +417,15 @@ def main_single(args, torch, mpt, W):
         del src, dst
 
     run = Runner(torch, mpt, ctx, scene, batch)
-    variants = [variant] if args.only_main else [variant] + [x for x in ("S", "Si", "Sp", "P", "Pp") if x != variant]
+    # S runs in the parametric form whenever the scene allows it, so Sp is
+    # the same run; it is listed only for scenes that need the implicit form
+    others = ("S", "Si", "P", "Pp") if run.ctx_form_auto_is_param() else ("S", "Sp", "P", "Pp")
+    variants = [variant] if args.only_main else [variant] + [x for x in others if x != variant]
     results, outs, flags = {}, {}, {}
     for v in variants:
         steps = args.steps if v == variant else max(5, args.steps // 4)
         warm = args.warmup if v == variant else 1
-        results[v], outs[v] = run.run(v, steps, warm, tune=not args.no_autotune)
+        results[v], outs[v] = run.run(v, steps, warm, tune=not args.no_autotune, graph=not args.no_graph)
         flags[v] = run.flags()
     main_r, r = results[variant], outs[variant]
     # physical validation of the headline variant's accepted paths (after
@@ -406,10 +454,13 @@ def main_single(args, torch, mpt, W):
         fname = "param" if form else "implicit"
         orun = oracle_run(O, scene, batch, cores, 10.0, args.cpu_sample or 2_000_000, fname)
         what = "the whole workload" if orun["m"] == n else f"a seeded uniform sample of the {n} solves"
+        one = oracle_single_thread(O, scene, orun["sb"], 6.0, fname)
         cpu = {"value": orun["acc"] / orun["t"], "unit": "accepted paths/s", "cores": cores, "kind": "oracle",
                "sample": f"{what} ({orun['m']} solves), {fname} form, solve + accept, {orun['reps']} passes, "
-                         f"{orun['t']:.1f} s",
-               "solves_per_s": orun["reps"] * orun["m"] / orun["t"]}
+                         f"{orun['t']:.1f} s on {cores} threads; one thread: the first {one['solves']} solves "
+                         f"of it, {one['s']:.1f} s",
+               "solves_per_s": orun["reps"] * orun["m"] / orun["t"],
+               "single_thread": {"value": one["value"], "solves_per_s": one["solves_per_s"]}}
         par = parity(O, scene, orun, r, flags[variant])
         ovis = O.visible_batch(scene, batch, r["x"], flags[variant], nthreads=cores)
         validation["oracle_flag_mismatches"] = int((ovis != vis.cpu().numpy()).sum())
@@ -590,13 +641,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--n-rx", type=int, default=0, help="receivers (0: the configuration's own)")
     ap.add_argument("--variant", default="auto", choices=["auto", "L", "A", "S", "Si", "Sp", "P", "Pp"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="largest oracle sample (0: 2,000,000 solves)")
     ap.add_argument("--train-steps", type=int, default=0, help="network training steps before timing")
     ap.add_argument("--only-main", action="store_true", help="time only the headline variant")
+    ap.add_argument("--no-graph", action="store_true", help="launch the timed steps directly (no HIP graph)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the tuner: launch choices from MPT_AUTOTUNE_CACHE, else the defaults")
     ap.add_argument("--alg1", action="store_true",

@@ -62,6 +62,13 @@ enum {
                                 (TX or RX, or a plane or straight edge exactly
                                 parallel to it): the law returns a ray to its
                                 own side, so no root exists                     */
+    MPT_PATH_OUTSIDE = 7,    /* FP32 stage only: the FP32 end point is a root of
+                                the infinite objects (residual below the polish
+                                gate) but some point lies outside its object's
+                                finite extent by more than extent_skip + 100
+                                |R|_inf metres; the FP64 polish and fallback
+                                stay next to it, so it is not polished and is
+                                never accepted (x holds the FP32 end point)    */
     MPT_PATH_FALLBACK = 0x80
 };
 
@@ -235,6 +242,15 @@ typedef struct {
                               polished when its residual is below
                               polish_gate, else re-solved by the FP64
                               fallback from its FP32 end point               */
+    double extent_skip;    /* 0.05 FP32 end points farther than this (plus
+                              100 |R|_inf) outside a finite extent end as
+                              MPT_PATH_OUTSIDE without the FP64 polish (the
+                              acceptance test would reject them); 0: off     */
+    double learned_gain;   /* 1.0  the learned starts: the network's points
+                              (projected onto the objects) replace the
+                              straight-line start only where their FP64 cost
+                              is below learned_gain x the straight-line
+                              start's cost (the solver judges the network) */
 } mpt_solve_opts;
 void mpt_default_opts(mpt_solve_opts *opts);
 
@@ -419,6 +435,13 @@ mpt_status mpt_mlp_train_step(mpt_ctx *ctx, const mpt_batch_desc *batch, const d
 mpt_status mpt_mlp_grad(mpt_ctx *ctx, const mpt_batch_desc *batch, const double *target_x,
                         const uint8_t *use, const int32_t *rows, int32_t n_rows, float *d_loss,
                         float *d_grad);
+/* mpt_mlp_grad with the network run in FP32 throughout (FP32 master
+ * weights, FP32 features and activations, FP32 vector-ALU products) instead
+ * of BF16 on the matrix cores: a check of the backward pass without BF16
+ * rounding.  Same arguments, layout and errors. */
+mpt_status mpt_mlp_grad_fp32(mpt_ctx *ctx, const mpt_batch_desc *batch, const double *target_x,
+                             const uint8_t *use, const int32_t *rows, int32_t n_rows, float *d_loss,
+                             float *d_grad);
 /* The 96 input features of every solve, FP32 [n][96] device (before the
  * BF16 rounding the network applies). */
 mpt_status mpt_mlp_features(mpt_ctx *ctx, const mpt_batch_desc *batch, float *d_feat);

@@ -403,6 +403,8 @@ void mpt_default_opts(mpt_solve_opts *o)
     o->stat_tol = 0.02;
     o->stat_win = 4;
     o->refill = 16;
+    o->extent_skip = 0.05;
+    o->learned_gain = 1.0;
 }
 
 static mpt_status batch_dev(mpt_ctx *c, const mpt_batch_desc *b, BatchDev &bd)
@@ -548,6 +550,10 @@ static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solv
     if (opts->grid < 0) return fail(c, MPT_E_INVALID_ARG, "negative grid");
     if (opts->spill < -1 || opts->spill > 64) return fail(c, MPT_E_INVALID_ARG, "spill must be -1..64");
     if (opts->stat_win < 0 || !(opts->stat_tol >= 0.0)) return fail(c, MPT_E_INVALID_ARG, "bad stall test options");
+    if (!(opts->extent_skip >= 0.0) || !isfinite(opts->extent_skip))
+        return fail(c, MPT_E_INVALID_ARG, "extent_skip must be finite and >= 0");
+    if (!(opts->learned_gain > 0.0) || !isfinite(opts->learned_gain))
+        return fail(c, MPT_E_INVALID_ARG, "learned_gain must be finite and > 0");
     if (opts->form != MPT_FORM_IMPLICIT && opts->form != MPT_FORM_PARAMETRIC && opts->form != MPT_FORM_AUTO)
         return fail(c, MPT_E_UNSUPPORTED, "form %d", opts->form);
     return MPT_OK;
@@ -616,6 +622,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.o.seed = opts->seed;
     kp.o.stat_tol = opts->stat_tol;
     kp.o.stat_win = opts->stat_win;
+    kp.o.extent_skip = opts->extent_skip;
     kp.x0_learned = w->x0l;
     kp.bin_cnt = ctr + 0;
     kp.head = ctr + 10;
@@ -645,10 +652,10 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
             int *rows = (int *)kp.pol_list, *count = ctr + 30;
             launch_curved_rows(bd, c->s, rows, count, s);
             st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s, rows, count);
-            if (!st) launch_learned_choose(c->s, bd, rows, count, false, w->x0l, s);
+            if (!st) launch_learned_choose(c->s, bd, rows, count, false, w->x0l, opts->learned_gain, s);
         } else {
             st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s);
-            if (!st) launch_learned_choose(c->s, bd, nullptr, nullptr, true, w->x0l, s);
+            if (!st) launch_learned_choose(c->s, bd, nullptr, nullptr, true, w->x0l, opts->learned_gain, s);
         }
         if (st) return fail(c, st, "network forward failed");
     }
@@ -1111,8 +1118,8 @@ mpt_status mpt_mlp_train_step(mpt_ctx *c, const mpt_batch_desc *b, const double 
     return st ? fail(c, st, "training step failed") : MPT_OK;
 }
 
-mpt_status mpt_mlp_grad(mpt_ctx *c, const mpt_batch_desc *b, const double *target_x, const uint8_t *use,
-                        const int32_t *rows, int32_t n_rows, float *d_loss, float *d_grad)
+static mpt_status mlp_grad_common(mpt_ctx *c, const mpt_batch_desc *b, const double *target_x, const uint8_t *use,
+                                  const int32_t *rows, int32_t n_rows, float *d_loss, float *d_grad, bool fp32)
 {
     if (!c) return MPT_E_INVALID_ARG;
     if (!c->has_scene) return fail(c, MPT_E_NO_SCENE, "no scene uploaded");
@@ -1124,8 +1131,21 @@ mpt_status mpt_mlp_grad(mpt_ctx *c, const mpt_batch_desc *b, const double *targe
     const int nr = rows ? n_rows : (int)b->n;
     if (nr <= 0 || (rows && (int64_t)n_rows > b->n)) return fail(c, MPT_E_INVALID_ARG, "bad row count");
     hipSetDevice(c->device);
-    st = mlp_grad_dev(c->mlp, c->s, bd, rows, nr, target_x, use, d_loss, d_grad, c->stream);
+    st = fp32 ? mlp_grad_f32_dev(c->mlp, c->s, bd, rows, nr, target_x, use, d_loss, d_grad, c->stream)
+              : mlp_grad_dev(c->mlp, c->s, bd, rows, nr, target_x, use, d_loss, d_grad, c->stream);
     return st ? fail(c, st, "gradient failed") : MPT_OK;
+}
+
+mpt_status mpt_mlp_grad(mpt_ctx *c, const mpt_batch_desc *b, const double *target_x, const uint8_t *use,
+                        const int32_t *rows, int32_t n_rows, float *d_loss, float *d_grad)
+{
+    return mlp_grad_common(c, b, target_x, use, rows, n_rows, d_loss, d_grad, false);
+}
+
+mpt_status mpt_mlp_grad_fp32(mpt_ctx *c, const mpt_batch_desc *b, const double *target_x, const uint8_t *use,
+                             const int32_t *rows, int32_t n_rows, float *d_loss, float *d_grad)
+{
+    return mlp_grad_common(c, b, target_x, use, rows, n_rows, d_loss, d_grad, true);
 }
 
 mpt_status mpt_mlp_features(mpt_ctx *c, const mpt_batch_desc *b, float *d_feat)

@@ -20,7 +20,7 @@ constexpr int kMaxN = 5;
 
 enum : int { TP = 0, TL = 1, TQ = 2, TC = 3 };
 enum : int { ST_CONV = 0, ST_MAXIT = 1, ST_STALL = 2, ST_DIVERGED = 3, ST_DEGEN = 4,
-             ST_BAD = 5, ST_LOCALMIN = 6, ST_PARKED = 250, ST_RUNNING = 255 };
+             ST_BAD = 5, ST_LOCALMIN = 6, ST_OUTSIDE = 7, ST_PARKED = 250, ST_RUNNING = 255 };
 
 // Packed record layout (kRec wide), written by the scene pack kernel:
 //  plane   : n[0..2] d[3] o[4..6] eu[7..9] ev[10..12]

@@ -54,6 +54,7 @@ struct OptsDev {
     uint64_t seed;
     double stat_tol;
     int stat_win;
+    double extent_skip;  // FP32 end points this far (m) outside a finite extent skip the polish (<= 0: off)
 };
 
 // Everything a solver kernel needs, passed by value.
@@ -90,7 +91,7 @@ void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const 
 const void *polish_kernel();
 void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st);
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
-                           double *x0l, hipStream_t st);
+                           double *x0l, double gain, hipStream_t st);
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
 void launch_polish_list(const KParams &kp, hipStream_t st);
 void launch_samples(const SceneDev &s, int k, double *samp, int *cnt, hipStream_t st);

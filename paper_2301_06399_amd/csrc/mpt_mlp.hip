@@ -4,7 +4,7 @@
 //
 //   features (96) -> 256 -> 256 -> 256 -> 15, GELU (erf form) after the
 //   hidden layers; BF16 weights and activations, FP32 accumulation on the
-//   matrix cores (v_mfma_f32_32x32x8bf16_1k), FP32 master weights + Adam.
+//   matrix cores (v_mfma_f32_32x32x16_bf16), FP32 master weights + Adam.
 //
 // Kernels: k_features (per path), k_gemm (LDS-tiled MFMA GEMM with bias /
 // GELU / GELU' epilogues and split-K partials), k_reduce_splits, k_colsum
@@ -153,8 +153,8 @@ struct Epi {
     int ldc;
 };
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 constexpr int GT = 64, GK = 32, GPAD = 8;
 
@@ -195,16 +195,12 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const bf16 *_
         }
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < GK; ks += 8) {
-            // A(i,k): lane = i + 32 (k / 4), element k % 4; B(k,j): lane = j + 32 (k / 4)
-            const int kk = ks + 4 * (lane >> 5);
-            short4_t a, bb;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                a[q] = (short)As[wm + (lane & 31)][kk + q];
-                bb[q] = (short)Bs[wn + (lane & 31)][kk + q];
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
+        for (int ks = 0; ks < GK; ks += 16) {
+            // A(i,k): lane = i + 32 (k / 8), element k % 8; B(k,j): lane = j + 32 (k / 8)
+            const int kk = ks + 8 * (lane >> 5);
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(&As[wm + (lane & 31)][kk]);
+            const bf16x8_t bb = *reinterpret_cast<const bf16x8_t *>(&Bs[wn + (lane & 31)][kk]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
         }
         __syncthreads();
     }
@@ -247,6 +243,82 @@ __global__ void k_colsum(const bf16 *__restrict__ X, int M, int N, int ld, float
     const int col = blockIdx.x;
     float s = 0.0f;
     for (int r = threadIdx.x; r < M; r += blockDim.x) s += bf2f(X[(size_t)r * ld + col]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[col] = red[0];
+}
+
+// ------------------------------------------------------------------ FP32 check mode
+// The same network in FP32 throughout (FP32 weights, features and
+// activations, the erf GELU above, FP32 accumulation on the vector ALUs):
+// a check of the backward pass's algebra without BF16 rounding.  Same
+// operand conventions and epilogues as k_gemm, 64 x 64 block tiles, each
+// thread 4 x 4 outputs, 16-deep K tiles in LDS.
+struct EpiF {
+    const float *bias;
+    float *zout, *hout, *fout;
+    const float *zin;
+    int ldc;
+};
+
+template <bool AT, bool BT, int EPI>
+__global__ void __launch_bounds__(256) k_gemm_f32(int M, int N, int K, const float *__restrict__ A, int lda,
+                                                   const float *__restrict__ B, int ldb, EpiF e, int kps)
+{
+    __shared__ float As[16][64 + 1];  // [k][m]
+    __shared__ float Bs[16][64 + 1];  // [k][n]
+    const int tid = threadIdx.x, tm = tid & 15, tn = tid >> 4;
+    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int kb = blockIdx.z * kps, ke = min(K, kb + kps);
+    float acc[4][4] = {};
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        for (int q = tid; q < 16 * 64; q += 256) {
+            const int kk = q >> 6, mm = q & 63, gk = k0 + kk;
+            const int gm = m0 + mm, gn = n0 + mm;
+            As[kk][mm] = (gm < M && gk < ke) ? (AT ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk]) : 0.0f;
+            Bs[kk][mm] = (gn < N && gk < ke) ? (BT ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn]) : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++)
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = fmaf(As[kk][tm + 16 * i], Bs[kk][tn + 16 * j], acc[i][j]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int row = m0 + tm + 16 * i, col = n0 + tn + 16 * j;
+            if (row >= M || col >= N) continue;
+            const float x = acc[i][j];
+            const size_t o = (size_t)row * e.ldc + col;
+            if (EPI == EPI_BIAS_GELU) {
+                const float z = x + e.bias[col];
+                e.zout[o] = z;
+                e.hout[o] = gelu(z);
+            } else if (EPI == EPI_BIAS) {
+                e.fout[o] = x + e.bias[col];
+            } else if (EPI == EPI_DGELU) {
+                e.hout[o] = x * gelu_d(e.zin[o]);
+            } else {
+                e.fout[(size_t)blockIdx.z * M * e.ldc + o] = x;
+            }
+        }
+}
+
+__global__ void k_colsum_f32(const float *__restrict__ X, int M, int N, int ld, float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int col = blockIdx.x;
+    float s = 0.0f;
+    for (int r = threadIdx.x; r < M; r += blockDim.x) s += X[(size_t)r * ld + col];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int d = 128; d > 0; d >>= 1) {
@@ -314,7 +386,8 @@ __global__ void k_loss_partial(SceneDev s, BatchDev b, const int *__restrict__ r
 
 // total loss and dY = 2 diff / count (bf16)
 __global__ void k_loss_final(const float *__restrict__ part, const int *__restrict__ cnt_part, int nblk,
-                             const float *__restrict__ diff, int nrows, bf16 *__restrict__ dY, float *__restrict__ loss)
+                             const float *__restrict__ diff, int nrows, bf16 *__restrict__ dY, float *__restrict__ loss,
+                             float *__restrict__ dYf = nullptr)
 {
     __shared__ float tot_s;
     __shared__ int tot_c;
@@ -329,8 +402,10 @@ __global__ void k_loss_final(const float *__restrict__ part, const int *__restri
     __syncthreads();
     // every block sums the few partials itself and scales its own slice
     const float sc = tot_c ? 2.0f / tot_c : 0.0f;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrows * F_OUTP; i += gridDim.x * blockDim.x)
-        dY[i] = f2bf(sc * diff[i]);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrows * F_OUTP; i += gridDim.x * blockDim.x) {
+        if (dY) dY[i] = f2bf(sc * diff[i]);
+        if (dYf) dYf[i] = sc * diff[i];
+    }
 }
 
 // ------------------------------------------------------------------ Adam
@@ -378,97 +453,121 @@ __global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restr
 }
 
 // ------------------------------------------------------------------ fused inference
-// One block = 64 paths: features -> three hidden layers -> output layer ->
-// world points, activations kept in LDS (two ping-pong buffers of
-// 64 x 256 BF16 with a 4-element row pad), weights read from L2.  Each of the
-// 4 waves computes 64 rows x 64 columns of a hidden layer as 2 x 2 MFMA tiles.
-constexpr int FR = 64, FLD = HID + 4;
+// One block = 128 paths and 8 waves: features -> three hidden layers ->
+// output layer -> world points, activations in LDS (two buffers of
+// 128 x 264 BF16).  Every layer is computed transposed, H^T = W X^T: the
+// weights are the matrix cores' A operand (rows = output units; each lane
+// loads 8 consecutive BF16 of one row from L2) and the activations the B
+// operand (8 consecutive BF16 of one path from LDS), so the accumulator
+// holds 4 consecutive output units of one path per register group and the
+// epilogue writes them to LDS with one 8-byte store.  Wave w takes output
+// units 64 (w % 4) .. +64 of paths 64 (w / 4) .. +64: 2 x 2 tiles of
+// v_mfma_f32_32x32x16_bf16.  With two waves per SIMD one wave's matrix
+// work overlaps the other's epilogue.
+//
+// GELU(z) = z Phi(z) with Phi read from a table in LDS: 1024 steps of 1/64
+// on [-8, 8] (Phi and its forward difference; linear interpolation, error
+// below 1e-5, under a tenth of a BF16 step; clamped ends give Phi = 0 and
+// 1 to FP32 precision).  The table entries are Phi = erfc(-z/sqrt 2)/2 in
+// FP32.
+constexpr int IR = 128;                 // paths per block
+constexpr int ILD = HID + 8;            // LDS row stride in BF16 (132 dwords)
+constexpr int TABN = 1024;
 constexpr size_t OW1_ = 0, OB1_ = OW1_ + (size_t)HID * F_IN, OW2_ = OB1_ + HID, OB2_ = OW2_ + (size_t)HID * HID,
                  OW3_ = OB2_ + HID, OB3_ = OW3_ + (size_t)HID * HID, OW4_ = OB3_ + HID,
                  OB4_ = OW4_ + (size_t)F_OUTP * HID;
+constexpr size_t INFER_LDS = (size_t)2 * IR * ILD * sizeof(bf16) + TABN * sizeof(float2) + IR * sizeof(double) +
+                             IR * sizeof(int);
 
-__device__ __forceinline__ short4_t lds4(const bf16 *p) { return *reinterpret_cast<const short4_t *>(p); }
-
-// out[FR][FLD] = GELU(in[FR][K] W^T + b) for this wave's 64 columns.
-// The weight fragments of the next 32-deep k group are loaded while the 16
-// MFMAs of the current group run (register double buffer).
-template <int K>
-__device__ __forceinline__ void fused_layer(const bf16 *in, bf16 *out, const bf16 *__restrict__ W,
-                                            const float *__restrict__ bias, int wave, int lane)
+__device__ __forceinline__ float gelu_tab(const float2 *tab, float z)
 {
-    constexpr int G = 4, NG = K / (8 * G);
-    static_assert(K % (8 * G) == 0, "K must be a multiple of 32");
+    // u = 64 (z + 8), clamped to the table
+    const float u = __builtin_amdgcn_fmed3f(fmaf(z, 64.0f, 512.0f), 0.0f, (float)TABN - 0.0009765625f);
+    const int i = (int)u;
+    const float f = u - (float)i;
+    const float2 t = tab[i];
+    return z * fmaf(t.y, f, t.x);
+}
+
+// out[path][unit] = GELU(in[path][0..K) W[unit]^T + bias[unit]) for this
+// wave's 64 units and 64 paths; the next 16-deep weight fragments are
+// loaded while the four MFMAs of the current ones run.
+template <int K>
+__device__ __forceinline__ void infer_layer(const bf16 *in, bf16 *out, const bf16 *__restrict__ W,
+                                            const float *__restrict__ bias, const float2 *tab, int wave, int lane)
+{
+    static_assert(K % 16 == 0, "K must be a multiple of 16");
+    const int u0 = 64 * (wave & 3), r0 = 64 * (wave >> 2);
+    const int li = lane & 31, kq = 8 * (lane >> 5);
     float16_t acc[2][2];
 #pragma unroll
-    for (int rt = 0; rt < 2; rt++)
+    for (int mt = 0; mt < 2; mt++)
 #pragma unroll
-        for (int ct = 0; ct < 2; ct++)
+        for (int nt = 0; nt < 2; nt++)
 #pragma unroll
-            for (int v = 0; v < 16; v++) acc[rt][ct][v] = 0.0f;
-    const int col0 = 64 * wave;
-    const int kq = 4 * (lane >> 5);
-    const bf16 *wrow[2] = {W + (size_t)(col0 + (lane & 31)) * K + kq, W + (size_t)(col0 + 32 + (lane & 31)) * K + kq};
-    short4_t bcur[G][2], bnxt[G][2];
+            for (int v = 0; v < 16; v++) acc[mt][nt][v] = 0.0f;
+    const bf16 *wp0 = W + (size_t)(u0 + li) * K + kq, *wp1 = W + (size_t)(u0 + 32 + li) * K + kq;
+    const bf16 *ip0 = in + (r0 + li) * ILD + kq, *ip1 = in + (r0 + 32 + li) * ILD + kq;
+    bf16x8_t a0 = *reinterpret_cast<const bf16x8_t *>(wp0), a1 = *reinterpret_cast<const bf16x8_t *>(wp1);
 #pragma unroll
-    for (int j = 0; j < G; j++)
-#pragma unroll
-        for (int ct = 0; ct < 2; ct++) bcur[j][ct] = lds4(wrow[ct] + 8 * j);
-#pragma unroll
-    for (int g = 0; g < NG; g++) {
-        if (g + 1 < NG) {
-#pragma unroll
-            for (int j = 0; j < G; j++)
-#pragma unroll
-                for (int ct = 0; ct < 2; ct++) bnxt[j][ct] = lds4(wrow[ct] + 32 * (g + 1) + 8 * j);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x8_t n0 = a0, n1 = a1;
+        if (k0 + 16 < K) {
+            n0 = *reinterpret_cast<const bf16x8_t *>(wp0 + k0 + 16);
+            n1 = *reinterpret_cast<const bf16x8_t *>(wp1 + k0 + 16);
         }
-#pragma unroll
-        for (int j = 0; j < G; j++) {
-            const int ks = 32 * g + 8 * j;
-            short4_t a[2];
-#pragma unroll
-            for (int rt = 0; rt < 2; rt++) a[rt] = lds4(in + (32 * rt + (lane & 31)) * FLD + ks + kq);
-#pragma unroll
-            for (int rt = 0; rt < 2; rt++)
-#pragma unroll
-                for (int ct = 0; ct < 2; ct++)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[rt], bcur[j][ct], acc[rt][ct], 0, 0, 0);
-        }
-        if (g + 1 < NG) {
-#pragma unroll
-            for (int j = 0; j < G; j++)
-#pragma unroll
-                for (int ct = 0; ct < 2; ct++) bcur[j][ct] = bnxt[j][ct];
-        }
+        const bf16x8_t b0 = *reinterpret_cast<const bf16x8_t *>(ip0 + k0);
+        const bf16x8_t b1 = *reinterpret_cast<const bf16x8_t *>(ip1 + k0);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        a0 = n0;
+        a1 = n1;
     }
+    // D(i, j): unit i = 8 (v / 4) + 4 (lane / 32) + v % 4 of the tile, path j = lane % 32
 #pragma unroll
-    for (int rt = 0; rt < 2; rt++)
+    for (int mt = 0; mt < 2; mt++)
 #pragma unroll
-        for (int ct = 0; ct < 2; ct++) {
-            const int col = col0 + 32 * ct + (lane & 31);
-            const float bc = bias[col];
+        for (int g = 0; g < 4; g++) {
+            const int u = u0 + 32 * mt + 8 * g + 4 * (lane >> 5);
+            const float4 bc = *reinterpret_cast<const float4 *>(bias + u);
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                const int row = 32 * rt + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-                out[row * FLD + col] = f2bf(gelu(acc[rt][ct][v] + bc));
+            for (int nt = 0; nt < 2; nt++) {
+                const float h0 = gelu_tab(tab, acc[mt][nt][4 * g + 0] + bc.x);
+                const float h1 = gelu_tab(tab, acc[mt][nt][4 * g + 1] + bc.y);
+                const float h2 = gelu_tab(tab, acc[mt][nt][4 * g + 2] + bc.z);
+                const float h3 = gelu_tab(tab, acc[mt][nt][4 * g + 3] + bc.w);
+                uint2 pk;
+                pk.x = (uint32_t)f2bf(h0) | ((uint32_t)f2bf(h1) << 16);
+                pk.y = (uint32_t)f2bf(h2) | ((uint32_t)f2bf(h3) << 16);
+                *reinterpret_cast<uint2 *>(out + (r0 + 32 * nt + li) * ILD + u) = pk;
             }
         }
 }
 
 // rows (may be null): solve ids to predict, *count of them; else all b.n
-__global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, const int *__restrict__ rows,
-                                                    const int *__restrict__ count, const bf16 *__restrict__ wb,
-                                                    const float *__restrict__ w, double *__restrict__ x)
+__global__ void __launch_bounds__(512, 1) k_mlp_fused(SceneDev s, BatchDev b, const int *__restrict__ rows,
+                                                       const int *__restrict__ count, const bf16 *__restrict__ wb,
+                                                       const float *__restrict__ w, double *__restrict__ x)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     bf16 *bufA = reinterpret_cast<bf16 *>(smem);
-    bf16 *bufB = bufA + FR * FLD;
-    double *Ls = reinterpret_cast<double *>(bufB + FR * FLD);
-    int *ids = reinterpret_cast<int *>(Ls + FR);
+    bf16 *bufB = bufA + IR * ILD;
+    float2 *tab = reinterpret_cast<float2 *>(bufB + IR * ILD);
+    double *Ls = reinterpret_cast<double *>(tab + TABN);
+    int *ids = reinterpret_cast<int *>(Ls + IR);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row0 = blockIdx.x * FR;
     const int nrows = rows ? *count : (int)b.n;
-    if (row0 >= nrows) return;  // block-uniform
-    if (tid < FR) {
+    if ((int)blockIdx.x * IR >= nrows) return;  // block-uniform
+    for (int i = tid; i < TABN; i += blockDim.x) {
+        const float z0 = -8.0f + (float)i * (1.0f / 64.0f), z1 = z0 + (1.0f / 64.0f);
+        const float p0 = 0.5f * erfcf(-z0 * 0.70710678118654752f), p1 = 0.5f * erfcf(-z1 * 0.70710678118654752f);
+        tab[i] = make_float2(p0, p1 - p0);
+    }
+    // persistent: the block walks the 128-path tiles
+    for (int row0 = blockIdx.x * IR; row0 < nrows; row0 += gridDim.x * IR) {
+    if (tid < IR) {
         float f[F_IN];
         double L = 1.0;
         const int r = row0 + tid;
@@ -478,45 +577,47 @@ __global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, const
             for (int j = 0; j < F_IN; j++) f[j] = 0.0f;
         Ls[tid] = L;
         ids[tid] = i;
-        for (int j = 0; j < F_IN; j++) bufA[tid * FLD + j] = f2bf(f[j]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(bufA + tid * ILD);
+#pragma unroll
+        for (int j = 0; j < F_IN; j += 2) dst[j / 2] = (uint32_t)f2bf(f[j]) | ((uint32_t)f2bf(f[j + 1]) << 16);
     }
     __syncthreads();
-    fused_layer<F_IN>(bufA, bufB, wb + OW1_, w + OB1_, wave, lane);
+    infer_layer<F_IN>(bufA, bufB, wb + OW1_, w + OB1_, tab, wave, lane);
     __syncthreads();
-    fused_layer<HID>(bufB, bufA, wb + OW2_, w + OB2_, wave, lane);
+    infer_layer<HID>(bufB, bufA, wb + OW2_, w + OB2_, tab, wave, lane);
     __syncthreads();
-    fused_layer<HID>(bufA, bufB, wb + OW3_, w + OB3_, wave, lane);
+    infer_layer<HID>(bufA, bufB, wb + OW3_, w + OB3_, tab, wave, lane);
     __syncthreads();
-    // output layer: waves 0 and 1 take 32 rows each; columns 16..31 are padding
-    if (wave < 2) {
+    // output layer, transposed as well: units 0..15 (lanes 16..31 of the A
+    // operand carry zero rows), waves 0..3 take 32 paths each
+    if (wave < 4) {
         float16_t acc;
 #pragma unroll
         for (int v = 0; v < 16; v++) acc[v] = 0.0f;
-        const int kq = 4 * (lane >> 5);
-        const int n = lane & 31;
+        const int li = lane & 31, kq = 8 * (lane >> 5);
+        const bf16 *wp = wb + OW4_ + (size_t)(li & 15) * HID + kq;
+        const bf16 *ip = bufB + (32 * wave + li) * ILD + kq;
 #pragma unroll 4
-        for (int ks = 0; ks < HID; ks += 8) {
-            const short4_t a = lds4(bufB + (32 * wave + (lane & 31)) * FLD + ks + kq);
-            short4_t bb;
-            if (n < F_OUTP) {
-                bb = lds4(wb + OW4_ + (size_t)n * HID + ks + kq);
-            } else {
-                bb[0] = bb[1] = bb[2] = bb[3] = 0;
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
+        for (int k0 = 0; k0 < HID; k0 += 16) {
+            bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(wp + k0);
+            if (li >= F_OUTP) a = bf16x8_t{};
+            const bf16x8_t bb = *reinterpret_cast<const bf16x8_t *>(ip + k0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
         }
-        const int col = lane & 31;
-        if (col < F_OUT) {
-            const float bc = w[OB4_ + col];
+        const int r = 32 * wave + li;
+        const int i = ids[r];
+        if (i >= 0) {
+            const int ord = b.order[i];
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                const int r = 32 * wave + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-                const int i = ids[r];
-                if (i < 0) continue;
-                const int ord = b.order[i];
-                x[(size_t)col * b.n + i] = (col < 3 * ord) ? s.tx[col % 3] + Ls[r] * (double)(acc[v] + bc) : 0.0;
+            for (int v = 0; v < 8; v++) {
+                const int u = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                if (u < F_OUT)
+                    x[(size_t)u * b.n + i] =
+                        (u < 3 * ord) ? s.tx[u % 3] + Ls[r] * (double)(acc[v] + w[OB4_ + u]) : 0.0;
             }
         }
+    }
+    __syncthreads();  // the next tile's features overwrite bufA, ids and Ls
     }
 }
 
@@ -540,6 +641,10 @@ struct MlpState {
           *lpart = nullptr;
     int *lcnt = nullptr;
     size_t part_cap = 0;
+    // FP32 check mode: features, activations and backward buffers in FP32
+    size_t fcap = 0;
+    float *Xf = nullptr, *H1f = nullptr, *H2f = nullptr, *H3f = nullptr, *dYf = nullptr, *dAf = nullptr,
+          *dBf = nullptr;
 };
 
 bool mlp_ready(const MlpState *m) { return m != nullptr && m->w != nullptr; }
@@ -556,10 +661,20 @@ static void free_ws(MlpState *m)
     m->cap = 0;
 }
 
+static void free_f32(MlpState *m)
+{
+    for (void *p : {(void *)m->Xf, (void *)m->H1f, (void *)m->H2f, (void *)m->H3f, (void *)m->dYf, (void *)m->dAf,
+                    (void *)m->dBf})
+        if (p) hipFree(p);
+    m->Xf = m->H1f = m->H2f = m->H3f = m->dYf = m->dAf = m->dBf = nullptr;
+    m->fcap = 0;
+}
+
 void mlp_free(MlpState *m)
 {
     if (!m) return;
     free_ws(m);
+    free_f32(m);
     hipFree(m->w);
     hipFree(m->m);
     hipFree(m->v);
@@ -697,10 +812,13 @@ mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, do
     if (!mlp_ready(m)) return MPT_E_NO_MODEL;
     if (b.n == 0) return MPT_OK;
     static_assert(OW4_ == OW4 && OB4_ == OB4, "parameter layout");
-    const size_t lds = (size_t)2 * FR * FLD * sizeof(bf16) + FR * (sizeof(double) + sizeof(int));
-    hipFuncSetAttribute((const void *)k_mlp_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    const unsigned g = (unsigned)((b.n + FR - 1) / FR);
-    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(256), lds, st, s, b, rows, count, m->wb, m->w, x_out);
+    hipFuncSetAttribute((const void *)k_mlp_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)INFER_LDS);
+    // one resident block per CU (the LDS holds one), each walking tiles
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t tiles = (b.n + IR - 1) / IR;
+    const unsigned g = (unsigned)(tiles < cus ? tiles : cus);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(512), INFER_LDS, st, s, b, rows, count, m->wb, m->w, x_out);
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
 }
 
@@ -783,6 +901,102 @@ static mpt_status grad_dev(MlpState *m, const SceneDev &s, const BatchDev &b, co
     wgrad(HID, F_IN, m->dA, HID, m->X, F_IN, m->g + OW1);
     hipLaunchKernelGGL(k_colsum, dim3(HID), dim3(256), 0, st, m->dA, nrows, HID, HID, m->g + OB1);
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
+}
+
+template <bool AT, bool BT, int EPI>
+static void gemm_f32(int M, int N, int K, const float *A, int lda, const float *B, int ldb, const EpiF &e, int splits,
+                     hipStream_t st)
+{
+    int kps = (K + splits - 1) / splits;
+    kps = ((kps + 15) / 16) * 16;
+    splits = (K + kps - 1) / kps;
+    dim3 grid((M + 63) / 64, (N + 63) / 64, splits);
+    hipLaunchKernelGGL((k_gemm_f32<AT, BT, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, e, kps);
+}
+
+// Loss and gradient of the network run in FP32 throughout (the check mode).
+mpt_status mlp_grad_f32_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,
+                            const double *target, const uint8_t *use, float *d_loss, float *d_grad, hipStream_t st)
+{
+    if (!mlp_ready(m)) return MPT_E_NO_MODEL;
+    if (nrows <= 0) return MPT_E_INVALID_ARG;
+    if (ensure_ws(m, (size_t)nrows, true)) return MPT_E_NOMEM;
+    if ((size_t)nrows > m->fcap) {
+        free_f32(m);
+        const size_t cap = m->cap;
+        bool ok = true;
+        auto A = [&](float **p, size_t n) { ok = ok && hipMalloc((void **)p, n * sizeof(float)) == hipSuccess; };
+        A(&m->Xf, cap * F_IN);
+        A(&m->H1f, cap * HID);
+        A(&m->H2f, cap * HID);
+        A(&m->H3f, cap * HID);
+        A(&m->dYf, cap * F_OUTP);
+        A(&m->dAf, cap * HID);
+        A(&m->dBf, cap * HID);
+        if (!ok) {
+            free_f32(m);
+            return MPT_E_NOMEM;
+        }
+        m->fcap = cap;
+    }
+    const float *w = m->w;
+    hipLaunchKernelGGL(k_features, dim3((nrows + 127) / 128), dim3(128), 0, st, s, b, rows, nrows, m->Xf, nullptr);
+    EpiF e{};
+    e.ldc = HID;
+    e.bias = w + OB1, e.zout = m->Z1, e.hout = m->H1f;
+    gemm_f32<false, true, EPI_BIAS_GELU>(nrows, HID, F_IN, m->Xf, F_IN, w + OW1, F_IN, e, 1, st);
+    e.bias = w + OB2, e.zout = m->Z2, e.hout = m->H2f;
+    gemm_f32<false, true, EPI_BIAS_GELU>(nrows, HID, HID, m->H1f, HID, w + OW2, HID, e, 1, st);
+    e.bias = w + OB3, e.zout = m->Z3, e.hout = m->H3f;
+    gemm_f32<false, true, EPI_BIAS_GELU>(nrows, HID, HID, m->H2f, HID, w + OW3, HID, e, 1, st);
+    EpiF e4{};
+    e4.ldc = F_OUTP;
+    e4.bias = w + OB4, e4.fout = m->Y;
+    gemm_f32<false, true, EPI_BIAS>(nrows, F_OUTP, HID, m->H3f, HID, w + OW4, HID, e4, 1, st);
+    const int nblk = (nrows + 255) / 256;
+    hipLaunchKernelGGL(k_loss_partial, dim3(nblk), dim3(256), 0, st, s, b, rows, nrows, m->Y, target, use, m->diff,
+                       m->lpart, m->lcnt);
+    hipLaunchKernelGGL(k_loss_final, dim3(std::min(256, (nrows * F_OUTP + 255) / 256)), dim3(256), 0, st, m->lpart,
+                       m->lcnt, nblk, m->diff, nrows, (bf16 *)nullptr, d_loss, m->dYf);
+    const int splits = nrows >= 4096 ? 16 : (nrows >= 1024 ? 4 : 1);
+    const size_t need = (size_t)splits * HID * HID;
+    if (m->part_cap < need) {
+        if (m->part) hipFree(m->part);
+        m->part = nullptr;
+        if (hipMalloc((void **)&m->part, need * 4) != hipSuccess) return MPT_E_NOMEM;
+        m->part_cap = need;
+    }
+    auto wgrad = [&](int Mo, int Ni, const float *dZ, int ldz, const float *Xin, int ldx, float *gout) {
+        EpiF eg{};
+        eg.ldc = Ni;
+        eg.fout = m->part;
+        int kps = (nrows + splits - 1) / splits;
+        kps = ((kps + 15) / 16) * 16;
+        const int sp = (nrows + kps - 1) / kps;
+        gemm_f32<true, false, EPI_F32>(Mo, Ni, nrows, dZ, ldz, Xin, ldx, eg, splits, st);
+        const size_t n = (size_t)Mo * Ni;
+        hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m->part, sp, n, gout);
+    };
+    wgrad(F_OUTP, HID, m->dYf, F_OUTP, m->H3f, HID, m->g + OW4);
+    hipLaunchKernelGGL(k_colsum_f32, dim3(F_OUTP), dim3(256), 0, st, m->dYf, nrows, F_OUTP, F_OUTP, m->g + OB4);
+    EpiF ed{};
+    ed.ldc = HID;
+    ed.zin = m->Z3, ed.hout = m->dAf;
+    gemm_f32<false, false, EPI_DGELU>(nrows, HID, F_OUTP, m->dYf, F_OUTP, w + OW4, HID, ed, 1, st);
+    wgrad(HID, HID, m->dAf, HID, m->H2f, HID, m->g + OW3);
+    hipLaunchKernelGGL(k_colsum_f32, dim3(HID), dim3(256), 0, st, m->dAf, nrows, HID, HID, m->g + OB3);
+    ed.zin = m->Z2, ed.hout = m->dBf;
+    gemm_f32<false, false, EPI_DGELU>(nrows, HID, HID, m->dAf, HID, w + OW3, HID, ed, 1, st);
+    wgrad(HID, HID, m->dBf, HID, m->H1f, HID, m->g + OW2);
+    hipLaunchKernelGGL(k_colsum_f32, dim3(HID), dim3(256), 0, st, m->dBf, nrows, HID, HID, m->g + OB2);
+    ed.zin = m->Z1, ed.hout = m->dAf;
+    gemm_f32<false, false, EPI_DGELU>(nrows, HID, HID, m->dBf, HID, w + OW2, HID, ed, 1, st);
+    wgrad(HID, F_IN, m->dAf, HID, m->Xf, F_IN, m->g + OW1);
+    hipLaunchKernelGGL(k_colsum_f32, dim3(HID), dim3(256), 0, st, m->dAf, nrows, HID, HID, m->g + OB1);
+    if (hipGetLastError() != hipSuccess) return MPT_E_DEVICE;
+    if (d_grad && hipMemcpyAsync(d_grad, m->g, NPAR * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return MPT_E_DEVICE;
+    return MPT_OK;
 }
 
 mpt_status mlp_grad_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,

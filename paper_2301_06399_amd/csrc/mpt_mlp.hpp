@@ -19,6 +19,8 @@ mpt_status mlp_train_step_dev(MlpState *m, const SceneDev &s, const BatchDev &b,
                               const double *target, const uint8_t *use, float lr, float *d_loss, hipStream_t st);
 mpt_status mlp_grad_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,
                         const double *target, const uint8_t *use, float *d_loss, float *d_grad, hipStream_t st);
+mpt_status mlp_grad_f32_dev(MlpState *m, const SceneDev &s, const BatchDev &b, const int *rows, int nrows,
+                            const double *target, const uint8_t *use, float *d_loss, float *d_grad, hipStream_t st);
 mpt_status mlp_features_dev(const SceneDev &s, const BatchDev &b, float *fout, hipStream_t st);
 mpt_status gemm_test_dev(int M, int N, int K, const float *A, int at, const float *B, int bt, float *C, int splits,
                          hipStream_t st);

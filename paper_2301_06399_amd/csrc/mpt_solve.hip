@@ -310,7 +310,7 @@ __device__ inline bool in_guard(const SceneDev &s, const double *X, int n)
 // solver's own cost judges the prediction.  Writes the chosen start points
 // into x0l (rows of the path; one thread per served path).
 template <int N>
-__device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, double *__restrict__ x0l)
+__device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, double *__restrict__ x0l, double gain)
 {
     SceneT<double> s64;
     s64.rec = s.rec64;
@@ -348,24 +348,24 @@ __device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, do
     double c0 = 0.0, r0 = 0.0, c1 = 0.0, r1 = 0.0;
     const bool ok0 = eval_cost<double, N>(s64, q, X0, nullptr, c0, r0);
     const bool ok1 = okn && eval_cost<double, N>(s64, q, Xn, nullptr, c1, r1);
-    const bool net = ok1 && (!ok0 || c1 < c0);
+    const bool net = ok1 && (!ok0 || c1 < gain * c0);
 #pragma unroll
     for (int j = 0; j < 3 * N; j++) x0l[(size_t)j * b.n + i] = net ? Xn[j] : X0[j];
 }
 
 __global__ void __launch_bounds__(256) k_learned_choose(SceneDev s, BatchDev b, const int *__restrict__ rows,
                                                         const int *__restrict__ count, int all,
-                                                        double *__restrict__ x0l)
+                                                        double *__restrict__ x0l, double gain)
 {
     const int64_t m = all ? b.n : (int64_t)*count;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = all ? t : rows[t];
         switch (valid_order(b, i, s.n_all)) {
-        case 1: choose_start<1>(s, b, i, x0l); break;
-        case 2: choose_start<2>(s, b, i, x0l); break;
-        case 3: choose_start<3>(s, b, i, x0l); break;
-        case 4: choose_start<4>(s, b, i, x0l); break;
-        case 5: choose_start<5>(s, b, i, x0l); break;
+        case 1: choose_start<1>(s, b, i, x0l, gain); break;
+        case 2: choose_start<2>(s, b, i, x0l, gain); break;
+        case 3: choose_start<3>(s, b, i, x0l, gain); break;
+        case 4: choose_start<4>(s, b, i, x0l, gain); break;
+        case 5: choose_start<5>(s, b, i, x0l, gain); break;
         default: break;
         }
     }
@@ -690,6 +690,39 @@ __device__ __forceinline__ int lm_step_uniform(int code, const SceneT<T> &sc, co
     return -1;
 }
 
+// True when some point lies outside its object's finite extent by more
+// than `margin` metres (rectangle sides, edge ends, paraboloid aperture; a
+// circle is its own extent).  FP64 world points and records.
+template <int N>
+__device__ __forceinline__ bool outside_extent(const double *rec64, const int *id, const int *ty, const double *X,
+                                               double margin)
+{
+    bool out = false;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const double *r = rec64 + (size_t)id[k] * kRec;
+        const double *x = X + 3 * k;
+        if (ty[k] == TP) {
+            const double e[3] = {x[0] - r[4], x[1] - r[5], x[2] - r[6]};
+            const double la = sqrt(r[7] * r[7] + r[8] * r[8] + r[9] * r[9]);
+            const double lb = sqrt(r[10] * r[10] + r[11] * r[11] + r[12] * r[12]);
+            const double a = (e[0] * r[7] + e[1] * r[8] + e[2] * r[9]) / la;
+            const double b = (e[0] * r[10] + e[1] * r[11] + e[2] * r[12]) / lb;
+            out = out || a < -margin || a > la + margin || b < -margin || b > lb + margin;
+        } else if (ty[k] == TL) {
+            const double sp = (x[0] - r[0]) * r[3] + (x[1] - r[1]) * r[4] + (x[2] - r[2]) * r[5];
+            out = out || sp < r[6] - margin || sp > r[7] + margin;
+        } else if (ty[k] == TQ) {
+            const double d[3] = {x[0] - r[0], x[1] - r[1], x[2] - r[2]};
+            const double h = d[0] * r[13] + d[1] * r[14] + d[2] * r[15];
+            const double w2 = (d[0] - h * r[13]) * (d[0] - h * r[13]) + (d[1] - h * r[14]) * (d[1] - h * r[14]) +
+                              (d[2] - h * r[15]) * (d[2] - h * r[15]);
+            out = out || w2 > (r[16] + margin) * (r[16] + margin);
+        }
+    }
+    return out;
+}
+
 template <int MODE, int N, int FORM = 0, bool TYPED = false>
 __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restrict__ srec)
 {
@@ -939,6 +972,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                 // ---- end of one path: write it (world frame)
                 const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
                                       MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
+                double Xw[3 * N];
                 if constexpr (FORM) {
                     // the points X(U) in the solver's frame, then world
 #pragma unroll
@@ -946,12 +980,14 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                         T Xk[3], Tm[3][2];
                         param_map<T>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, L.X[2 * k], L.X[2 * k + 1], Xk, Tm);
 #pragma unroll
-                        for (int i = 0; i < 3; i++) kp.out.x[(size_t)(3 * k + i) * kp.b.n + sid] = (double)Xk[i] + sh[i];
+                        for (int i = 0; i < 3; i++) Xw[3 * k + i] = (double)Xk[i] + sh[i];
                     }
                 } else {
 #pragma unroll
-                    for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j] + sh[j % 3];
+                    for (int j = 0; j < 3 * N; j++) Xw[j] = (double)L.X[j] + sh[j % 3];
                 }
+#pragma unroll
+                for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = Xw[j];
                 kp.out.cost[sid] = (double)L.C;
                 int it = L.it;
                 if (MODE == MODE_FALLBACK64) it += kp.out.iters[sid];
@@ -974,9 +1010,17 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     // by the polish - a converged or stalled FP32 point that
                     // does not polish
                     const bool small_res = (double)L.rinf <= kp.o.polish_gate;
-                    const bool to_polish = small_res && (st == ST_CONV || st == ST_MAXIT || st == ST_LOCALMIN ||
-                                                         st == ST_STALL);
+                    bool to_polish = small_res && (st == ST_CONV || st == ST_MAXIT || st == ST_LOCALMIN ||
+                                                   st == ST_STALL);
                     const bool to_fb = (st == ST_DEGEN) || (st == ST_MAXIT && p.planar && !small_res);
+                    // a root-like end point far outside a finite extent: the
+                    // polish and the fallback stay next to it (within a few
+                    // times its residual), so the path cannot be accepted
+                    if (to_polish && kp.o.extent_skip > 0.0 &&
+                        outside_extent<N>(kp.s.rec64, p.id, p.ty, Xw, kp.o.extent_skip + 100.0 * (double)L.rinf)) {
+                        to_polish = false;
+                        code = ST_OUTSIDE;
+                    }
                     if (to_polish) {
                         // listed for the polish after the LM passes (no
                         // atomic with a return value in the iteration loop)
@@ -1399,11 +1443,11 @@ void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *co
 }
 
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
-                           double *x0l, hipStream_t st)
+                           double *x0l, double gain, hipStream_t st)
 {
     if (b.n == 0) return;
     const unsigned g = (unsigned)std::min<int64_t>((b.n + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_learned_choose, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l);
+    hipLaunchKernelGGL(k_learned_choose, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l, gain);
 }
 
 // The polish list: the solves the FP32 passes routed to the polish, grouped

@@ -18,14 +18,30 @@ from . import mpt
 from . import workloads as W
 
 
-def train(ctx, scene, train_batch, steps=3000, batch_rows=4096, lr=1e-3, seed=1, log=None):
+def targets(ctx, db, form=mpt.FORM_IMPLICIT, ends=False):
+    """Training targets: the plain FP64 solver's end points from the straight
+    line, in `form`.  Only the roots (CONVERGED), or with `ends` every end
+    point of a finished descent (roots and non-root stationary points), so
+    that the network learns where the descent from the line ends."""
+    import torch
+    out = ctx.solve(db, mpt.default_opts(precision=mpt.FP64_PLAIN, form=form))
+    st = out.status.to(torch.int32) & 0x7F
+    if ends:
+        ok = (st == mpt.CONVERGED) | (st == mpt.LOCALMIN) | (st == mpt.MAXITER) | (st == mpt.STALLED)
+        ok &= torch.isfinite(out.x).all(dim=0)
+    else:
+        ok = st == mpt.CONVERGED
+    return out, ok.to(torch.uint8)
+
+
+def train(ctx, scene, train_batch, steps=3000, batch_rows=4096, lr=1e-3, seed=1, log=None,
+          form=mpt.FORM_IMPLICIT, ends=False):
     """Solve `train_batch` with the plain FP64 solver, then train for `steps`
     Adam steps with cosine-decayed learning rate.  Returns the loss history."""
     import torch
     ctx.upload_scene(scene)
     db = mpt.DeviceBatch(train_batch)
-    out = ctx.solve(db, mpt.default_opts(precision=mpt.FP64_PLAIN))
-    use = (out.status == mpt.CONVERGED).to(torch.uint8)
+    out, use = targets(ctx, db, form, ends)
     ctx.mlp_init(seed)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
@@ -42,7 +58,7 @@ def train(ctx, scene, train_batch, steps=3000, batch_rows=4096, lr=1e-3, seed=1,
         pos += batch_rows
         a = lr * 0.5 * (1.0 + math.cos(math.pi * it / max(1, steps)))
         ctx.mlp_train_step(db, out.x, use=use, lr=a, loss=loss, rows=rows)
-        if it % 200 == 0 or it == steps - 1:
+        if it % 1000 == 0 or it == steps - 1:
             hist.append((it, float(loss.item())))
             if log:
                 print(f"# train step {it}: loss {hist[-1][1]:.5f}", file=log, flush=True)
@@ -82,9 +98,11 @@ def train_joint(ctx, parts, steps=4000, batch_rows=4096, lr=1e-3, seed=1, log=No
     return hist
 
 
-def prepare(ctx, scene, batch, steps=None, n_rx=8192, log=sys.stderr):
-    """Train the network for the workload of `scene` (configurations 2 and 3)
-    on held-apart problems; returns True when the learned start is ready."""
+def prepare(ctx, scene, batch, steps=None, n_rx=16384, log=sys.stderr):
+    """Train the network for the workload of `scene` (the curved and the
+    stress scenes) on held-apart problems (about a million, targets from the
+    parametric form the solver runs); returns True when the learned start is
+    ready."""
     if len(scene.lines) and len(scene.quadrics):
         cfg, n_rx, per_rx = 5, max(1, n_rx // 16), 1024   # the stress scene
     elif len(scene.quadrics) or len(scene.circles):
@@ -104,7 +122,7 @@ def prepare(ctx, scene, batch, steps=None, n_rx=8192, log=sys.stderr):
                np.allclose(getattr(sc, k), getattr(scene, k)) for k in ("planes", "lines", "quadrics", "circles"))
     if not same:
         return False  # no training generator for this scene
-    hist = train(ctx, sc, tb, steps=steps or 3000, log=log)
+    hist = train(ctx, sc, tb, steps=steps or 20000, log=log, form=mpt.FORM_PARAMETRIC)
     ctx.upload_scene(scene)
     if log:
         print(f"# learned start trained in {time.time() - t:.1f}s, final loss {hist[-1][1]:.5f}", file=log, flush=True)

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libmpt.so")
 MPT_OK = 0
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NO_SCENE",
                 5: "E_UNSUPPORTED", 6: "E_NO_MODEL", 7: "E_CAPACITY"}
-CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN = range(7)
+CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN, OUTSIDE = range(8)
 FALLBACK = 0x80
 FP64_PLAIN, FP32_POLISH64 = 0, 1
 INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL, INIT_RANDOM = 0, 1, 2, 3, 4
@@ -53,7 +53,8 @@ class SolveOpts(C.Structure):
                 ("tol_res32", C.c_double), ("tau_root32", C.c_double), ("polish_gate", C.c_double),
                 ("seed", C.c_uint64), ("spill", C.c_int32), ("form", C.c_int32),
                 ("stat_tol", C.c_double), ("stat_win", C.c_int32), ("refill", C.c_int32),
-                ("max_iter32_planar", C.c_int32)]
+                ("max_iter32_planar", C.c_int32), ("extent_skip", C.c_double),
+                ("learned_gain", C.c_double)]
 
 
 class SolveOut(C.Structure):
@@ -67,7 +68,7 @@ EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt
            "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
            "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused", "mpt_visible",
            "mpt_visibility", "mpt_visibility_rx", "mpt_candidates", "mpt_last_launch", "mpt_set_timing",
-           "mpt_solve_batch_noalloc"]
+           "mpt_solve_batch_noalloc", "mpt_mlp_grad_fp32"]
 
 _lib = None
 
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH):
     L.mpt_mlp_init.argtypes = [vp, C.c_uint64]
     L.mpt_mlp_train_step.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, C.c_float, vp]
     L.mpt_mlp_grad.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, vp, vp]
+    L.mpt_mlp_grad_fp32.argtypes = [vp, C.POINTER(BatchDesc), vp, vp, vp, C.c_int32, vp, vp]
     L.mpt_mlp_features.argtypes = [vp, C.POINTER(BatchDesc), vp]
     L.mpt_mlp_param_count.argtypes = [C.POINTER(C.c_size_t)]
     L.mpt_gemm_bf16_check.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int32, vp, C.c_int32, vp,
@@ -446,7 +448,8 @@ class Context:
         self._leave()
         self._check(rc, "mpt_mlp_train_step")
 
-    def mlp_grad(self, dbatch: DeviceBatch, target_x, use=None, rows=None):
+    def mlp_grad(self, dbatch: DeviceBatch, target_x, use=None, rows=None, fp32=False):
+        """Loss and gradient without an update; fp32: the FP32 check mode."""
         torch = self.torch
         n = C.c_size_t(0)
         self.L.mpt_mlp_param_count(C.byref(n))
@@ -455,10 +458,10 @@ class Context:
         bd = dbatch.desc()
         nr = int(rows.numel()) if rows is not None else dbatch.n
         self._enter()
-        rc = self.L.mpt_mlp_grad(self.h, C.byref(bd), _ptr(target_x), _ptr(use), _ptr(rows), nr, _ptr(loss),
-                                 _ptr(g))
+        fn = self.L.mpt_mlp_grad_fp32 if fp32 else self.L.mpt_mlp_grad
+        rc = fn(self.h, C.byref(bd), _ptr(target_x), _ptr(use), _ptr(rows), nr, _ptr(loss), _ptr(g))
         self._leave()
-        self._check(rc, "mpt_mlp_grad")
+        self._check(rc, "mpt_mlp_grad_fp32" if fp32 else "mpt_mlp_grad")
         return float(loss.item()), g
 
     def mlp_features(self, dbatch: DeviceBatch):

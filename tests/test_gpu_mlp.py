@@ -75,12 +75,40 @@ def test_gradients_match_fp64_reference(ctx):
     for i in range(2000):
         mask[i, :3 * sb.order[i]] = u[i]
     G_gpu = R.unpack(g.cpu().numpy())
-    for rounding, tol, ltol in ((True, 5e-3, 1e-4), (False, 3e-2, 1e-2)):
+    for rounding, tol, ltol in ((True, 5e-3, 1e-4), (False, 2e-2, 1e-2)):
         loss_r, G, _ = R.loss_and_grad(P, X, T, mask, rounding=rounding)
         assert abs(loss_g - loss_r) <= ltol * loss_r, (rounding, loss_g, loss_r)
         for k in G:
             rel = np.linalg.norm(G_gpu[k] - G[k]) / max(np.linalg.norm(G[k]), 1e-30)
             assert rel <= tol, (rounding, k, rel)
+
+
+def test_fp32_gradients_match_fp64_reference(ctx):
+    """The backward pass run in FP32 throughout (no BF16 rounding anywhere)
+    against the exact FP64 network and its gradient: relative error at the
+    level of FP32 accumulation."""
+    import torch
+    sc, b, db, out = solved_training_set(ctx, 3, 16)
+    use = (out.status == 0).to(torch.uint8)
+    ctx.mlp_init(11)
+    rows = torch.arange(0, 512, dtype=torch.int32, device="cuda")
+    loss_g, g = ctx.mlp_grad(db, out.x, use=use, rows=rows, fp32=True)
+    hdr, w, _, _ = R.parse_blob(ctx.mlp_save())
+    P = R.unpack(w)
+    sb = b.subset(np.arange(512))
+    X = R.features(sc, sb)
+    T = R.targets(sc, sb, out.x.cpu().numpy()[:, :512])
+    mask = np.zeros((512, 16))
+    u = use.cpu().numpy()[:512]
+    for i in range(512):
+        mask[i, :3 * sb.order[i]] = u[i]
+    assert mask.sum() > 100
+    loss_r, G, _ = R.loss_and_grad(P, X, T, mask, rounding=False)
+    assert abs(loss_g - loss_r) <= 1e-6 * loss_r, (loss_g, loss_r)
+    G_gpu = R.unpack(g.cpu().numpy())
+    for k in G:
+        rel = np.linalg.norm(G_gpu[k] - G[k]) / max(np.linalg.norm(G[k]), 1e-30)
+        assert rel <= 1e-6, (k, rel)
 
 
 def test_training_lowers_loss_and_blob_roundtrip(ctx):

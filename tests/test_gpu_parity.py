@@ -211,7 +211,26 @@ def test_full_street_canyon_sampled(ctx):
     assert point_err(g["x"][:, samp], orc["x"], sb.order, both) <= TOL_M
     assert g["count"] == int(g["accept"].sum())
     # every status is final (no pending routing code left)
-    assert set(np.unique(g["status"] & 0x7F)) <= {0, 1, 2, 3, 4, 5, 6}
+    assert set(np.unique(g["status"] & 0x7F)) <= {0, 1, 2, 3, 4, 5, 6, 7}
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_extent_skip_changes_no_flag(ctx, form):
+    """FP32 end points far outside a finite extent skip the FP64 polish and
+    end as OUTSIDE; with the skip switched off the same solves are
+    polished, and the accept flags are the same bit for bit (none of the
+    skipped solves is accepted either way)."""
+    from paper_2301_06399_amd import mpt
+    sc, b = W.config5(n_rx=128, per_rx=1024)
+    on = gpu_solve(ctx, sc, b, form=form)
+    off = gpu_solve(ctx, sc, b, form=form, extent_skip=0.0)
+    skipped = (on["status"] & 0x7F) == 7
+    assert skipped.sum() > 0.2 * b.n
+    assert not ((off["status"] & 0x7F) == 7).any()
+    assert np.array_equal(on["accept"], off["accept"])
+    assert not off["accept"][skipped].any()
+    both = on["accept"] == 1
+    assert np.array_equal(on["x"][:, both], off["x"][:, both])
 
 
 def test_graph_replay_matches_eager(ctx):
@@ -428,3 +447,48 @@ def test_grazing_continuum_rejected(ctx):
         for form in (0, 1):
             g = gpu_solve(ctx, sc, b, precision=prec, form=form)
             assert list(g["accept"]) == [0, 1], (prec, form)
+
+
+def _curved_mask(sc, b):
+    t = sc.type_of(np.maximum(b.prim, 0))
+    act = np.arange(5)[:, None] < b.order[None, :]
+    return np.any(act & (t >= 2), axis=0)
+
+
+@pytest.mark.parametrize("variant", ["S", "L"])
+def test_stress_subset_matches_oracle(ctx, variant):
+    """The stress workload (orders 3-5, two or more diffractions, facets and
+    paraboloids) in the form and with the start
+    the benchmark times: the straight line (S) or the learned start trained
+    on held-apart problems of the same scene (L).  Planes and straight
+    edges: flags bit-identical to the oracle's.  Curved: every GPU root the
+    oracle's straight-line run did not find is confirmed by an oracle solve
+    from the GPU point, and the oracle's roots the GPU missed stay within
+    the bound of the start it used (the same start: 0.5%; the learned
+    start, which may land in another basin: 5%)."""
+    from paper_2301_06399_amd import mpt, learned
+    sc, b = W.config5(n_rx=256, per_rx=1024)
+    ctx.upload_scene(sc)
+    init = mpt.INIT_LINE
+    if variant == "L":
+        assert learned.prepare(ctx, sc, b, steps=1500, n_rx=2048, log=None)
+        init = mpt.INIT_LEARNED
+    g = gpu_solve(ctx, sc, b, form=2, init=init)
+    orc = O.solve_batch(sc, b, form="param")
+    orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
+    curved = _curved_mask(sc, b)
+    assert curved.sum() > 20000 and (~curved).sum() > 200000
+    flat = ~curved
+    mism = np.where(flat & (g["accept"] != orc_acc))[0]
+    assert len(mism) == 0, mism[:10]
+    both = flat & (g["accept"] == 1) & (orc_acc == 1)
+    assert point_err(g["x"], orc["x"], b.order, both) <= TOL_M
+    sub = np.where(curved)[0]
+    bc = b.subset(sub)
+    gc = {k: (g[k][..., sub] if k == "x" else g[k][sub]) for k in ("x", "accept")}
+    n_extra = verify_extra_roots(sc, bc, gc, orc_acc[sub])
+    missed = int(((gc["accept"] == 0) & (orc_acc[sub] == 1)).sum())
+    n_orc = int(orc_acc[sub].sum())
+    assert n_orc > 50
+    assert missed <= (0.005 if variant == "S" else 0.05) * n_orc, (missed, n_orc, n_extra)
+    assert np.array_equal(g["idx"], np.where(g["accept"] == 1)[0])
