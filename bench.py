@@ -10,8 +10,9 @@ Default workload: the multi-diffraction stress workload (the street canyon
 plus 30 paraboloids; 16,384 receivers x 1024 lists of order 3-5 with at
 least two diffractions = 16,777,216 solves), the largest configuration, with
 the learned start trained on held-apart problems of the same scene and the
-timed steps replayed from a captured HIP graph.  --config 1 / 2 / 3 select
-the room, the street canyon and the curved scene; --config 4 is the
+timed steps replayed from a captured HIP graph.  --config 1 / 2 / 3 / 6
+select the room, the street canyon, the curved scene and the glazed street
+canyon (refraction through glass panes); --config 4 is the
 learned-start evaluation (one network trained on 2 M solver outputs of the
 street-canyon and curved generators, timed on 1 M held-out problems).
 
@@ -36,12 +37,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WKEY = {1: "room", 2: "street_canyon", 3: "curved", 4: "learned_heldout", 5: "stress"}
+WKEY = {1: "room", 2: "street_canyon", 3: "curved", 4: "learned_heldout", 5: "stress", 6: "glazed"}
 NAMES = {1: "room 10x10x3 m, 6 walls + 2 edges, 256 RX x 64 lists (order 1-2)",
          2: "street canyon 50 boxes (251 facets + 400 edges), 4096 RX x 64 lists (order 1-3)",
          3: "curved: 200 paraboloids + 100 circles, 16384 RX x 64 lists (order 1-5)",
          4: "learned start, held-out: street canyon 8192 RX x 64 (order 1-3) + curved 8192 RX x 64 (order 1-5)",
-         5: "stress: street canyon + 30 paraboloids, 16384 RX x 1024 lists of order 3-5 with >= 2 diffractions"}
+         5: "stress: street canyon + 30 paraboloids, 16384 RX x 1024 lists of order 3-5 with >= 2 diffractions",
+         6: "glazed street canyon: 50 boxes + 40 glass panes (refracting facets), 4096 RX x 64 lists of order 2-4 "
+            "through a pane"}
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12, "bf16": 2.5e15}
 MLP_FLOPS_PER_ROW = 2 * (96 * 256 + 256 * 256 + 256 * 256 + 256 * 15)
 # variant: (precision, start, form); form 0 = implicit (Eq. 12), 1 = parametric
@@ -641,7 +644,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--n-rx", type=int, default=0, help="receivers (0: the configuration's own)")
     ap.add_argument("--variant", default="auto", choices=["auto", "L", "A", "S", "Si", "Sp", "P", "Pp"])
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -125,6 +125,13 @@ typedef struct {
     const double *planes, *lines, *quadrics, *circles;
     const double *wedges;  /* [n_lines][7] or NULL (validation, visibility)     */
     const double *sides;   /* [n_planes] or NULL (visibility matrix only)        */
+    const double *refraction; /* [n_planes][2] or NULL: the refractive indices
+                              of a facet that refracts instead of reflecting
+                              (Sec. VI: Snell's law as one more law equation):
+                              the index on the side its normal points to,
+                              then the other side's; (0, 0) marks a mirror.
+                              Both positive or both 0, else
+                              MPT_E_INVALID_ARG                               */
 } mpt_scene_desc;
 mpt_status mpt_scene_upload(mpt_ctx *ctx, const mpt_scene_desc *scene);
 

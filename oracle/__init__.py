@@ -35,7 +35,7 @@ class _Scene(C.Structure):
     _fields_ = [("tx", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("n_pl", C.c_int32), ("n_ln", C.c_int32), ("n_q", C.c_int32), ("n_c", C.c_int32),
                 ("pl", C.c_void_p), ("ln", C.c_void_p), ("q", C.c_void_p), ("c", C.c_void_p),
-                ("wd", C.c_void_p), ("sd", C.c_void_p)]
+                ("wd", C.c_void_p), ("sd", C.c_void_p), ("rf", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -99,6 +99,8 @@ class OracleScene:
         self.wd = np.ascontiguousarray(wd, dtype=np.float64) if wd is not None and len(wd) else None
         sd = getattr(scene, "sides", None)
         self.sd = np.ascontiguousarray(sd, dtype=np.float64) if sd is not None and len(sd) else None
+        rf = getattr(scene, "refraction", None)
+        self.rf = np.ascontiguousarray(rf, dtype=np.float64) if rf is not None and len(rf) else None
         s = _Scene()
         s.tx[:] = list(scene.tx)
         s.lo[:] = list(scene.aabb_lo)
@@ -107,6 +109,7 @@ class OracleScene:
         s.pl, s.ln, s.q, s.c = (_p(a) for a in self.keep)
         s.wd = _p(self.wd)
         s.sd = _p(self.sd)
+        s.rf = _p(self.rf)
         self.s = s
 
     @property

@@ -144,11 +144,28 @@ static void edge_rows(int t, const double *r, const double *X, double f[2], doub
     }
 }
 
+/* Refractive indices of facet `id` (a plane id): 1 with (front, back) when
+ * the facet refracts (Sec. VI: Snell's law as one more law equation), else
+ * 0 - the facet reflects. */
+static int refracts(const orc_scene *s, int id, double *nf, double *nb)
+{
+    if (!s->rf || id < 0 || id >= s->n_pl) return 0;
+    *nf = s->rf[2 * (size_t)id];
+    *nb = s->rf[2 * (size_t)id + 1];
+    return *nf > 0.0 && *nb > 0.0;
+}
+
 /* ------------------------------------------------------------ residual */
 /*
  * Rows of interaction k, in metres:
  *   reflection  S_k (r^ - (i^ - 2<i^,n^>n^))      3 rows  (Eq. 8 rescaled)
  *               f_k(X_k)                          1 row   (Eq. 11)
+ *   refraction  S_k (n_t r^_t - n_i i^_t)         3 rows  (Snell's law on a
+ *               f_k(X_k)                          1 row    refracting facet)
+ *     where v_t = v - <v,n^> n^ is the part along the facet, n_i the index of
+ *     the side the ray arrives from (the side n^ points to when <i^,n^> < 0)
+ *     and n_t the other side's; the law rows hold for any ray that keeps its
+ *     tangential slowness, so acceptance also checks that it crosses
  *   diffraction S_k <i^ - r^, e^>                 1 row   (Eq. 9 rescaled)
  *               two rows vanishing on the edge    2 rows  (Eq. 11 for edges)
  * with i = X_k - X_{k-1}, r = X_{k+1} - X_k and S_k = (|i| + |r|)/2.  Eq. (8)
@@ -191,26 +208,47 @@ int orc_residual(const orc_scene *s, const double rx[3], int n, const int32_t *i
             double nh[3];
             for (int i = 0; i < 3; i++) nh[i] = g[i] / lg;
             double sdot = dot3(ih, nh);
-            for (int i = 0; i < 3; i++) u[i] = rh[i] - ih[i] + 2.0 * sdot * nh[i];
-            double Q[3][3], QPa[3][3], Nm[3][3], Pn[3][3], T[3][3], TN[3][3];
-            for (int i = 0; i < 3; i++)
-                for (int j = 0; j < 3; j++) {
-                    Q[i][j] = (i == j ? 1.0 : 0.0) - 2.0 * nh[i] * nh[j];
-                    Pn[i][j] = (i == j ? 1.0 : 0.0) - nh[i] * nh[j];
+            double nf, nb;
+            if (t == TP && refracts(s, ids[k], &nf, &nb)) {
+                /* u = n_t Pn r^ - n_i Pn i^ with Pn = I - n n^T (constant on a
+                 * plane): dU/dX_{k-1} = n_i Pn Pa, dU/dX_{k+1} = n_t Pn Pb */
+                double ni = (sdot < 0.0) ? nf : nb, nt = (sdot < 0.0) ? nb : nf;
+                double sr = dot3(rh, nh);
+                double PnPa[3][3], PnPb[3][3], Pn[3][3];
+                for (int i = 0; i < 3; i++) {
+                    u[i] = nt * (rh[i] - sr * nh[i]) - ni * (ih[i] - sdot * nh[i]);
+                    for (int j = 0; j < 3; j++) Pn[i][j] = (i == j ? 1.0 : 0.0) - nh[i] * nh[j];
                 }
-            mm3(Q, Pa, QPa);
-            mm3(Pn, H, Nm); /* d n^ / dX = (I - n n^T) H / |g| */
-            for (int i = 0; i < 3; i++)
-                for (int j = 0; j < 3; j++) Nm[i][j] /= lg;
-            for (int i = 0; i < 3; i++)
-                for (int j = 0; j < 3; j++) T[i][j] = 2.0 * (nh[i] * ih[j] + (i == j ? sdot : 0.0));
-            mm3(T, Nm, TN);
-            for (int i = 0; i < 3; i++)
-                for (int j = 0; j < 3; j++) {
-                    Up[i][j] = QPa[i][j];
-                    Un[i][j] = Pb[i][j];
-                    Uk[i][j] = -Pb[i][j] - QPa[i][j] + TN[i][j];
-                }
+                mm3(Pn, Pa, PnPa);
+                mm3(Pn, Pb, PnPb);
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        Up[i][j] = ni * PnPa[i][j];
+                        Un[i][j] = nt * PnPb[i][j];
+                        Uk[i][j] = -Up[i][j] - Un[i][j];
+                    }
+            } else {
+                for (int i = 0; i < 3; i++) u[i] = rh[i] - ih[i] + 2.0 * sdot * nh[i];
+                double Q[3][3], QPa[3][3], Nm[3][3], Pn[3][3], T[3][3], TN[3][3];
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        Q[i][j] = (i == j ? 1.0 : 0.0) - 2.0 * nh[i] * nh[j];
+                        Pn[i][j] = (i == j ? 1.0 : 0.0) - nh[i] * nh[j];
+                    }
+                mm3(Q, Pa, QPa);
+                mm3(Pn, H, Nm); /* d n^ / dX = (I - n n^T) H / |g| */
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) Nm[i][j] /= lg;
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) T[i][j] = 2.0 * (nh[i] * ih[j] + (i == j ? sdot : 0.0));
+                mm3(T, Nm, TN);
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        Up[i][j] = QPa[i][j];
+                        Un[i][j] = Pb[i][j];
+                        Uk[i][j] = -Pb[i][j] - QPa[i][j] + TN[i][j];
+                    }
+            }
             nl = 3;
             obj[0] = f;
             for (int j = 0; j < 3; j++) dobj[0][j] = g[j];
@@ -305,7 +343,16 @@ void orc_init_line(const orc_scene *s, const double rx[3], int n, const int32_t 
     for (int k = 0; k < n; k++) {
         const double *rec;
         int t = prim_type(s, ids[k], &rec);
-        double a = (double)(k + 1) / (double)(n + 1), P[3];
+        double a = (double)(k + 1) / (double)(n + 1), P[3], nf, nb;
+        /* a refracting facet is crossed: where the TX -> RX segment meets its
+         * plane, when it does */
+        if (t == TP && refracts(s, ids[k], &nf, &nb)) {
+            double dd[3];
+            sub3(rx, s->tx, dd);
+            double den = dot3(rec, dd);
+            double c = (den != 0.0) ? (rec[3] - dot3(rec, s->tx)) / den : -1.0;
+            if (c > 0.0 && c < 1.0) a = c;
+        }
         for (int i = 0; i < 3; i++) P[i] = s->tx[i] + a * (rx[i] - s->tx[i]);
         project(t, rec, P, X + 3 * k);
     }
@@ -807,6 +854,7 @@ int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t 
         sub3(Q, P, d);
         if (!(norm3(d) >= min_seg)) return 0;
     }
+    double medium = 0.0; /* index of the medium the ray travels in (0: not yet known) */
     for (int k = 0; k < n; k++) {
         const double *rec;
         int t = prim_type(s, ids[k], &rec);
@@ -826,6 +874,19 @@ int orc_accept_one(const orc_scene *s, const double rx[3], int n, const int32_t 
                 for (int i = 0; i < 3; i++) nr[i] = 2.0 * (A[i][0] * w[0] + A[i][1] * w[1] + A[i][2] * w[2]) + rec[9 + i];
             }
             if (!(fabs(dot3(d, nr)) >= ORC_GRAZE * norm3(d) * norm3(nr))) return 0;
+            /* a refracting facet passes the ray to its other side, and the
+             * ray arrives in the medium the previous refracting facet of the
+             * path sent it into */
+            double nf, nb;
+            if (t == TP && refracts(s, ids[k], &nf, &nb)) {
+                const double *Q = (k == n - 1) ? rx : X + 3 * (k + 1);
+                double e[3];
+                sub3(Q, X + 3 * k, e);
+                if (!(dot3(d, nr) * dot3(e, nr) > 0.0)) return 0;
+                const double in = (dot3(d, nr) < 0.0) ? nf : nb, out = (dot3(d, nr) < 0.0) ? nb : nf;
+                if (medium > 0.0 && in != medium) return 0;
+                medium = out;
+            }
         }
     }
     return 1;

@@ -68,6 +68,10 @@ typedef struct {
     const double *sd;              /* [n_pl] side of each facet that faces free
                                       space: +1 along n, -1 against n, 0 both;
                                       NULL: every facet two-sided              */
+    const double *rf;              /* [n_pl][2] refractive indices of a facet
+                                      that refracts: (index on the side n
+                                      points to, index on the other side);
+                                      (0, 0) or NULL: the facet reflects      */
 } orc_scene;
 
 typedef struct {

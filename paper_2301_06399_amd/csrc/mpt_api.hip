@@ -25,9 +25,9 @@ struct mpt_ctx {
     int cu = 256;
     size_t lds_max = 65536;  // dynamic LDS a block may use
     // scene
-    double *raw = nullptr, *rec64 = nullptr, *wd = nullptr, *sd = nullptr;
+    double *raw = nullptr, *rec64 = nullptr, *wd = nullptr, *sd = nullptr, *rfd = nullptr;
     float *rec32 = nullptr;
-    size_t scene_cap = 0, raw_cap = 0, wd_cap = 0, sd_cap = 0;
+    size_t scene_cap = 0, raw_cap = 0, wd_cap = 0, sd_cap = 0, rfd_cap = 0;
     // candidate generation: sample points, their counts, path counts / offsets
     double *samp = nullptr;
     int *scnt = nullptr;
@@ -196,6 +196,7 @@ mpt_status mpt_destroy(mpt_ctx *c)
     hipFree(c->rec32);
     hipFree(c->wd);
     hipFree(c->sd);
+    hipFree(c->rfd);
     hipFree(c->samp);
     hipFree(c->scnt);
     hipFree(c->ccnt);
@@ -290,6 +291,12 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
         for (int i = 0; i < np; i++)
             if (d->sides[i] != -1.0 && d->sides[i] != 0.0 && d->sides[i] != 1.0)
                 return fail(c, MPT_E_INVALID_ARG, "plane %d: side is not -1, 0 or 1", i);
+    if (d->refraction)
+        for (int i = 0; i < np; i++) {
+            const double a = d->refraction[2 * (size_t)i], b = d->refraction[2 * (size_t)i + 1];
+            if (!((a == 0.0 && b == 0.0) || (a > 0.0 && b > 0.0 && isfinite(a) && isfinite(b))))
+                return fail(c, MPT_E_INVALID_ARG, "plane %d: refractive indices must be both positive or both 0", i);
+        }
     const size_t n_all = (size_t)np + nl + nq + nc;
     const size_t raw_n = (size_t)np * 13 + (size_t)nl * 8 + (size_t)nq * 17 + (size_t)nc * 7;
     hipSetDevice(c->device);
@@ -335,7 +342,13 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
         s.lo[i] = d->aabb_lo[i];
         s.hi[i] = d->aabb_hi[i];
     }
-    launch_pack(c->raw, s, np, nl, nq, nc, c->stream);
+    const bool refr = d->refraction && np > 0;
+    if (refr) {
+        if ((st = ensure(c, (void **)&c->rfd, &c->rfd_cap, (size_t)np * 2, sizeof(double)))) return st;
+        HIPCHK(c, hipMemcpyAsync(c->rfd, d->refraction, (size_t)np * 2 * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+    }
+    launch_pack(c->raw, refr ? c->rfd : nullptr, s, np, nl, nq, nc, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->s = s;
@@ -353,6 +366,7 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
     mix(d->aabb_lo, 3 * sizeof(double));
     mix(d->aabb_hi, 3 * sizeof(double));
     mix(host.data(), raw_n * sizeof(double));
+    if (refr) mix(d->refraction, (size_t)np * 2 * sizeof(double));
     c->scene_hash = h;
     c->curved = (nq + nc) > 0;
     c->param_ok = true;
@@ -650,7 +664,8 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
             // the network serves only the paths with a curved object: list
             // them (the polish list is free until the FP32 pass) and predict
             int *rows = (int *)kp.pol_list, *count = ctr + 30;
-            launch_curved_rows(bd, c->s, rows, count, s);
+            // block counts in the straggler list, free until the LM pass
+            launch_curved_rows(bd, c->s, rows, count, (int *)kp.spill_list, s);
             st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s, rows, count);
             if (!st) launch_learned_choose(c->s, bd, rows, count, false, w->x0l, opts->learned_gain, s);
         } else {
@@ -666,7 +681,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
         const size_t rec_bytes = (size_t)c->s.n_all * kRec * (md == MODE_FP32 ? sizeof(float) : sizeof(double));
         const bool lds = rec_bytes <= c->lds_max;
         auto go = [&](int ord, hipStream_t where) {
-            const int form = (md == MODE_FALLBACK64) ? MPT_FORM_IMPLICIT : form_used;
+            const int form = form_used;
             const void *k = lm_kernel(md, ord, lds, form);
             if (lds) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rec_bytes);
             int g = opts->grid;

@@ -23,7 +23,9 @@ enum : int { ST_CONV = 0, ST_MAXIT = 1, ST_STALL = 2, ST_DIVERGED = 3, ST_DEGEN 
              ST_BAD = 5, ST_LOCALMIN = 6, ST_OUTSIDE = 7, ST_PARKED = 250, ST_RUNNING = 255 };
 
 // Packed record layout (kRec wide), written by the scene pack kernel:
-//  plane   : n[0..2] d[3] o[4..6] eu[7..9] ev[10..12]
+//  plane   : n[0..2] d[3] o[4..6] eu[7..9] ev[10..12] e1[13..15] (eu/|eu|, the
+//            parametric frame) n_front[16] n_back[17] (refractive indices of a
+//            refracting facet; 0 for a mirror)
 //  line    : p[0..2] e[3..5] s0[6] s1[7] u1[8..10] u2[11..13]
 //  quadric : p[0..2] A[3..8] (xx xy xz yy yz zz) b[9..11] c[12] ax[13..15] rap[16]
 //  circle  : c[0..2] n[3..5] R[6]
@@ -149,9 +151,18 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
         const T ig = drsqrt(lg2);
         const T nh[3] = {g[0] * ig, g[1] * ig, g[2] * ig};
         const T s = dot3(ih, nh);
+        // a refracting facet (record entries 16, 17: the indices of the side
+        // the normal points to and of the other side): Snell's law, the part
+        // of n r^ along the facet equals that of n i^ (Sec. VI), with n_i the
+        // index of the side the ray arrives from
+        const bool refr = (t == TP) && (r[16] > T(0));
+        const T n_i = refr ? ((s < T(0)) ? r[16] : r[17]) : T(0);
+        const T n_t = refr ? ((s < T(0)) ? r[17] : r[16]) : T(0);
+        const T sr = dot3(rh, nh);
         T ul[3];
 #pragma unroll
-        for (int i = 0; i < 3; i++) ul[i] = rh[i] - ih[i] + T(2) * s * nh[i];
+        for (int i = 0; i < 3; i++)
+            ul[i] = refr ? n_t * (rh[i] - sr * nh[i]) - n_i * (ih[i] - s * nh[i]) : rh[i] - ih[i] + T(2) * s * nh[i];
 #pragma unroll
         for (int i = 0; i < 3; i++) u[i] = S * ul[i];
         u[3] = f;
@@ -186,17 +197,41 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
 #pragma unroll
                     for (int j = 0; j < 3; j++) TN[i][j] = T(0);
             }
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
+            if (refr) {
+                // u = n_t Pn r^ - n_i Pn i^, Pn = I - n n^T constant on a plane:
+                // dU/dX_{k-1} = n_i Pn Pa, dU/dX_{k+1} = n_t Pn Pb, dU/dX_k = -(both)
+                T ma[3], mb[3];
 #pragma unroll
                 for (int j = 0; j < 3; j++) {
-                    const T pa = ((i == j) ? ia : T(0)) - ih[i] * ih[j] * ia;
-                    const T pb = ((i == j) ? ib : T(0)) - rh[i] * rh[j] * ib;
-                    const T qpa = pa - nh[i] * m[j];
-                    // product rule with dS: dS/dX_{k-1} = -ih/2, dS/dX_k = (ih - rh)/2, dS/dX_{k+1} = rh/2
-                    Jp[i][j] = S * qpa - T(0.5) * ul[i] * ih[j];
-                    Jn[i][j] = S * pb + T(0.5) * ul[i] * rh[j];
-                    Jk[i][j] = S * (TN[i][j] - pb - qpa) + T(0.5) * ul[i] * (ih[j] - rh[j]);
+                    ma[j] = (nh[j] - s * ih[j]) * ia;
+                    mb[j] = (nh[j] - sr * rh[j]) * ib;
+                }
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+#pragma unroll
+                    for (int j = 0; j < 3; j++) {
+                        const T pa = ((i == j) ? ia : T(0)) - ih[i] * ih[j] * ia;
+                        const T pb = ((i == j) ? ib : T(0)) - rh[i] * rh[j] * ib;
+                        const T up = n_i * (pa - nh[i] * ma[j]);
+                        const T un = n_t * (pb - nh[i] * mb[j]);
+                        Jp[i][j] = S * up - T(0.5) * ul[i] * ih[j];
+                        Jn[i][j] = S * un + T(0.5) * ul[i] * rh[j];
+                        Jk[i][j] = -S * (up + un) + T(0.5) * ul[i] * (ih[j] - rh[j]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+#pragma unroll
+                    for (int j = 0; j < 3; j++) {
+                        const T pa = ((i == j) ? ia : T(0)) - ih[i] * ih[j] * ia;
+                        const T pb = ((i == j) ? ib : T(0)) - rh[i] * rh[j] * ib;
+                        const T qpa = pa - nh[i] * m[j];
+                        // product rule with dS: dS/dX_{k-1} = -ih/2, dS/dX_k = (ih - rh)/2, dS/dX_{k+1} = rh/2
+                        Jp[i][j] = S * qpa - T(0.5) * ul[i] * ih[j];
+                        Jn[i][j] = S * pb + T(0.5) * ul[i] * rh[j];
+                        Jk[i][j] = S * (TN[i][j] - pb - qpa) + T(0.5) * ul[i] * (ih[j] - rh[j]);
+                    }
                 }
             }
 #pragma unroll

@@ -80,7 +80,8 @@ struct KParams {
     double *spill_f;           // [2][n] damping and plateau reference of a parked path
 };
 
-void launch_pack(const double *raw, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c, hipStream_t st);
+void launch_pack(const double *raw, const double *refr, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c,
+                 hipStream_t st);
 void launch_zero(int *p, int n, hipStream_t st);
 int bin_key_count();
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
@@ -89,7 +90,7 @@ const void *lm_kernel(int mode, int order, bool lds, int form);
 void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const KParams &kp, int grid, int block,
                hipStream_t st);
 const void *polish_kernel();
-void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st);
+void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, int *blk, hipStream_t st);
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
                            double *x0l, double gain, hipStream_t st);
 void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);

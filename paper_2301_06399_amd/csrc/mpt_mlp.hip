@@ -65,58 +65,82 @@ __device__ __forceinline__ float gelu_d(float z)
 // one-hot type, then the object in the frame - plane: n, (d - n.TX)/L;
 // straight edge: e, the edge point nearest TX; quadric: anchor, L A, b;
 // circle: centre, normal, R/L - then a present bit.  Unused slots are zero.
+// Frame of row i: its receiver and the scale L = |RX - TX| (1 when RX is
+// missing or coincides with TX).
+__device__ __forceinline__ double row_frame(const SceneDev &s, const BatchDev &b, int i, double rx[3])
+{
+    const int ri = b.rx_index[i];
+    const bool ok_rx = ri >= 0 && ri < b.n_rx;
+    for (int c = 0; c < 3; c++) rx[c] = ok_rx ? b.rx[3 * (size_t)ri + c] : 0.0;
+    double L = sqrt((rx[0] - s.tx[0]) * (rx[0] - s.tx[0]) + (rx[1] - s.tx[1]) * (rx[1] - s.tx[1]) +
+                    (rx[2] - s.tx[2]) * (rx[2] - s.tx[2]));
+    if (!(L > 0.0) || !isfinite(L)) L = 1.0;
+    return L;
+}
+
+// The SLOT features of interaction k of row i (zeros beyond its order or
+// for an invalid id).
+__device__ __forceinline__ void slot_features(const SceneDev &s, const BatchDev &b, int i, int k, int ord, double L,
+                                              float f[SLOT])
+{
+#pragma unroll
+    for (int j = 0; j < SLOT; j++) f[j] = 0.0f;
+    if (k >= ord) return;
+    const int id = b.prim[(size_t)k * b.n + i];
+    if (id < 0 || id >= s.n_all) return;
+    const double is = 1.0 / L;
+    const int t = prim_type(id, s.n_pl, s.n_pl_ln, s.n_pl_ln_q);
+    const double *q = s.rec64 + (size_t)id * kRec;
+    float p[12];
+#pragma unroll
+    for (int j = 0; j < 12; j++) p[j] = 0.0f;
+    if (t == TP) {
+        for (int c = 0; c < 3; c++) p[c] = (float)q[c];
+        p[3] = (float)((q[3] - (q[0] * s.tx[0] + q[1] * s.tx[1] + q[2] * s.tx[2])) * is);
+    } else if (t == TL) {
+        const double w = (s.tx[0] - q[0]) * q[3] + (s.tx[1] - q[1]) * q[4] + (s.tx[2] - q[2]) * q[5];
+        for (int c = 0; c < 3; c++) {
+            p[c] = (float)q[3 + c];
+            p[3 + c] = (float)((q[c] + w * q[3 + c] - s.tx[c]) * is);
+        }
+    } else if (t == TQ) {
+        for (int c = 0; c < 3; c++) p[c] = (float)((q[c] - s.tx[c]) * is);
+        for (int c = 0; c < 6; c++) p[3 + c] = (float)(q[3 + c] * L);
+        for (int c = 0; c < 3; c++) p[9 + c] = (float)q[9 + c];
+    } else {
+        for (int c = 0; c < 3; c++) {
+            p[c] = (float)((q[c] - s.tx[c]) * is);
+            p[3 + c] = (float)q[3 + c];
+        }
+        p[6] = (float)(q[6] * is);
+    }
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++) f[tt] = (t == tt) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 12; j++) f[4 + j] = p[j];
+    f[16] = 1.0f;
+}
+
+// Frame: origin TX, scale 1/L with L = |RX - TX|.  Per interaction slot k:
+// one-hot type, then the object in the frame - plane: n, (d - n.TX)/L;
+// straight edge: e, the edge point nearest TX; quadric: anchor, L A, b;
+// circle: centre, normal, R/L - then a present bit.  Unused slots are zero.
 __device__ __forceinline__ void row_features(const SceneDev &s, const BatchDev &b, int i, float f[F_IN], double &Lout)
 {
 #pragma unroll
     for (int j = 0; j < F_IN; j++) f[j] = 0.0f;
     const int ord = b.order[i];
-    const int ri = b.rx_index[i];
-    const bool ok_rx = ri >= 0 && ri < b.n_rx;
-    double rx[3] = {0, 0, 0};
-    if (ok_rx)
-        for (int c = 0; c < 3; c++) rx[c] = b.rx[3 * (size_t)ri + c];
-    double L = sqrt((rx[0] - s.tx[0]) * (rx[0] - s.tx[0]) + (rx[1] - s.tx[1]) * (rx[1] - s.tx[1]) +
-                    (rx[2] - s.tx[2]) * (rx[2] - s.tx[2]));
-    if (!(L > 0.0) || !isfinite(L)) L = 1.0;
+    double rx[3];
+    const double L = row_frame(s, b, i, rx);
     Lout = L;
     const double is = 1.0 / L;
     for (int c = 0; c < 3; c++) f[c] = (float)((rx[c] - s.tx[c]) * is);
 #pragma unroll
     for (int k = 0; k < kMaxN; k++) {
-        if (k >= ord) continue;
-        const int id = b.prim[(size_t)k * b.n + i];
-        if (id < 0 || id >= s.n_all) continue;
-        const int t = prim_type(id, s.n_pl, s.n_pl_ln, s.n_pl_ln_q);
-        const double *q = s.rec64 + (size_t)id * kRec;
-        const int base = 6 + SLOT * k;
-        float p[12];
+        float g[SLOT];
+        slot_features(s, b, i, k, ord, L, g);
 #pragma unroll
-        for (int j = 0; j < 12; j++) p[j] = 0.0f;
-        if (t == TP) {
-            for (int c = 0; c < 3; c++) p[c] = (float)q[c];
-            p[3] = (float)((q[3] - (q[0] * s.tx[0] + q[1] * s.tx[1] + q[2] * s.tx[2])) * is);
-        } else if (t == TL) {
-            const double w = (s.tx[0] - q[0]) * q[3] + (s.tx[1] - q[1]) * q[4] + (s.tx[2] - q[2]) * q[5];
-            for (int c = 0; c < 3; c++) {
-                p[c] = (float)q[3 + c];
-                p[3 + c] = (float)((q[c] + w * q[3 + c] - s.tx[c]) * is);
-            }
-        } else if (t == TQ) {
-            for (int c = 0; c < 3; c++) p[c] = (float)((q[c] - s.tx[c]) * is);
-            for (int c = 0; c < 6; c++) p[3 + c] = (float)(q[3 + c] * L);
-            for (int c = 0; c < 3; c++) p[9 + c] = (float)q[9 + c];
-        } else {
-            for (int c = 0; c < 3; c++) {
-                p[c] = (float)((q[c] - s.tx[c]) * is);
-                p[3 + c] = (float)q[3 + c];
-            }
-            p[6] = (float)(q[6] * is);
-        }
-#pragma unroll
-        for (int tt = 0; tt < 4; tt++) f[base + tt] = (t == tt) ? 1.0f : 0.0f;
-#pragma unroll
-        for (int j = 0; j < 12; j++) f[base + 4 + j] = p[j];
-        f[base + 16] = 1.0f;
+        for (int j = 0; j < SLOT; j++) f[6 + SLOT * k + j] = g[j];
     }
 }
 
@@ -567,19 +591,31 @@ __global__ void __launch_bounds__(512, 1) k_mlp_fused(SceneDev s, BatchDev b, co
     }
     // persistent: the block walks the 128-path tiles
     for (int row0 = blockIdx.x * IR; row0 < nrows; row0 += gridDim.x * IR) {
-    if (tid < IR) {
-        float f[F_IN];
-        double L = 1.0;
-        const int r = row0 + tid;
+    {
+        // features, four threads per path: thread q of a path writes slot q
+        // (and thread 0 the receiver, slot 4 and the zero padding)
+        const int pr = tid >> 2, q = tid & 3;
+        const int r = row0 + pr;
         const int i = (r < nrows) ? (rows ? rows[r] : r) : -1;
-        if (i >= 0) row_features(s, b, i, f, L);
-        else
-            for (int j = 0; j < F_IN; j++) f[j] = 0.0f;
-        Ls[tid] = L;
-        ids[tid] = i;
-        uint32_t *dst = reinterpret_cast<uint32_t *>(bufA + tid * ILD);
-#pragma unroll
-        for (int j = 0; j < F_IN; j += 2) dst[j / 2] = (uint32_t)f2bf(f[j]) | ((uint32_t)f2bf(f[j + 1]) << 16);
+        bf16 *dst = bufA + pr * ILD;
+        double rx[3] = {0.0, 0.0, 0.0};
+        const double L = (i >= 0) ? row_frame(s, b, i, rx) : 1.0;
+        const int ord = (i >= 0) ? b.order[i] : 0;
+        float g[SLOT];
+        slot_features(s, b, i < 0 ? 0 : i, q, i < 0 ? 0 : ord, L, g);
+        for (int j = 0; j < SLOT; j++) dst[6 + SLOT * q + j] = f2bf(g[j]);
+        if (q == 0) {
+            const double is = 1.0 / L;
+            for (int c = 0; c < 3; c++) {
+                dst[c] = f2bf(i >= 0 ? (float)((rx[c] - s.tx[c]) * is) : 0.0f);
+                dst[3 + c] = f2bf(0.0f);
+            }
+            slot_features(s, b, i < 0 ? 0 : i, 4, i < 0 ? 0 : ord, L, g);
+            for (int j = 0; j < SLOT; j++) dst[6 + SLOT * 4 + j] = f2bf(g[j]);
+            for (int j = 6 + SLOT * kMaxN; j < F_IN; j++) dst[j] = f2bf(0.0f);
+            Ls[pr] = L;
+            ids[pr] = i;
+        }
     }
     __syncthreads();
     infer_layer<F_IN>(bufA, bufB, wb + OW1_, w + OB1_, tab, wave, lane);

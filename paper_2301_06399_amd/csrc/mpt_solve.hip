@@ -16,8 +16,9 @@ namespace mpt {
 // ------------------------------------------------------------------ pack
 // Ortho-normal pair across a unit vector (Duff et al., "Building an
 // orthonormal basis, revisited", JCGT 2017).
-__global__ void k_pack(const double *__restrict__ raw, int n_pl, int n_ln, int n_q, int n_c, double tx0, double tx1,
-                       double tx2, double *__restrict__ rec64, float *__restrict__ rec32)
+__global__ void k_pack(const double *__restrict__ raw, const double *__restrict__ refr, int n_pl, int n_ln, int n_q,
+                       int n_c, double tx0, double tx1, double tx2, double *__restrict__ rec64,
+                       float *__restrict__ rec32)
 {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     const int n_all = n_pl + n_ln + n_q + n_c;
@@ -41,6 +42,11 @@ __global__ void k_pack(const double *__restrict__ raw, int n_pl, int n_ln, int n
     if (t == TP) {
         const double l = sqrt(r[7] * r[7] + r[8] * r[8] + r[9] * r[9]);
         for (int i = 0; i < 3; i++) o[13 + i] = l > 0.0 ? r[7 + i] / l : 0.0;
+        // refractive indices of a refracting facet (0, 0: a mirror)
+        if (refr) {
+            o[16] = refr[2 * (size_t)id];
+            o[17] = refr[2 * (size_t)id + 1];
+        }
     }
     if (t == TC) across_dir(r + 3, o + 7, o + 10);
     if (t == TQ) {
@@ -227,23 +233,73 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
 
 // Ids of the valid solves whose list holds a quadric or a circle (the paths
 // the learned start serves), appended with wave-aggregated atomics.
-__global__ void __launch_bounds__(256) k_curved_rows(BatchDev b, int n_all, int n_pl_ln, int *__restrict__ rows,
-                                                      int *__restrict__ count)
+// The solves with a paraboloid or circle, listed in increasing id order
+// without a contended counter: each of the grid's blocks owns a contiguous
+// range of solves; pass 1 counts per block, pass 2 scans the block counts
+// (one block), pass 3 writes each block's solves at its offset.
+__device__ __forceinline__ bool curved_row(const BatchDev &b, int64_t i, int n_all, int n_pl_ln)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool mine = false;
     if (i < b.n) {
         const int ord = valid_order(b, i, n_all);
         for (int k = 0; k < kMaxN; k++)
             if (k < ord) mine = mine || b.prim[(size_t)k * b.n + i] >= n_pl_ln;
     }
-    const uint64_t m = __ballot(mine);
-    if (!m) return;
-    const int leader = (int)__builtin_ctzll(m);
-    int base = 0;
-    if (__lane_id() == leader) base = atomicAdd(count, (int)__popcll(m));
-    base = __shfl(base, leader);
-    if (mine) rows[base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull))] = (int)i;
+    return mine;
+}
+
+__global__ void __launch_bounds__(256) k_curved_count(BatchDev b, int n_all, int n_pl_ln, int64_t per,
+                                                       int *__restrict__ blk_cnt)
+{
+    __shared__ int red[4];
+    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(b.n, i0 + per);
+    int c = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) c += curved_row(b, i, n_all, n_pl_ln);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// exclusive scan of nblk (<= 1024) counts in place; *count = the total
+__global__ void __launch_bounds__(1024) k_curved_scan(int *__restrict__ blk_cnt, int nblk, int *__restrict__ count)
+{
+    __shared__ int s[1024];
+    const int t = threadIdx.x;
+    s[t] = (t < nblk) ? blk_cnt[t] : 0;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = (t >= o) ? s[t - o] : 0;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    if (t < nblk) blk_cnt[t] = s[t] - ((t < nblk) ? blk_cnt[t] : 0);
+    if (t == 1023) *count = s[t];
+}
+
+__global__ void __launch_bounds__(256) k_curved_fill(BatchDev b, int n_all, int n_pl_ln, int64_t per,
+                                                      const int *__restrict__ blk_off, int *__restrict__ rows)
+{
+    __shared__ int wsum[4];
+    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(b.n, i0 + per);
+    int base = blk_off[blockIdx.x];
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    for (int64_t j0 = i0; j0 < i1; j0 += blockDim.x) {
+        const int64_t i = j0 + threadIdx.x;
+        const bool mine = (i < i1) && curved_row(b, i, n_all, n_pl_ln);
+        const uint64_t m = __ballot(mine);
+        if (lane == 0) wsum[w] = (int)__popcll(m);
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int q = 0; q < 4; q++) {
+            before += (q < w) ? wsum[q] : 0;
+            tot += wsum[q];
+        }
+        if (mine) rows[base + before + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int)i;
+        base += tot;
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------ init
@@ -309,6 +365,21 @@ __device__ inline bool in_guard(const SceneDev &s, const double *X, int n)
 // straight-line start of a path only when their FP64 cost is lower: the
 // solver's own cost judges the prediction.  Writes the chosen start points
 // into x0l (rows of the path; one thread per served path).
+// Fraction along TX -> RX of the straight-line start of interaction k of N:
+// k+1 over N+1, or, on a refracting facet (which the ray crosses), the
+// point where the segment meets its plane when it does.
+__device__ __forceinline__ double line_fraction(int ty, const double *r, const double *tx, const double *rx, int k,
+                                                int N)
+{
+    double a = (double)(k + 1) / (double)(N + 1);
+    if (ty == TP && r[16] > 0.0) {
+        const double den = r[0] * (rx[0] - tx[0]) + r[1] * (rx[1] - tx[1]) + r[2] * (rx[2] - tx[2]);
+        const double c = (den != 0.0) ? (r[3] - (r[0] * tx[0] + r[1] * tx[1] + r[2] * tx[2])) / den : -1.0;
+        if (c > 0.0 && c < 1.0) a = c;
+    }
+    return a;
+}
+
 template <int N>
 __device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, double *__restrict__ x0l, double gain)
 {
@@ -333,7 +404,7 @@ __device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, do
     bool okn = true;
 #pragma unroll
     for (int k = 0; k < N; k++) {
-        const double a = (double)(k + 1) / (double)(N + 1);
+        const double a = line_fraction(q.ty[k], s.rec64 + (size_t)q.id[k] * kRec, s.tx, q.rx, k, N);
         double P[3], Pn[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
@@ -628,6 +699,7 @@ __device__ bool sides_forbid_root(const SceneDev &s, const int *id, const int *t
     for (int k = 0; k < N; k++) {
         if (ty[k] != TP) continue;
         const double *r = s.rec64 + (size_t)id[k] * kRec;
+        if (r[16] > 0.0) continue;  // a refracting facet passes the ray to its other side
         const double n[3] = {r[0], r[1], r[2]}, o[3] = {r[4], r[5], r[6]};
         double a = 0.0, b = 0.0;
         bool ka = true, kb = true;
@@ -815,7 +887,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     for (int k = 0; k < N; k++) {
                         p.id[k] = kp.b.prim[(size_t)k * kp.b.n + sid];
                         p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
-                        p.planar = p.planar && (p.ty[k] == TP || p.ty[k] == TL);
+                        p.planar = p.planar && (p.ty[k] == TL ||
+                                                (p.ty[k] == TP && kp.s.rec64[(size_t)p.id[k] * kRec + 16] <= 0.0));
                     }
                     const double sh[3] = {MODE == MODE_FP32 ? kp.s.tx[0] : 0.0, MODE == MODE_FP32 ? kp.s.tx[1] : 0.0,
                                           MODE == MODE_FP32 ? kp.s.tx[2] : 0.0};
@@ -848,7 +921,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                         const bool rnd = init == INIT_RANDOM;
 #pragma unroll
                         for (int k = 0; k < N; k++) {
-                            const double a = (double)(k + 1) / (double)(N + 1);
+                            const double *rk = kp.s.rec64 + (size_t)p.id[k] * kRec;
+                            const double a = line_fraction(p.ty[k], rk, kp.s.tx, rx, k, N);
                             double P[3];
 #pragma unroll
                             for (int i = 0; i < 3; i++) {
@@ -945,13 +1019,15 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
             if (!park) {
                 st = -1;
                 if constexpr (TYPED && MODE == MODE_FP32 && FORM == 1 && N <= 3) {
-                    // every planar path takes its fixed-type step, whatever
-                    // the other lanes of its wave hold, so that its result
-                    // does not depend on the schedule
-                    int code = 0;
+                    if (p.planar) {
+                        // every planar path takes its fixed-type step, whatever
+                        // the other lanes of its wave hold, so that its result
+                        // does not depend on the schedule
+                        int code = 0;
 #pragma unroll
-                    for (int k = 0; k < N; k++) code |= p.ty[k] << (2 * k);
-                    st = lm_step_uniform<T, N, FORM>(code, sc, p, L, o);
+                        for (int k = 0; k < N; k++) code |= p.ty[k] << (2 * k);
+                        st = lm_step_uniform<T, N, FORM>(code, sc, p, L, o);
+                    }
                 }
                 if (st == -1) {
                     if constexpr (FORM) st = lm_step_param<T, N>(sc, p, L, o);
@@ -1009,10 +1085,39 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     // alone is no evidence that none exists), or - decided
                     // by the polish - a converged or stalled FP32 point that
                     // does not polish
-                    const bool small_res = (double)L.rinf <= kp.o.polish_gate;
+                    // the gate is at least 30 times the FP32 rounding level of
+                    // this path's residual: a law row carries the rounding of
+                    // its unit directions (eps32 |X| / shortest segment) times
+                    // its scale (up to the longest segment), which reaches
+                    // 1e-2 m on a thin glass pane far from TX
+                    const double rx_w[3] = {(double)p.rx[0] + sh[0], (double)p.rx[1] + sh[1], (double)p.rx[2] + sh[2]};
+                    double xmax = 0.0, smin = __builtin_huge_val(), smax = 0.0;
+#pragma unroll
+                    for (int k = 0; k <= N; k++) {
+                        double e2 = 0.0;
+#pragma unroll
+                        for (int i = 0; i < 3; i++) {
+                            const double a = (k == 0) ? kp.s.tx[i] : Xw[3 * (k - 1) + i];
+                            const double bq = (k == N) ? rx_w[i] : Xw[3 * k + i];
+                            e2 += (bq - a) * (bq - a);
+                            if (k < N) xmax = fmax(xmax, fabs(Xw[3 * k + i] - kp.s.tx[i]));
+                        }
+                        smin = fmin(smin, sqrt(e2));
+                        smax = fmax(smax, sqrt(e2));
+                    }
+                    const double noise = 6e-8 * (1.0 + xmax) * smax / fmax(smin, 1e-12);
+                    const bool small_res = (double)L.rinf <= fmax(kp.o.polish_gate, 30.0 * noise);
                     bool to_polish = small_res && (st == ST_CONV || st == ST_MAXIT || st == ST_LOCALMIN ||
                                                    st == ST_STALL);
-                    const bool to_fb = (st == ST_DEGEN) || (st == ST_MAXIT && p.planar && !small_res);
+                    // a path through a refracting facet has a unique root
+                    // (the optical length is convex), so a descent that ends
+                    // far from a root goes to the FP64 fallback as well
+                    bool refr_path = false;
+#pragma unroll
+                    for (int k = 0; k < N; k++)
+                        refr_path = refr_path || (p.ty[k] == TP && kp.s.rec64[(size_t)p.id[k] * kRec + 16] > 0.0);
+                    const bool to_fb = (st == ST_DEGEN) || (st == ST_MAXIT && p.planar && !small_res) ||
+                                       (refr_path && !small_res);
                     // a root-like end point far outside a finite extent: the
                     // polish and the fallback stay next to it (within a few
                     // times its residual), so the path cannot be accepted
@@ -1239,6 +1344,7 @@ __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, 
         const double d[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
         ok = ok && (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= min_seg);
     }
+    double medium = 0.0;  // index of the medium the ray travels in (0: not yet known)
 #pragma unroll
     for (int k = 0; k < N; k++) {
         const double *r = s.rec64 + (size_t)id[k] * kRec;
@@ -1275,6 +1381,18 @@ __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, 
             const double lv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
             const double ln = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
             ok = ok && (fabs(vn) >= kGraze * lv * ln);
+            if (ty[k] == TP && r[16] > 0.0) {
+                // a refracting facet passes the ray to its other side, and the
+                // ray arrives in the medium the previous refracting facet of
+                // the path sent it into
+                const double *Q = (k == N - 1) ? rx : X + 3 * (k + 1);
+                const double e[3] = {Q[0] - x[0], Q[1] - x[1], Q[2] - x[2]};
+                const double en = e[0] * nr[0] + e[1] * nr[1] + e[2] * nr[2];
+                ok = ok && (vn * en > 0.0);
+                const double in = (vn < 0.0) ? r[16] : r[17], out = (vn < 0.0) ? r[17] : r[16];
+                ok = ok && !(medium > 0.0 && in != medium);
+                medium = out;
+            }
         }
     }
     return ok;
@@ -1366,12 +1484,13 @@ __global__ void __launch_bounds__(256) k_accept_scatter(const uint8_t *__restric
 }
 
 // ------------------------------------------------------------------ host launchers
-void launch_pack(const double *raw, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c, hipStream_t st)
+void launch_pack(const double *raw, const double *refr, const SceneDev &s, int n_pl, int n_ln, int n_q, int n_c,
+                 hipStream_t st)
 {
     const int n = n_pl + n_ln + n_q + n_c;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_pack, dim3((n + 127) / 128), dim3(128), 0, st, raw, n_pl, n_ln, n_q, n_c, s.tx[0], s.tx[1],
-                       s.tx[2], (double *)s.rec64, (float *)s.rec32);
+    hipLaunchKernelGGL(k_pack, dim3((n + 127) / 128), dim3(128), 0, st, raw, refr, n_pl, n_ln, n_q, n_c, s.tx[0],
+                       s.tx[1], s.tx[2], (double *)s.rec64, (float *)s.rec32);
 }
 
 void launch_zero(int *p, int n, hipStream_t st)
@@ -1410,8 +1529,8 @@ static const void *lm_kernel_t(int order)
 }
 
 // order 0: the mixed-order kernel; 1..5: the per-order kernels; 6: the
-// kernel of orders 1-3
-// The fallback always runs the implicit form (from the FP32 end point).
+// kernel of orders 1-3.  The fallback runs one mixed-order launch in the
+// solve's form (from the FP32 end point).
 const void *lm_kernel(int mode, int order, bool lds, int form)
 {
     switch (mode) {
@@ -1422,6 +1541,7 @@ const void *lm_kernel(int mode, int order, bool lds, int form)
         if (form) return lds ? lm_kernel_t<MODE_FP32, true, 1>(order) : lm_kernel_t<MODE_FP32, false, 1>(order);
         return lds ? lm_kernel_t<MODE_FP32, true, 0>(order) : lm_kernel_t<MODE_FP32, false, 0>(order);
     default:
+        if (form) return lds ? (const void *)k_lm<MODE_FALLBACK64, true, 1> : (const void *)k_lm<MODE_FALLBACK64, false, 1>;
         return lds ? lm_kernel_t<MODE_FALLBACK64, true, 0>(order) : lm_kernel_t<MODE_FALLBACK64, false, 0>(order);
     }
 }
@@ -1435,11 +1555,16 @@ void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const 
 
 const void *polish_kernel() { return (const void *)k_polish; }
 
-void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, hipStream_t st)
+void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, int *blk, hipStream_t st)
 {
     if (b.n == 0) return;
-    hipLaunchKernelGGL(k_curved_rows, dim3((unsigned)((b.n + 255) / 256)), dim3(256), 0, st, b, s.n_all, s.n_pl_ln,
-                       rows, count);
+    // blocks of at least 256 solves, at most 1024 of them (blk holds one
+    // count each; the caller's scratch has at least that many entries)
+    const int64_t nblk = std::min<int64_t>(1024, (b.n + 255) / 256);
+    const int64_t per = (b.n + nblk - 1) / nblk;
+    hipLaunchKernelGGL(k_curved_count, dim3((unsigned)nblk), dim3(256), 0, st, b, s.n_all, s.n_pl_ln, per, blk);
+    hipLaunchKernelGGL(k_curved_scan, dim3(1), dim3(1024), 0, st, blk, (int)nblk, count);
+    hipLaunchKernelGGL(k_curved_fill, dim3((unsigned)nblk), dim3(256), 0, st, b, s.n_all, s.n_pl_ln, per, blk, rows);
 }
 
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,

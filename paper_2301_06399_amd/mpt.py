@@ -35,7 +35,7 @@ class SceneDesc(C.Structure):
                 ("n_planes", C.c_int32), ("n_lines", C.c_int32), ("n_quadrics", C.c_int32),
                 ("n_circles", C.c_int32), ("planes", C.c_void_p), ("lines", C.c_void_p),
                 ("quadrics", C.c_void_p), ("circles", C.c_void_p), ("wedges", C.c_void_p),
-                ("sides", C.c_void_p)]
+                ("sides", C.c_void_p), ("refraction", C.c_void_p)]
 
 
 class BatchDesc(C.Structure):
@@ -291,6 +291,12 @@ class Context:
             if sd.shape != (len(keep[0]),):
                 raise ValueError("sides: one value per plane facet")
             d.sides = sd.ctypes.data
+        rf = getattr(scene, "refraction", None)
+        if rf is not None and len(rf):
+            rf = np.ascontiguousarray(rf, np.float64)
+            if rf.shape != (len(keep[0]), 2):
+                raise ValueError("refraction: two indices per plane facet")
+            d.refraction = rf.ctypes.data
         self._check(self.L.mpt_scene_upload(self.h, C.byref(d)), "mpt_scene_upload")
         self.n_all = int(sum(len(a) for a in keep))
 

@@ -26,6 +26,11 @@ solid lies where both <x - X, m1> and <x - X, m2> are negative), 2 an inner
 corner (the solid lies where either is negative).  Physical validation uses
 it to keep diffracted rays out of the solids.
 
+Optional refractive indices of each plane facet (two values, empty array:
+none): a facet with both indices positive refracts instead of reflecting
+(Snell's law; the first index is that of the side its normal points to, the
+second that of the other side); (0, 0) marks a mirror.
+
 Optional side of each plane facet (one value, empty array: none): +1 free
 space lies on the side the normal points to, -1 on the other side, 0 on
 both (a thin two-sided surface).  The visibility matrix of the candidate
@@ -62,15 +67,18 @@ class Scene:
     sides: np.ndarray = field(default_factory=lambda: np.zeros(0))
     aabb_lo: np.ndarray = field(default_factory=lambda: np.zeros(3))
     aabb_hi: np.ndarray = field(default_factory=lambda: np.zeros(3))
+    refraction: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
 
     def __post_init__(self):
         self.tx = np.ascontiguousarray(self.tx, dtype=np.float64)
-        for k in ("planes", "lines", "quadrics", "circles", "wedges", "sides"):
+        for k in ("planes", "lines", "quadrics", "circles", "wedges", "sides", "refraction"):
             setattr(self, k, np.ascontiguousarray(getattr(self, k), dtype=np.float64))
         if len(self.wedges) and self.wedges.shape != (len(self.lines), WEDGE_W):
             raise ValueError("wedges: one record of 7 values per straight edge, or none")
         if len(self.sides) and self.sides.shape != (len(self.planes),):
             raise ValueError("sides: one value per plane facet, or none")
+        if len(self.refraction) and self.refraction.shape != (len(self.planes), 2):
+            raise ValueError("refraction: two indices per plane facet, or none")
         self.aabb_lo = np.ascontiguousarray(self.aabb_lo, dtype=np.float64)
         self.aabb_hi = np.ascontiguousarray(self.aabb_hi, dtype=np.float64)
 
@@ -526,4 +534,94 @@ def training_batch(cfg: int, n_rx: int, per_rx: int = 64, stream: str = "train")
     return sc, Batch(rx, rx_index, order, prim)
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
+# ---------------------------------------------------------------- refraction
+def glazed_scene(n_panes: int = 40) -> Scene:
+    """The street canyon plus glass panes standing in the streets: each pane
+    is a slab of two parallel vertical refracting facets (glass index 1.5
+    inside, 1.0 outside), thickness U(0.1, 0.5) m, width U(4, 12) m, height
+    U(3, 10) m from the ground, facing x or y, centred in free space.  The
+    box facets stay mirrors."""
+    sc = street_canyon_scene(6)
+    rng = np.random.default_rng(seed(6, "scene") + 91)
+    planes, refr, sides = [list(p) for p in sc.planes], [[0.0, 0.0]] * len(sc.planes), list(sc.sides)
+    xy = sc._free_xy(rng, n_panes, margin=8.0)
+    panes = []
+    for (cx, cy) in xy:
+        t, w, h = rng.uniform(0.1, 0.5), rng.uniform(4, 12), rng.uniform(3, 10)
+        ax = int(rng.integers(0, 2))          # 0: faces along x, 1: along y
+        nrm = np.array([1.0, 0.0, 0.0]) if ax == 0 else np.array([0.0, 1.0, 0.0])
+        tan = np.array([0.0, 1.0, 0.0]) if ax == 0 else np.array([1.0, 0.0, 0.0])
+        c = np.array([cx, cy, 0.0])
+        for sgn in (-1.0, 1.0):
+            n = sgn * nrm                     # outward normal: air (1.0) in front, glass (1.5) behind
+            o = c + 0.5 * t * n - 0.5 * w * tan
+            planes.append(plane_rect(n, n @ o, o, w * tan, [0.0, 0.0, h]))
+            refr.append([1.0, 1.5])
+            sides.append(0.0)
+        panes.append((c, nrm, tan, t, w, h))
+    out = Scene(tx=sc.tx, planes=np.array(planes), lines=sc.lines, wedges=sc.wedges, sides=np.array(sides),
+                refraction=np.array(refr), aabb_lo=sc.aabb_lo, aabb_hi=sc.aabb_hi)
+    out._boxes, out._free_xy = sc._boxes, sc._free_xy
+    out._n_box_planes = len(sc.planes)
+    out._panes = panes
+    return out
+
+
+def config6(n_rx: int = 4096, per_rx: int = 64) -> tuple[Scene, Batch]:
+    """Paths through glass panes.  Receiver i stands 1-8 m behind pane
+    i mod 40 (on the side away from TX, within its width, at 1.5 m, outside
+    the boxes).  Its lists have order 2-4 and hold the two facets of that
+    pane back to back in the order a ray from TX crosses them (into the
+    glass, out again), at a random position; the other elements are drawn
+    uniformly over the box facets and edges, no immediate repeat."""
+    sc = glazed_scene()
+    rng = np.random.default_rng(seed(6, "rx"))
+    nb = sc._n_box_planes
+    n_panes = len(sc._panes)
+    rx = np.zeros((n_rx, 3))
+    first = np.zeros(n_rx, np.int32)
+    for i in range(n_rx):
+        c, nrm, tan, t, w, h = sc._panes[i % n_panes]
+        away = -1.0 if (sc.tx - c) @ nrm > 0 else 1.0     # the side away from TX
+        for attempt in range(200):
+            # behind the pane; after 100 failed draws (a box or the map's
+            # edge behind it) in front of it (then no path crosses the pane)
+            side = away if attempt < 100 else -away
+            p = c + side * nrm * (0.5 * t + rng.uniform(1.0, 8.0)) + tan * rng.uniform(-0.4, 0.4) * w
+            inside = False
+            for cx, cy, bw, bd, bh in sc._boxes:
+                inside |= abs(p[0] - cx) < bw / 2 + 1.0 and abs(p[1] - cy) < bd / 2 + 1.0
+            if not inside and 1 < p[0] < 199 and 1 < p[1] < 199:
+                break
+        else:
+            p = np.append(sc._free_xy(rng, 1)[0], 0.0)
+        rx[i] = [p[0], p[1], 1.5]
+        # the facet whose outward normal faces TX is crossed first
+        first[i] = nb + 2 * (i % n_panes) + (0 if away > 0 else 1)
+    rs = np.random.default_rng(seed(6, "seq"))
+    n = n_rx * per_rx
+    rx_index = np.repeat(np.arange(n_rx, dtype=np.int32), per_rx)
+    others = np.concatenate([np.arange(nb), np.arange(len(sc.planes), sc.n_prims)]).astype(np.int32)
+    order = rs.integers(2, 5, n).astype(np.int32)
+    pos = (rs.random(n) * (order - 1)).astype(np.int32)        # slot of the first pane facet
+    f0 = first[rx_index]
+    f1 = np.where((f0 - nb) % 2 == 0, f0 + 1, f0 - 1).astype(np.int32)
+    prim = -np.ones((MAX_ORDER, n), np.int32)
+    for k in range(MAX_ORDER):
+        prim[k] = np.where(k < order, others[rs.integers(0, len(others), n)], -1)
+    for k in range(MAX_ORDER):
+        prim[k] = np.where(pos == k, f0, prim[k])
+        prim[k] = np.where(pos + 1 == k, f1, prim[k])
+    fixed = lambda k: (pos == k) | (pos + 1 == k)
+    for k in range(1, MAX_ORDER):
+        rep = (k < order) & (prim[k] == prim[k - 1])
+        while rep.any():
+            a = rep & ~fixed(k)
+            prim[k, a] = others[rs.integers(0, len(others), int(a.sum()))]
+            b = rep & fixed(k)
+            prim[k - 1, b] = others[rs.integers(0, len(others), int(b.sum()))]
+            rep = (k < order) & (prim[k] == prim[k - 1])
+    return sc, Batch(rx, rx_index, order, prim)
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5, 6: config6}

@@ -71,33 +71,39 @@ def image_method(tx, rx, normals, offsets):
 
 
 # ---------------------------------------------------------------- Fermat
-def _fermat_eval(tx, rx, O, Bm, z, eps, want_hess=True):
-    """Smoothed length sum_j sqrt(|d_j|^2 + eps^2), its gradient and Hessian
-    in the parameters z [B,n,2] of the points P_k = O_k + Bm_k z_k (O [B,n,3],
-    Bm [B,n,3,2] with orthonormal columns; a line's second column is zero).
+def _fermat_eval(tx, rx, O, Bm, z, eps, want_hess=True, wt=None):
+    """Smoothed optical length sum_j wt_j sqrt(|d_j|^2 + eps^2) (wt: the
+    refractive index of each segment's medium, 1 by default), its gradient
+    and Hessian in the parameters z [B,n,2] of the points P_k = O_k + Bm_k z_k
+    (O [B,n,3], Bm [B,n,3,2] with orthonormal columns; a line's second
+    column is zero).
 
     With w = d/s the unit-ish segment directions, the Hessian of one term
-    is (I - w w^T)/s; its blocks in z are B_k^T (I - w w^T) B_l / s, formed
-    from the Gram matrices B_k^T B_l and the projections B_k^T w."""
+    is wt (I - w w^T)/s; its blocks in z are wt B_k^T (I - w w^T) B_l / s,
+    formed from the Gram matrices B_k^T B_l and the projections B_k^T w."""
     B, n = z.shape[0], z.shape[1]
+    if wt is None:
+        wt = np.ones((B, n + 1))
     X = O + (Bm @ z[..., None])[..., 0]
     P = np.concatenate([np.broadcast_to(tx, (B, 1, 3)), X, rx[:, None]], axis=1)
     d = P[:, 1:] - P[:, :-1]                                  # [B,n+1,3]
     s = np.sqrt((d * d).sum(-1) + eps * eps)                  # [B,n+1]
-    f = s.sum(-1)
+    f = (wt * s).sum(-1)
     with np.errstate(divide="ignore", invalid="ignore"):
         w = d / s[..., None]
         Bt = np.swapaxes(Bm, -1, -2)
         a = (Bt @ w[:, :-1, :, None])[..., 0]                 # B_k^T w (segment into X_k)
         c = (Bt @ w[:, 1:, :, None])[..., 0]                  # B_k^T w (segment out of X_k)
-        g = a - c                                             # [B,n,2]
+        wi, wo = wt[:, :-1, None], wt[:, 1:, None]
+        g = wi * a - wo * c                                   # [B,n,2]
         if not want_hess:
             return f, g, None, X
         si, so = s[:, :-1, None, None], s[:, 1:, None, None]
         G = Bt @ Bm                                           # [B,n,2,2]
-        Dg = G / si + G / so - a[..., :, None] * a[..., None, :] / si - c[..., :, None] * c[..., None, :] / so
+        Dg = (wi[..., None] * (G - a[..., :, None] * a[..., None, :]) / si
+              + wo[..., None] * (G - c[..., :, None] * c[..., None, :]) / so)
         Ck = Bt[:, :-1] @ Bm[:, 1:]                           # [B,n-1,2,2]
-        Of = -(Ck - c[:, :-1, :, None] * a[:, 1:, None, :]) / s[:, 1:-1, None, None]
+        Of = -wt[:, 1:-1, None, None] * (Ck - c[:, :-1, :, None] * a[:, 1:, None, :]) / s[:, 1:-1, None, None]
     H = np.zeros((B, n, 2, n, 2))
     k = np.arange(n)
     H[:, k, :, k, :] = np.moveaxis(Dg, 1, 0)
@@ -107,18 +113,21 @@ def _fermat_eval(tx, rx, O, Bm, z, eps, want_hess=True):
     return f, g, H.reshape(B, 2 * n, 2 * n), X
 
 
-def fermat_minimiser(tx, rx, O, Bm, free, z0):
+def fermat_minimiser(tx, rx, O, Bm, free, z0, wt=None):
     """Global minimiser of the total length over infinite planes and lines.
 
     O [B,n,3] is a point of each object and Bm [B,n,3,2] an orthonormal
     basis of its directions (a line's second column is zero and its second
     parameter is not free: free [B,n,2]).  Damped Newton with backtracking
     on the smoothed length, eps = 1, 1e-2, ..., 1e-12, then exact Newton
-    steps where no segment is nearly empty.  Returns the points [B,n,3], the
-    largest exact gradient component and the shortest segment."""
+    steps where no segment is nearly empty.  wt [B,n+1]: the refractive index
+    of each segment's medium (the optical length), 1 by default.  Returns the
+    points [B,n,3], the largest exact gradient component and the shortest
+    segment."""
     tx = np.asarray(tx, float)
     z = z0 * free
     B, n = z.shape[0], z.shape[1]
+    wt = np.ones((B, n + 1)) if wt is None else np.asarray(wt, float)
     fixed = (~free).reshape(B, 2 * n).astype(float)
     ladder = 0.5 ** np.arange(12)
 
@@ -133,13 +142,13 @@ def fermat_minimiser(tx, rx, O, Bm, free, z0):
             if not len(act):
                 break
             Oi, Bi, rxi, zi = O[act], Bm[act], rx[act], z[act]
-            f, g, H, _ = _fermat_eval(tx, rxi, Oi, Bi, zi, eps)
+            f, g, H, _ = _fermat_eval(tx, rxi, Oi, Bi, zi, eps, wt=wt[act])
             dz = newton_dir(H, g, act)
             slope = (g * dz).sum((1, 2))
             # backtracking: the full step first, then ladders of shorter ones,
             # each ladder tried at once
             m = len(act)
-            f1, _, _, _ = _fermat_eval(tx, rxi, Oi, Bi, zi + dz, eps, want_hess=False)
+            f1, _, _, _ = _fermat_eval(tx, rxi, Oi, Bi, zi + dz, eps, want_hess=False, wt=wt[act])
             step = np.where(f1 <= f + 1e-4 * slope, 1.0, 0.0)
             for lad in range(6):
                 pend = np.where(step == 0.0)[0]
@@ -151,7 +160,7 @@ def fermat_minimiser(tx, rx, O, Bm, free, z0):
                 zt = zi[pend][:, None] + lv[None, :, None, None] * dz[pend][:, None]
                 ft, _, _, _ = _fermat_eval(tx, np.repeat(rxi[pend], L, 0), np.repeat(Oi[pend], L, 0),
                                            np.repeat(Bi[pend], L, 0), zt.reshape(q * L, n, 2), eps,
-                                           want_hess=False)
+                                           want_hess=False, wt=np.repeat(wt[act][pend], L, 0))
                 ok = ft.reshape(q, L) <= f[pend, None] + 1e-4 * lv[None, :] * slope[pend, None]
                 hit = ok.any(1)
                 step[pend[hit]] = lv[ok[hit].argmax(1)]
@@ -162,7 +171,7 @@ def fermat_minimiser(tx, rx, O, Bm, free, z0):
             tol = max(1e-13, 1e-4 * eps)
             done = (moved <= tol * (1 + np.abs(zi).max((1, 2)))) | (np.abs(g).max((1, 2)) <= 1e-15)
             act = act[~done]
-    f, g, _, X = _fermat_eval(tx, rx, O, Bm, z, 0.0, want_hess=False)
+    f, g, _, X = _fermat_eval(tx, rx, O, Bm, z, 0.0, want_hess=False, wt=wt)
     P = np.concatenate([np.broadcast_to(tx, (B, 1, 3)), X, rx[:, None]], axis=1)
     smin = np.linalg.norm(np.diff(P, axis=1), axis=2).min(1)
     smooth = np.where(smin > 1e-9)[0]
@@ -170,12 +179,12 @@ def fermat_minimiser(tx, rx, O, Bm, free, z0):
         if not len(smooth):
             break
         Oi, Bi, rxi = O[smooth], Bm[smooth], rx[smooth]
-        f0, g0, H0, _ = _fermat_eval(tx, rxi, Oi, Bi, z[smooth], 0.0)
+        f0, g0, H0, _ = _fermat_eval(tx, rxi, Oi, Bi, z[smooth], 0.0, wt=wt[smooth])
         dz = newton_dir(H0, g0, smooth)
-        _, g1, _, _ = _fermat_eval(tx, rxi, Oi, Bi, z[smooth] + dz, 0.0, want_hess=False)
+        _, g1, _, _ = _fermat_eval(tx, rxi, Oi, Bi, z[smooth] + dz, 0.0, want_hess=False, wt=wt[smooth])
         better = np.abs(g1 * free[smooth]).max((1, 2)) < np.abs(g0 * free[smooth]).max((1, 2))
         z[smooth[better]] += dz[better]
-    f, g, _, X = _fermat_eval(tx, rx, O, Bm, z, 0.0, want_hess=False)
+    f, g, _, X = _fermat_eval(tx, rx, O, Bm, z, 0.0, want_hess=False, wt=wt)
     P = np.concatenate([np.broadcast_to(tx, (B, 1, 3)), X, rx[:, None]], axis=1)
     smin = np.linalg.norm(np.diff(P, axis=1), axis=2).min(1)
     gn = np.nan_to_num(np.abs(g * free).max((1, 2)), nan=np.inf)
@@ -193,7 +202,8 @@ def _rect_coords(rec, X):
 
 def planar_paths_closed_form(scene, batch, idx=None, margin=1e-7):
     """Closed-form accept flags of paths whose objects are all planes and
-    straight edges.
+    straight edges (the planes reflect, or refract where the scene gives
+    them refractive indices).
 
     Returns (idx, accept, ambiguous, X): the solve ids considered (the
     planar ones among `idx`), the flags the acceptance rule gives at the
@@ -220,9 +230,13 @@ def planar_paths_closed_form(scene, batch, idx=None, margin=1e-7):
     planes = scene.planes if npl else np.array([[0, 0, 1.0] + [0.0] * 10])
     lines = scene.lines if nln else np.zeros((1, 8))
     rxall = batch.rx[batch.rx_index[idx]]
-    # reflection-only chains take the image method, the others Fermat;
-    # both are grouped by order
-    refl_only = np.all(~act[:, planar] | (typ == 0), axis=0) if len(idx) else np.zeros(0, bool)
+    # refractive indices (front, back) of each facet slot; (0, 0): a mirror
+    rfi = (scene.refraction if len(getattr(scene, "refraction", [])) else np.zeros((max(npl, 1), 2)))
+    refr = (typ == 0) & (rfi[np.where(typ == 0, prim, 0), 0] > 0)
+    # reflection-only chains take the image method, the others Fermat (the
+    # optical length where a facet refracts); both are grouped by order
+    refl_only = (np.all(~act[:, planar] | (typ == 0), axis=0) & ~np.any(refr, axis=0)) if len(idx) \
+        else np.zeros(0, bool)
     code = order * 2 + refl_only
     for c in np.unique(code):
         sel = np.where(code == c)[0]
@@ -251,19 +265,47 @@ def planar_paths_closed_form(scene, batch, idx=None, margin=1e-7):
                 free[:, k, 1] = isp
                 Pk = tx + (k + 1) / (n + 1) * (rx - tx)
                 z0[:, k] = (np.swapaxes(Bm[:, k], 1, 2) @ (Pk - O[:, k])[..., None])[..., 0]
-            X, gn, smin = fermat_minimiser(tx, rx, O, Bm, free, z0)
-            P = np.concatenate([np.broadcast_to(tx, (Bn, 1, 3)), X, rx[:, None]], axis=1)
-            # a minimiser with a segment far below the shortest admissible
-            # one is never accepted, whether it is a kink or not
-            smooth = smin > 1e-7
-            signed = np.ones(Bn, bool)
-            unsure = smooth & (gn > 1e-9)
-            for k in range(n):
-                nv = pl[k][:, 0:3]
-                a = np.einsum("bi,bi->b", P[:, k + 1] - P[:, k], nv)
-                b = np.einsum("bi,bi->b", P[:, k + 2] - P[:, k + 1], nv)
-                signed &= (kinds[k] != 0) | (a * b < 0)
-            exists = smooth & signed
+            rf = refr[:n, sel]                                # [n, B]
+            nfk = [np.where(rf[k], rfi[np.where(kinds[k] == 0, prim[k, sel], 0), 0], 0.0) for k in range(n)]
+            nbk = [np.where(rf[k], rfi[np.where(kinds[k] == 0, prim[k, sel], 0), 1], 0.0) for k in range(n)]
+            first = np.argmax(rf, axis=0)                     # first refracting slot (if any)
+            has_rf = rf.any(axis=0)
+            starts = ([np.ones(Bn)] if not has_rf.any() else
+                      [np.where(has_rf, np.choose(first, nfk), 1.0), np.where(has_rf, np.choose(first, nbk), 1.0)])
+            exists = np.zeros(Bn, bool)
+            unsure = np.zeros(Bn, bool)
+            Xbest = None
+            for m0 in starts:
+                # the medium of each segment: a refracting facet takes the ray
+                # to its other side's index, a reflection keeps it
+                wt = np.empty((Bn, n + 1))
+                m = m0.copy()
+                for k in range(n):
+                    wt[:, k] = m
+                    m = np.where(rf[k], np.where(m == nfk[k], nbk[k], nfk[k]), m)
+                wt[:, n] = m
+                X, gn, smin = fermat_minimiser(tx, rx, O, Bm, free, z0, wt=wt)
+                P = np.concatenate([np.broadcast_to(tx, (Bn, 1, 3)), X, rx[:, None]], axis=1)
+                # a minimiser with a segment far below the shortest admissible
+                # one is never accepted, whether it is a kink or not
+                smooth = smin > 1e-7
+                signed = np.ones(Bn, bool)
+                for k in range(n):
+                    nv = pl[k][:, 0:3]
+                    a = np.einsum("bi,bi->b", P[:, k + 1] - P[:, k], nv)
+                    b = np.einsum("bi,bi->b", P[:, k + 2] - P[:, k + 1], nv)
+                    # reflections return to the incoming side; refractions
+                    # cross, arriving from the side whose index is the
+                    # segment's medium
+                    arrive = np.where(a < 0, nfk[k], nbk[k])
+                    ok_r = (a * b > 0) & (arrive == wt[:, k])
+                    signed &= np.where(kinds[k] != 0, True, np.where(rf[k], ok_r, a * b < 0))
+                ex = smooth & signed
+                take = ex & ~exists
+                Xbest = X if Xbest is None else np.where(take[:, None, None], X, Xbest)
+                unsure |= ex & (gn > 1e-9)
+                exists |= ex
+            X = Xbest
         # acceptance at the closed-form root
         P = np.concatenate([np.broadcast_to(tx, (len(sel), 1, 3)), X, rx[:, None]], axis=1)
         seg = np.linalg.norm(np.diff(P, axis=1), axis=2)
