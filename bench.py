@@ -435,7 +435,8 @@ def main_single(args, torch, mpt, W):
     # the step; reported beside it, not part of the metric)
     acc_t = torch.from_numpy(flags[variant]).to("cuda")
     out_v = mpt.DeviceOut(n)
-    out_v.x.copy_(torch.from_numpy(r["x"]).to("cuda"))
+    out_v.x.zero_()
+    out_v.points().copy_(torch.from_numpy(r["x"]).to("cuda"))
     vis, nvis = ctx.visible(run.db, out_v, acc_t)
     torch.cuda.synchronize()
     t = time.perf_counter()

@@ -74,6 +74,12 @@ enum {
 
 enum { MPT_PLANE = 0, MPT_LINE = 1, MPT_QUADRIC = 2, MPT_CIRCLE = 3 };
 enum { MPT_MAX_ORDER = 5 };
+/* Point arrays (start points, solver outputs, network predictions, training
+ * targets) hold one row of MPT_ROW doubles per solve: the 3 * order
+ * coordinates x1, y1, z1, x2, ... of its points, then zeros.  A row is 128
+ * bytes, so a solve's points fill one cache line and a path's store or load
+ * is one contiguous access. */
+enum { MPT_ROW = 16 };
 
 /* Record widths (doubles) of the host scene arrays. */
 enum { MPT_PLANE_W = 13, MPT_LINE_W = 8, MPT_QUADRIC_W = 17, MPT_CIRCLE_W = 7, MPT_WEDGE_W = 7 };
@@ -144,7 +150,7 @@ mpt_status mpt_scene_upload(mpt_ctx *ctx, const mpt_scene_desc *scene);
  *   order     [n] int32 number of interactions n_t, 1..5
  *   prim      [5][n] int32 global primitive ids (component-major; entries
  *             beyond the order are ignored)
- *   x0        [15][n] FP64 start points for MPT_INIT_USER, else NULL
+ *   x0        [n][MPT_ROW] FP64 start points for MPT_INIT_USER, else NULL
  */
 typedef struct {
     int64_t n;
@@ -262,7 +268,7 @@ typedef struct {
 void mpt_default_opts(mpt_solve_opts *opts);
 
 /* Outputs, DEVICE pointers owned by the caller:
- *   x           [15][n] FP64 points (component-major, zero beyond 3*order)
+ *   x           [n][MPT_ROW] FP64 points (zero beyond 3*order)
  *   cost        [n] FP64 final cost C = |R|^2 (Eq. 12 with the rescaled rows)
  *   iters       [n] int32 iterations run (FP32 + polish + fallback)
  *   status      [n] uint8 MPT_PATH_* code, bit 7 = fallback used
@@ -296,7 +302,7 @@ mpt_status mpt_solve_batch(mpt_ctx *ctx, const mpt_batch_desc *batch, const mpt_
  * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
  * mpt_solve_batch with spill = 0.  Its counters and lists live in a static
  * device scratch array of the library, sized for at most
- * MPT_NOALLOC_MAX_SOLVES solves (12.6 MB, held by every GPU the library
+ * MPT_NOALLOC_MAX_SOLVES solves (37.8 MB, held by every GPU the library
  * runs on until the process ends); the counters are cleared by a fill
  * kernel at the start of every call.  Every call on one GPU shares that
  * scratch, so calls that overlap on one GPU (other contexts or streams)
@@ -429,7 +435,7 @@ mpt_status mpt_mlp_init(mpt_ctx *ctx, uint64_t seed);
 /* One Adam step (FP32 master weights, beta 0.9 / 0.999, eps 1e-8) on the
  * masked mean-squared error between the predicted and the target points,
  * in frame units, of the minibatch `rows` (device int32 [n_rows] ids into the
- * batch; NULL = every solve).  target_x: [15][n] FP64 device, for example the
+ * batch; NULL = every solve).  target_x: [n][MPT_ROW] FP64 device, for example the
  * solver's converged points; coordinates beyond a path's order and solves
  * whose `use` flag (uint8 [n], NULL = all) is zero are masked out.
  * *d_loss (device FP32, may be NULL) receives the loss before the step.  */
@@ -462,7 +468,7 @@ mpt_status mpt_mlp_param_count(size_t *count);
 mpt_status mpt_gemm_bf16_check(mpt_ctx *ctx, int32_t M, int32_t N, int32_t K, const float *A,
                                int32_t a_trans, const float *B, int32_t b_trans, float *C,
                                int32_t splits);
-/* Predicted points [15][n] FP64 world frame (device, caller-owned). */
+/* Predicted points [n][MPT_ROW] FP64 world frame (device, caller-owned). */
 mpt_status mpt_mlp_predict(mpt_ctx *ctx, const mpt_batch_desc *batch, double *x_out);
 /* The same prediction through the layer-by-layer GEMM kernels training
  * uses (activations in device memory) instead of the fused kernel; for

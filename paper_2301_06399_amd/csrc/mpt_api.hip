@@ -15,6 +15,8 @@
 #include "mpt_mlp.hpp"
 #include "mpt_flops.hpp"
 
+static_assert(mpt::kRow == MPT_ROW, "point row width");
+
 using namespace mpt;
 
 struct mpt_ctx {
@@ -80,13 +82,13 @@ static const int kSpillCounters = 32 + kKeyCounters;
 static const int kCounters = kSpillCounters + 16;
 
 // Scratch of the allocation-free solve (mpt_solve_batch_noalloc): the
-// counters and the perm / polish / fallback lists of at most
-// MPT_NOALLOC_MAX_SOLVES solves (12.6 MB).  Every GPU the library runs on
+// counters, the perm / polish / fallback lists and the bin-ordered receiver
+// and primitive ids of at most MPT_NOALLOC_MAX_SOLVES solves (37.8 MB).  Every GPU the library runs on
 // holds its own copy until the process ends, and every such call on that
 // GPU shares it.  In host code `scratch` names a host-side stand-in: its
 // device address comes from hipGetSymbolAddress, once per device, when a
 // context is created there (scratch_setup).
-static const size_t kScratchInts = (size_t)kCounters + 3 * (size_t)MPT_NOALLOC_MAX_SOLVES;
+static const size_t kScratchInts = (size_t)kCounters + 9 * (size_t)MPT_NOALLOC_MAX_SOLVES;
 static __device__ __align__(256) int scratch[kScratchInts];
 static const int kMaxDevices = 64;
 static std::mutex g_scratch_mu;
@@ -578,9 +580,9 @@ static mpt_status size_buffers(mpt_ctx *c, int64_t n, bool learned)
 {
     const size_t m = (size_t)(n > 0 ? n : 1);
     mpt_status st;
-    if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 4 * m, sizeof(int)))) return st;
+    if ((st = ensure(c, (void **)&c->ws, &c->ws_cap, kCounters + 10 * m, sizeof(int)))) return st;
     if ((st = ensure(c, (void **)&c->spf, &c->spf_cap, 3 * m, sizeof(double)))) return st;
-    if (learned && (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, 15 * m, sizeof(double)))) return st;
+    if (learned && (st = ensure(c, (void **)&c->x0l, &c->x0l_cap, MPT_ROW * m, sizeof(double)))) return st;
     return MPT_OK;
 }
 
@@ -645,16 +647,18 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.perm = ctr + kCounters;
     kp.pol_list = ctr + kCounters + n;
     kp.fb_list = ctr + kCounters + 2 * n;
+    kp.slot_rx = ctr + kCounters + 3 * n;
+    kp.slot_prim = ctr + kCounters + 4 * n;
     kp.spill_t = spill;
     kp.refill = opts->refill > 1 ? (opts->refill < 64 ? opts->refill : 64) : 1;
     kp.spill_cnt = ctr + kSpillCounters;
     kp.spill_head = ctr + kSpillCounters + 5;
-    kp.spill_list = w->spf ? ctr + kCounters + 3 * n : nullptr;
+    kp.spill_list = w->spf ? ctr + kCounters + 9 * n : nullptr;
     kp.spill_f = w->spf;
 
     if (timed) hipEventRecord(c->ev[0], s);
     launch_zero(ctr, kCounters, s);
-    launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, s);
+    launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, (int *)kp.slot_rx, (int *)kp.slot_prim, s);
     if (timed) hipEventRecord(c->ev[1], s);
     // the network serves the paths with a curved object: none without
     // paraboloids and circles in the scene

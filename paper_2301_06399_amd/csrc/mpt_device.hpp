@@ -17,6 +17,7 @@ namespace mpt {
 
 constexpr int kRec = 18;        // doubles / floats per packed primitive record
 constexpr int kMaxN = 5;
+constexpr int kRow = 16;        // doubles per solve in a point array (3 kMaxN coordinates, then zeros)
 
 enum : int { TP = 0, TL = 1, TQ = 2, TC = 3 };
 enum : int { ST_CONV = 0, ST_MAXIT = 1, ST_STALL = 2, ST_DIVERGED = 3, ST_DEGEN = 4,

@@ -63,9 +63,11 @@ struct KParams {
     BatchDev b;
     OutDev out;
     OptsDev o;
-    const double *x0_learned;  // [15][n] network start points (world)
+    const double *x0_learned;  // [n][kRow] network start points (world)
     const int *bin_cnt;        // [5] solves per order
-    const int *perm;           // [n] solve ids grouped by order
+    const int *perm;           // [n] solve ids grouped by order (bin order)
+    const int *slot_rx;        // [n] receiver of each bin slot
+    const int *slot_prim;      // [5][n] primitive ids of each bin slot
     int *head;                 // [10] work counters: bins, fallback lists
     int *pol_cnt;              // [5]
     int *pol_list;             // [n] polish lists (bin-relative slots)
@@ -85,7 +87,7 @@ void launch_pack(const double *raw, const double *refr, const SceneDev &s, int n
 void launch_zero(int *p, int n, hipStream_t st);
 int bin_key_count();
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
-                hipStream_t st);
+                int *slot_rx, int *slot_prim, hipStream_t st);
 const void *lm_kernel(int mode, int order, bool lds, int form);
 void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const KParams &kp, int grid, int block,
                hipStream_t st);

@@ -383,7 +383,7 @@ __global__ void k_loss_partial(SceneDev s, BatchDev b, const int *__restrict__ r
         for (int j = 0; j < F_OUTP; j++) {
             float dd = 0.0f;
             if (u && j < 3 * ord) {
-                const double t = (target[(size_t)j * b.n + i] - s.tx[j % 3]) / L;
+                const double t = (target[(size_t)i * kRow + j] - s.tx[j % 3]) / L;
                 dd = Y[(size_t)r * F_OUTP + j] - (float)t;
                 if (!isfinite(dd)) dd = 0.0f;
                 sum += dd * dd;
@@ -472,8 +472,8 @@ __global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restr
         }
         if (d2 > 0.0 && isfinite(d2)) L = sqrt(d2);
     }
-    for (int j = 0; j < F_OUT; j++)
-        x[(size_t)j * b.n + i] = (j < 3 * ord) ? s.tx[j % 3] + L * (double)Y[(size_t)i * F_OUTP + j] : 0.0;
+    for (int j = 0; j < kRow; j++)
+        x[(size_t)i * kRow + j] = (j < 3 * ord) ? s.tx[j % 3] + L * (double)Y[(size_t)i * F_OUTP + j] : 0.0;
 }
 
 // ------------------------------------------------------------------ fused inference
@@ -647,9 +647,7 @@ __global__ void __launch_bounds__(512, 1) k_mlp_fused(SceneDev s, BatchDev b, co
 #pragma unroll
             for (int v = 0; v < 8; v++) {
                 const int u = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                if (u < F_OUT)
-                    x[(size_t)u * b.n + i] =
-                        (u < 3 * ord) ? s.tx[u % 3] + Ls[r] * (double)(acc[v] + w[OB4_ + u]) : 0.0;
+                x[(size_t)i * kRow + u] = (u < 3 * ord) ? s.tx[u % 3] + Ls[r] * (double)(acc[v] + w[OB4_ + u]) : 0.0;
             }
         }
     }
@@ -875,7 +873,7 @@ mpt_status mlp_predict_unfused(MlpState *m, const SceneDev &s, const BatchDev &b
         v.prim = b.prim + c0;
         hipLaunchKernelGGL(k_features, dim3((nr + 127) / 128), dim3(128), 0, st, s, v, nullptr, nr, nullptr, m->X);
         forward(m, nr, false, st);
-        hipLaunchKernelGGL(k_decode, dim3((nr + 255) / 256), dim3(256), 0, st, s, v, nr, m->Y, x_out + c0);
+        hipLaunchKernelGGL(k_decode, dim3((nr + 255) / 256), dim3(256), 0, st, s, v, nr, m->Y, x_out + c0 * kRow);
     }
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
 }

@@ -134,17 +134,16 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out,
         if (i >= b.n) break;
         const int ord = valid_order(b, i, n_all);
         if (ord < 0) {
-            for (int q = 0; q < 3 * kMaxN; q++) out.x[(size_t)q * b.n + i] = 0.0;
+            for (int q = 0; q < kRow; q++) out.x[(size_t)i * kRow + q] = 0.0;
             out.cost[i] = __builtin_huge_val();
             out.iters[i] = 0;
             out.status[i] = ST_BAD;
             if (out.stage)
                 for (int q = 0; q < 4; q++) out.stage[(size_t)q * b.n + i] = 0;
         } else {
-            // the rows past the path's own points and the later stages'
-            // iteration counts are zero: written here, coalesced, so that the
-            // solver kernels store only what a path produces
-            for (int q = 3 * ord; q < 3 * kMaxN; q++) out.x[(size_t)q * b.n + i] = 0.0;
+            // the later stages' iteration counts are zero: written here,
+            // coalesced, so that the solver kernels store only what a path
+            // produces (the solver writes a path's whole point row)
             if (out.stage)
                 for (int q = 1; q < 4; q++) out.stage[(size_t)q * b.n + i] = 0;
             atomicAdd(&loc[bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q)], 1);
@@ -203,20 +202,25 @@ __device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
     return off;
 }
 
+// Each solve's slot in bin order, and its receiver and primitive ids copied
+// to that slot: the solver reads a wave's paths from consecutive slots
+// (coalesced) instead of gathering them by solve id.
 __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all, int n_pl, int n_pl_ln, int n_pl_ln_q,
                                                             const int *__restrict__ key_off,
-                                                            int *__restrict__ key_cursor, int *__restrict__ perm)
+                                                            int *__restrict__ key_cursor, int *__restrict__ perm,
+                                                            int *__restrict__ slot_rx, int *__restrict__ slot_prim)
 {
     __shared__ int loc[kNumKeys];
     __shared__ int gbase[kNumKeys];
     for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock) loc[k] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
-    int key[kBinItems], rank[kBinItems];
+    int key[kBinItems], rank[kBinItems], ords[kBinItems];
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
         const int ord = (i < b.n) ? valid_order(b, i, n_all) : -1;
+        ords[j] = ord;
         key[j] = (ord > 0) ? bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q) : -1;
         rank[j] = (key[j] >= 0) ? atomicAdd(&loc[key[j]], 1) : 0;
     }
@@ -227,13 +231,17 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
-        if (key[j] >= 0) perm[gbase[key[j]] + rank[j]] = (int)i;
+        if (key[j] >= 0) {
+            const int slot = gbase[key[j]] + rank[j];
+            perm[slot] = (int)i;
+            slot_rx[slot] = b.rx_index[i];
+            for (int k = 0; k < kMaxN; k++)
+                if (k < ords[j]) slot_prim[(size_t)k * b.n + slot] = b.prim[(size_t)k * b.n + i];
+        }
     }
 }
 
-// Ids of the valid solves whose list holds a quadric or a circle (the paths
-// the learned start serves), appended with wave-aggregated atomics.
-// The solves with a paraboloid or circle, listed in increasing id order
+// The solves with a paraboloid or circle (the paths the learned start serves), listed in increasing id order
 // without a contended counter: each of the grid's blocks owns a contiguous
 // range of solves; pass 1 counts per block, pass 2 scans the block counts
 // (one block), pass 3 writes each block's solves at its offset.
@@ -409,7 +417,7 @@ __device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, do
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             P[c] = s.tx[c] + a * (q.rx[c] - s.tx[c]);
-            Pn[c] = x0l[(size_t)(3 * k + c) * b.n + i];
+            Pn[c] = x0l[(size_t)i * kRow + 3 * k + c];
             okn = okn && isfinite(Pn[c]);
         }
         const double *r = s.rec64 + (size_t)q.id[k] * kRec;
@@ -421,7 +429,7 @@ __device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, do
     const bool ok1 = okn && eval_cost<double, N>(s64, q, Xn, nullptr, c1, r1);
     const bool net = ok1 && (!ok0 || c1 < gain * c0);
 #pragma unroll
-    for (int j = 0; j < 3 * N; j++) x0l[(size_t)j * b.n + i] = net ? Xn[j] : X0[j];
+    for (int j = 0; j < 3 * N; j++) x0l[(size_t)i * kRow + j] = net ? Xn[j] : X0[j];
 }
 
 __global__ void __launch_bounds__(256) k_learned_choose(SceneDev s, BatchDev b, const int *__restrict__ rows,
@@ -875,17 +883,23 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                 const int rank = (int)__popcll(need & ((1ull << lane) - 1ull));
                 const int take = min((int)__popcll(need), avail);
                 if (!active && rank < take) {
-                    sid = list[off + cbase + rank];
+                    const int slot = off + cbase + rank;
+                    sid = list[slot];
                     active = true;
                     // ---- start of one path
+                    // the first pass reads the bin-ordered copies of the
+                    // receiver and primitive ids (consecutive slots); the
+                    // fallback and the straggler pass go by solve id
+                    const bool binned = !resume && MODE != MODE_FALLBACK64;
+                    const int *pid = binned ? kp.slot_prim + slot : kp.b.prim + sid;
                     double rx[3], X0[3 * N];
-                    const int ri = kp.b.rx_index[sid];
+                    const int ri = binned ? kp.slot_rx[slot] : kp.b.rx_index[sid];
 #pragma unroll
                     for (int i = 0; i < 3; i++) rx[i] = kp.b.rx[3 * (size_t)ri + i];
                     p.planar = true;
 #pragma unroll
                     for (int k = 0; k < N; k++) {
-                        p.id[k] = kp.b.prim[(size_t)k * kp.b.n + sid];
+                        p.id[k] = pid[(size_t)k * kp.b.n];
                         p.ty[k] = prim_type(p.id[k], kp.s.n_pl, kp.s.n_pl_ln, kp.s.n_pl_ln_q);
                         p.planar = p.planar && (p.ty[k] == TL ||
                                                 (p.ty[k] == TP && kp.s.rec64[(size_t)p.id[k] * kRec + 16] <= 0.0));
@@ -897,7 +911,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     if (resume) {
                         // a parked path: its state exactly as it was left
 #pragma unroll
-                        for (int j = 0; j < D; j++) L.X[j] = (T)kp.out.x[(size_t)j * kp.b.n + sid];
+                        for (int j = 0; j < D; j++) L.X[j] = (T)kp.out.x[(size_t)sid * kRow + j];
                         L.it = kp.out.iters[sid];
                         it0 = L.it;
                         L.lam = (T)kp.spill_f[sid];
@@ -943,7 +957,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                                                                      : kp.x0_learned;
 #pragma unroll
                         for (int j = 0; j < 3 * N; j++) {
-                            X0[j] = x0[(size_t)j * kp.b.n + sid];
+                            X0[j] = x0[(size_t)sid * kRow + j];
                             ok = ok && isfinite(X0[j]);
                         }
                     }
@@ -993,7 +1007,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     if (st0 != ST_RUNNING) {
                         // finished before the first iteration
 #pragma unroll
-                        for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (st0 != ST_BAD) ? X0[j] : 0.0;
+                        for (int j = 0; j < kRow; j++)
+                            kp.out.x[(size_t)sid * kRow + j] = (j < 3 * N && st0 != ST_BAD) ? X0[j < 3 * N ? j : 0] : 0.0;
                         kp.out.cost[sid] = __builtin_huge_val();
                         if (MODE != MODE_FALLBACK64) {
                             kp.out.iters[sid] = 0;
@@ -1037,7 +1052,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
             if (st == ST_PARKED) {
                 // ---- a parked path: its exact state, for the straggler launch
 #pragma unroll
-                for (int j = 0; j < D; j++) kp.out.x[(size_t)j * kp.b.n + sid] = (double)L.X[j];
+                for (int j = 0; j < D; j++) kp.out.x[(size_t)sid * kRow + j] = (double)L.X[j];
                 kp.out.iters[sid] = L.it;
                 kp.spill_f[sid] = (double)L.lam;
                 kp.spill_f[(size_t)kp.b.n + sid] = (double)L.Cref;
@@ -1062,8 +1077,9 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
 #pragma unroll
                     for (int j = 0; j < 3 * N; j++) Xw[j] = (double)L.X[j] + sh[j % 3];
                 }
+                // the whole row (one cache line): the points, then zeros
 #pragma unroll
-                for (int j = 0; j < 3 * N; j++) kp.out.x[(size_t)j * kp.b.n + sid] = Xw[j];
+                for (int j = 0; j < kRow; j++) kp.out.x[(size_t)sid * kRow + j] = (j < 3 * N) ? Xw[j < 3 * N ? j : 0] : 0.0;
                 kp.out.cost[sid] = (double)L.C;
                 int it = L.it;
                 if (MODE == MODE_FALLBACK64) it += kp.out.iters[sid];
@@ -1253,7 +1269,7 @@ __device__ void polish_bin(const KParams &kp)
         }
         double X[M];
 #pragma unroll
-        for (int j = 0; j < M; j++) X[j] = kp.out.x[(size_t)j * kp.b.n + sid];
+        for (int j = 0; j < M; j++) X[j] = kp.out.x[(size_t)sid * kRow + j];
         bool ok = true, small = false;
         int steps = 0;
         for (int ps = 0; ps < kp.o.polish_steps && ok && !small; ps++) {
@@ -1288,7 +1304,7 @@ __device__ void polish_bin(const KParams &kp)
         if (kp.out.stage) kp.out.stage[(size_t)kp.b.n + sid] = steps;
         if (root) {
 #pragma unroll
-            for (int j = 0; j < M; j++) kp.out.x[(size_t)j * kp.b.n + sid] = X[j];
+            for (int j = 0; j < M; j++) kp.out.x[(size_t)sid * kRow + j] = X[j];
             kp.out.cost[sid] = C;
             kp.out.status[sid] = ST_CONV;
         } else {
@@ -1412,7 +1428,7 @@ __global__ void __launch_bounds__(256) k_accept_flags(SceneDev s, BatchDev b, Ou
             double rx[3], X[3 * kMaxN];
             int id[kMaxN], ty[kMaxN];
             for (int j = 0; j < 3; j++) rx[j] = b.rx[3 * (size_t)ri + j];
-            for (int j = 0; j < 3 * kMaxN; j++) X[j] = (j < 3 * ord) ? in.x[(size_t)j * b.n + i] : 0.0;
+            for (int j = 0; j < 3 * kMaxN; j++) X[j] = (j < 3 * ord) ? in.x[(size_t)i * kRow + j] : 0.0;
             bool okid = true;
             for (int k = 0; k < kMaxN; k++) {
                 id[k] = (k < ord) ? b.prim[(size_t)k * b.n + i] : 0;
@@ -1502,7 +1518,7 @@ int bin_key_count() { return kNumKeys; }
 
 // keys: [3][kNumKeys] ints (counts, offsets, cursors), zeroed by the caller
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
-                hipStream_t st)
+                int *slot_rx, int *slot_prim, hipStream_t st)
 {
     if (b.n == 0) return;
     const unsigned g = (unsigned)((b.n + kBinBlock * kBinItems - 1) / (kBinBlock * kBinItems));
@@ -1511,7 +1527,7 @@ void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bi
                        kcnt);
     hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, kcnt, koff, bin_cnt);
     hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), 0, st, b, s.n_all, s.n_pl, s.n_pl_ln, s.n_pl_ln_q,
-                       koff, kcur, perm);
+                       koff, kcur, perm, slot_rx, slot_prim);
 }
 
 template <int MODE, bool LDS, int FORM>

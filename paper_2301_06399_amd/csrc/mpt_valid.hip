@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(256) k_visible(SceneDev s, BatchDev b, OutDevC
         for (int k = 0; ok && k <= n; k++) {
             double P[3], Q[3], d[3];
             for (int c = 0; c < 3; c++) {
-                P[c] = (k == 0) ? s.tx[c] : in.x[(size_t)(3 * (k - 1) + c) * b.n + i];
-                Q[c] = (k == n) ? rx[c] : in.x[(size_t)(3 * k + c) * b.n + i];
+                P[c] = (k == 0) ? s.tx[c] : in.x[(size_t)i * kRow + 3 * (k - 1) + c];
+                Q[c] = (k == n) ? rx[c] : in.x[(size_t)i * kRow + 3 * k + c];
                 d[c] = Q[c] - P[c];
             }
             const int ip = (k == 0) ? -1 : b.prim[(size_t)(k - 1) * b.n + i];

@@ -28,7 +28,7 @@ def targets(ctx, db, form=mpt.FORM_IMPLICIT, ends=False):
     st = out.status.to(torch.int32) & 0x7F
     if ends:
         ok = (st == mpt.CONVERGED) | (st == mpt.LOCALMIN) | (st == mpt.MAXITER) | (st == mpt.STALLED)
-        ok &= torch.isfinite(out.x).all(dim=0)
+        ok &= torch.isfinite(out.x).all(dim=1)
     else:
         ok = st == mpt.CONVERGED
     return out, ok.to(torch.uint8)

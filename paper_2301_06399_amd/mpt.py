@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_
                 5: "E_UNSUPPORTED", 6: "E_NO_MODEL", 7: "E_CAPACITY"}
 CONVERGED, MAXITER, STALLED, DIVERGED, DEGENERATE, BAD_INPUT, LOCALMIN, OUTSIDE = range(8)
 FALLBACK = 0x80
+ROW = 16  # doubles per solve in a point array (MPT_ROW)
 FP64_PLAIN, FP32_POLISH64 = 0, 1
 INIT_LINE, INIT_USER, INIT_LEARNED, INIT_LEARNED_ALL, INIT_RANDOM = 0, 1, 2, 3, 4
 FORM_IMPLICIT, FORM_PARAMETRIC, FORM_AUTO = 0, 1, 2
@@ -141,6 +142,15 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def to_rows(x):
+    """[15][n] points (the host batches' layout) -> the library's [n][ROW]
+    rows, zero beyond the 15 coordinates."""
+    x = np.asarray(x, np.float64)
+    r = np.zeros((x.shape[1], ROW), np.float64)
+    r[:, :x.shape[0]] = x.T
+    return r
+
+
 class DeviceBatch:
     """A batch's arrays resident in device memory (torch tensors)."""
 
@@ -152,7 +162,7 @@ class DeviceBatch:
         self.rx_index = torch.from_numpy(np.ascontiguousarray(batch.rx_index, np.int32)).to(device)
         self.order = torch.from_numpy(np.ascontiguousarray(batch.order, np.int32)).to(device)
         self.prim = torch.from_numpy(np.ascontiguousarray(batch.prim, np.int32)).to(device)
-        self.x0 = None if batch.x0 is None else torch.from_numpy(np.ascontiguousarray(batch.x0, np.float64)).to(device)
+        self.x0 = None if batch.x0 is None else torch.from_numpy(to_rows(batch.x0)).to(device)
 
     def desc(self) -> BatchDesc:
         return BatchDesc(self.n, self.n_rx, _ptr(self.rx), _ptr(self.rx_index), _ptr(self.order), _ptr(self.prim),
@@ -178,7 +188,8 @@ def device_batch(rx, rx_index, order, prim):
 class DeviceOut:
     def __init__(self, n, device="cuda", stages=False):
         import torch
-        self.x = torch.empty((15, max(n, 0)), dtype=torch.float64, device=device)
+        # one row of ROW doubles per solve (the library's point layout)
+        self.x = torch.empty((max(n, 0), ROW), dtype=torch.float64, device=device)
         self.cost = torch.empty(max(n, 0), dtype=torch.float64, device=device)
         self.iters = torch.empty(max(n, 0), dtype=torch.int32, device=device)
         self.status = torch.empty(max(n, 0), dtype=torch.uint8, device=device)
@@ -187,8 +198,13 @@ class DeviceOut:
     def desc(self) -> SolveOut:
         return SolveOut(_ptr(self.x), _ptr(self.cost), _ptr(self.iters), _ptr(self.status), _ptr(self.stage))
 
+    def points(self):
+        """The points as a [15][n] view of the row-major array."""
+        return self.x[:, :15].t()
+
     def numpy(self):
-        r = {"x": self.x.cpu().numpy(), "cost": self.cost.cpu().numpy(), "iters": self.iters.cpu().numpy(),
+        r = {"x": np.ascontiguousarray(self.points().cpu().numpy()), "cost": self.cost.cpu().numpy(),
+             "iters": self.iters.cpu().numpy(),
              "status": self.status.cpu().numpy()}
         if self.stage is not None:
             r["stage"] = self.stage.cpu().numpy()
@@ -497,24 +513,24 @@ class Context:
         return Cm
 
     def mlp_predict_unfused(self, dbatch: DeviceBatch, x_out=None):
-        x_out = x_out if x_out is not None else self.torch.zeros((15, dbatch.n), dtype=self.torch.float64,
+        x_out = x_out if x_out is not None else self.torch.zeros((dbatch.n, ROW), dtype=self.torch.float64,
                                                                  device="cuda")
         bd = dbatch.desc()
         self._enter()
         rc = self.L.mpt_mlp_predict_unfused(self.h, C.byref(bd), _ptr(x_out))
         self._leave()
         self._check(rc, "mpt_mlp_predict_unfused")
-        return x_out
+        return x_out[:, :15].t()
 
     def mlp_predict(self, dbatch: DeviceBatch, x_out=None):
-        x_out = x_out if x_out is not None else self.torch.empty((15, dbatch.n), dtype=self.torch.float64,
+        x_out = x_out if x_out is not None else self.torch.empty((dbatch.n, ROW), dtype=self.torch.float64,
                                                                  device="cuda")
         bd = dbatch.desc()
         self._enter()
         rc = self.L.mpt_mlp_predict(self.h, C.byref(bd), _ptr(x_out))
         self._leave()
         self._check(rc, "mpt_mlp_predict")
-        return x_out
+        return x_out[:, :15].t()
 
     def mlp_save(self) -> bytes:
         n = C.c_size_t(0)

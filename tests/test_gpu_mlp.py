@@ -69,7 +69,7 @@ def test_gradients_match_fp64_reference(ctx):
     P = R.unpack(w)
     sb = b.subset(np.arange(2000))
     X = R.features(sc, sb)
-    T = R.targets(sc, sb, out.x.cpu().numpy()[:, :2000])
+    T = R.targets(sc, sb, out.numpy()["x"][:, :2000])
     mask = np.zeros((2000, 16))
     u = use.cpu().numpy()[:2000]
     for i in range(2000):
@@ -97,7 +97,7 @@ def test_fp32_gradients_match_fp64_reference(ctx):
     P = R.unpack(w)
     sb = b.subset(np.arange(512))
     X = R.features(sc, sb)
-    T = R.targets(sc, sb, out.x.cpu().numpy()[:, :512])
+    T = R.targets(sc, sb, out.numpy()["x"][:, :512])
     mask = np.zeros((512, 16))
     u = use.cpu().numpy()[:512]
     for i in range(512):
