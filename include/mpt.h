@@ -184,7 +184,9 @@ enum { MPT_FORM_IMPLICIT = 0, MPT_FORM_PARAMETRIC = 1, MPT_FORM_AUTO = 2 };
  * register budget, all five running concurrently on forked streams;
  * MPT_SCHED_SPLIT: one persistent launch for orders 1-3 (the register
  * budget of order 3) and one launch each for orders 4 and 5 beside it.
- * Every schedule gives the same results. */
+ * Every schedule gives the same results.  A scene with a refracting facet
+ * always runs MPT_SCHED_PERSISTENT (the only kernel compiled with the rows
+ * of such facets). */
 enum { MPT_SCHED_PER_ORDER = 0, MPT_SCHED_PERSISTENT = 1, MPT_SCHED_AUTO = 2, MPT_SCHED_SPLIT = 3 };
 
 /* Solver options; mpt_default_opts fills the defaults noted here. */

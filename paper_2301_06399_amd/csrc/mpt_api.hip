@@ -41,6 +41,7 @@ struct mpt_ctx {
     SceneDev s{};
     bool has_scene = false;
     bool curved = false;     // the scene has paraboloids or circles
+    bool refr = false;       // some facet of the scene refracts
     bool param_ok = true;    // every quadric is a paraboloid of revolution
     uint64_t scene_hash = 0; // FNV-1a of the uploaded records and TX: the tuning key
     // workspace: counters | perm | polish lists | fallback lists
@@ -371,6 +372,9 @@ mpt_status mpt_scene_upload(mpt_ctx *c, const mpt_scene_desc *d)
     if (refr) mix(d->refraction, (size_t)np * 2 * sizeof(double));
     c->scene_hash = h;
     c->curved = (nq + nc) > 0;
+    c->refr = false;
+    if (refr)
+        for (int i = 0; i < np && !c->refr; i++) c->refr = d->refraction[2 * (size_t)i] > 0.0;
     c->param_ok = true;
     for (int i = 0; i < nq; i++) {
         // the parametric form needs A = k (I - ax ax^T), b = -ax, c = 0
@@ -536,6 +540,9 @@ static void choose(mpt_ctx *c, const mpt_solve_opts *o, int64_t n, int &sched, i
     if (o->sched != MPT_SCHED_AUTO) sched = o->sched;
     if (o->block) block = o->block;
     if (o->spill >= 0) spill = o->spill;
+    // the rows of refracting facets are compiled into the mixed-order
+    // kernel only
+    if (c->refr) sched = MPT_SCHED_PERSISTENT, gdiv = 1;
 }
 
 static mpt_status check_opts(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opts *opts, const mpt_solve_out *out)
@@ -605,6 +612,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     if (st) return st;
     const int64_t n = b->n;
     const bool learned = opts->init == MPT_INIT_LEARNED || opts->init == MPT_INIT_LEARNED_ALL;
+    if (c->refr) sched = MPT_SCHED_PERSISTENT, gdiv = 1;  // the only kernel with refracting rows
     Work own{nullptr, nullptr, nullptr};
     if (!w) {
         if ((st = size_buffers(c, n, learned))) return st;
@@ -686,7 +694,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
         const bool lds = rec_bytes <= c->lds_max;
         auto go = [&](int ord, hipStream_t where) {
             const int form = form_used;
-            const void *k = lm_kernel(md, ord, lds, form);
+            const void *k = lm_kernel(md, ord, lds, form, c->refr);
             if (lds) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rec_bytes);
             int g = opts->grid;
             if (!g) {
@@ -695,7 +703,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
                 g = resident_grid(c, k, blk, n, lds ? rec_bytes : 0);
                 if (first && gdiv > 1) g = (g + gdiv - 1) / gdiv;
             }
-            launch_lm(md, ord, lds, form, rec_bytes, kp, g, blk, where);
+            launch_lm(md, ord, lds, form, c->refr, rec_bytes, kp, g, blk, where);
         };
         if (sch == MPT_SCHED_PERSISTENT) {
             go(0, s);
@@ -736,7 +744,7 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     if (timed) hipEventRecord(c->ev[4], s);
     if (n > 0 && mode == MODE_FP32) {
         launch_polish_list(kp, s);
-        launch_polish(kp, resident_grid(c, polish_kernel(), 256, n), 256, s);
+        launch_polish(kp, c->refr, resident_grid(c, polish_kernel(c->refr), 256, n), 256, s);
     }
     if (timed) hipEventRecord(c->ev[5], s);
     // the fallback handles a handful of paths: one mixed-order launch
@@ -850,6 +858,7 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
     for (int fm : forms) {
         for (int sp : {0, 8, 16, 32})
             for (int blk : {128, 256}) cands.push_back({MPT_SCHED_PERSISTENT, blk, 1, sp, fm});
+        if (c->refr) continue;  // refracting facets: the mixed-order kernel only
         for (int sp : {0, 16})
             for (int blk : {64, 128, 256})
                 for (int gd : {1, 2}) cands.push_back({MPT_SCHED_PER_ORDER, blk, gd, sp, fm});
@@ -921,7 +930,8 @@ template <int N>
 static void count_one(const int32_t *types, int64_t out[4], bool param)
 {
     // a small synthetic scene: one record per interaction with generic
-    // (non-zero, non-special) values, so no operation is skipped by accident
+    // (non-zero, non-special) values, so no operation is skipped by accident;
+    // planes are mirrors (the rows of a refracting facet are not counted)
     uint64_t st = 0x9e3779b97f4a7c15ull;
     auto rnd = [&]() {
         st = st * 6364136223846793005ull + 1442695040888963407ull;
@@ -956,26 +966,26 @@ static void count_one(const int32_t *types, int64_t out[4], bool param)
     constexpr int M = 3 * N;
     // one LM iteration
     tally() = FlopTally();
-    assemble<Cnt, N>(sc, p, X, A, g, C, rinf);
+    assemble<Cnt, N, false>(sc, p, X, A, g, C, rinf);
     Cnt lam(rnd()), dmax(rnd());
     for (int i = 0; i < M; i++) A[Band<N>::at(i, i)] += lam * fmax(A[Band<N>::at(i, i)], Cnt(1e-12) * dmax);
     chol_band<Cnt, N>(A);
     chol_solve_band<Cnt, N>(A, g);
     Cnt Ct, rt;
-    eval_cost<Cnt, N>(sc, p, X, g, Ct, rt);
+    eval_cost<Cnt, N, false>(sc, p, X, g, Ct, rt);
     for (int i = 0; i < M; i++) X[i] += g[i];
     out[0] = tally().flops();
     out[3] = tally().sqrt + tally().div;
     // one polish step
     tally() = FlopTally();
-    assemble<Cnt, N>(sc, p, X, A, g, C, rinf);
+    assemble<Cnt, N, false>(sc, p, X, A, g, C, rinf);
     chol_band<Cnt, N>(A);
     chol_solve_band<Cnt, N>(A, g);
     for (int i = 0; i < M; i++) X[i] += g[i];
     out[1] = tally().flops();
     // one residual evaluation
     tally() = FlopTally();
-    eval_cost<Cnt, N>(sc, p, X, nullptr, C, rinf);
+    eval_cost<Cnt, N, false>(sc, p, X, nullptr, C, rinf);
     out[2] = tally().flops();
     if (!param) return;
     // the parametric form: one iteration over the 2N parameters (the polish
@@ -986,7 +996,7 @@ static void count_one(const int32_t *types, int64_t out[4], bool param)
         U[2 * k + 1] = (types[k] == MPT_PLANE || types[k] == MPT_QUADRIC) ? Cnt(rnd()) : Cnt(0.0);
     }
     tally() = FlopTally();
-    assemble_param<Cnt, N>(sc, p, U, Ap, gp, C, rinf);
+    assemble_param<Cnt, N, false>(sc, p, U, Ap, gp, C, rinf);
     for (int i = 0; i < 2 * N; i++) {
         const bool real = (i % 2 == 0) || types[i / 2] == MPT_PLANE || types[i / 2] == MPT_QUADRIC;
         Cnt &d = Ap[Band<N, 2>::at(i, i)];
@@ -995,11 +1005,11 @@ static void count_one(const int32_t *types, int64_t out[4], bool param)
     chol_band<Cnt, N, 2>(Ap);
     chol_solve_band<Cnt, N, 2>(Ap, gp);
     bool guard;
-    eval_cost_param<Cnt, N>(sc, p, U, gp, Ct, rt, guard);
+    eval_cost_param<Cnt, N, false>(sc, p, U, gp, Ct, rt, guard);
     out[0] = tally().flops();
     out[3] = tally().sqrt + tally().div;
     tally() = FlopTally();
-    eval_cost_param<Cnt, N>(sc, p, U, nullptr, C, rinf, guard);
+    eval_cost_param<Cnt, N, false>(sc, p, U, nullptr, C, rinf, guard);
     out[2] = tally().flops();
 }
 

@@ -105,9 +105,10 @@ __host__ __device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0]
 // (|X-c|^2 - R^2)/(2R)                                     (Eq. 11)
 // Derivative blocks: Jp = d/dX_{k-1} (law rows), Jk = d/dX_k (all rows),
 // Jn = d/dX_{k+1} (law rows).
-// Returns false when a direction is undefined (degenerate).
+// Returns false when a direction is undefined (degenerate).  REFR = false
+// compiles the refracting-facet rows out (scenes without such facets).
 // -------------------------------------------------------------------------
-template <typename T, bool WITH_J>
+template <typename T, bool WITH_J, bool REFR = true>
 __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__restrict__ r, const T *Xp, const T *Xk,
                                                  const T *Xn, T u[5], T Jp[3][3], T Jk[5][3], T Jn[3][3])
 {
@@ -156,7 +157,7 @@ __host__ __device__ __forceinline__ bool interaction_rows(int t, const T *__rest
         // the normal points to and of the other side): Snell's law, the part
         // of n r^ along the facet equals that of n i^ (Sec. VI), with n_i the
         // index of the side the ray arrives from
-        const bool refr = (t == TP) && (r[16] > T(0));
+        const bool refr = REFR && (t == TP) && (r[16] > T(0));
         const T n_i = refr ? ((s < T(0)) ? r[16] : r[17]) : T(0);
         const T n_t = refr ? ((s < T(0)) ? r[17] : r[16]) : T(0);
         const T sr = dot3(rh, nh);
@@ -337,7 +338,7 @@ __host__ __device__ __forceinline__ void point_at(int k, const T *X, const T *dx
 }
 
 // Residual cost and inf-norm at X (+dx).  Returns false if degenerate.
-template <typename T, int N>
+template <typename T, int N, bool REFR = true>
 __host__ __device__ __forceinline__ bool eval_cost(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X, const T *dx,
                                           T &C, T &rinf)
 {
@@ -350,7 +351,7 @@ __host__ __device__ __forceinline__ bool eval_cost(const SceneT<T> &sc, const Pa
         point_at<T, N>(k - 1, X, dx, sc.tx, p.rx, Xp);
         point_at<T, N>(k, X, dx, sc.tx, p.rx, Xk);
         point_at<T, N>(k + 1, X, dx, sc.tx, p.rx, Xn);
-        const bool okk = interaction_rows<T, false>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xk, Xn, u,
+        const bool okk = interaction_rows<T, false, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xk, Xn, u,
                                                     nullptr, nullptr, nullptr);
         ok = ok && okk;
 #pragma unroll
@@ -363,7 +364,7 @@ __host__ __device__ __forceinline__ bool eval_cost(const SceneT<T> &sc, const Pa
 }
 
 // Residual, J^T J (in-band, packed lower) and g = J^T R at X.
-template <typename T, int N>
+template <typename T, int N, bool REFR = true>
 __host__ __device__ __forceinline__ bool assemble(const SceneT<T> &sc, const PathIn<T, N> &p, const T *X,
                                          T *A, T *g, T &C, T &rinf)
 {
@@ -384,7 +385,7 @@ __host__ __device__ __forceinline__ bool assemble(const SceneT<T> &sc, const Pat
         point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
         point_at<T, N>(k, X, nullptr, sc.tx, p.rx, Xk);
         point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
-        const bool okk = interaction_rows<T, true>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xk, Xn, u, Jp, Jk, Jn);
+        const bool okk = interaction_rows<T, true, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xk, Xn, u, Jp, Jk, Jn);
         ok = ok && okk;
 #pragma unroll
         for (int i = 0; i < 5; i++) {
@@ -533,7 +534,7 @@ __host__ __device__ __forceinline__ bool param_of(int t, const double *__restric
 
 // Law rows of the parametric form at X(U + dU) (dU may be null): cost, inf
 // norm, and whether every trial point stays in the guard box.
-template <typename T, int N>
+template <typename T, int N, bool REFR = true>
 __host__ __device__ __forceinline__ bool eval_cost_param(const SceneT<T> &sc, const PathIn<T, N> &p, const T *U,
                                                 const T *dU, T &C, T &rinf, bool &guard)
 {
@@ -554,7 +555,7 @@ __host__ __device__ __forceinline__ bool eval_cost_param(const SceneT<T> &sc, co
         T Xp[3], Xn[3], u[5];
         point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
         point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
-        const bool okk = interaction_rows<T, false>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
+        const bool okk = interaction_rows<T, false, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
                                                     nullptr, nullptr, nullptr);
         ok = ok && okk;
 #pragma unroll
@@ -568,7 +569,7 @@ __host__ __device__ __forceinline__ bool eval_cost_param(const SceneT<T> &sc, co
 
 // Normal equations of the parametric form: band of J^T J (2 x 2 blocks) and
 // J^T I, with J = dI/dX . dX/dU by the chain rule.
-template <typename T, int N>
+template <typename T, int N, bool REFR = true>
 __host__ __device__ __forceinline__ bool assemble_param(const SceneT<T> &sc, const PathIn<T, N> &p, const T *U, T *A,
                                                T *g, T &C, T &rinf)
 {
@@ -592,7 +593,7 @@ __host__ __device__ __forceinline__ bool assemble_param(const SceneT<T> &sc, con
         T Xp[3], Xn[3], u[5], Jp[3][3], Jk[5][3], Jn[3][3];
         point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
         point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
-        const bool okk = interaction_rows<T, true>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
+        const bool okk = interaction_rows<T, true, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
                                                    Jp, Jk, Jn);
         ok = ok && okk;
 #pragma unroll

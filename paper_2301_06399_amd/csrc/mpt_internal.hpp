@@ -88,14 +88,14 @@ void launch_zero(int *p, int n, hipStream_t st);
 int bin_key_count();
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
                 int *slot_rx, int *slot_prim, hipStream_t st);
-const void *lm_kernel(int mode, int order, bool lds, int form);
-void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const KParams &kp, int grid, int block,
-               hipStream_t st);
-const void *polish_kernel();
+const void *lm_kernel(int mode, int order, bool lds, int form, bool refr);
+void launch_lm(int mode, int order, bool lds, int form, bool refr, size_t lds_bytes, const KParams &kp, int grid,
+               int block, hipStream_t st);
+const void *polish_kernel(bool refr);
 void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, int *blk, hipStream_t st);
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
                            double *x0l, double gain, hipStream_t st);
-void launch_polish(const KParams &kp, int grid, int block, hipStream_t st);
+void launch_polish(const KParams &kp, bool refr, int grid, int block, hipStream_t st);
 void launch_polish_list(const KParams &kp, hipStream_t st);
 void launch_samples(const SceneDev &s, int k, double *samp, int *cnt, hipStream_t st);
 void launch_visibility(const SceneDev &s, int k, double min_seg, const double *samp, const int *cnt, uint32_t *V,

@@ -477,8 +477,9 @@ struct Lane {
 };
 
 // One Levenberg-Marquardt iteration on the cost of Eq. (12) with the
-// rescaled rows; returns ST_RUNNING or the final status.
-template <typename T, int N>
+// rescaled rows; returns ST_RUNNING or the final status.  REFR: the scene
+// has refracting facets (their rows are compiled in).
+template <typename T, int N, bool REFR>
 __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &p, Lane<T, N> &L,
                                        const LMOpts<T> &o)
 {
@@ -494,7 +495,7 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
         C = L.C0;
         rinf = L.r0;
     } else {
-        if (!assemble<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+        if (!assemble<T, N, REFR>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
         if constexpr (LT::kKeep) {
 #pragma unroll
             for (int i = 0; i < Band<N>::SIZE; i++) L.A0[i] = A[i];
@@ -550,7 +551,7 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
         }
     const bool small = dinf <= o.tol_step * (T(1) + xinf);
     T Ct = T(0), rt = T(0);
-    bool okt = guard && eval_cost<T, N>(sc, p, L.X, g, Ct, rt);
+    bool okt = guard && eval_cost<T, N, REFR>(sc, p, L.X, g, Ct, rt);
     if (okt && Ct < C) {
 #pragma unroll
         for (int i = 0; i < M; i++) L.X[i] += g[i];
@@ -569,7 +570,7 @@ __device__ __forceinline__ int lm_step(const SceneT<T> &sc, const PathIn<T, N> &
 
 // One Levenberg-Marquardt iteration of the parametric form (Eq. (15)), with
 // the same rules; the placeholder parameter of an edge is held fixed.
-template <typename T, int N>
+template <typename T, int N, bool REFR>
 __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T, N> &p, Lane<T, N, 2 * N> &L,
                                              const LMOpts<T> &o)
 {
@@ -585,7 +586,7 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
         C = L.C0;
         rinf = L.r0;
     } else {
-        if (!assemble_param<T, N>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
+        if (!assemble_param<T, N, REFR>(sc, p, L.X, A, g, C, rinf)) return ST_DEGEN;
         if constexpr (LT::kKeep) {
 #pragma unroll
             for (int i = 0; i < Band<N, 2>::SIZE; i++) L.A0[i] = A[i];
@@ -644,7 +645,7 @@ __device__ __forceinline__ int lm_step_param(const SceneT<T> &sc, const PathIn<T
     const bool small = dinf <= o.tol_step * (T(1) + xinf);
     T Ct = T(0), rt = T(0);
     bool guard = true;
-    bool okt = eval_cost_param<T, N>(sc, p, L.X, g, Ct, rt, guard) && guard;
+    bool okt = eval_cost_param<T, N, REFR>(sc, p, L.X, g, Ct, rt, guard) && guard;
     if (okt && Ct < C) {
 #pragma unroll
         for (int i = 0; i < M; i++) L.X[i] += g[i];
@@ -744,9 +745,9 @@ __device__ __forceinline__ int lm_step_fixed(const SceneT<T> &sc, const PathIn<T
     PathIn<T, N> q = p;
 #pragma unroll
     for (int k = 0; k < N; k++) q.ty[k] = (CODE >> (2 * k)) & 3;
-    q.planar = true;
-    if constexpr (FORM) return lm_step_param<T, N>(sc, q, L, o);
-    else return lm_step<T, N>(sc, q, L, o);
+    q.planar = true;  // planes and straight edges: no refracting facet
+    if constexpr (FORM) return lm_step_param<T, N, false>(sc, q, L, o);
+    else return lm_step<T, N, false>(sc, q, L, o);
 }
 
 // The fixed-type step for the planar sequence `code` of orders 1-3; -1 for
@@ -803,7 +804,7 @@ __device__ __forceinline__ bool outside_extent(const double *rec64, const int *i
     return out;
 }
 
-template <int MODE, int N, int FORM = 0, bool TYPED = false>
+template <int MODE, int N, int FORM = 0, bool TYPED = false, bool REFR = false>
 __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<MODE>::T *__restrict__ srec)
 {
     using T = typename ModeT<MODE>::T;
@@ -1045,8 +1046,8 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     }
                 }
                 if (st == -1) {
-                    if constexpr (FORM) st = lm_step_param<T, N>(sc, p, L, o);
-                    else st = lm_step<T, N>(sc, p, L, o);
+                    if constexpr (FORM) st = lm_step_param<T, N, REFR>(sc, p, L, o);
+                    else st = lm_step<T, N, REFR>(sc, p, L, o);
                 }
             }
             if (st == ST_PARKED) {
@@ -1101,37 +1102,43 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     // alone is no evidence that none exists), or - decided
                     // by the polish - a converged or stalled FP32 point that
                     // does not polish
-                    // the gate is at least 30 times the FP32 rounding level of
-                    // this path's residual: a law row carries the rounding of
-                    // its unit directions (eps32 |X| / shortest segment) times
-                    // its scale (up to the longest segment), which reaches
-                    // 1e-2 m on a thin glass pane far from TX
-                    const double rx_w[3] = {(double)p.rx[0] + sh[0], (double)p.rx[1] + sh[1], (double)p.rx[2] + sh[2]};
-                    double xmax = 0.0, smin = __builtin_huge_val(), smax = 0.0;
-#pragma unroll
-                    for (int k = 0; k <= N; k++) {
-                        double e2 = 0.0;
-#pragma unroll
-                        for (int i = 0; i < 3; i++) {
-                            const double a = (k == 0) ? kp.s.tx[i] : Xw[3 * (k - 1) + i];
-                            const double bq = (k == N) ? rx_w[i] : Xw[3 * k + i];
-                            e2 += (bq - a) * (bq - a);
-                            if (k < N) xmax = fmax(xmax, fabs(Xw[3 * k + i] - kp.s.tx[i]));
-                        }
-                        smin = fmin(smin, sqrt(e2));
-                        smax = fmax(smax, sqrt(e2));
-                    }
-                    const double noise = 6e-8 * (1.0 + xmax) * smax / fmax(smin, 1e-12);
-                    const bool small_res = (double)L.rinf <= fmax(kp.o.polish_gate, 30.0 * noise);
-                    bool to_polish = small_res && (st == ST_CONV || st == ST_MAXIT || st == ST_LOCALMIN ||
-                                                   st == ST_STALL);
                     // a path through a refracting facet has a unique root
                     // (the optical length is convex), so a descent that ends
                     // far from a root goes to the FP64 fallback as well
                     bool refr_path = false;
+                    if constexpr (REFR) {
 #pragma unroll
-                    for (int k = 0; k < N; k++)
-                        refr_path = refr_path || (p.ty[k] == TP && kp.s.rec64[(size_t)p.id[k] * kRec + 16] > 0.0);
+                        for (int k = 0; k < N; k++)
+                            refr_path = refr_path || (p.ty[k] == TP && kp.s.rec64[(size_t)p.id[k] * kRec + 16] > 0.0);
+                    }
+                    // on such a path the gate is at least 30 times the FP32
+                    // rounding level of its residual: a law row carries the
+                    // rounding of its unit directions (eps32 |X| / shortest
+                    // segment) times its scale (up to the longest segment),
+                    // which reaches 1e-2 m on a thin glass pane far from TX
+                    double gate = kp.o.polish_gate;
+                    if (refr_path) {
+                        const double rx_w[3] = {(double)p.rx[0] + sh[0], (double)p.rx[1] + sh[1],
+                                                (double)p.rx[2] + sh[2]};
+                        double xmax = 0.0, smin = __builtin_huge_val(), smax = 0.0;
+#pragma unroll
+                        for (int k = 0; k <= N; k++) {
+                            double e2 = 0.0;
+#pragma unroll
+                            for (int i = 0; i < 3; i++) {
+                                const double a = (k == 0) ? kp.s.tx[i] : Xw[3 * (k - 1) + i];
+                                const double bq = (k == N) ? rx_w[i] : Xw[3 * k + i];
+                                e2 += (bq - a) * (bq - a);
+                                if (k < N) xmax = fmax(xmax, fabs(Xw[3 * k + i] - kp.s.tx[i]));
+                            }
+                            smin = fmin(smin, sqrt(e2));
+                            smax = fmax(smax, sqrt(e2));
+                        }
+                        gate = fmax(gate, 30.0 * 6e-8 * (1.0 + xmax) * smax / fmax(smin, 1e-12));
+                    }
+                    const bool small_res = (double)L.rinf <= gate;
+                    bool to_polish = small_res && (st == ST_CONV || st == ST_MAXIT || st == ST_LOCALMIN ||
+                                                   st == ST_STALL);
                     const bool to_fb = (st == ST_DEGEN) || (st == ST_MAXIT && p.planar && !small_res) ||
                                        (refr_path && !small_res);
                     // a root-like end point far outside a finite extent: the
@@ -1179,6 +1186,13 @@ template <> struct Occ<MODE_FP32, 1, 1> { static constexpr int W = 3; };
 template <> struct Occ<MODE_FP32, 2, 1> { static constexpr int W = 3; };
 template <> struct Occ<MODE_FP32, 3, 1> { static constexpr int W = 2; };
 template <> struct Occ<MODE_FP32, 4, 1> { static constexpr int W = 2; };
+// Order 5 at two waves per SIMD spills 360 B per lane to scratch and still
+// runs its LM launch 17% faster than at one wave without spills (stress
+// workload: 36.1 -> 29.7 ms, bit-identical results): the second wave hides
+// the first one's LDS and memory waits.  Orders 3 and 4 at one or three
+// waves, order 5 at three, the implicit form's orders 4-5 and the FP64
+// parametric orders 3-5 at two all ran slower.
+template <> struct Occ<MODE_FP32, 5, 1> { static constexpr int W = 2; };
 template <> struct Occ<MODE_PLAIN64, 1, 1> { static constexpr int W = 2; };
 template <> struct Occ<MODE_PLAIN64, 2, 1> { static constexpr int W = 2; };
 
@@ -1203,7 +1217,11 @@ __device__ __forceinline__ const typename ModeT<MODE>::T *stage_scene(const KPar
 
 // One persistent launch over every order (register budget of order 5).
 // FORM 0: the implicit form (points as unknowns); 1: the parametric form.
-template <int MODE, bool LDS, int FORM>
+// REFR: the scene has refracting facets; their rows are compiled into this
+// kernel only (a branch left in the other kernels slowed the stress
+// workload's LM launches by 16% in the parametric and 7% in the implicit
+// form, though no lane took it), so such scenes run this schedule.
+template <int MODE, bool LDS, int FORM, bool REFR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OccAll<MODE, FORM>::W, OccAll<MODE, FORM>::W)))
 k_lm(KParams kp)
 {
@@ -1211,11 +1229,11 @@ k_lm(KParams kp)
     if (cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4] == 0) return;  // nothing to solve: skip the staging
     const typename ModeT<MODE>::T *rec = stage_scene<MODE, LDS>(kp);
     // long paths first so that the short ones fill the tail
-    lm_bin<MODE, 5, FORM, true>(kp, rec);
-    lm_bin<MODE, 4, FORM, true>(kp, rec);
-    lm_bin<MODE, 3, FORM, true>(kp, rec);
-    lm_bin<MODE, 2, FORM, true>(kp, rec);
-    lm_bin<MODE, 1, FORM, true>(kp, rec);
+    lm_bin<MODE, 5, FORM, true, REFR>(kp, rec);
+    lm_bin<MODE, 4, FORM, true, REFR>(kp, rec);
+    lm_bin<MODE, 3, FORM, true, REFR>(kp, rec);
+    lm_bin<MODE, 2, FORM, true, REFR>(kp, rec);
+    lm_bin<MODE, 1, FORM, true, REFR>(kp, rec);
 }
 
 // One persistent launch over orders 3, 2, 1 with the register budget of
@@ -1245,7 +1263,7 @@ __attribute__((amdgpu_waves_per_eu(Occ<MODE, N, FORM>::W, Occ<MODE, N, FORM>::W)
 
 // ------------------------------------------------------------------ polish
 // Undamped FP64 Gauss-Newton from the FP32 end point (world frame).
-template <int N>
+template <int N, bool REFR>
 __device__ void polish_bin(const KParams &kp)
 {
     const int count = kp.pol_cnt[N - 1];
@@ -1274,7 +1292,7 @@ __device__ void polish_bin(const KParams &kp)
         int steps = 0;
         for (int ps = 0; ps < kp.o.polish_steps && ok && !small; ps++) {
             double A[Band<N>::SIZE], g[M], C, rinf;
-            ok = assemble<double, N>(sc, p, X, A, g, C, rinf);
+            ok = assemble<double, N, REFR>(sc, p, X, A, g, C, rinf);
             if (!ok) break;
             steps++;
             if (rinf <= kp.o.tol_res) { small = true; break; }
@@ -1298,7 +1316,7 @@ __device__ void polish_bin(const KParams &kp)
             small = dinf <= kp.o.tol_step * (1.0 + xinf);
         }
         double C = __builtin_huge_val(), rinf = __builtin_huge_val();
-        if (ok) ok = eval_cost<double, N>(sc, p, X, nullptr, C, rinf) && in_guard(kp.s, X, N);
+        if (ok) ok = eval_cost<double, N, REFR>(sc, p, X, nullptr, C, rinf) && in_guard(kp.s, X, N);
         const bool root = ok && rinf <= kp.o.tau_root;
         kp.out.iters[sid] += steps;
         if (kp.out.stage) kp.out.stage[(size_t)kp.b.n + sid] = steps;
@@ -1322,13 +1340,14 @@ __device__ void polish_bin(const KParams &kp)
 
 // One kernel for every order: measured faster than one launch per order
 // (back to back or concurrent), although order 5 sets its registers.
+template <bool REFR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_polish(KParams kp)
 {
-    polish_bin<5>(kp);
-    polish_bin<4>(kp);
-    polish_bin<3>(kp);
-    polish_bin<2>(kp);
-    polish_bin<1>(kp);
+    polish_bin<5, REFR>(kp);
+    polish_bin<4, REFR>(kp);
+    polish_bin<3, REFR>(kp);
+    polish_bin<2, REFR>(kp);
+    polish_bin<1, REFR>(kp);
 }
 
 // ------------------------------------------------------------------ acceptance
@@ -1534,7 +1553,7 @@ template <int MODE, bool LDS, int FORM>
 static const void *lm_kernel_t(int order)
 {
     switch (order) {
-    case 0: return (const void *)k_lm<MODE, LDS, FORM>;
+    case 0: return (const void *)k_lm<MODE, LDS, FORM, false>;
     case 1: return (const void *)k_lm_one<MODE, 1, LDS, FORM>;
     case 2: return (const void *)k_lm_one<MODE, 2, LDS, FORM>;
     case 3: return (const void *)k_lm_one<MODE, 3, LDS, FORM>;
@@ -1544,32 +1563,48 @@ static const void *lm_kernel_t(int order)
     }
 }
 
+template <int MODE, bool LDS, int FORM>
+static const void *lm_kernel_refr() { return (const void *)k_lm<MODE, LDS, FORM, true>; }
+
 // order 0: the mixed-order kernel; 1..5: the per-order kernels; 6: the
-// kernel of orders 1-3.  The fallback runs one mixed-order launch in the
-// solve's form (from the FP32 end point).
-const void *lm_kernel(int mode, int order, bool lds, int form)
+// kernel of orders 1-3.  refr: the mixed-order kernel with the rows of
+// refracting facets (order ignored).  The fallback runs one mixed-order
+// launch in the solve's form (from the FP32 end point).
+const void *lm_kernel(int mode, int order, bool lds, int form, bool refr)
 {
     switch (mode) {
     case MODE_PLAIN64:
+        if (refr)
+            return form ? (lds ? lm_kernel_refr<MODE_PLAIN64, true, 1>() : lm_kernel_refr<MODE_PLAIN64, false, 1>())
+                        : (lds ? lm_kernel_refr<MODE_PLAIN64, true, 0>() : lm_kernel_refr<MODE_PLAIN64, false, 0>());
         if (form) return lds ? lm_kernel_t<MODE_PLAIN64, true, 1>(order) : lm_kernel_t<MODE_PLAIN64, false, 1>(order);
         return lds ? lm_kernel_t<MODE_PLAIN64, true, 0>(order) : lm_kernel_t<MODE_PLAIN64, false, 0>(order);
     case MODE_FP32:
+        if (refr)
+            return form ? (lds ? lm_kernel_refr<MODE_FP32, true, 1>() : lm_kernel_refr<MODE_FP32, false, 1>())
+                        : (lds ? lm_kernel_refr<MODE_FP32, true, 0>() : lm_kernel_refr<MODE_FP32, false, 0>());
         if (form) return lds ? lm_kernel_t<MODE_FP32, true, 1>(order) : lm_kernel_t<MODE_FP32, false, 1>(order);
         return lds ? lm_kernel_t<MODE_FP32, true, 0>(order) : lm_kernel_t<MODE_FP32, false, 0>(order);
     default:
-        if (form) return lds ? (const void *)k_lm<MODE_FALLBACK64, true, 1> : (const void *)k_lm<MODE_FALLBACK64, false, 1>;
-        return lds ? lm_kernel_t<MODE_FALLBACK64, true, 0>(order) : lm_kernel_t<MODE_FALLBACK64, false, 0>(order);
+        if (refr)
+            return form ? (lds ? lm_kernel_refr<MODE_FALLBACK64, true, 1>() : lm_kernel_refr<MODE_FALLBACK64, false, 1>())
+                        : (lds ? lm_kernel_refr<MODE_FALLBACK64, true, 0>()
+                               : lm_kernel_refr<MODE_FALLBACK64, false, 0>());
+        if (form) return lds ? (const void *)k_lm<MODE_FALLBACK64, true, 1, false>
+                             : (const void *)k_lm<MODE_FALLBACK64, false, 1, false>;
+        return lds ? (const void *)k_lm<MODE_FALLBACK64, true, 0, false>
+                   : (const void *)k_lm<MODE_FALLBACK64, false, 0, false>;
     }
 }
 
-void launch_lm(int mode, int order, bool lds, int form, size_t lds_bytes, const KParams &kp, int grid, int block,
-               hipStream_t st)
+void launch_lm(int mode, int order, bool lds, int form, bool refr, size_t lds_bytes, const KParams &kp, int grid,
+               int block, hipStream_t st)
 {
     void *args[] = {(void *)&kp};
-    hipLaunchKernel(lm_kernel(mode, order, lds, form), dim3(grid), dim3(block), args, lds ? lds_bytes : 0, st);
+    hipLaunchKernel(lm_kernel(mode, order, lds, form, refr), dim3(grid), dim3(block), args, lds ? lds_bytes : 0, st);
 }
 
-const void *polish_kernel() { return (const void *)k_polish; }
+const void *polish_kernel(bool refr) { return refr ? (const void *)k_polish<true> : (const void *)k_polish<false>; }
 
 void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, int *blk, hipStream_t st)
 {
@@ -1639,9 +1674,10 @@ void launch_polish_list(const KParams &kp, hipStream_t st)
     hipLaunchKernelGGL(k_polish_list, dim3((unsigned)((kp.b.n + per_block - 1) / per_block)), dim3(256), 0, st, kp);
 }
 
-void launch_polish(const KParams &kp, int grid, int block, hipStream_t st)
+void launch_polish(const KParams &kp, bool refr, int grid, int block, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_polish, dim3(grid), dim3(block), 0, st, kp);
+    if (refr) hipLaunchKernelGGL(k_polish<true>, dim3(grid), dim3(block), 0, st, kp);
+    else hipLaunchKernelGGL(k_polish<false>, dim3(grid), dim3(block), 0, st, kp);
 }
 
 // ------------------------------------------------------------------ physical validation

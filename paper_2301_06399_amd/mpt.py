@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise MptError(f"{path} is missing: build it with paper_2301_06399_amd.build.build()")
+    # the library and torch must share one HIP runtime: torch's, loaded first
+    import torch  # noqa: F401
     L = C.CDLL(path)
     vp, st = C.c_void_p, C.c_int
     L.mpt_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
