@@ -664,25 +664,24 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     kp.spill_list = w->spf ? ctr + kCounters + 9 * n : nullptr;
     kp.spill_f = w->spf;
 
-    if (timed) hipEventRecord(c->ev[0], s);
-    launch_zero(ctr, kCounters, s);
-    launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, (int *)kp.slot_rx, (int *)kp.slot_prim, s);
-    if (timed) hipEventRecord(c->ev[1], s);
     // the network serves the paths with a curved object: none without
     // paraboloids and circles in the scene
     const bool net = learned && n > 0 && (opts->init == MPT_INIT_LEARNED_ALL || c->s.n_pl_ln < c->s.n_all);
+    // with MPT_INIT_LEARNED the binning lists the paths with a curved object
+    // (in the polish list, free until the FP32 pass)
+    int *rows = (net && opts->init == MPT_INIT_LEARNED) ? (int *)kp.pol_list : nullptr, *rows_cnt = ctr + 30;
+    if (timed) hipEventRecord(c->ev[0], s);
+    launch_zero(ctr, kCounters, s);
+    launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, (int *)kp.slot_rx, (int *)kp.slot_prim, rows,
+               rows_cnt, s);
+    if (timed) hipEventRecord(c->ev[1], s);
     if (net) {
         if (opts->init == MPT_INIT_LEARNED) {
-            // the network serves only the paths with a curved object: list
-            // them (the polish list is free until the FP32 pass) and predict
-            int *rows = (int *)kp.pol_list, *count = ctr + 30;
-            // block counts in the straggler list, free until the LM pass
-            launch_curved_rows(bd, c->s, rows, count, (int *)kp.spill_list, s);
-            st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s, rows, count);
-            if (!st) launch_learned_choose(c->s, bd, rows, count, false, w->x0l, opts->learned_gain, s);
+            st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s, rows, rows_cnt);
+            if (!st) launch_learned_choose(c->s, bd, rows, rows_cnt, false, w->x0l, opts->learned_gain, c->refr, s);
         } else {
             st = mlp_predict_dev(c->mlp, c->s, bd, w->x0l, s);
-            if (!st) launch_learned_choose(c->s, bd, nullptr, nullptr, true, w->x0l, opts->learned_gain, s);
+            if (!st) launch_learned_choose(c->s, bd, nullptr, nullptr, true, w->x0l, opts->learned_gain, c->refr, s);
         }
         if (st) return fail(c, st, "network forward failed");
     }
@@ -1078,9 +1077,9 @@ mpt_status mpt_accept(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_out *
     if (!(tau_res >= 0) || !(min_seg >= 0)) return fail(c, MPT_E_INVALID_ARG, "negative threshold");
     hipSetDevice(c->device);
     const size_t nblk = (size_t)((b->n + 255) / 256);
-    if ((st = ensure(c, (void **)&c->blk, &c->blk_cap, nblk ? nblk : 1, sizeof(int)))) return st;
+    if ((st = ensure(c, (void **)&c->blk, &c->blk_cap, nblk + 1, sizeof(int)))) return st;
     OutDevC ic{in->x, in->cost, in->iters, in->status};
-    launch_accept(c->s, bd, ic, tau_res, min_seg, accept, accepted_idx, d_count, c->blk, c->stream);
+    launch_accept(c->s, bd, ic, tau_res, min_seg, accept, accepted_idx, d_count, c->blk, c->refr, c->stream);
     HIPCHK(c, hipGetLastError());
     if (h_count) {
         int32_t v = 0;

@@ -86,15 +86,16 @@ void launch_pack(const double *raw, const double *refr, const SceneDev &s, int n
                  hipStream_t st);
 void launch_zero(int *p, int n, hipStream_t st);
 int bin_key_count();
+// rows / rows_cnt (or null): the list of the solves with a paraboloid or a
+// circle, appended in no particular order
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
-                int *slot_rx, int *slot_prim, hipStream_t st);
+                int *slot_rx, int *slot_prim, int *rows, int *rows_cnt, hipStream_t st);
 const void *lm_kernel(int mode, int order, bool lds, int form, bool refr);
 void launch_lm(int mode, int order, bool lds, int form, bool refr, size_t lds_bytes, const KParams &kp, int grid,
                int block, hipStream_t st);
 const void *polish_kernel(bool refr);
-void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, int *blk, hipStream_t st);
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
-                           double *x0l, double gain, hipStream_t st);
+                           double *x0l, double gain, bool refr, hipStream_t st);
 void launch_polish(const KParams &kp, bool refr, int grid, int block, hipStream_t st);
 void launch_polish_list(const KParams &kp, hipStream_t st);
 void launch_samples(const SceneDev &s, int k, double *samp, int *cnt, hipStream_t st);
@@ -111,6 +112,6 @@ void launch_cand_fill(const SceneDev &s, const uint32_t *V, const uint32_t *B, c
 void launch_visible(const SceneDev &s, const BatchDev &b, const OutDevC &in, const uint8_t *acc, double min_seg,
                     uint8_t *vis, int *count, int *list, size_t lds_max, int cu, hipStream_t st);
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
-                   uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st);
+                   uint8_t *acc, int *idx, int *count, int *block_cnt, bool refr, hipStream_t st);
 
 }  // namespace mpt

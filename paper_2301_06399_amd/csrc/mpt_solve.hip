@@ -204,18 +204,25 @@ __device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
 
 // Each solve's slot in bin order, and its receiver and primitive ids copied
 // to that slot: the solver reads a wave's paths from consecutive slots
-// (coalesced) instead of gathering them by solve id.
+// (coalesced) instead of gathering them by solve id.  With `rows`, the
+// solves whose list holds a paraboloid or a circle (a type digit of 2 or 3
+// in the key) are also listed there, one atomic per block (the paths the
+// learned start serves; their order in the list does not matter).
 __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all, int n_pl, int n_pl_ln, int n_pl_ln_q,
                                                             const int *__restrict__ key_off,
                                                             int *__restrict__ key_cursor, int *__restrict__ perm,
-                                                            int *__restrict__ slot_rx, int *__restrict__ slot_prim)
+                                                            int *__restrict__ slot_rx, int *__restrict__ slot_prim,
+                                                            int *__restrict__ rows, int *__restrict__ rows_cnt)
 {
     __shared__ int loc[kNumKeys];
     __shared__ int gbase[kNumKeys];
+    __shared__ int ccount, cbase;
     for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock) loc[k] = 0;
+    if (threadIdx.x == 0) ccount = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
-    int key[kBinItems], rank[kBinItems], ords[kBinItems];
+    const int lane = __lane_id();
+    int key[kBinItems], rank[kBinItems], ords[kBinItems], crank[kBinItems];
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
@@ -223,10 +230,18 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
         ords[j] = ord;
         key[j] = (ord > 0) ? bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q) : -1;
         rank[j] = (key[j] >= 0) ? atomicAdd(&loc[key[j]], 1) : 0;
+        // base-4 type digits: 2 (quadric) and 3 (circle) have bit 1 set
+        const bool cur = rows && key[j] >= 0 && ((key[j] - kKeyBase[ord > 0 ? ord : 1]) & 0x2AA) != 0;
+        const uint64_t m = __ballot(cur);
+        int wb = 0;
+        if (lane == 0 && m) wb = atomicAdd(&ccount, (int)__popcll(m));
+        wb = __shfl(wb, 0);
+        crank[j] = cur ? wb + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock)
         gbase[k] = loc[k] ? key_off[k] + atomicAdd(&key_cursor[k], loc[k]) : 0;
+    if (threadIdx.x == 0) cbase = (rows && ccount) ? atomicAdd(rows_cnt, ccount) : 0;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
@@ -238,75 +253,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
             for (int k = 0; k < kMaxN; k++)
                 if (k < ords[j]) slot_prim[(size_t)k * b.n + slot] = b.prim[(size_t)k * b.n + i];
         }
-    }
-}
-
-// The solves with a paraboloid or circle (the paths the learned start serves), listed in increasing id order
-// without a contended counter: each of the grid's blocks owns a contiguous
-// range of solves; pass 1 counts per block, pass 2 scans the block counts
-// (one block), pass 3 writes each block's solves at its offset.
-__device__ __forceinline__ bool curved_row(const BatchDev &b, int64_t i, int n_all, int n_pl_ln)
-{
-    bool mine = false;
-    if (i < b.n) {
-        const int ord = valid_order(b, i, n_all);
-        for (int k = 0; k < kMaxN; k++)
-            if (k < ord) mine = mine || b.prim[(size_t)k * b.n + i] >= n_pl_ln;
-    }
-    return mine;
-}
-
-__global__ void __launch_bounds__(256) k_curved_count(BatchDev b, int n_all, int n_pl_ln, int64_t per,
-                                                       int *__restrict__ blk_cnt)
-{
-    __shared__ int red[4];
-    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(b.n, i0 + per);
-    int c = 0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) c += curved_row(b, i, n_all, n_pl_ln);
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
-    if (__lane_id() == 0) red[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-// exclusive scan of nblk (<= 1024) counts in place; *count = the total
-__global__ void __launch_bounds__(1024) k_curved_scan(int *__restrict__ blk_cnt, int nblk, int *__restrict__ count)
-{
-    __shared__ int s[1024];
-    const int t = threadIdx.x;
-    s[t] = (t < nblk) ? blk_cnt[t] : 0;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int v = (t >= o) ? s[t - o] : 0;
-        __syncthreads();
-        s[t] += v;
-        __syncthreads();
-    }
-    if (t < nblk) blk_cnt[t] = s[t] - ((t < nblk) ? blk_cnt[t] : 0);
-    if (t == 1023) *count = s[t];
-}
-
-__global__ void __launch_bounds__(256) k_curved_fill(BatchDev b, int n_all, int n_pl_ln, int64_t per,
-                                                      const int *__restrict__ blk_off, int *__restrict__ rows)
-{
-    __shared__ int wsum[4];
-    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(b.n, i0 + per);
-    int base = blk_off[blockIdx.x];
-    const int w = threadIdx.x >> 6, lane = __lane_id();
-    for (int64_t j0 = i0; j0 < i1; j0 += blockDim.x) {
-        const int64_t i = j0 + threadIdx.x;
-        const bool mine = (i < i1) && curved_row(b, i, n_all, n_pl_ln);
-        const uint64_t m = __ballot(mine);
-        if (lane == 0) wsum[w] = (int)__popcll(m);
-        __syncthreads();
-        int before = 0, tot = 0;
-        for (int q = 0; q < 4; q++) {
-            before += (q < w) ? wsum[q] : 0;
-            tot += wsum[q];
-        }
-        if (mine) rows[base + before + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int)i;
-        base += tot;
-        __syncthreads();
+        if (crank[j] >= 0) rows[cbase + crank[j]] = (int)i;
     }
 }
 
@@ -388,7 +335,7 @@ __device__ __forceinline__ double line_fraction(int ty, const double *r, const d
     return a;
 }
 
-template <int N>
+template <int N, bool REFR>
 __device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, double *__restrict__ x0l, double gain)
 {
     SceneT<double> s64;
@@ -425,13 +372,14 @@ __device__ void choose_start(const SceneDev &s, const BatchDev &b, int64_t i, do
         project(q.ty[k], r, okn ? Pn : P, Xn + 3 * k);
     }
     double c0 = 0.0, r0 = 0.0, c1 = 0.0, r1 = 0.0;
-    const bool ok0 = eval_cost<double, N>(s64, q, X0, nullptr, c0, r0);
-    const bool ok1 = okn && eval_cost<double, N>(s64, q, Xn, nullptr, c1, r1);
+    const bool ok0 = eval_cost<double, N, REFR>(s64, q, X0, nullptr, c0, r0);
+    const bool ok1 = okn && eval_cost<double, N, REFR>(s64, q, Xn, nullptr, c1, r1);
     const bool net = ok1 && (!ok0 || c1 < gain * c0);
 #pragma unroll
     for (int j = 0; j < 3 * N; j++) x0l[(size_t)i * kRow + j] = net ? Xn[j] : X0[j];
 }
 
+template <bool REFR>
 __global__ void __launch_bounds__(256) k_learned_choose(SceneDev s, BatchDev b, const int *__restrict__ rows,
                                                         const int *__restrict__ count, int all,
                                                         double *__restrict__ x0l, double gain)
@@ -440,11 +388,11 @@ __global__ void __launch_bounds__(256) k_learned_choose(SceneDev s, BatchDev b, 
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = all ? t : rows[t];
         switch (valid_order(b, i, s.n_all)) {
-        case 1: choose_start<1>(s, b, i, x0l, gain); break;
-        case 2: choose_start<2>(s, b, i, x0l, gain); break;
-        case 3: choose_start<3>(s, b, i, x0l, gain); break;
-        case 4: choose_start<4>(s, b, i, x0l, gain); break;
-        case 5: choose_start<5>(s, b, i, x0l, gain); break;
+        case 1: choose_start<1, REFR>(s, b, i, x0l, gain); break;
+        case 2: choose_start<2, REFR>(s, b, i, x0l, gain); break;
+        case 3: choose_start<3, REFR>(s, b, i, x0l, gain); break;
+        case 4: choose_start<4, REFR>(s, b, i, x0l, gain); break;
+        case 5: choose_start<5, REFR>(s, b, i, x0l, gain); break;
         default: break;
         }
     }
@@ -1357,7 +1305,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 // normal that acceptance allows.
 constexpr double kGraze = 1e-9;
 
-template <int N>
+template <int N, bool REFR>
 __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, const int *ty, const double *X,
                             double tau_res, double min_seg)
 {
@@ -1371,7 +1319,7 @@ __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, 
 #pragma unroll
     for (int k = 0; k < N; k++) { p.id[k] = id[k]; p.ty[k] = ty[k]; }
     double C, rinf;
-    bool ok = eval_cost<double, N>(sc, p, X, nullptr, C, rinf) && (rinf <= tau_res);
+    bool ok = eval_cost<double, N, REFR>(sc, p, X, nullptr, C, rinf) && (rinf <= tau_res);
 #pragma unroll
     for (int k = 0; k <= N; k++) {
         const double *P = (k == 0) ? s.tx : X + 3 * (k - 1);
@@ -1433,16 +1381,57 @@ __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, 
     return ok;
 }
 
-__global__ void __launch_bounds__(256) k_accept_flags(SceneDev s, BatchDev b, OutDevC in, double tau_res,
-                                                       double min_seg, uint8_t *__restrict__ acc,
-                                                       int *__restrict__ block_cnt)
+// Pass 1: clear the flags and list the converged solves, the only ones the
+// test can accept (a few percent of a batch), so that the FP64 test runs on
+// full waves instead of one or two lanes of each.  A block covers
+// 256 x kAccItems solves and takes its part of the list with one atomic (one
+// per wave contended on the counter and cost more than the test itself).
+constexpr int kAccItems = 16;
+__global__ void __launch_bounds__(256) k_accept_list(BatchDev b, const uint8_t *__restrict__ status,
+                                                      uint8_t *__restrict__ acc, int *__restrict__ list,
+                                                      int *__restrict__ cnt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool a = false;
-    if (i < b.n) {
+    __shared__ int bcount, bbase;
+    if (threadIdx.x == 0) bcount = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * 256 * kAccItems;
+    const int lane = __lane_id();
+    int r[kAccItems];
+#pragma unroll
+    for (int j = 0; j < kAccItems; j++) {
+        const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
+        bool c = false;
+        if (i < b.n) {
+            const int ord = b.order[i];
+            c = ord >= 1 && ord <= kMaxN && (status[i] & 0x7f) == ST_CONV;
+            acc[i] = 0;
+        }
+        const uint64_t m = __ballot(c);
+        int wb = 0;
+        if (lane == 0 && m) wb = atomicAdd(&bcount, (int)__popcll(m));
+        wb = __shfl(wb, 0);
+        r[j] = c ? wb + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) bbase = bcount ? atomicAdd(cnt, bcount) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kAccItems; j++)
+        if (r[j] >= 0) list[bbase + r[j]] = (int)(base + (int64_t)j * 256 + threadIdx.x);
+}
+
+// Pass 2: the test on the listed solves (grid-stride over the list).
+template <bool REFR>
+__global__ void __launch_bounds__(256) k_accept_eval(SceneDev s, BatchDev b, OutDevC in, double tau_res,
+                                                      double min_seg, uint8_t *__restrict__ acc,
+                                                      const int *__restrict__ list, const int *__restrict__ cnt)
+{
+    const int m = *cnt;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const int64_t i = list[t];
         const int ord = b.order[i];
-        const uint8_t st = in.status[i];
-        if (ord >= 1 && ord <= kMaxN && (st & 0x7f) == ST_CONV) {
+        bool a = false;
+        {
             const int ri = b.rx_index[i];
             double rx[3], X[3 * kMaxN];
             int id[kMaxN], ty[kMaxN];
@@ -1456,16 +1445,24 @@ __global__ void __launch_bounds__(256) k_accept_flags(SceneDev s, BatchDev b, Ou
             }
             if (okid) {
                 switch (ord) {
-                case 1: a = accept_path<1>(s, rx, id, ty, X, tau_res, min_seg); break;
-                case 2: a = accept_path<2>(s, rx, id, ty, X, tau_res, min_seg); break;
-                case 3: a = accept_path<3>(s, rx, id, ty, X, tau_res, min_seg); break;
-                case 4: a = accept_path<4>(s, rx, id, ty, X, tau_res, min_seg); break;
-                default: a = accept_path<5>(s, rx, id, ty, X, tau_res, min_seg); break;
+                case 1: a = accept_path<1, REFR>(s, rx, id, ty, X, tau_res, min_seg); break;
+                case 2: a = accept_path<2, REFR>(s, rx, id, ty, X, tau_res, min_seg); break;
+                case 3: a = accept_path<3, REFR>(s, rx, id, ty, X, tau_res, min_seg); break;
+                case 4: a = accept_path<4, REFR>(s, rx, id, ty, X, tau_res, min_seg); break;
+                default: a = accept_path<5, REFR>(s, rx, id, ty, X, tau_res, min_seg); break;
                 }
             }
         }
         acc[i] = a ? 1 : 0;
     }
+}
+
+// Pass 3: accepted solves per block of 256 (for the ordered compaction).
+__global__ void __launch_bounds__(256) k_accept_count(const uint8_t *__restrict__ acc, int64_t n,
+                                                       int *__restrict__ block_cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool a = (i < n) && acc[i];
     __shared__ int wcnt[4];
     const uint64_t m = __ballot(a);
     if (__lane_id() == 0) wcnt[threadIdx.x >> 6] = (int)__popcll(m);
@@ -1537,7 +1534,7 @@ int bin_key_count() { return kNumKeys; }
 
 // keys: [3][kNumKeys] ints (counts, offsets, cursors), zeroed by the caller
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
-                int *slot_rx, int *slot_prim, hipStream_t st)
+                int *slot_rx, int *slot_prim, int *rows, int *rows_cnt, hipStream_t st)
 {
     if (b.n == 0) return;
     const unsigned g = (unsigned)((b.n + kBinBlock * kBinItems - 1) / (kBinBlock * kBinItems));
@@ -1546,7 +1543,7 @@ void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bi
                        kcnt);
     hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, kcnt, koff, bin_cnt);
     hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), 0, st, b, s.n_all, s.n_pl, s.n_pl_ln, s.n_pl_ln_q,
-                       koff, kcur, perm, slot_rx, slot_prim);
+                       koff, kcur, perm, slot_rx, slot_prim, rows, rows_cnt);
 }
 
 template <int MODE, bool LDS, int FORM>
@@ -1606,24 +1603,13 @@ void launch_lm(int mode, int order, bool lds, int form, bool refr, size_t lds_by
 
 const void *polish_kernel(bool refr) { return refr ? (const void *)k_polish<true> : (const void *)k_polish<false>; }
 
-void launch_curved_rows(const BatchDev &b, const SceneDev &s, int *rows, int *count, int *blk, hipStream_t st)
-{
-    if (b.n == 0) return;
-    // blocks of at least 256 solves, at most 1024 of them (blk holds one
-    // count each; the caller's scratch has at least that many entries)
-    const int64_t nblk = std::min<int64_t>(1024, (b.n + 255) / 256);
-    const int64_t per = (b.n + nblk - 1) / nblk;
-    hipLaunchKernelGGL(k_curved_count, dim3((unsigned)nblk), dim3(256), 0, st, b, s.n_all, s.n_pl_ln, per, blk);
-    hipLaunchKernelGGL(k_curved_scan, dim3(1), dim3(1024), 0, st, blk, (int)nblk, count);
-    hipLaunchKernelGGL(k_curved_fill, dim3((unsigned)nblk), dim3(256), 0, st, b, s.n_all, s.n_pl_ln, per, blk, rows);
-}
-
 void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows, const int *count, bool all,
-                           double *x0l, double gain, hipStream_t st)
+                           double *x0l, double gain, bool refr, hipStream_t st)
 {
     if (b.n == 0) return;
     const unsigned g = (unsigned)std::min<int64_t>((b.n + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_learned_choose, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l, gain);
+    if (refr) hipLaunchKernelGGL(k_learned_choose<true>, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l, gain);
+    else hipLaunchKernelGGL(k_learned_choose<false>, dim3(g), dim3(256), 0, st, s, b, rows, count, all ? 1 : 0, x0l, gain);
 }
 
 // The polish list: the solves the FP32 passes routed to the polish, grouped
@@ -1681,15 +1667,24 @@ void launch_polish(const KParams &kp, bool refr, int grid, int block, hipStream_
 }
 
 // ------------------------------------------------------------------ physical validation
+// block_cnt: nblk + 1 ints (the last one counts the listed solves); the
+// converged solves are listed in idx, which the compaction then overwrites
 void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, double tau_res, double min_seg,
-                   uint8_t *acc, int *idx, int *count, int *block_cnt, hipStream_t st)
+                   uint8_t *acc, int *idx, int *count, int *block_cnt, bool refr, hipStream_t st)
 {
     const int nblk = (int)((b.n + 255) / 256);
     if (nblk == 0) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, count, 1);
         return;
     }
-    hipLaunchKernelGGL(k_accept_flags, dim3(nblk), dim3(256), 0, st, s, b, in, tau_res, min_seg, acc, block_cnt);
+    int *lcnt = block_cnt + nblk;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, lcnt, 1);
+    hipLaunchKernelGGL(k_accept_list, dim3((unsigned)((b.n + 256 * kAccItems - 1) / (256 * kAccItems))), dim3(256), 0,
+                       st, b, in.status, acc, idx, lcnt);
+    const dim3 g(std::min(nblk, 2048));
+    if (refr) hipLaunchKernelGGL(k_accept_eval<true>, g, dim3(256), 0, st, s, b, in, tau_res, min_seg, acc, idx, lcnt);
+    else hipLaunchKernelGGL(k_accept_eval<false>, g, dim3(256), 0, st, s, b, in, tau_res, min_seg, acc, idx, lcnt);
+    hipLaunchKernelGGL(k_accept_count, dim3(nblk), dim3(256), 0, st, acc, b.n, block_cnt);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_cnt, nblk, count);
     hipLaunchKernelGGL(k_accept_scatter, dim3(nblk), dim3(256), 0, st, acc, b.n, block_cnt, idx);
 }
