@@ -504,6 +504,13 @@ __host__ __device__ __forceinline__ bool param_map(int t, const T *__restrict__ 
     return ok;
 }
 
+// The angle of a circle's start point, out of line: inlined, the FP64
+// arctangent's registers count in every solver kernel (whose start code
+// holds it) whether or not a circle is solved; called, it costs a register
+// save only on the paths that take it.  Order-5 parametric FP32 kernel:
+// 236 -> 80 bytes of spill per lane.
+__host__ __device__ __attribute__((noinline)) inline double circle_angle(double y, double x) { return atan2(y, x); }
+
 // Parameters of a point of an object (the start points, already put on it).
 __host__ __device__ __forceinline__ bool param_of(int t, const double *__restrict__ r, const double X[3],
                                                   double U[2])
@@ -528,7 +535,7 @@ __host__ __device__ __forceinline__ bool param_of(int t, const double *__restric
         U[1] = dot3(d, e2);
         return r[17] > 0.0;
     }
-    U[0] = r[6] * atan2(d[0] * r[10] + d[1] * r[11] + d[2] * r[12], d[0] * r[7] + d[1] * r[8] + d[2] * r[9]);
+    U[0] = r[6] * circle_angle(d[0] * r[10] + d[1] * r[11] + d[2] * r[12], d[0] * r[7] + d[1] * r[8] + d[2] * r[9]);
     return true;
 }
 
@@ -538,25 +545,28 @@ template <typename T, int N, bool REFR = true>
 __host__ __device__ __forceinline__ bool eval_cost_param(const SceneT<T> &sc, const PathIn<T, N> &p, const T *U,
                                                 const T *dU, T &C, T &rinf, bool &guard)
 {
-    T X[3 * N], Tm[3][2];
+    // points k-1, k, k+1 in a rolling window (slot j % 3): point j is mapped
+    // just before the rows that first need it, so at most three are live
+    T Xw[3][3], Tm[3][2];
     bool ok = true;
     guard = true;
+    auto map = [&](int j) {
+        const T s = U[2 * j] + (dU ? dU[2 * j] : T(0)), u = U[2 * j + 1] + (dU ? dU[2 * j + 1] : T(0));
+        ok = param_map<T>(p.ty[j], sc.rec + (size_t)p.id[j] * kRec, s, u, Xw[j % 3], Tm) && ok;
 #pragma unroll
-    for (int k = 0; k < N; k++) {
-        const T s = U[2 * k] + (dU ? dU[2 * k] : T(0)), u = U[2 * k + 1] + (dU ? dU[2 * k + 1] : T(0));
-        ok = param_map<T>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, s, u, X + 3 * k, Tm) && ok;
-#pragma unroll
-        for (int i = 0; i < 3; i++) guard = guard && (X[3 * k + i] >= sc.glo[i]) && (X[3 * k + i] <= sc.ghi[i]);
-    }
+        for (int i = 0; i < 3; i++) guard = guard && (Xw[j % 3][i] >= sc.glo[i]) && (Xw[j % 3][i] <= sc.ghi[i]);
+    };
+    map(0);
     C = T(0);
     rinf = T(0);
 #pragma unroll
     for (int k = 0; k < N; k++) {
-        T Xp[3], Xn[3], u[5];
-        point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
-        point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
-        const bool okk = interaction_rows<T, false, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
-                                                    nullptr, nullptr, nullptr);
+        if (k + 1 < N) map(k + 1);
+        T u[5];
+        const T *Xp = (k == 0) ? sc.tx : Xw[(k + 2) % 3];
+        const T *Xn = (k + 1 < N) ? Xw[(k + 1) % 3] : p.rx;
+        const bool okk = interaction_rows<T, false, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xw[k % 3], Xn,
+                                                          u, nullptr, nullptr, nullptr);
         ok = ok && okk;
 #pragma unroll
         for (int i = 0; i < 3; i++) {
@@ -581,20 +591,26 @@ __host__ __device__ __forceinline__ bool assemble_param(const SceneT<T> &sc, con
             if (Band<N, 2>::in(i, j)) A[Band<N, 2>::at(i, j)] = T(0);
 #pragma unroll
     for (int i = 0; i < M; i++) g[i] = T(0);
-    T X[3 * N], Tm[N][3][2];
+    // points and parametrisation Jacobians of interactions k-1, k, k+1 in a
+    // rolling window (slot j % 3), mapped just before the rows that first
+    // need them: at most three are live instead of all N
+    T Xw[3][3], Tw[3][3][2];
     bool ok = true;
-#pragma unroll
-    for (int k = 0; k < N; k++)
-        ok = param_map<T>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, U[2 * k], U[2 * k + 1], X + 3 * k, Tm[k]) && ok;
+    auto map = [&](int j) {
+        ok = param_map<T>(p.ty[j], sc.rec + (size_t)p.id[j] * kRec, U[2 * j], U[2 * j + 1], Xw[j % 3], Tw[j % 3]) &&
+             ok;
+    };
+    map(0);
     C = T(0);
     rinf = T(0);
 #pragma unroll
     for (int k = 0; k < N; k++) {
-        T Xp[3], Xn[3], u[5], Jp[3][3], Jk[5][3], Jn[3][3];
-        point_at<T, N>(k - 1, X, nullptr, sc.tx, p.rx, Xp);
-        point_at<T, N>(k + 1, X, nullptr, sc.tx, p.rx, Xn);
-        const bool okk = interaction_rows<T, true, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, X + 3 * k, Xn, u,
-                                                   Jp, Jk, Jn);
+        if (k + 1 < N) map(k + 1);
+        T u[5], Jp[3][3], Jk[5][3], Jn[3][3];
+        const T *Xp = (k == 0) ? sc.tx : Xw[(k + 2) % 3];
+        const T *Xn = (k + 1 < N) ? Xw[(k + 1) % 3] : p.rx;
+        const bool okk = interaction_rows<T, true, REFR>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, Xp, Xw[k % 3], Xn,
+                                                         u, Jp, Jk, Jn);
         ok = ok && okk;
 #pragma unroll
         for (int row = 0; row < 3; row++) {
@@ -608,9 +624,9 @@ __host__ __device__ __forceinline__ bool assemble_param(const SceneT<T> &sc, con
                 T vp = T(0), vk = T(0), vn = T(0);
 #pragma unroll
                 for (int j = 0; j < 3; j++) {
-                    if (k > 0) vp += Jp[row][j] * Tm[k > 0 ? k - 1 : 0][j][c];
-                    vk += Jk[row][j] * Tm[k][j][c];
-                    if (k + 1 < N) vn += Jn[row][j] * Tm[k + 1 < N ? k + 1 : 0][j][c];
+                    if (k > 0) vp += Jp[row][j] * Tw[(k + 2) % 3][j][c];
+                    vk += Jk[row][j] * Tw[k % 3][j][c];
+                    if (k + 1 < N) vn += Jn[row][j] * Tw[(k + 1) % 3][j][c];
                 }
                 jr[c] = vp;
                 jr[2 + c] = vk;

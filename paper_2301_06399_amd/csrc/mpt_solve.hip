@@ -841,7 +841,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     // fallback and the straggler pass go by solve id
                     const bool binned = !resume && MODE != MODE_FALLBACK64;
                     const int *pid = binned ? kp.slot_prim + slot : kp.b.prim + sid;
-                    double rx[3], X0[3 * N];
+                    double rx[3];
                     const int ri = binned ? kp.slot_rx[slot] : kp.b.rx_index[sid];
 #pragma unroll
                     for (int i = 0; i < 3; i++) rx[i] = kp.b.rx[3 * (size_t)ri + i];
@@ -870,7 +870,7 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                         L.C = T(__builtin_huge_val());
                         L.rinf = T(__builtin_huge_val());
                     } else {
-                    bool ok = true;
+                    bool ok = true, inside = true;
                     // the fallback restarts from the FP32 end point (already root-like)
                     const int init = (MODE == MODE_FALLBACK64) ? INIT_USER : kp.o.init;
                     // the learned start serves the paths with a curved object;
@@ -878,14 +878,24 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     bool use_net = (init == INIT_LEARNED_ALL);
                     if (init == INIT_LEARNED)
                         for (int k = 0; k < N; k++) use_net = use_net || p.ty[k] == TQ || p.ty[k] == TC;
-                    if (init == INIT_RANDOM || init == INIT_LINE || (init == INIT_LEARNED && !use_net)) {
-                        // the projection onto each object of a point on the
-                        // TX -> RX segment, or of a random point of the scene box
-                        const bool rnd = init == INIT_RANDOM;
+                    const bool from_line = init == INIT_RANDOM || init == INIT_LINE || (init == INIT_LEARNED && !use_net);
+                    const bool rnd = init == INIT_RANDOM;
+                    // the fallback's FP32 end point, the caller's points, or
+                    // the learned start chosen before the LM pass
+                    const double *x0 = (MODE == MODE_FALLBACK64) ? kp.out.x
+                                       : (init == INIT_USER)     ? kp.b.x0
+                                                                 : kp.x0_learned;
+                    // one interaction at a time (few FP64 values live beside
+                    // the busy lanes' state): its start point, its parameters
+                    // in the parametric form, the guard box test
 #pragma unroll
-                        for (int k = 0; k < N; k++) {
-                            const double *rk = kp.s.rec64 + (size_t)p.id[k] * kRec;
-                            const double a = line_fraction(p.ty[k], rk, kp.s.tx, rx, k, N);
+                    for (int k = 0; k < N; k++) {
+                        const double *r64 = kp.s.rec64 + (size_t)p.id[k] * kRec;
+                        double Xk[3];
+                        if (from_line) {
+                            // the projection onto the object of a point on the
+                            // TX -> RX segment, or of a random point of the scene box
+                            const double a = line_fraction(p.ty[k], r64, kp.s.tx, rx, k, N);
                             double P[3];
 #pragma unroll
                             for (int i = 0; i < 3; i++) {
@@ -896,54 +906,37 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                                     P[i] = kp.s.tx[i] + a * (rx[i] - kp.s.tx[i]);
                                 }
                             }
-                            project(p.ty[k], kp.s.rec64 + (size_t)p.id[k] * kRec, P, X0 + 3 * k);
-                        }
-                    } else {
-                        // the fallback's FP32 end point, the caller's points,
-                        // or the learned start chosen before the LM pass
-                        const double *x0 = (MODE == MODE_FALLBACK64) ? kp.out.x
-                                           : (init == INIT_USER)     ? kp.b.x0
-                                                                     : kp.x0_learned;
+                            project(p.ty[k], r64, P, Xk);
+                        } else {
 #pragma unroll
-                        for (int j = 0; j < 3 * N; j++) {
-                            X0[j] = x0[(size_t)sid * kRow + j];
-                            ok = ok && isfinite(X0[j]);
+                            for (int i = 0; i < 3; i++) {
+                                Xk[i] = x0[(size_t)sid * kRow + 3 * k + i];
+                                ok = ok && isfinite(Xk[i]);
+                            }
                         }
-                    }
-                    int st0 = ST_RUNNING;
-                    if constexpr (FORM) {
-                        // the parameters of the start points; the path starts
-                        // at X(U), which must lie in the guard box
-                        double U[2 * N];
-#pragma unroll
-                        for (int k = 0; k < N; k++) {
-                            const double *r64 = kp.s.rec64 + (size_t)p.id[k] * kRec;
+                        if constexpr (FORM) {
+                            // the parameters of the start point; the path
+                            // starts at X(U), which must lie in the guard box
                             double u2[2];
-                            ok = param_of(p.ty[k], r64, X0 + 3 * k, u2) && ok;
-                            U[2 * k] = u2[0];
-                            U[2 * k + 1] = u2[1];
+                            ok = param_of(p.ty[k], r64, Xk, u2) && ok;
                             if (p.ty[k] == TQ) {
                                 // the start point lifted onto the paraboloid
                                 double e1[3], e2[3];
                                 across_dir(r64 + 13, e1, e2);
                                 const double h = r64[17] * (u2[0] * u2[0] + u2[1] * u2[1]);
 #pragma unroll
-                                for (int i = 0; i < 3; i++)
-                                    X0[3 * k + i] = r64[i] + u2[0] * e1[i] + u2[1] * e2[i] + h * r64[13 + i];
+                                for (int i = 0; i < 3; i++) Xk[i] = r64[i] + u2[0] * e1[i] + u2[1] * e2[i] + h * r64[13 + i];
                             }
+                            L.X[2 * k] = (T)u2[0];
+                            L.X[2 * k + 1] = (T)u2[1];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(Xk[i] - sh[i]);
                         }
-                        if (!ok) st0 = ST_BAD;
-                        else if (!in_guard(kp.s, X0, N)) st0 = ST_DIVERGED;
 #pragma unroll
-                        for (int j = 0; j < D; j++) L.X[j] = (T)U[j];
-                    } else {
-                        if (!ok) st0 = ST_BAD;
-                        else if (!in_guard(kp.s, X0, N)) st0 = ST_DIVERGED;
-#pragma unroll
-                        for (int k = 0; k < N; k++)
-#pragma unroll
-                            for (int i = 0; i < 3; i++) L.X[3 * k + i] = (T)(X0[3 * k + i] - sh[i]);
+                        for (int i = 0; i < 3; i++) inside = inside && (Xk[i] >= kp.s.glo[i]) && (Xk[i] <= kp.s.ghi[i]);
                     }
+                    int st0 = !ok ? ST_BAD : !inside ? ST_DIVERGED : ST_RUNNING;
                     if (MODE != MODE_FALLBACK64 && st0 == ST_RUNNING && sides_forbid_root<N>(kp.s, p.id, p.ty, rx))
                         st0 = ST_LOCALMIN;
                     L.it = 0;
@@ -954,10 +947,25 @@ __device__ __forceinline__ void lm_bin(const KParams &kp, const typename ModeT<M
                     L.rinf = T(__builtin_huge_val());
                     L.Cref = L.C;
                     if (st0 != ST_RUNNING) {
-                        // finished before the first iteration
+                        // finished before the first iteration: the start
+                        // points as the solver holds them (zeros for bad input)
+                        double Xs[3 * N];
+#pragma unroll
+                        for (int k = 0; k < N; k++) {
+                            if constexpr (FORM) {
+                                T Xk[3], Tm[3][2];
+                                param_map<T>(p.ty[k], sc.rec + (size_t)p.id[k] * kRec, L.X[2 * k], L.X[2 * k + 1], Xk,
+                                             Tm);
+#pragma unroll
+                                for (int i = 0; i < 3; i++) Xs[3 * k + i] = (double)Xk[i] + sh[i];
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < 3; i++) Xs[3 * k + i] = (double)L.X[3 * k + i] + sh[i];
+                            }
+                        }
 #pragma unroll
                         for (int j = 0; j < kRow; j++)
-                            kp.out.x[(size_t)sid * kRow + j] = (j < 3 * N && st0 != ST_BAD) ? X0[j < 3 * N ? j : 0] : 0.0;
+                            kp.out.x[(size_t)sid * kRow + j] = (j < 3 * N && st0 != ST_BAD) ? Xs[j < 3 * N ? j : 0] : 0.0;
                         kp.out.cost[sid] = __builtin_huge_val();
                         if (MODE != MODE_FALLBACK64) {
                             kp.out.iters[sid] = 0;
