@@ -460,6 +460,27 @@ __host__ __device__ __forceinline__ void across_dir(const T *a, T u1[3], T u2[3]
     u2[2] = -a[1];
 }
 
+// sin and cos of a (radians) in FP32 for the FP32 solver, which evaluates
+// them in every iteration of a circle path.  Cody-Waite reduction by pi/2,
+// split into three floats of 8, 11 and 24 significant bits (k p1 and k p2
+// are exact for |k| < 4096, |a| < 6400), then the Taylor series of sin to
+// r^9 and cos to r^8 on |r| <= pi/4 (truncation error below 3e-8).  The
+// library routine's wide-range reduction raised the register budget of
+// every parametric FP32 kernel (order 5: 80 -> 64 bytes of spill per lane).
+__host__ __device__ __forceinline__ void sincos32(float a, float &s, float &c)
+{
+    const float k = rintf(a * 0x1.45f306p-1f);  // a / (pi/2), rounded
+    float r = fmaf(-k, 0x1.92p0f, a);
+    r = fmaf(-k, 0x1.fb4p-12f, r);
+    r = fmaf(-k, 0x1.4442d2p-24f, r);
+    const float r2 = r * r;
+    const float sp = r + r * r2 * (-1.0f / 6.0f + r2 * (1.0f / 120.0f + r2 * (-1.0f / 5040.0f + r2 * (1.0f / 362880.0f))));
+    const float cp = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24.0f + r2 * (-1.0f / 720.0f + r2 * (1.0f / 40320.0f))));
+    const int q = (int)k & 3;  // a = k pi/2 + r
+    s = (q == 0) ? sp : (q == 1) ? cp : (q == 2) ? -sp : -cp;
+    c = (q == 0) ? cp : (q == 1) ? -sp : (q == 2) ? -cp : sp;
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ bool param_map(int t, const T *__restrict__ r, T s, T u, T X[3], T Tm[3][2])
 {
@@ -493,7 +514,13 @@ __host__ __device__ __forceinline__ bool param_map(int t, const T *__restrict__ 
         }
     } else {
         const T R = r[6], a = s * drcp(R);
-        const T ca = cos(a), sa = sin(a);
+        T ca, sa;
+        if constexpr (sizeof(T) == 4) {
+            sincos32(a, sa, ca);
+        } else {
+            ca = cos(a);
+            sa = sin(a);
+        }
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             X[i] = r[i] + R * (ca * r[7 + i] + sa * r[10 + i]);
