@@ -200,12 +200,13 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0, sched=None):
     flops_resume = algorithmic_flops(table, batch.order, code, r["stage"][3], "lm")
     mode = 1 if prec == "fp32" else 0
     if st.get("lm_per_order"):
-        # concurrent per-order launches: the dominant one is the order with
-        # the most algorithmic work, timed by its own events
-        dom = int(np.argmax(per_order_flops))
-        kname = f"k_lm_one<{mode}, {dom + 1}, ..., {form}>"
-        kfile = f"k_lm_one_order{dom + 1}_{prec}" + ("_param" if form else "")
-        flops_dom, ms_dom = per_order_flops[dom], st["lm_per_order"][dom]
+        # concurrent per-order launches: they share the GPU for the whole
+        # pass (which order's kernel ends first depends on how the hardware
+        # queues interleave them), so the unit is the pass, timed from the
+        # fork to the join on the solve's stream
+        kname = f"LM pass: k_lm_one<{mode}, 1..5, ..., {form}> (per-order launches, concurrent)"
+        kfile = f"lm_pass_{prec}" + ("_param" if form else "")
+        flops_dom, ms_dom = flops_pass, st["lm"]
     elif sched == mpt.SCHED_SPLIT and sum(per_order_flops[3:]) == 0:
         # orders 1-3 in one launch; the launches of orders 4 and 5 found
         # nothing to do
