@@ -190,22 +190,26 @@ def test_learned_start_on_curved_paths(ctx):
     the roots the oracle's straight-line run finds are mostly found too."""
     from paper_2301_06399_amd import learned, mpt
     sc, tb = W.training_batch(3, n_rx=512, per_rx=64)
-    learned.train(ctx, sc, tb, steps=400, batch_rows=4096)
     hsc, hb = W.training_batch(3, n_rx=48, per_rx=64, stream="heldout")
-    ctx.upload_scene(hsc)
-    db = mpt.DeviceBatch(hb)
-    out = ctx.solve(db, mpt.default_opts(init=mpt.INIT_LEARNED))
-    acc, idx, k = ctx.accept(db, out)
-    g = out.numpy()
-    gacc = acc.cpu().numpy()
-    orc = O.solve_batch(hsc, hb)
-    oacc = O.accept_batch(hsc, hb, orc["x"], orc["status"])
-    for i in np.where(gacc == 1)[0]:
-        n = hb.order[i]
-        X, c, it, st = O.solve_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], x0=g["x"][:3 * n, i])
-        assert st == O.CONVERGED and np.abs(X - g["x"][:3 * n, i]).max() <= 1e-6
-        assert O.accept_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], X, st)
-    assert ((gacc == 0) & (oacc == 1)).sum() <= 0.1 * max(1, oacc.sum())
+    for form, train_form, ofm, bar in ((mpt.FORM_IMPLICIT, mpt.FORM_IMPLICIT, "implicit", 0.03),
+                                       (mpt.FORM_AUTO, mpt.FORM_PARAMETRIC, "param", 0.01)):
+        learned.train(ctx, sc, tb, steps=1000, batch_rows=4096, form=train_form)
+        ctx.upload_scene(hsc)
+        db = mpt.DeviceBatch(hb)
+        out = ctx.solve(db, mpt.default_opts(init=mpt.INIT_LEARNED, form=form))
+        acc, idx, k = ctx.accept(db, out)
+        g = out.numpy()
+        gacc = acc.cpu().numpy()
+        orc = O.solve_batch(hsc, hb, form=ofm)
+        oacc = O.accept_batch(hsc, hb, orc["x"], orc["status"])
+        for i in np.where(gacc == 1)[0]:
+            n = hb.order[i]
+            X, c, it, st = O.solve_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], x0=g["x"][:3 * n, i], form=ofm)
+            assert st == O.CONVERGED and np.abs(X - g["x"][:3 * n, i]).max() <= 1e-6
+            assert O.accept_one(hsc, hb.rx[hb.rx_index[i]], hb.prim[:n, i], X, st)
+        missed = int(((gacc == 0) & (oacc == 1)).sum())
+        print(ofm, "oracle roots", int(oacc.sum()), "GPU roots", int(gacc.sum()), "missed", missed)
+        assert missed <= bar * max(1, oacc.sum())
 
 
 def test_learned_start_gain_over_straight_line(ctx):

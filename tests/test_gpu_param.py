@@ -58,13 +58,17 @@ def test_param_curved_matches_oracle(ctx, prec):
     orc = O.solve_batch(sc, b, form="param")
     orc_acc = O.accept_batch(sc, b, orc["x"], orc["status"])
     g = gpu_solve(ctx, sc, b, precision=prec, form=1)
+    # observed: FP64 every flag and point; FP32 99.95% of flags (4 of 1380
+    # oracle roots missed) and 99.93% of common roots the same
     agree = np.mean(g["accept"] == orc_acc)
-    assert agree > (0.999 if prec == 0 else 0.98), agree
+    assert agree >= (0.9995 if prec == 0 else 0.995), agree
+    missed = int(((g["accept"] == 0) & (orc_acc == 1)).sum())
+    assert missed <= (0.0005 if prec == 0 else 0.01) * max(1, int(orc_acc.sum()))
     verify_extra_roots(sc, b, g, orc_acc)
     both = (g["accept"] == 1) & (orc_acc == 1)
     same = both & np.array([np.allclose(g["x"][:3 * n, i], orc["x"][:3 * n, i], atol=TOL_M)
                             for i, n in enumerate(b.order)])
-    assert same.sum() >= (0.999 if prec == 0 else 0.98) * both.sum()
+    assert same.sum() >= (0.9995 if prec == 0 else 0.995) * both.sum()
     for i in np.where(both & ~same)[0]:
         n = b.order[i]
         assert O.accept_one(sc, b.rx[b.rx_index[i]], b.prim[:n, i], g["x"][:3 * n, i], O.CONVERGED)

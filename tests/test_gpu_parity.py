@@ -120,15 +120,17 @@ def test_curved_subset_matches_oracle(ctx, prec):
     # same start point: a common root is the same root
     same = both & np.array([np.allclose(g["x"][:3 * n, i], orc["x"][:3 * n, i], atol=TOL_M)
                             for i, n in enumerate(b.order)])
+    # observed: FP64 every flag and point; FP32 99.88% of flags, 19 of 2545
+    # oracle roots missed, every common root the same
     if prec == 0:
-        assert same.sum() >= 0.999 * both.sum()
-        assert np.mean(g["accept"] == orc_acc) > 0.999
+        assert same.sum() >= 0.9995 * both.sum()
+        assert np.mean(g["accept"] == orc_acc) >= 0.9995
     else:
-        assert same.sum() >= 0.98 * both.sum()
-        assert np.mean(g["accept"] == orc_acc) > 0.98
+        assert same.sum() >= 0.995 * both.sum()
+        assert np.mean(g["accept"] == orc_acc) > 0.995
     # oracle-only roots the GPU missed stay rare; GPU-only roots are verified
     missed = int(((g["accept"] == 0) & (orc_acc == 1)).sum())
-    assert missed <= 0.02 * max(1, int(orc_acc.sum()))
+    assert missed <= (0.0005 if prec == 0 else 0.015) * max(1, int(orc_acc.sum()))
     verify_extra_roots(sc, b, g, orc_acc)
     # different common roots are both valid roots (several may exist)
     for i in np.where(both & ~same)[0]:
