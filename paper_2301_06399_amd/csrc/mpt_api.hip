@@ -76,7 +76,7 @@ struct mpt_ctx {
     std::vector<unsigned char> gkey;
 };
 
-// bin_cnt 0..4, (5..9 unused), head 10..19, pol_cnt 20..24, fb_cnt 25..29, curved rows 30, then
+// bin_cnt 0..4, curved-row cursors 5..9, head 10..19, pol_cnt 20..24, fb_cnt 25..29, curved rows 30, then
 // 3 x 1364 key counters, then spill_cnt 0..4 and spill_head 5..9
 static const int kKeyCounters = 3 * 1364;
 static const int kSpillCounters = 32 + kKeyCounters;
@@ -668,12 +668,13 @@ static mpt_status enqueue_solve(mpt_ctx *c, const mpt_batch_desc *b, const mpt_s
     // paraboloids and circles in the scene
     const bool net = learned && n > 0 && (opts->init == MPT_INIT_LEARNED_ALL || c->s.n_pl_ln < c->s.n_all);
     // with MPT_INIT_LEARNED the binning lists the paths with a curved object
-    // (in the polish list, free until the FP32 pass)
+    // (in the polish list, free until the FP32 pass), grouped by order:
+    // per-order cursors in counters 5..9, the length in counter 30
     int *rows = (net && opts->init == MPT_INIT_LEARNED) ? (int *)kp.pol_list : nullptr, *rows_cnt = ctr + 30;
     if (timed) hipEventRecord(c->ev[0], s);
     launch_zero(ctr, kCounters, s);
     launch_bin(bd, kp.out, c->s, ctr + 0, ctr + 32, (int *)kp.perm, (int *)kp.slot_rx, (int *)kp.slot_prim, rows,
-               rows_cnt, s);
+               ctr + 5, s);
     if (timed) hipEventRecord(c->ev[1], s);
     if (net) {
         if (opts->init == MPT_INIT_LEARNED) {

@@ -86,10 +86,11 @@ void launch_pack(const double *raw, const double *refr, const SceneDev &s, int n
                  hipStream_t st);
 void launch_zero(int *p, int n, hipStream_t st);
 int bin_key_count();
-// rows / rows_cnt (or null): the list of the solves with a paraboloid or a
-// circle, appended in no particular order
+// rows (or null): the list of the solves with a paraboloid or a circle,
+// grouped by order; curved: [5] per-order cursors, and curved[25] receives
+// the list's length
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
-                int *slot_rx, int *slot_prim, int *rows, int *rows_cnt, hipStream_t st);
+                int *slot_rx, int *slot_prim, int *rows, int *curved, hipStream_t st);
 const void *lm_kernel(int mode, int order, bool lds, int form, bool refr);
 void launch_lm(int mode, int order, bool lds, int form, bool refr, size_t lds_bytes, const KParams &kp, int grid,
                int block, hipStream_t st);

@@ -156,8 +156,12 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out,
 
 // One block: exclusive scan of the key counts -> key offsets; per-order
 // totals -> bin counts (the bins of the LM kernels are the orders).
+// curved (or null): the start of each order's part of the list of the
+// solves with a curved object ([5], then used as cursors by the scatter),
+// and curved[25] receives the list's length (the counter slots of the
+// solve's workspace are laid out so).
 __global__ void __launch_bounds__(1024) k_bin_offsets(const int *__restrict__ key_cnt, int *__restrict__ key_off,
-                                                       int *__restrict__ bin_cnt)
+                                                       int *__restrict__ bin_cnt, int *__restrict__ curved)
 {
     __shared__ int part[1024];
     __shared__ int offs[kNumKeys + 1];
@@ -189,9 +193,24 @@ __global__ void __launch_bounds__(1024) k_bin_offsets(const int *__restrict__ ke
     if (t == 1023) offs[kNumKeys] = part[1023];
     __syncthreads();
     // per-order totals: the keys of one order are contiguous
+    __shared__ int ccnt[kMaxN];
     if (t < kMaxN) {
         const int kb = kKeyBase[t + 1], ke = (t + 1 < kMaxN) ? kKeyBase[t + 2] : kNumKeys;
         bin_cnt[t] = offs[ke] - offs[kb];
+        // the solves with a curved object: a type digit of 2 or 3 in the key
+        int cc = 0;
+        for (int k = kb; k < ke; k++)
+            if (((k - kb) & 0x2AA) != 0) cc += offs[k + 1] - offs[k];
+        ccnt[t] = cc;
+    }
+    __syncthreads();
+    if (curved && t == 0) {
+        int run = 0;
+        for (int o = 0; o < kMaxN; o++) {
+            curved[o] = run;
+            run += ccnt[o];
+        }
+        curved[25] = run;
     }
 }
 
@@ -206,22 +225,22 @@ __device__ inline int bin_offset(const int *cnt, int k)  // k = order 1..5
 // to that slot: the solver reads a wave's paths from consecutive slots
 // (coalesced) instead of gathering them by solve id.  With `rows`, the
 // solves whose list holds a paraboloid or a circle (a type digit of 2 or 3
-// in the key) are also listed there, one atomic per block (the paths the
-// learned start serves; their order in the list does not matter).
+// in the key) are also listed there, grouped by order (`curved`: each
+// order's cursor, one atomic per block and order), so that the waves of the
+// learned start's kernels hold one order each.
 __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all, int n_pl, int n_pl_ln, int n_pl_ln_q,
                                                             const int *__restrict__ key_off,
                                                             int *__restrict__ key_cursor, int *__restrict__ perm,
                                                             int *__restrict__ slot_rx, int *__restrict__ slot_prim,
-                                                            int *__restrict__ rows, int *__restrict__ rows_cnt)
+                                                            int *__restrict__ rows, int *__restrict__ curved)
 {
     __shared__ int loc[kNumKeys];
     __shared__ int gbase[kNumKeys];
-    __shared__ int ccount, cbase;
+    __shared__ int ccount[kMaxN], cbase[kMaxN];
     for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock) loc[k] = 0;
-    if (threadIdx.x == 0) ccount = 0;
+    if (threadIdx.x < kMaxN) ccount[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
-    const int lane = __lane_id();
     int key[kBinItems], rank[kBinItems], ords[kBinItems], crank[kBinItems];
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
@@ -232,16 +251,13 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
         rank[j] = (key[j] >= 0) ? atomicAdd(&loc[key[j]], 1) : 0;
         // base-4 type digits: 2 (quadric) and 3 (circle) have bit 1 set
         const bool cur = rows && key[j] >= 0 && ((key[j] - kKeyBase[ord > 0 ? ord : 1]) & 0x2AA) != 0;
-        const uint64_t m = __ballot(cur);
-        int wb = 0;
-        if (lane == 0 && m) wb = atomicAdd(&ccount, (int)__popcll(m));
-        wb = __shfl(wb, 0);
-        crank[j] = cur ? wb + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+        crank[j] = cur ? atomicAdd(&ccount[ord - 1], 1) : -1;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock)
         gbase[k] = loc[k] ? key_off[k] + atomicAdd(&key_cursor[k], loc[k]) : 0;
-    if (threadIdx.x == 0) cbase = (rows && ccount) ? atomicAdd(rows_cnt, ccount) : 0;
+    if (rows && threadIdx.x < kMaxN)
+        cbase[threadIdx.x] = ccount[threadIdx.x] ? atomicAdd(&curved[threadIdx.x], ccount[threadIdx.x]) : 0;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
@@ -253,7 +269,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
             for (int k = 0; k < kMaxN; k++)
                 if (k < ords[j]) slot_prim[(size_t)k * b.n + slot] = b.prim[(size_t)k * b.n + i];
         }
-        if (crank[j] >= 0) rows[cbase + crank[j]] = (int)i;
+        if (crank[j] >= 0) rows[cbase[ords[j] - 1] + crank[j]] = (int)i;
     }
 }
 
@@ -1542,16 +1558,16 @@ int bin_key_count() { return kNumKeys; }
 
 // keys: [3][kNumKeys] ints (counts, offsets, cursors), zeroed by the caller
 void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bin_cnt, int *keys, int *perm,
-                int *slot_rx, int *slot_prim, int *rows, int *rows_cnt, hipStream_t st)
+                int *slot_rx, int *slot_prim, int *rows, int *curved, hipStream_t st)
 {
     if (b.n == 0) return;
     const unsigned g = (unsigned)((b.n + kBinBlock * kBinItems - 1) / (kBinBlock * kBinItems));
     int *kcnt = keys, *koff = keys + kNumKeys, *kcur = keys + 2 * kNumKeys;
     hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kBinBlock), 0, st, b, out, s.n_all, s.n_pl, s.n_pl_ln, s.n_pl_ln_q,
                        kcnt);
-    hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, kcnt, koff, bin_cnt);
+    hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, kcnt, koff, bin_cnt, rows ? curved : nullptr);
     hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), 0, st, b, s.n_all, s.n_pl, s.n_pl_ln, s.n_pl_ln_q,
-                       koff, kcur, perm, slot_rx, slot_prim, rows, rows_cnt);
+                       koff, kcur, perm, slot_rx, slot_prim, rows, curved);
 }
 
 template <int MODE, bool LDS, int FORM>
