@@ -477,9 +477,11 @@ __global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restr
 }
 
 // ------------------------------------------------------------------ fused inference
-// One block = 128 paths and 8 waves: features -> three hidden layers ->
+// One block = 64 paths and 4 waves: features -> three hidden layers ->
 // output layer -> world points, activations in LDS (two buffers of
-// 128 x 264 BF16).  Every layer is computed transposed, H^T = W X^T: the
+// 64 x 264 BF16, 76 KB with the GELU table), so two blocks share a CU and
+// one block's feature gathers overlap the other's matrix work (128 paths
+// and 8 waves in one block per CU took 7% longer).  Every layer is computed transposed, H^T = W X^T: the
 // weights are the matrix cores' A operand (rows = output units; each lane
 // loads 8 consecutive BF16 of one row from L2) and the activations the B
 // operand (8 consecutive BF16 of one path from LDS), so the accumulator
@@ -494,7 +496,7 @@ __global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restr
 // below 1e-5, under a tenth of a BF16 step; clamped ends give Phi = 0 and
 // 1 to FP32 precision).  The table entries are Phi = erfc(-z/sqrt 2)/2 in
 // FP32.
-constexpr int IR = 128;                 // paths per block
+constexpr int IR = 64;                  // paths per block
 constexpr int ILD = HID + 8;            // LDS row stride in BF16 (132 dwords)
 constexpr int TABN = 1024;
 constexpr size_t OW1_ = 0, OB1_ = OW1_ + (size_t)HID * F_IN, OW2_ = OB1_ + HID, OB2_ = OW2_ + (size_t)HID * HID,
@@ -571,7 +573,7 @@ __device__ __forceinline__ void infer_layer(const bf16 *in, bf16 *out, const bf1
 }
 
 // rows (may be null): solve ids to predict, *count of them; else all b.n
-__global__ void __launch_bounds__(512, 1) k_mlp_fused(SceneDev s, BatchDev b, const int *__restrict__ rows,
+__global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, const int *__restrict__ rows,
                                                        const int *__restrict__ count, const bf16 *__restrict__ wb,
                                                        const float *__restrict__ w, double *__restrict__ x)
 {
@@ -625,8 +627,8 @@ __global__ void __launch_bounds__(512, 1) k_mlp_fused(SceneDev s, BatchDev b, co
     infer_layer<HID>(bufA, bufB, wb + OW3_, w + OB3_, tab, wave, lane);
     __syncthreads();
     // output layer, transposed as well: units 0..15 (lanes 16..31 of the A
-    // operand carry zero rows), waves 0..3 take 32 paths each
-    if (wave < 4) {
+    // operand carry zero rows), waves 0 and 1 take 32 paths each
+    if (wave < IR / 32) {
         float16_t acc;
 #pragma unroll
         for (int v = 0; v < 16; v++) acc[v] = 0.0f;
@@ -847,12 +849,12 @@ mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, do
     if (b.n == 0) return MPT_OK;
     static_assert(OW4_ == OW4 && OB4_ == OB4, "parameter layout");
     hipFuncSetAttribute((const void *)k_mlp_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)INFER_LDS);
-    // one resident block per CU (the LDS holds one), each walking tiles
+    // two resident blocks per CU (the LDS holds two), each walking tiles
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t tiles = (b.n + IR - 1) / IR;
-    const unsigned g = (unsigned)(tiles < cus ? tiles : cus);
-    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(512), INFER_LDS, st, s, b, rows, count, m->wb, m->w, x_out);
+    const unsigned g = (unsigned)(tiles < 2 * cus ? tiles : 2 * cus);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(256), INFER_LDS, st, s, b, rows, count, m->wb, m->w, x_out);
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
 }
 
