@@ -197,14 +197,21 @@ __global__ void __launch_bounds__(1024) k_bin_offsets(const int *__restrict__ ke
     if (t < kMaxN) {
         const int kb = kKeyBase[t + 1], ke = (t + 1 < kMaxN) ? kKeyBase[t + 2] : kNumKeys;
         bin_cnt[t] = offs[ke] - offs[kb];
-        // the solves with a curved object: a type digit of 2 or 3 in the key
-        int cc = 0;
-        for (int k = kb; k < ke; k++)
-            if (((k - kb) & 0x2AA) != 0) cc += offs[k + 1] - offs[k];
-        ccnt[t] = cc;
+        ccnt[t] = 0;
+    }
+    if (!curved) return;
+    __syncthreads();
+    // the solves with a curved object (a type digit of 2 or 3 in the key),
+    // per order: each thread adds its own keys' counts
+#pragma unroll
+    for (int q = 0; q < per; q++) {
+        const int k = lo + q;
+        int o = 1;
+        while (o < kMaxN && k >= kKeyBase[o + 1]) o++;
+        if (k < hi && c[q] && ((k - kKeyBase[o]) & 0x2AA) != 0) atomicAdd(&ccnt[o - 1], c[q]);
     }
     __syncthreads();
-    if (curved && t == 0) {
+    if (t == 0) {
         int run = 0;
         for (int o = 0; o < kMaxN; o++) {
             curved[o] = run;
