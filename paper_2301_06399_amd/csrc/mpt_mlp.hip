@@ -30,6 +30,34 @@ typedef uint16_t bf16;
 __device__ __forceinline__ bf16 f2bf(float f) { return __builtin_bit_cast(bf16, (__bf16)f); }
 __device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Inference copy of the three hidden-layer weight matrices in the order the
+// fused kernel's waves read them as matrix-core A fragments: layer l (K
+// inputs, S = K / 16 steps of 16) is a run of [4 unit blocks of 64][S steps]
+// [2 halves of 32 units][64 lanes] fragments of 8 BF16, lane j holding unit
+// 32 half + (j % 32) of its block, inputs 16 step + 8 (j / 32) .. +8.  One
+// wave's fragment is 1 KB contiguous, so each load instruction reads whole
+// cache lines (the [out][in] matrix gives each lane its own row).  Written
+// wherever the BF16 weights are, from the same values.
+constexpr size_t NFRAG = (size_t)HID * F_IN + 2 * (size_t)HID * HID;
+__host__ __device__ constexpr long long frag_of(size_t i)
+{
+    // flat parameter layout: W1 [HID][F_IN], b1, W2 [HID][HID], b2, W3, b3, ...
+    constexpr size_t w1 = 0, w2 = w1 + (size_t)HID * F_IN + HID, w3 = w2 + (size_t)HID * HID + HID;
+    size_t off, K, base;
+    if (i < w1 + (size_t)HID * F_IN) {
+        off = i - w1, K = F_IN, base = 0;
+    } else if (i >= w2 && i < w2 + (size_t)HID * HID) {
+        off = i - w2, K = HID, base = (size_t)HID * F_IN;
+    } else if (i >= w3 && i < w3 + (size_t)HID * HID) {
+        off = i - w3, K = HID, base = (size_t)HID * F_IN + (size_t)HID * HID;
+    } else {
+        return -1;
+    }
+    const size_t u = off / K, k = off % K, S = K / 16;
+    const size_t blk = u / 64, half = (u % 64) / 32, lane = u % 32 + 32 * ((k % 16) / 8);
+    return (long long)(base + (((blk * S + k / 16) * 2 + half) * 64 + lane) * 8 + k % 8);
+}
+
 // GELU in its erf form, with erf from Abramowitz & Stegun 7.1.26 (Hastings'
 // rational approximation, |error| <= 1.5e-7, far below BF16 resolution):
 // erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
@@ -434,8 +462,8 @@ __global__ void k_loss_final(const float *__restrict__ part, const int *__restri
 
 // ------------------------------------------------------------------ Adam
 __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, bf16 *__restrict__ wb, int n, float lr, float b1, float b2,
-                       float eps, float c1, float c2)
+                       const float *__restrict__ g, bf16 *__restrict__ wb, bf16 *__restrict__ wf, int n, float lr,
+                       float b1, float b2, float eps, float c1, float c2)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -446,13 +474,22 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     v[i] = vi;
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     w[i] = wi;
-    if (wb) wb[i] = f2bf(wi);
+    if (wb) {
+        const bf16 h = f2bf(wi);
+        wb[i] = h;
+        const long long j = frag_of((size_t)i);
+        if (j >= 0) wf[j] = h;
+    }
 }
 
-__global__ void k_to_bf16(const float *__restrict__ w, bf16 *__restrict__ wb, int n)
+__global__ void k_to_bf16(const float *__restrict__ w, bf16 *__restrict__ wb, bf16 *__restrict__ wf, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) wb[i] = f2bf(w[i]);
+    if (i >= n) return;
+    const bf16 h = f2bf(w[i]);
+    wb[i] = h;
+    const long long j = frag_of((size_t)i);
+    if (j >= 0) wf[j] = h;
 }
 
 // ------------------------------------------------------------------ decode
@@ -481,15 +518,17 @@ __global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restr
 // output layer -> world points, activations in LDS (two buffers of
 // 64 x 264 BF16, 76 KB with the GELU table), so two blocks share a CU and
 // one block's feature gathers overlap the other's matrix work (128 paths
-// and 8 waves in one block per CU took 7% longer).  Every layer is computed transposed, H^T = W X^T: the
-// weights are the matrix cores' A operand (rows = output units; each lane
-// loads 8 consecutive BF16 of one row from L2) and the activations the B
-// operand (8 consecutive BF16 of one path from LDS), so the accumulator
-// holds 4 consecutive output units of one path per register group and the
-// epilogue writes them to LDS with one 8-byte store.  Wave w takes output
-// units 64 (w % 4) .. +64 of paths 64 (w / 4) .. +64: 2 x 2 tiles of
-// v_mfma_f32_32x32x16_bf16.  With two waves per SIMD one wave's matrix
-// work overlaps the other's epilogue.
+// and 8 waves in one block per CU took 7% longer).  Every layer is computed
+// transposed, H^T = W X^T: the weights are the matrix cores' A operand
+// (rows = output units), read from L2 as whole 1 KB fragments of the
+// fragment-ordered copy a few steps ahead of the matrix cores (one row per
+// lane, as the [out][in] matrix gives, made the layers a third slower), and
+// the activations the B operand (8 consecutive BF16 of one path from LDS),
+// so the accumulator holds 4 consecutive output units of one path per
+// register group and the epilogue writes them to LDS with one 8-byte store.
+// Wave w takes output units 64 (w % 4) .. +64 of paths 64 (w / 4) .. +64:
+// 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.  With two waves per SIMD one
+// wave's matrix work overlaps the other's epilogue.
 //
 // GELU(z) = z Phi(z) with Phi read from a table in LDS: 1024 steps of 1/64
 // on [-8, 8] (Phi and its forward difference; linear interpolation, error
@@ -497,6 +536,9 @@ __global__ void k_decode(SceneDev s, BatchDev b, int nrows, const float *__restr
 // 1 to FP32 precision).  The table entries are Phi = erfc(-z/sqrt 2)/2 in
 // FP32.
 constexpr int IR = 64;                  // paths per block
+// weight fragment steps loaded ahead of the matrix cores (1 and 2 ran 7%
+// and 2% longer, 6 no faster, 8 leaves one wave per SIMD)
+constexpr int PF = 4;
 constexpr int ILD = HID + 8;            // LDS row stride in BF16 (132 dwords)
 constexpr int TABN = 1024;
 constexpr size_t OW1_ = 0, OB1_ = OW1_ + (size_t)HID * F_IN, OW2_ = OB1_ + HID, OB2_ = OW2_ + (size_t)HID * HID,
@@ -519,7 +561,7 @@ __device__ __forceinline__ float gelu_tab(const float2 *tab, float z)
 // wave's 64 units and 64 paths; the next 16-deep weight fragments are
 // loaded while the four MFMAs of the current ones run.
 template <int K>
-__device__ __forceinline__ void infer_layer(const bf16 *in, bf16 *out, const bf16 *__restrict__ W,
+__device__ __forceinline__ void infer_layer(const bf16 *in, bf16 *out, const bf16 *__restrict__ Wf,
                                             const float *__restrict__ bias, const float2 *tab, int wave, int lane)
 {
     static_assert(K % 16 == 0, "K must be a multiple of 16");
@@ -532,24 +574,37 @@ __device__ __forceinline__ void infer_layer(const bf16 *in, bf16 *out, const bf1
         for (int nt = 0; nt < 2; nt++)
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[mt][nt][v] = 0.0f;
-    const bf16 *wp0 = W + (size_t)(u0 + li) * K + kq, *wp1 = W + (size_t)(u0 + 32 + li) * K + kq;
+    // this wave's fragments: unit block wave % 4, step t, half h at
+    // wf[(2 t + h) 64]; each is read from L2 once per tile, so the loads run
+    // PF steps ahead of the matrix cores (a ring of PF fragment pairs)
+    constexpr int S = K / 16, D = PF < S ? PF : S;
+    // the block offset is wave-uniform (scalar base), the lane offset the
+    // only per-lane part of the address
+    const int blk = __builtin_amdgcn_readfirstlane(wave & 3);
+    const bf16x8_t *wf = reinterpret_cast<const bf16x8_t *>(Wf) + (size_t)blk * S * 2 * 64 + lane;
     const bf16 *ip0 = in + (r0 + li) * ILD + kq, *ip1 = in + (r0 + 32 + li) * ILD + kq;
-    bf16x8_t a0 = *reinterpret_cast<const bf16x8_t *>(wp0), a1 = *reinterpret_cast<const bf16x8_t *>(wp1);
+    bf16x8_t a0[D], a1[D];
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x8_t n0 = a0, n1 = a1;
-        if (k0 + 16 < K) {
-            n0 = *reinterpret_cast<const bf16x8_t *>(wp0 + k0 + 16);
-            n1 = *reinterpret_cast<const bf16x8_t *>(wp1 + k0 + 16);
+    for (int t = 0; t < D; t++) {
+        a0[t] = wf[t * 128];
+        a1[t] = wf[t * 128 + 64];
+    }
+#pragma unroll
+    for (int t = 0; t < S; t++) {
+        const bf16x8_t x0 = a0[t % D], x1 = a1[t % D];
+        if (t + D < S) {
+            a0[t % D] = wf[(t + D) * 128];
+            a1[t % D] = wf[(t + D) * 128 + 64];
         }
-        const bf16x8_t b0 = *reinterpret_cast<const bf16x8_t *>(ip0 + k0);
-        const bf16x8_t b1 = *reinterpret_cast<const bf16x8_t *>(ip1 + k0);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
-        a0 = n0;
-        a1 = n1;
+        const bf16x8_t b0 = *reinterpret_cast<const bf16x8_t *>(ip0 + 16 * t);
+        const bf16x8_t b1 = *reinterpret_cast<const bf16x8_t *>(ip1 + 16 * t);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, b1, acc[1][1], 0, 0, 0);
+        // keep each step's loads in their step: the scheduler would otherwise
+        // issue all of a layer's fragment loads at once (128 VGPRs)
+        __builtin_amdgcn_sched_barrier(0);
     }
     // D(i, j): unit i = 8 (v / 4) + 4 (lane / 32) + v % 4 of the tile, path j = lane % 32
 #pragma unroll
@@ -575,7 +630,8 @@ __device__ __forceinline__ void infer_layer(const bf16 *in, bf16 *out, const bf1
 // rows (may be null): solve ids to predict, *count of them; else all b.n
 __global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, const int *__restrict__ rows,
                                                        const int *__restrict__ count, const bf16 *__restrict__ wb,
-                                                       const float *__restrict__ w, double *__restrict__ x)
+                                                       const bf16 *wf, const float *__restrict__ w,
+                                                       double *__restrict__ x)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     bf16 *bufA = reinterpret_cast<bf16 *>(smem);
@@ -620,11 +676,11 @@ __global__ void __launch_bounds__(256) k_mlp_fused(SceneDev s, BatchDev b, const
         }
     }
     __syncthreads();
-    infer_layer<F_IN>(bufA, bufB, wb + OW1_, w + OB1_, tab, wave, lane);
+    infer_layer<F_IN>(bufA, bufB, wf, w + OB1_, tab, wave, lane);
     __syncthreads();
-    infer_layer<HID>(bufB, bufA, wb + OW2_, w + OB2_, tab, wave, lane);
+    infer_layer<HID>(bufB, bufA, wf + (size_t)HID * F_IN, w + OB2_, tab, wave, lane);
     __syncthreads();
-    infer_layer<HID>(bufA, bufB, wb + OW3_, w + OB3_, tab, wave, lane);
+    infer_layer<HID>(bufA, bufB, wf + (size_t)HID * F_IN + (size_t)HID * HID, w + OB3_, tab, wave, lane);
     __syncthreads();
     // output layer, transposed as well: units 0..15 (lanes 16..31 of the A
     // operand carry zero rows), waves 0 and 1 take 32 paths each
@@ -668,6 +724,7 @@ constexpr size_t OW1 = 0, OB1 = OW1 + (size_t)HID * F_IN, OW2 = OB1 + HID, OB2 =
 struct MlpState {
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     bf16 *wb = nullptr;  // bf16 copy of the weights (same layout)
+    bf16 *wf = nullptr;  // the hidden layers' bf16 weights in fragment order
     int64_t step = 0;
     uint64_t seed = 0;
     // activation workspace for up to cap rows
@@ -716,6 +773,7 @@ void mlp_free(MlpState *m)
     hipFree(m->v);
     hipFree(m->g);
     hipFree(m->wb);
+    hipFree(m->wf);
     hipFree(m->part);
     delete m;
 }
@@ -784,7 +842,7 @@ static mpt_status alloc_params(MlpState *m)
 {
     bool ok = hipMalloc((void **)&m->w, NPAR * 4) == hipSuccess && hipMalloc((void **)&m->m, NPAR * 4) == hipSuccess &&
               hipMalloc((void **)&m->v, NPAR * 4) == hipSuccess && hipMalloc((void **)&m->g, NPAR * 4) == hipSuccess &&
-              hipMalloc((void **)&m->wb, NPAR * 2) == hipSuccess;
+              hipMalloc((void **)&m->wb, NPAR * 2) == hipSuccess && hipMalloc((void **)&m->wf, NFRAG * 2) == hipSuccess;
     return ok ? MPT_OK : MPT_E_NOMEM;
 }
 
@@ -799,7 +857,7 @@ mpt_status mlp_init(MlpState **pm, uint64_t seed, hipStream_t st)
     if (hipMemcpyAsync(m->w, h.data(), NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess) return MPT_E_DEVICE;
     if (hipMemcpyAsync(m->m, z.data(), NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess) return MPT_E_DEVICE;
     if (hipMemcpyAsync(m->v, z.data(), NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess) return MPT_E_DEVICE;
-    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->wb, (int)NPAR);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->wb, m->wf, (int)NPAR);
     if (hipStreamSynchronize(st) != hipSuccess) return MPT_E_DEVICE;
     m->step = 0;
     m->seed = seed;
@@ -848,13 +906,22 @@ mpt_status mlp_predict_dev(MlpState *m, const SceneDev &s, const BatchDev &b, do
     if (!mlp_ready(m)) return MPT_E_NO_MODEL;
     if (b.n == 0) return MPT_OK;
     static_assert(OW4_ == OW4 && OB4_ == OB4, "parameter layout");
+    static_assert(frag_of(OW1) == 0 && frag_of(OW2) == (long long)HID * F_IN &&
+                      frag_of(OW3) == (long long)(HID * F_IN + HID * HID) && frag_of(OB3 - 1) == (long long)NFRAG - 1,
+                  "fragment layout: first and last weight of each layer");
+    static_assert(frag_of(OB1) < 0 && frag_of(OB2) < 0 && frag_of(OB3) < 0 && frag_of(OW4) < 0,
+                  "fragment layout: biases and the output layer are not in it");
+    static_assert(frag_of(OW1 + 1) == 1 && frag_of(OW1 + 8) == 32 * 8 && frag_of(OW1 + F_IN) == 8 &&
+                      frag_of(OW1 + 32 * F_IN) == 64 * 8 && frag_of(OW1 + 16) == 2 * 64 * 8 &&
+                      frag_of(OW1 + 64 * F_IN) == (F_IN / 16) * 2 * 64 * 8,
+                  "fragment layout: element, lane, half, step and unit-block strides");
     hipFuncSetAttribute((const void *)k_mlp_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)INFER_LDS);
     // two resident blocks per CU (the LDS holds two), each walking tiles
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t tiles = (b.n + IR - 1) / IR;
     const unsigned g = (unsigned)(tiles < 2 * cus ? tiles : 2 * cus);
-    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(256), INFER_LDS, st, s, b, rows, count, m->wb, m->w, x_out);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(g), dim3(256), INFER_LDS, st, s, b, rows, count, m->wb, m->wf, m->w, x_out);
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
 }
 
@@ -1058,7 +1125,7 @@ mpt_status mlp_train_step_dev(MlpState *m, const SceneDev &s, const BatchDev &b,
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.0f - powf(b1, (float)m->step), c2 = 1.0f - powf(b2, (float)m->step);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->m, m->v, m->g, m->wb,
-                       (int)NPAR, lr, b1, b2, 1e-8f, c1, c2);
+                       m->wf, (int)NPAR, lr, b1, b2, 1e-8f, c1, c2);
     return hipGetLastError() == hipSuccess ? MPT_OK : MPT_E_DEVICE;
 }
 
@@ -1168,7 +1235,7 @@ mpt_status mlp_load(MlpState **pm, const void *blob, size_t bytes, hipStream_t s
         hipMemcpyAsync(m->m, d + NPAR * 4, NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(m->v, d + 2 * NPAR * 4, NPAR * 4, hipMemcpyHostToDevice, st) != hipSuccess)
         return MPT_E_DEVICE;
-    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->wb, (int)NPAR);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st, m->w, m->wb, m->wf, (int)NPAR);
     if (hipStreamSynchronize(st) != hipSuccess) return MPT_E_DEVICE;
     m->step = step;
     m->seed = seed;
