@@ -107,19 +107,56 @@ __device__ inline int valid_order(const BatchDev &b, int64_t i, int n_all)
 // the lanes of a wave mostly follow one type path (no divergence between
 // reflection and diffraction code).  Key = kKeyBase[order] + code.
 constexpr int kBinBlock = 256;
-constexpr int kBinItems = 2;  // solves per thread (enough blocks to fill the chip)
+// solves per thread, their loads issued together (stress workload binning:
+// 1.34 ms with two solves per thread each loaded as a chain of dependent
+// loads; 1.11, 0.73 and 0.69 ms with the loads issued together and two,
+// four and eight solves per thread; 0.77-0.80 ms with 16-32 solves per
+// thread in chunks of eight, which halves or quarters the blocks' atomics
+// on the key counters but loads the ids again after the atomics)
+constexpr int kBinItems = 8;
+constexpr int kBinPerBlock = kBinBlock * kBinItems;
 constexpr int kNumKeys = 4 + 16 + 64 + 256 + 1024;
 __device__ __constant__ int kKeyBase[kMaxN + 1] = {0, 0, 4, 20, 84, 340};
 
-__device__ inline int bin_key(const BatchDev &b, int64_t i, int ord, int a, int bb, int c)
+// A solve's order, receiver and ids as the binning reads them: every load
+// is issued before any is used (the id rows beyond the order are the
+// caller's memory as well), so a thread's loads are in flight together
+// instead of one dependent round trip after another.  ord = -1 marks an
+// invalid solve (the same test as valid_order).
+struct SolveIds {
+    int ord, ri, id[kMaxN];
+};
+
+__device__ inline void load_ids(const BatchDev &b, int64_t i, SolveIds &r)
+{
+    r.ord = b.order[i];
+    r.ri = b.rx_index[i];
+#pragma unroll
+    for (int k = 0; k < kMaxN; k++) r.id[k] = b.prim[(size_t)k * b.n + i];
+}
+
+__device__ inline void check_ids(const BatchDev &b, int n_all, SolveIds &r)
+{
+    bool bad = r.ord < 1 || r.ord > kMaxN || r.ri < 0 || r.ri >= b.n_rx;
+    if (!bad) {
+        bad = !finite3(b.rx + 3 * (size_t)r.ri);
+#pragma unroll
+        for (int k = 0; k < kMaxN; k++)
+            if (k < r.ord) bad = bad || r.id[k] < 0 || r.id[k] >= n_all;
+    }
+    if (bad) r.ord = -1;
+}
+
+__device__ inline int bin_key(const SolveIds &r, int a, int bb, int c)
 {
     int code = 0, mul = 1;
+#pragma unroll
     for (int k = 0; k < kMaxN; k++)
-        if (k < ord) {
-            code += prim_type(b.prim[(size_t)k * b.n + i], a, bb, c) * mul;
+        if (k < r.ord) {
+            code += prim_type(r.id[k], a, bb, c) * mul;
             mul *= 4;
         }
-    return kKeyBase[ord] + code;
+    return kKeyBase[r.ord] + code;
 }
 
 __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out, int n_all, int n_pl, int n_pl_ln,
@@ -128,12 +165,23 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out,
     __shared__ int loc[kNumKeys];
     for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock) loc[k] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
+    const int64_t base = (int64_t)blockIdx.x * kBinPerBlock;
+    SolveIds r[kBinItems];
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+        const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
+        if (i < b.n) load_ids(b, i, r[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+        const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
+        if (i < b.n) check_ids(b, n_all, r[j]);
+    }
+#pragma unroll
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
         if (i >= b.n) break;
-        const int ord = valid_order(b, i, n_all);
-        if (ord < 0) {
+        if (r[j].ord < 0) {
             for (int q = 0; q < kRow; q++) out.x[(size_t)i * kRow + q] = 0.0;
             out.cost[i] = __builtin_huge_val();
             out.iters[i] = 0;
@@ -146,7 +194,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(BatchDev b, OutDev out,
             // produces (the solver writes a path's whole point row)
             if (out.stage)
                 for (int q = 1; q < 4; q++) out.stage[(size_t)q * b.n + i] = 0;
-            atomicAdd(&loc[bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q)], 1);
+            atomicAdd(&loc[bin_key(r[j], n_pl, n_pl_ln, n_pl_ln_q)], 1);
         }
     }
     __syncthreads();
@@ -247,14 +295,24 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
     for (int k = threadIdx.x; k < kNumKeys; k += kBinBlock) loc[k] = 0;
     if (threadIdx.x < kMaxN) ccount[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kBinBlock * kBinItems;
-    int key[kBinItems], rank[kBinItems], ords[kBinItems], crank[kBinItems];
+    const int64_t base = (int64_t)blockIdx.x * kBinPerBlock;
+    int key[kBinItems], rank[kBinItems], crank[kBinItems];
+    SolveIds r[kBinItems];
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
         const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
-        const int ord = (i < b.n) ? valid_order(b, i, n_all) : -1;
-        ords[j] = ord;
-        key[j] = (ord > 0) ? bin_key(b, i, ord, n_pl, n_pl_ln, n_pl_ln_q) : -1;
+        r[j].ord = -1;
+        if (i < b.n) load_ids(b, i, r[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+        const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
+        if (i < b.n) check_ids(b, n_all, r[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+        const int ord = r[j].ord;
+        key[j] = (ord > 0) ? bin_key(r[j], n_pl, n_pl_ln, n_pl_ln_q) : -1;
         rank[j] = (key[j] >= 0) ? atomicAdd(&loc[key[j]], 1) : 0;
         // base-4 type digits: 2 (quadric) and 3 (circle) have bit 1 set
         const bool cur = rows && key[j] >= 0 && ((key[j] - kKeyBase[ord > 0 ? ord : 1]) & 0x2AA) != 0;
@@ -272,11 +330,12 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BatchDev b, int n_all
         if (key[j] >= 0) {
             const int slot = gbase[key[j]] + rank[j];
             perm[slot] = (int)i;
-            slot_rx[slot] = b.rx_index[i];
+            slot_rx[slot] = r[j].ri;
+#pragma unroll
             for (int k = 0; k < kMaxN; k++)
-                if (k < ords[j]) slot_prim[(size_t)k * b.n + slot] = b.prim[(size_t)k * b.n + i];
+                if (k < r[j].ord) slot_prim[(size_t)k * b.n + slot] = r[j].id[k];
         }
-        if (crank[j] >= 0) rows[cbase[ords[j] - 1] + crank[j]] = (int)i;
+        if (crank[j] >= 0) rows[cbase[r[j].ord - 1] + crank[j]] = (int)i;
     }
 }
 
@@ -1510,27 +1569,56 @@ __global__ void __launch_bounds__(256) k_accept_count(const uint8_t *__restrict_
 // Exclusive scan of the per-block counts by one block; total -> *count.
 __global__ void __launch_bounds__(1024) k_scan_blocks(int *__restrict__ block_cnt, int nblk, int *__restrict__ count)
 {
-    __shared__ int part[1024];
-    const int t = threadIdx.x;
-    const int per = (nblk + 1023) / 1024;
-    const int lo = t * per, hi = min(lo + per, nblk);
+    // wave w owns a contiguous segment and reads it 64 entries at a time
+    // (coalesced, eight loads in flight per lane); the 16 segment totals
+    // give each wave its starting offset
+    constexpr int kU = 8;
+    __shared__ int wtot[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int seg = ((nblk + 15) / 16 + 64 * kU - 1) / (64 * kU) * (64 * kU);
+    const int lo = min(w * seg, nblk), hi = min(lo + seg, nblk);
     int s = 0;
-    for (int i = lo; i < hi; i++) s += block_cnt[i];
-    part[t] = s;
+    for (int i0 = lo; i0 < hi; i0 += 64 * kU) {
+        int v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int i = i0 + 64 * u + lane;
+            v[u] = (i < hi) ? block_cnt[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; u++) s += v[u];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0) wtot[w] = s;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int v = (t >= d) ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    int run = 0;
+    for (int j = 0; j < w; j++) run += wtot[j];
+    for (int i0 = lo; i0 < hi; i0 += 64 * kU) {
+        int v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int i = i0 + 64 * u + lane;
+            v[u] = (i < hi) ? block_cnt[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            int incl = v[u];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int x = __shfl_up(incl, d);
+                if (lane >= d) incl += x;
+            }
+            const int i = i0 + 64 * u + lane;
+            if (i < hi) block_cnt[i] = run + incl - v[u];
+            run += __shfl(incl, 63);
+        }
     }
-    int run = (t == 0) ? 0 : part[t - 1];
-    for (int i = lo; i < hi; i++) {
-        const int c = block_cnt[i];
-        block_cnt[i] = run;
-        run += c;
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int j = 0; j < 16; j++) tot += wtot[j];
+        *count = tot;
     }
-    if (t == 1023) *count = part[1023];
 }
 
 __global__ void __launch_bounds__(256) k_accept_scatter(const uint8_t *__restrict__ acc, int64_t n,
@@ -1570,7 +1658,7 @@ void launch_bin(const BatchDev &b, const OutDev &out, const SceneDev &s, int *bi
                 int *slot_rx, int *slot_prim, int *rows, int *curved, hipStream_t st)
 {
     if (b.n == 0) return;
-    const unsigned g = (unsigned)((b.n + kBinBlock * kBinItems - 1) / (kBinBlock * kBinItems));
+    const unsigned g = (unsigned)((b.n + kBinPerBlock - 1) / kBinPerBlock);
     int *kcnt = keys, *koff = keys + kNumKeys, *kcur = keys + 2 * kNumKeys;
     hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kBinBlock), 0, st, b, out, s.n_all, s.n_pl, s.n_pl_ln, s.n_pl_ln_q,
                        kcnt);
@@ -1649,47 +1737,67 @@ void launch_learned_choose(const SceneDev &s, const BatchDev &b, const int *rows
 // by order at the bins' offsets.  Each block counts its solves per order in
 // LDS and takes its slots with one global atomic per order, so that the
 // counters see a few hundred atomics rather than one per wave.
-constexpr int kPolListPer = 8;  // solves per thread
-
+// solves per thread: kPolChunks chunks of kPolListPer solves whose loads
+// are issued together; large blocks, so that few blocks take slots with
+// the device-wide atomics on the five per-order counters (one counter is
+// served one atomic at a time: with 8 solves per thread the 8192 blocks'
+// atomics took 0.29 ms on the stress workload)
+constexpr int kPolListPer = 8;
+constexpr int kPolChunks = 4;
 __global__ void __launch_bounds__(256) k_polish_list(KParams kp)
 {
     __shared__ int lcnt[kMaxN], lbase[kMaxN];
-    const int64_t b0 = (int64_t)blockIdx.x * blockDim.x * kPolListPer;
+    const int64_t b0 = (int64_t)blockIdx.x * blockDim.x * kPolListPer * kPolChunks;
     if (threadIdx.x < kMaxN) lcnt[threadIdx.x] = 0;
     __syncthreads();
-    int ord[kPolListPer], slot[kPolListPer];
-    for (int q = 0; q < kPolListPer; q++) {
-        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
-        ord[q] = 0;
-        if (i < kp.b.n) {
-            const int st = kp.out.status[i];
-            if (st == ROUTE_POLISH_FB || st == ROUTE_POLISH_MAXIT || st == ROUTE_POLISH_LOCALMIN) ord[q] = kp.b.order[i];
+    // per solve: its order (0: not listed) | its rank among the block's
+    // solves of that order << 3
+    int os[kPolChunks][kPolListPer];
+    for (int c = 0; c < kPolChunks; c++) {
+        int ord[kPolListPer], st[kPolListPer];
+        // every load of the chunk first (status and order), so that they
+        // are in flight together
+#pragma unroll
+        for (int q = 0; q < kPolListPer; q++) {
+            const int64_t i = b0 + (int64_t)(c * kPolListPer + q) * blockDim.x + threadIdx.x;
+            st[q] = -1;
+            ord[q] = 0;
+            if (i < kp.b.n) {
+                st[q] = kp.out.status[i];
+                ord[q] = kp.b.order[i];
+            }
         }
-        slot[q] = 0;
-        for (int o = 1; o <= kMaxN; o++) {
-            const uint64_t m = __ballot(ord[q] == o);
-            if (!m) continue;
-            const int leader = (int)__builtin_ctzll(m);
-            int base = 0;
-            if (__lane_id() == leader) base = atomicAdd(&lcnt[o - 1], (int)__popcll(m));
-            base = __shfl(base, leader);
-            if (ord[q] == o) slot[q] = base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull));
+        for (int q = 0; q < kPolListPer; q++) {
+            if (!(st[q] == ROUTE_POLISH_FB || st[q] == ROUTE_POLISH_MAXIT || st[q] == ROUTE_POLISH_LOCALMIN)) ord[q] = 0;
+            int slot = 0;
+            for (int o = 1; o <= kMaxN; o++) {
+                const uint64_t m = __ballot(ord[q] == o);
+                if (!m) continue;
+                const int leader = (int)__builtin_ctzll(m);
+                int base = 0;
+                if (__lane_id() == leader) base = atomicAdd(&lcnt[o - 1], (int)__popcll(m));
+                base = __shfl(base, leader);
+                if (ord[q] == o) slot = base + (int)__popcll(m & ((1ull << __lane_id()) - 1ull));
+            }
+            os[c][q] = ord[q] | (slot << 3);
         }
     }
     __syncthreads();
     if (threadIdx.x < kMaxN)
         lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&kp.pol_cnt[threadIdx.x], lcnt[threadIdx.x]) : 0;
     __syncthreads();
-    for (int q = 0; q < kPolListPer; q++) {
-        const int64_t i = b0 + (int64_t)q * blockDim.x + threadIdx.x;
-        if (ord[q] > 0) kp.pol_list[bin_offset(kp.bin_cnt, ord[q]) + lbase[ord[q] - 1] + slot[q]] = (int)i;
-    }
+    for (int c = 0; c < kPolChunks; c++)
+        for (int q = 0; q < kPolListPer; q++) {
+            const int64_t i = b0 + (int64_t)(c * kPolListPer + q) * blockDim.x + threadIdx.x;
+            const int o = os[c][q] & 7;
+            if (o > 0) kp.pol_list[bin_offset(kp.bin_cnt, o) + lbase[o - 1] + (os[c][q] >> 3)] = (int)i;
+        }
 }
 
 void launch_polish_list(const KParams &kp, hipStream_t st)
 {
     if (kp.b.n == 0) return;
-    const int64_t per_block = 256 * kPolListPer;
+    const int64_t per_block = 256 * kPolListPer * kPolChunks;
     hipLaunchKernelGGL(k_polish_list, dim3((unsigned)((kp.b.n + per_block - 1) / per_block)), dim3(256), 0, st, kp);
 }
 
