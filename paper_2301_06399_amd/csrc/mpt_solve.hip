@@ -1476,9 +1476,11 @@ __device__ bool accept_path(const SceneDev &s, const double *rx, const int *id, 
 // Pass 1: clear the flags and list the converged solves, the only ones the
 // test can accept (a few percent of a batch), so that the FP64 test runs on
 // full waves instead of one or two lanes of each.  A block covers
-// 256 x kAccItems solves and takes its part of the list with one atomic (one
-// per wave contended on the counter and cost more than the test itself).
+// 256 x kAccItems x kAccChunks solves and takes its part of the list with one
+// device-wide atomic (one per wave contended on the counter and cost more
+// than the test itself); each chunk's loads are issued together.
 constexpr int kAccItems = 16;
+constexpr int kAccChunks = 4;
 __global__ void __launch_bounds__(256) k_accept_list(BatchDev b, const uint8_t *__restrict__ status,
                                                       uint8_t *__restrict__ acc, int *__restrict__ list,
                                                       int *__restrict__ cnt)
@@ -1486,30 +1488,40 @@ __global__ void __launch_bounds__(256) k_accept_list(BatchDev b, const uint8_t *
     __shared__ int bcount, bbase;
     if (threadIdx.x == 0) bcount = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * 256 * kAccItems;
+    const int64_t base = (int64_t)blockIdx.x * 256 * kAccItems * kAccChunks;
     const int lane = __lane_id();
-    int r[kAccItems];
+    int r[kAccChunks][kAccItems];
+    for (int c = 0; c < kAccChunks; c++) {
+        int ord[kAccItems], st[kAccItems];
 #pragma unroll
-    for (int j = 0; j < kAccItems; j++) {
-        const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
-        bool c = false;
-        if (i < b.n) {
-            const int ord = b.order[i];
-            c = ord >= 1 && ord <= kMaxN && (status[i] & 0x7f) == ST_CONV;
-            acc[i] = 0;
+        for (int j = 0; j < kAccItems; j++) {
+            const int64_t i = base + (int64_t)(c * kAccItems + j) * 256 + threadIdx.x;
+            ord[j] = 0;
+            st[j] = 0;
+            if (i < b.n) {
+                ord[j] = b.order[i];
+                st[j] = status[i];
+            }
         }
-        const uint64_t m = __ballot(c);
-        int wb = 0;
-        if (lane == 0 && m) wb = atomicAdd(&bcount, (int)__popcll(m));
-        wb = __shfl(wb, 0);
-        r[j] = c ? wb + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+#pragma unroll
+        for (int j = 0; j < kAccItems; j++) {
+            const int64_t i = base + (int64_t)(c * kAccItems + j) * 256 + threadIdx.x;
+            if (i < b.n) acc[i] = 0;
+            const bool v = ord[j] >= 1 && ord[j] <= kMaxN && (st[j] & 0x7f) == ST_CONV;
+            const uint64_t m = __ballot(v);
+            int wb = 0;
+            if (lane == 0 && m) wb = atomicAdd(&bcount, (int)__popcll(m));
+            wb = __shfl(wb, 0);
+            r[c][j] = v ? wb + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) bbase = bcount ? atomicAdd(cnt, bcount) : 0;
     __syncthreads();
+    for (int c = 0; c < kAccChunks; c++)
 #pragma unroll
-    for (int j = 0; j < kAccItems; j++)
-        if (r[j] >= 0) list[bbase + r[j]] = (int)(base + (int64_t)j * 256 + threadIdx.x);
+        for (int j = 0; j < kAccItems; j++)
+            if (r[c][j] >= 0) list[bbase + r[c][j]] = (int)(base + (int64_t)(c * kAccItems + j) * 256 + threadIdx.x);
 }
 
 // Pass 2: the test on the listed solves (grid-stride over the list).
@@ -1820,8 +1832,9 @@ void launch_accept(const SceneDev &s, const BatchDev &b, const OutDevC &in, doub
     }
     int *lcnt = block_cnt + nblk;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, lcnt, 1);
-    hipLaunchKernelGGL(k_accept_list, dim3((unsigned)((b.n + 256 * kAccItems - 1) / (256 * kAccItems))), dim3(256), 0,
-                       st, b, in.status, acc, idx, lcnt);
+    const int64_t per_list_block = 256 * kAccItems * kAccChunks;
+    hipLaunchKernelGGL(k_accept_list, dim3((unsigned)((b.n + per_list_block - 1) / per_list_block)), dim3(256), 0, st,
+                       b, in.status, acc, idx, lcnt);
     const dim3 g(std::min(nblk, 2048));
     if (refr) hipLaunchKernelGGL(k_accept_eval<true>, g, dim3(256), 0, st, s, b, in, tau_res, min_seg, acc, idx, lcnt);
     else hipLaunchKernelGGL(k_accept_eval<false>, g, dim3(256), 0, st, s, b, in, tau_res, min_seg, acc, idx, lcnt);
