@@ -81,12 +81,22 @@ def type_codes(scene, batch):
     return code
 
 
-def algorithmic_flops(table, order, code, iters, kind):
+def algorithmic_flops(table, order, code, iters, kind, kept=False):
+    """FLOPs of `iters` iterations of each path at its order and types.
+    kept: the FP32 solver of orders 1-3 keeps the normal equations after a
+    rejected step and skips their assembly in the next iteration; the
+    number of such iterations is not recorded, so they are bounded from
+    below: every iteration after a path's first is charged without its
+    assembly (a lower bound of the work done)."""
     tot = 0
     for n in range(1, 6):
         m = order == n
         if m.any():
-            tot += int((table[n][kind][code[m]] * iters[m].astype(np.int64)).sum())
+            it = iters[m].astype(np.int64)
+            f = table[n][kind][code[m]] * it
+            if kept and n <= 3 and kind == "lm":
+                f = f - table[n]["assembly"][code[m]] * np.maximum(it - 1, 0)
+            tot += int(f.sum())
     return tot
 
 
@@ -192,12 +202,14 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0, sched=None):
     table = mpt.flops_table(form)
     code = type_codes(scene, batch)
     it1 = r["stage"][0] - r["stage"][3]   # iterations before a straggler was parked
-    per_order_flops = []
+    kept = prec == "fp32"
+    per_order_flops, per_order_upper = [], []
     for nn in range(1, 6):
         m = batch.order == nn
-        per_order_flops.append(algorithmic_flops(table, batch.order[m], code[m], it1[m], "lm"))
+        per_order_flops.append(algorithmic_flops(table, batch.order[m], code[m], it1[m], "lm", kept))
+        per_order_upper.append(algorithmic_flops(table, batch.order[m], code[m], it1[m], "lm"))
     flops_pass = sum(per_order_flops)
-    flops_resume = algorithmic_flops(table, batch.order, code, r["stage"][3], "lm")
+    flops_resume = algorithmic_flops(table, batch.order, code, r["stage"][3], "lm", kept)
     mode = 1 if prec == "fp32" else 0
     if st.get("lm_per_order"):
         # concurrent per-order launches: they share the GPU for the whole
@@ -229,9 +241,13 @@ def lm_roofline(scene, batch, r, st, prec, cfg, mpt, form=0, sched=None):
         if kv.get("source_hash") == kernel_source_hash():
             traffic = float(kv["hbm_bytes_per_launch"])
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK[prec], "traffic": traffic, "kernel": kname,
+            "frac": achieved / PEAK[prec],
+            # every iteration charged with its assembly: the upper bound of the work
+            "frac_upper": sum(per_order_upper) / (ms_dom * 1e-3) / PEAK[prec],
+            "traffic": traffic, "kernel": kname,
             "flops_per_launch": flops_dom, "launch_ms": ms_dom,
             "lm_pass": {"flops": flops_pass, "ms": st["lm"], "tflops": flops_pass / (st["lm"] * 1e-3) / 1e12,
+                        "flops_upper": sum(per_order_upper),
                         "flops_per_order": per_order_flops, "ms_per_order": st.get("lm_per_order"),
                         "straggler_flops": flops_resume, "straggler_ms": st["resume"]}}
 

@@ -496,6 +496,16 @@ mpt_status mpt_mlp_load(mpt_ctx *ctx, const void *blob, size_t bytes);
  * form. */
 mpt_status mpt_flops_per_iter(int order, const int32_t *types, int32_t form, int64_t out[4]);
 
+/* The part of out[0] of mpt_flops_per_iter that builds the residual, the
+ * Jacobian and the banded normal equations and gradient (Sec. III-B, Eq. 12
+ * with the rescaled rows; Eq. 15 with form = MPT_FORM_PARAMETRIC), in *out.
+ * After a rejected step the point has not moved, so the FP32 solver of
+ * orders 1-3 keeps these from the previous iteration and runs only the rest
+ * of out[0] (damping, banded Cholesky, solve, trial cost); counts of the
+ * algorithmic work charge such iterations out[0] minus this figure.
+ * Host only.  MPT_E_INVALID_ARG as mpt_flops_per_iter. */
+mpt_status mpt_flops_assembly(int order, const int32_t *types, int32_t form, int64_t *out);
+
 /* Stage timing of mpt_solve_batch, on (1) by default: each solve then
  * records 7 HIP events at its stage boundaries (a few microseconds each on
  * the stream) for mpt_last_timings and mpt_last_lm_timings.  Off (0): no

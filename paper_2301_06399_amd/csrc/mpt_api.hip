@@ -927,7 +927,7 @@ mpt_status mpt_autotune(mpt_ctx *c, const mpt_batch_desc *b, const mpt_solve_opt
 
 // ---------------------------------------------------------------- FLOP count
 template <int N>
-static void count_one(const int32_t *types, int64_t out[4], bool param)
+static void count_one(const int32_t *types, int64_t out[4], bool param, int64_t *asm_flops = nullptr)
 {
     // a small synthetic scene: one record per interaction with generic
     // (non-zero, non-special) values, so no operation is skipped by accident;
@@ -967,6 +967,7 @@ static void count_one(const int32_t *types, int64_t out[4], bool param)
     // one LM iteration
     tally() = FlopTally();
     assemble<Cnt, N, false>(sc, p, X, A, g, C, rinf);
+    if (asm_flops && !param) *asm_flops = tally().flops();
     Cnt lam(rnd()), dmax(rnd());
     for (int i = 0; i < M; i++) A[Band<N>::at(i, i)] += lam * fmax(A[Band<N>::at(i, i)], Cnt(1e-12) * dmax);
     chol_band<Cnt, N>(A);
@@ -997,6 +998,7 @@ static void count_one(const int32_t *types, int64_t out[4], bool param)
     }
     tally() = FlopTally();
     assemble_param<Cnt, N, false>(sc, p, U, Ap, gp, C, rinf);
+    if (asm_flops) *asm_flops = tally().flops();
     for (int i = 0; i < 2 * N; i++) {
         const bool real = (i % 2 == 0) || types[i / 2] == MPT_PLANE || types[i / 2] == MPT_QUADRIC;
         Cnt &d = Ap[Band<N, 2>::at(i, i)];
@@ -1026,6 +1028,24 @@ extern "C" mpt_status mpt_flops_per_iter(int order, const int32_t *types, int32_
     case 3: count_one<3>(types, out, param); break;
     case 4: count_one<4>(types, out, param); break;
     default: count_one<5>(types, out, param); break;
+    }
+    return MPT_OK;
+}
+
+extern "C" mpt_status mpt_flops_assembly(int order, const int32_t *types, int32_t form, int64_t *out)
+{
+    if (!types || !out || order < 1 || order > MPT_MAX_ORDER) return MPT_E_INVALID_ARG;
+    if (form != MPT_FORM_IMPLICIT && form != MPT_FORM_PARAMETRIC) return MPT_E_INVALID_ARG;
+    for (int k = 0; k < order; k++)
+        if (types[k] < MPT_PLANE || types[k] > MPT_CIRCLE) return MPT_E_INVALID_ARG;
+    const bool param = form == MPT_FORM_PARAMETRIC;
+    int64_t all[4];
+    switch (order) {
+    case 1: count_one<1>(types, all, param, out); break;
+    case 2: count_one<2>(types, all, param, out); break;
+    case 3: count_one<3>(types, all, param, out); break;
+    case 4: count_one<4>(types, all, param, out); break;
+    default: count_one<5>(types, all, param, out); break;
     }
     return MPT_OK;
 }

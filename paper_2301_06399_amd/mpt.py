@@ -66,7 +66,7 @@ class SolveOut(C.Structure):
 EXPORTS = ["mpt_create", "mpt_destroy", "mpt_last_error", "mpt_set_stream", "mpt_synchronize",
            "mpt_scene_upload", "mpt_default_opts", "mpt_solve_batch", "mpt_accept", "mpt_mlp_init",
            "mpt_mlp_train_step", "mpt_mlp_predict", "mpt_mlp_save", "mpt_mlp_load", "mpt_last_timings",
-           "mpt_flops_per_iter", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
+           "mpt_flops_per_iter", "mpt_flops_assembly", "mpt_autotune", "mpt_mlp_grad", "mpt_mlp_features", "mpt_mlp_param_count",
            "mpt_gemm_bf16_check", "mpt_last_lm_timings", "mpt_mlp_predict_unfused", "mpt_visible",
            "mpt_visibility", "mpt_visibility_rx", "mpt_candidates", "mpt_last_launch", "mpt_set_timing",
            "mpt_solve_batch_noalloc", "mpt_mlp_grad_fp32"]
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     L.mpt_mlp_load.argtypes = [vp, vp, C.c_size_t]
     L.mpt_last_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_flops_per_iter.argtypes = [C.c_int, vp, C.c_int32, vp]
+    L.mpt_flops_assembly.argtypes = [C.c_int, vp, C.c_int32, vp]
     L.mpt_last_lm_timings.argtypes = [vp, C.POINTER(C.c_float)]
     L.mpt_last_launch.argtypes = [vp, C.POINTER(C.c_int32)]
     L.mpt_set_timing.argtypes = [vp, C.c_int32]
@@ -222,7 +223,12 @@ def flops_per_iter(types, form=FORM_IMPLICIT) -> dict:
     rc = L.mpt_flops_per_iter(len(t), t.ctypes.data, int(form), out.ctypes.data)
     if rc != MPT_OK:
         raise MptError(f"mpt_flops_per_iter: {STATUS_NAMES.get(rc, rc)}")
-    return {"lm": int(out[0]), "polish": int(out[1]), "residual": int(out[2]), "sqrt_div": int(out[3])}
+    a = np.zeros(1, np.int64)
+    rc = L.mpt_flops_assembly(len(t), t.ctypes.data, int(form), a.ctypes.data)
+    if rc != MPT_OK:
+        raise MptError(f"mpt_flops_assembly: {STATUS_NAMES.get(rc, rc)}")
+    return {"lm": int(out[0]), "polish": int(out[1]), "residual": int(out[2]), "sqrt_div": int(out[3]),
+            "assembly": int(a[0])}
 
 
 def flops_table(form=FORM_IMPLICIT) -> dict:
@@ -233,11 +239,12 @@ def flops_table(form=FORM_IMPLICIT) -> dict:
         lm = np.zeros(4 ** n, np.int64)
         po = np.zeros(4 ** n, np.int64)
         re_ = np.zeros(4 ** n, np.int64)
+        asm = np.zeros(4 ** n, np.int64)
         for code in range(4 ** n):
             types = [(code // 4 ** k) % 4 for k in range(n)]
             f = flops_per_iter(types, form)
-            lm[code], po[code], re_[code] = f["lm"], f["polish"], f["residual"]
-        tab[n] = {"lm": lm, "polish": po, "residual": re_}
+            lm[code], po[code], re_[code], asm[code] = f["lm"], f["polish"], f["residual"], f["assembly"]
+        tab[n] = {"lm": lm, "polish": po, "residual": re_, "assembly": asm}
     return tab
 
 

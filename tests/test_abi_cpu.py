@@ -105,3 +105,16 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         for fname, _ in py._fields_:
             f = getattr(py, fname)
             assert got[(cname, fname)] == (f.offset, f.size), (cname, fname)
+
+
+def test_assembly_flops_are_a_proper_part_of_an_iteration():
+    """The assembly count is positive and below a whole LM iteration for every
+    order and type sequence, in both forms (host-only calls)."""
+    from paper_2301_06399_amd import mpt
+    for form in (mpt.FORM_IMPLICIT, mpt.FORM_PARAMETRIC):
+        tab = mpt.flops_table(form)
+        for n in range(1, 6):
+            a, lm = tab[n]["assembly"], tab[n]["lm"]
+            assert (a > 0).all() and (a < lm).all(), (form, n)
+    with pytest.raises(mpt.MptError):
+        mpt.flops_per_iter([0, 7], mpt.FORM_IMPLICIT)
