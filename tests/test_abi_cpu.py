@@ -118,3 +118,24 @@ def test_assembly_flops_are_a_proper_part_of_an_iteration():
             assert (a > 0).all() and (a < lm).all(), (form, n)
     with pytest.raises(mpt.MptError):
         mpt.flops_per_iter([0, 7], mpt.FORM_IMPLICIT)
+
+
+def test_bench_flop_count_bounds_kept_iterations():
+    """The roofline's FLOP count charges the FP32 orders 1-3 iterations after
+    a path's first without their assembly (a lower bound) and charges orders
+    4-5 and the uncorrected count in full."""
+    import importlib.util
+    import numpy as np
+    from paper_2301_06399_amd import mpt
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    tab = mpt.flops_table(mpt.FORM_PARAMETRIC)
+    order = np.array([3, 3, 4, 5, 3], np.int32)
+    code = np.array([0, 1 + 4 * 2, 5, 21, 2], np.int64)
+    iters = np.array([1, 7, 9, 4, 0], np.int32)
+    full = bench.algorithmic_flops(tab, order, code, iters, "lm")
+    low = bench.algorithmic_flops(tab, order, code, iters, "lm", kept=True)
+    want_full = sum(int(tab[n]["lm"][c]) * int(i) for n, c, i in zip(order, code, iters))
+    skipped = int(tab[3]["assembly"][1 + 4 * 2]) * 6     # the 7-iteration order-3 path
+    assert full == want_full and low == full - skipped
